@@ -1,0 +1,199 @@
+"""CPU reference (oracle) for the sp-DBA transform-domain update.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  The library in
+``paper_2609_03922_amd`` never imports it and shares no code with it.
+
+The arithmetic lives in ``spdba_oracle.c`` (plain C, FP64 unless the FP32
+emulation entry point is used); this module only marshals numpy arrays through
+ctypes.  ``mlp`` holds the FP64 / bf16-emulating reference of the activation
+proposer's network.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+OP_CH, OP_GS, OP_NLSE = 1, 2, 3
+FLAG_DENSE, FLAG_PIN_K0 = 1, 2
+OK, EINVAL, ENONFINITE = 0, 1, 6
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class _Inst(ctypes.Structure):
+    _fields_ = [
+        ("op", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("dims", ctypes.c_int64 * 3),
+        ("block", ctypes.c_int32 * 3),
+        ("pad", ctypes.c_int32),
+        ("tau", ctypes.c_double),
+        ("dx", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("p", ctypes.c_double * 8),
+    ]
+
+
+@dataclass
+class Inst:
+    """One grid instance: operator, grid, block shape, threshold, parameters.
+
+    ``dims``/``block`` are 3-tuples (slowest..fastest), unused axes 1.
+    ``p``: CH (M, kappa); GS (Du, Dv, F, k); NLSE (beta2, gamma, alpha).
+    For NLSE, ``dx`` is the sample spacing and ``dt`` the propagation step.
+    """
+
+    op: int
+    dims: tuple
+    block: tuple
+    tau: float
+    dx: float
+    dt: float
+    p: tuple = ()
+    flags: int = FLAG_PIN_K0
+
+    @property
+    def n_modes(self) -> int:
+        return int(np.prod(self.dims))
+
+    @property
+    def n_blocks(self) -> int:
+        return int(np.prod([d // b for d, b in zip(self.dims, self.block)]))
+
+    @property
+    def n_species(self) -> int:
+        return 2 if self.op == OP_GS else 1
+
+    def _c(self) -> _Inst:
+        s = _Inst()
+        s.op = self.op
+        s.flags = self.flags
+        for i in range(3):
+            s.dims[i] = int(self.dims[i])
+            s.block[i] = int(self.block[i])
+        s.tau, s.dx, s.dt = float(self.tau), float(self.dx), float(self.dt)
+        pp = list(self.p) + [0.0] * (8 - len(self.p))
+        for i in range(8):
+            s.p[i] = float(pp[i])
+        return s
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+
+            _b.build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        lib.or_fft.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+        lib.or_sincos.argtypes = [ctypes.c_double, P, P]
+        lib.or_apply_f64.argtypes = [P, P, P, P, P, P, P, P, P]
+        lib.or_apply_f32.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
+        lib.or_step_f64.argtypes = [P, ctypes.c_int64, P, P, P, P, P]
+        lib.or_ch_energy.argtypes = [P, P, P, P]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc):
+    if rc == ENONFINITE:
+        raise OracleError("non-finite indicator value")
+    if rc != OK:
+        raise OracleError(f"oracle error {rc}")
+
+
+def fft(a: np.ndarray, sign: int) -> np.ndarray:
+    """n-D FFT of a complex array (1..3 dims). sign=-1 forward, +1 inverse (1/N)."""
+    a = np.ascontiguousarray(a, dtype=np.complex128).copy()
+    shape = list(a.shape)
+    dims = (ctypes.c_int64 * 3)(*([1] * (3 - len(shape)) + shape))
+    _check(_load().or_fft(_ptr(a), dims, int(sign)))
+    return a
+
+
+def sincos(x: float):
+    s, c = ctypes.c_double(), ctypes.c_double()
+    _load().or_sincos(float(x), ctypes.byref(s), ctypes.byref(c))
+    return s.value, c.value
+
+
+def apply(inst: Inst, q, rhs=None, *, dtype="f64", k0=None, rhs_k0=None, skip=None):
+    """One kernel-level update of one instance (candidate, indicator, mask, update).
+
+    q, rhs: complex arrays of n_species * n_modes values (species concatenated).
+    For dtype 'f32' with CH/GS, k0/rhs_k0 hold the FP64 k=0 values per species.
+    Returns dict(q, a_b, G, mask, worklist, count, k0).
+    """
+    lib = _load()
+    c = inst._c()
+    nb = inst.n_blocks
+    a_b = np.zeros(nb, np.float64)
+    mask = np.zeros(nb, np.uint8)
+    wl = np.zeros(max(nb, 1), np.uint32)
+    G = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.uint8)
+    if dtype == "f64":
+        qq = np.ascontiguousarray(q, dtype=np.complex128).reshape(-1).copy()
+        rr = None if rhs is None else np.ascontiguousarray(rhs, dtype=np.complex128).reshape(-1)
+        rc = lib.or_apply_f64(ctypes.byref(c), _ptr(qq), _ptr(rr), _ptr(sk), _ptr(a_b),
+                              ctypes.byref(G), _ptr(mask), _ptr(wl), ctypes.byref(cnt))
+        k0o = None
+    elif dtype == "f32":
+        qq = np.ascontiguousarray(q, dtype=np.complex64).reshape(-1).copy()
+        rr = None if rhs is None else np.ascontiguousarray(rhs, dtype=np.complex64).reshape(-1)
+        k0o = None if k0 is None else np.ascontiguousarray(k0, dtype=np.float64).copy()
+        rk = None if rhs_k0 is None else np.ascontiguousarray(rhs_k0, dtype=np.float64)
+        rc = lib.or_apply_f32(ctypes.byref(c), _ptr(qq), _ptr(rr), _ptr(k0o), _ptr(rk), _ptr(sk),
+                              _ptr(a_b), ctypes.byref(G), _ptr(mask), _ptr(wl), ctypes.byref(cnt))
+    else:
+        raise ValueError(dtype)
+    _check(rc)
+    n = cnt.value
+    return dict(q=qq, a_b=a_b, G=G.value, mask=mask, worklist=wl[:n].copy(), count=n, k0=k0o)
+
+
+def step(inst: Inst, state, nsteps: int, *, masks=False, diag=False, ab=False):
+    """nsteps full FP64 steps.  state: CH c-hat; GS u-hat|v-hat; NLSE E(t).
+
+    Returns dict(state, masks [nsteps, per, nb], diag [nsteps, 4], ab, active_steps).
+    """
+    lib = _load()
+    c = inst._c()
+    nb = inst.n_blocks
+    per = 2 if inst.op == OP_NLSE else 1
+    st = np.ascontiguousarray(state, dtype=np.complex128).reshape(-1).copy()
+    mk = np.zeros((nsteps, per, nb), np.uint8) if masks else None
+    dg = np.zeros((nsteps, 4), np.float64) if diag else None
+    abv = np.zeros((nsteps, per, nb), np.float64) if ab else None
+    act = np.zeros(nb, np.int64)
+    _check(lib.or_step_f64(ctypes.byref(c), int(nsteps), _ptr(st), _ptr(mk), _ptr(dg),
+                           _ptr(abv), _ptr(act)))
+    return dict(state=st, masks=mk, diag=dg, ab=abv, active_steps=act)
+
+
+def ch_energy(inst: Inst, chat):
+    lib = _load()
+    c = inst._c()
+    ch = np.ascontiguousarray(chat, dtype=np.complex128).reshape(-1)
+    e, m = ctypes.c_double(), ctypes.c_double()
+    _check(lib.or_ch_energy(ctypes.byref(c), _ptr(ch), ctypes.byref(e), ctypes.byref(m)))
+    return e.value, m.value

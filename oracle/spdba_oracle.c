@@ -1,0 +1,670 @@
+/*
+ * spdba_oracle.c -- plain, slow CPU reference for the sp-DBA hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg.  Never linked into or called by the library.
+ *
+ * What it computes, and where the paper defines it:
+ *   - Blockwise activation (Methods, "Spectral dynamic block activation"): the
+ *     transformed field is split into blocks; each block gets one decision from
+ *     an activity measure compared with a threshold; active blocks run the model
+ *     update, frozen blocks keep their stored coefficients.
+ *   - The activity measure used here is the squared size of the candidate
+ *     increment, a(k) = |q'(k) - q(k)|^2, its block maximum a_b and the instance
+ *     maximum G; a block is active when a_b > tau^2 G.  The paper leaves the
+ *     measure application-specific (block energy, RMS amplitude, spectral power);
+ *     this increment form and the relative threshold are the workload's choice.
+ *   - The zero-frequency block is kept active (S6.1) when PIN_K0 is set.
+ *   - Update cores:
+ *       CH   : conserved dynamics d c/dt = M lap(f'(c) - kappa lap c) (S3.1 form),
+ *              semi-implicit: c' = (c - dt M k^2 N) / (1 + dt M kappa k^4),
+ *              N = F[c^3 - c].
+ *       GS   : semi-implicit reaction-diffusion update (S4.2) with a diagonal
+ *              diffusion matrix: u' = (u + dt R_u)/(1 + dt Du k^2), same for v.
+ *       NLSE : linear half-step of the symmetric split-step method (S5.2),
+ *              E' = exp[(-alpha/2 + i beta2 w^2 / 2) h/2] E.
+ *   - Rounding order is pinned so that an implementation in the same working
+ *     precision reproduces every bit: coefficients are formed in FP64 from the
+ *     exact integer m^2, rounded once to the working precision, and the
+ *     candidate is fma(-s, N, q) * a (CH), fma(dt, R, q) * a (GS),
+ *     (Hr E_r - Hi E_i, Hr E_i + Hi E_r) with one fma each (NLSE).  The
+ *     increment is squared in FP64 without contraction.
+ *
+ * Build with -ffp-contract=off: every fused multiply-add below is explicit.
+ */
+#include "spdba_oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define TWO_PI 6.283185307179586476925286766559
+
+/* ------------------------------------------------------------------------ */
+/* geometry                                                                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n[3];   /* extents nz, ny, nx */
+    int64_t b[3];   /* block edges        */
+    int64_t nb3[3]; /* blocks per axis    */
+    int64_t nb;     /* number of blocks   */
+    int64_t N;      /* number of modes    */
+    int64_t ext;    /* common extent of the used axes */
+    int nspec;      /* species per mode   */
+} geom_t;
+
+static int make_geom(const or_inst *d, geom_t *g) {
+    int64_t ext = 0;
+    if (d->op != OR_OP_CH && d->op != OR_OP_GS && d->op != OR_OP_NLSE) return OR_EINVAL;
+    g->N = 1;
+    g->nb = 1;
+    for (int a = 0; a < 3; ++a) {
+        int64_t n = d->dims[a];
+        int64_t b = d->block[a];
+        if (n < 1 || b < 1 || n % b != 0) return OR_EINVAL;
+        if (n > 1) {
+            if (ext == 0) ext = n;
+            else if (ext != n) return OR_EINVAL;
+        }
+        g->n[a] = n;
+        g->b[a] = b;
+        g->nb3[a] = n / b;
+        g->N *= n;
+        g->nb *= n / b;
+    }
+    g->ext = ext ? ext : 1;
+    g->nspec = (d->op == OR_OP_GS) ? 2 : 1;
+    if (!(d->tau >= 0.0) || !(d->dt > 0.0) || !(d->dx > 0.0)) return OR_EINVAL;
+    return OR_OK;
+}
+
+/* m = i for i < n/2, else i - n (the Nyquist index maps to -n/2; n = 1 gives 0) */
+static inline int64_t signed_index(int64_t i, int64_t n) { return (2 * i < n) ? i : i - n; }
+
+/* block id of mode (iz, iy, ix) in C order over the block grid */
+static inline int64_t block_of(const geom_t *g, int64_t iz, int64_t iy, int64_t ix) {
+    return ((iz / g->b[0]) * g->nb3[1] + iy / g->b[1]) * g->nb3[2] + ix / g->b[2];
+}
+
+/* k^2 = (2 pi / (n dx))^2 * (mz^2 + my^2 + mx^2), the integer sum exact */
+static inline double kk_base(const geom_t *g, double dx) {
+    double K = TWO_PI / ((double)g->ext * dx);
+    return K * K;
+}
+
+static inline int64_t m2_of(const geom_t *g, int64_t iz, int64_t iy, int64_t ix) {
+    int64_t mz = signed_index(iz, g->n[0]);
+    int64_t my = signed_index(iy, g->n[1]);
+    int64_t mx = signed_index(ix, g->n[2]);
+    return mz * mz + my * my + mx * mx;
+}
+
+/* ------------------------------------------------------------------------ */
+/* FFT: iterative radix-2 (Cooley-Tukey) on each line, twiddles per index   */
+/* ------------------------------------------------------------------------ */
+
+static void fft_line(double *a, int64_t n, int sign, const double *tw) {
+    /* bit-reversal permutation */
+    for (int64_t i = 1, j = 0; i < n; ++i) {
+        int64_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) {
+            double tr = a[2 * i], ti = a[2 * i + 1];
+            a[2 * i] = a[2 * j];
+            a[2 * i + 1] = a[2 * j + 1];
+            a[2 * j] = tr;
+            a[2 * j + 1] = ti;
+        }
+    }
+    for (int64_t len = 2; len <= n; len <<= 1) {
+        int64_t half = len >> 1, stride = n / len;
+        for (int64_t s = 0; s < n; s += len) {
+            for (int64_t k = 0; k < half; ++k) {
+                double wr = tw[2 * k * stride];
+                double wi = (double)sign * tw[2 * k * stride + 1];
+                double *u = a + 2 * (s + k), *v = a + 2 * (s + k + half);
+                double vr = v[0] * wr - v[1] * wi;
+                double vi = v[0] * wi + v[1] * wr;
+                v[0] = u[0] - vr;
+                v[1] = u[1] - vi;
+                u[0] = u[0] + vr;
+                u[1] = u[1] + vi;
+            }
+        }
+    }
+}
+
+static int is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int or_fft(double *a, const int64_t dims[3], int sign) {
+    int64_t N = dims[0] * dims[1] * dims[2];
+    for (int ax = 0; ax < 3; ++ax)
+        if (!is_pow2(dims[ax])) return OR_EINVAL;
+    for (int ax = 0; ax < 3; ++ax) {
+        int64_t n = dims[ax];
+        if (n == 1) continue;
+        /* element stride along this axis, and the number of lines */
+        int64_t stride = 1;
+        for (int b = ax + 1; b < 3; ++b) stride *= dims[b];
+        int64_t lines = N / n;
+        double *tw = (double *)malloc(sizeof(double) * (size_t)n);
+        for (int64_t j = 0; j < n / 2; ++j) {
+            double ang = TWO_PI * (double)j / (double)n;
+            tw[2 * j] = cos(ang);
+            tw[2 * j + 1] = sin(ang);
+        }
+#pragma omp parallel
+        {
+            double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+#pragma omp for schedule(static)
+            for (int64_t l = 0; l < lines; ++l) {
+                /* line l: inner index (below this axis) and outer index (above) */
+                int64_t inner = l % stride, outer = l / stride;
+                double *base = a + 2 * (outer * n * stride + inner);
+                for (int64_t i = 0; i < n; ++i) {
+                    buf[2 * i] = base[2 * i * stride];
+                    buf[2 * i + 1] = base[2 * i * stride + 1];
+                }
+                fft_line(buf, n, sign, tw);
+                for (int64_t i = 0; i < n; ++i) {
+                    base[2 * i * stride] = buf[2 * i];
+                    base[2 * i * stride + 1] = buf[2 * i + 1];
+                }
+            }
+            free(buf);
+        }
+        free(tw);
+    }
+    if (sign > 0) {
+        double inv = 1.0 / (double)N;
+        for (int64_t i = 0; i < 2 * N; ++i) a[i] *= inv;
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* sin/cos: Cody-Waite reduction by pi/2 in three parts, then Taylor series */
+/* of sin and cos on |r| <= pi/4 evaluated by Horner's rule with fma.       */
+/* ------------------------------------------------------------------------ */
+
+#define PIO2_1 1.57079632673412561417e+00  /* first 33 bits of pi/2  */
+#define PIO2_2 6.07710050630396597660e-11  /* next 33 bits           */
+#define PIO2_3 2.02226624879595063154e-21  /* pi/2 - PIO2_1 - PIO2_2 */
+#define TWO_OVER_PI 6.36619772367581382433e-01
+
+void or_sincos(double x, double *s, double *c) {
+    double q = nearbyint(x * TWO_OVER_PI);
+    double r = fma(-q, PIO2_1, x);
+    r = fma(-q, PIO2_2, r);
+    r = fma(-q, PIO2_3, r);
+    double r2 = r * r;
+    /* sin r = r + r^3 (-1/3! + r^2/5! - ... + r^14/17!) */
+    double ps = 1.0 / 355687428096000.0;         /*  1/17! */
+    ps = fma(ps, r2, -1.0 / 1307674368000.0);    /* -1/15! */
+    ps = fma(ps, r2, 1.0 / 6227020800.0);        /*  1/13! */
+    ps = fma(ps, r2, -1.0 / 39916800.0);         /* -1/11! */
+    ps = fma(ps, r2, 1.0 / 362880.0);            /*  1/9!  */
+    ps = fma(ps, r2, -1.0 / 5040.0);             /* -1/7!  */
+    ps = fma(ps, r2, 1.0 / 120.0);               /*  1/5!  */
+    ps = fma(ps, r2, -1.0 / 6.0);                /* -1/3!  */
+    double sn = fma(r * r2, ps, r);
+    /* cos r = 1 + r^2 (-1/2! + r^2/4! - ... - r^16/18!) */
+    double pc = -1.0 / 6402373705728000.0;       /* -1/18! */
+    pc = fma(pc, r2, 1.0 / 20922789888000.0);    /*  1/16! */
+    pc = fma(pc, r2, -1.0 / 87178291200.0);      /* -1/14! */
+    pc = fma(pc, r2, 1.0 / 479001600.0);         /*  1/12! */
+    pc = fma(pc, r2, -1.0 / 3628800.0);          /* -1/10! */
+    pc = fma(pc, r2, 1.0 / 40320.0);             /*  1/8!  */
+    pc = fma(pc, r2, -1.0 / 720.0);              /* -1/6!  */
+    pc = fma(pc, r2, 1.0 / 24.0);                /*  1/4!  */
+    pc = fma(pc, r2, -0.5);                      /* -1/2!  */
+    double cs = fma(r2, pc, 1.0);
+    long qi = (long)q & 3;
+    switch (qi) {
+        case 0: *s = sn; *c = cs; break;
+        case 1: *s = cs; *c = -sn; break;
+        case 2: *s = -sn; *c = -cs; break;
+        default: *s = -cs; *c = sn; break;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-operator constants, formed once per instance in FP64                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double K2;        /* (2 pi / (n dx))^2 */
+    /* CH */
+    double dtM, dtMk; /* dt*M, dt*M*kappa */
+    /* GS */
+    double dt, dtDu, dtDv;
+    /* NLSE: theta = cth * m^2, amplitude A */
+    double cth, A;
+} consts_t;
+
+static void make_consts(const or_inst *d, const geom_t *g, consts_t *c) {
+    memset(c, 0, sizeof(*c));
+    c->K2 = kk_base(g, d->dx);
+    c->dt = d->dt;
+    if (d->op == OR_OP_CH) {
+        c->dtM = d->dt * d->p[0];
+        c->dtMk = c->dtM * d->p[1];
+    } else if (d->op == OR_OP_GS) {
+        c->dtDu = d->dt * d->p[0];
+        c->dtDv = d->dt * d->p[1];
+    } else {
+        /* H = exp[(-alpha/2 + i beta2 w^2/2) h/2]: phase beta2 w^2 h / 4 */
+        c->cth = ((d->p[0] * d->dt) * 0.25) * c->K2;
+        c->A = exp(-(d->p[2] * d->dt) * 0.25);
+    }
+}
+
+/* CH coefficients at m^2: s = dt M k^2, a = 1/(1 + dt M kappa k^4) */
+static inline void ch_coef(const consts_t *c, int64_t m2, double *s, double *a) {
+    double k2 = c->K2 * (double)m2;
+    *s = c->dtM * k2;
+    *a = 1.0 / (1.0 + c->dtMk * (k2 * k2));
+}
+
+/* GS coefficients at m^2: a_u = 1/(1 + dt Du k^2), a_v likewise */
+static inline void gs_coef(const consts_t *c, int64_t m2, double *au, double *av) {
+    double k2 = c->K2 * (double)m2;
+    *au = 1.0 / (1.0 + c->dtDu * k2);
+    *av = 1.0 / (1.0 + c->dtDv * k2);
+}
+
+/* NLSE half-step factor H at m^2 */
+static inline void nlse_coef(const consts_t *c, int64_t m2, double *hr, double *hi) {
+    double th = c->cth * (double)m2;
+    double sn, cs;
+    or_sincos(th, &sn, &cs);
+    *hr = c->A * cs;
+    *hi = c->A * sn;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kernel-level apply: candidate for all modes, indicator, mask, update     */
+/* ------------------------------------------------------------------------ */
+
+/* squared increment, FP64, no contraction */
+static inline double sq2(double dr, double di) { return dr * dr + di * di; }
+
+int or_apply_f64(const or_inst *d, double *q, const double *rhs, const uint8_t *skip,
+                 double *a_b, double *G, uint8_t *mask, uint32_t *wl, int64_t *count) {
+    geom_t g;
+    int rc = make_geom(d, &g);
+    if (rc) return rc;
+    if (d->op != OR_OP_NLSE && rhs == NULL) return OR_EINVAL;
+    consts_t c;
+    make_consts(d, &g, &c);
+    const int64_t N = g.N;
+    const int dense = (d->flags & OR_FLAG_DENSE) != 0;
+    const int pin = (d->flags & OR_FLAG_PIN_K0) != 0;
+
+    /* step 1: candidate q' for every mode, and a(k) */
+    double *cand = (double *)malloc(sizeof(double) * 2 * (size_t)(N * g.nspec));
+    double *ak = (double *)malloc(sizeof(double) * (size_t)N);
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
+        int64_t m2 = m2_of(&g, iz, iy, ix);
+        double a;
+        if (d->op == OR_OP_CH) {
+            double s, f;
+            ch_coef(&c, m2, &s, &f);
+            double qr = q[2 * i], qi = q[2 * i + 1];
+            double nr = rhs[2 * i], ni = rhs[2 * i + 1];
+            double cr = fma(-s, nr, qr) * f, ci = fma(-s, ni, qi) * f;
+            cand[2 * i] = cr;
+            cand[2 * i + 1] = ci;
+            a = sq2(cr - qr, ci - qi);
+        } else if (d->op == OR_OP_GS) {
+            double au, av;
+            gs_coef(&c, m2, &au, &av);
+            const double *u = q, *v = q + 2 * N, *ru = rhs, *rv = rhs + 2 * N;
+            double ur = fma(c.dt, ru[2 * i], u[2 * i]) * au;
+            double ui = fma(c.dt, ru[2 * i + 1], u[2 * i + 1]) * au;
+            double vr = fma(c.dt, rv[2 * i], v[2 * i]) * av;
+            double vi = fma(c.dt, rv[2 * i + 1], v[2 * i + 1]) * av;
+            cand[2 * i] = ur;
+            cand[2 * i + 1] = ui;
+            cand[2 * N + 2 * i] = vr;
+            cand[2 * N + 2 * i + 1] = vi;
+            a = sq2(ur - u[2 * i], ui - u[2 * i + 1]) + sq2(vr - v[2 * i], vi - v[2 * i + 1]);
+        } else {
+            double hr, hi;
+            nlse_coef(&c, m2, &hr, &hi);
+            double er = q[2 * i], ei = q[2 * i + 1];
+            double cr = fma(hr, er, -(hi * ei));
+            double ci = fma(hr, ei, hi * er);
+            cand[2 * i] = cr;
+            cand[2 * i + 1] = ci;
+            a = sq2(cr - er, ci - ei);
+        }
+        if (!(a <= DBL_MAX)) bad |= 1;
+        ak[i] = a;
+    }
+
+    /* steps 2-4: a_b = max over the block, G = max over evaluated blocks,
+     * active iff a_b > fl(tau^2 G), or the block holds k = 0 and PIN_K0 */
+    for (int64_t b = 0; b < g.nb; ++b) a_b[b] = 0.0;
+    if (!dense) {
+        for (int64_t i = 0; i < N; ++i) {
+            int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
+            int64_t b = block_of(&g, iz, iy, ix);
+            if (skip && skip[b] && !(pin && b == 0)) continue;
+            if (ak[i] > a_b[b]) a_b[b] = ak[i];
+        }
+    }
+    double gmax = 0.0;
+    if (!dense)
+        for (int64_t b = 0; b < g.nb; ++b)
+            if (a_b[b] > gmax) gmax = a_b[b];
+    double thr = (d->tau * d->tau) * gmax;
+    int64_t cnt = 0;
+    for (int64_t b = 0; b < g.nb; ++b) {
+        int on;
+        if (dense) on = 1;
+        else if (pin && b == 0) on = 1;
+        else if (skip && skip[b]) on = 0;
+        else on = a_b[b] > thr;
+        mask[b] = (uint8_t)on;
+        if (on) wl[cnt++] = (uint32_t)b;
+    }
+    *G = gmax;
+    *count = cnt;
+
+    /* step 5: active blocks take the candidate, frozen blocks keep q */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
+        if (!mask[block_of(&g, iz, iy, ix)]) continue;
+        for (int s = 0; s < g.nspec; ++s) {
+            q[2 * (s * N + i)] = cand[2 * (s * N + i)];
+            q[2 * (s * N + i) + 1] = cand[2 * (s * N + i) + 1];
+        }
+    }
+    free(cand);
+    free(ak);
+    return (bad && !dense) ? OR_ENONFINITE : OR_OK;
+}
+
+int or_apply_f32(const or_inst *d, float *q, const float *rhs, double *k0,
+                 const double *rhs_k0, const uint8_t *skip, double *a_b, double *G,
+                 uint8_t *mask, uint32_t *wl, int64_t *count) {
+    geom_t g;
+    int rc = make_geom(d, &g);
+    if (rc) return rc;
+    if (d->op != OR_OP_NLSE && (rhs == NULL || k0 == NULL || rhs_k0 == NULL)) return OR_EINVAL;
+    consts_t c;
+    make_consts(d, &g, &c);
+    const int64_t N = g.N;
+    const int dense = (d->flags & OR_FLAG_DENSE) != 0;
+    const int pin = (d->flags & OR_FLAG_PIN_K0) != 0;
+    const int k0path = (d->op != OR_OP_NLSE); /* real fields: k = 0 kept in FP64 */
+    const float dtf = (float)c.dt;
+
+    float *cand = (float *)malloc(sizeof(float) * 2 * (size_t)(N * g.nspec));
+    double *ak = (double *)malloc(sizeof(double) * (size_t)N);
+    double k0c[2] = {0.0, 0.0};
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
+        int64_t m2 = m2_of(&g, iz, iy, ix);
+        double a;
+        if (k0path && i == 0) {
+            /* the k = 0 mode in FP64 (coefficients at k = 0) */
+            if (d->op == OR_OP_CH) {
+                double s, f;
+                ch_coef(&c, 0, &s, &f);
+                k0c[0] = fma(-s, rhs_k0[0], k0[0]) * f;
+                double dr = k0c[0] - k0[0];
+                a = sq2(dr, 0.0);
+            } else {
+                double au, av;
+                gs_coef(&c, 0, &au, &av);
+                k0c[0] = fma(c.dt, rhs_k0[0], k0[0]) * au;
+                k0c[1] = fma(c.dt, rhs_k0[1], k0[1]) * av;
+                a = sq2(k0c[0] - k0[0], 0.0) + sq2(k0c[1] - k0[1], 0.0);
+            }
+            for (int s = 0; s < g.nspec; ++s) {
+                cand[2 * (s * N)] = 0.0f;
+                cand[2 * (s * N) + 1] = 0.0f;
+            }
+        } else if (d->op == OR_OP_CH) {
+            double s, f;
+            ch_coef(&c, m2, &s, &f);
+            float sf = (float)s, ff = (float)f;
+            float qr = q[2 * i], qi = q[2 * i + 1];
+            float cr = fmaf(-sf, rhs[2 * i], qr) * ff;
+            float ci = fmaf(-sf, rhs[2 * i + 1], qi) * ff;
+            cand[2 * i] = cr;
+            cand[2 * i + 1] = ci;
+            a = sq2((double)cr - (double)qr, (double)ci - (double)qi);
+        } else if (d->op == OR_OP_GS) {
+            double au, av;
+            gs_coef(&c, m2, &au, &av);
+            float auf = (float)au, avf = (float)av;
+            const float *u = q, *v = q + 2 * N, *ru = rhs, *rv = rhs + 2 * N;
+            float ur = fmaf(dtf, ru[2 * i], u[2 * i]) * auf;
+            float ui = fmaf(dtf, ru[2 * i + 1], u[2 * i + 1]) * auf;
+            float vr = fmaf(dtf, rv[2 * i], v[2 * i]) * avf;
+            float vi = fmaf(dtf, rv[2 * i + 1], v[2 * i + 1]) * avf;
+            cand[2 * i] = ur;
+            cand[2 * i + 1] = ui;
+            cand[2 * N + 2 * i] = vr;
+            cand[2 * N + 2 * i + 1] = vi;
+            a = sq2((double)ur - (double)u[2 * i], (double)ui - (double)u[2 * i + 1]) +
+                sq2((double)vr - (double)v[2 * i], (double)vi - (double)v[2 * i + 1]);
+        } else {
+            double hr, hi;
+            nlse_coef(&c, m2, &hr, &hi);
+            float hrf = (float)hr, hif = (float)hi;
+            float er = q[2 * i], ei = q[2 * i + 1];
+            float cr = fmaf(hrf, er, -(hif * ei));
+            float ci = fmaf(hrf, ei, hif * er);
+            cand[2 * i] = cr;
+            cand[2 * i + 1] = ci;
+            a = sq2((double)cr - (double)er, (double)ci - (double)ei);
+        }
+        if (!(a <= DBL_MAX)) bad |= 1;
+        ak[i] = a;
+    }
+
+    for (int64_t b = 0; b < g.nb; ++b) a_b[b] = 0.0;
+    if (!dense) {
+        for (int64_t i = 0; i < N; ++i) {
+            int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
+            int64_t b = block_of(&g, iz, iy, ix);
+            if (skip && skip[b] && !(pin && b == 0)) continue;
+            if (ak[i] > a_b[b]) a_b[b] = ak[i];
+        }
+    }
+    double gmax = 0.0;
+    if (!dense)
+        for (int64_t b = 0; b < g.nb; ++b)
+            if (a_b[b] > gmax) gmax = a_b[b];
+    double thr = (d->tau * d->tau) * gmax;
+    int64_t cnt = 0;
+    for (int64_t b = 0; b < g.nb; ++b) {
+        int on;
+        if (dense) on = 1;
+        else if (pin && b == 0) on = 1;
+        else if (skip && skip[b]) on = 0;
+        else on = a_b[b] > thr;
+        mask[b] = (uint8_t)on;
+        if (on) wl[cnt++] = (uint32_t)b;
+    }
+    *G = gmax;
+    *count = cnt;
+
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
+        if (!mask[block_of(&g, iz, iy, ix)]) continue;
+        for (int s = 0; s < g.nspec; ++s) {
+            q[2 * (s * N + i)] = cand[2 * (s * N + i)];
+            q[2 * (s * N + i) + 1] = cand[2 * (s * N + i) + 1];
+        }
+    }
+    if (k0path) {
+        if (mask[0])
+            for (int s = 0; s < g.nspec; ++s) k0[s] = k0c[s];
+        for (int s = 0; s < g.nspec; ++s) {
+            q[2 * (s * N)] = 0.0f;
+            q[2 * (s * N) + 1] = 0.0f;
+        }
+    }
+    free(cand);
+    free(ak);
+    return (bad && !dense) ? OR_ENONFINITE : OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Full FP64 steps                                                           */
+/* ------------------------------------------------------------------------ */
+
+int or_ch_energy(const or_inst *d, const double *chat, double *energy, double *mass) {
+    /* F = dx^d sum_x f(c) + (kappa/2) (dx^d / N) sum_k k^2 |c_k|^2,
+     * f(c) = (c^2 - 1)^2 / 4 (so f'(c) = c^3 - c); mass = mean of c. */
+    geom_t g;
+    int rc = make_geom(d, &g);
+    if (rc) return rc;
+    const int64_t N = g.N;
+    int ndim = (g.n[0] > 1) + (g.n[1] > 1) + (g.n[2] > 1);
+    if (ndim == 0) ndim = 1;
+    double dvol = 1.0;
+    for (int k = 0; k < ndim; ++k) dvol *= d->dx;
+    double *w = (double *)malloc(sizeof(double) * 2 * (size_t)N);
+    memcpy(w, chat, sizeof(double) * 2 * (size_t)N);
+    or_fft(w, g.n, +1);
+    double K2 = kk_base(&g, d->dx);
+    double bulk = 0.0, grad = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        double cc = w[2 * i];
+        double t = cc * cc - 1.0;
+        bulk += 0.25 * t * t;
+        int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
+        double k2 = K2 * (double)m2_of(&g, iz, iy, ix);
+        grad += k2 * (chat[2 * i] * chat[2 * i] + chat[2 * i + 1] * chat[2 * i + 1]);
+    }
+    free(w);
+    *energy = dvol * bulk + 0.5 * d->p[1] * (dvol / (double)N) * grad;
+    *mass = chat[0] / (double)N;
+    return OR_OK;
+}
+
+int or_step_f64(const or_inst *d, int64_t nsteps, double *state, uint8_t *masks,
+                double *diag, double *ab, int64_t *active_steps) {
+    geom_t g;
+    int rc = make_geom(d, &g);
+    if (rc) return rc;
+    const int64_t N = g.N, nb = g.nb;
+    const int per = (d->op == OR_OP_NLSE) ? 2 : 1;
+    double *w = (double *)malloc(sizeof(double) * 2 * (size_t)(N * g.nspec));
+    double *a_b = (double *)malloc(sizeof(double) * (size_t)nb);
+    uint8_t *mk = (uint8_t *)malloc((size_t)nb);
+    uint32_t *wl = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)nb);
+    if (active_steps)
+        for (int64_t b = 0; b < nb; ++b) active_steps[b] = 0;
+    rc = OR_OK;
+    for (int64_t st = 0; st < nsteps && rc == OR_OK; ++st) {
+        double G;
+        int64_t cnt;
+        if (d->op == OR_OP_CH) {
+            if (diag) {
+                double F, m;
+                or_ch_energy(d, state, &F, &m);
+                diag[4 * st] = m;
+                diag[4 * st + 1] = F;
+                diag[4 * st + 2] = 0.0;
+                diag[4 * st + 3] = 0.0;
+            }
+            /* real space: c = Re F^-1[c-hat]; nonlinear term c^3 - c; N-hat */
+            memcpy(w, state, sizeof(double) * 2 * (size_t)N);
+            or_fft(w, g.n, +1);
+            for (int64_t i = 0; i < N; ++i) {
+                double cc = w[2 * i];
+                w[2 * i] = cc * cc * cc - cc;
+                w[2 * i + 1] = 0.0;
+            }
+            or_fft(w, g.n, -1);
+            rc = or_apply_f64(d, state, w, NULL, a_b, &G, mk, wl, &cnt);
+        } else if (d->op == OR_OP_GS) {
+            /* R_u = -u v^2 + F (1 - u), R_v = u v^2 - (F + k) v */
+            const double Fp = d->p[2], kp = d->p[3];
+            memcpy(w, state, sizeof(double) * 4 * (size_t)N);
+            or_fft(w, g.n, +1);
+            or_fft(w + 2 * N, g.n, +1);
+            if (diag) {
+                double su = 0.0, sv = 0.0;
+                for (int64_t i = 0; i < N; ++i) {
+                    su += w[2 * i];
+                    sv += w[2 * N + 2 * i];
+                }
+                diag[4 * st] = su / (double)N;
+                diag[4 * st + 1] = sv / (double)N;
+                diag[4 * st + 2] = 0.0;
+                diag[4 * st + 3] = 0.0;
+            }
+            for (int64_t i = 0; i < N; ++i) {
+                double u = w[2 * i], v = w[2 * N + 2 * i];
+                double uvv = u * v * v;
+                w[2 * i] = -uvv + Fp * (1.0 - u);
+                w[2 * i + 1] = 0.0;
+                w[2 * N + 2 * i] = uvv - (Fp + kp) * v;
+                w[2 * N + 2 * i + 1] = 0.0;
+            }
+            or_fft(w, g.n, -1);
+            or_fft(w + 2 * N, g.n, -1);
+            rc = or_apply_f64(d, state, w, NULL, a_b, &G, mk, wl, &cnt);
+        } else {
+            /* symmetric split step: linear half, Kerr rotation, linear half */
+            if (diag) {
+                double p = 0.0;
+                for (int64_t i = 0; i < N; ++i)
+                    p += state[2 * i] * state[2 * i] + state[2 * i + 1] * state[2 * i + 1];
+                diag[4 * st] = p;
+                diag[4 * st + 1] = diag[4 * st + 2] = diag[4 * st + 3] = 0.0;
+            }
+            const double gam = d->p[1], h = d->dt;
+            for (int half = 0; half < 2 && rc == OR_OK; ++half) {
+                or_fft(state, g.n, -1);
+                rc = or_apply_f64(d, state, NULL, NULL, a_b, &G, mk, wl, &cnt);
+                or_fft(state, g.n, +1);
+                if (masks) memcpy(masks + (st * per + half) * nb, mk, (size_t)nb);
+                if (ab) memcpy(ab + (st * per + half) * nb, a_b, sizeof(double) * (size_t)nb);
+                if (active_steps)
+                    for (int64_t b = 0; b < nb; ++b) active_steps[b] += mk[b];
+                if (half == 0) {
+                    for (int64_t i = 0; i < N; ++i) {
+                        double er = state[2 * i], ei = state[2 * i + 1];
+                        double ph = gam * (er * er + ei * ei) * h;
+                        double cs = cos(ph), sn = sin(ph);
+                        state[2 * i] = er * cs - ei * sn;
+                        state[2 * i + 1] = er * sn + ei * cs;
+                    }
+                }
+            }
+            continue;
+        }
+        if (masks) memcpy(masks + st * nb, mk, (size_t)nb);
+        if (ab) memcpy(ab + st * nb, a_b, sizeof(double) * (size_t)nb);
+        if (active_steps)
+            for (int64_t b = 0; b < nb; ++b) active_steps[b] += mk[b];
+    }
+    free(w);
+    free(a_b);
+    free(mk);
+    free(wl);
+    return rc;
+}

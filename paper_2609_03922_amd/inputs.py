@@ -1,0 +1,113 @@
+"""Seeded synthetic inputs shared by the library's tests, the oracle's tests and
+the benchmark.
+
+This module only draws random numbers and shapes them into initial fields and
+test spectra; it contains none of the update method's arithmetic (no
+wavenumbers, coefficients, indicators or time steps).  Every generator takes an
+explicit seed and uses NumPy's PCG64 (``default_rng``), so both sides of a
+parity test receive the same bytes.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def rng_for(seed: int, *stream: int) -> np.random.Generator:
+    return np.random.default_rng([int(seed), *[int(s) for s in stream]])
+
+
+def dims3(ndim: int, n: int) -> tuple:
+    """(nz, ny, nx) with unused leading axes set to 1."""
+    return tuple([1] * (3 - ndim) + [n] * ndim)
+
+
+def block3(ndim: int, b: int) -> tuple:
+    return tuple([1] * (3 - ndim) + [b] * ndim)
+
+
+# --------------------------------------------------------------------------
+# batched workload sizes
+# --------------------------------------------------------------------------
+
+def instance_sizes(cfg: dict) -> list:
+    """Per-instance grid extent of a batched workload, drawn from its seed."""
+    r = rng_for(cfg["seed"], 0)
+    if cfg["op"] == "nlse":
+        e = r.integers(cfg["log2_min"], cfg["log2_max"] + 1, size=cfg["n_instances"])
+        return [int(2 ** int(x)) for x in e]
+    if cfg["op"] == "gs":
+        return [int(x) for x in r.choice(np.array(cfg["sizes"]), size=cfg["n_instances"])]
+    return [int(cfg["n"])]
+
+
+# --------------------------------------------------------------------------
+# initial fields (real space / time domain)
+# --------------------------------------------------------------------------
+
+def uniform_field(seed: int, inst: int, shape, mean: float, half_width: float,
+                  dtype=np.float64) -> np.ndarray:
+    """mean + U(-half_width, half_width), i.i.d. per grid point."""
+    r = rng_for(seed, 1, inst)
+    return (mean + r.uniform(-half_width, half_width, size=shape)).astype(dtype)
+
+
+def gs_patch_field(seed: int, inst: int, n: int, patches: int = 10, patch: int = 8,
+                   u_val: float = 0.5, v_val: float = 0.25, dtype=np.float32):
+    """u = 1, v = 0 with `patches` square patches (periodic wrap, overwrite)."""
+    r = rng_for(seed, 2, inst)
+    u = np.ones((n, n), np.float64)
+    v = np.zeros((n, n), np.float64)
+    corners = r.integers(0, n, size=(patches, 2))
+    idx = np.arange(patch)
+    for cy, cx in corners:
+        ys = (cy + idx) % n
+        xs = (cx + idx) % n
+        u[np.ix_(ys, xs)] = u_val
+        v[np.ix_(ys, xs)] = v_val
+    return u.astype(dtype), v.astype(dtype)
+
+
+def qam16_rrc_signal(seed: int, inst: int, n: int, sps: int = 2, rolloff: float = 0.1,
+                     power_w: float = 1e-3, dtype=np.complex64) -> np.ndarray:
+    """Random 16-QAM symbols, zero-stuffed to `sps` samples/symbol, shaped by a
+    root-raised-cosine response applied exactly in frequency (circular), then
+    scaled to mean |E|^2 = power_w."""
+    r = rng_for(seed, 3, inst)
+    nsym = n // sps
+    levels = np.array([-3.0, -1.0, 1.0, 3.0])
+    sym = levels[r.integers(0, 4, nsym)] + 1j * levels[r.integers(0, 4, nsym)]
+    x = np.zeros(n, np.complex128)
+    x[::sps] = sym
+    f = np.fft.fftfreq(n) * sps  # frequency in units of the symbol rate
+    af = np.abs(f)
+    f1, f2 = (1 - rolloff) / 2, (1 + rolloff) / 2
+    h = np.zeros(n)
+    h[af <= f1] = 1.0
+    mid = (af > f1) & (af <= f2)
+    h[mid] = np.sqrt(0.5 * (1 + np.cos(np.pi / rolloff * (af[mid] - f1))))
+    y = np.fft.ifft(np.fft.fft(x) * h)
+    y *= np.sqrt(power_w / np.mean(np.abs(y) ** 2))
+    return y.astype(dtype)
+
+
+# --------------------------------------------------------------------------
+# spectra for kernel-level tests: structured random coefficients
+# --------------------------------------------------------------------------
+
+def shaped_spectrum(seed: int, stream: int, dims, width: float, floor: float = 1e-4,
+                    scale: float = 1.0, dtype=np.complex128) -> np.ndarray:
+    """Random complex coefficients whose magnitude falls off as a Gaussian in the
+    distance from index 0 (periodic), plus a small floor -- a stand-in for the
+    concentrated spectra of the workloads.  `width` is in index units."""
+    r = rng_for(seed, 4, stream)
+    shape = tuple(int(d) for d in dims)
+    g = r.standard_normal(shape) + 1j * r.standard_normal(shape)
+    dist2 = np.zeros(shape)
+    for ax, n in enumerate(shape):
+        i = np.arange(n)
+        d = np.minimum(i, n - i).astype(np.float64)
+        sh = [1] * len(shape)
+        sh[ax] = n
+        dist2 = dist2 + (d.reshape(sh)) ** 2
+    amp = np.exp(-dist2 / (2.0 * width * width)) + floor
+    return (scale * amp * g).astype(dtype)
