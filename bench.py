@@ -1,0 +1,238 @@
+"""Benchmark of the sp-DBA hot path on one MI355X.
+
+Default workload: 3-D Cahn-Hilliard on a 256^3 periodic grid, FP32 fields and
+transforms with FP64 k = 0 mode and FP64 indicator reductions, 8^3 k-space
+blocks, relative threshold 1e-6, dt = 0.01, seeded initial field
+0.1 + U(-0.02, 0.02).  A step is one full pass of the hot path: inverse FFT,
+fused nonlinear term, forward FFT, indicator, compaction, active-block update.
+
+Prints ONE JSON line.  ``value`` is whole-job throughput in Gpts/s: grid points
+advanced per second over the timed steps (transforms included), inputs resident
+in HBM.  Extra keys report steps/s, the update-stage rate, the dense (Regular)
+run on the same input, the roofline of the dominant kernel of the update stage
+(the indicator, from HIP events on the plan's stream inside the timed region)
+and the CPU oracle on a bounded sample.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spectral-update Gpts/s + steps/s, sp-DBA vs dense on GPU at fixed L2 error"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", default="ch3d_256_f32")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense comparison run")
+    ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph per step")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def build_descs(cfg, S, inputs, **over):
+    sizes = inputs.instance_sizes(cfg) if "n_instances" in cfg else [cfg["n"]]
+    return [S.desc_from_config(cfg, n=n, **over) for n in sizes], sizes
+
+
+def init_fields(plan, cfg, sizes, inputs, np, torch):
+    for i, n in enumerate(sizes):
+        d = plan.descs[i]
+        if cfg["op"] == "ch":
+            ic = cfg["ic"]
+            f = inputs.uniform_field(cfg["seed"], i, (n,) * cfg["ndim"], ic["mean"], ic["half_width"],
+                                     dtype=np.float64 if d.dtype == "f64" else np.float32)
+            plan.set_field(i, torch.from_numpy(f.ravel()))
+        elif cfg["op"] == "gs":
+            u, v = inputs.gs_patch_field(cfg["seed"], i, n)
+            plan.set_field(i, torch.from_numpy(np.concatenate([u.ravel(), v.ravel()])))
+        else:
+            plan.set_field(i, torch.from_numpy(inputs.qam16_rrc_signal(cfg["seed"], i, n)))
+
+
+def indicator_bytes(cfg, descs):
+    """Algorithmic bytes of one indicator launch: every mode's state and
+    right-hand side (NLSE: state only) in the working precision, plus one FP64
+    a_b per block."""
+    tot = 0
+    for d in descs:
+        esz = 16 if d.dtype == "f64" else 8
+        arrays = {"ch": 2, "gs": 4, "nlse": 1}[d.op]
+        tot += d.n_modes * esz * arrays + 8 * d.n_blocks
+    return tot
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is "
+                                   "described in DESIGN.md and not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2609_03922_amd import configs, inputs
+    from paper_2609_03922_amd import spdba as S
+
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "copy_probe_bytes_written": b.numel() * 4}))
+        return
+
+    cfg = configs.BY_NAME[args.config]
+    K = args.steps if args.steps is not None else min(cfg["steps"], 500)
+    W = args.warmup
+    descs, sizes = build_descs(cfg, S, inputs, timing=not args.graph, graph=args.graph)
+    total_modes = sum(d.n_modes for d in descs)
+
+    # ---- sp-DBA run (timed) --------------------------------------------
+    plan = S.Plan(descs)
+    init_fields(plan, cfg, sizes, inputs, np, torch)
+    plan.step(W)
+    torch.cuda.synchronize()
+    init_fields(plan, cfg, sizes, inputs, np, torch)  # timed steps are the workload's steps 0..K-1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.step(K)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    s0 = plan.stats(0)  # stage means over the last (up to 64) timed steps
+    active = sum(plan.stats(i)["active_blocks"] for i in range(len(descs)))
+    nblocks = sum(d.n_blocks for d in descs)
+    sp_field = [plan.get_field(i) for i in range(len(descs))]
+    stage_ms = None
+    roof = None
+    if not args.graph:
+        names = ("fft", "nonlinear", "indicator", "compaction", "update", "step")
+        stage_ms = {k: float(v) for k, v in zip(names, s0["stage_ms"])}
+        ib = indicator_bytes(cfg, descs)
+        ind_s = stage_ms["indicator"] * 1e-3
+        ach = ib / ind_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_indicator",
+                "bytes_per_launch": ib, "avg_launch_us": round(ind_s * 1e6, 2)}
+    plan.destroy()
+
+    # ---- dense (Regular) run on the same input ----------------------------
+    dense = None
+    if not args.no_dense:
+        ddescs, _ = build_descs(cfg, S, inputs, dense=True, timing=not args.graph, graph=args.graph)
+        dp = S.Plan(ddescs)
+        init_fields(dp, cfg, sizes, inputs, np, torch)
+        dp.step(W)
+        init_fields(dp, cfg, sizes, inputs, np, torch)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dp.step(K)
+        torch.cuda.synchronize()
+        TD = time.perf_counter() - t1
+        dst = dp.stats(0)["stage_ms"]
+        num = den = 0.0
+        for i in range(len(ddescs)):
+            a = sp_field[i].double().cpu()
+            b = dp.get_field(i).double().cpu()
+            if cfg["op"] == "ch":
+                a = a - b.mean()
+                b = b - b.mean()
+            num += float(torch.sum(torch.abs(a - b) ** 2))
+            den += float(torch.sum(torch.abs(b) ** 2))
+        dense = {"steps_per_s": K / TD, "wall_s": TD, "rel_l2_spdba_vs_dense": (num / max(den, 1e-300)) ** 0.5}
+        if not args.graph:
+            dense["stage_ms"] = {"fft": dst[0], "nonlinear": dst[1], "update": dst[4], "step": dst[5]}
+        dp.destroy()
+
+    # ---- CPU oracle baseline ------------------------------------------------
+    cpu = None
+    if not args.no_cpu:
+        cpu = oracle_baseline(cfg, descs, sizes, inputs, np)
+
+    steps_per_s = K / T
+    out = {
+        "metric": METRIC,
+        "value": round(total_modes * K / T / 1e9, 4),
+        "unit": "Gpts/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(1e3 * T / K, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if descs[0].dtype == "f32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "grid": f"{cfg.get('n', 'batch')}^{cfg['ndim']}",
+                   "block": cfg["block"], "tau": cfg["tau"], "instances": len(descs),
+                   "modes": total_modes, "parallelism": "single-gpu", "hip_graph": bool(args.graph)},
+        "steps_per_s": round(steps_per_s, 3),
+        "active_fraction_last_step": round(active / nblocks, 4),
+    }
+    if stage_ms is not None:
+        upd_stage_ms = stage_ms["indicator"] + stage_ms["compaction"] + stage_ms["update"]
+        out["stage_ms"] = {k: round(v, 4) for k, v in stage_ms.items()}
+        out["update_stage_gpts_s"] = round(total_modes / (upd_stage_ms * 1e-3) / 1e9, 3)
+        out["roofline"] = roof
+    if dense is not None:
+        out["dense"] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in dense.items()}
+        out["speedup_steps_vs_dense"] = round(steps_per_s / dense["steps_per_s"], 4)
+        if stage_ms is not None and "stage_ms" in dense:
+            out["update_stage_speedup_vs_dense"] = round(
+                dense["stage_ms"]["update"] / (stage_ms["indicator"] + stage_ms["compaction"] + stage_ms["update"]), 4)
+    out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+def oracle_baseline(cfg, descs, sizes, inputs, np):
+    import oracle as O
+
+    d = descs[0]
+    opmap = {"ch": O.OP_CH, "gs": O.OP_GS, "nlse": O.OP_NLSE}
+    inst = O.Inst(op=opmap[d.op], dims=d.dims3, block=d.block3, tau=d.tau, dx=d.dx, dt=d.dt,
+                  p=tuple(d.params), flags=O.FLAG_PIN_K0)
+    n = sizes[0]
+    if cfg["op"] == "ch":
+        ic = cfg["ic"]
+        f = inputs.uniform_field(cfg["seed"], 0, (n,) * cfg["ndim"], ic["mean"], ic["half_width"])
+        st = O.fft(f, -1)
+    elif cfg["op"] == "gs":
+        u, v = inputs.gs_patch_field(cfg["seed"], 0, n, dtype=np.float64)
+        st = np.concatenate([O.fft(u, -1).ravel(), O.fft(v, -1).ravel()])
+    else:
+        st = inputs.qam16_rrc_signal(cfg["seed"], 0, n).astype(np.complex128)
+    # grow the sample until it takes about 10 s of CPU work
+    steps, elapsed = 1, 0.0
+    while True:
+        t0 = time.perf_counter()
+        st = O.step(inst, st, steps)["state"]
+        elapsed = time.perf_counter() - t0
+        if elapsed >= 10.0 or steps >= 64:
+            break
+        steps *= 4 if elapsed < 2.5 else 2
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(d.n_modes * steps / elapsed / 1e9, 6), "unit": "Gpts/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} full FP64 steps of instance 0 ({n}^{cfg['ndim']}) of {cfg['name']}, "
+                      f"{elapsed:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

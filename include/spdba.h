@@ -1,0 +1,209 @@
+/*
+ * spdba.h -- C ABI of the MI355X (gfx950) sp-DBA transform-domain update.
+ *
+ * The method (spectral dynamic block activation): the transformed field is
+ * split into k-space blocks; each step, every block gets one decision from an
+ * activity measure compared with a threshold; active blocks run the model's
+ * update core and frozen blocks keep their stored coefficients (Methods,
+ * "Spectral dynamic block activation"; Supplementary S2.1).  The transforms are
+ * rocFFT calls, untouched.  This library implements the per-step indicator, the
+ * compaction of the active-block list, the active-only update, the dense update
+ * (Regular mode) and the fused real-space nonlinear term, as HIP kernels.
+ *
+ * Entry points map onto the paper's integration interface (Supplementary S2.1,
+ * "Pseudocode for integration of sp-DBA into a solver"):
+ *     spdba_init     -> spdba_plan_create + spdba_plan_bind
+ *     spdba_apply    -> spdba_apply (update stage only) / spdba_step (full step)
+ *     spdba_destroy  -> spdba_destroy
+ *
+ * Conventions
+ *   - Grids: dims[3] = {nz, ny, nx} slowest..fastest, unused leading axes = 1;
+ *     used extents are equal powers of two.  Complex data are interleaved
+ *     (re, im), natural FFT order (index i <-> signed wavenumber index
+ *     m = i for i < n/2, else i - n), C order, x fastest, full c2c spectrum.
+ *   - Blocks: block[3] edges per axis, dividing dims; block ids are C order over
+ *     the block grid; block 0 holds k = 0.
+ *   - Threshold: with the candidate increment dq(k) = q'(k) - q(k) of the
+ *     current step, a(k) = |dq(k)|^2 (FP64; Gray-Scott sums both species),
+ *     a_b = max over the block, G = max over the instance; block b is active iff
+ *     a_b > fl(fl(tau*tau) * G), or b = 0 with SPDBA_FLAG_PIN_K0 (Supplementary
+ *     S6.1 keeps the zero-frequency block active).
+ *   - Precision: SPDBA_F64 computes in FP64 throughout.  SPDBA_F32 keeps fields,
+ *     transforms and the update in FP32 complex; the k = 0 coefficient of the
+ *     real-field operators (CH, GS) is held as an FP64 scalar per species (its
+ *     FP32 array slot stays 0), and a(k), a_b, G and all sums are FP64.
+ *   - Memory: the caller allocates and owns the state and work buffers (sizes
+ *     from spdba_plan_buffer_sizes) and the stream; the library never allocates
+ *     device memory.  All device pointers are HIP device pointers.  Host output
+ *     arrays are caller-owned.
+ *   - Errors: every call returns an spdba_status.  Validation errors return
+ *     immediately and leave the plan unchanged.  Device and rocFFT errors return
+ *     SPDBA_EDEVICE / SPDBA_EFFT.  A non-finite indicator value raises a device
+ *     flag that surfaces as SPDBA_ENONFINITE at the next synchronising call
+ *     (spdba_active_mask, spdba_indicator, spdba_worklist, spdba_stats,
+ *     spdba_get_spectrum).  Calls are asynchronous on the plan's stream unless
+ *     stated.  A plan is not thread-safe; separate plans are independent.
+ */
+#ifndef SPDBA_H
+#define SPDBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t spdba_status;
+enum {
+    SPDBA_OK = 0,
+    SPDBA_EINVAL = 1,       /* invalid argument or descriptor            */
+    SPDBA_EUNSUPPORTED = 2, /* valid but unsupported combination         */
+    SPDBA_ESTATE = 3,       /* call out of order (e.g. before bind)      */
+    SPDBA_EDEVICE = 4,      /* HIP runtime error                         */
+    SPDBA_EFFT = 5,         /* rocFFT error                              */
+    SPDBA_ENONFINITE = 6    /* a non-finite indicator value was produced */
+};
+
+/* Operators (update cores).  op_params per operator:
+ *   CAHN_HILLIARD {M, kappa}: c' = (c - dt M k^2 N)/(1 + dt M kappa k^4),
+ *       N = F[c^3 - c]; conserved dynamics of Supplementary S3.1 with a
+ *       double-well f(c) = (c^2 - 1)^2 / 4, semi-implicit as in S4.2.
+ *   GRAY_SCOTT {Du, Dv, F, k}: u' = (u + dt R_u)/(1 + dt Du k^2), likewise v,
+ *       R_u = -u v^2 + F (1 - u), R_v = u v^2 - (F + k) v (S4.2 semi-implicit
+ *       update with a diagonal diffusion matrix).
+ *   NLSE {beta2, gamma, alpha}: symmetric split step (S5.2); each linear half
+ *       step E' = exp[(-alpha/2 + i beta2 w^2/2) h/2] E is one sp-DBA update,
+ *       the Kerr step E <- E exp(i gamma |E|^2 h) runs in the time domain.
+ *       dx is the sample spacing, dt the step h; w = 2 pi m / (n dx).       */
+enum { SPDBA_OP_CAHN_HILLIARD = 1, SPDBA_OP_GRAY_SCOTT = 2, SPDBA_OP_NLSE = 3 };
+enum { SPDBA_F32 = 0, SPDBA_F64 = 1 };
+
+enum {
+    SPDBA_FLAG_DENSE = 1u << 0,        /* Regular mode (paper mode 0): update every block */
+    SPDBA_FLAG_PIN_K0 = 1u << 1,       /* block 0 (k = 0) always active                    */
+    SPDBA_FLAG_GRAPH = 1u << 2,        /* spdba_step replays a captured HIP graph          */
+    SPDBA_FLAG_TIMING = 1u << 3        /* record per-stage HIP events (stats.stage_ms)     */
+};
+
+typedef struct {
+    int32_t ndim;          /* 1, 2 or 3                                           */
+    int32_t op;            /* SPDBA_OP_*, equal for every instance of a plan      */
+    int64_t dims[3];       /* {nz, ny, nx}, unused leading axes 1                 */
+    int32_t block[3];      /* block edges per axis, unused 1                      */
+    int32_t dtype;         /* SPDBA_F32 / SPDBA_F64, equal for every instance     */
+    uint32_t flags;        /* SPDBA_FLAG_*, equal for every instance              */
+    int32_t reserved;      /* must be 0                                           */
+    double threshold;      /* tau >= 0                                            */
+    double dx;             /* grid spacing (NLSE: sample spacing)                 */
+    double dt;             /* time step (NLSE: propagation step h)                */
+    double op_params[8];   /* see the operator list above; unused entries 0       */
+} spdba_instance_desc;
+
+typedef struct {
+    int64_t steps;            /* completed spdba_step steps                         */
+    int64_t active_blocks;    /* active blocks of this instance in the last update  */
+    int64_t total_blocks;     /* blocks of this instance                            */
+    double G;                 /* instance max of a_b in the last update             */
+    double mean[2];           /* per-species mean of the current field              */
+    double energy;            /* CH: free energy of the state entering the last step
+                                 (dx^d sum f(c) + kappa/2 dx^d/N sum k^2 |c_k|^2);
+                                 NaN when not available                             */
+    double stage_ms[6];       /* SPDBA_FLAG_TIMING: mean over the last (up to 64)
+                                 spdba_step steps of the per-stage GPU time in ms:
+                                 fft, nonlinear, indicator, compaction, update,
+                                 whole step (plan-wide); HIP events on the plan
+                                 stream, eager steps only                          */
+    int32_t input_preserving_fft; /* 1 if out-of-place inverse transforms keep their
+                                     input (probed at bind), 0 if a copy is used    */
+    int32_t reserved;
+} spdba_stats_t;
+
+typedef struct spdba_plan_s *spdba_plan;
+
+/* Create a plan for n_inst >= 1 instances advancing independently (a batch).
+ * stream: hipStream_t on which all work is enqueued (NULL = default stream).
+ * Validates every descriptor: EINVAL for ndim not in {1,2,3}, unequal or
+ * non-power-of-two used extents, block edges not dividing dims, tau < 0 or NaN,
+ * dt <= 0, dx <= 0, NULL pointers, n_inst < 1; EUNSUPPORTED for mixed op/dtype/
+ * flags across instances or unknown op/dtype.  Creates the rocFFT plans (one
+ * per distinct grid size).  On success *out receives the plan.  Requires a GPU. */
+spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, void *stream,
+                               spdba_plan *out);
+
+/* Device bytes the caller must provide: state (persistent: spectra, FP64 k = 0
+ * scalars) and work (scratch: transform buffer, rocFFT work area, indicator,
+ * mask, worklist, partial sums).  Both 256-byte aligned sizes. */
+spdba_status spdba_plan_buffer_sizes(spdba_plan plan, size_t *state_bytes, size_t *work_bytes);
+
+/* Bind caller-owned device buffers (at least the sizes above, 256-byte aligned).
+ * Uploads the instance table and probes the transforms.  The state contents
+ * are undefined until spdba_set_field / spdba_set_spectrum. */
+spdba_status spdba_plan_bind(spdba_plan plan, void *d_state, void *d_work);
+
+/* Load instance `inst`'s initial field (real space / time domain), device
+ * array in the working precision: CH n reals (c); GS 2n reals (u then v);
+ * NLSE n complex (E).  Transforms it into the stored state. */
+spdba_status spdba_set_field(spdba_plan plan, int32_t inst, const void *d_real);
+
+/* Write instance `inst`'s current field to d_out (same layout as set_field). */
+spdba_status spdba_get_field(spdba_plan plan, int32_t inst, void *d_out);
+
+/* Raw access to the stored transform-domain state of `inst` (nspec x n
+ * complex, working precision; for NLSE the spectrum that the next update
+ * acts on).  For F32 CH/GS the k = 0 coefficients are exchanged in FP64 via
+ * h_k0 (host, nspec doubles; NULL in set_spectrum = take slot 0 of d_hat;
+ * get_spectrum then writes slot 0 of d_hat as 0).  get_spectrum synchronises. */
+spdba_status spdba_set_spectrum(spdba_plan plan, int32_t inst, const void *d_hat, const double *h_k0);
+spdba_status spdba_get_spectrum(spdba_plan plan, int32_t inst, void *d_hat, double *h_k0);
+
+/* n_steps full steps of every instance (asynchronous).  Per step for CH/GS:
+ * inverse FFT, fused nonlinear term, forward FFT, indicator, compaction, active
+ * update (or dense update); NLSE: two linear half steps around the Kerr step,
+ * each half step with its own indicator and mask. */
+spdba_status spdba_step(spdba_plan plan, int32_t n_steps);
+
+/* Update stage only (the paper's spdba_apply): with right-hand side d_rhs_hat
+ * (device, all instances concatenated in instance order, nspec x n complex
+ * each; ignored for NLSE, may be NULL) and, for F32 CH/GS, its FP64 k = 0 values
+ * h_rhs_k0 (host, n_inst x nspec doubles, NULL = slot 0 of d_rhs_hat). */
+spdba_status spdba_apply(spdba_plan plan, const void *d_rhs_hat, const double *h_rhs_k0);
+
+/* Skip set for the learned proposer: d_skip (device, one byte per block over
+ * all instances, 1 = frozen without evaluation; caller-owned, must stay valid)
+ * is read by every later update; NULL clears it.  Block 0 of an instance with
+ * PIN_K0 is never skipped.  Skipped blocks report a_b = 0 and are excluded
+ * from G. */
+spdba_status spdba_set_skip(spdba_plan plan, const uint8_t *d_skip);
+
+/* Synchronising read-backs of the last update of instance `inst` (host arrays):
+ * the 0/1 mask (n >= blocks), a_b values and G (n >= blocks), and the ordered
+ * active-block worklist as instance-local block ids (n >= blocks). */
+spdba_status spdba_active_mask(spdba_plan plan, int32_t inst, uint8_t *host_out, size_t n);
+spdba_status spdba_indicator(spdba_plan plan, int32_t inst, double *host_ab, size_t n, double *host_G);
+spdba_status spdba_worklist(spdba_plan plan, int32_t inst, uint32_t *host_out, size_t n, int64_t *count);
+
+/* Device views for on-device consumers (the proposer): pointers into the work
+ * buffer, valid until the next step; NULL arguments are skipped. */
+spdba_status spdba_device_views(spdba_plan plan, const double **d_ab, const uint8_t **d_mask,
+                                int64_t *total_blocks);
+
+/* Synchronising statistics of instance `inst`. */
+spdba_status spdba_stats(spdba_plan plan, int32_t inst, spdba_stats_t *out);
+
+/* Launch geometry (autotuner hook): kernel 0 = indicator, 1 = update,
+ * 2 = dense update, 3 = nonlinear term; value = waves per workgroup (1..16,
+ * power of two) for 0 and 3, workgroups per CU for the persistent update 1,
+ * threads per workgroup (64..1024) for 2. */
+spdba_status spdba_set_launch(spdba_plan plan, int32_t kernel, int32_t value);
+
+/* Release the plan (host metadata, rocFFT plans, graphs).  NULL-safe. */
+spdba_status spdba_destroy(spdba_plan plan);
+
+/* Static description of a status code. */
+const char *spdba_status_string(spdba_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPDBA_H */

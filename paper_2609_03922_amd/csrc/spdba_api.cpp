@@ -1,0 +1,882 @@
+// spdba_api.cpp -- host side of the sp-DBA library: descriptor validation,
+// buffer layout, rocFFT plans, stage sequencing, HIP-graph replay and
+// read-backs.  Implements the C ABI declared in include/spdba.h.
+//
+// The host never touches field data: every step of the method runs in the HIP
+// kernels of spdba_kernels.hip or in rocFFT.
+
+#include "spdba.h"
+#include "spdba_internal.h"
+
+#include <rocfft/rocfft.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <vector>
+
+using namespace spdba;
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+std::once_flag g_rocfft_once;
+rocfft_status g_rocfft_setup = rocfft_status_success;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// One rocFFT plan with its input-preservation property.
+struct Fft {
+    rocfft_plan plan = nullptr;
+    bool preserves = true;  // out-of-place plans: input survives execution
+};
+
+// Instances of one grid size, contiguous in memory (transform batch).
+struct Group {
+    int64_t N = 0;
+    int count = 0;
+    int64_t off = 0;       // first complex element of the group
+    Fft inv_oop, fwd_ip;   // batched: CH/GS inverse state->work, forward in place on work
+    Fft inv_ip;            // batched in-place inverse (NLSE, or CH/GS copy fallback)
+    Fft inv1_oop, fwd1_ip, inv1_ip;  // one instance (nspec transforms)
+};
+
+}  // namespace
+
+struct spdba_plan_s {
+    std::vector<spdba_instance_desc> desc;
+    std::vector<InstDev> hinst;      // host copy of the device table (original order)
+    std::vector<uint16_t> blk_inst;  // owning instance per global block
+    std::vector<int> group_of;       // instance -> group
+    std::vector<Group> groups;
+    int n_inst = 0, op = 0, nspec = 1, ndim = 1;
+    bool dbl = false, dense = false, pin = false, use_graph = false, timing = false;
+    hipStream_t stream = nullptr;
+    int64_t total_elems = 0, nb_total = 0, n_strips = 0, n_tiles = 0, n_chunks = 0;
+    size_t esize = 8;  // bytes per complex element
+    size_t fft_work = 0;
+    // buffer layout
+    size_t st_spec = 0, st_k0 = 0, state_bytes = 0;
+    size_t w_W = 0, w_fft = 0, w_ab = 0, w_mask = 0, w_wl = 0, w_chunk = 0, w_cnt = 0, w_G = 0,
+           w_Glast = 0, w_rk0 = 0, w_nl = 0, w_ind = 0, w_dense = 0, w_binst = 0, w_table = 0,
+           w_probe = 0, work_bytes = 0;
+    bool bound = false;
+    char *d_state = nullptr, *d_work = nullptr;
+    Ctx ctx{};
+    rocfft_execution_info info = nullptr;
+    int64_t steps = 0;
+    bool last_dense = false;
+    bool inv_preserving = true;
+    // launch geometry
+    int ind_waves = 4, nl_waves = 4, upd_per_cu = 4, dense_threads = 256, cu_count = 256;
+    // graph of one step
+    hipGraphExec_t graph = nullptr;
+    bool graph_failed = false;
+    // stage events: a ring of per-step sets, read only after the stream drained
+    static constexpr int kRing = 64;
+    hipEvent_t ev[kRing][12] = {};
+    bool have_events = false;
+    int ring = 0;         // set used by the step being enqueued
+    int ring_filled = 0;  // sets holding a complete step
+    const uint8_t *d_skip = nullptr;
+};
+
+namespace {
+
+spdba_status dev_err(hipError_t e) { return e == hipSuccess ? SPDBA_OK : SPDBA_EDEVICE; }
+
+#define TRY_HIP(x)                                   \
+    do {                                             \
+        hipError_t _e = (x);                         \
+        if (_e != hipSuccess) return SPDBA_EDEVICE;  \
+    } while (0)
+#define TRY(x)                            \
+    do {                                  \
+        spdba_status _s = (x);            \
+        if (_s != SPDBA_OK) return _s;    \
+    } while (0)
+
+spdba_status validate(const spdba_instance_desc *d, int32_t n, void *) {
+    if (!d || n < 1 || n > 65535) return SPDBA_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        const spdba_instance_desc &x = d[i];
+        if (x.ndim < 1 || x.ndim > 3) return SPDBA_EINVAL;
+        if (x.reserved != 0) return SPDBA_EINVAL;
+        int64_t ext = 0;
+        for (int a = 0; a < 3; ++a) {
+            const int64_t dm = x.dims[a];
+            const int64_t b = x.block[a];
+            const bool used = a >= 3 - x.ndim;
+            if (!used) {
+                if (dm != 1 || b != 1) return SPDBA_EINVAL;
+                continue;
+            }
+            if (!is_pow2(dm) || dm < 2) return SPDBA_EINVAL;
+            if (ext == 0) ext = dm;
+            else if (ext != dm) return SPDBA_EINVAL;
+            if (b < 1 || dm % b != 0) return SPDBA_EINVAL;
+        }
+        if (!(x.threshold >= 0.0) || !std::isfinite(x.threshold)) return SPDBA_EINVAL;
+        if (!(x.dt > 0.0) || !std::isfinite(x.dt)) return SPDBA_EINVAL;
+        if (!(x.dx > 0.0) || !std::isfinite(x.dx)) return SPDBA_EINVAL;
+        for (int p = 0; p < 8; ++p)
+            if (!std::isfinite(x.op_params[p])) return SPDBA_EINVAL;
+        if (x.op < SPDBA_OP_CAHN_HILLIARD || x.op > SPDBA_OP_NLSE) return SPDBA_EUNSUPPORTED;
+        if (x.dtype != SPDBA_F32 && x.dtype != SPDBA_F64) return SPDBA_EUNSUPPORTED;
+        if (x.flags & ~uint32_t(SPDBA_FLAG_DENSE | SPDBA_FLAG_PIN_K0 | SPDBA_FLAG_GRAPH |
+                                SPDBA_FLAG_TIMING))
+            return SPDBA_EUNSUPPORTED;
+        // a lane reads 16 bytes: the x block edge must hold whole lanes
+        const int V = x.dtype == SPDBA_F32 ? 2 : 1;
+        if (x.block[2] < V) return SPDBA_EUNSUPPORTED;
+        if (i > 0 && (x.op != d[0].op || x.dtype != d[0].dtype || x.flags != d[0].flags ||
+                      x.ndim != d[0].ndim))
+            return SPDBA_EUNSUPPORTED;
+    }
+    return SPDBA_OK;
+}
+
+spdba_status create_fft(spdba_plan p, const InstDev &I, Fft &f, bool forward, bool inplace,
+                        int64_t batch) {
+    size_t len[3];
+    const int nd = p->ndim;
+    // rocFFT takes lengths fastest dimension first
+    for (int a = 0; a < nd; ++a) len[a] = (size_t)I.n[2 - a];
+    rocfft_status st = rocfft_plan_create(
+        &f.plan, inplace ? rocfft_placement_inplace : rocfft_placement_notinplace,
+        forward ? rocfft_transform_type_complex_forward : rocfft_transform_type_complex_inverse,
+        p->dbl ? rocfft_precision_double : rocfft_precision_single, (size_t)nd, len, (size_t)batch,
+        nullptr);
+    if (st != rocfft_status_success) return SPDBA_EFFT;
+    size_t wb = 0;
+    if (rocfft_plan_get_work_buffer_size(f.plan, &wb) != rocfft_status_success) return SPDBA_EFFT;
+    p->fft_work = std::max(p->fft_work, wb);
+    return SPDBA_OK;
+}
+
+void destroy_fft(Fft &f) {
+    if (f.plan) rocfft_plan_destroy(f.plan);
+    f.plan = nullptr;
+}
+
+spdba_status exec_fft(spdba_plan p, const Fft &f, void *in, void *out) {
+    void *ib[1] = {in};
+    void *ob[1] = {out};
+    rocfft_status st = rocfft_execute(f.plan, ib, out ? ob : nullptr, p->info);
+    return st == rocfft_status_success ? SPDBA_OK : SPDBA_EFFT;
+}
+
+char *state_ptr(spdba_plan p, int64_t elem_off) { return p->d_state + p->st_spec + elem_off * p->esize; }
+char *work_ptr(spdba_plan p, int64_t elem_off) { return p->d_work + p->w_W + elem_off * p->esize; }
+
+// inverse transform of a state region into the work buffer, keeping the state
+spdba_status inverse_keep(spdba_plan p, const Fft &oop, const Fft &ip, int64_t off, int64_t n_elems) {
+    if (oop.preserves) return exec_fft(p, oop, state_ptr(p, off), work_ptr(p, off));
+    TRY_HIP(hipMemcpyAsync(work_ptr(p, off), state_ptr(p, off), (size_t)n_elems * p->esize,
+                           hipMemcpyDeviceToDevice, p->stream));
+    return exec_fft(p, ip, work_ptr(p, off), nullptr);
+}
+
+void record(spdba_plan p, int i) {
+    if (p->timing && p->have_events && !p->use_graph) (void)hipEventRecord(p->ev[p->ring][i], p->stream);
+}
+
+void ring_advance(spdba_plan p) {
+    if (p->timing && p->have_events && !p->use_graph) {
+        p->ring = (p->ring + 1) % spdba_plan_s::kRing;
+        p->ring_filled = std::min(p->ring_filled + 1, spdba_plan_s::kRing);
+    }
+}
+
+// update stage: indicator + compaction + active update, or the dense update
+spdba_status update_stage(spdba_plan p, int ev_base) {
+    const bool d = p->dbl;
+    if (p->dense) {
+        TRY_HIP(launch_dense(p->ctx, d, p->dense_threads, p->stream));
+        record(p, ev_base + 2);
+        p->last_dense = true;
+        return SPDBA_OK;
+    }
+    TRY_HIP(launch_indicator(p->ctx, d, p->ind_waves, p->stream));
+    record(p, ev_base);
+    TRY_HIP(launch_compact(p->ctx, p->stream));
+    record(p, ev_base + 1);
+    // a multiple of 8: the update splits its list into one segment per XCD
+    const int grid = ((p->cu_count * p->upd_per_cu + 7) / 8) * 8;
+    TRY_HIP(launch_update(p->ctx, d, grid, p->stream));
+    record(p, ev_base + 2);
+    p->last_dense = false;
+    return SPDBA_OK;
+}
+
+// one full step, enqueued on the plan stream
+spdba_status enqueue_step(spdba_plan p) {
+    const bool d = p->dbl;
+    if (p->op != OP_NLSE) {
+        record(p, 0);
+        for (auto &g : p->groups)
+            TRY(inverse_keep(p, g.inv_oop, g.inv_ip, g.off, g.N * g.count * p->nspec));
+        record(p, 1);
+        TRY_HIP(launch_nonlinear(p->ctx, d, p->nl_waves, p->stream));
+        record(p, 2);
+        for (auto &g : p->groups) TRY(exec_fft(p, g.fwd_ip, work_ptr(p, g.off), nullptr));
+        if (p->op == OP_GS && !d) TRY_HIP(launch_k0_rhs(p->ctx, p->stream));
+        record(p, 3);
+        TRY(update_stage(p, 4));
+        return SPDBA_OK;
+    }
+    // NLSE: linear half step, Kerr step, linear half step (all in place on the state)
+    for (int half = 0; half < 2; ++half) {
+        record(p, half ? 6 : 0);
+        for (auto &g : p->groups) TRY(exec_fft(p, g.fwd_ip, state_ptr(p, g.off), nullptr));
+        record(p, half ? 7 : 1);
+        TRY(update_stage(p, half ? 8 : 2));
+        for (auto &g : p->groups) TRY(exec_fft(p, g.inv_ip, state_ptr(p, g.off), nullptr));
+        record(p, half ? 11 : 5);
+        if (half == 0) TRY_HIP(launch_nonlinear(p->ctx, d, p->nl_waves, p->stream));
+    }
+    return SPDBA_OK;
+}
+
+spdba_status probe_preserving(spdba_plan p, Fft &oop, int64_t off, int64_t n_elems) {
+    uint32_t *bad = reinterpret_cast<uint32_t *>(p->d_work + p->w_probe);
+    TRY_HIP(hipMemsetAsync(bad, 0, 4, p->stream));
+    TRY_HIP(launch_fill_pattern(state_ptr(p, off), n_elems, p->dbl, p->stream));
+    TRY(exec_fft(p, oop, state_ptr(p, off), work_ptr(p, off)));
+    TRY_HIP(launch_check_pattern(state_ptr(p, off), n_elems, p->dbl, bad, p->stream));
+    uint32_t h = 0;
+    TRY_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, p->stream));
+    TRY_HIP(hipStreamSynchronize(p->stream));
+    oop.preserves = (h == 0);
+    return SPDBA_OK;
+}
+
+spdba_status check_nonfinite(spdba_plan p) {
+    uint32_t h = 0;
+    TRY_HIP(hipMemcpyAsync(&h, p->ctx.nonfinite, 4, hipMemcpyDeviceToHost, p->stream));
+    TRY_HIP(hipStreamSynchronize(p->stream));
+    if (h) {
+        TRY_HIP(hipMemsetAsync(p->ctx.nonfinite, 0, 4, p->stream));
+        TRY_HIP(hipStreamSynchronize(p->stream));
+        return SPDBA_ENONFINITE;
+    }
+    return SPDBA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *spdba_status_string(spdba_status s) {
+    switch (s) {
+        case SPDBA_OK: return "success";
+        case SPDBA_EINVAL: return "invalid argument";
+        case SPDBA_EUNSUPPORTED: return "unsupported combination";
+        case SPDBA_ESTATE: return "call out of order";
+        case SPDBA_EDEVICE: return "HIP runtime error";
+        case SPDBA_EFFT: return "rocFFT error";
+        case SPDBA_ENONFINITE: return "non-finite indicator value";
+        default: return "unknown status";
+    }
+}
+
+spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, void *stream,
+                               spdba_plan *out) {
+    if (!out) return SPDBA_EINVAL;
+    *out = nullptr;
+    TRY(validate(inst, n_inst, stream));
+    // everything below needs a device
+    int dev = 0;
+    TRY_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    TRY_HIP(hipGetDeviceProperties(&prop, dev));
+    std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
+    if (g_rocfft_setup != rocfft_status_success) return SPDBA_EFFT;
+
+    spdba_plan p = new (std::nothrow) spdba_plan_s();
+    if (!p) return SPDBA_EDEVICE;
+    p->desc.assign(inst, inst + n_inst);
+    p->n_inst = n_inst;
+    p->op = inst[0].op;
+    p->ndim = inst[0].ndim;
+    p->dbl = inst[0].dtype == SPDBA_F64;
+    p->dense = (inst[0].flags & SPDBA_FLAG_DENSE) != 0;
+    p->pin = (inst[0].flags & SPDBA_FLAG_PIN_K0) != 0;
+    p->use_graph = (inst[0].flags & SPDBA_FLAG_GRAPH) != 0;
+    p->timing = (inst[0].flags & SPDBA_FLAG_TIMING) != 0;
+    p->nspec = p->op == OP_GS ? 2 : 1;
+    p->stream = reinterpret_cast<hipStream_t>(stream);
+    p->esize = p->dbl ? 16 : 8;
+    p->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    const int V = p->dbl ? 1 : 2;
+    const int64_t TE = p->dbl ? 512 : 1024;
+
+    // memory order: larger grids first, original order within a size
+    std::vector<int> order(n_inst);
+    std::iota(order.begin(), order.end(), 0);
+    auto Nof = [&](int i) { return inst[i].dims[0] * inst[i].dims[1] * inst[i].dims[2]; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return Nof(a) > Nof(b); });
+    std::vector<int64_t> mem_off(n_inst);
+    int64_t acc = 0;
+    p->group_of.assign(n_inst, -1);
+    for (int k = 0; k < n_inst; ++k) {
+        const int i = order[k];
+        const int64_t N = Nof(i);
+        if (p->groups.empty() || p->groups.back().N != N) {
+            Group g;
+            g.N = N;
+            g.off = acc;
+            p->groups.push_back(g);
+        }
+        p->groups.back().count++;
+        p->group_of[i] = (int)p->groups.size() - 1;
+        mem_off[i] = acc;
+        acc += N * p->nspec;
+    }
+    p->total_elems = acc;
+
+    // per-instance table in original order
+    int64_t blk = 0, strip = 0, tile = 0;
+    p->hinst.resize(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        const spdba_instance_desc &x = inst[i];
+        InstDev I;
+        std::memset(&I, 0, sizeof(I));
+        I.off = mem_off[i];
+        I.N = Nof(i);
+        for (int a = 0; a < 3; ++a) {
+            I.n[a] = (int32_t)x.dims[a];
+            I.b[a] = x.block[a];
+            I.nbk[a] = (int32_t)(x.dims[a] / x.block[a]);
+        }
+        I.nb = (int64_t)I.nbk[0] * I.nbk[1] * I.nbk[2];
+        I.blk_off = blk;
+        blk += I.nb;
+        I.S = std::min<int>(I.nbk[2], std::max(1, 64 * V / I.b[2]));
+        I.chunks = std::max(1, I.b[2] / (64 * V));
+        I.nstrips = (int64_t)I.nbk[0] * I.nbk[1] * (I.nbk[2] / I.S);
+        I.strip_off = strip;
+        strip += I.nstrips;
+        I.ntiles = (I.N + TE - 1) / TE;
+        I.tile_off = tile;
+        tile += I.ntiles;
+        I.nspec = p->nspec;
+        I.k0path = (!p->dbl && p->op != OP_NLSE) ? 1 : 0;
+        I.pin = p->pin ? 1 : 0;
+        const int64_t ext = x.dims[2];
+        const double K = kTwoPi / ((double)ext * x.dx);
+        I.K2 = K * K;
+        I.tau2 = x.threshold * x.threshold;
+        I.invN = 1.0 / (double)I.N;
+        double dvol = 1.0;
+        for (int a = 0; a < x.ndim; ++a) dvol *= x.dx;
+        I.dvol = dvol;
+        if (p->op == OP_CH) {
+            I.c0 = x.dt * x.op_params[0];
+            I.c1 = I.c0 * x.op_params[1];
+        } else if (p->op == OP_GS) {
+            I.c0 = x.dt;
+            I.c1 = x.dt * x.op_params[0];
+            I.c2 = x.dt * x.op_params[1];
+            I.q0 = x.op_params[2];
+            I.q1 = x.op_params[3];
+        } else {
+            I.c0 = ((x.op_params[0] * x.dt) * 0.25) * I.K2;
+            I.c1 = std::exp(-(x.op_params[2] * x.dt) * 0.25);
+            I.q0 = x.op_params[1] * x.dt;
+        }
+        p->hinst[i] = I;
+    }
+    p->nb_total = blk;
+    p->n_strips = strip;
+    p->n_tiles = tile;
+    p->n_chunks = (blk + CHUNK_BLOCKS - 1) / CHUNK_BLOCKS;
+    if (blk > 0xFFFFFFFFll) {
+        delete p;
+        return SPDBA_EUNSUPPORTED;
+    }
+    p->blk_inst.resize(blk);
+    for (int i = 0; i < n_inst; ++i)
+        for (int64_t b = 0; b < p->hinst[i].nb; ++b) p->blk_inst[p->hinst[i].blk_off + b] = (uint16_t)i;
+
+    // rocFFT plans, one set per grid size
+    spdba_status st = SPDBA_OK;
+    for (auto &g : p->groups) {
+        int rep = -1;
+        for (int i = 0; i < n_inst; ++i)
+            if (p->group_of[i] == (int)(&g - &p->groups[0])) { rep = i; break; }
+        const InstDev &I = p->hinst[rep];
+        const int64_t batch = (int64_t)g.count * p->nspec;
+        if (p->op == OP_NLSE) {
+            if ((st = create_fft(p, I, g.fwd_ip, true, true, batch))) break;
+            if ((st = create_fft(p, I, g.inv_ip, false, true, batch))) break;
+        } else {
+            if ((st = create_fft(p, I, g.inv_oop, false, false, batch))) break;
+            if ((st = create_fft(p, I, g.fwd_ip, true, true, batch))) break;
+            if ((st = create_fft(p, I, g.inv_ip, false, true, batch))) break;
+            if ((st = create_fft(p, I, g.inv1_oop, false, false, p->nspec))) break;
+            if ((st = create_fft(p, I, g.fwd1_ip, true, true, p->nspec))) break;
+            if ((st = create_fft(p, I, g.inv1_ip, false, true, p->nspec))) break;
+        }
+    }
+    if (st == SPDBA_OK && rocfft_execution_info_create(&p->info) != rocfft_status_success)
+        st = SPDBA_EFFT;
+    if (st == SPDBA_OK && p->stream &&
+        rocfft_execution_info_set_stream(p->info, p->stream) != rocfft_status_success)
+        st = SPDBA_EFFT;
+    if (st != SPDBA_OK) {
+        spdba_destroy(p);
+        return st;
+    }
+
+    // buffer layout
+    size_t o = 0;
+    p->st_spec = o;
+    o = align256(o + (size_t)p->total_elems * p->esize);
+    p->st_k0 = o;
+    o = align256(o + (size_t)n_inst * 2 * sizeof(double));
+    p->state_bytes = o;
+    o = 0;
+    auto take = [&o](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    p->w_W = take((size_t)p->total_elems * p->esize);
+    p->w_fft = take(std::max<size_t>(p->fft_work, 256));
+    p->w_ab = take((size_t)blk * sizeof(double));
+    p->w_mask = take((size_t)blk);
+    p->w_wl = take((size_t)blk * sizeof(uint32_t));
+    p->w_chunk = take((size_t)p->n_chunks * sizeof(uint32_t));
+    p->w_cnt = take(8);
+    p->w_G = take((size_t)n_inst * 8);
+    p->w_Glast = take((size_t)n_inst * 8);
+    p->w_rk0 = take((size_t)n_inst * 2 * sizeof(double));
+    p->w_nl = take((size_t)tile * 2 * sizeof(double));
+    p->w_ind = take((size_t)strip * sizeof(double));
+    p->w_dense = take((size_t)tile * sizeof(double));
+    p->w_binst = take((size_t)blk * sizeof(uint16_t));
+    p->w_table = take((size_t)n_inst * sizeof(InstDev));
+    p->w_probe = take(8);
+    p->work_bytes = o;
+    *out = p;
+    return SPDBA_OK;
+}
+
+spdba_status spdba_plan_buffer_sizes(spdba_plan p, size_t *state_bytes, size_t *work_bytes) {
+    if (!p) return SPDBA_EINVAL;
+    if (state_bytes) *state_bytes = p->state_bytes;
+    if (work_bytes) *work_bytes = p->work_bytes;
+    return SPDBA_OK;
+}
+
+spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
+    if (!p || !d_state || !d_work) return SPDBA_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(d_state) & 255) || (reinterpret_cast<uintptr_t>(d_work) & 255))
+        return SPDBA_EINVAL;
+    p->d_state = static_cast<char *>(d_state);
+    p->d_work = static_cast<char *>(d_work);
+    if (p->fft_work > 0 &&
+        rocfft_execution_info_set_work_buffer(p->info, p->d_work + p->w_fft, p->fft_work) !=
+            rocfft_status_success)
+        return SPDBA_EFFT;
+    Ctx &c = p->ctx;
+    c.inst = reinterpret_cast<const InstDev *>(p->d_work + p->w_table);
+    c.n_inst = p->n_inst;
+    c.nspec = p->nspec;
+    c.op = p->op;
+    c.dense = p->dense ? 1 : 0;
+    c.state = p->d_state + p->st_spec;
+    c.work = p->d_work + p->w_W;
+    c.k0 = reinterpret_cast<double *>(p->d_state + p->st_k0);
+    c.rhs_k0 = reinterpret_cast<double *>(p->d_work + p->w_rk0);
+    c.a_b = reinterpret_cast<double *>(p->d_work + p->w_ab);
+    c.G = reinterpret_cast<unsigned long long *>(p->d_work + p->w_G);
+    c.G_last = reinterpret_cast<unsigned long long *>(p->d_work + p->w_Glast);
+    c.mask = reinterpret_cast<uint8_t *>(p->d_work + p->w_mask);
+    c.worklist = reinterpret_cast<uint32_t *>(p->d_work + p->w_wl);
+    c.chunk_cnt = reinterpret_cast<uint32_t *>(p->d_work + p->w_chunk);
+    c.count = reinterpret_cast<uint32_t *>(p->d_work + p->w_cnt);
+    c.nonfinite = reinterpret_cast<uint32_t *>(p->d_work + p->w_cnt + 4);
+    c.nl_part = reinterpret_cast<double *>(p->d_work + p->w_nl);
+    c.ind_part = reinterpret_cast<double *>(p->d_work + p->w_ind);
+    c.dense_part = reinterpret_cast<double *>(p->d_work + p->w_dense);
+    c.blk_inst = reinterpret_cast<const uint16_t *>(p->d_work + p->w_binst);
+    c.skip = p->d_skip;
+    c.nb_total = p->nb_total;
+    c.n_strips = p->n_strips;
+    c.n_tiles = p->n_tiles;
+    c.n_chunks = p->n_chunks;
+    TRY_HIP(hipMemcpyAsync(p->d_work + p->w_table, p->hinst.data(), p->hinst.size() * sizeof(InstDev),
+                           hipMemcpyHostToDevice, p->stream));
+    TRY_HIP(hipMemcpyAsync(p->d_work + p->w_binst, p->blk_inst.data(),
+                           p->blk_inst.size() * sizeof(uint16_t), hipMemcpyHostToDevice, p->stream));
+    TRY_HIP(hipMemsetAsync(p->d_state + p->st_k0, 0, (size_t)p->n_inst * 2 * sizeof(double), p->stream));
+    TRY_HIP(hipMemsetAsync(c.rhs_k0, 0, (size_t)p->n_inst * 2 * sizeof(double), p->stream));
+    TRY_HIP(hipMemsetAsync(c.count, 0, 8, p->stream));
+    TRY_HIP(hipMemsetAsync(c.mask, 0, (size_t)p->nb_total, p->stream));
+    TRY_HIP(hipMemsetAsync(c.a_b, 0, (size_t)p->nb_total * sizeof(double), p->stream));
+    TRY_HIP(launch_reset(c, p->stream));
+    if (p->dense) {  // Regular mode: every block active, the list is every block
+        std::vector<uint32_t> all((size_t)p->nb_total);
+        std::iota(all.begin(), all.end(), 0u);
+        const uint32_t cnt = (uint32_t)p->nb_total;
+        TRY_HIP(hipMemsetAsync(c.mask, 1, (size_t)p->nb_total, p->stream));
+        TRY_HIP(hipMemcpyAsync(c.worklist, all.data(), all.size() * 4, hipMemcpyHostToDevice, p->stream));
+        TRY_HIP(hipMemcpyAsync(c.count, &cnt, 4, hipMemcpyHostToDevice, p->stream));
+        TRY_HIP(hipStreamSynchronize(p->stream));
+    }
+    TRY_HIP(hipStreamSynchronize(p->stream));
+    p->bound = true;
+    // out-of-place inverse transforms: does the input survive?
+    p->inv_preserving = true;
+    if (p->op != OP_NLSE) {
+        for (auto &g : p->groups) {
+            TRY(probe_preserving(p, g.inv_oop, g.off, g.N * g.count * p->nspec));
+            TRY(probe_preserving(p, g.inv1_oop, g.off, g.N * p->nspec));
+            p->inv_preserving = p->inv_preserving && g.inv_oop.preserves && g.inv1_oop.preserves;
+        }
+        TRY_HIP(hipMemsetAsync(p->d_state + p->st_spec, 0, (size_t)p->total_elems * p->esize, p->stream));
+        TRY_HIP(hipStreamSynchronize(p->stream));
+    }
+    if (p->timing && !p->have_events) {
+        for (auto &set : p->ev)
+            for (auto &e : set) TRY_HIP(hipEventCreate(&e));
+        p->have_events = true;
+    }
+    return SPDBA_OK;
+}
+
+spdba_status spdba_set_field(spdba_plan p, int32_t inst, const void *d_real) {
+    if (!p || !d_real || inst < 0 || inst >= p->n_inst) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    const InstDev &I = p->hinst[inst];
+    const int64_t n = I.N * p->nspec;
+    if (p->op == OP_NLSE) {
+        TRY_HIP(launch_scale_copy(p->dbl, d_real, state_ptr(p, I.off), n, (double)I.N, p->stream));
+        return SPDBA_OK;
+    }
+    const Group &g = p->groups[p->group_of[inst]];
+    TRY_HIP(launch_real_to_complex(p->ctx, p->dbl, inst, d_real, n, p->stream));
+    TRY(exec_fft(p, g.fwd1_ip, work_ptr(p, I.off), nullptr));
+    TRY_HIP(launch_copy_spectrum(p->ctx, p->dbl, inst, work_ptr(p, I.off), state_ptr(p, I.off), n,
+                                 I.k0path, nullptr, p->stream));
+    if (I.k0path) TRY_HIP(launch_real_sums_to_k0(p->ctx, p->dbl, inst, d_real, I.ntiles, p->stream));
+    return SPDBA_OK;
+}
+
+spdba_status spdba_get_field(spdba_plan p, int32_t inst, void *d_out) {
+    if (!p || !d_out || inst < 0 || inst >= p->n_inst) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    const InstDev &I = p->hinst[inst];
+    const int64_t n = I.N * p->nspec;
+    if (p->op == OP_NLSE) {
+        TRY_HIP(launch_scale_copy(p->dbl, state_ptr(p, I.off), d_out, n, I.invN, p->stream));
+        return SPDBA_OK;
+    }
+    const Group &g = p->groups[p->group_of[inst]];
+    TRY(inverse_keep(p, g.inv1_oop, g.inv1_ip, I.off, n));
+    TRY_HIP(launch_work_to_real(p->ctx, p->dbl, inst, d_out, n, p->stream));
+    return SPDBA_OK;
+}
+
+spdba_status spdba_set_spectrum(spdba_plan p, int32_t inst, const void *d_hat, const double *h_k0) {
+    if (!p || !d_hat || inst < 0 || inst >= p->n_inst) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    const InstDev &I = p->hinst[inst];
+    const int64_t n = I.N * p->nspec;
+    double *k0 = p->ctx.k0 + 2 * inst;
+    TRY_HIP(launch_copy_spectrum(p->ctx, p->dbl, inst, d_hat, state_ptr(p, I.off), n, I.k0path,
+                                 (I.k0path && !h_k0) ? k0 : nullptr, p->stream));
+    if (I.k0path && h_k0) {
+        TRY_HIP(hipMemcpyAsync(k0, h_k0, (size_t)p->nspec * sizeof(double), hipMemcpyHostToDevice,
+                               p->stream));
+        TRY_HIP(hipStreamSynchronize(p->stream));
+    }
+    return SPDBA_OK;
+}
+
+spdba_status spdba_get_spectrum(spdba_plan p, int32_t inst, void *d_hat, double *h_k0) {
+    if (!p || !d_hat || inst < 0 || inst >= p->n_inst) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    const InstDev &I = p->hinst[inst];
+    TRY_HIP(hipMemcpyAsync(d_hat, state_ptr(p, I.off), (size_t)(I.N * p->nspec) * p->esize,
+                           hipMemcpyDeviceToDevice, p->stream));
+    if (h_k0) {
+        double tmp[2] = {0.0, 0.0};
+        TRY_HIP(hipMemcpyAsync(tmp, p->ctx.k0 + 2 * inst, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                               p->stream));
+        TRY_HIP(hipStreamSynchronize(p->stream));
+        for (int s = 0; s < p->nspec; ++s) h_k0[s] = I.k0path ? tmp[s] : 0.0;
+    }
+    TRY_HIP(hipStreamSynchronize(p->stream));
+    return check_nonfinite(p);
+}
+
+spdba_status spdba_step(spdba_plan p, int32_t n_steps) {
+    if (!p || n_steps < 0) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    if (n_steps == 0) return SPDBA_OK;
+    if (p->use_graph && !p->graph_failed) {
+        if (!p->graph) {
+            hipGraph_t gr = nullptr;
+            hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeRelaxed);
+            spdba_status st = SPDBA_OK;
+            if (e == hipSuccess) st = enqueue_step(p);
+            hipError_t e2 = hipStreamEndCapture(p->stream, &gr);
+            if (e != hipSuccess || st != SPDBA_OK || e2 != hipSuccess || !gr ||
+                hipGraphInstantiate(&p->graph, gr, nullptr, nullptr, 0) != hipSuccess) {
+                p->graph = nullptr;
+                p->graph_failed = true;
+                (void)hipGetLastError();
+            }
+            if (gr) (void)hipGraphDestroy(gr);
+        }
+        if (p->graph) {
+            for (int i = 0; i < n_steps; ++i) TRY_HIP(hipGraphLaunch(p->graph, p->stream));
+            p->steps += n_steps;
+            return SPDBA_OK;
+        }
+    }
+    for (int i = 0; i < n_steps; ++i) {
+        TRY(enqueue_step(p));
+        ring_advance(p);
+        p->steps++;
+    }
+    return SPDBA_OK;
+}
+
+spdba_status spdba_apply(spdba_plan p, const void *d_rhs_hat, const double *h_rhs_k0) {
+    if (!p) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    if (p->op != OP_NLSE) {
+        if (!d_rhs_hat) return SPDBA_EINVAL;
+        int64_t src = 0;
+        for (int i = 0; i < p->n_inst; ++i) {
+            const InstDev &I = p->hinst[i];
+            const int64_t n = I.N * p->nspec;
+            const char *sp = static_cast<const char *>(d_rhs_hat) + src * p->esize;
+            TRY_HIP(launch_copy_spectrum(p->ctx, p->dbl, i, sp, work_ptr(p, I.off), n, 0,
+                                         (I.k0path && !h_rhs_k0) ? p->ctx.rhs_k0 + 2 * i : nullptr,
+                                         p->stream));
+            src += n;
+        }
+        if (h_rhs_k0 && !p->dbl) {
+            std::vector<double> tmp((size_t)p->n_inst * 2, 0.0);
+            for (int i = 0; i < p->n_inst; ++i)
+                for (int s = 0; s < p->nspec; ++s) tmp[2 * i + s] = h_rhs_k0[i * p->nspec + s];
+            TRY_HIP(hipMemcpyAsync(p->ctx.rhs_k0, tmp.data(), tmp.size() * sizeof(double),
+                                   hipMemcpyHostToDevice, p->stream));
+            TRY_HIP(hipStreamSynchronize(p->stream));
+        }
+    }
+    // the update stage alone: events 3..6 of a CH/GS step
+    record(p, 3);
+    TRY(update_stage(p, p->op == OP_NLSE ? 2 : 4));
+    return SPDBA_OK;
+}
+
+spdba_status spdba_set_skip(spdba_plan p, const uint8_t *d_skip) {
+    if (!p) return SPDBA_EINVAL;
+    p->d_skip = d_skip;
+    p->ctx.skip = d_skip;
+    if (p->graph) {  // the captured graph holds the old pointer
+        (void)hipGraphExecDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    return SPDBA_OK;
+}
+
+spdba_status spdba_active_mask(spdba_plan p, int32_t inst, uint8_t *host_out, size_t n) {
+    if (!p || !host_out || inst < 0 || inst >= p->n_inst) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    const InstDev &I = p->hinst[inst];
+    if (n < (size_t)I.nb) return SPDBA_EINVAL;
+    TRY_HIP(hipMemcpyAsync(host_out, p->ctx.mask + I.blk_off, (size_t)I.nb, hipMemcpyDeviceToHost,
+                           p->stream));
+    return check_nonfinite(p);
+}
+
+spdba_status spdba_indicator(spdba_plan p, int32_t inst, double *host_ab, size_t n, double *host_G) {
+    if (!p || inst < 0 || inst >= p->n_inst) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    const InstDev &I = p->hinst[inst];
+    if (host_ab) {
+        if (n < (size_t)I.nb) return SPDBA_EINVAL;
+        TRY_HIP(hipMemcpyAsync(host_ab, p->ctx.a_b + I.blk_off, (size_t)I.nb * sizeof(double),
+                               hipMemcpyDeviceToHost, p->stream));
+    }
+    if (host_G) {
+        unsigned long long g = 0;
+        TRY_HIP(hipMemcpyAsync(&g, p->ctx.G_last + inst, 8, hipMemcpyDeviceToHost, p->stream));
+        TRY_HIP(hipStreamSynchronize(p->stream));
+        double v;
+        std::memcpy(&v, &g, 8);
+        *host_G = v;
+    }
+    return check_nonfinite(p);
+}
+
+spdba_status spdba_worklist(spdba_plan p, int32_t inst, uint32_t *host_out, size_t n, int64_t *count) {
+    if (!p || !host_out || !count || inst < 0 || inst >= p->n_inst) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    const InstDev &I = p->hinst[inst];
+    if (n < (size_t)I.nb) return SPDBA_EINVAL;
+    uint32_t total = 0;
+    TRY_HIP(hipMemcpyAsync(&total, p->ctx.count, 4, hipMemcpyDeviceToHost, p->stream));
+    TRY_HIP(hipStreamSynchronize(p->stream));
+    std::vector<uint32_t> all(total);
+    if (total)
+        TRY_HIP(hipMemcpyAsync(all.data(), p->ctx.worklist, (size_t)total * 4, hipMemcpyDeviceToHost,
+                               p->stream));
+    TRY_HIP(hipStreamSynchronize(p->stream));
+    int64_t k = 0;
+    for (uint32_t v : all)
+        if ((int64_t)v >= I.blk_off && (int64_t)v < I.blk_off + I.nb) host_out[k++] = (uint32_t)(v - I.blk_off);
+    *count = k;
+    return check_nonfinite(p);
+}
+
+spdba_status spdba_device_views(spdba_plan p, const double **d_ab, const uint8_t **d_mask,
+                                int64_t *total_blocks) {
+    if (!p) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    if (d_ab) *d_ab = p->ctx.a_b;
+    if (d_mask) *d_mask = p->ctx.mask;
+    if (total_blocks) *total_blocks = p->nb_total;
+    return SPDBA_OK;
+}
+
+spdba_status spdba_stats(spdba_plan p, int32_t inst, spdba_stats_t *out) {
+    if (!p || !out || inst < 0 || inst >= p->n_inst) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    std::memset(out, 0, sizeof(*out));
+    const InstDev &I = p->hinst[inst];
+    std::vector<uint8_t> mk((size_t)I.nb);
+    TRY_HIP(hipMemcpyAsync(mk.data(), p->ctx.mask + I.blk_off, (size_t)I.nb, hipMemcpyDeviceToHost,
+                           p->stream));
+    unsigned long long g = 0;
+    TRY_HIP(hipMemcpyAsync(&g, p->ctx.G_last + inst, 8, hipMemcpyDeviceToHost, p->stream));
+    double k0[2] = {0.0, 0.0};
+    TRY_HIP(hipMemcpyAsync(k0, p->ctx.k0 + 2 * inst, 16, hipMemcpyDeviceToHost, p->stream));
+    double slot0[2][2] = {{0, 0}, {0, 0}};
+    if (p->dbl && p->op != OP_NLSE)
+        for (int s = 0; s < p->nspec; ++s)
+            TRY_HIP(hipMemcpyAsync(slot0[s], state_ptr(p, I.off + s * I.N), 16, hipMemcpyDeviceToHost,
+                                   p->stream));
+    std::vector<double> nlp, egp;
+    if (p->op == OP_CH && p->steps > 0) {
+        nlp.resize((size_t)I.ntiles * 2);
+        TRY_HIP(hipMemcpyAsync(nlp.data(), p->ctx.nl_part + 2 * I.tile_off, nlp.size() * 8,
+                               hipMemcpyDeviceToHost, p->stream));
+        if (p->last_dense) {
+            egp.resize((size_t)I.ntiles);
+            TRY_HIP(hipMemcpyAsync(egp.data(), p->ctx.dense_part + I.tile_off, egp.size() * 8,
+                                   hipMemcpyDeviceToHost, p->stream));
+        } else {
+            egp.resize((size_t)I.nstrips);
+            TRY_HIP(hipMemcpyAsync(egp.data(), p->ctx.ind_part + I.strip_off, egp.size() * 8,
+                                   hipMemcpyDeviceToHost, p->stream));
+        }
+    }
+    TRY_HIP(hipStreamSynchronize(p->stream));
+    out->steps = p->steps;
+    out->total_blocks = I.nb;
+    int64_t a = 0;
+    for (uint8_t v : mk) a += v;
+    out->active_blocks = a;
+    std::memcpy(&out->G, &g, 8);
+    for (int s = 0; s < p->nspec; ++s)
+        out->mean[s] = p->op == OP_NLSE ? 0.0 : (I.k0path ? k0[s] : slot0[s][0]) * I.invN;
+    out->energy = NAN;
+    if (!nlp.empty()) {
+        double bulk = 0.0, grad = 0.0;
+        for (int64_t t = 0; t < I.ntiles; ++t) bulk += nlp[2 * t];
+        for (double v : egp) grad += v;
+        out->energy = I.dvol * bulk + 0.5 * p->desc[inst].op_params[1] * (I.dvol * I.invN) * grad;
+    }
+    if (p->timing && p->have_events && p->ring_filled > 0) {
+        // mean over the completed steps held in the ring (the stream has drained)
+        const int nset = p->ring_filled;
+        double acc6[6] = {0, 0, 0, 0, 0, 0};
+        for (int k = 1; k <= nset; ++k) {
+            hipEvent_t *ev = p->ev[(p->ring - k + spdba_plan_s::kRing) % spdba_plan_s::kRing];
+            auto el = [&](int a0, int b0) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, ev[a0], ev[b0]) != hipSuccess) return 0.0;
+                return (double)ms;
+            };
+            double st[6] = {0, 0, 0, 0, 0, 0};
+            if (p->op != OP_NLSE) {
+                st[0] = el(0, 1) + el(2, 3);
+                st[1] = el(1, 2);
+                if (!p->last_dense) {
+                    st[2] = el(3, 4);
+                    st[3] = el(4, 5);
+                    st[4] = el(5, 6);
+                } else {
+                    st[4] = el(3, 6);
+                }
+                st[5] = el(0, 6);
+            } else {
+                st[0] = el(0, 1) + el(6, 7) + el(4, 5) + el(10, 11);
+                if (!p->last_dense) {
+                    st[2] = el(1, 2) + el(7, 8);
+                    st[3] = el(2, 3) + el(8, 9);
+                    st[4] = el(3, 4) + el(9, 10);
+                } else {
+                    st[4] = el(1, 4) + el(7, 10);
+                }
+                st[1] = el(5, 6);
+                st[5] = el(0, 11);
+            }
+            for (int j = 0; j < 6; ++j) acc6[j] += st[j];
+        }
+        for (int j = 0; j < 6; ++j) out->stage_ms[j] = acc6[j] / nset;
+    }
+    out->input_preserving_fft = p->inv_preserving ? 1 : 0;
+    return check_nonfinite(p);
+}
+
+spdba_status spdba_set_launch(spdba_plan p, int32_t kernel, int32_t value) {
+    if (!p) return SPDBA_EINVAL;
+    auto pow2_in = [](int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; };
+    switch (kernel) {
+        case 0: if (!pow2_in(value, 1, 16)) return SPDBA_EINVAL; p->ind_waves = value; break;
+        case 1: if (value < 1 || value > 64) return SPDBA_EINVAL; p->upd_per_cu = value; break;
+        case 2: if (!pow2_in(value, 64, 1024)) return SPDBA_EINVAL; p->dense_threads = value; break;
+        case 3: if (!pow2_in(value, 1, 16)) return SPDBA_EINVAL; p->nl_waves = value; break;
+        default: return SPDBA_EINVAL;
+    }
+    if (p->graph) {
+        (void)hipGraphExecDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    return SPDBA_OK;
+}
+
+spdba_status spdba_destroy(spdba_plan p) {
+    if (!p) return SPDBA_OK;
+    if (p->graph) (void)hipGraphExecDestroy(p->graph);
+    for (auto &g : p->groups) {
+        destroy_fft(g.inv_oop);
+        destroy_fft(g.fwd_ip);
+        destroy_fft(g.inv_ip);
+        destroy_fft(g.inv1_oop);
+        destroy_fft(g.fwd1_ip);
+        destroy_fft(g.inv1_ip);
+    }
+    if (p->info) rocfft_execution_info_destroy(p->info);
+    if (p->have_events)
+        for (auto &set : p->ev)
+            for (auto &e : set) (void)hipEventDestroy(e);
+    delete p;
+    return SPDBA_OK;
+}
+
+}  // extern "C"

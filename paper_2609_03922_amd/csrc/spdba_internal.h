@@ -1,0 +1,99 @@
+// spdba_internal.h -- device-side instance table and kernel launchers shared by
+// the host API (spdba_api.cpp) and the HIP kernels (spdba_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spdba {
+
+enum Op : int { OP_CH = 1, OP_GS = 2, OP_NLSE = 3 };
+
+// Per-instance constants, uploaded once at bind.  Offsets are in complex
+// elements (state and transform buffers share one layout) or block / strip /
+// tile ids in the concatenated spaces of all instances.
+struct InstDev {
+    int64_t off;        // first complex element of species 0 in state / work
+    int64_t N;          // modes per species
+    int64_t blk_off;    // first global block id
+    int64_t nb;         // blocks
+    int64_t strip_off;  // first global indicator strip id
+    int64_t nstrips;
+    int64_t tile_off;   // first global elementwise tile id
+    int64_t ntiles;
+    int32_t n[3];       // nz, ny, nx
+    int32_t b[3];       // block edges
+    int32_t nbk[3];     // blocks per axis
+    int32_t S;          // blocks per strip along x
+    int32_t chunks;     // 64-lane chunks per block row (when a block row is wider than a wave row)
+    int32_t nspec;
+    int32_t k0path;     // 1: FP32 real field, k = 0 kept in FP64
+    int32_t pin;        // PIN_K0
+    double K2;          // (2 pi / (n dx))^2
+    double c0, c1, c2;  // CH: dt*M, dt*M*kappa, -; GS: dt, dt*Du, dt*Dv; NLSE: theta/m^2, A, -
+    double tau2;        // fl(tau*tau)
+    double invN;        // 1/N (exact power of two)
+    double q0, q1;      // nonlinear parameters: GS F, k; NLSE gamma*h, -
+    double dvol;        // dx^d
+};
+
+// Everything a kernel needs, passed by value.
+struct Ctx {
+    const InstDev *inst;
+    int32_t n_inst;
+    int32_t nspec;
+    int32_t op;
+    int32_t dense;
+    void *state;               // complex T
+    void *work;                // complex T
+    double *k0;                // [n_inst][2] FP64 k = 0 state
+    double *rhs_k0;            // [n_inst][2]
+    double *a_b;               // [nb_total]
+    unsigned long long *G;     // [n_inst] bits of a non-negative double
+    unsigned long long *G_last;// [n_inst] G of the last completed update
+    uint8_t *mask;             // [nb_total]
+    uint32_t *worklist;        // [nb_total] global block ids, ascending
+    uint32_t *chunk_cnt;       // [n_chunks]
+    uint32_t *count;           // [1] active blocks over all instances
+    double *nl_part;           // [n_tiles][2] per-tile FP64 sums of the nonlinear stage
+    double *ind_part;          // [n_strips] per-strip FP64 sums (CH gradient energy)
+    double *dense_part;        // [n_tiles] per-tile FP64 sums of the dense update
+    uint32_t *nonfinite;       // [1]
+    const uint16_t *blk_inst;  // [nb_total] owning instance of each block
+    const uint8_t *skip;       // [nb_total] or nullptr
+    int64_t nb_total;
+    int64_t n_strips;
+    int64_t n_tiles;
+    int64_t n_chunks;
+};
+
+constexpr int TILE_THREADS = 256;
+constexpr int CHUNK_BLOCKS = 1024;  // compaction chunk
+
+// elementwise tile size in complex elements per dtype (FP32: 4 per thread, FP64: 2)
+template <typename T> constexpr int tile_elems() { return sizeof(T) == 4 ? 1024 : 512; }
+
+// Launchers (return hipError_t of the launch).  `dbl` selects FP64.
+hipError_t launch_nonlinear(const Ctx &c, bool dbl, int waves, hipStream_t s);
+hipError_t launch_k0_rhs(const Ctx &c, hipStream_t s);
+hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s);
+hipError_t launch_compact(const Ctx &c, hipStream_t s);
+hipError_t launch_update(const Ctx &c, bool dbl, int grid, hipStream_t s);
+hipError_t launch_dense(const Ctx &c, bool dbl, int threads, hipStream_t s);
+hipError_t launch_reset(const Ctx &c, hipStream_t s);
+// set_field / get_field helpers on one instance (sizes from the host table)
+hipError_t launch_real_to_complex(const Ctx &c, bool dbl, int inst, const void *real, int64_t n,
+                                  hipStream_t s);
+hipError_t launch_real_sums_to_k0(const Ctx &c, bool dbl, int inst, const void *real,
+                                  int64_t ntiles, hipStream_t s);
+hipError_t launch_work_to_real(const Ctx &c, bool dbl, int inst, void *out, int64_t n,
+                               hipStream_t s);
+hipError_t launch_scale_copy(bool dbl, const void *src, void *dst, int64_t n_complex, double scale,
+                             hipStream_t s);
+hipError_t launch_copy_spectrum(const Ctx &c, bool dbl, int inst, const void *src, void *dst,
+                                int64_t n, int zero_slot0, double *k0_dst, hipStream_t s);
+// probe helpers
+hipError_t launch_fill_pattern(void *buf, int64_t n_elems, bool dbl, hipStream_t s);
+hipError_t launch_check_pattern(const void *buf, int64_t n_elems, bool dbl, uint32_t *bad, hipStream_t s);
+
+}  // namespace spdba

@@ -1,0 +1,919 @@
+// spdba_kernels.hip -- gfx950 kernels of the sp-DBA transform-domain update.
+//
+// Stages of one step (Methods, "Spectral dynamic block activation"; the
+// transformed-field update of Supplementary S2.1):
+//   k_nonlinear  fused real-space term on the inverse-transformed field
+//   k_indicator  candidate increment of every mode, FP64 a(k), block max a_b,
+//                instance max G (order-free atomic max on the bit pattern)
+//   k_compact_*  threshold, per-block mask and the ascending active-block list
+//   k_update     persistent walk of the active list: model update of every mode
+//                of each active block; frozen blocks are never touched
+//   k_dense      Regular mode: the same update core over every mode
+//
+// Memory-bound throughout: vector loads of 16 B per lane, each wave row covers
+// at least 1 KiB of contiguous coefficients, partial sums in FP64 in a fixed
+// order (no floating-point atomics), integer-exact compaction.  The rounding
+// of the update core is fixed (explicit fma, coefficients formed in FP64 from
+// the exact integer m^2 and rounded once) so that masks are reproducible bit
+// for bit by any implementation of the same arithmetic.
+//
+// Built with -ffp-contract=off: every fused multiply-add is written out.
+
+#include "spdba_internal.h"
+
+#include <float.h>
+
+namespace spdba {
+
+// -------------------------------------------------------------------------
+// small helpers
+// -------------------------------------------------------------------------
+
+__device__ __forceinline__ int sidx(int i, int n) { return (2 * i < n) ? i : i - n; }
+
+__device__ __forceinline__ int find_by_offset(const InstDev *ins, int n, int64_t id, int which) {
+    // binary search for the last instance whose offset (strip/tile) <= id
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        int64_t o = which == 0 ? ins[mid].strip_off : ins[mid].tile_off;
+        if (o <= id) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T> struct CV;
+template <> struct CV<float> {
+    static constexpr int V = 2;  // complex values per 16-byte lane access
+    __device__ static void ld(const float *p, float (&re)[2], float (&im)[2]) {
+        float4 v = *reinterpret_cast<const float4 *>(p);
+        re[0] = v.x; im[0] = v.y; re[1] = v.z; im[1] = v.w;
+    }
+    __device__ static void st(float *p, const float (&re)[2], const float (&im)[2]) {
+        *reinterpret_cast<float4 *>(p) = make_float4(re[0], im[0], re[1], im[1]);
+    }
+};
+template <> struct CV<double> {
+    static constexpr int V = 1;
+    __device__ static void ld(const double *p, double (&re)[1], double (&im)[1]) {
+        double2 v = *reinterpret_cast<const double2 *>(p);
+        re[0] = v.x; im[0] = v.y;
+    }
+    __device__ static void st(double *p, const double (&re)[1], const double (&im)[1]) {
+        *reinterpret_cast<double2 *>(p) = make_double2(re[0], im[0]);
+    }
+};
+
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ void sc_t(float x, float &s, float &c) { sincosf(x, &s, &c); }
+__device__ __forceinline__ void sc_t(double x, double &s, double &c) { sincos(x, &s, &c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// sin and cos: Cody-Waite reduction by pi/2 (three-part constant, fdlibm
+// split) and Taylor series of sin / cos on |r| <= pi/4, Horner with fma.
+__device__ __forceinline__ void sincos_cw(double x, double &sn, double &cs) {
+    const double q = rint(x * 6.36619772367581382433e-01);
+    double r = __builtin_fma(-q, 1.57079632673412561417e+00, x);
+    r = __builtin_fma(-q, 6.07710050630396597660e-11, r);
+    r = __builtin_fma(-q, 2.02226624879595063154e-21, r);
+    const double r2 = r * r;
+    double ps = 1.0 / 355687428096000.0;
+    ps = __builtin_fma(ps, r2, -1.0 / 1307674368000.0);
+    ps = __builtin_fma(ps, r2, 1.0 / 6227020800.0);
+    ps = __builtin_fma(ps, r2, -1.0 / 39916800.0);
+    ps = __builtin_fma(ps, r2, 1.0 / 362880.0);
+    ps = __builtin_fma(ps, r2, -1.0 / 5040.0);
+    ps = __builtin_fma(ps, r2, 1.0 / 120.0);
+    ps = __builtin_fma(ps, r2, -1.0 / 6.0);
+    const double s = __builtin_fma(r * r2, ps, r);
+    double pc = -1.0 / 6402373705728000.0;
+    pc = __builtin_fma(pc, r2, 1.0 / 20922789888000.0);
+    pc = __builtin_fma(pc, r2, -1.0 / 87178291200.0);
+    pc = __builtin_fma(pc, r2, 1.0 / 479001600.0);
+    pc = __builtin_fma(pc, r2, -1.0 / 3628800.0);
+    pc = __builtin_fma(pc, r2, 1.0 / 40320.0);
+    pc = __builtin_fma(pc, r2, -1.0 / 720.0);
+    pc = __builtin_fma(pc, r2, 1.0 / 24.0);
+    pc = __builtin_fma(pc, r2, -0.5);
+    const double c = __builtin_fma(r2, pc, 1.0);
+    const int qi = (int)((long long)q & 3);
+    if (qi == 0) { sn = s; cs = c; }
+    else if (qi == 1) { sn = c; cs = -s; }
+    else if (qi == 2) { sn = -s; cs = -c; }
+    else { sn = -c; cs = s; }
+}
+
+// -------------------------------------------------------------------------
+// update cores (identical arithmetic in indicator, active update and dense)
+// -------------------------------------------------------------------------
+
+// CH: s = dt M k^2, a = 1/(1 + dt M kappa k^4) in FP64, then working precision.
+template <typename T>
+__device__ __forceinline__ void ch_coef(const InstDev &I, long long m2, T &s, T &a) {
+    const double k2 = I.K2 * (double)m2;
+    const double sd = I.c0 * k2;
+    const double ad = 1.0 / (1.0 + I.c1 * (k2 * k2));
+    s = (T)sd;
+    a = (T)ad;
+}
+template <typename T>
+__device__ __forceinline__ void gs_coef(const InstDev &I, long long m2, T &au, T &av) {
+    const double k2 = I.K2 * (double)m2;
+    au = (T)(1.0 / (1.0 + I.c1 * k2));
+    av = (T)(1.0 / (1.0 + I.c2 * k2));
+}
+template <typename T>
+__device__ __forceinline__ void nlse_coef(const InstDev &I, long long m2, T &hr, T &hi) {
+    double sn, cs;
+    sincos_cw(I.c0 * (double)m2, sn, cs);
+    hr = (T)(I.c1 * cs);
+    hi = (T)(I.c1 * sn);
+}
+
+__device__ __forceinline__ double sq2(double dr, double di) { return dr * dr + di * di; }
+
+// Candidate of one CH mode and its squared increment.
+template <typename T>
+__device__ __forceinline__ double ch_cand(T s, T a, T qr, T qi, T nr, T ni, T &cr, T &ci) {
+    cr = fmat(-s, nr, qr) * a;
+    ci = fmat(-s, ni, qi) * a;
+    return sq2((double)cr - (double)qr, (double)ci - (double)qi);
+}
+template <typename T>
+__device__ __forceinline__ double gs_cand(T dt, T a, T qr, T qi, T rr, T ri, T &cr, T &ci) {
+    cr = fmat(dt, rr, qr) * a;
+    ci = fmat(dt, ri, qi) * a;
+    return sq2((double)cr - (double)qr, (double)ci - (double)qi);
+}
+template <typename T>
+__device__ __forceinline__ double nlse_cand(T hr, T hi, T er, T ei, T &cr, T &ci) {
+    cr = fmat(hr, er, -(hi * ei));
+    ci = fmat(hr, ei, hi * er);
+    return sq2((double)cr - (double)er, (double)ci - (double)ei);
+}
+
+// FP64 k = 0 candidate of the real-field operators (coefficients at k = 0).
+__device__ __forceinline__ double k0_cand(const InstDev &I, int op, const double *k0,
+                                          const double *rk0, double *out) {
+    if (op == OP_CH) {
+        const double s = I.c0 * 0.0;
+        const double a = 1.0 / (1.0 + I.c1 * (0.0 * 0.0));
+        out[0] = __builtin_fma(-s, rk0[0], k0[0]) * a;
+        return sq2(out[0] - k0[0], 0.0);
+    }
+    const double au = 1.0 / (1.0 + I.c1 * 0.0);
+    const double av = 1.0 / (1.0 + I.c2 * 0.0);
+    out[0] = __builtin_fma(I.c0, rk0[0], k0[0]) * au;
+    out[1] = __builtin_fma(I.c0, rk0[1], k0[1]) * av;
+    return sq2(out[0] - k0[0], 0.0) + sq2(out[1] - k0[1], 0.0);
+}
+
+// -------------------------------------------------------------------------
+// deterministic reductions
+// -------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Sum over the workgroup in a fixed order: butterfly within each wave, then
+// wave totals added in wave order by thread 0.  Result valid in thread 0.
+template <int NQ>
+__device__ __forceinline__ void block_sum(double (&v)[NQ], double *lds /* [NQ][16] */) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) lds[q * 16 + w] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            double t = 0.0;
+            for (int i = 0; i < nw; ++i) t += lds[q * 16 + i];
+            v[q] = t;
+        }
+    }
+}
+
+// -------------------------------------------------------------------------
+// fused real-space nonlinear term (one pass, in place on the transform buffer)
+// -------------------------------------------------------------------------
+
+template <typename T, int OP>
+__global__ void __launch_bounds__(1024) k_nonlinear(Ctx c) {
+    constexpr int V = CV<T>::V;
+    constexpr int TE = tile_elems<T>();
+    __shared__ double lds[2 * 16];
+    const int64_t tile = blockIdx.x;
+    const int ii = find_by_offset(c.inst, c.n_inst, tile, 1);
+    const InstDev &I = c.inst[ii];
+    const int64_t t0 = (tile - I.tile_off) * TE;
+    T *base = reinterpret_cast<T *>(OP == OP_NLSE ? c.state : c.work) + 2 * I.off;
+    double acc[2] = {0.0, 0.0};
+    if (OP == OP_CH) {
+        const T invN = (T)I.invN;
+        const T mean = I.k0path ? (T)(c.k0[2 * ii] * I.invN) : (T)0;
+        for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
+            const int64_t e = t0 + j;
+            if (e >= I.N) break;
+            T re[V], im[V];
+            CV<T>::ld(base + 2 * e, re, im);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const T cc = re[v] * invN + mean;
+                re[v] = cc * cc * cc - cc;
+                im[v] = (T)0;
+                const double cd = (double)cc;
+                const double t = cd * cd - 1.0;
+                acc[0] += 0.25 * (t * t);
+                acc[1] += (double)re[v];
+            }
+            CV<T>::st(base + 2 * e, re, im);
+        }
+    } else if (OP == OP_GS) {
+        const T invN = (T)I.invN;
+        const T mu = I.k0path ? (T)(c.k0[2 * ii] * I.invN) : (T)0;
+        const T mv = I.k0path ? (T)(c.k0[2 * ii + 1] * I.invN) : (T)0;
+        const T F = (T)I.q0, Fk = (T)(I.q0 + I.q1);
+        T *bu = base, *bv = base + 2 * I.N;
+        for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
+            const int64_t e = t0 + j;
+            if (e >= I.N) break;
+            T ur[V], ui[V], vr[V], vi[V];
+            CV<T>::ld(bu + 2 * e, ur, ui);
+            CV<T>::ld(bv + 2 * e, vr, vi);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const T u = ur[v] * invN + mu;
+                const T w = vr[v] * invN + mv;
+                const T uvv = u * w * w;
+                ur[v] = -uvv + F * ((T)1 - u);
+                vr[v] = uvv - Fk * w;
+                ui[v] = (T)0;
+                vi[v] = (T)0;
+                acc[0] += (double)ur[v];
+                acc[1] += (double)vr[v];
+            }
+            CV<T>::st(bu + 2 * e, ur, ui);
+            CV<T>::st(bv + 2 * e, vr, vi);
+        }
+    } else {
+        const T sc = (T)(I.invN * I.invN);  // stored field carries a factor N^2 here
+        const T gh = (T)I.q0;
+        for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
+            const int64_t e = t0 + j;
+            if (e >= I.N) break;
+            T re[V], im[V];
+            CV<T>::ld(base + 2 * e, re, im);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const T er = re[v] * sc, ei = im[v] * sc;
+                const T ph = gh * (er * er + ei * ei);
+                T sn, cs;
+                sc_t(ph, sn, cs);
+                re[v] = er * cs - ei * sn;
+                im[v] = er * sn + ei * cs;
+            }
+            CV<T>::st(base + 2 * e, re, im);
+        }
+        return;
+    }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+        c.nl_part[2 * tile] = acc[0];
+        c.nl_part[2 * tile + 1] = acc[1];
+    }
+}
+
+// FP64 totals of the per-tile partials of each instance, fixed order.
+// mode 0: nonlinear right-hand side at k = 0 (GS) -> rhs_k0; mode 1: field
+// sums -> k0 (set_field).
+__global__ void __launch_bounds__(256) k_k0_total(Ctx c, int mode, int only_inst) {
+    __shared__ double lds[2 * 16];
+    const int ii = only_inst >= 0 ? only_inst : (int)blockIdx.x;
+    const InstDev &I = c.inst[ii];
+    double acc[2] = {0.0, 0.0};
+    for (int64_t t = threadIdx.x; t < I.ntiles; t += blockDim.x) {
+        acc[0] += c.nl_part[2 * (I.tile_off + t)];
+        acc[1] += c.nl_part[2 * (I.tile_off + t) + 1];
+    }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+        double *dst = mode == 0 ? c.rhs_k0 : c.k0;
+        dst[2 * ii] = acc[0];
+        dst[2 * ii + 1] = I.nspec > 1 ? acc[1] : 0.0;
+    }
+}
+
+// -------------------------------------------------------------------------
+// indicator: one workgroup per strip of S x-adjacent blocks; its waves split
+// the rows of the strip; lanes cover 16 contiguous bytes each.
+// -------------------------------------------------------------------------
+
+template <typename T, int OP>
+__global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
+    constexpr int V = CV<T>::V;
+    constexpr int U = 4;  // rows in flight per wave
+    __shared__ double lds_max[16][64];
+    __shared__ double lds_sum[16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int64_t strip = blockIdx.x;
+    const int ii = find_by_offset(c.inst, c.n_inst, strip, 0);
+    const InstDev &I = c.inst[ii];
+    const int64_t ls = strip - I.strip_off;
+    const int nsx = I.nbk[2] / I.S;
+    const int sx = (int)(ls % nsx);
+    const int64_t t = ls / nsx;
+    const int sby = (int)(t % I.nbk[1]);
+    const int sbz = (int)(t / I.nbk[1]);
+    const int rows = I.b[0] * I.b[1];
+    const int chunks = I.chunks;
+    const int total_it = rows * chunks;
+    const int x_lane = sx * I.S * I.b[2] + lane * V;  // x of this lane in chunk 0
+    // lanes beyond the strip width stay idle (narrow grids)
+    const bool lane_on = chunks > 1 || lane * V < I.S * I.b[2];
+
+    const T *q0p = reinterpret_cast<const T *>(c.state) + 2 * I.off;
+    const T *r0p = reinterpret_cast<const T *>(c.work) + 2 * I.off;
+    const T *q1p = q0p + 2 * I.N;
+    const T *r1p = r0p + 2 * I.N;
+
+    double amax = 0.0, esum = 0.0;
+    bool bad = false;
+    T c0s = 0, c1s = 0;
+    if (OP == OP_GS) c0s = (T)I.c0;
+    (void)c1s;
+
+    for (int it0 = w; it0 < total_it; it0 += nw * U) {
+        T qr[U][V], qi[U][V], nr[U][V], ni[U][V], q2r[U][V], q2i[U][V], n2r[U][V], n2i[U][V];
+        int64_t eidx[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int it = it0 + u * nw;
+            eidx[u] = -1;
+            if (lane_on && it < total_it) {
+                const int r = it / chunks, ch = it - r * chunks;
+                const int z = sbz * I.b[0] + r / I.b[1];
+                const int y = sby * I.b[1] + (r - (r / I.b[1]) * I.b[1]);
+                const int x = x_lane + ch * 64 * V;
+                const int64_t e = ((int64_t)z * I.n[1] + y) * I.n[2] + x;
+                eidx[u] = e;
+                CV<T>::ld(q0p + 2 * e, qr[u], qi[u]);
+                if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr[u], ni[u]);
+                if (OP == OP_GS) {
+                    CV<T>::ld(q1p + 2 * e, q2r[u], q2i[u]);
+                    CV<T>::ld(r1p + 2 * e, n2r[u], n2i[u]);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (eidx[u] < 0) continue;
+            const int64_t e = eidx[u];
+            const int x0 = (int)(e % I.n[2]);
+            const int64_t zy = e / I.n[2];
+            const int y = (int)(zy % I.n[1]);
+            const int z = (int)(zy / I.n[1]);
+            const long long myz = (long long)sidx(z, I.n[0]) * sidx(z, I.n[0]) +
+                                  (long long)sidx(y, I.n[1]) * sidx(y, I.n[1]);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int x = x0 + v;
+                const long long mx = sidx(x, I.n[2]);
+                const long long m2 = myz + mx * mx;
+                double a;
+                if (I.k0path && e + v == 0) {
+                    double tmp[2];
+                    a = k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+                } else if (OP == OP_CH) {
+                    T s, f, cr, ci;
+                    ch_coef<T>(I, m2, s, f);
+                    a = ch_cand<T>(s, f, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
+                    const double k2 = I.K2 * (double)m2;
+                    esum += k2 * sq2((double)qr[u][v], (double)qi[u][v]);
+                } else if (OP == OP_GS) {
+                    T au, av, cr, ci;
+                    gs_coef<T>(I, m2, au, av);
+                    a = gs_cand<T>(c0s, au, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
+                    a = a + gs_cand<T>(c0s, av, q2r[u][v], q2i[u][v], n2r[u][v], n2i[u][v], cr, ci);
+                } else {
+                    T hr, hi, cr, ci;
+                    nlse_coef<T>(I, m2, hr, hi);
+                    a = nlse_cand<T>(hr, hi, qr[u][v], qi[u][v], cr, ci);
+                }
+                bad |= !(a <= DBL_MAX);
+                amax = a > amax ? a : amax;
+            }
+        }
+    }
+    // per-block maximum over the lanes of the block, then over the waves
+    const int LB = chunks > 1 ? 64 : (I.b[2] / V);
+    for (int off = 1; off < LB; off <<= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+    lds_max[w][lane] = amax;
+    if (OP == OP_CH) {
+        esum = wave_sum(esum);
+        if (lane == 0) lds_sum[w] = esum;
+    }
+    if (bad) atomicOr(c.nonfinite, 1u);
+    __syncthreads();
+    if (w == 0) {
+        double m = lds_max[0][lane];
+        for (int i = 1; i < nw; ++i) m = fmax(m, lds_max[i][lane]);
+        const int nblk = chunks > 1 ? 1 : I.S;
+        if (lane % LB == 0 && lane / LB < nblk) {
+            const int bx = sx * I.S + lane / LB;
+            const int64_t lb = ((int64_t)sbz * I.nbk[1] + sby) * I.nbk[2] + bx;
+            const int64_t gb = I.blk_off + lb;
+            const bool skipped = c.skip && c.skip[gb] && !(I.pin && lb == 0);
+            c.a_b[gb] = skipped ? 0.0 : m;
+            if (skipped) m = 0.0;
+        } else {
+            m = 0.0;
+        }
+        const double sm = wave_max(m);
+        if (lane == 0 && sm > 0.0) atomicMax(c.G + ii, (unsigned long long)__double_as_longlong(sm));
+        if (OP == OP_CH && lane == 0) {
+            double tsum = 0.0;
+            for (int i = 0; i < nw; ++i) tsum += lds_sum[i];
+            c.ind_part[strip] = tsum;
+        }
+    }
+}
+
+// -------------------------------------------------------------------------
+// compaction: chunk counts, then ordered write of the active-block list
+// -------------------------------------------------------------------------
+
+__device__ __forceinline__ bool block_active(const Ctx &c, int64_t gb) {
+    const int ii = c.blk_inst[gb];
+    const InstDev &I = c.inst[ii];
+    const int64_t lb = gb - I.blk_off;
+    if (c.dense) return true;
+    if (I.pin && lb == 0) return true;
+    if (c.skip && c.skip[gb]) return false;
+    const double G = __longlong_as_double((long long)c.G[ii]);
+    const double thr = I.tau2 * G;
+    return c.a_b[gb] > thr;
+}
+
+__global__ void __launch_bounds__(256) k_compact_count(Ctx c) {
+    __shared__ uint32_t lds[4];
+    const int64_t base = (int64_t)blockIdx.x * CHUNK_BLOCKS;
+    uint32_t n = 0;
+#pragma unroll
+    for (int k = 0; k < CHUNK_BLOCKS / 256; ++k) {
+        const int64_t gb = base + k * 256 + threadIdx.x;
+        if (gb < c.nb_total) {
+            const bool on = block_active(c, gb);
+            c.mask[gb] = on ? 1 : 0;
+            n += on ? 1u : 0u;
+        }
+    }
+    // integer sum: order-free
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) n += __shfl_xor(n, off, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) c.chunk_cnt[blockIdx.x] = lds[0] + lds[1] + lds[2] + lds[3];
+}
+
+__global__ void __launch_bounds__(256) k_compact_write(Ctx c) {
+    __shared__ uint32_t scan[256];
+    __shared__ uint32_t red[4];
+    const int64_t chunk = blockIdx.x;
+    // offset = sum of the counts of the preceding chunks
+    uint32_t pre = 0;
+    for (int64_t k = threadIdx.x; k < chunk; k += 256) pre += c.chunk_cnt[k];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) pre += __shfl_xor(pre, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pre;
+    // each thread owns 4 consecutive blocks of the chunk
+    const int64_t b0 = chunk * CHUNK_BLOCKS + 4 * threadIdx.x;
+    uint32_t bits = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (b0 + k < c.nb_total && c.mask[b0 + k]) bits |= 1u << k;
+    const uint32_t mine = __popc(bits);
+    scan[threadIdx.x] = mine;
+    __syncthreads();
+    const uint32_t offset = red[0] + red[1] + red[2] + red[3];
+    // inclusive Hillis-Steele scan over 256 entries
+    for (int d = 1; d < 256; d <<= 1) {
+        const uint32_t v = threadIdx.x >= d ? scan[threadIdx.x - d] : 0u;
+        __syncthreads();
+        scan[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t pos = offset + scan[threadIdx.x] - mine;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (bits & (1u << k)) c.worklist[pos++] = (uint32_t)(b0 + k);
+    if (chunk == c.n_chunks - 1 && threadIdx.x == 255) *c.count = offset + scan[255];
+}
+
+// -------------------------------------------------------------------------
+// active-block update: persistent workgroups walk the ordered list.  The list
+// is cut into 8 contiguous segments, one per XCD (workgroup id mod 8), so
+// x-adjacent active blocks that share cache lines meet in the same L2.
+// -------------------------------------------------------------------------
+
+template <typename T, int OP>
+__device__ __forceinline__ void update_block(const Ctx &c, int64_t gb) {
+    constexpr int V = CV<T>::V;
+    const int ii = c.blk_inst[gb];
+    const InstDev &I = c.inst[ii];
+    const int64_t lb = gb - I.blk_off;
+    const int bx = (int)(lb % I.nbk[2]);
+    const int64_t t = lb / I.nbk[2];
+    const int by = (int)(t % I.nbk[1]);
+    const int bz = (int)(t / I.nbk[1]);
+    const int lpr = I.b[2] / V;  // lanes per block row
+    const int slots = I.b[0] * I.b[1] * lpr;
+    T *q0p = reinterpret_cast<T *>(c.state) + 2 * I.off;
+    const T *r0p = reinterpret_cast<const T *>(c.work) + 2 * I.off;
+    T *q1p = q0p + 2 * I.N;
+    const T *r1p = r0p + 2 * I.N;
+    for (int s = threadIdx.x; s < slots; s += blockDim.x) {
+        const int r = s / lpr, l = s - r * lpr;
+        const int z = bz * I.b[0] + r / I.b[1];
+        const int y = by * I.b[1] + (r - (r / I.b[1]) * I.b[1]);
+        const int x0 = bx * I.b[2] + l * V;
+        const int64_t e = ((int64_t)z * I.n[1] + y) * I.n[2] + x0;
+        const long long myz = (long long)sidx(z, I.n[0]) * sidx(z, I.n[0]) +
+                              (long long)sidx(y, I.n[1]) * sidx(y, I.n[1]);
+        T qr[V], qi[V], nr[V], ni[V], q2r[V], q2i[V], n2r[V], n2i[V];
+        CV<T>::ld(q0p + 2 * e, qr, qi);
+        if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr, ni);
+        if (OP == OP_GS) {
+            CV<T>::ld(q1p + 2 * e, q2r, q2i);
+            CV<T>::ld(r1p + 2 * e, n2r, n2i);
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const long long mx = sidx(x0 + v, I.n[2]);
+            const long long m2 = myz + mx * mx;
+            if (I.k0path && e + v == 0) {
+                double tmp[2];
+                k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+                c.k0[2 * ii] = tmp[0];
+                if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
+                qr[v] = qi[v] = (T)0;
+                q2r[v] = q2i[v] = (T)0;
+            } else if (OP == OP_CH) {
+                T s, f, cr, ci;
+                ch_coef<T>(I, m2, s, f);
+                ch_cand<T>(s, f, qr[v], qi[v], nr[v], ni[v], cr, ci);
+                qr[v] = cr;
+                qi[v] = ci;
+            } else if (OP == OP_GS) {
+                T au, av, cr, ci;
+                const T dt = (T)I.c0;
+                gs_coef<T>(I, m2, au, av);
+                gs_cand<T>(dt, au, qr[v], qi[v], nr[v], ni[v], cr, ci);
+                qr[v] = cr;
+                qi[v] = ci;
+                gs_cand<T>(dt, av, q2r[v], q2i[v], n2r[v], n2i[v], cr, ci);
+                q2r[v] = cr;
+                q2i[v] = ci;
+            } else {
+                T hr, hi, cr, ci;
+                nlse_coef<T>(I, m2, hr, hi);
+                nlse_cand<T>(hr, hi, qr[v], qi[v], cr, ci);
+                qr[v] = cr;
+                qi[v] = ci;
+            }
+        }
+        CV<T>::st(q0p + 2 * e, qr, qi);
+        if (OP == OP_GS) CV<T>::st(q1p + 2 * e, q2r, q2i);
+    }
+}
+
+template <typename T, int OP>
+__global__ void __launch_bounds__(256) k_update(Ctx c) {
+    const uint32_t total = *c.count;
+    const int P = gridDim.x;  // multiple of 8
+    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per = P >> 3;
+    const uint32_t seg = (total + 7) / 8;
+    const uint32_t lo = min(total, seg * xcd), hi = min(total, seg * (xcd + 1));
+    for (uint32_t e = lo + local; e < hi; e += per) update_block<T, OP>(c, c.worklist[e]);
+    // the instance maxima are consumed: keep a copy for read-back and clear
+    // them for the next indicator pass
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < c.n_inst; i += blockDim.x) {
+            c.G_last[i] = c.G[i];
+            c.G[i] = 0ull;
+        }
+}
+
+// -------------------------------------------------------------------------
+// Regular (dense) update: the same core over every mode, elementwise tiles
+// -------------------------------------------------------------------------
+
+template <typename T, int OP>
+__global__ void __launch_bounds__(1024) k_dense(Ctx c) {
+    constexpr int V = CV<T>::V;
+    constexpr int TE = tile_elems<T>();
+    __shared__ double lds[16];
+    const int64_t tile = blockIdx.x;
+    const int ii = find_by_offset(c.inst, c.n_inst, tile, 1);
+    const InstDev &I = c.inst[ii];
+    const int64_t t0 = (tile - I.tile_off) * TE;
+    T *q0p = reinterpret_cast<T *>(c.state) + 2 * I.off;
+    const T *r0p = reinterpret_cast<const T *>(c.work) + 2 * I.off;
+    T *q1p = q0p + 2 * I.N;
+    const T *r1p = r0p + 2 * I.N;
+    double acc[1] = {0.0};
+    for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
+        const int64_t e = t0 + j;
+        if (e >= I.N) break;
+        const int x0 = (int)(e % I.n[2]);
+        const int64_t zy = e / I.n[2];
+        const int y = (int)(zy % I.n[1]);
+        const int z = (int)(zy / I.n[1]);
+        const long long myz = (long long)sidx(z, I.n[0]) * sidx(z, I.n[0]) +
+                              (long long)sidx(y, I.n[1]) * sidx(y, I.n[1]);
+        T qr[V], qi[V], nr[V], ni[V], q2r[V], q2i[V], n2r[V], n2i[V];
+        CV<T>::ld(q0p + 2 * e, qr, qi);
+        if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr, ni);
+        if (OP == OP_GS) {
+            CV<T>::ld(q1p + 2 * e, q2r, q2i);
+            CV<T>::ld(r1p + 2 * e, n2r, n2i);
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const long long mx = sidx(x0 + v, I.n[2]);
+            const long long m2 = myz + mx * mx;
+            if (I.k0path && e + v == 0) {
+                double tmp[2];
+                k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+                c.k0[2 * ii] = tmp[0];
+                if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
+                qr[v] = qi[v] = (T)0;
+                q2r[v] = q2i[v] = (T)0;
+            } else if (OP == OP_CH) {
+                T s, f, cr, ci;
+                ch_coef<T>(I, m2, s, f);
+                acc[0] += (I.K2 * (double)m2) * sq2((double)qr[v], (double)qi[v]);
+                ch_cand<T>(s, f, qr[v], qi[v], nr[v], ni[v], cr, ci);
+                qr[v] = cr;
+                qi[v] = ci;
+            } else if (OP == OP_GS) {
+                T au, av, cr, ci;
+                const T dt = (T)I.c0;
+                gs_coef<T>(I, m2, au, av);
+                gs_cand<T>(dt, au, qr[v], qi[v], nr[v], ni[v], cr, ci);
+                qr[v] = cr;
+                qi[v] = ci;
+                gs_cand<T>(dt, av, q2r[v], q2i[v], n2r[v], n2i[v], cr, ci);
+                q2r[v] = cr;
+                q2i[v] = ci;
+            } else {
+                T hr, hi, cr, ci;
+                nlse_coef<T>(I, m2, hr, hi);
+                nlse_cand<T>(hr, hi, qr[v], qi[v], cr, ci);
+                qr[v] = cr;
+                qi[v] = ci;
+            }
+        }
+        CV<T>::st(q0p + 2 * e, qr, qi);
+        if (OP == OP_GS) CV<T>::st(q1p + 2 * e, q2r, q2i);
+    }
+    if (OP == OP_CH) {
+        block_sum<1>(acc, lds);
+        if (threadIdx.x == 0) c.dense_part[tile] = acc[0];
+    }
+}
+
+__global__ void k_reset(Ctx c) {
+    for (int i = threadIdx.x; i < c.n_inst; i += blockDim.x) c.G[i] = c.G_last[i] = 0ull;
+    if (threadIdx.x == 0) *c.count = 0u;
+}
+
+// -------------------------------------------------------------------------
+// field <-> state helpers (one instance)
+// -------------------------------------------------------------------------
+
+// W[s][i] = (real[s][i], 0)
+template <typename T>
+__global__ void k_real_to_complex(Ctx c, int ii, const T *real) {
+    const InstDev &I = c.inst[ii];
+    T *w = reinterpret_cast<T *>(c.work) + 2 * I.off;
+    const int64_t n = I.N * I.nspec;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        w[2 * i] = real[i];
+        w[2 * i + 1] = (T)0;
+    }
+}
+
+// per-tile FP64 sums of a real field (both species) -> nl_part
+template <typename T>
+__global__ void __launch_bounds__(256) k_real_tile_sums(Ctx c, int ii, const T *real) {
+    constexpr int TE = tile_elems<T>();
+    __shared__ double lds[2 * 16];
+    const InstDev &I = c.inst[ii];
+    const int64_t t0 = (int64_t)blockIdx.x * TE;
+    double acc[2] = {0.0, 0.0};
+    for (int j = threadIdx.x; j < TE; j += blockDim.x) {
+        const int64_t e = t0 + j;
+        if (e >= I.N) break;
+        acc[0] += (double)real[e];
+        if (I.nspec > 1) acc[1] += (double)real[I.N + e];
+    }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+        c.nl_part[2 * (I.tile_off + blockIdx.x)] = acc[0];
+        c.nl_part[2 * (I.tile_off + blockIdx.x) + 1] = acc[1];
+    }
+}
+
+// copy an instance spectrum src -> dst; optionally zero slot 0 of each species
+// after storing it (widened to FP64) in k0_dst[species]
+template <typename T>
+__global__ void k_copy_spectrum(Ctx c, int ii, const T *src, T *dst, int zero_slot0, double *k0_dst) {
+    const InstDev &I = c.inst[ii];
+    const int64_t n = I.N * I.nspec;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        T re = src[2 * i], im = src[2 * i + 1];
+        if (zero_slot0 && (i % I.N) == 0) {
+            if (k0_dst) k0_dst[i / I.N] = (double)re;
+            re = (T)0;
+            im = (T)0;
+        }
+        dst[2 * i] = re;
+        dst[2 * i + 1] = im;
+    }
+}
+
+// out[s][i] = Re(W[s][i]) / N + mean_s
+template <typename T>
+__global__ void k_work_to_real(Ctx c, int ii, T *out) {
+    const InstDev &I = c.inst[ii];
+    const T *w = reinterpret_cast<const T *>(c.work) + 2 * I.off;
+    const int64_t n = I.N * I.nspec;
+    const T invN = (T)I.invN;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int s = (int)(i / I.N);
+        const T mean = I.k0path ? (T)(c.k0[2 * ii + s] * I.invN) : (T)0;
+        out[i] = w[2 * i] * invN + mean;
+    }
+}
+
+template <typename T>
+__global__ void k_scale_copy(int64_t n, const T *src, T *dst, T scale) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i] * scale;
+}
+
+template <typename T>
+__global__ void k_fill_pattern(T *buf, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        buf[i] = (T)((i * 2654435761ull) % 1000003ull) * (T)1e-3;
+}
+template <typename T>
+__global__ void k_check_pattern(const T *buf, int64_t n, uint32_t *bad) {
+    uint32_t b = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b |= buf[i] != (T)((i * 2654435761ull) % 1000003ull) * (T)1e-3;
+    if (b) atomicOr(bad, 1u);
+}
+
+// -------------------------------------------------------------------------
+// launchers
+// -------------------------------------------------------------------------
+
+template <typename T>
+static hipError_t nl_launch(const Ctx &c, int waves, hipStream_t s) {
+    dim3 grid((unsigned)c.n_tiles), block(64 * waves);
+    if (c.op == OP_CH) hipLaunchKernelGGL((k_nonlinear<T, OP_CH>), grid, block, 0, s, c);
+    else if (c.op == OP_GS) hipLaunchKernelGGL((k_nonlinear<T, OP_GS>), grid, block, 0, s, c);
+    else hipLaunchKernelGGL((k_nonlinear<T, OP_NLSE>), grid, block, 0, s, c);
+    return hipGetLastError();
+}
+hipError_t launch_nonlinear(const Ctx &c, bool dbl, int waves, hipStream_t s) {
+    return dbl ? nl_launch<double>(c, waves, s) : nl_launch<float>(c, waves, s);
+}
+
+hipError_t launch_k0_rhs(const Ctx &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_k0_total, dim3(c.n_inst), dim3(256), 0, s, c, 0, -1);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t ind_launch(const Ctx &c, int waves, hipStream_t s) {
+    dim3 grid((unsigned)c.n_strips), block(64 * waves);
+    if (c.op == OP_CH) hipLaunchKernelGGL((k_indicator<T, OP_CH>), grid, block, 0, s, c);
+    else if (c.op == OP_GS) hipLaunchKernelGGL((k_indicator<T, OP_GS>), grid, block, 0, s, c);
+    else hipLaunchKernelGGL((k_indicator<T, OP_NLSE>), grid, block, 0, s, c);
+    return hipGetLastError();
+}
+hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s) {
+    return dbl ? ind_launch<double>(c, waves, s) : ind_launch<float>(c, waves, s);
+}
+
+hipError_t launch_compact(const Ctx &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_compact_count, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_compact_write, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t upd_launch(const Ctx &c, int grid, hipStream_t s) {
+    if (c.op == OP_CH) hipLaunchKernelGGL((k_update<T, OP_CH>), dim3(grid), dim3(256), 0, s, c);
+    else if (c.op == OP_GS) hipLaunchKernelGGL((k_update<T, OP_GS>), dim3(grid), dim3(256), 0, s, c);
+    else hipLaunchKernelGGL((k_update<T, OP_NLSE>), dim3(grid), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+hipError_t launch_update(const Ctx &c, bool dbl, int grid, hipStream_t s) {
+    return dbl ? upd_launch<double>(c, grid, s) : upd_launch<float>(c, grid, s);
+}
+
+template <typename T>
+static hipError_t dense_launch(const Ctx &c, int threads, hipStream_t s) {
+    dim3 grid((unsigned)c.n_tiles), block(threads);
+    if (c.op == OP_CH) hipLaunchKernelGGL((k_dense<T, OP_CH>), grid, block, 0, s, c);
+    else if (c.op == OP_GS) hipLaunchKernelGGL((k_dense<T, OP_GS>), grid, block, 0, s, c);
+    else hipLaunchKernelGGL((k_dense<T, OP_NLSE>), grid, block, 0, s, c);
+    return hipGetLastError();
+}
+hipError_t launch_dense(const Ctx &c, bool dbl, int threads, hipStream_t s) {
+    return dbl ? dense_launch<double>(c, threads, s) : dense_launch<float>(c, threads, s);
+}
+
+hipError_t launch_reset(const Ctx &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, c);
+    return hipGetLastError();
+}
+
+static unsigned grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    return (unsigned)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+
+hipError_t launch_real_to_complex(const Ctx &c, bool dbl, int inst, const void *real, int64_t n,
+                                  hipStream_t s) {
+    if (dbl) hipLaunchKernelGGL(k_real_to_complex<double>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (const double *)real);
+    else hipLaunchKernelGGL(k_real_to_complex<float>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (const float *)real);
+    return hipGetLastError();
+}
+
+hipError_t launch_real_sums_to_k0(const Ctx &c, bool dbl, int inst, const void *real,
+                                  int64_t ntiles, hipStream_t s) {
+    if (dbl) hipLaunchKernelGGL(k_real_tile_sums<double>, dim3((unsigned)ntiles), dim3(256), 0, s, c, inst, (const double *)real);
+    else hipLaunchKernelGGL(k_real_tile_sums<float>, dim3((unsigned)ntiles), dim3(256), 0, s, c, inst, (const float *)real);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_k0_total, dim3(1), dim3(256), 0, s, c, 1, inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_work_to_real(const Ctx &c, bool dbl, int inst, void *out, int64_t n,
+                               hipStream_t s) {
+    if (dbl) hipLaunchKernelGGL(k_work_to_real<double>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (double *)out);
+    else hipLaunchKernelGGL(k_work_to_real<float>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (float *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(bool dbl, const void *src, void *dst, int64_t n, double scale,
+                             hipStream_t s) {
+    if (dbl) hipLaunchKernelGGL(k_scale_copy<double>, dim3(grid_for(2 * n)), dim3(256), 0, s, n, (const double *)src, (double *)dst, scale);
+    else hipLaunchKernelGGL(k_scale_copy<float>, dim3(grid_for(2 * n)), dim3(256), 0, s, n, (const float *)src, (float *)dst, (float)scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_spectrum(const Ctx &c, bool dbl, int inst, const void *src, void *dst,
+                                int64_t n, int zero_slot0, double *k0_dst, hipStream_t s) {
+    if (dbl) hipLaunchKernelGGL(k_copy_spectrum<double>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (const double *)src, (double *)dst, zero_slot0, k0_dst);
+    else hipLaunchKernelGGL(k_copy_spectrum<float>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (const float *)src, (float *)dst, zero_slot0, k0_dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_pattern(void *buf, int64_t n, bool dbl, hipStream_t s) {
+    if (dbl) hipLaunchKernelGGL(k_fill_pattern<double>, dim3(grid_for(2 * n)), dim3(256), 0, s, (double *)buf, n);
+    else hipLaunchKernelGGL(k_fill_pattern<float>, dim3(grid_for(2 * n)), dim3(256), 0, s, (float *)buf, n);
+    return hipGetLastError();
+}
+hipError_t launch_check_pattern(const void *buf, int64_t n, bool dbl, uint32_t *bad, hipStream_t s) {
+    if (dbl) hipLaunchKernelGGL(k_check_pattern<double>, dim3(grid_for(2 * n)), dim3(256), 0, s, (const double *)buf, n, bad);
+    else hipLaunchKernelGGL(k_check_pattern<float>, dim3(grid_for(2 * n)), dim3(256), 0, s, (const float *)buf, n, bad);
+    return hipGetLastError();
+}
+
+}  // namespace spdba

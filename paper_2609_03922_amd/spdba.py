@@ -1,0 +1,357 @@
+"""Python binding of libspdba.so (include/spdba.h): argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels and rocFFT; this
+module converts Python values to the C ABI and back.  PyTorch provides device
+memory and the stream.  If the library is not built the import of any entry
+point fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspdba.so")
+
+SPDBA_OK, SPDBA_EINVAL, SPDBA_EUNSUPPORTED, SPDBA_ESTATE = 0, 1, 2, 3
+SPDBA_EDEVICE, SPDBA_EFFT, SPDBA_ENONFINITE = 4, 5, 6
+SPDBA_OP_CAHN_HILLIARD, SPDBA_OP_GRAY_SCOTT, SPDBA_OP_NLSE = 1, 2, 3
+SPDBA_F32, SPDBA_F64 = 0, 1
+SPDBA_FLAG_DENSE, SPDBA_FLAG_PIN_K0, SPDBA_FLAG_GRAPH, SPDBA_FLAG_TIMING = 1, 2, 4, 8
+
+OPS = {"ch": SPDBA_OP_CAHN_HILLIARD, "gs": SPDBA_OP_GRAY_SCOTT, "nlse": SPDBA_OP_NLSE}
+DTYPES = {"f32": SPDBA_F32, "f64": SPDBA_F64}
+
+# every entry point the header declares
+EXPORTS = (
+    "spdba_plan_create", "spdba_plan_buffer_sizes", "spdba_plan_bind", "spdba_set_field",
+    "spdba_get_field", "spdba_set_spectrum", "spdba_get_spectrum", "spdba_step", "spdba_apply",
+    "spdba_set_skip", "spdba_active_mask", "spdba_indicator", "spdba_worklist",
+    "spdba_device_views", "spdba_stats", "spdba_set_launch", "spdba_destroy",
+    "spdba_status_string",
+)
+
+
+class SpdbaError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+class InstanceDesc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("op", ctypes.c_int32),
+        ("dims", ctypes.c_int64 * 3),
+        ("block", ctypes.c_int32 * 3),
+        ("dtype", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_int32),
+        ("threshold", ctypes.c_double),
+        ("dx", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("op_params", ctypes.c_double * 8),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int64),
+        ("active_blocks", ctypes.c_int64),
+        ("total_blocks", ctypes.c_int64),
+        ("G", ctypes.c_double),
+        ("mean", ctypes.c_double * 2),
+        ("energy", ctypes.c_double),
+        ("stage_ms", ctypes.c_double * 6),
+        ("input_preserving_fft", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load libspdba.so (import torch first so that one HIP runtime is shared)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "spdba_plan_create": [ctypes.POINTER(InstanceDesc), I32, P, ctypes.POINTER(P)],
+        "spdba_plan_buffer_sizes": [P, ctypes.POINTER(SZ), ctypes.POINTER(SZ)],
+        "spdba_plan_bind": [P, P, P],
+        "spdba_set_field": [P, I32, P],
+        "spdba_get_field": [P, I32, P],
+        "spdba_set_spectrum": [P, I32, P, P],
+        "spdba_get_spectrum": [P, I32, P, P],
+        "spdba_step": [P, I32],
+        "spdba_apply": [P, P, P],
+        "spdba_set_skip": [P, P],
+        "spdba_active_mask": [P, I32, P, SZ],
+        "spdba_indicator": [P, I32, P, SZ, P],
+        "spdba_worklist": [P, I32, P, SZ, ctypes.POINTER(I64)],
+        "spdba_device_views": [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(I64)],
+        "spdba_stats": [P, I32, ctypes.POINTER(Stats)],
+        "spdba_set_launch": [P, I32, I32],
+        "spdba_destroy": [P],
+        "spdba_status_string": [I32],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name == "spdba_status_string" else ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+def status_string(s: int) -> str:
+    return load().spdba_status_string(int(s)).decode()
+
+
+def _ck(status: int, where: str):
+    if status != SPDBA_OK:
+        raise SpdbaError(status, where)
+
+
+@dataclass
+class Desc:
+    """One instance: operator, precision, grid, block shape, threshold, parameters."""
+
+    op: str
+    dtype: str
+    ndim: int
+    n: int
+    block: int
+    tau: float
+    dx: float
+    dt: float
+    params: tuple
+    dense: bool = False
+    pin_k0: bool = True
+    graph: bool = False
+    timing: bool = False
+
+    @property
+    def dims3(self):
+        return tuple([1] * (3 - self.ndim) + [self.n] * self.ndim)
+
+    @property
+    def block3(self):
+        return tuple([1] * (3 - self.ndim) + [self.block] * self.ndim)
+
+    @property
+    def n_modes(self):
+        return self.n ** self.ndim
+
+    @property
+    def n_blocks(self):
+        return (self.n // self.block) ** self.ndim
+
+    @property
+    def nspec(self):
+        return 2 if self.op == "gs" else 1
+
+    def to_c(self) -> InstanceDesc:
+        d = InstanceDesc()
+        d.ndim = self.ndim
+        d.op = OPS[self.op]
+        for a in range(3):
+            d.dims[a] = self.dims3[a]
+            d.block[a] = self.block3[a]
+        d.dtype = DTYPES[self.dtype]
+        d.flags = ((SPDBA_FLAG_DENSE if self.dense else 0) | (SPDBA_FLAG_PIN_K0 if self.pin_k0 else 0)
+                   | (SPDBA_FLAG_GRAPH if self.graph else 0) | (SPDBA_FLAG_TIMING if self.timing else 0))
+        d.reserved = 0
+        d.threshold = float(self.tau)
+        d.dx, d.dt = float(self.dx), float(self.dt)
+        pp = list(self.params) + [0.0] * (8 - len(self.params))
+        for i in range(8):
+            d.op_params[i] = float(pp[i])
+        return d
+
+
+def descs_array(descs):
+    arr = (InstanceDesc * len(descs))()
+    for i, d in enumerate(descs):
+        arr[i] = d.to_c() if isinstance(d, Desc) else d
+    return arr
+
+
+def spdba_plan_create(descs, stream=None) -> ctypes.c_void_p:
+    arr = descs_array(descs)
+    h = ctypes.c_void_p()
+    _ck(load().spdba_plan_create(arr, len(descs), stream, ctypes.byref(h)), "spdba_plan_create")
+    return h
+
+
+def spdba_plan_create_status(descs, stream=None) -> int:
+    """Status of plan creation only (no plan kept); used by validation tests."""
+    arr = descs_array(descs)
+    h = ctypes.c_void_p()
+    st = load().spdba_plan_create(arr, len(descs), stream, ctypes.byref(h))
+    if st == SPDBA_OK:
+        load().spdba_destroy(h)
+    return st
+
+
+class Plan:
+    """A bound plan with torch-owned state and work buffers."""
+
+    def __init__(self, descs, stream=None):
+        import torch
+
+        self.descs = list(descs)
+        self.torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.h = spdba_plan_create(self.descs, ctypes.c_void_p(self.stream.cuda_stream))
+        lib = load()
+        sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        _ck(lib.spdba_plan_buffer_sizes(self.h, ctypes.byref(sb), ctypes.byref(wb)), "buffer_sizes")
+        self.state_bytes, self.work_bytes = sb.value, wb.value
+        # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks
+        self.d_state = torch.empty(self.state_bytes + 256, dtype=torch.uint8, device="cuda")
+        self.d_work = torch.empty(self.work_bytes + 256, dtype=torch.uint8, device="cuda")
+        sp = self._aligned(self.d_state)
+        wp = self._aligned(self.d_work)
+        _ck(lib.spdba_plan_bind(self.h, sp, wp), "spdba_plan_bind")
+        self._skip = None
+
+    @staticmethod
+    def _aligned(t):
+        p = t.data_ptr()
+        return ctypes.c_void_p((p + 255) & ~255)
+
+    # ---- dtype helpers --------------------------------------------------
+    def _real_dtype(self, i):
+        return self.torch.float64 if self.descs[i].dtype == "f64" else self.torch.float32
+
+    def _cplx_dtype(self, i):
+        return self.torch.complex128 if self.descs[i].dtype == "f64" else self.torch.complex64
+
+    # ---- field / spectrum -----------------------------------------------
+    def set_field(self, i, field):
+        d = self.descs[i]
+        want = self._cplx_dtype(i) if d.op == "nlse" else self._real_dtype(i)
+        field = field.to(device="cuda", dtype=want).contiguous()
+        assert field.numel() == d.n_modes * d.nspec
+        _ck(load().spdba_set_field(self.h, i, ctypes.c_void_p(field.data_ptr())), "spdba_set_field")
+        self.stream.synchronize()
+
+    def get_field(self, i):
+        d = self.descs[i]
+        want = self._cplx_dtype(i) if d.op == "nlse" else self._real_dtype(i)
+        out = self.torch.empty(d.n_modes * d.nspec, dtype=want, device="cuda")
+        _ck(load().spdba_get_field(self.h, i, ctypes.c_void_p(out.data_ptr())), "spdba_get_field")
+        self.stream.synchronize()
+        return out
+
+    def set_spectrum(self, i, hat, k0=None):
+        d = self.descs[i]
+        hat = hat.to(device="cuda", dtype=self._cplx_dtype(i)).contiguous()
+        assert hat.numel() == d.n_modes * d.nspec
+        kk = None
+        if k0 is not None:
+            k0a = np.ascontiguousarray(k0, dtype=np.float64)
+            kk = k0a.ctypes.data_as(ctypes.c_void_p)
+        _ck(load().spdba_set_spectrum(self.h, i, ctypes.c_void_p(hat.data_ptr()), kk), "set_spectrum")
+        self.stream.synchronize()
+
+    def get_spectrum(self, i):
+        d = self.descs[i]
+        out = self.torch.empty(d.n_modes * d.nspec, dtype=self._cplx_dtype(i), device="cuda")
+        k0 = np.zeros(2, np.float64)
+        _ck(load().spdba_get_spectrum(self.h, i, ctypes.c_void_p(out.data_ptr()),
+                                      k0.ctypes.data_as(ctypes.c_void_p)), "get_spectrum")
+        return out, k0[: d.nspec].copy()
+
+    # ---- stepping -------------------------------------------------------
+    def step(self, n=1):
+        _ck(load().spdba_step(self.h, int(n)), "spdba_step")
+
+    def apply(self, rhs=None, rhs_k0=None):
+        rp = None
+        if rhs is not None:
+            rhs = rhs.to(device="cuda", dtype=self._cplx_dtype(0)).contiguous()
+            rp = ctypes.c_void_p(rhs.data_ptr())
+        kp = None
+        if rhs_k0 is not None:
+            rk = np.ascontiguousarray(rhs_k0, dtype=np.float64)
+            kp = rk.ctypes.data_as(ctypes.c_void_p)
+        _ck(load().spdba_apply(self.h, rp, kp), "spdba_apply")
+        self.stream.synchronize()  # keeps rhs alive until the copies ran
+
+    def set_skip(self, skip):
+        self._skip = None if skip is None else skip.to(device="cuda", dtype=self.torch.uint8).contiguous()
+        ptr = None if self._skip is None else ctypes.c_void_p(self._skip.data_ptr())
+        _ck(load().spdba_set_skip(self.h, ptr), "spdba_set_skip")
+
+    def set_launch(self, kernel, value):
+        _ck(load().spdba_set_launch(self.h, int(kernel), int(value)), "spdba_set_launch")
+
+    # ---- read-backs -----------------------------------------------------
+    def active_mask(self, i):
+        nb = self.descs[i].n_blocks
+        out = np.zeros(nb, np.uint8)
+        _ck(load().spdba_active_mask(self.h, i, out.ctypes.data_as(ctypes.c_void_p), nb), "active_mask")
+        return out
+
+    def indicator(self, i):
+        nb = self.descs[i].n_blocks
+        ab = np.zeros(nb, np.float64)
+        G = ctypes.c_double()
+        _ck(load().spdba_indicator(self.h, i, ab.ctypes.data_as(ctypes.c_void_p), nb,
+                                   ctypes.byref(G)), "indicator")
+        return ab, G.value
+
+    def worklist(self, i):
+        nb = self.descs[i].n_blocks
+        out = np.zeros(nb, np.uint32)
+        cnt = ctypes.c_int64()
+        _ck(load().spdba_worklist(self.h, i, out.ctypes.data_as(ctypes.c_void_p), nb,
+                                  ctypes.byref(cnt)), "worklist")
+        return out[: cnt.value].copy()
+
+    def device_views(self):
+        ab, mk, nb = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64()
+        _ck(load().spdba_device_views(self.h, ctypes.byref(ab), ctypes.byref(mk), ctypes.byref(nb)),
+            "device_views")
+        return ab.value, mk.value, nb.value
+
+    def stats(self, i):
+        s = Stats()
+        _ck(load().spdba_stats(self.h, i, ctypes.byref(s)), "spdba_stats")
+        return dict(steps=s.steps, active_blocks=s.active_blocks, total_blocks=s.total_blocks,
+                    G=s.G, mean=list(s.mean), energy=s.energy, stage_ms=list(s.stage_ms),
+                    input_preserving_fft=s.input_preserving_fft)
+
+    def destroy(self):
+        if self.h is not None and self.h.value:
+            load().spdba_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def desc_from_config(cfg: dict, n: int | None = None, **over) -> Desc:
+    """Descriptor of one instance of a workload record (configs.py)."""
+    from . import inputs  # noqa: F401  (kept beside the configs)
+
+    d = Desc(op=cfg["op"], dtype=cfg["dtype"], ndim=cfg["ndim"], n=n if n is not None else cfg["n"],
+             block=cfg["block"], tau=cfg["tau"], dx=cfg["dx"], dt=cfg["dt"], params=tuple(cfg["params"]))
+    for k, v in over.items():
+        setattr(d, k, v)
+    return d

@@ -1,0 +1,78 @@
+"""Host-side checks of libspdba.so that need no GPU: the library loads, exports
+every entry point include/spdba.h declares, and rejects invalid descriptors
+before touching a device."""
+import os
+import re
+
+import pytest
+
+from paper_2609_03922_amd import spdba
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "spdba.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(spdba_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = spdba.load()
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(spdba.EXPORTS)
+
+
+def test_status_strings():
+    assert spdba.status_string(0) == "success"
+    assert "invalid" in spdba.status_string(1)
+    assert spdba.status_string(99) == "unknown status"
+
+
+def _good(**kw):
+    d = spdba.Desc(op="ch", dtype="f32", ndim=3, n=32, block=8, tau=1e-6, dx=1.0, dt=0.01,
+                   params=(1.0, 1.0))
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("mutate,expect", [
+    (lambda c: setattr(c, "ndim", 0), spdba.SPDBA_EINVAL),
+    (lambda c: setattr(c, "ndim", 4), spdba.SPDBA_EINVAL),
+    (lambda c: c.block.__setitem__(2, 5), spdba.SPDBA_EINVAL),      # does not divide
+    (lambda c: c.dims.__setitem__(2, 48), spdba.SPDBA_EINVAL),      # not a power of two
+    (lambda c: c.dims.__setitem__(1, 64), spdba.SPDBA_EINVAL),      # unequal extents
+    (lambda c: setattr(c, "threshold", -1.0), spdba.SPDBA_EINVAL),
+    (lambda c: setattr(c, "threshold", float("nan")), spdba.SPDBA_EINVAL),
+    (lambda c: setattr(c, "dt", 0.0), spdba.SPDBA_EINVAL),
+    (lambda c: setattr(c, "dx", -1.0), spdba.SPDBA_EINVAL),
+    (lambda c: setattr(c, "reserved", 1), spdba.SPDBA_EINVAL),
+    (lambda c: c.op_params.__setitem__(0, float("inf")), spdba.SPDBA_EINVAL),
+    (lambda c: setattr(c, "op", 9), spdba.SPDBA_EUNSUPPORTED),
+    (lambda c: setattr(c, "dtype", 7), spdba.SPDBA_EUNSUPPORTED),
+    (lambda c: setattr(c, "flags", 1 << 20), spdba.SPDBA_EUNSUPPORTED),
+    (lambda c: (c.block.__setitem__(2, 1)), spdba.SPDBA_EUNSUPPORTED),  # FP32 lane needs 2 values
+])
+def test_invalid_descriptors_rejected_without_device(mutate, expect):
+    c = _good().to_c()
+    mutate(c)
+    assert spdba.spdba_plan_create_status([c]) == expect
+
+
+def test_mixed_batch_rejected():
+    a = _good().to_c()
+    b = _good(dtype="f64").to_c()
+    assert spdba.spdba_plan_create_status([a, b]) == spdba.SPDBA_EUNSUPPORTED
+    assert spdba.spdba_plan_create_status([]) == spdba.SPDBA_EINVAL
+
+
+def test_null_arguments():
+    lib = spdba.load()
+    assert lib.spdba_plan_create(None, 1, None, None) == spdba.SPDBA_EINVAL
+    assert lib.spdba_destroy(None) == spdba.SPDBA_OK
+    assert lib.spdba_step(None, 1) == spdba.SPDBA_EINVAL
+    assert lib.spdba_stats(None, 0, None) == spdba.SPDBA_EINVAL
