@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense comparison run")
     ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph per step")
+    ap.add_argument("--tune", action="store_true", help="re-run the launch autotuner first")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -89,14 +90,25 @@ def main():
     from paper_2609_03922_amd import spdba as S
 
     if args.copy_probe:
-        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        # plain device copy of 1 GiB (exceeds the 256 MB Infinity Cache): the
+        # achievable streaming bandwidth, and the reference for the HBM byte
+        # counters (FETCH_SIZE / WRITE_SIZE of this kernel vs its known size)
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         a.fill_(1.0)
+        b.fill_(0.0)
         torch.cuda.synchronize()
-        for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
             b.copy_(a)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "copy_probe_bytes_written": b.numel() * 4}))
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copy_ms": round(ms, 4),
+                          "copy_GBps_read_plus_write": round(2 * nbytes / ms / 1e6, 1)}))
         return
 
     cfg = configs.BY_NAME[args.config]
@@ -105,8 +117,22 @@ def main():
     descs, sizes = build_descs(cfg, S, inputs, timing=not args.graph, graph=args.graph)
     total_modes = sum(d.n_modes for d in descs)
 
+    from paper_2609_03922_amd import autotune
+
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    tuned = None
+    if args.tune:
+        def make_plan(dense):
+            dd, _ = build_descs(cfg, S, inputs, dense=dense, timing=True)
+            return S.Plan(dd)
+        choice, _ = autotune.tune(make_plan, lambda p: init_fields(p, cfg, sizes, inputs, np, torch), arch=arch)
+        tuned = {str(k): v for k, v in choice.items()}
+
     # ---- sp-DBA run (timed) --------------------------------------------
     plan = S.Plan(descs)
+    entry = autotune.apply_cached(plan, arch)
+    if entry:
+        tuned = entry["choice"]
     init_fields(plan, cfg, sizes, inputs, np, torch)
     plan.step(W)
     torch.cuda.synchronize()
@@ -138,6 +164,7 @@ def main():
     if not args.no_dense:
         ddescs, _ = build_descs(cfg, S, inputs, dense=True, timing=not args.graph, graph=args.graph)
         dp = S.Plan(ddescs)
+        autotune.apply_cached(dp, arch)
         init_fields(dp, cfg, sizes, inputs, np, torch)
         dp.step(W)
         init_fields(dp, cfg, sizes, inputs, np, torch)
@@ -185,6 +212,7 @@ def main():
                    "modes": total_modes, "parallelism": "single-gpu", "hip_graph": bool(args.graph)},
         "steps_per_s": round(steps_per_s, 3),
         "active_fraction_last_step": round(active / nblocks, 4),
+        "launch": tuned,
     }
     if stage_ms is not None:
         upd_stage_ms = stage_ms["indicator"] + stage_ms["compaction"] + stage_ms["update"]

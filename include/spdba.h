@@ -116,7 +116,7 @@ typedef struct {
                                  stream, eager steps only                          */
     int32_t input_preserving_fft; /* 1 if out-of-place inverse transforms keep their
                                      input (probed at bind), 0 if a copy is used    */
-    int32_t reserved;
+    int32_t graph_replay;     /* 1 if spdba_step replays a captured HIP graph       */
 } spdba_stats_t;
 
 typedef struct spdba_plan_s *spdba_plan;
@@ -191,10 +191,10 @@ spdba_status spdba_device_views(spdba_plan plan, const double **d_ab, const uint
 /* Synchronising statistics of instance `inst`. */
 spdba_status spdba_stats(spdba_plan plan, int32_t inst, spdba_stats_t *out);
 
-/* Launch geometry (autotuner hook): kernel 0 = indicator, 1 = update,
- * 2 = dense update, 3 = nonlinear term; value = waves per workgroup (1..16,
- * power of two) for 0 and 3, workgroups per CU for the persistent update 1,
- * threads per workgroup (64..1024) for 2. */
+/* Launch geometry (autotuner hook); never changes results: kernel 0 =
+ * indicator (value = waves per workgroup, power of two 1..16), 1 = persistent
+ * active update (workgroups per compute unit, 1..64), 2 = dense update
+ * (threads per workgroup, power of two 64..1024).  Resets the stage-time ring. */
 spdba_status spdba_set_launch(spdba_plan plan, int32_t kernel, int32_t value);
 
 /* Release the plan (host metadata, rocFFT plans, graphs).  NULL-safe. */

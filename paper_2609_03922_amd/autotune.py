@@ -1,0 +1,84 @@
+"""Launch-geometry autotuner for a plan.
+
+Times candidate launch shapes of the indicator (waves per workgroup), the
+persistent active update (workgroups per compute unit) and the dense update
+(threads per workgroup) with the library's per-stage HIP events, keeps the
+fastest, and caches the choice in a JSON file keyed by GPU architecture,
+operator, precision, block shape and the multiset of grid sizes.  Launch shape
+never changes results (the reductions it touches are order-free maxima), so
+tuning is safe between runs.  The activation block shape is not tuned: it
+changes the masks.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
+
+CANDIDATES = {
+    0: (1, 2, 4, 8),         # indicator: waves per workgroup
+    1: (2, 4, 6, 8, 12, 16),  # active update: workgroups per CU
+    2: (128, 256, 512, 1024),  # dense update: threads per workgroup
+}
+DEFAULTS = {0: 4, 1: 4, 2: 256}
+STAGE_OF = {0: 2, 1: 4, 2: 4}  # stage_ms index that each kernel dominates
+
+
+def cache_key(descs, arch: str) -> str:
+    d = descs[0]
+    sizes = ",".join(str(x) for x in sorted((x.n for x in descs), reverse=True))
+    return f"{arch}|{d.op}|{d.dtype}|nd{d.ndim}|b{d.block}|n[{sizes}]"
+
+
+def load_cache(path: str = CACHE_PATH) -> dict:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def save_cache(cache: dict, path: str = CACHE_PATH) -> None:
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def apply_cached(plan, arch: str, path: str = CACHE_PATH) -> dict | None:
+    entry = load_cache(path).get(cache_key(plan.descs, arch))
+    if entry:
+        for k, v in entry["choice"].items():
+            plan.set_launch(int(k), int(v))
+    return entry
+
+
+def tune(make_plan, init_fields, steps: int = 20, arch: str = "gfx950", path: str | None = CACHE_PATH):
+    """make_plan(dense: bool) -> Plan with timing enabled; init_fields(plan)
+    loads the workload's initial state.  Returns {kernel: best value} and the
+    timings; stores them in the cache when `path` is given."""
+    result, timings = {}, {}
+    for dense in (False, True):
+        plan = make_plan(dense)
+        kernels = (2,) if dense else (0, 1)
+        for k in kernels:
+            best, best_ms = None, None
+            for v in CANDIDATES[k]:
+                plan.set_launch(k, v)
+                init_fields(plan)
+                plan.step(3)  # warm the shape
+                plan.set_launch(k, v)  # restart the timing ring
+                plan.step(steps)
+                ms = plan.stats(0)["stage_ms"][STAGE_OF[k]]
+                timings[f"{k}:{v}"] = ms
+                if best_ms is None or ms < best_ms:
+                    best, best_ms = v, ms
+            plan.set_launch(k, best)
+            result[k] = best
+        key = cache_key(plan.descs, arch)
+        plan.destroy()
+    if path:
+        cache = load_cache(path)
+        cache[key] = {"choice": {str(k): v for k, v in result.items()}, "stage_ms": timings}
+        save_cache(cache, path)
+    return result, timings

@@ -41,7 +41,8 @@ struct Group {
     int64_t N = 0;
     int count = 0;
     int64_t off = 0;       // first complex element of the group
-    Fft inv_oop, fwd_ip;   // batched: CH/GS inverse state->work, forward in place on work
+    Fft inv_oop, fwd_ip;   // batched: CH/GS inverse state->work; NLSE forward in place
+    Fft fwd_oop;           // batched: CH/GS forward work->rhs
     Fft inv_ip;            // batched in-place inverse (NLSE, or CH/GS copy fallback)
     Fft inv1_oop, fwd1_ip, inv1_ip;  // one instance (nspec transforms)
 };
@@ -62,7 +63,7 @@ struct spdba_plan_s {
     size_t fft_work = 0;
     // buffer layout
     size_t st_spec = 0, st_k0 = 0, state_bytes = 0;
-    size_t w_W = 0, w_fft = 0, w_ab = 0, w_mask = 0, w_wl = 0, w_chunk = 0, w_cnt = 0, w_G = 0,
+    size_t w_W = 0, w_R = 0, w_fft = 0, w_ab = 0, w_mask = 0, w_wl = 0, w_chunk = 0, w_cnt = 0, w_G = 0,
            w_Glast = 0, w_rk0 = 0, w_nl = 0, w_ind = 0, w_dense = 0, w_binst = 0, w_table = 0,
            w_probe = 0, work_bytes = 0;
     bool bound = false;
@@ -173,6 +174,7 @@ spdba_status exec_fft(spdba_plan p, const Fft &f, void *in, void *out) {
 
 char *state_ptr(spdba_plan p, int64_t elem_off) { return p->d_state + p->st_spec + elem_off * p->esize; }
 char *work_ptr(spdba_plan p, int64_t elem_off) { return p->d_work + p->w_W + elem_off * p->esize; }
+char *rhs_ptr(spdba_plan p, int64_t elem_off) { return p->d_work + p->w_R + elem_off * p->esize; }
 
 // inverse transform of a state region into the work buffer, keeping the state
 spdba_status inverse_keep(spdba_plan p, const Fft &oop, const Fft &ip, int64_t off, int64_t n_elems) {
@@ -224,7 +226,7 @@ spdba_status enqueue_step(spdba_plan p) {
         record(p, 1);
         TRY_HIP(launch_nonlinear(p->ctx, d, p->nl_waves, p->stream));
         record(p, 2);
-        for (auto &g : p->groups) TRY(exec_fft(p, g.fwd_ip, work_ptr(p, g.off), nullptr));
+        for (auto &g : p->groups) TRY(exec_fft(p, g.fwd_oop, work_ptr(p, g.off), rhs_ptr(p, g.off)));
         if (p->op == OP_GS && !d) TRY_HIP(launch_k0_rhs(p->ctx, p->stream));
         record(p, 3);
         TRY(update_stage(p, 4));
@@ -359,6 +361,14 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
         blk += I.nb;
         I.S = std::min<int>(I.nbk[2], std::max(1, 64 * V / I.b[2]));
         I.chunks = std::max(1, I.b[2] / (64 * V));
+        auto lg = [](int64_t v) { int l = 0; while ((int64_t(1) << l) < v) ++l; return l; };
+        for (int a = 0; a < 3; ++a) {
+            I.ln[a] = lg(I.n[a]);
+            I.lb[a] = lg(I.b[a]);
+            I.lnbk[a] = lg(I.nbk[a]);
+        }
+        I.lS = lg(I.S);
+        I.lchunks = lg(I.chunks);
         I.nstrips = (int64_t)I.nbk[0] * I.nbk[1] * (I.nbk[2] / I.S);
         I.strip_off = strip;
         strip += I.nstrips;
@@ -417,7 +427,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
             if ((st = create_fft(p, I, g.inv_ip, false, true, batch))) break;
         } else {
             if ((st = create_fft(p, I, g.inv_oop, false, false, batch))) break;
-            if ((st = create_fft(p, I, g.fwd_ip, true, true, batch))) break;
+            if ((st = create_fft(p, I, g.fwd_oop, true, false, batch))) break;
             if ((st = create_fft(p, I, g.inv_ip, false, true, batch))) break;
             if ((st = create_fft(p, I, g.inv1_oop, false, false, p->nspec))) break;
             if ((st = create_fft(p, I, g.fwd1_ip, true, true, p->nspec))) break;
@@ -448,6 +458,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
         return at;
     };
     p->w_W = take((size_t)p->total_elems * p->esize);
+    p->w_R = (p->op == OP_NLSE) ? p->w_W : take((size_t)p->total_elems * p->esize);
     p->w_fft = take(std::max<size_t>(p->fft_work, 256));
     p->w_ab = take((size_t)blk * sizeof(double));
     p->w_mask = take((size_t)blk);
@@ -493,6 +504,7 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     c.dense = p->dense ? 1 : 0;
     c.state = p->d_state + p->st_spec;
     c.work = p->d_work + p->w_W;
+    c.rhs = p->d_work + p->w_R;
     c.k0 = reinterpret_cast<double *>(p->d_state + p->st_k0);
     c.rhs_k0 = reinterpret_cast<double *>(p->d_work + p->w_rk0);
     c.a_b = reinterpret_cast<double *>(p->d_work + p->w_ab);
@@ -661,7 +673,7 @@ spdba_status spdba_apply(spdba_plan p, const void *d_rhs_hat, const double *h_rh
             const InstDev &I = p->hinst[i];
             const int64_t n = I.N * p->nspec;
             const char *sp = static_cast<const char *>(d_rhs_hat) + src * p->esize;
-            TRY_HIP(launch_copy_spectrum(p->ctx, p->dbl, i, sp, work_ptr(p, I.off), n, 0,
+            TRY_HIP(launch_copy_spectrum(p->ctx, p->dbl, i, sp, rhs_ptr(p, I.off), n, 0,
                                          (I.k0path && !h_rhs_k0) ? p->ctx.rhs_k0 + 2 * i : nullptr,
                                          p->stream));
             src += n;
@@ -840,6 +852,7 @@ spdba_status spdba_stats(spdba_plan p, int32_t inst, spdba_stats_t *out) {
         for (int j = 0; j < 6; ++j) out->stage_ms[j] = acc6[j] / nset;
     }
     out->input_preserving_fft = p->inv_preserving ? 1 : 0;
+    out->graph_replay = p->graph != nullptr ? 1 : 0;
     return check_nonfinite(p);
 }
 
@@ -850,9 +863,9 @@ spdba_status spdba_set_launch(spdba_plan p, int32_t kernel, int32_t value) {
         case 0: if (!pow2_in(value, 1, 16)) return SPDBA_EINVAL; p->ind_waves = value; break;
         case 1: if (value < 1 || value > 64) return SPDBA_EINVAL; p->upd_per_cu = value; break;
         case 2: if (!pow2_in(value, 64, 1024)) return SPDBA_EINVAL; p->dense_threads = value; break;
-        case 3: if (!pow2_in(value, 1, 16)) return SPDBA_EINVAL; p->nl_waves = value; break;
         default: return SPDBA_EINVAL;
     }
+    p->ring_filled = 0;  // timings of the previous geometry are stale
     if (p->graph) {
         (void)hipGraphExecDestroy(p->graph);
         p->graph = nullptr;
@@ -866,6 +879,7 @@ spdba_status spdba_destroy(spdba_plan p) {
     for (auto &g : p->groups) {
         destroy_fft(g.inv_oop);
         destroy_fft(g.fwd_ip);
+        destroy_fft(g.fwd_oop);
         destroy_fft(g.inv_ip);
         destroy_fft(g.inv1_oop);
         destroy_fft(g.fwd1_ip);

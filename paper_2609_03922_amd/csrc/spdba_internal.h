@@ -29,6 +29,10 @@ struct InstDev {
     int32_t nspec;
     int32_t k0path;     // 1: FP32 real field, k = 0 kept in FP64
     int32_t pin;        // PIN_K0
+    int32_t ln[3];      // log2 of n[] (all extents and block edges are powers of two)
+    int32_t lb[3];      // log2 of b[]
+    int32_t lnbk[3];    // log2 of nbk[]
+    int32_t lS, lchunks;
     double K2;          // (2 pi / (n dx))^2
     double c0, c1, c2;  // CH: dt*M, dt*M*kappa, -; GS: dt, dt*Du, dt*Dv; NLSE: theta/m^2, A, -
     double tau2;        // fl(tau*tau)
@@ -45,7 +49,8 @@ struct Ctx {
     int32_t op;
     int32_t dense;
     void *state;               // complex T
-    void *work;                // complex T
+    void *work;                // complex T: inverse transform / nonlinear term
+    void *rhs;                 // complex T: forward transform of the nonlinear term
     double *k0;                // [n_inst][2] FP64 k = 0 state
     double *rhs_k0;            // [n_inst][2]
     double *a_b;               // [nb_total]

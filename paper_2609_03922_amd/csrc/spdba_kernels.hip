@@ -222,50 +222,106 @@ __global__ void __launch_bounds__(1024) k_nonlinear(Ctx c) {
     double acc[2] = {0.0, 0.0};
     if (OP == OP_CH) {
         const T invN = (T)I.invN;
-        const T mean = I.k0path ? (T)(c.k0[2 * ii] * I.invN) : (T)0;
-        for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
-            const int64_t e = t0 + j;
-            if (e >= I.N) break;
-            T re[V], im[V];
-            CV<T>::ld(base + 2 * e, re, im);
+        if (I.k0path) {
+            // W holds N (c - cbar) (the k = 0 slot is 0).  The nonlinear term is
+            // expanded about the FP64 mean, f'(cbar + d) - f'(cbar) =
+            // d (3 cbar^2 - 1 + d (3 cbar + d)), so c = cbar + d is never rounded
+            // to FP32; the dropped constant only reaches k = 0, which the FP64
+            // side path carries.  The FP64 sums use the full c.
+            const double cbar = c.k0[2 * ii] * I.invN;
+            const T A1 = (T)(3.0 * cbar * cbar - 1.0), A2 = (T)(3.0 * cbar);
+            for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
+                const int64_t e = t0 + j;
+                if (e >= I.N) break;
+                T re[V], im[V];
+                CV<T>::ld(base + 2 * e, re, im);
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const T cc = re[v] * invN + mean;
-                re[v] = cc * cc * cc - cc;
-                im[v] = (T)0;
-                const double cd = (double)cc;
-                const double t = cd * cd - 1.0;
-                acc[0] += 0.25 * (t * t);
-                acc[1] += (double)re[v];
+                for (int v = 0; v < V; ++v) {
+                    const T d = re[v] * invN;
+                    re[v] = d * (A1 + d * (A2 + d));
+                    im[v] = (T)0;
+                    const double cd = cbar + (double)d;
+                    const double t = cd * cd - 1.0;
+                    acc[0] += 0.25 * (t * t);
+                    acc[1] += cd * cd * cd - cd;
+                }
+                CV<T>::st(base + 2 * e, re, im);
             }
-            CV<T>::st(base + 2 * e, re, im);
+        } else {
+            for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
+                const int64_t e = t0 + j;
+                if (e >= I.N) break;
+                T re[V], im[V];
+                CV<T>::ld(base + 2 * e, re, im);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const T cc = re[v] * invN;
+                    re[v] = cc * cc * cc - cc;
+                    im[v] = (T)0;
+                    const double cd = (double)cc;
+                    const double t = cd * cd - 1.0;
+                    acc[0] += 0.25 * (t * t);
+                    acc[1] += (double)re[v];
+                }
+                CV<T>::st(base + 2 * e, re, im);
+            }
         }
     } else if (OP == OP_GS) {
         const T invN = (T)I.invN;
-        const T mu = I.k0path ? (T)(c.k0[2 * ii] * I.invN) : (T)0;
-        const T mv = I.k0path ? (T)(c.k0[2 * ii + 1] * I.invN) : (T)0;
         const T F = (T)I.q0, Fk = (T)(I.q0 + I.q1);
         T *bu = base, *bv = base + 2 * I.N;
-        for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
-            const int64_t e = t0 + j;
-            if (e >= I.N) break;
-            T ur[V], ui[V], vr[V], vi[V];
-            CV<T>::ld(bu + 2 * e, ur, ui);
-            CV<T>::ld(bv + 2 * e, vr, vi);
+        if (I.k0path) {
+            // deviations from the FP64 means: with P = uv^2 - ubar vbar^2 =
+            // ubar dv (2 vbar + dv) + du v^2, R_u - R_u(means) = -P - F du and
+            // R_v - R_v(means) = P - (F + k) dv; the constants only reach k = 0.
+            // The FP64 sums (the k = 0 right-hand side) use the full u, v.
+            const double ub = c.k0[2 * ii] * I.invN, vb = c.k0[2 * ii + 1] * I.invN;
+            const T Uf = (T)ub, Vf = (T)vb, V2 = (T)(2.0 * vb);
+            for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
+                const int64_t e = t0 + j;
+                if (e >= I.N) break;
+                T ur[V], ui[V], vr[V], vi[V];
+                CV<T>::ld(bu + 2 * e, ur, ui);
+                CV<T>::ld(bv + 2 * e, vr, vi);
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const T u = ur[v] * invN + mu;
-                const T w = vr[v] * invN + mv;
-                const T uvv = u * w * w;
-                ur[v] = -uvv + F * ((T)1 - u);
-                vr[v] = uvv - Fk * w;
-                ui[v] = (T)0;
-                vi[v] = (T)0;
-                acc[0] += (double)ur[v];
-                acc[1] += (double)vr[v];
+                for (int v = 0; v < V; ++v) {
+                    const T du = ur[v] * invN, dv = vr[v] * invN;
+                    const T vv = Vf + dv;
+                    const T P = Uf * (dv * (V2 + dv)) + du * (vv * vv);
+                    ur[v] = -P - F * du;
+                    vr[v] = P - Fk * dv;
+                    ui[v] = (T)0;
+                    vi[v] = (T)0;
+                    const double u64 = ub + (double)du, v64 = vb + (double)dv;
+                    const double uvv = u64 * v64 * v64;
+                    acc[0] += -uvv + I.q0 * (1.0 - u64);
+                    acc[1] += uvv - (I.q0 + I.q1) * v64;
+                }
+                CV<T>::st(bu + 2 * e, ur, ui);
+                CV<T>::st(bv + 2 * e, vr, vi);
             }
-            CV<T>::st(bu + 2 * e, ur, ui);
-            CV<T>::st(bv + 2 * e, vr, vi);
+        } else {
+            for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
+                const int64_t e = t0 + j;
+                if (e >= I.N) break;
+                T ur[V], ui[V], vr[V], vi[V];
+                CV<T>::ld(bu + 2 * e, ur, ui);
+                CV<T>::ld(bv + 2 * e, vr, vi);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const T u = ur[v] * invN;
+                    const T w = vr[v] * invN;
+                    const T uvv = u * w * w;
+                    ur[v] = -uvv + F * ((T)1 - u);
+                    vr[v] = uvv - Fk * w;
+                    ui[v] = (T)0;
+                    vi[v] = (T)0;
+                    acc[0] += (double)ur[v];
+                    acc[1] += (double)vr[v];
+                }
+                CV<T>::st(bu + 2 * e, ur, ui);
+                CV<T>::st(bv + 2 * e, vr, vi);
+            }
         }
     } else {
         const T sc = (T)(I.invN * I.invN);  // stored field carries a factor N^2 here
@@ -331,42 +387,44 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
     const int ii = find_by_offset(c.inst, c.n_inst, strip, 0);
     const InstDev &I = c.inst[ii];
     const int64_t ls = strip - I.strip_off;
-    const int nsx = I.nbk[2] / I.S;
-    const int sx = (int)(ls % nsx);
-    const int64_t t = ls / nsx;
-    const int sby = (int)(t % I.nbk[1]);
-    const int sbz = (int)(t / I.nbk[1]);
-    const int rows = I.b[0] * I.b[1];
+    const int lnsx = I.lnbk[2] - I.lS;  // log2 strips per block row
+    const int sx = (int)(ls & ((1 << lnsx) - 1));
+    const int64_t t = ls >> lnsx;
+    const int sby = (int)(t & ((1 << I.lnbk[1]) - 1));
+    const int sbz = (int)(t >> I.lnbk[1]);
     const int chunks = I.chunks;
-    const int total_it = rows * chunks;
-    const int x_lane = sx * I.S * I.b[2] + lane * V;  // x of this lane in chunk 0
+    const int total_it = (I.b[0] * I.b[1]) << I.lchunks;
+    const int x_lane = ((sx << I.lS) << I.lb[2]) + lane * V;  // x of this lane in chunk 0
     // lanes beyond the strip width stay idle (narrow grids)
-    const bool lane_on = chunks > 1 || lane * V < I.S * I.b[2];
+    const bool lane_on = chunks > 1 || lane * V < (I.S << I.lb[2]);
 
     const T *q0p = reinterpret_cast<const T *>(c.state) + 2 * I.off;
-    const T *r0p = reinterpret_cast<const T *>(c.work) + 2 * I.off;
+    const T *r0p = reinterpret_cast<const T *>(c.rhs) + 2 * I.off;
     const T *q1p = q0p + 2 * I.N;
     const T *r1p = r0p + 2 * I.N;
 
     double amax = 0.0, esum = 0.0;
     bool bad = false;
-    T c0s = 0, c1s = 0;
-    if (OP == OP_GS) c0s = (T)I.c0;
-    (void)c1s;
+    const T c0s = (OP == OP_GS) ? (T)I.c0 : (T)0;
 
     for (int it0 = w; it0 < total_it; it0 += nw * U) {
         T qr[U][V], qi[U][V], nr[U][V], ni[U][V], q2r[U][V], q2i[U][V], n2r[U][V], n2i[U][V];
+        int xs[U];
+        long long myz[U];
         int64_t eidx[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int it = it0 + u * nw;
             eidx[u] = -1;
             if (lane_on && it < total_it) {
-                const int r = it / chunks, ch = it - r * chunks;
-                const int z = sbz * I.b[0] + r / I.b[1];
-                const int y = sby * I.b[1] + (r - (r / I.b[1]) * I.b[1]);
+                const int r = it >> I.lchunks, ch = it & (chunks - 1);
+                const int z = (sbz << I.lb[0]) + (r >> I.lb[1]);
+                const int y = (sby << I.lb[1]) + (r & (I.b[1] - 1));
                 const int x = x_lane + ch * 64 * V;
-                const int64_t e = ((int64_t)z * I.n[1] + y) * I.n[2] + x;
+                const int64_t e = ((((int64_t)z << I.ln[1]) + y) << I.ln[2]) + x;
+                const int mz = sidx(z, I.n[0]), my = sidx(y, I.n[1]);
+                xs[u] = x;
+                myz[u] = (long long)mz * mz + (long long)my * my;
                 eidx[u] = e;
                 CV<T>::ld(q0p + 2 * e, qr[u], qi[u]);
                 if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr[u], ni[u]);
@@ -380,17 +438,10 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
         for (int u = 0; u < U; ++u) {
             if (eidx[u] < 0) continue;
             const int64_t e = eidx[u];
-            const int x0 = (int)(e % I.n[2]);
-            const int64_t zy = e / I.n[2];
-            const int y = (int)(zy % I.n[1]);
-            const int z = (int)(zy / I.n[1]);
-            const long long myz = (long long)sidx(z, I.n[0]) * sidx(z, I.n[0]) +
-                                  (long long)sidx(y, I.n[1]) * sidx(y, I.n[1]);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const int x = x0 + v;
-                const long long mx = sidx(x, I.n[2]);
-                const long long m2 = myz + mx * mx;
+                const long long mx = sidx(xs[u] + v, I.n[2]);
+                const long long m2 = myz[u] + mx * mx;
                 double a;
                 if (I.k0path && e + v == 0) {
                     double tmp[2];
@@ -431,8 +482,8 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
         for (int i = 1; i < nw; ++i) m = fmax(m, lds_max[i][lane]);
         const int nblk = chunks > 1 ? 1 : I.S;
         if (lane % LB == 0 && lane / LB < nblk) {
-            const int bx = sx * I.S + lane / LB;
-            const int64_t lb = ((int64_t)sbz * I.nbk[1] + sby) * I.nbk[2] + bx;
+            const int bx = (sx << I.lS) + lane / LB;
+            const int64_t lb = ((((int64_t)sbz << I.lnbk[1]) + sby) << I.lnbk[2]) + bx;
             const int64_t gb = I.blk_off + lb;
             const bool skipped = c.skip && c.skip[gb] && !(I.pin && lb == 0);
             c.a_b[gb] = skipped ? 0.0 : m;
@@ -533,22 +584,22 @@ __device__ __forceinline__ void update_block(const Ctx &c, int64_t gb) {
     const int ii = c.blk_inst[gb];
     const InstDev &I = c.inst[ii];
     const int64_t lb = gb - I.blk_off;
-    const int bx = (int)(lb % I.nbk[2]);
-    const int64_t t = lb / I.nbk[2];
-    const int by = (int)(t % I.nbk[1]);
-    const int bz = (int)(t / I.nbk[1]);
-    const int lpr = I.b[2] / V;  // lanes per block row
-    const int slots = I.b[0] * I.b[1] * lpr;
+    const int bx = (int)(lb & (I.nbk[2] - 1));
+    const int64_t t = lb >> I.lnbk[2];
+    const int by = (int)(t & (I.nbk[1] - 1));
+    const int bz = (int)(t >> I.lnbk[1]);
+    const int llpr = I.lb[2] - (V == 2 ? 1 : 0);  // log2 lanes per block row
+    const int slots = (I.b[0] * I.b[1]) << llpr;
     T *q0p = reinterpret_cast<T *>(c.state) + 2 * I.off;
-    const T *r0p = reinterpret_cast<const T *>(c.work) + 2 * I.off;
+    const T *r0p = reinterpret_cast<const T *>(c.rhs) + 2 * I.off;
     T *q1p = q0p + 2 * I.N;
     const T *r1p = r0p + 2 * I.N;
     for (int s = threadIdx.x; s < slots; s += blockDim.x) {
-        const int r = s / lpr, l = s - r * lpr;
-        const int z = bz * I.b[0] + r / I.b[1];
-        const int y = by * I.b[1] + (r - (r / I.b[1]) * I.b[1]);
-        const int x0 = bx * I.b[2] + l * V;
-        const int64_t e = ((int64_t)z * I.n[1] + y) * I.n[2] + x0;
+        const int r = s >> llpr, l = s & ((1 << llpr) - 1);
+        const int z = (bz << I.lb[0]) + (r >> I.lb[1]);
+        const int y = (by << I.lb[1]) + (r & (I.b[1] - 1));
+        const int x0 = (bx << I.lb[2]) + l * V;
+        const int64_t e = ((((int64_t)z << I.ln[1]) + y) << I.ln[2]) + x0;
         const long long myz = (long long)sidx(z, I.n[0]) * sidx(z, I.n[0]) +
                               (long long)sidx(y, I.n[1]) * sidx(y, I.n[1]);
         T qr[V], qi[V], nr[V], ni[V], q2r[V], q2i[V], n2r[V], n2i[V];
@@ -629,17 +680,17 @@ __global__ void __launch_bounds__(1024) k_dense(Ctx c) {
     const InstDev &I = c.inst[ii];
     const int64_t t0 = (tile - I.tile_off) * TE;
     T *q0p = reinterpret_cast<T *>(c.state) + 2 * I.off;
-    const T *r0p = reinterpret_cast<const T *>(c.work) + 2 * I.off;
+    const T *r0p = reinterpret_cast<const T *>(c.rhs) + 2 * I.off;
     T *q1p = q0p + 2 * I.N;
     const T *r1p = r0p + 2 * I.N;
     double acc[1] = {0.0};
     for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
         const int64_t e = t0 + j;
         if (e >= I.N) break;
-        const int x0 = (int)(e % I.n[2]);
-        const int64_t zy = e / I.n[2];
-        const int y = (int)(zy % I.n[1]);
-        const int z = (int)(zy / I.n[1]);
+        const int x0 = (int)(e & (I.n[2] - 1));
+        const int64_t zy = e >> I.ln[2];
+        const int y = (int)(zy & (I.n[1] - 1));
+        const int z = (int)(zy >> I.ln[1]);
         const long long myz = (long long)sidx(z, I.n[0]) * sidx(z, I.n[0]) +
                               (long long)sidx(y, I.n[1]) * sidx(y, I.n[1]);
         T qr[V], qi[V], nr[V], ni[V], q2r[V], q2i[V], n2r[V], n2i[V];

@@ -68,7 +68,7 @@ class Stats(ctypes.Structure):
         ("energy", ctypes.c_double),
         ("stage_ms", ctypes.c_double * 6),
         ("input_preserving_fft", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("graph_replay", ctypes.c_int32),
     ]
 
 
@@ -212,7 +212,9 @@ class Plan:
 
         self.descs = list(descs)
         self.torch = torch
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        # a stream of its own (default priority): HIP graphs cannot be captured
+        # on the legacy default stream
+        self.stream = stream if stream is not None else torch.cuda.Stream()
         self.h = spdba_plan_create(self.descs, ctypes.c_void_p(self.stream.cuda_stream))
         lib = load()
         sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
@@ -231,6 +233,10 @@ class Plan:
         p = t.data_ptr()
         return ctypes.c_void_p((p + 255) & ~255)
 
+    def _enter(self):
+        # work already queued by torch (copies of inputs) precedes the library's
+        self.stream.wait_stream(self.torch.cuda.current_stream())
+
     # ---- dtype helpers --------------------------------------------------
     def _real_dtype(self, i):
         return self.torch.float64 if self.descs[i].dtype == "f64" else self.torch.float32
@@ -244,6 +250,7 @@ class Plan:
         want = self._cplx_dtype(i) if d.op == "nlse" else self._real_dtype(i)
         field = field.to(device="cuda", dtype=want).contiguous()
         assert field.numel() == d.n_modes * d.nspec
+        self._enter()
         _ck(load().spdba_set_field(self.h, i, ctypes.c_void_p(field.data_ptr())), "spdba_set_field")
         self.stream.synchronize()
 
@@ -251,6 +258,7 @@ class Plan:
         d = self.descs[i]
         want = self._cplx_dtype(i) if d.op == "nlse" else self._real_dtype(i)
         out = self.torch.empty(d.n_modes * d.nspec, dtype=want, device="cuda")
+        self._enter()
         _ck(load().spdba_get_field(self.h, i, ctypes.c_void_p(out.data_ptr())), "spdba_get_field")
         self.stream.synchronize()
         return out
@@ -263,6 +271,7 @@ class Plan:
         if k0 is not None:
             k0a = np.ascontiguousarray(k0, dtype=np.float64)
             kk = k0a.ctypes.data_as(ctypes.c_void_p)
+        self._enter()
         _ck(load().spdba_set_spectrum(self.h, i, ctypes.c_void_p(hat.data_ptr()), kk), "set_spectrum")
         self.stream.synchronize()
 
@@ -270,13 +279,18 @@ class Plan:
         d = self.descs[i]
         out = self.torch.empty(d.n_modes * d.nspec, dtype=self._cplx_dtype(i), device="cuda")
         k0 = np.zeros(2, np.float64)
+        self._enter()
         _ck(load().spdba_get_spectrum(self.h, i, ctypes.c_void_p(out.data_ptr()),
                                       k0.ctypes.data_as(ctypes.c_void_p)), "get_spectrum")
+        self.stream.synchronize()
         return out, k0[: d.nspec].copy()
 
     # ---- stepping -------------------------------------------------------
     def step(self, n=1):
         _ck(load().spdba_step(self.h, int(n)), "spdba_step")
+
+    def synchronize(self):
+        self.stream.synchronize()
 
     def apply(self, rhs=None, rhs_k0=None):
         rp = None
@@ -287,12 +301,14 @@ class Plan:
         if rhs_k0 is not None:
             rk = np.ascontiguousarray(rhs_k0, dtype=np.float64)
             kp = rk.ctypes.data_as(ctypes.c_void_p)
+        self._enter()
         _ck(load().spdba_apply(self.h, rp, kp), "spdba_apply")
         self.stream.synchronize()  # keeps rhs alive until the copies ran
 
     def set_skip(self, skip):
         self._skip = None if skip is None else skip.to(device="cuda", dtype=self.torch.uint8).contiguous()
         ptr = None if self._skip is None else ctypes.c_void_p(self._skip.data_ptr())
+        self._enter()
         _ck(load().spdba_set_skip(self.h, ptr), "spdba_set_skip")
 
     def set_launch(self, kernel, value):
@@ -332,12 +348,14 @@ class Plan:
         _ck(load().spdba_stats(self.h, i, ctypes.byref(s)), "spdba_stats")
         return dict(steps=s.steps, active_blocks=s.active_blocks, total_blocks=s.total_blocks,
                     G=s.G, mean=list(s.mean), energy=s.energy, stage_ms=list(s.stage_ms),
-                    input_preserving_fft=s.input_preserving_fft)
+                    input_preserving_fft=s.input_preserving_fft, graph_replay=s.graph_replay)
 
     def destroy(self):
         if self.h is not None and self.h.value:
+            self.stream.synchronize()  # the buffers go back to torch below
             load().spdba_destroy(self.h)
         self.h = None
+        self.d_state = self.d_work = self._skip = None
 
     def __del__(self):
         try:
