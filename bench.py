@@ -77,6 +77,26 @@ def indicator_bytes(cfg, descs):
     return tot
 
 
+def profiled_traffic(workload: str):
+    """HBM bytes per indicator launch from the committed rocprofv3 PMC summary,
+    or None when the kernel source changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"k_indicator_{workload}.md")
+    src = os.path.join(ROOT, "paper_2609_03922_amd", "csrc", "spdba_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            k, _, v = line.partition(":")
+            vals[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if vals.get("kernel_source_sha256_16") != sha or "traffic_bytes_per_launch" not in vals:
+        return None
+    return int(float(vals["traffic_bytes_per_launch"]))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -155,7 +175,8 @@ def main():
         ind_s = stage_ms["indicator"] * 1e-3
         ach = ib / ind_s / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_indicator",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(cfg["name"]),
+                "kernel": "k_indicator",
                 "bytes_per_launch": ib, "avg_launch_us": round(ind_s * 1e6, 2)}
     plan.destroy()
 
@@ -220,7 +241,7 @@ def main():
         out["update_stage_gpts_s"] = round(total_modes / (upd_stage_ms * 1e-3) / 1e9, 3)
         out["roofline"] = roof
     if dense is not None:
-        out["dense"] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in dense.items()}
+        out["dense"] = {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in dense.items()}
         out["speedup_steps_vs_dense"] = round(steps_per_s / dense["steps_per_s"], 4)
         if stage_ms is not None and "stage_ms" in dense:
             out["update_stage_speedup_vs_dense"] = round(
