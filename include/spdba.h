@@ -184,9 +184,11 @@ spdba_status spdba_indicator(spdba_plan plan, int32_t inst, double *host_ab, siz
 spdba_status spdba_worklist(spdba_plan plan, int32_t inst, uint32_t *host_out, size_t n, int64_t *count);
 
 /* Device views for on-device consumers (the proposer): pointers into the work
- * buffer, valid until the next step; NULL arguments are skipped. */
+ * buffer -- per-block a_b (FP64), per-block mask (u8), per-instance G of the
+ * last completed update (FP64) -- valid for the plan's lifetime and rewritten
+ * by every update; NULL arguments are skipped. */
 spdba_status spdba_device_views(spdba_plan plan, const double **d_ab, const uint8_t **d_mask,
-                                int64_t *total_blocks);
+                                const double **d_G, int64_t *total_blocks);
 
 /* Synchronising statistics of instance `inst`. */
 spdba_status spdba_stats(spdba_plan plan, int32_t inst, spdba_stats_t *out);

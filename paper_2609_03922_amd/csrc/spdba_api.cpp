@@ -7,6 +7,7 @@
 
 #include "spdba.h"
 #include "spdba_internal.h"
+#include "spdba_proposer.h"
 
 #include <rocfft/rocfft.h>
 
@@ -85,6 +86,7 @@ struct spdba_plan_s {
     int ring = 0;         // set used by the step being enqueued
     int ring_filled = 0;  // sets holding a complete step
     const uint8_t *d_skip = nullptr;
+    double *d_eb = nullptr;
 };
 
 namespace {
@@ -271,6 +273,16 @@ spdba_status check_nonfinite(spdba_plan p) {
 }
 
 }  // namespace
+
+namespace spdba {
+const Ctx *plan_ctx(spdba_plan p) { return p && p->bound ? &p->ctx : nullptr; }
+const InstDev *plan_hinst(spdba_plan p, int *n_inst, int64_t *nb_total) {
+    if (!p) return nullptr;
+    *n_inst = p->n_inst;
+    *nb_total = p->nb_total;
+    return p->hinst.data();
+}
+}  // namespace spdba
 
 extern "C" {
 
@@ -520,6 +532,7 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     c.dense_part = reinterpret_cast<double *>(p->d_work + p->w_dense);
     c.blk_inst = reinterpret_cast<const uint16_t *>(p->d_work + p->w_binst);
     c.skip = p->d_skip;
+    c.e_b = p->d_eb;
     c.nb_total = p->nb_total;
     c.n_strips = p->n_strips;
     c.n_tiles = p->n_tiles;
@@ -704,6 +717,17 @@ spdba_status spdba_set_skip(spdba_plan p, const uint8_t *d_skip) {
     return SPDBA_OK;
 }
 
+spdba_status spdba_set_block_energy(spdba_plan p, double *d_eb) {
+    if (!p) return SPDBA_EINVAL;
+    p->d_eb = d_eb;
+    p->ctx.e_b = d_eb;
+    if (p->graph) {
+        (void)hipGraphExecDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    return SPDBA_OK;
+}
+
 spdba_status spdba_active_mask(spdba_plan p, int32_t inst, uint8_t *host_out, size_t n) {
     if (!p || !host_out || inst < 0 || inst >= p->n_inst) return SPDBA_EINVAL;
     if (!p->bound) return SPDBA_ESTATE;
@@ -755,11 +779,12 @@ spdba_status spdba_worklist(spdba_plan p, int32_t inst, uint32_t *host_out, size
 }
 
 spdba_status spdba_device_views(spdba_plan p, const double **d_ab, const uint8_t **d_mask,
-                                int64_t *total_blocks) {
+                                const double **d_G, int64_t *total_blocks) {
     if (!p) return SPDBA_EINVAL;
     if (!p->bound) return SPDBA_ESTATE;
     if (d_ab) *d_ab = p->ctx.a_b;
     if (d_mask) *d_mask = p->ctx.mask;
+    if (d_G) *d_G = reinterpret_cast<const double *>(p->ctx.G_last);
     if (total_blocks) *total_blocks = p->nb_total;
     return SPDBA_OK;
 }

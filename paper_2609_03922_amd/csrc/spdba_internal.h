@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct spdba_plan_s;
+
 namespace spdba {
 
 enum Op : int { OP_CH = 1, OP_GS = 2, OP_NLSE = 3 };
@@ -66,6 +68,7 @@ struct Ctx {
     uint32_t *nonfinite;       // [1]
     const uint16_t *blk_inst;  // [nb_total] owning instance of each block
     const uint8_t *skip;       // [nb_total] or nullptr
+    double *e_b;               // [nb_total] per-block energies or nullptr
     int64_t nb_total;
     int64_t n_strips;
     int64_t n_tiles;
@@ -100,5 +103,9 @@ hipError_t launch_copy_spectrum(const Ctx &c, bool dbl, int inst, const void *sr
 // probe helpers
 hipError_t launch_fill_pattern(void *buf, int64_t n_elems, bool dbl, hipStream_t s);
 hipError_t launch_check_pattern(const void *buf, int64_t n_elems, bool dbl, uint32_t *bad, hipStream_t s);
+
+// plan internals for the proposer kernels (spdba_api.cpp)
+const Ctx *plan_ctx(::spdba_plan_s *p);
+const InstDev *plan_hinst(::spdba_plan_s *p, int *n_inst, int64_t *nb_total);
 
 }  // namespace spdba

@@ -381,6 +381,7 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
     constexpr int V = CV<T>::V;
     constexpr int U = 4;  // rows in flight per wave
     __shared__ double lds_max[16][64];
+    __shared__ double lds_eb[16][64];
     __shared__ double lds_sum[16];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int64_t strip = blockIdx.x;
@@ -395,15 +396,21 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
     const int chunks = I.chunks;
     const int total_it = (I.b[0] * I.b[1]) << I.lchunks;
     const int x_lane = ((sx << I.lS) << I.lb[2]) + lane * V;  // x of this lane in chunk 0
-    // lanes beyond the strip width stay idle (narrow grids)
-    const bool lane_on = chunks > 1 || lane * V < (I.S << I.lb[2]);
+    // lanes beyond the strip width stay idle (narrow grids); lanes whose block
+    // is in the skip set issue no loads at all
+    const int LB = chunks > 1 ? 64 : (I.b[2] / V);
+    const int lane_bx = (sx << I.lS) + (chunks > 1 ? 0 : lane / LB);
+    const int64_t lane_lb = ((((int64_t)sbz << I.lnbk[1]) + sby) << I.lnbk[2]) + lane_bx;
+    bool lane_on = chunks > 1 || lane * V < (I.S << I.lb[2]);
+    if (lane_on && c.skip && c.skip[I.blk_off + lane_lb] && !(I.pin && lane_lb == 0)) lane_on = false;
 
     const T *q0p = reinterpret_cast<const T *>(c.state) + 2 * I.off;
     const T *r0p = reinterpret_cast<const T *>(c.rhs) + 2 * I.off;
     const T *q1p = q0p + 2 * I.N;
     const T *r1p = r0p + 2 * I.N;
 
-    double amax = 0.0, esum = 0.0;
+    double amax = 0.0, esum = 0.0, ebs = 0.0;
+    const bool want_eb = c.e_b != nullptr;
     bool bad = false;
     const T c0s = (OP == OP_GS) ? (T)I.c0 : (T)0;
 
@@ -464,13 +471,24 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
                 }
                 bad |= !(a <= DBL_MAX);
                 amax = a > amax ? a : amax;
+                if (want_eb) {
+                    if (I.k0path && e + v == 0) {
+                        for (int s = 0; s < I.nspec; ++s) ebs += c.k0[2 * ii + s] * c.k0[2 * ii + s];
+                    } else {
+                        ebs += sq2((double)qr[u][v], (double)qi[u][v]);
+                        if (OP == OP_GS) ebs += sq2((double)q2r[u][v], (double)q2i[u][v]);
+                    }
+                }
             }
         }
     }
     // per-block maximum over the lanes of the block, then over the waves
-    const int LB = chunks > 1 ? 64 : (I.b[2] / V);
     for (int off = 1; off < LB; off <<= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
     lds_max[w][lane] = amax;
+    if (want_eb) {
+        for (int off = 1; off < LB; off <<= 1) ebs += __shfl_xor(ebs, off, 64);
+        lds_eb[w][lane] = ebs;
+    }
     if (OP == OP_CH) {
         esum = wave_sum(esum);
         if (lane == 0) lds_sum[w] = esum;
@@ -488,6 +506,11 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
             const bool skipped = c.skip && c.skip[gb] && !(I.pin && lb == 0);
             c.a_b[gb] = skipped ? 0.0 : m;
             if (skipped) m = 0.0;
+            if (want_eb) {
+                double es = 0.0;
+                for (int i = 0; i < nw; ++i) es += lds_eb[i][lane];
+                c.e_b[gb] = skipped ? 0.0 : es;
+            }
         } else {
             m = 0.0;
         }

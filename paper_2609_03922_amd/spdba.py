@@ -34,6 +34,12 @@ EXPORTS = (
     "spdba_device_views", "spdba_stats", "spdba_set_launch", "spdba_destroy",
     "spdba_status_string",
 )
+# entry points of include/spdba_proposer.h
+PROPOSER_EXPORTS = (
+    "spdba_mlp_forward", "spdba_mlp_backward_scratch", "spdba_mlp_backward", "spdba_mlp_bce",
+    "spdba_mlp_adam", "spdba_mlp_to_bf16", "spdba_proposer_features", "spdba_proposer_labels",
+    "spdba_proposer_skip", "spdba_proposer_miss", "spdba_set_block_energy",
+)
 
 
 class SpdbaError(RuntimeError):
@@ -100,16 +106,30 @@ def load():
         "spdba_active_mask": [P, I32, P, SZ],
         "spdba_indicator": [P, I32, P, SZ, P],
         "spdba_worklist": [P, I32, P, SZ, ctypes.POINTER(I64)],
-        "spdba_device_views": [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(I64)],
+        "spdba_device_views": [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                               ctypes.POINTER(I64)],
         "spdba_stats": [P, I32, ctypes.POINTER(Stats)],
         "spdba_set_launch": [P, I32, I32],
         "spdba_destroy": [P],
         "spdba_status_string": [I32],
+        "spdba_mlp_forward": [P, I64, P, P, P, P, P, P],
+        "spdba_mlp_backward_scratch": [I64],
+        "spdba_mlp_backward": [P, P, P, P, I64, P, P, P, P],
+        "spdba_mlp_bce": [P, P, I64, ctypes.c_float, P, P, P, P],
+        "spdba_mlp_adam": [P, P, P, P, P, I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                           ctypes.c_float, I64, P],
+        "spdba_mlp_to_bf16": [P, P, I64, P],
+        "spdba_proposer_features": [P, P, P, P, P, ctypes.c_float, P, P, P],
+        "spdba_proposer_labels": [P, I32, I64, P, P],
+        "spdba_proposer_skip": [P, I64, ctypes.c_float, P, P],
+        "spdba_proposer_miss": [P, P, I64, P, P],
+        "spdba_set_block_energy": [P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
-        fn.restype = ctypes.c_char_p if name == "spdba_status_string" else ctypes.c_int32
+        fn.restype = (ctypes.c_char_p if name == "spdba_status_string" else
+                      ctypes.c_size_t if name == "spdba_mlp_backward_scratch" else ctypes.c_int32)
     _lib = lib
     return lib
 
@@ -338,10 +358,20 @@ class Plan:
         return out[: cnt.value].copy()
 
     def device_views(self):
-        ab, mk, nb = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64()
-        _ck(load().spdba_device_views(self.h, ctypes.byref(ab), ctypes.byref(mk), ctypes.byref(nb)),
-            "device_views")
-        return ab.value, mk.value, nb.value
+        """(a_b, mask, G) device addresses and the number of blocks."""
+        ab, mk, g, nb = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64()
+        _ck(load().spdba_device_views(self.h, ctypes.byref(ab), ctypes.byref(mk), ctypes.byref(g),
+                                      ctypes.byref(nb)), "device_views")
+        return ab.value, mk.value, g.value, nb.value
+
+    def set_block_energy(self, eb):
+        """eb: torch float64 tensor with one value per block of the plan, or None."""
+        self._eb = eb
+        ptr = None if eb is None else ctypes.c_void_p(eb.data_ptr())
+        _ck(load().spdba_set_block_energy(self.h, ptr), "spdba_set_block_energy")
+
+    def total_blocks(self):
+        return sum(d.n_blocks for d in self.descs)
 
     def stats(self, i):
         s = Stats()
@@ -356,6 +386,7 @@ class Plan:
             load().spdba_destroy(self.h)
         self.h = None
         self.d_state = self.d_work = self._skip = None
+        self._eb = None
 
     def __del__(self):
         try:
@@ -373,3 +404,70 @@ def desc_from_config(cfg: dict, n: int | None = None, **over) -> Desc:
     for k, v in over.items():
         setattr(d, k, v)
     return d
+
+
+# ---------------------------------------------------------------------------
+# proposer entry points (include/spdba_proposer.h), torch tensors in and out
+# ---------------------------------------------------------------------------
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _sp(stream):
+    return ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+
+
+def spdba_mlp_forward(x, w_bf16, prob=None, logit=None, h1=None, h2=None, stream=None):
+    _ck(load().spdba_mlp_forward(_p(x), x.shape[0], _p(w_bf16), _p(prob), _p(logit), _p(h1), _p(h2),
+                                 _sp(stream)), "spdba_mlp_forward")
+
+
+def spdba_mlp_backward_scratch(n):
+    return int(load().spdba_mlp_backward_scratch(int(n)))
+
+
+def spdba_mlp_backward(x, h1, h2, dlogit, w, grad, scratch, stream=None):
+    _ck(load().spdba_mlp_backward(_p(x), _p(h1), _p(h2), _p(dlogit), x.shape[0], _p(w), _p(grad),
+                                  _p(scratch), _sp(stream)), "spdba_mlp_backward")
+
+
+def spdba_mlp_bce(logit, y, pos_weight, dlogit, loss, scratch, stream=None):
+    _ck(load().spdba_mlp_bce(_p(logit), _p(y), logit.shape[0], float(pos_weight), _p(dlogit), _p(loss),
+                             _p(scratch), _sp(stream)), "spdba_mlp_bce")
+
+
+def spdba_mlp_adam(w, m, v, g, w_bf16, lr, t, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _ck(load().spdba_mlp_adam(_p(w), _p(m), _p(v), _p(g), _p(w_bf16), w.numel(), float(lr), float(beta1),
+                              float(beta2), float(eps), int(t), _sp(stream)), "spdba_mlp_adam")
+
+
+def spdba_mlp_to_bf16(w, w_bf16, stream=None):
+    _ck(load().spdba_mlp_to_bf16(_p(w), _p(w_bf16), w.numel(), _sp(stream)), "spdba_mlp_to_bf16")
+
+
+def spdba_proposer_features(plan, ab3, G3, mask_addr, eb, step_fraction, x, scratch, stream=None):
+    """ab3 / G3: three device addresses (ints) or tensors each; mask_addr: int or tensor."""
+    addr = lambda t: t if isinstance(t, int) else t.data_ptr()
+    abp = (ctypes.c_void_p * 3)(*[addr(t) for t in ab3])
+    gp = (ctypes.c_void_p * 3)(*[addr(t) for t in G3])
+    _ck(load().spdba_proposer_features(plan.h, abp, gp, ctypes.c_void_p(addr(mask_addr)), _p(eb),
+                                       float(step_fraction), _p(x), _p(scratch), _sp(stream)),
+        "spdba_proposer_features")
+
+
+def spdba_proposer_labels(masks, y, stream=None):
+    """masks: torch uint8 [n_masks, total_blocks]."""
+    _ck(load().spdba_proposer_labels(_p(masks), masks.shape[0], masks.shape[1], _p(y), _sp(stream)),
+        "spdba_proposer_labels")
+
+
+def spdba_proposer_skip(prob, threshold, skip, stream=None):
+    _ck(load().spdba_proposer_skip(_p(prob), prob.numel(), float(threshold), _p(skip), _sp(stream)),
+        "spdba_proposer_skip")
+
+
+def spdba_proposer_miss(skip, mask_addr, nb, count, stream=None):
+    m = mask_addr if isinstance(mask_addr, int) else mask_addr.data_ptr()
+    _ck(load().spdba_proposer_miss(_p(skip), ctypes.c_void_p(m), int(nb), _p(count), _sp(stream)),
+        "spdba_proposer_miss")

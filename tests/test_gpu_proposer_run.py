@@ -1,0 +1,79 @@
+"""End-to-end learned proposer on a small 3-D Cahn-Hilliard grid: train on
+masks logged from plain runs, choose the threshold on a held-out seed, then
+run an unseen seed with the window protocol.  The proposer must skip a real
+share of the indicator work while its field stays close to plain sp-DBA and
+to the dense update."""
+import numpy as np
+import pytest
+
+from paper_2609_03922_amd import inputs
+from paper_2609_03922_amd import proposer as P
+from paper_2609_03922_amd import spdba as S
+
+pytestmark = pytest.mark.gpu
+
+N, B, STEPS, K = 64, 8, 200, 10
+
+
+def _desc(**kw):
+    return S.Desc(op="ch", dtype="f32", ndim=3, n=N, block=B, tau=1e-6, dx=1.0, dt=0.01,
+                  params=(1.0, 1.0), **kw)
+
+
+def _plan(seed, **kw):
+    import torch
+
+    p = S.Plan([_desc(**kw)])
+    f = inputs.uniform_field(seed, 0, (N, N, N), 0.1, 0.02, dtype=np.float32)
+    p.set_field(0, torch.from_numpy(f.ravel()))
+    return p
+
+
+def _log(seed):
+    plan = _plan(seed)
+    run = P.WindowRunner(plan, None, K=K, total_steps=STEPS, log_masks=True)
+    run.step(STEPS)
+    X, Y = run.dataset()
+    plan.destroy()
+    return X, Y
+
+
+def test_proposer_trains_and_skips_with_bounded_error():
+    import torch
+
+    Xs, Ys = zip(*[_log(s) for s in (2001, 2002)])
+    X, Y = torch.cat(Xs), torch.cat(Ys)
+    prop = P.Proposer(seed=1)
+    losses = prop.train(X, Y, epochs=40, batch=2048, lr=3e-3, pos_weight=4.0)
+    Xh, Yh = _log(2003)
+    thr = prop.choose_threshold(Xh, Yh, recall=0.999)
+    p = prop.predict(Xh).cpu().numpy()
+    y = Yh.cpu().numpy() > 0.5
+    recall = np.mean(p[y] >= thr)
+    skip_share = np.mean(p < thr)
+    print(f"losses {losses[0]:.4f} -> {losses[-1]:.4f}; held-out positives {y.mean():.3f}, "
+          f"threshold {thr:.4f}, recall {recall:.4f}, proposed skip share {skip_share:.3f}", flush=True)
+    assert losses[-1] < losses[0]
+    assert recall >= 0.999
+
+    # unseen seed: plain, proposer, dense
+    fields = {}
+    hist = None
+    for mode in ("plain", "proposer", "dense"):
+        plan = _plan(1005, dense=(mode == "dense"))
+        run = P.WindowRunner(plan, prop if mode == "proposer" else None, K=K, total_steps=STEPS)
+        run.step(STEPS)
+        fields[mode] = plan.get_field(0).double().cpu().numpy()
+        if mode == "proposer":
+            hist = dict(run.history)
+        plan.destroy()
+    mean = fields["dense"].mean()
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b - mean)
+    e_plain = rel(fields["plain"], fields["dense"])
+    e_prop = rel(fields["proposer"], fields["dense"])
+    e_pp = rel(fields["proposer"], fields["plain"])
+    skipped = hist["skipped_block_steps"] / (hist["steps"] * (N // B) ** 3)
+    print(f"proposer run: {hist}; skipped block-steps {skipped:.3f}; rel-L2 plain-vs-dense {e_plain:.2e}, "
+          f"proposer-vs-dense {e_prop:.2e}, proposer-vs-plain {e_pp:.2e}", flush=True)
+    assert skipped > 0.05
+    assert e_prop < 1e-4 and e_pp < 1e-4

@@ -11,10 +11,10 @@ from paper_2609_03922_amd import spdba
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def header_functions():
-    src = open(os.path.join(ROOT, "include", "spdba.h")).read()
+def header_functions(name="spdba.h"):
+    src = open(os.path.join(ROOT, "include", name)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(spdba_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(spdba_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -24,6 +24,10 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(spdba.EXPORTS)
+    pnames = header_functions("spdba_proposer.h")
+    for n in pnames:
+        assert hasattr(lib, n), n
+    assert set(pnames) == set(spdba.PROPOSER_EXPORTS)
 
 
 def test_status_strings():
