@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-dense", action="store_true", help="skip the dense comparison run")
     ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph per step")
     ap.add_argument("--tune", action="store_true", help="re-run the launch autotuner first")
+    ap.add_argument("--no-equal-error", action="store_true",
+                    help="skip the threshold sweep at equal L2 error against the FP64 dense run")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -50,14 +52,14 @@ def build_descs(cfg, S, inputs, **over):
     return [S.desc_from_config(cfg, n=n, **over) for n in sizes], sizes
 
 
-def init_fields(plan, cfg, sizes, inputs, np, torch):
+def init_fields(plan, cfg, sizes, inputs, np, torch, ic_dtype=None):
     for i, n in enumerate(sizes):
         d = plan.descs[i]
         if cfg["op"] == "ch":
             ic = cfg["ic"]
             f = inputs.uniform_field(cfg["seed"], i, (n,) * cfg["ndim"], ic["mean"], ic["half_width"],
-                                     dtype=np.float64 if d.dtype == "f64" else np.float32)
-            plan.set_field(i, torch.from_numpy(f.ravel()))
+                                     dtype=ic_dtype or (np.float64 if d.dtype == "f64" else np.float32))
+            plan.set_field(i, torch.from_numpy(f.astype(np.float64 if d.dtype == "f64" else np.float32).ravel()))
         elif cfg["op"] == "gs":
             u, v = inputs.gs_patch_field(cfg["seed"], i, n)
             plan.set_field(i, torch.from_numpy(np.concatenate([u.ravel(), v.ravel()])))
@@ -132,6 +134,8 @@ def main():
         return
 
     cfg = configs.BY_NAME[args.config]
+    if "proposer" in cfg:
+        return proposer_bench(args, cfg)
     K = args.steps if args.steps is not None else min(cfg["steps"], 500)
     W = args.warmup
     descs, sizes = build_descs(cfg, S, inputs, timing=not args.graph, graph=args.graph)
@@ -145,7 +149,9 @@ def main():
         def make_plan(dense):
             dd, _ = build_descs(cfg, S, inputs, dense=dense, timing=True)
             return S.Plan(dd)
-        choice, _ = autotune.tune(make_plan, lambda p: init_fields(p, cfg, sizes, inputs, np, torch), arch=arch)
+        choice, timings = autotune.tune(make_plan, lambda p: init_fields(p, cfg, sizes, inputs, np, torch),
+                                        arch=arch)
+        print("launch tuning (stage ms):", json.dumps(timings), file=sys.stderr, flush=True)
         tuned = {str(k): v for k, v in choice.items()}
 
     # ---- sp-DBA run (timed) --------------------------------------------
@@ -209,6 +215,11 @@ def main():
             dense["stage_ms"] = {"fft": dst[0], "nonlinear": dst[1], "update": dst[4], "step": dst[5]}
         dp.destroy()
 
+    # ---- equal-L2-error protocol ----------------------------------------------
+    eq = None
+    if not args.no_equal_error and cfg["op"] == "ch" and descs[0].dtype == "f32":
+        eq = equal_error(cfg, sizes, K, W, S, inputs, autotune, arch, np, torch)
+
     # ---- CPU oracle baseline ------------------------------------------------
     cpu = None
     if not args.no_cpu:
@@ -246,7 +257,177 @@ def main():
         if stage_ms is not None and "stage_ms" in dense:
             out["update_stage_speedup_vs_dense"] = round(
                 dense["stage_ms"]["update"] / (stage_ms["indicator"] + stage_ms["compaction"] + stage_ms["update"]), 4)
+    out["equal_error"] = eq
     out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+def equal_error(cfg, sizes, K, W, S, inputs, autotune, arch, np, torch,
+                taus=(1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6)):
+    """Threshold sweep at equal L2 error.  Truth: the FP64 dense run of the
+    same workload on the GPU (FP64 path parity-tested against the oracle to
+    1e-10).  e_d: FP32 dense error; tau* = largest tau with e(tau) <= 1.1 e_d.
+    Errors are rel-L2 of the field fluctuation after K steps."""
+    def run(dtype, tau, dense, timed=False):
+        descs = [S.desc_from_config(cfg, n=n, dtype=dtype, tau=tau, dense=dense) for n in sizes]
+        p = S.Plan(descs)
+        autotune.apply_cached(p, arch)
+        # every run starts from the FP32-rounded initial field
+        init_fields(p, cfg, sizes, inputs, np, torch, ic_dtype=np.float32)
+        if timed:
+            p.step(W)
+            init_fields(p, cfg, sizes, inputs, np, torch, ic_dtype=np.float32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.step(K)
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        f = p.get_field(0).double()
+        act = p.stats(0)["active_blocks"] / p.descs[0].n_blocks
+        p.destroy()
+        return f, T, act
+
+    truth, _, _ = run("f64", cfg["tau"], True)
+    mean = float(truth.mean())
+    nrm = float(torch.linalg.norm(truth - mean))
+    err = lambda f: float(torch.linalg.norm(f - truth)) / nrm
+    fd, Td, _ = run("f32", cfg["tau"], True, timed=True)
+    e_d = err(fd)
+    sweep = []
+    for tau in taus:
+        f, _, act = run("f32", tau, False)
+        sweep.append({"tau": tau, "rel_l2": err(f), "active_fraction_last_step": round(act, 4)})
+    ok = [r for r in sweep if r["rel_l2"] <= 1.1 * e_d]
+    tau_star = max(r["tau"] for r in ok) if ok else None
+    res = {"truth": "FP64 dense run on the GPU", "steps": K, "dense_f32_rel_l2": e_d, "sweep": sweep,
+           "tau_star": tau_star, "dense_steps_per_s": K / Td}
+    if tau_star is not None:
+        _, Ts, act = run("f32", tau_star, False, timed=True)
+        res.update({"spdba_steps_per_s_at_tau_star": K / Ts,
+                    "speedup_steps_vs_dense_at_equal_error": (K / Ts) / (K / Td),
+                    "active_fraction_at_tau_star": round(act, 4)})
+    return res
+
+
+def proposer_bench(args, cfg):
+    """512^3 CH with the learned proposer: train on logged 256^3 plain runs,
+    pick the threshold for 99.9 % recall on a held-out seed, then time the
+    proposer, the plain rule and the dense update on the workload's seed."""
+    import numpy as np
+    import torch
+
+    from paper_2609_03922_amd import autotune, inputs
+    from paper_2609_03922_amd import proposer as P
+    from paper_2609_03922_amd import spdba as S
+
+    pc = cfg["proposer"]
+    Kw, audit = pc["K"], pc["audit_steps"]
+    K = args.steps if args.steps is not None else min(cfg["steps"], 500)
+    W = args.warmup
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    n_train = pc["train_n"]
+    seeds = list(pc["train_seeds"])
+    log_steps = int(os.environ.get("SPDBA_PROPOSER_LOG_STEPS", cfg["steps"]))
+
+    def make(n, seed, **kw):
+        d = S.desc_from_config(cfg, n=n, timing=True, **kw)
+        p = S.Plan([d])
+        autotune.apply_cached(p, arch)
+        ic = cfg["ic"]
+        f = inputs.uniform_field(seed, 0, (n,) * 3, ic["mean"], ic["half_width"], dtype=np.float32)
+        p.set_field(0, torch.from_numpy(f.ravel()))
+        return p
+
+    if args.tune:
+        def make_tune(dense):
+            return make(cfg["n"], cfg["seed"], dense=dense)
+
+        def init_tune(p):
+            ic = cfg["ic"]
+            f = inputs.uniform_field(cfg["seed"], 0, (cfg["n"],) * 3, ic["mean"], ic["half_width"],
+                                     dtype=np.float32)
+            p.set_field(0, torch.from_numpy(f.ravel()))
+
+        _, timings = autotune.tune(make_tune, init_tune, steps=10, arch=arch)
+        print("launch tuning (stage ms):", json.dumps(timings), file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    data = []
+    for sd in seeds:
+        p = make(n_train, sd)
+        run = P.WindowRunner(p, None, K=Kw, audit=audit, total_steps=log_steps, log_masks=True)
+        run.step(log_steps)
+        data.append(run.dataset())
+        p.destroy()
+    X = torch.cat([d[0] for d in data[:-1]])
+    Y = torch.cat([d[1] for d in data[:-1]])
+    prop = P.Proposer(seed=1)
+    losses = prop.train(X, Y, epochs=3, batch=16384, lr=2e-3, pos_weight=4.0)
+    thr = prop.choose_threshold(data[-1][0], data[-1][1], recall=1.0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    results = {}
+    fields = {}
+    for mode in ("proposer", "plain", "dense"):
+        p = make(cfg["n"], cfg["seed"], dense=(mode == "dense"))
+        run = P.WindowRunner(p, prop if mode == "proposer" else None, K=Kw, audit=audit, total_steps=K)
+        run.step(W)
+        ic = cfg["ic"]
+        f = inputs.uniform_field(cfg["seed"], 0, (cfg["n"],) * 3, ic["mean"], ic["half_width"], dtype=np.float32)
+        p.set_field(0, torch.from_numpy(f.ravel()))
+        run = P.WindowRunner(p, prop if mode == "proposer" else None, K=Kw, audit=audit, total_steps=K)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run.step(K)
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t1
+        st = p.stats(0)
+        fields[mode] = p.get_field(0).double()
+        nb = p.total_blocks()
+        results[mode] = {"steps_per_s": K / T, "wall_s": T,
+                         "stage_ms_last64": {k: round(v, 4) for k, v in zip(
+                             ("fft", "nonlinear", "indicator", "compaction", "update", "step"), st["stage_ms"])},
+                         "active_fraction_last_step": st["active_blocks"] / nb}
+        if mode == "proposer":
+            h = run.history
+            results[mode]["windows"] = h["windows"]
+            results[mode]["misses"] = h["misses"]
+            results[mode]["skipped_block_step_share"] = h["skipped_block_steps"] / max(1, h["steps"] * nb)
+        p.destroy()
+    mean = float(fields["dense"].mean())
+    def rel(a, b):
+        return float(torch.linalg.norm(a - b) / torch.linalg.norm(b - mean))
+    errs = {"proposer_vs_dense": rel(fields["proposer"], fields["dense"]),
+            "plain_vs_dense": rel(fields["plain"], fields["dense"]),
+            "proposer_vs_plain": rel(fields["proposer"], fields["plain"])}
+    modes = cfg["n"] ** 3
+    pr = results["proposer"]
+    pl = results["plain"]
+    upd = lambda r: r["stage_ms_last64"]["indicator"] + r["stage_ms_last64"]["compaction"] + r["stage_ms_last64"]["update"]
+    ib = modes * 16 + 8 * (cfg["n"] // cfg["block"]) ** 3
+    ind_s = pl["stage_ms_last64"]["indicator"] * 1e-3
+    out = {
+        "metric": METRIC, "value": round(modes * pr["steps_per_s"] / 1e9, 4), "unit": "Gpts/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": round(1e3 / pr["steps_per_s"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": cfg["name"], "grid": f"{cfg['n']}^3", "block": cfg["block"], "tau": cfg["tau"],
+                   "K": Kw, "audit_steps": audit, "train": f"{len(seeds) - 1} seeds x {log_steps} steps at {n_train}^3",
+                   "parallelism": "single-gpu"},
+        "proposer": pr, "plain": pl, "dense": results["dense"], "field_rel_l2": errs,
+        "training": {"samples": int(X.shape[0]), "losses": [round(l, 5) for l in losses], "threshold": thr,
+                     "seconds": round(t_train, 2)},
+        "speedup_steps_vs_plain": round(pr["steps_per_s"] / pl["steps_per_s"], 4),
+        "speedup_steps_vs_dense": round(pr["steps_per_s"] / results["dense"]["steps_per_s"], 4),
+        "update_stage_ms": {"proposer": round(upd(pr), 4), "plain": round(upd(pl), 4),
+                            "dense": results["dense"]["stage_ms_last64"]["update"]},
+        "launch": (autotune.load_cache().get(autotune.cache_key([S.desc_from_config(cfg)], arch)) or {}).get("choice"),
+        "roofline": {"bound": "hbm", "achieved": round(ib / ind_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ib / ind_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(cfg["name"]),
+                     "kernel": "k_indicator (plain run, all blocks)", "bytes_per_launch": ib,
+                     "avg_launch_us": round(ind_s * 1e6, 2)},
+        "cpu_baseline": None,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -17,12 +17,15 @@ import os
 CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
 CANDIDATES = {
-    0: (1, 2, 4, 8),         # indicator: waves per workgroup
-    1: (2, 4, 6, 8, 12, 16),  # active update: workgroups per CU
+    0: (1, 2, 4, 8),           # indicator: waves per workgroup
+    1: (2, 4, 8, 16),          # block-list update: workgroups per CU
     2: (128, 256, 512, 1024),  # dense update: threads per workgroup
+    4: (2, 4, 8),              # strip-walk update: waves per workgroup
 }
-DEFAULTS = {0: 4, 1: 4, 2: 256}
-STAGE_OF = {0: 2, 1: 4, 2: 4}  # stage_ms index that each kernel dominates
+DEFAULTS = {0: 4, 1: 4, 2: 256, 3: 1, 4: 4}
+# stage_ms indices each kernel is judged on; the update modes are compared on
+# compaction + update, since the strip walk folds the threshold pass in
+STAGE_OF = {0: (2,), 1: (3, 4), 2: (4,), 4: (3, 4)}
 
 
 def cache_key(descs, arch: str) -> str:
@@ -48,7 +51,7 @@ def save_cache(cache: dict, path: str = CACHE_PATH) -> None:
 def apply_cached(plan, arch: str, path: str = CACHE_PATH) -> dict | None:
     entry = load_cache(path).get(cache_key(plan.descs, arch))
     if entry:
-        for k, v in entry["choice"].items():
+        for k, v in sorted(entry["choice"].items()):
             plan.set_launch(int(k), int(v))
     return entry
 
@@ -58,23 +61,38 @@ def tune(make_plan, init_fields, steps: int = 20, arch: str = "gfx950", path: st
     loads the workload's initial state.  Returns {kernel: best value} and the
     timings; stores them in the cache when `path` is given."""
     result, timings = {}, {}
+
+    def sweep(plan, k, fixed=()):
+        best, best_ms = None, None
+        for v in CANDIDATES[k]:
+            for fk, fv in fixed:
+                plan.set_launch(fk, fv)
+            plan.set_launch(k, v)
+            init_fields(plan)
+            plan.step(3)  # warm the shape
+            plan.set_launch(k, v)  # restart the timing ring
+            plan.step(steps)
+            st = plan.stats(0)["stage_ms"]
+            ms = sum(st[i] for i in STAGE_OF[k])
+            timings[f"{k}:{v}"] = ms
+            if best_ms is None or ms < best_ms:
+                best, best_ms = v, ms
+        return best, best_ms
+
     for dense in (False, True):
         plan = make_plan(dense)
-        kernels = (2,) if dense else (0, 1)
-        for k in kernels:
-            best, best_ms = None, None
-            for v in CANDIDATES[k]:
-                plan.set_launch(k, v)
-                init_fields(plan)
-                plan.step(3)  # warm the shape
-                plan.set_launch(k, v)  # restart the timing ring
-                plan.step(steps)
-                ms = plan.stats(0)["stage_ms"][STAGE_OF[k]]
-                timings[f"{k}:{v}"] = ms
-                if best_ms is None or ms < best_ms:
-                    best, best_ms = v, ms
-            plan.set_launch(k, best)
-            result[k] = best
+        if dense:
+            result[2], _ = sweep(plan, 2)
+        else:
+            result[0], _ = sweep(plan, 0)
+            plan.set_launch(0, result[0])
+            w4, t_strip = sweep(plan, 4, fixed=((3, 1),))
+            p1, t_list = sweep(plan, 1, fixed=((3, 0),))
+            p2, t_multi = sweep(plan, 1, fixed=((3, 2),))
+            best = min((t_strip, 1), (t_list, 0), (t_multi, 2))[1]
+            result[3] = best
+            result[4] = w4
+            result[1] = p2 if best == 2 else p1
         key = cache_key(plan.descs, arch)
         plan.destroy()
     if path:

@@ -76,6 +76,10 @@ struct spdba_plan_s {
     bool inv_preserving = true;
     // launch geometry
     int ind_waves = 4, nl_waves = 4, upd_per_cu = 4, dense_threads = 256, cu_count = 256;
+    int upd_mode = 1;      // 0: block-list walk, 1: strip walk, 2: block-list walk, 4 entries in flight
+    int upd_waves = 4;     // strip walk: waves per workgroup
+    int max_slots = 0;     // largest block in 16-byte lane slots
+    bool list_stale = false;  // the ordered active list lags the mask
     // graph of one step
     hipGraphExec_t graph = nullptr;
     bool graph_failed = false;
@@ -208,11 +212,22 @@ spdba_status update_stage(spdba_plan p, int ev_base) {
     }
     TRY_HIP(launch_indicator(p->ctx, d, p->ind_waves, p->stream));
     record(p, ev_base);
-    TRY_HIP(launch_compact(p->ctx, p->stream));
-    record(p, ev_base + 1);
-    // a multiple of 8: the update splits its list into one segment per XCD
-    const int grid = ((p->cu_count * p->upd_per_cu + 7) / 8) * 8;
-    TRY_HIP(launch_update(p->ctx, d, grid, p->stream));
+    if (p->upd_mode == 1) {
+        // threshold, mask and update in one pass; the ordered list is built
+        // from the mask only when it is read back
+        record(p, ev_base + 1);
+        TRY_HIP(launch_update_strip(p->ctx, d, p->upd_waves, p->stream));
+        p->list_stale = true;
+    } else {
+        TRY_HIP(launch_compact(p->ctx, p->stream));
+        record(p, ev_base + 1);
+        p->list_stale = false;
+        // a multiple of 8: the update splits its list into one segment per XCD
+        const int grid = ((p->cu_count * p->upd_per_cu + 7) / 8) * 8;
+        // four entries in flight need blocks of at most one slot per thread
+        const int multi = (p->upd_mode == 2 && p->max_slots <= 256) ? 1 : 0;
+        TRY_HIP(launch_update(p->ctx, d, grid, multi, p->stream));
+    }
     record(p, ev_base + 2);
     p->last_dense = false;
     return SPDBA_OK;
@@ -381,6 +396,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
         }
         I.lS = lg(I.S);
         I.lchunks = lg(I.chunks);
+        p->max_slots = std::max(p->max_slots, I.b[0] * I.b[1] * (I.b[2] / V));
         I.nstrips = (int64_t)I.nbk[0] * I.nbk[1] * (I.nbk[2] / I.S);
         I.strip_off = strip;
         strip += I.nstrips;
@@ -476,7 +492,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     p->w_mask = take((size_t)blk);
     p->w_wl = take((size_t)blk * sizeof(uint32_t));
     p->w_chunk = take((size_t)p->n_chunks * sizeof(uint32_t));
-    p->w_cnt = take(8);
+    p->w_cnt = take(16);
     p->w_G = take((size_t)n_inst * 8);
     p->w_Glast = take((size_t)n_inst * 8);
     p->w_rk0 = take((size_t)n_inst * 2 * sizeof(double));
@@ -527,6 +543,7 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     c.chunk_cnt = reinterpret_cast<uint32_t *>(p->d_work + p->w_chunk);
     c.count = reinterpret_cast<uint32_t *>(p->d_work + p->w_cnt);
     c.nonfinite = reinterpret_cast<uint32_t *>(p->d_work + p->w_cnt + 4);
+    c.done = reinterpret_cast<uint32_t *>(p->d_work + p->w_cnt + 8);
     c.nl_part = reinterpret_cast<double *>(p->d_work + p->w_nl);
     c.ind_part = reinterpret_cast<double *>(p->d_work + p->w_ind);
     c.dense_part = reinterpret_cast<double *>(p->d_work + p->w_dense);
@@ -543,7 +560,7 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
                            p->blk_inst.size() * sizeof(uint16_t), hipMemcpyHostToDevice, p->stream));
     TRY_HIP(hipMemsetAsync(p->d_state + p->st_k0, 0, (size_t)p->n_inst * 2 * sizeof(double), p->stream));
     TRY_HIP(hipMemsetAsync(c.rhs_k0, 0, (size_t)p->n_inst * 2 * sizeof(double), p->stream));
-    TRY_HIP(hipMemsetAsync(c.count, 0, 8, p->stream));
+    TRY_HIP(hipMemsetAsync(c.count, 0, 16, p->stream));
     TRY_HIP(hipMemsetAsync(c.mask, 0, (size_t)p->nb_total, p->stream));
     TRY_HIP(hipMemsetAsync(c.a_b, 0, (size_t)p->nb_total * sizeof(double), p->stream));
     TRY_HIP(launch_reset(c, p->stream));
@@ -763,6 +780,10 @@ spdba_status spdba_worklist(spdba_plan p, int32_t inst, uint32_t *host_out, size
     if (!p->bound) return SPDBA_ESTATE;
     const InstDev &I = p->hinst[inst];
     if (n < (size_t)I.nb) return SPDBA_EINVAL;
+    if (p->list_stale) {  // build the ordered list from the current mask
+        TRY_HIP(launch_compact(p->ctx, p->stream, 1));
+        p->list_stale = false;
+    }
     uint32_t total = 0;
     TRY_HIP(hipMemcpyAsync(&total, p->ctx.count, 4, hipMemcpyDeviceToHost, p->stream));
     TRY_HIP(hipStreamSynchronize(p->stream));
@@ -888,6 +909,8 @@ spdba_status spdba_set_launch(spdba_plan p, int32_t kernel, int32_t value) {
         case 0: if (!pow2_in(value, 1, 16)) return SPDBA_EINVAL; p->ind_waves = value; break;
         case 1: if (value < 1 || value > 64) return SPDBA_EINVAL; p->upd_per_cu = value; break;
         case 2: if (!pow2_in(value, 64, 1024)) return SPDBA_EINVAL; p->dense_threads = value; break;
+        case 3: if (value < 0 || value > 2) return SPDBA_EINVAL; p->upd_mode = value; break;
+        case 4: if (!pow2_in(value, 1, 16)) return SPDBA_EINVAL; p->upd_waves = value; break;
         default: return SPDBA_EINVAL;
     }
     p->ring_filled = 0;  // timings of the previous geometry are stale

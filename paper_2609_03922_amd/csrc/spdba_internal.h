@@ -62,6 +62,7 @@ struct Ctx {
     uint32_t *worklist;        // [nb_total] global block ids, ascending
     uint32_t *chunk_cnt;       // [n_chunks]
     uint32_t *count;           // [1] active blocks over all instances
+    uint32_t *done;            // [1] workgroup arrival counter (self-resetting)
     double *nl_part;           // [n_tiles][2] per-tile FP64 sums of the nonlinear stage
     double *ind_part;          // [n_strips] per-strip FP64 sums (CH gradient energy)
     double *dense_part;        // [n_tiles] per-tile FP64 sums of the dense update
@@ -85,8 +86,9 @@ template <typename T> constexpr int tile_elems() { return sizeof(T) == 4 ? 1024 
 hipError_t launch_nonlinear(const Ctx &c, bool dbl, int waves, hipStream_t s);
 hipError_t launch_k0_rhs(const Ctx &c, hipStream_t s);
 hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s);
-hipError_t launch_compact(const Ctx &c, hipStream_t s);
-hipError_t launch_update(const Ctx &c, bool dbl, int grid, hipStream_t s);
+hipError_t launch_compact(const Ctx &c, hipStream_t s, int from_mask = 0);
+hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_t s);
+hipError_t launch_update_strip(const Ctx &c, bool dbl, int waves, hipStream_t s);
 hipError_t launch_dense(const Ctx &c, bool dbl, int threads, hipStream_t s);
 hipError_t launch_reset(const Ctx &c, hipStream_t s);
 // set_field / get_field helpers on one instance (sizes from the host table)

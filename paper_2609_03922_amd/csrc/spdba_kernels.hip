@@ -540,7 +540,7 @@ __device__ __forceinline__ bool block_active(const Ctx &c, int64_t gb) {
     return c.a_b[gb] > thr;
 }
 
-__global__ void __launch_bounds__(256) k_compact_count(Ctx c) {
+__global__ void __launch_bounds__(256) k_compact_count(Ctx c, int from_mask) {
     __shared__ uint32_t lds[4];
     const int64_t base = (int64_t)blockIdx.x * CHUNK_BLOCKS;
     uint32_t n = 0;
@@ -548,8 +548,13 @@ __global__ void __launch_bounds__(256) k_compact_count(Ctx c) {
     for (int k = 0; k < CHUNK_BLOCKS / 256; ++k) {
         const int64_t gb = base + k * 256 + threadIdx.x;
         if (gb < c.nb_total) {
-            const bool on = block_active(c, gb);
-            c.mask[gb] = on ? 1 : 0;
+            bool on;
+            if (from_mask) {
+                on = c.mask[gb] != 0;
+            } else {
+                on = block_active(c, gb);
+                c.mask[gb] = on ? 1 : 0;
+            }
             n += on ? 1u : 0u;
         }
     }
@@ -672,6 +677,14 @@ __device__ __forceinline__ void update_block(const Ctx &c, int64_t gb) {
     }
 }
 
+// instance maxima consumed: keep a copy for read-back, clear for the next pass
+__global__ void k_consume_G(Ctx c) {
+    for (int i = threadIdx.x; i < c.n_inst; i += blockDim.x) {
+        c.G_last[i] = c.G[i];
+        c.G[i] = 0ull;
+    }
+}
+
 template <typename T, int OP>
 __global__ void __launch_bounds__(256) k_update(Ctx c) {
     const uint32_t total = *c.count;
@@ -680,13 +693,252 @@ __global__ void __launch_bounds__(256) k_update(Ctx c) {
     const uint32_t seg = (total + 7) / 8;
     const uint32_t lo = min(total, seg * xcd), hi = min(total, seg * (xcd + 1));
     for (uint32_t e = lo + local; e < hi; e += per) update_block<T, OP>(c, c.worklist[e]);
-    // the instance maxima are consumed: keep a copy for read-back and clear
-    // them for the next indicator pass
-    if (blockIdx.x == 0)
-        for (int i = threadIdx.x; i < c.n_inst; i += blockDim.x) {
-            c.G_last[i] = c.G[i];
-            c.G[i] = 0ull;
+}
+
+// several list entries per workgroup iteration: all their loads are issued
+// before any store, so more bytes are in flight per thread
+template <typename T, int OP, int UB>
+__global__ void __launch_bounds__(256) k_update_multi(Ctx c) {
+    constexpr int V = CV<T>::V;
+    const uint32_t total = *c.count;
+    const int P = gridDim.x;  // multiple of 8
+    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per = P >> 3;
+    const uint32_t seg = (total + 7) / 8;
+    const uint32_t lo = min(total, seg * xcd), hi = min(total, seg * (xcd + 1));
+    for (uint32_t e0 = lo + local; e0 < hi; e0 += per * UB) {
+        T qr[UB][V], qi[UB][V], nr[UB][V], ni[UB][V], q2r[UB][V], q2i[UB][V], n2r[UB][V], n2i[UB][V];
+        int64_t eidx[UB], base[UB];
+        long long myz[UB];
+        int xs[UB], iis[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            const uint32_t e = e0 + u * per;
+            eidx[u] = -1;
+            if (e >= hi) continue;
+            const int64_t gb = c.worklist[e];
+            const int ii = c.blk_inst[gb];
+            const InstDev &I = c.inst[ii];
+            const int llpr = I.lb[2] - (V == 2 ? 1 : 0);
+            const int slots = (I.b[0] * I.b[1]) << llpr;
+            if ((int)threadIdx.x >= slots) continue;  // blocks of at most 256 slots here
+            const int64_t lb = gb - I.blk_off;
+            const int bx = (int)(lb & (I.nbk[2] - 1));
+            const int64_t t = lb >> I.lnbk[2];
+            const int by = (int)(t & (I.nbk[1] - 1));
+            const int bz = (int)(t >> I.lnbk[1]);
+            const int s = threadIdx.x;
+            const int r = s >> llpr, l = s & ((1 << llpr) - 1);
+            const int z = (bz << I.lb[0]) + (r >> I.lb[1]);
+            const int y = (by << I.lb[1]) + (r & (I.b[1] - 1));
+            const int x0 = (bx << I.lb[2]) + l * V;
+            const int64_t el = ((((int64_t)z << I.ln[1]) + y) << I.ln[2]) + x0;
+            myz[u] = (long long)sidx(z, I.n[0]) * sidx(z, I.n[0]) + (long long)sidx(y, I.n[1]) * sidx(y, I.n[1]);
+            xs[u] = x0;
+            iis[u] = ii;
+            eidx[u] = el;
+            base[u] = 2 * I.off;
+            const T *q0p = reinterpret_cast<const T *>(c.state) + base[u];
+            const T *r0p = reinterpret_cast<const T *>(c.rhs) + base[u];
+            CV<T>::ld(q0p + 2 * el, qr[u], qi[u]);
+            if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * el, nr[u], ni[u]);
+            if (OP == OP_GS) {
+                CV<T>::ld(q0p + 2 * I.N + 2 * el, q2r[u], q2i[u]);
+                CV<T>::ld(r0p + 2 * I.N + 2 * el, n2r[u], n2i[u]);
+            }
         }
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            if (eidx[u] < 0) continue;
+            const int ii = iis[u];
+            const InstDev &I = c.inst[ii];
+            const int64_t el = eidx[u];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const long long mx = sidx(xs[u] + v, I.n[2]);
+                const long long m2 = myz[u] + mx * mx;
+                if (I.k0path && el + v == 0) {
+                    double tmp[2];
+                    k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+                    c.k0[2 * ii] = tmp[0];
+                    if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
+                    qr[u][v] = qi[u][v] = (T)0;
+                    q2r[u][v] = q2i[u][v] = (T)0;
+                } else if (OP == OP_CH) {
+                    T s, f, cr, ci;
+                    ch_coef<T>(I, m2, s, f);
+                    ch_cand<T>(s, f, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
+                    qr[u][v] = cr;
+                    qi[u][v] = ci;
+                } else if (OP == OP_GS) {
+                    T au, av, cr, ci;
+                    const T dt = (T)I.c0;
+                    gs_coef<T>(I, m2, au, av);
+                    gs_cand<T>(dt, au, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
+                    qr[u][v] = cr;
+                    qi[u][v] = ci;
+                    gs_cand<T>(dt, av, q2r[u][v], q2i[u][v], n2r[u][v], n2i[u][v], cr, ci);
+                    q2r[u][v] = cr;
+                    q2i[u][v] = ci;
+                } else {
+                    T hr, hi2, cr, ci;
+                    nlse_coef<T>(I, m2, hr, hi2);
+                    nlse_cand<T>(hr, hi2, qr[u][v], qi[u][v], cr, ci);
+                    qr[u][v] = cr;
+                    qi[u][v] = ci;
+                }
+            }
+            T *q0p = reinterpret_cast<T *>(c.state) + base[u];
+            CV<T>::st(q0p + 2 * el, qr[u], qi[u]);
+            if (OP == OP_GS) CV<T>::st(q0p + 2 * I.N + 2 * el, q2r[u], q2i[u]);
+        }
+    }
+}
+
+// -------------------------------------------------------------------------
+// active update, strip variant: the indicator's traversal (one workgroup per
+// strip of S x-adjacent blocks, waves split the rows, 16 B per lane, 1 KiB per
+// wave row) with every lane predicated on its block's mask.  Frozen blocks
+// issue no loads or stores; a strip with no active block exits at once.  Long
+// contiguous rows keep DRAM pages busy when many neighbouring blocks are
+// active, where the block-list walk moves 64-byte row pieces.
+// -------------------------------------------------------------------------
+
+template <typename T, int OP>
+__device__ __forceinline__ void update_strip_body(const Ctx &c, const InstDev &I, int ii, bool lane_on,
+                                                  int sbz, int sby, int sx, int lane, int w, int nw) {
+    constexpr int V = CV<T>::V;
+    constexpr int U = 4;
+    const int chunks = I.chunks;
+    const int total_it = (I.b[0] * I.b[1]) << I.lchunks;
+    const int x_lane = ((sx << I.lS) << I.lb[2]) + lane * V;
+    T *q0p = reinterpret_cast<T *>(c.state) + 2 * I.off;
+    const T *r0p = reinterpret_cast<const T *>(c.rhs) + 2 * I.off;
+    T *q1p = q0p + 2 * I.N;
+    const T *r1p = r0p + 2 * I.N;
+    const T dt = (OP == OP_GS) ? (T)I.c0 : (T)0;
+    for (int it0 = w; it0 < total_it; it0 += nw * U) {
+        T qr[U][V], qi[U][V], nr[U][V], ni[U][V], q2r[U][V], q2i[U][V], n2r[U][V], n2i[U][V];
+        int xs[U];
+        long long myz[U];
+        int64_t eidx[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int it = it0 + u * nw;
+            eidx[u] = -1;
+            if (lane_on && it < total_it) {
+                const int r = it >> I.lchunks, ch = it & (chunks - 1);
+                const int z = (sbz << I.lb[0]) + (r >> I.lb[1]);
+                const int y = (sby << I.lb[1]) + (r & (I.b[1] - 1));
+                const int x = x_lane + ch * 64 * V;
+                const int64_t e = ((((int64_t)z << I.ln[1]) + y) << I.ln[2]) + x;
+                const int mz = sidx(z, I.n[0]), my = sidx(y, I.n[1]);
+                xs[u] = x;
+                myz[u] = (long long)mz * mz + (long long)my * my;
+                eidx[u] = e;
+                CV<T>::ld(q0p + 2 * e, qr[u], qi[u]);
+                if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr[u], ni[u]);
+                if (OP == OP_GS) {
+                    CV<T>::ld(q1p + 2 * e, q2r[u], q2i[u]);
+                    CV<T>::ld(r1p + 2 * e, n2r[u], n2i[u]);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (eidx[u] < 0) continue;
+            const int64_t e = eidx[u];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const long long mx = sidx(xs[u] + v, I.n[2]);
+                const long long m2 = myz[u] + mx * mx;
+                if (I.k0path && e + v == 0) {
+                    double tmp[2];
+                    k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+                    c.k0[2 * ii] = tmp[0];
+                    if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
+                    qr[u][v] = qi[u][v] = (T)0;
+                    q2r[u][v] = q2i[u][v] = (T)0;
+                } else if (OP == OP_CH) {
+                    T s, f, cr, ci;
+                    ch_coef<T>(I, m2, s, f);
+                    ch_cand<T>(s, f, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
+                    qr[u][v] = cr;
+                    qi[u][v] = ci;
+                } else if (OP == OP_GS) {
+                    T au, av, cr, ci;
+                    gs_coef<T>(I, m2, au, av);
+                    gs_cand<T>(dt, au, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
+                    qr[u][v] = cr;
+                    qi[u][v] = ci;
+                    gs_cand<T>(dt, av, q2r[u][v], q2i[u][v], n2r[u][v], n2i[u][v], cr, ci);
+                    q2r[u][v] = cr;
+                    q2i[u][v] = ci;
+                } else {
+                    T hr, hi, cr, ci;
+                    nlse_coef<T>(I, m2, hr, hi);
+                    nlse_cand<T>(hr, hi, qr[u][v], qi[u][v], cr, ci);
+                    qr[u][v] = cr;
+                    qi[u][v] = ci;
+                }
+            }
+            CV<T>::st(q0p + 2 * e, qr[u], qi[u]);
+            if (OP == OP_GS) CV<T>::st(q1p + 2 * e, q2r[u], q2i[u]);
+        }
+    }
+}
+
+// Strip walk with the threshold fused in: each lane decides its block (the
+// compaction's rule), the lane leaders write the mask, active lanes update.
+template <typename T, int OP>
+__global__ void __launch_bounds__(1024) k_update_strip(Ctx c) {
+    constexpr int V = CV<T>::V;
+    __shared__ int any_active;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int64_t strip = blockIdx.x;
+    const int ii = find_by_offset(c.inst, c.n_inst, strip, 0);
+    const InstDev &I = c.inst[ii];
+    const int64_t ls = strip - I.strip_off;
+    const int lnsx = I.lnbk[2] - I.lS;
+    const int sx = (int)(ls & ((1 << lnsx) - 1));
+    const int64_t t = ls >> lnsx;
+    const int sby = (int)(t & ((1 << I.lnbk[1]) - 1));
+    const int sbz = (int)(t >> I.lnbk[1]);
+    const int chunks = I.chunks;
+    const int LB = chunks > 1 ? 64 : (I.b[2] / V);
+    const int lane_bx = (sx << I.lS) + (chunks > 1 ? 0 : lane / LB);
+    const int64_t lane_lb = ((((int64_t)sbz << I.lnbk[1]) + sby) << I.lnbk[2]) + lane_bx;
+    const bool in_strip = chunks > 1 || lane * V < (I.S << I.lb[2]);
+    bool lane_on = false;
+    if (in_strip) {
+        const int64_t gb = I.blk_off + lane_lb;
+        bool on;
+        if (c.dense) on = true;
+        else if (I.pin && lane_lb == 0) on = true;
+        else if (c.skip && c.skip[gb]) on = false;
+        else on = c.a_b[gb] > I.tau2 * __longlong_as_double((long long)c.G[ii]);
+        lane_on = on;
+        if (w == 0 && (chunks > 1 ? lane == 0 : (lane % LB) == 0)) c.mask[gb] = on ? 1 : 0;
+    }
+    if (threadIdx.x == 0) any_active = 0;
+    __syncthreads();
+    if (lane_on) any_active = 1;
+    __syncthreads();
+    if (any_active) update_strip_body<T, OP>(c, I, ii, lane_on, sbz, sby, sx, lane, w, nw);
+    // the last workgroup to finish hands G over (read-back copy, cleared for
+    // the next indicator pass); every workgroup has read G before it arrives
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int done = atomicAdd(c.done, 1u);
+        if (done == gridDim.x - 1) {
+            __threadfence();
+            for (int i = 0; i < c.n_inst; ++i) {
+                c.G_last[i] = c.G[i];
+                c.G[i] = 0ull;
+            }
+            *c.done = 0u;
+        }
+    }
 }
 
 // -------------------------------------------------------------------------
@@ -900,23 +1152,43 @@ hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s) {
     return dbl ? ind_launch<double>(c, waves, s) : ind_launch<float>(c, waves, s);
 }
 
-hipError_t launch_compact(const Ctx &c, hipStream_t s) {
-    hipLaunchKernelGGL(k_compact_count, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c);
+hipError_t launch_compact(const Ctx &c, hipStream_t s, int from_mask) {
+    hipLaunchKernelGGL(k_compact_count, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c, from_mask);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_compact_write, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c);
     return hipGetLastError();
 }
 
+template <typename T, int OP>
+static void upd_launch_op(const Ctx &c, int grid, int multi, hipStream_t s) {
+    if (multi) hipLaunchKernelGGL((k_update_multi<T, OP, 4>), dim3(grid), dim3(256), 0, s, c);
+    else hipLaunchKernelGGL((k_update<T, OP>), dim3(grid), dim3(256), 0, s, c);
+}
 template <typename T>
-static hipError_t upd_launch(const Ctx &c, int grid, hipStream_t s) {
-    if (c.op == OP_CH) hipLaunchKernelGGL((k_update<T, OP_CH>), dim3(grid), dim3(256), 0, s, c);
-    else if (c.op == OP_GS) hipLaunchKernelGGL((k_update<T, OP_GS>), dim3(grid), dim3(256), 0, s, c);
-    else hipLaunchKernelGGL((k_update<T, OP_NLSE>), dim3(grid), dim3(256), 0, s, c);
+static hipError_t upd_launch(const Ctx &c, int grid, int multi, hipStream_t s) {
+    if (c.op == OP_CH) upd_launch_op<T, OP_CH>(c, grid, multi, s);
+    else if (c.op == OP_GS) upd_launch_op<T, OP_GS>(c, grid, multi, s);
+    else upd_launch_op<T, OP_NLSE>(c, grid, multi, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_consume_G, dim3(1), dim3(64), 0, s, c);
     return hipGetLastError();
 }
-hipError_t launch_update(const Ctx &c, bool dbl, int grid, hipStream_t s) {
-    return dbl ? upd_launch<double>(c, grid, s) : upd_launch<float>(c, grid, s);
+hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_t s) {
+    return dbl ? upd_launch<double>(c, grid, multi, s) : upd_launch<float>(c, grid, multi, s);
+}
+
+template <typename T>
+static hipError_t upd_strip_launch(const Ctx &c, int waves, hipStream_t s) {
+    dim3 grid((unsigned)c.n_strips), block(64 * waves);
+    if (c.op == OP_CH) hipLaunchKernelGGL((k_update_strip<T, OP_CH>), grid, block, 0, s, c);
+    else if (c.op == OP_GS) hipLaunchKernelGGL((k_update_strip<T, OP_GS>), grid, block, 0, s, c);
+    else hipLaunchKernelGGL((k_update_strip<T, OP_NLSE>), grid, block, 0, s, c);
+    return hipGetLastError();
+}
+hipError_t launch_update_strip(const Ctx &c, bool dbl, int waves, hipStream_t s) {
+    return dbl ? upd_strip_launch<double>(c, waves, s) : upd_strip_launch<float>(c, waves, s);
 }
 
 template <typename T>

@@ -85,8 +85,9 @@ class Proposer:
             losses.append(tot / max(cnt, 1))
         return losses
 
-    def choose_threshold(self, X, Y, recall=0.999):
-        """Largest threshold whose recall of positive labels is >= `recall`."""
+    def choose_threshold(self, X, Y, recall=1.0):
+        """Largest threshold whose recall of positive labels is >= `recall`
+        (recall 1: just below the lowest score of any positive)."""
         p = self.predict(X).cpu().numpy()
         y = Y.cpu().numpy() > 0.5
         pos = np.sort(p[y])

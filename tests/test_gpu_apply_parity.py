@@ -24,10 +24,12 @@ def D(op, dtype, ndim, n, block, tau, dx=1.0, dt=0.01, params=None, **kw):
     return S.Desc(op=op, dtype=dtype, ndim=ndim, n=n, block=block, tau=tau, dx=dx, dt=dt, params=p, **kw)
 
 
-def run_case(descs, seed, skip=None, floor=0.0):
+def run_case(descs, seed, skip=None, floor=0.0, update_variant=None):
     import torch
 
     plan = S.Plan(descs)
+    if update_variant is not None:
+        plan.set_launch(3, update_variant)
     ins = [draw_apply_inputs(d, seed, i, floor=floor) for i, d in enumerate(descs)]
     for i, (d, (q, r, k0, rk0)) in enumerate(zip(descs, ins)):
         plan.set_spectrum(i, torch.from_numpy(q), k0=k0 if k0path(d) else None)
@@ -83,11 +85,12 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("variant", [1, 0, 2], ids=["strip_walk", "block_list", "block_list_x4"])
 @pytest.mark.parametrize("descs,seed", CASES, ids=[f"case{c[1]}" for c in CASES])
-def test_apply_bit_exact(descs, seed):
-    print(f"apply parity case {seed}: {[(d.op, d.dtype, d.n, d.block, d.tau) for d in descs]}",
-          flush=True)
-    run_case(descs, seed)
+def test_apply_bit_exact(descs, seed, variant):
+    print(f"apply parity case {seed} update variant {variant}: "
+          f"{[(d.op, d.dtype, d.n, d.block, d.tau) for d in descs]}", flush=True)
+    run_case(descs, seed, update_variant=variant)
 
 
 def test_apply_skip_set_bit_exact():
@@ -113,13 +116,30 @@ def test_apply_floor_all_active_and_nonfinite():
     plan.destroy()
 
 
-FULL = [
-    ("ch3d_256_f32", [D("ch", "f32", 3, 256, 8, 1e-6)], 31),
-    ("ch2d_128_f64", [D("ch", "f64", 2, 128, 16, 1e-6)], 32),
-]
+def _batch(cfg):
+    from paper_2609_03922_amd import configs  # noqa: F401
+
+    return [S.desc_from_config(cfg, n=n) for n in inputs.instance_sizes(cfg)]
 
 
-@pytest.mark.parametrize("name,descs,seed", FULL, ids=[f[0] for f in FULL])
-def test_apply_bit_exact_full_size(name, descs, seed):
-    print(f"full-size apply parity {name}", flush=True)
+def _full_cases():
+    from paper_2609_03922_amd import configs as C
+
+    return [
+        ("ch3d_256_f32", lambda: [S.desc_from_config(C.CH3D_256_F32)], 31),
+        ("ch2d_128_f64", lambda: [S.desc_from_config(C.CH2D_128_F64)], 32),
+        ("nlse1d_batch48_f32", lambda: _batch(C.NLSE1D_BATCH48_F32), 33),
+        ("gs2d_batch32_f32", lambda: _batch(C.GS2D_BATCH32_F32), 34),
+        ("ch3d_512_f32", lambda: [S.desc_from_config(C.CH3D_512_F32_PROPOSER)], 35),
+    ]
+
+
+FULL = _full_cases()
+
+
+@pytest.mark.parametrize("name,make,seed", FULL, ids=[f[0] for f in FULL])
+def test_apply_bit_exact_full_size(name, make, seed):
+    descs = make()
+    print(f"full-size apply parity {name}: {len(descs)} instances, "
+          f"{sum(d.n_modes for d in descs)} modes", flush=True)
     run_case(descs, seed)
