@@ -65,7 +65,8 @@ enum {
     SPDBA_ENONFINITE = 6    /* a non-finite indicator value was produced */
 };
 
-/* Operators (update cores).  op_params per operator:
+/* Operators (update cores).  op_params per operator (M, kappa, Du, Dv must be
+ * non-negative: the implicit denominators are then at least 1):
  *   CAHN_HILLIARD {M, kappa}: c' = (c - dt M k^2 N)/(1 + dt M kappa k^4),
  *       N = F[c^3 - c]; conserved dynamics of Supplementary S3.1 with a
  *       double-well f(c) = (c^2 - 1)^2 / 4, semi-implicit as in S4.2.

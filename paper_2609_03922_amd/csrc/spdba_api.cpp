@@ -133,6 +133,11 @@ spdba_status validate(const spdba_instance_desc *d, int32_t n, void *) {
         if (!(x.dx > 0.0) || !std::isfinite(x.dx)) return SPDBA_EINVAL;
         for (int p = 0; p < 8; ++p)
             if (!std::isfinite(x.op_params[p])) return SPDBA_EINVAL;
+        // the implicit denominators 1 + dt M kappa k^4 and 1 + dt D k^2 stay >= 1
+        if (x.op == SPDBA_OP_CAHN_HILLIARD && !(x.op_params[0] >= 0.0 && x.op_params[1] >= 0.0))
+            return SPDBA_EINVAL;
+        if (x.op == SPDBA_OP_GRAY_SCOTT && !(x.op_params[0] >= 0.0 && x.op_params[1] >= 0.0))
+            return SPDBA_EINVAL;
         if (x.op < SPDBA_OP_CAHN_HILLIARD || x.op > SPDBA_OP_NLSE) return SPDBA_EUNSUPPORTED;
         if (x.dtype != SPDBA_F32 && x.dtype != SPDBA_F64) return SPDBA_EUNSUPPORTED;
         if (x.flags & ~uint32_t(SPDBA_FLAG_DENSE | SPDBA_FLAG_PIN_K0 | SPDBA_FLAG_GRAPH |

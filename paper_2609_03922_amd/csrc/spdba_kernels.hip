@@ -109,26 +109,62 @@ __device__ __forceinline__ void sincos_cw(double x, double &sn, double &cs) {
 // -------------------------------------------------------------------------
 
 // CH: s = dt M k^2, a = 1/(1 + dt M kappa k^4) in FP64, then working precision.
+// Operator constants in registers.  Hot loops take them by value: read
+// through the instance table they would be re-fetched after every store to
+// the state (the compiler cannot rule out aliasing).
+struct Coef {
+    double K2, c0, c1, c2;
+    __device__ static Coef of(const InstDev &I) {
+        Coef k;
+        k.K2 = I.K2;
+        k.c0 = I.c0;
+        k.c1 = I.c1;
+        k.c2 = I.c2;
+        return k;
+    }
+};
+
+// 1/t for finite t >= 1: the hardware reciprocal estimate, two Newton-Raphson
+// refinements and one residual correction (Markstein).  Without exponent
+// scaling, which no such t needs, these are the steps of the IEEE-correct
+// division 1/t, so the result is the correctly rounded reciprocal.
+__device__ __forceinline__ double recip_ge1(double t) {
+    double r = __builtin_amdgcn_rcp(t);
+    double e = __builtin_fma(-t, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-t, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    const double rem = __builtin_fma(-t, r, 1.0);
+    return __builtin_fma(rem, r, r);
+}
+
+// Coefficients of one mode from its integer |m|^2, passed as an exact double.
 template <typename T>
-__device__ __forceinline__ void ch_coef(const InstDev &I, long long m2, T &s, T &a) {
-    const double k2 = I.K2 * (double)m2;
-    const double sd = I.c0 * k2;
-    const double ad = 1.0 / (1.0 + I.c1 * (k2 * k2));
+__device__ __forceinline__ void ch_coef(const Coef &K, double m2, T &s, T &a) {
+    const double k2 = K.K2 * m2;
+    const double sd = K.c0 * k2;
+    const double ad = recip_ge1(1.0 + K.c1 * (k2 * k2));
     s = (T)sd;
     a = (T)ad;
 }
 template <typename T>
-__device__ __forceinline__ void gs_coef(const InstDev &I, long long m2, T &au, T &av) {
-    const double k2 = I.K2 * (double)m2;
-    au = (T)(1.0 / (1.0 + I.c1 * k2));
-    av = (T)(1.0 / (1.0 + I.c2 * k2));
+__device__ __forceinline__ void gs_coef(const Coef &K, double m2, T &au, T &av) {
+    const double k2 = K.K2 * m2;
+    au = (T)recip_ge1(1.0 + K.c1 * k2);
+    av = (T)recip_ge1(1.0 + K.c2 * k2);
 }
 template <typename T>
-__device__ __forceinline__ void nlse_coef(const InstDev &I, long long m2, T &hr, T &hi) {
+__device__ __forceinline__ void nlse_coef(const Coef &K, double m2, T &hr, T &hi) {
     double sn, cs;
-    sincos_cw(I.c0 * (double)m2, sn, cs);
-    hr = (T)(I.c1 * cs);
-    hi = (T)(I.c1 * sn);
+    sincos_cw(K.c0 * m2, sn, cs);
+    hr = (T)(K.c1 * cs);
+    hi = (T)(K.c1 * sn);
+}
+
+// |m|^2 parts as exact doubles (integers far below 2^53)
+__device__ __forceinline__ double sq_d(int m) {
+    const double d = (double)m;
+    return d * d;
 }
 
 __device__ __forceinline__ double sq2(double dr, double di) { return dr * dr + di * di; }
@@ -371,68 +407,78 @@ __global__ void __launch_bounds__(256) k_k0_total(Ctx c, int mode, int only_inst
     }
 }
 
+// Strip geometry in registers: the instance fields a row walk needs.
+struct Geo {
+    int lch, lb1, b1m, ln1, ln2, n0, n1, n2, z0, y0;
+    __device__ static Geo of(const InstDev &I, int sbz, int sby) {
+        Geo g;
+        g.lch = I.lchunks;
+        g.lb1 = I.lb[1];
+        g.b1m = I.b[1] - 1;
+        g.ln1 = I.ln[1];
+        g.ln2 = I.ln[2];
+        g.n0 = I.n[0];
+        g.n1 = I.n[1];
+        g.n2 = I.n[2];
+        g.z0 = sbz << I.lb[0];
+        g.y0 = sby << I.lb[1];
+        return g;
+    }
+};
+
 // -------------------------------------------------------------------------
 // indicator: one workgroup per strip of S x-adjacent blocks; its waves split
 // the rows of the strip; lanes cover 16 contiguous bytes each.
 // -------------------------------------------------------------------------
 
-template <typename T, int OP>
-__global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
+// Row walk of one strip for the indicator.  MC: a block row spans several
+// 64-lane chunks (one block per strip); otherwise every lane keeps its x for
+// the whole strip and its |m_x|^2 is computed once.  Lanes that are off
+// (beyond a narrow strip, or in the skip set) never load: their registers stay
+// zero, which every operator maps to a zero increment and zero energy.
+template <typename T, int OP, bool MC>
+__device__ __forceinline__ void indicator_rows(const Ctx &c, const InstDev &I, int ii, int sbz, int sby,
+                                               int x_lane, bool lane_on, bool k0_lane, int w, int nw,
+                                               bool want_eb, double &amax, double &esum, double &ebs,
+                                               bool &bad) {
     constexpr int V = CV<T>::V;
-    constexpr int U = 4;  // rows in flight per wave
-    __shared__ double lds_max[16][64];
-    __shared__ double lds_eb[16][64];
-    __shared__ double lds_sum[16];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int64_t strip = blockIdx.x;
-    const int ii = find_by_offset(c.inst, c.n_inst, strip, 0);
-    const InstDev &I = c.inst[ii];
-    const int64_t ls = strip - I.strip_off;
-    const int lnsx = I.lnbk[2] - I.lS;  // log2 strips per block row
-    const int sx = (int)(ls & ((1 << lnsx) - 1));
-    const int64_t t = ls >> lnsx;
-    const int sby = (int)(t & ((1 << I.lnbk[1]) - 1));
-    const int sbz = (int)(t >> I.lnbk[1]);
+    constexpr int U = OP == OP_GS ? 2 : 4;  // rows in flight per wave (GS: two species, half)
+    // every instance field the row loop needs, read once (fields first read
+    // inside the predicated load block would be re-fetched row by row)
+    const Geo g = Geo::of(I, sbz, sby);
+    const Coef K = Coef::of(I);
     const int chunks = I.chunks;
-    const int total_it = (I.b[0] * I.b[1]) << I.lchunks;
-    const int x_lane = ((sx << I.lS) << I.lb[2]) + lane * V;  // x of this lane in chunk 0
-    // lanes beyond the strip width stay idle (narrow grids); lanes whose block
-    // is in the skip set issue no loads at all
-    const int LB = chunks > 1 ? 64 : (I.b[2] / V);
-    const int lane_bx = (sx << I.lS) + (chunks > 1 ? 0 : lane / LB);
-    const int64_t lane_lb = ((((int64_t)sbz << I.lnbk[1]) + sby) << I.lnbk[2]) + lane_bx;
-    bool lane_on = chunks > 1 || lane * V < (I.S << I.lb[2]);
-    if (lane_on && c.skip && c.skip[I.blk_off + lane_lb] && !(I.pin && lane_lb == 0)) lane_on = false;
-
+    const int total_it = (I.b[0] * I.b[1]) << g.lch;
     const T *q0p = reinterpret_cast<const T *>(c.state) + 2 * I.off;
     const T *r0p = reinterpret_cast<const T *>(c.rhs) + 2 * I.off;
     const T *q1p = q0p + 2 * I.N;
     const T *r1p = r0p + 2 * I.N;
-
-    double amax = 0.0, esum = 0.0, ebs = 0.0;
-    const bool want_eb = c.e_b != nullptr;
-    bool bad = false;
-    const T c0s = (OP == OP_GS) ? (T)I.c0 : (T)0;
-
+    const T c0s = (OP == OP_GS) ? (T)K.c0 : (T)0;
+    double mx2[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) mx2[v] = sq_d(sidx(x_lane + v, g.n2));
+    T qr[U][V], qi[U][V], nr[U][V], ni[U][V], q2r[U][V], q2i[U][V], n2r[U][V], n2i[U][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            qr[u][v] = qi[u][v] = nr[u][v] = ni[u][v] = (T)0;
+            q2r[u][v] = q2i[u][v] = n2r[u][v] = n2i[u][v] = (T)0;
+        }
     for (int it0 = w; it0 < total_it; it0 += nw * U) {
-        T qr[U][V], qi[U][V], nr[U][V], ni[U][V], q2r[U][V], q2i[U][V], n2r[U][V], n2i[U][V];
+        double myz[U];
         int xs[U];
-        long long myz[U];
-        int64_t eidx[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int it = it0 + u * nw;
-            eidx[u] = -1;
-            if (lane_on && it < total_it) {
-                const int r = it >> I.lchunks, ch = it & (chunks - 1);
-                const int z = (sbz << I.lb[0]) + (r >> I.lb[1]);
-                const int y = (sby << I.lb[1]) + (r & (I.b[1] - 1));
-                const int x = x_lane + ch * 64 * V;
-                const int64_t e = ((((int64_t)z << I.ln[1]) + y) << I.ln[2]) + x;
-                const int mz = sidx(z, I.n[0]), my = sidx(y, I.n[1]);
-                xs[u] = x;
-                myz[u] = (long long)mz * mz + (long long)my * my;
-                eidx[u] = e;
+            const int it = it0 + u * nw;  // wave-uniform
+            const int r = MC ? it >> g.lch : it, ch = MC ? it & (chunks - 1) : 0;
+            const int z = g.z0 + (r >> g.lb1);
+            const int y = g.y0 + (r & g.b1m);
+            const int x = x_lane + ch * 64 * V;
+            xs[u] = x;
+            myz[u] = sq_d(sidx(z, g.n0)) + sq_d(sidx(y, g.n1));
+            if (it < total_it && lane_on) {
+                const int64_t e = ((((int64_t)z << g.ln1) + y) << g.ln2) + x;
                 CV<T>::ld(q0p + 2 * e, qr[u], qi[u]);
                 if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr[u], ni[u]);
                 if (OP == OP_GS) {
@@ -443,44 +489,94 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (eidx[u] < 0) continue;
-            const int64_t e = eidx[u];
+            if (it0 + u * nw >= total_it) continue;  // wave-uniform
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const long long mx = sidx(xs[u] + v, I.n[2]);
-                const long long m2 = myz[u] + mx * mx;
+                double m2;
+                if (MC) {
+                    const double mx = (double)sidx(xs[u] + v, g.n2);
+                    m2 = __builtin_fma(mx, mx, myz[u]);
+                } else {
+                    m2 = myz[u] + mx2[v];
+                }
                 double a;
-                if (I.k0path && e + v == 0) {
-                    double tmp[2];
-                    a = k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
-                } else if (OP == OP_CH) {
+                if (OP == OP_CH) {
                     T s, f, cr, ci;
-                    ch_coef<T>(I, m2, s, f);
+                    ch_coef<T>(K, m2, s, f);
                     a = ch_cand<T>(s, f, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
-                    const double k2 = I.K2 * (double)m2;
-                    esum += k2 * sq2((double)qr[u][v], (double)qi[u][v]);
+                    esum += (K.K2 * m2) * sq2((double)qr[u][v], (double)qi[u][v]);
                 } else if (OP == OP_GS) {
                     T au, av, cr, ci;
-                    gs_coef<T>(I, m2, au, av);
+                    gs_coef<T>(K, m2, au, av);
                     a = gs_cand<T>(c0s, au, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
                     a = a + gs_cand<T>(c0s, av, q2r[u][v], q2i[u][v], n2r[u][v], n2i[u][v], cr, ci);
                 } else {
                     T hr, hi, cr, ci;
-                    nlse_coef<T>(I, m2, hr, hi);
+                    nlse_coef<T>(K, m2, hr, hi);
                     a = nlse_cand<T>(hr, hi, qr[u][v], qi[u][v], cr, ci);
                 }
+                // the FP32 slot of k = 0 (real-field operators) is held at
+                // zero; its increment comes from the FP64 side path
+                const bool k0s = v == 0 && u == 0 && k0_lane && it0 == 0;
+                a = k0s ? 0.0 : a;
                 bad |= !(a <= DBL_MAX);
-                amax = a > amax ? a : amax;
+                amax = fmax(amax, a);
                 if (want_eb) {
-                    if (I.k0path && e + v == 0) {
-                        for (int s = 0; s < I.nspec; ++s) ebs += c.k0[2 * ii + s] * c.k0[2 * ii + s];
-                    } else {
-                        ebs += sq2((double)qr[u][v], (double)qi[u][v]);
-                        if (OP == OP_GS) ebs += sq2((double)q2r[u][v], (double)q2i[u][v]);
-                    }
+                    double e2 = sq2((double)qr[u][v], (double)qi[u][v]);
+                    if (OP == OP_GS) e2 += sq2((double)q2r[u][v], (double)q2i[u][v]);
+                    ebs += k0s ? 0.0 : e2;
                 }
             }
         }
+    }
+}
+
+template <typename T, int OP>
+__global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
+    constexpr int V = CV<T>::V;
+    __shared__ double lds_max[16][64];
+    __shared__ double lds_eb[16][64];
+    __shared__ double lds_sum[16];
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    // wave index made scalar: the row loop is then uniform per wave and
+    // compiles to scalar branches, so no exec-mask joins split the loads
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t strip = blockIdx.x;
+    const int ii = find_by_offset(c.inst, c.n_inst, strip, 0);
+    const InstDev &I = c.inst[ii];
+    const int64_t ls = strip - I.strip_off;
+    const int lnsx = I.lnbk[2] - I.lS;  // log2 strips per block row
+    const int sx = (int)(ls & ((1 << lnsx) - 1));
+    const int64_t t = ls >> lnsx;
+    const int sby = (int)(t & ((1 << I.lnbk[1]) - 1));
+    const int sbz = (int)(t >> I.lnbk[1]);
+    const int chunks = I.chunks;
+    const int x_lane = ((sx << I.lS) << I.lb[2]) + lane * V;  // x of this lane in chunk 0
+    // lanes beyond the strip width stay idle (narrow grids); lanes whose block
+    // is in the skip set issue no loads at all
+    const int LB = chunks > 1 ? 64 : (I.b[2] / V);
+    const int lane_bx = (sx << I.lS) + (chunks > 1 ? 0 : lane / LB);
+    const int64_t lane_lb = ((((int64_t)sbz << I.lnbk[1]) + sby) << I.lnbk[2]) + lane_bx;
+    bool lane_on = chunks > 1 || lane * V < (I.S << I.lb[2]);
+    if (lane_on && c.skip && c.skip[I.blk_off + lane_lb] && !(I.pin && lane_lb == 0)) lane_on = false;
+    const bool k0_lane = I.k0path && ls == 0 && lane == 0;
+
+    double amax = 0.0, esum = 0.0, ebs = 0.0;
+    const bool want_eb = c.e_b != nullptr;
+    bool bad = false;
+    if (chunks > 1)
+        indicator_rows<T, OP, true>(c, I, ii, sbz, sby, x_lane, lane_on, k0_lane, w, nw, want_eb, amax, esum,
+                                    ebs, bad);
+    else
+        indicator_rows<T, OP, false>(c, I, ii, sbz, sby, x_lane, lane_on, k0_lane, w, nw, want_eb, amax, esum,
+                                     ebs, bad);
+    if (k0_lane && w == 0) {
+        double tmp[2];
+        const double a = k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+        bad |= !(a <= DBL_MAX);
+        amax = fmax(amax, a);
+        if (want_eb)
+            for (int s = 0; s < I.nspec; ++s) ebs += c.k0[2 * ii + s] * c.k0[2 * ii + s];
     }
     // per-block maximum over the lanes of the block, then over the waves
     for (int off = 1; off < LB; off <<= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
@@ -618,18 +714,22 @@ __device__ __forceinline__ void update_block(const Ctx &c, int64_t gb) {
     const int bz = (int)(t >> I.lnbk[1]);
     const int llpr = I.lb[2] - (V == 2 ? 1 : 0);  // log2 lanes per block row
     const int slots = (I.b[0] * I.b[1]) << llpr;
+    const Geo g = Geo::of(I, bz, by);
+    const Coef K = Coef::of(I);
+    const int x_blk = bx << I.lb[2];
+    const bool k0_blk = I.k0path && lb == 0;
     T *q0p = reinterpret_cast<T *>(c.state) + 2 * I.off;
     const T *r0p = reinterpret_cast<const T *>(c.rhs) + 2 * I.off;
     T *q1p = q0p + 2 * I.N;
     const T *r1p = r0p + 2 * I.N;
+    const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
     for (int s = threadIdx.x; s < slots; s += blockDim.x) {
         const int r = s >> llpr, l = s & ((1 << llpr) - 1);
-        const int z = (bz << I.lb[0]) + (r >> I.lb[1]);
-        const int y = (by << I.lb[1]) + (r & (I.b[1] - 1));
-        const int x0 = (bx << I.lb[2]) + l * V;
-        const int64_t e = ((((int64_t)z << I.ln[1]) + y) << I.ln[2]) + x0;
-        const long long myz = (long long)sidx(z, I.n[0]) * sidx(z, I.n[0]) +
-                              (long long)sidx(y, I.n[1]) * sidx(y, I.n[1]);
+        const int z = g.z0 + (r >> g.lb1);
+        const int y = g.y0 + (r & g.b1m);
+        const int x0 = x_blk + l * V;
+        const int64_t e = ((((int64_t)z << g.ln1) + y) << g.ln2) + x0;
+        const double myz = sq_d(sidx(z, g.n0)) + sq_d(sidx(y, g.n1));
         T qr[V], qi[V], nr[V], ni[V], q2r[V], q2i[V], n2r[V], n2i[V];
         CV<T>::ld(q0p + 2 * e, qr, qi);
         if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr, ni);
@@ -639,41 +739,41 @@ __device__ __forceinline__ void update_block(const Ctx &c, int64_t gb) {
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            const long long mx = sidx(x0 + v, I.n[2]);
-            const long long m2 = myz + mx * mx;
-            if (I.k0path && e + v == 0) {
-                double tmp[2];
-                k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
-                c.k0[2 * ii] = tmp[0];
-                if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
-                qr[v] = qi[v] = (T)0;
-                q2r[v] = q2i[v] = (T)0;
-            } else if (OP == OP_CH) {
-                T s, f, cr, ci;
-                ch_coef<T>(I, m2, s, f);
-                ch_cand<T>(s, f, qr[v], qi[v], nr[v], ni[v], cr, ci);
-                qr[v] = cr;
-                qi[v] = ci;
+            const double mx = (double)sidx(x0 + v, g.n2);
+            const double m2 = __builtin_fma(mx, mx, myz);
+            T cr, ci;
+            if (OP == OP_CH) {
+                T sc, f;
+                ch_coef<T>(K, m2, sc, f);
+                ch_cand<T>(sc, f, qr[v], qi[v], nr[v], ni[v], cr, ci);
             } else if (OP == OP_GS) {
-                T au, av, cr, ci;
-                const T dt = (T)I.c0;
-                gs_coef<T>(I, m2, au, av);
+                T au, av, dr, di;
+                gs_coef<T>(K, m2, au, av);
                 gs_cand<T>(dt, au, qr[v], qi[v], nr[v], ni[v], cr, ci);
-                qr[v] = cr;
-                qi[v] = ci;
-                gs_cand<T>(dt, av, q2r[v], q2i[v], n2r[v], n2i[v], cr, ci);
-                q2r[v] = cr;
-                q2i[v] = ci;
+                gs_cand<T>(dt, av, q2r[v], q2i[v], n2r[v], n2i[v], dr, di);
+                q2r[v] = dr;
+                q2i[v] = di;
             } else {
-                T hr, hi, cr, ci;
-                nlse_coef<T>(I, m2, hr, hi);
+                T hr, hi;
+                nlse_coef<T>(K, m2, hr, hi);
                 nlse_cand<T>(hr, hi, qr[v], qi[v], cr, ci);
-                qr[v] = cr;
-                qi[v] = ci;
             }
+            qr[v] = cr;
+            qi[v] = ci;
+        }
+        // the FP32 slot of k = 0 stays zero (its value lives in FP64)
+        if (k0_blk && s == 0) {
+            qr[0] = qi[0] = (T)0;
+            q2r[0] = q2i[0] = (T)0;
         }
         CV<T>::st(q0p + 2 * e, qr, qi);
         if (OP == OP_GS) CV<T>::st(q1p + 2 * e, q2r, q2i);
+    }
+    if (k0_blk && threadIdx.x == 0) {
+        double tmp[2];
+        k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+        c.k0[2 * ii] = tmp[0];
+        if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
     }
 }
 
@@ -708,7 +808,7 @@ __global__ void __launch_bounds__(256) k_update_multi(Ctx c) {
     for (uint32_t e0 = lo + local; e0 < hi; e0 += per * UB) {
         T qr[UB][V], qi[UB][V], nr[UB][V], ni[UB][V], q2r[UB][V], q2i[UB][V], n2r[UB][V], n2i[UB][V];
         int64_t eidx[UB], base[UB];
-        long long myz[UB];
+        double myz[UB];
         int xs[UB], iis[UB];
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
@@ -732,7 +832,7 @@ __global__ void __launch_bounds__(256) k_update_multi(Ctx c) {
             const int y = (by << I.lb[1]) + (r & (I.b[1] - 1));
             const int x0 = (bx << I.lb[2]) + l * V;
             const int64_t el = ((((int64_t)z << I.ln[1]) + y) << I.ln[2]) + x0;
-            myz[u] = (long long)sidx(z, I.n[0]) * sidx(z, I.n[0]) + (long long)sidx(y, I.n[1]) * sidx(y, I.n[1]);
+            myz[u] = sq_d(sidx(z, I.n[0])) + sq_d(sidx(y, I.n[1]));
             xs[u] = x0;
             iis[u] = ii;
             eidx[u] = el;
@@ -751,45 +851,50 @@ __global__ void __launch_bounds__(256) k_update_multi(Ctx c) {
             if (eidx[u] < 0) continue;
             const int ii = iis[u];
             const InstDev &I = c.inst[ii];
+            const Coef K = Coef::of(I);
+            const int n2 = I.n[2];
+            const int64_t N = I.N;
+            const bool k0s = I.k0path && eidx[u] == 0;
             const int64_t el = eidx[u];
+            const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const long long mx = sidx(xs[u] + v, I.n[2]);
-                const long long m2 = myz[u] + mx * mx;
-                if (I.k0path && el + v == 0) {
-                    double tmp[2];
-                    k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
-                    c.k0[2 * ii] = tmp[0];
-                    if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
-                    qr[u][v] = qi[u][v] = (T)0;
-                    q2r[u][v] = q2i[u][v] = (T)0;
-                } else if (OP == OP_CH) {
-                    T s, f, cr, ci;
-                    ch_coef<T>(I, m2, s, f);
+                const double mx = (double)sidx(xs[u] + v, n2);
+                const double m2 = __builtin_fma(mx, mx, myz[u]);
+                T cr, ci;
+                if (OP == OP_CH) {
+                    T s, f;
+                    ch_coef<T>(K, m2, s, f);
                     ch_cand<T>(s, f, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
-                    qr[u][v] = cr;
-                    qi[u][v] = ci;
                 } else if (OP == OP_GS) {
-                    T au, av, cr, ci;
-                    const T dt = (T)I.c0;
-                    gs_coef<T>(I, m2, au, av);
+                    T au, av, dr, di;
+                    gs_coef<T>(K, m2, au, av);
                     gs_cand<T>(dt, au, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
-                    qr[u][v] = cr;
-                    qi[u][v] = ci;
-                    gs_cand<T>(dt, av, q2r[u][v], q2i[u][v], n2r[u][v], n2i[u][v], cr, ci);
-                    q2r[u][v] = cr;
-                    q2i[u][v] = ci;
+                    gs_cand<T>(dt, av, q2r[u][v], q2i[u][v], n2r[u][v], n2i[u][v], dr, di);
+                    q2r[u][v] = dr;
+                    q2i[u][v] = di;
                 } else {
-                    T hr, hi2, cr, ci;
-                    nlse_coef<T>(I, m2, hr, hi2);
+                    T hr, hi2;
+                    nlse_coef<T>(K, m2, hr, hi2);
                     nlse_cand<T>(hr, hi2, qr[u][v], qi[u][v], cr, ci);
-                    qr[u][v] = cr;
-                    qi[u][v] = ci;
                 }
+                qr[u][v] = cr;
+                qi[u][v] = ci;
+            }
+            if (k0s) {  // the FP32 slot of k = 0 stays zero
+                qr[u][0] = qi[u][0] = (T)0;
+                q2r[u][0] = q2i[u][0] = (T)0;
             }
             T *q0p = reinterpret_cast<T *>(c.state) + base[u];
             CV<T>::st(q0p + 2 * el, qr[u], qi[u]);
-            if (OP == OP_GS) CV<T>::st(q0p + 2 * I.N + 2 * el, q2r[u], q2i[u]);
+            if (OP == OP_GS) CV<T>::st(q0p + 2 * N + 2 * el, q2r[u], q2i[u]);
+            if (k0s) {
+                const InstDev &J = c.inst[ii];
+                double tmp[2];
+                k0_cand(J, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+                c.k0[2 * ii] = tmp[0];
+                if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
+            }
         }
     }
 }
@@ -805,36 +910,46 @@ __global__ void __launch_bounds__(256) k_update_multi(Ctx c) {
 
 template <typename T, int OP>
 __device__ __forceinline__ void update_strip_body(const Ctx &c, const InstDev &I, int ii, bool lane_on,
-                                                  int sbz, int sby, int sx, int lane, int w, int nw) {
+                                                  int sbz, int sby, int sx, int lane, int w, int nw,
+                                                  bool k0_lane) {
     constexpr int V = CV<T>::V;
-    constexpr int U = 4;
+    constexpr int U = OP == OP_GS ? 2 : 4;
     const int chunks = I.chunks;
-    const int total_it = (I.b[0] * I.b[1]) << I.lchunks;
+    const Geo g = Geo::of(I, sbz, sby);
+    const Coef K = Coef::of(I);
+    const int total_it = (I.b[0] * I.b[1]) << g.lch;
     const int x_lane = ((sx << I.lS) << I.lb[2]) + lane * V;
     T *q0p = reinterpret_cast<T *>(c.state) + 2 * I.off;
     const T *r0p = reinterpret_cast<const T *>(c.rhs) + 2 * I.off;
     T *q1p = q0p + 2 * I.N;
     const T *r1p = r0p + 2 * I.N;
-    const T dt = (OP == OP_GS) ? (T)I.c0 : (T)0;
+    const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
+    // frozen lanes never load or store; their registers are set once so that
+    // the unconditional arithmetic below reads defined values
+    T qr[U][V], qi[U][V], nr[U][V], ni[U][V], q2r[U][V], q2i[U][V], n2r[U][V], n2i[U][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            qr[u][v] = qi[u][v] = nr[u][v] = ni[u][v] = (T)0;
+            q2r[u][v] = q2i[u][v] = n2r[u][v] = n2i[u][v] = (T)0;
+        }
     for (int it0 = w; it0 < total_it; it0 += nw * U) {
-        T qr[U][V], qi[U][V], nr[U][V], ni[U][V], q2r[U][V], q2i[U][V], n2r[U][V], n2i[U][V];
         int xs[U];
-        long long myz[U];
+        double myz[U];
         int64_t eidx[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int it = it0 + u * nw;
-            eidx[u] = -1;
-            if (lane_on && it < total_it) {
-                const int r = it >> I.lchunks, ch = it & (chunks - 1);
-                const int z = (sbz << I.lb[0]) + (r >> I.lb[1]);
-                const int y = (sby << I.lb[1]) + (r & (I.b[1] - 1));
-                const int x = x_lane + ch * 64 * V;
-                const int64_t e = ((((int64_t)z << I.ln[1]) + y) << I.ln[2]) + x;
-                const int mz = sidx(z, I.n[0]), my = sidx(y, I.n[1]);
-                xs[u] = x;
-                myz[u] = (long long)mz * mz + (long long)my * my;
-                eidx[u] = e;
+            const int it = it0 + u * nw;  // wave-uniform
+            const int r = it >> g.lch, ch = it & (chunks - 1);
+            const int z = g.z0 + (r >> g.lb1);
+            const int y = g.y0 + (r & g.b1m);
+            const int x = x_lane + ch * 64 * V;
+            xs[u] = x;
+            myz[u] = sq_d(sidx(z, g.n0)) + sq_d(sidx(y, g.n1));
+            eidx[u] = ((((int64_t)z << g.ln1) + y) << g.ln2) + x;
+            if (it < total_it && lane_on) {
+                const int64_t e = eidx[u];
                 CV<T>::ld(q0p + 2 * e, qr[u], qi[u]);
                 if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr[u], ni[u]);
                 if (OP == OP_GS) {
@@ -845,45 +960,48 @@ __device__ __forceinline__ void update_strip_body(const Ctx &c, const InstDev &I
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (eidx[u] < 0) continue;
-            const int64_t e = eidx[u];
+            if (it0 + u * nw >= total_it) continue;  // wave-uniform
+            T cq[V], cqi[V], cq2[V], cq2i[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const long long mx = sidx(xs[u] + v, I.n[2]);
-                const long long m2 = myz[u] + mx * mx;
-                if (I.k0path && e + v == 0) {
-                    double tmp[2];
-                    k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
-                    c.k0[2 * ii] = tmp[0];
-                    if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
-                    qr[u][v] = qi[u][v] = (T)0;
-                    q2r[u][v] = q2i[u][v] = (T)0;
-                } else if (OP == OP_CH) {
-                    T s, f, cr, ci;
-                    ch_coef<T>(I, m2, s, f);
+                const double mx = (double)sidx(xs[u] + v, g.n2);
+                const double m2 = __builtin_fma(mx, mx, myz[u]);
+                T cr, ci;
+                if (OP == OP_CH) {
+                    T s, f;
+                    ch_coef<T>(K, m2, s, f);
                     ch_cand<T>(s, f, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
-                    qr[u][v] = cr;
-                    qi[u][v] = ci;
                 } else if (OP == OP_GS) {
-                    T au, av, cr, ci;
-                    gs_coef<T>(I, m2, au, av);
+                    T au, av, dr, di;
+                    gs_coef<T>(K, m2, au, av);
                     gs_cand<T>(dt, au, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
-                    qr[u][v] = cr;
-                    qi[u][v] = ci;
-                    gs_cand<T>(dt, av, q2r[u][v], q2i[u][v], n2r[u][v], n2i[u][v], cr, ci);
-                    q2r[u][v] = cr;
-                    q2i[u][v] = ci;
+                    gs_cand<T>(dt, av, q2r[u][v], q2i[u][v], n2r[u][v], n2i[u][v], dr, di);
+                    cq2[v] = dr;
+                    cq2i[v] = di;
                 } else {
-                    T hr, hi, cr, ci;
-                    nlse_coef<T>(I, m2, hr, hi);
+                    T hr, hi;
+                    nlse_coef<T>(K, m2, hr, hi);
                     nlse_cand<T>(hr, hi, qr[u][v], qi[u][v], cr, ci);
-                    qr[u][v] = cr;
-                    qi[u][v] = ci;
                 }
+                cq[v] = cr;
+                cqi[v] = ci;
             }
-            CV<T>::st(q0p + 2 * e, qr[u], qi[u]);
-            if (OP == OP_GS) CV<T>::st(q1p + 2 * e, q2r[u], q2i[u]);
+            // the FP32 slot of k = 0 stays zero (its value lives in FP64)
+            if (u == 0 && k0_lane && it0 == 0) {
+                cq[0] = cqi[0] = (T)0;
+                if (OP == OP_GS) cq2[0] = cq2i[0] = (T)0;
+            }
+            if (lane_on) {
+                CV<T>::st(q0p + 2 * eidx[u], cq, cqi);
+                if (OP == OP_GS) CV<T>::st(q1p + 2 * eidx[u], cq2, cq2i);
+            }
         }
+    }
+    if (k0_lane && w == 0 && lane_on) {
+        double tmp[2];
+        k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+        c.k0[2 * ii] = tmp[0];
+        if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
     }
 }
 
@@ -893,7 +1011,8 @@ template <typename T, int OP>
 __global__ void __launch_bounds__(1024) k_update_strip(Ctx c) {
     constexpr int V = CV<T>::V;
     __shared__ int any_active;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t strip = blockIdx.x;
     const int ii = find_by_offset(c.inst, c.n_inst, strip, 0);
     const InstDev &I = c.inst[ii];
@@ -923,15 +1042,13 @@ __global__ void __launch_bounds__(1024) k_update_strip(Ctx c) {
     __syncthreads();
     if (lane_on) any_active = 1;
     __syncthreads();
-    if (any_active) update_strip_body<T, OP>(c, I, ii, lane_on, sbz, sby, sx, lane, w, nw);
-    // the last workgroup to finish hands G over (read-back copy, cleared for
-    // the next indicator pass); every workgroup has read G before it arrives
-    __threadfence();
-    __syncthreads();
+    // every lane's G value has been consumed by now (it decided lane_on before
+    // the barrier), so the last workgroup to arrive may hand G over: read-back
+    // copy, cleared for the next indicator pass.  No fence: the arrival orders
+    // nothing but G reads, and the kernel boundary publishes the writes.
     if (threadIdx.x == 0) {
         const unsigned int done = atomicAdd(c.done, 1u);
         if (done == gridDim.x - 1) {
-            __threadfence();
             for (int i = 0; i < c.n_inst; ++i) {
                 c.G_last[i] = c.G[i];
                 c.G[i] = 0ull;
@@ -939,6 +1056,8 @@ __global__ void __launch_bounds__(1024) k_update_strip(Ctx c) {
             *c.done = 0u;
         }
     }
+    const bool k0_lane = I.k0path && ls == 0 && lane == 0;
+    if (any_active) update_strip_body<T, OP>(c, I, ii, lane_on, sbz, sby, sx, lane, w, nw, k0_lane);
 }
 
 // -------------------------------------------------------------------------
@@ -954,20 +1073,25 @@ __global__ void __launch_bounds__(1024) k_dense(Ctx c) {
     const int ii = find_by_offset(c.inst, c.n_inst, tile, 1);
     const InstDev &I = c.inst[ii];
     const int64_t t0 = (tile - I.tile_off) * TE;
+    const Coef K = Coef::of(I);
+    const int64_t N = I.N;
+    const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2], ln1 = I.ln[1], ln2 = I.ln[2];
+    const bool k0_tile = I.k0path && t0 == 0;
     T *q0p = reinterpret_cast<T *>(c.state) + 2 * I.off;
     const T *r0p = reinterpret_cast<const T *>(c.rhs) + 2 * I.off;
-    T *q1p = q0p + 2 * I.N;
-    const T *r1p = r0p + 2 * I.N;
+    T *q1p = q0p + 2 * N;
+    const T *r1p = r0p + 2 * N;
+    const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
     double acc[1] = {0.0};
-    for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
+    const int jstep = blockDim.x * V;
+    for (int j = threadIdx.x * V; j < TE; j += jstep) {
         const int64_t e = t0 + j;
-        if (e >= I.N) break;
-        const int x0 = (int)(e & (I.n[2] - 1));
-        const int64_t zy = e >> I.ln[2];
-        const int y = (int)(zy & (I.n[1] - 1));
-        const int z = (int)(zy >> I.ln[1]);
-        const long long myz = (long long)sidx(z, I.n[0]) * sidx(z, I.n[0]) +
-                              (long long)sidx(y, I.n[1]) * sidx(y, I.n[1]);
+        if (e >= N) break;
+        const int x0 = (int)(e & (n2 - 1));
+        const int64_t zy = e >> ln2;
+        const int y = (int)(zy & (n1 - 1));
+        const int z = (int)(zy >> ln1);
+        const double myz = sq_d(sidx(z, n0)) + sq_d(sidx(y, n1));
         T qr[V], qi[V], nr[V], ni[V], q2r[V], q2i[V], n2r[V], n2i[V];
         CV<T>::ld(q0p + 2 * e, qr, qi);
         if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr, ni);
@@ -977,42 +1101,42 @@ __global__ void __launch_bounds__(1024) k_dense(Ctx c) {
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            const long long mx = sidx(x0 + v, I.n[2]);
-            const long long m2 = myz + mx * mx;
-            if (I.k0path && e + v == 0) {
-                double tmp[2];
-                k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
-                c.k0[2 * ii] = tmp[0];
-                if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
-                qr[v] = qi[v] = (T)0;
-                q2r[v] = q2i[v] = (T)0;
-            } else if (OP == OP_CH) {
-                T s, f, cr, ci;
-                ch_coef<T>(I, m2, s, f);
-                acc[0] += (I.K2 * (double)m2) * sq2((double)qr[v], (double)qi[v]);
+            const double mx = (double)sidx(x0 + v, n2);
+            const double m2 = __builtin_fma(mx, mx, myz);
+            T cr, ci;
+            if (OP == OP_CH) {
+                T s, f;
+                ch_coef<T>(K, m2, s, f);
+                // zero at k = 0 (m2 = 0), where the FP32 slot holds zero
+                acc[0] += (K.K2 * m2) * sq2((double)qr[v], (double)qi[v]);
                 ch_cand<T>(s, f, qr[v], qi[v], nr[v], ni[v], cr, ci);
-                qr[v] = cr;
-                qi[v] = ci;
             } else if (OP == OP_GS) {
-                T au, av, cr, ci;
-                const T dt = (T)I.c0;
-                gs_coef<T>(I, m2, au, av);
+                T au, av, dr, di;
+                gs_coef<T>(K, m2, au, av);
                 gs_cand<T>(dt, au, qr[v], qi[v], nr[v], ni[v], cr, ci);
-                qr[v] = cr;
-                qi[v] = ci;
-                gs_cand<T>(dt, av, q2r[v], q2i[v], n2r[v], n2i[v], cr, ci);
-                q2r[v] = cr;
-                q2i[v] = ci;
+                gs_cand<T>(dt, av, q2r[v], q2i[v], n2r[v], n2i[v], dr, di);
+                q2r[v] = dr;
+                q2i[v] = di;
             } else {
-                T hr, hi, cr, ci;
-                nlse_coef<T>(I, m2, hr, hi);
+                T hr, hi;
+                nlse_coef<T>(K, m2, hr, hi);
                 nlse_cand<T>(hr, hi, qr[v], qi[v], cr, ci);
-                qr[v] = cr;
-                qi[v] = ci;
             }
+            qr[v] = cr;
+            qi[v] = ci;
+        }
+        if (k0_tile && j == 0) {  // the FP32 slot of k = 0 stays zero
+            qr[0] = qi[0] = (T)0;
+            q2r[0] = q2i[0] = (T)0;
         }
         CV<T>::st(q0p + 2 * e, qr, qi);
         if (OP == OP_GS) CV<T>::st(q1p + 2 * e, q2r, q2i);
+    }
+    if (k0_tile && threadIdx.x == 0) {
+        double tmp[2];
+        k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+        c.k0[2 * ii] = tmp[0];
+        if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
     }
     if (OP == OP_CH) {
         block_sum<1>(acc, lds);

@@ -56,6 +56,8 @@ def _good(**kw):
     (lambda c: setattr(c, "dx", -1.0), spdba.SPDBA_EINVAL),
     (lambda c: setattr(c, "reserved", 1), spdba.SPDBA_EINVAL),
     (lambda c: c.op_params.__setitem__(0, float("inf")), spdba.SPDBA_EINVAL),
+    (lambda c: c.op_params.__setitem__(1, -1.0), spdba.SPDBA_EINVAL),   # negative kappa
+    (lambda c: c.op_params.__setitem__(0, -0.5), spdba.SPDBA_EINVAL),   # negative mobility
     (lambda c: setattr(c, "op", 9), spdba.SPDBA_EUNSUPPORTED),
     (lambda c: setattr(c, "dtype", 7), spdba.SPDBA_EUNSUPPORTED),
     (lambda c: setattr(c, "flags", 1 << 20), spdba.SPDBA_EUNSUPPORTED),
