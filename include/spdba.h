@@ -196,11 +196,13 @@ spdba_status spdba_stats(spdba_plan plan, int32_t inst, spdba_stats_t *out);
 
 /* Launch geometry (autotuner hook); never changes results: kernel 0 =
  * indicator (value = waves per workgroup, power of two 1..16), 1 = persistent
- * block-list update (workgroups per compute unit, 1..64), 2 = dense update
- * (threads per workgroup, power of two 64..1024), 3 = active-update variant
- * (0 = persistent walk of the ordered block list, 1 = strip walk predicated on
- * the mask, 2 = block-list walk with four entries in flight per workgroup;
- * default 1), 4 = strip-walk update (waves per workgroup, 1..16).
+ * active update (workgroups per compute unit, 1..64; both the block-list walk
+ * and the strip walk), 2 = dense update (threads per workgroup, power of two
+ * 64..1024), 3 = active-update variant (0 = persistent walk of the ordered
+ * block list, 1 = persistent strip walk that applies the threshold itself and
+ * skips strips whose largest block value is at or below it, 2 = block-list
+ * walk with four entries in flight per workgroup; default 1), 4 = strip-walk
+ * update (waves per workgroup, power of two 1..16).
  * Resets the stage-time ring. */
 spdba_status spdba_set_launch(spdba_plan plan, int32_t kernel, int32_t value);
 

@@ -100,9 +100,13 @@ spdba_status spdba_proposer_features(spdba_plan plan, const double *const ab[3],
 spdba_status spdba_proposer_labels(const uint8_t *masks, int32_t n_masks, int64_t total_blocks,
                                    float *y, void *stream);
 
-/* Skip set from probabilities: skip[b] = prob[b] < threshold (u8). */
+/* Skip set from probabilities: skip[b] = prob[b] < threshold (u8).  gate
+ * (device u32, may be NULL): when it holds a non-zero miss count the whole set
+ * is cleared instead, so the next window runs the plain rule without a host
+ * round trip.  count (device u32, may be NULL) accumulates the number of
+ * blocks put in the set.  A NaN threshold is EINVAL. */
 spdba_status spdba_proposer_skip(const float *prob, int64_t total_blocks, float threshold,
-                                 uint8_t *skip, void *stream);
+                                 const uint32_t *gate, uint8_t *skip, uint32_t *count, void *stream);
 
 /* Audit: adds to *count (u32, device) the number of blocks that are in the
  * skip set and active in mask (integer atomics, order-free). */

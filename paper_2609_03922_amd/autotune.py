@@ -1,8 +1,9 @@
 """Launch-geometry autotuner for a plan.
 
 Times candidate launch shapes of the indicator (waves per workgroup), the
-persistent active update (workgroups per compute unit) and the dense update
-(threads per workgroup) with the library's per-stage HIP events, keeps the
+active update (strip walk: waves per workgroup and persistent workgroups per
+compute unit; block-list walk: workgroups per compute unit) and the dense
+update (threads per workgroup) with the library's per-stage HIP events, keeps the
 fastest, and caches the choice in a JSON file keyed by GPU architecture,
 operator, precision, block shape and the multiset of grid sizes.  Launch shape
 never changes results (the reductions it touches are order-free maxima), so
@@ -18,7 +19,7 @@ CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_
 
 CANDIDATES = {
     0: (1, 2, 4, 8),           # indicator: waves per workgroup
-    1: (2, 4, 8, 16),          # block-list update: workgroups per CU
+    1: (2, 4, 8, 16),          # list walk / persistent strip walk: workgroups per CU
     2: (128, 256, 512, 1024),  # dense update: threads per workgroup
     4: (2, 4, 8),              # strip-walk update: waves per workgroup
 }
@@ -56,43 +57,57 @@ def apply_cached(plan, arch: str, path: str = CACHE_PATH) -> dict | None:
     return entry
 
 
-def tune(make_plan, init_fields, steps: int = 20, arch: str = "gfx950", path: str | None = CACHE_PATH):
+def tune(make_plan, init_fields, steps: int = 20, arch: str = "gfx950", path: str | None = CACHE_PATH,
+         warm: int = 0):
     """make_plan(dense: bool) -> Plan with timing enabled; init_fields(plan)
-    loads the workload's initial state.  Returns {kernel: best value} and the
-    timings; stores them in the cache when `path` is given."""
+    loads the workload's initial state, which is then advanced `warm` steps so
+    that the sweep sees the active fraction of the measured regime (the best
+    update variant depends on it).  Each candidate is timed twice, in a forward
+    and a reverse pass over the candidates, to cancel the slow drift of the
+    active fraction.  Returns {kernel: best value} and the timings; stores them
+    in the cache when `path` is given."""
     result, timings = {}, {}
 
-    def sweep(plan, k, fixed=()):
-        best, best_ms = None, None
-        for v in CANDIDATES[k]:
-            for fk, fv in fixed:
-                plan.set_launch(fk, fv)
-            plan.set_launch(k, v)
-            init_fields(plan)
-            plan.step(3)  # warm the shape
-            plan.set_launch(k, v)  # restart the timing ring
-            plan.step(steps)
-            st = plan.stats(0)["stage_ms"]
-            ms = sum(st[i] for i in STAGE_OF[k])
-            timings[f"{k}:{v}"] = ms
-            if best_ms is None or ms < best_ms:
-                best, best_ms = v, ms
-        return best, best_ms
+    def measure(plan, k, v, fixed):
+        for fk, fv in fixed:
+            plan.set_launch(fk, fv)
+        plan.set_launch(k, v)
+        plan.step(3)  # warm the shape
+        plan.set_launch(k, v)  # restart the timing ring
+        plan.step(steps)
+        st = plan.stats(0)["stage_ms"]
+        return sum(st[i] for i in STAGE_OF[k])
+
+    def sweep(plan, k, fixed=(), tag=""):
+        cand = list(CANDIDATES[k])
+        acc = {v: 0.0 for v in cand}
+        for order in (cand, cand[::-1]):
+            for v in order:
+                acc[v] += 0.5 * measure(plan, k, v, fixed)
+        for v in cand:
+            timings[f"{tag}{k}:{v}"] = acc[v]
+        best = min(cand, key=lambda v: acc[v])
+        return best, acc[best]
 
     for dense in (False, True):
         plan = make_plan(dense)
+        init_fields(plan)
+        if warm:
+            plan.step(warm)
         if dense:
             result[2], _ = sweep(plan, 2)
         else:
             result[0], _ = sweep(plan, 0)
             plan.set_launch(0, result[0])
-            w4, t_strip = sweep(plan, 4, fixed=((3, 1),))
-            p1, t_list = sweep(plan, 1, fixed=((3, 0),))
-            p2, t_multi = sweep(plan, 1, fixed=((3, 2),))
+            # strip walk: waves per workgroup, then persistent workgroups per CU
+            w4, _ = sweep(plan, 4, fixed=((3, 1),), tag="strip ")
+            ps, t_strip = sweep(plan, 1, fixed=((3, 1), (4, w4)), tag="strip ")
+            p1, t_list = sweep(plan, 1, fixed=((3, 0),), tag="list ")
+            p2, t_multi = sweep(plan, 1, fixed=((3, 2),), tag="list4 ")
             best = min((t_strip, 1), (t_list, 0), (t_multi, 2))[1]
             result[3] = best
             result[4] = w4
-            result[1] = p2 if best == 2 else p1
+            result[1] = {1: ps, 0: p1, 2: p2}[best]
         key = cache_key(plan.descs, arch)
         plan.destroy()
     if path:

@@ -65,7 +65,7 @@ struct spdba_plan_s {
     // buffer layout
     size_t st_spec = 0, st_k0 = 0, state_bytes = 0;
     size_t w_W = 0, w_R = 0, w_fft = 0, w_ab = 0, w_mask = 0, w_wl = 0, w_chunk = 0, w_cnt = 0, w_G = 0,
-           w_Glast = 0, w_rk0 = 0, w_nl = 0, w_ind = 0, w_dense = 0, w_binst = 0, w_table = 0,
+           w_Glast = 0, w_rk0 = 0, w_nl = 0, w_ind = 0, w_smax = 0, w_dense = 0, w_binst = 0, w_table = 0,
            w_probe = 0, work_bytes = 0;
     bool bound = false;
     char *d_state = nullptr, *d_work = nullptr;
@@ -221,12 +221,15 @@ spdba_status update_stage(spdba_plan p, int ev_base) {
         // threshold, mask and update in one pass; the ordered list is built
         // from the mask only when it is read back
         record(p, ev_base + 1);
-        TRY_HIP(launch_update_strip(p->ctx, d, p->upd_waves, p->stream));
+        // persistent: a grid stride over the strips
+        const int64_t grid = std::min<int64_t>(p->n_strips, (int64_t)p->cu_count * p->upd_per_cu);
+        TRY_HIP(launch_update_strip(p->ctx, d, p->upd_waves, (int)grid, p->stream));
         p->list_stale = true;
     } else {
-        TRY_HIP(launch_compact(p->ctx, p->stream));
+        // one-pass threshold, mask and unordered append of the active blocks
+        TRY_HIP(launch_compact_append(p->ctx, p->stream));
         record(p, ev_base + 1);
-        p->list_stale = false;
+        p->list_stale = true;
         // a multiple of 8: the update splits its list into one segment per XCD
         const int grid = ((p->cu_count * p->upd_per_cu + 7) / 8) * 8;
         // four entries in flight need blocks of at most one slot per thread
@@ -503,6 +506,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     p->w_rk0 = take((size_t)n_inst * 2 * sizeof(double));
     p->w_nl = take((size_t)tile * 2 * sizeof(double));
     p->w_ind = take((size_t)strip * sizeof(double));
+    p->w_smax = take((size_t)strip * sizeof(double));
     p->w_dense = take((size_t)tile * sizeof(double));
     p->w_binst = take((size_t)blk * sizeof(uint16_t));
     p->w_table = take((size_t)n_inst * sizeof(InstDev));
@@ -551,6 +555,7 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     c.done = reinterpret_cast<uint32_t *>(p->d_work + p->w_cnt + 8);
     c.nl_part = reinterpret_cast<double *>(p->d_work + p->w_nl);
     c.ind_part = reinterpret_cast<double *>(p->d_work + p->w_ind);
+    c.strip_max = reinterpret_cast<double *>(p->d_work + p->w_smax);
     c.dense_part = reinterpret_cast<double *>(p->d_work + p->w_dense);
     c.blk_inst = reinterpret_cast<const uint16_t *>(p->d_work + p->w_binst);
     c.skip = p->d_skip;

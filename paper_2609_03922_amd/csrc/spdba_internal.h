@@ -65,6 +65,7 @@ struct Ctx {
     uint32_t *done;            // [1] workgroup arrival counter (self-resetting)
     double *nl_part;           // [n_tiles][2] per-tile FP64 sums of the nonlinear stage
     double *ind_part;          // [n_strips] per-strip FP64 sums (CH gradient energy)
+    double *strip_max;         // [n_strips] largest block value a_b of each strip
     double *dense_part;        // [n_tiles] per-tile FP64 sums of the dense update
     uint32_t *nonfinite;       // [1]
     const uint16_t *blk_inst;  // [nb_total] owning instance of each block
@@ -87,8 +88,9 @@ hipError_t launch_nonlinear(const Ctx &c, bool dbl, int waves, hipStream_t s);
 hipError_t launch_k0_rhs(const Ctx &c, hipStream_t s);
 hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s);
 hipError_t launch_compact(const Ctx &c, hipStream_t s, int from_mask = 0);
+hipError_t launch_compact_append(const Ctx &c, hipStream_t s);
 hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_t s);
-hipError_t launch_update_strip(const Ctx &c, bool dbl, int waves, hipStream_t s);
+hipError_t launch_update_strip(const Ctx &c, bool dbl, int waves, int grid, hipStream_t s);
 hipError_t launch_dense(const Ctx &c, bool dbl, int threads, hipStream_t s);
 hipError_t launch_reset(const Ctx &c, hipStream_t s);
 // set_field / get_field helpers on one instance (sizes from the host table)

@@ -611,7 +611,11 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
             m = 0.0;
         }
         const double sm = wave_max(m);
-        if (lane == 0 && sm > 0.0) atomicMax(c.G + ii, (unsigned long long)__double_as_longlong(sm));
+        if (lane == 0) {
+            if (strip == 0) *c.count = 0u;  // the one-pass compaction appends to it
+            c.strip_max[strip] = sm;  // lets the update drop whole frozen strips
+            if (sm > 0.0) atomicMax(c.G + ii, (unsigned long long)__double_as_longlong(sm));
+        }
         if (OP == OP_CH && lane == 0) {
             double tsum = 0.0;
             for (int i = 0; i < nw; ++i) tsum += lds_sum[i];
@@ -696,6 +700,60 @@ __global__ void __launch_bounds__(256) k_compact_write(Ctx c) {
     if (chunk == c.n_chunks - 1 && threadIdx.x == 255) *c.count = offset + scan[255];
 }
 
+// One-pass compaction for the update: threshold and mask of a chunk of 1024
+// blocks, then one atomic append of the chunk's active blocks (ascending
+// within the chunk).  The update needs no global order; the ordered list the
+// API returns is rebuilt from the mask when it is read.  The last workgroup to
+// arrive hands G over, as the strip walk does.  The indicator clears the
+// counter.
+__global__ void __launch_bounds__(256) k_compact_append(Ctx c) {
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t base;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t b0 = (int64_t)blockIdx.x * CHUNK_BLOCKS + 4 * threadIdx.x;
+    uint32_t bits = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t gb = b0 + k;
+        if (gb < c.nb_total) {
+            const bool on = block_active(c, gb);
+            c.mask[gb] = on ? 1 : 0;
+            bits |= (on ? 1u : 0u) << k;
+        }
+    }
+    const uint32_t mine = __popc(bits);
+    // exclusive prefix within the wave (shift-up scan), then across waves
+    uint32_t incl = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t v = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += v;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        base = tot ? atomicAdd(c.count, tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t pos = base + incl - mine;
+    for (int i = 0; i < w; ++i) pos += wsum[i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (bits & (1u << k)) c.worklist[pos++] = (uint32_t)(b0 + k);
+    // every G read of this workgroup happened before the barriers above
+    if (threadIdx.x == 0) {
+        const unsigned int done = atomicAdd(c.done, 1u);
+        if (done == gridDim.x - 1) {
+            for (int i = 0; i < c.n_inst; ++i) {
+                c.G_last[i] = c.G[i];
+                c.G[i] = 0ull;
+            }
+            *c.done = 0u;
+        }
+    }
+}
+
 // -------------------------------------------------------------------------
 // active-block update: persistent workgroups walk the ordered list.  The list
 // is cut into 8 contiguous segments, one per XCD (workgroup id mod 8), so
@@ -777,13 +835,6 @@ __device__ __forceinline__ void update_block(const Ctx &c, int64_t gb) {
     }
 }
 
-// instance maxima consumed: keep a copy for read-back, clear for the next pass
-__global__ void k_consume_G(Ctx c) {
-    for (int i = threadIdx.x; i < c.n_inst; i += blockDim.x) {
-        c.G_last[i] = c.G[i];
-        c.G[i] = 0ull;
-    }
-}
 
 template <typename T, int OP>
 __global__ void __launch_bounds__(256) k_update(Ctx c) {
@@ -1005,47 +1056,53 @@ __device__ __forceinline__ void update_strip_body(const Ctx &c, const InstDev &I
     }
 }
 
-// Strip walk with the threshold fused in: each lane decides its block (the
-// compaction's rule), the lane leaders write the mask, active lanes update.
+// Strip walk with the threshold fused in, persistent: each workgroup takes
+// strips in a grid stride.  A strip whose largest block value is at or below
+// the instance threshold is frozen as a whole (one 8-byte read, its mask bytes
+// cleared); otherwise each lane decides its block (the compaction's rule), the
+// lane leaders write the mask and the waves walk the rows of the active lanes.
+// Every wave holds the same lanes, so a wave-wide vote replaces any barrier.
 template <typename T, int OP>
 __global__ void __launch_bounds__(1024) k_update_strip(Ctx c) {
     constexpr int V = CV<T>::V;
-    __shared__ int any_active;
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t strip = blockIdx.x;
-    const int ii = find_by_offset(c.inst, c.n_inst, strip, 0);
-    const InstDev &I = c.inst[ii];
-    const int64_t ls = strip - I.strip_off;
-    const int lnsx = I.lnbk[2] - I.lS;
-    const int sx = (int)(ls & ((1 << lnsx) - 1));
-    const int64_t t = ls >> lnsx;
-    const int sby = (int)(t & ((1 << I.lnbk[1]) - 1));
-    const int sbz = (int)(t >> I.lnbk[1]);
-    const int chunks = I.chunks;
-    const int LB = chunks > 1 ? 64 : (I.b[2] / V);
-    const int lane_bx = (sx << I.lS) + (chunks > 1 ? 0 : lane / LB);
-    const int64_t lane_lb = ((((int64_t)sbz << I.lnbk[1]) + sby) << I.lnbk[2]) + lane_bx;
-    const bool in_strip = chunks > 1 || lane * V < (I.S << I.lb[2]);
-    bool lane_on = false;
-    if (in_strip) {
-        const int64_t gb = I.blk_off + lane_lb;
-        bool on;
-        if (c.dense) on = true;
-        else if (I.pin && lane_lb == 0) on = true;
-        else if (c.skip && c.skip[gb]) on = false;
-        else on = c.a_b[gb] > I.tau2 * __longlong_as_double((long long)c.G[ii]);
-        lane_on = on;
-        if (w == 0 && (chunks > 1 ? lane == 0 : (lane % LB) == 0)) c.mask[gb] = on ? 1 : 0;
+    for (int64_t strip = blockIdx.x; strip < c.n_strips; strip += gridDim.x) {
+        const int ii = find_by_offset(c.inst, c.n_inst, strip, 0);
+        const InstDev &I = c.inst[ii];
+        const int64_t ls = strip - I.strip_off;
+        const int lnsx = I.lnbk[2] - I.lS;
+        const int sx = (int)(ls & ((1 << lnsx) - 1));
+        const int64_t t = ls >> lnsx;
+        const int sby = (int)(t & ((1 << I.lnbk[1]) - 1));
+        const int sbz = (int)(t >> I.lnbk[1]);
+        const int chunks = I.chunks;
+        const int LB = chunks > 1 ? 64 : (I.b[2] / V);
+        const int lane_bx = (sx << I.lS) + (chunks > 1 ? 0 : lane / LB);
+        const int64_t lane_lb = ((((int64_t)sbz << I.lnbk[1]) + sby) << I.lnbk[2]) + lane_bx;
+        const bool in_strip = chunks > 1 || lane * V < (I.S << I.lb[2]);
+        const double thr = I.tau2 * __longlong_as_double((long long)c.G[ii]);
+        const bool live = c.dense || (I.pin && ls == 0) || c.strip_max[strip] > thr;
+        bool lane_on = false;
+        if (in_strip) {
+            const int64_t gb = I.blk_off + lane_lb;
+            bool on = false;
+            if (live) {
+                if (c.dense) on = true;
+                else if (I.pin && lane_lb == 0) on = true;
+                else if (c.skip && c.skip[gb]) on = false;
+                else on = c.a_b[gb] > thr;
+            }
+            lane_on = on;
+            if (w == 0 && (chunks > 1 ? lane == 0 : (lane % LB) == 0)) c.mask[gb] = on ? 1 : 0;
+        }
+        const bool k0_lane = I.k0path && ls == 0 && lane == 0;
+        if (__any(lane_on)) update_strip_body<T, OP>(c, I, ii, lane_on, sbz, sby, sx, lane, w, nw, k0_lane);
     }
-    if (threadIdx.x == 0) any_active = 0;
+    // every G value this workgroup used was consumed before the barrier, so
+    // the last workgroup to arrive may hand G over: read-back copy, cleared for
+    // the next indicator pass (the kernel boundary publishes the writes)
     __syncthreads();
-    if (lane_on) any_active = 1;
-    __syncthreads();
-    // every lane's G value has been consumed by now (it decided lane_on before
-    // the barrier), so the last workgroup to arrive may hand G over: read-back
-    // copy, cleared for the next indicator pass.  No fence: the arrival orders
-    // nothing but G reads, and the kernel boundary publishes the writes.
     if (threadIdx.x == 0) {
         const unsigned int done = atomicAdd(c.done, 1u);
         if (done == gridDim.x - 1) {
@@ -1056,8 +1113,6 @@ __global__ void __launch_bounds__(1024) k_update_strip(Ctx c) {
             *c.done = 0u;
         }
     }
-    const bool k0_lane = I.k0path && ls == 0 && lane == 0;
-    if (any_active) update_strip_body<T, OP>(c, I, ii, lane_on, sbz, sby, sx, lane, w, nw, k0_lane);
 }
 
 // -------------------------------------------------------------------------
@@ -1276,6 +1331,11 @@ hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s) {
     return dbl ? ind_launch<double>(c, waves, s) : ind_launch<float>(c, waves, s);
 }
 
+hipError_t launch_compact_append(const Ctx &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_compact_append, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+
 hipError_t launch_compact(const Ctx &c, hipStream_t s, int from_mask) {
     hipLaunchKernelGGL(k_compact_count, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c, from_mask);
     hipError_t e = hipGetLastError();
@@ -1294,9 +1354,6 @@ static hipError_t upd_launch(const Ctx &c, int grid, int multi, hipStream_t s) {
     if (c.op == OP_CH) upd_launch_op<T, OP_CH>(c, grid, multi, s);
     else if (c.op == OP_GS) upd_launch_op<T, OP_GS>(c, grid, multi, s);
     else upd_launch_op<T, OP_NLSE>(c, grid, multi, s);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_consume_G, dim3(1), dim3(64), 0, s, c);
     return hipGetLastError();
 }
 hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_t s) {
@@ -1304,15 +1361,15 @@ hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_
 }
 
 template <typename T>
-static hipError_t upd_strip_launch(const Ctx &c, int waves, hipStream_t s) {
-    dim3 grid((unsigned)c.n_strips), block(64 * waves);
-    if (c.op == OP_CH) hipLaunchKernelGGL((k_update_strip<T, OP_CH>), grid, block, 0, s, c);
-    else if (c.op == OP_GS) hipLaunchKernelGGL((k_update_strip<T, OP_GS>), grid, block, 0, s, c);
-    else hipLaunchKernelGGL((k_update_strip<T, OP_NLSE>), grid, block, 0, s, c);
+static hipError_t upd_strip_launch(const Ctx &c, int waves, int grid, hipStream_t s) {
+    dim3 g((unsigned)grid), block(64 * waves);
+    if (c.op == OP_CH) hipLaunchKernelGGL((k_update_strip<T, OP_CH>), g, block, 0, s, c);
+    else if (c.op == OP_GS) hipLaunchKernelGGL((k_update_strip<T, OP_GS>), g, block, 0, s, c);
+    else hipLaunchKernelGGL((k_update_strip<T, OP_NLSE>), g, block, 0, s, c);
     return hipGetLastError();
 }
-hipError_t launch_update_strip(const Ctx &c, bool dbl, int waves, hipStream_t s) {
-    return dbl ? upd_strip_launch<double>(c, waves, s) : upd_strip_launch<float>(c, waves, s);
+hipError_t launch_update_strip(const Ctx &c, bool dbl, int waves, int grid, hipStream_t s) {
+    return dbl ? upd_strip_launch<double>(c, waves, grid, s) : upd_strip_launch<float>(c, waves, grid, s);
 }
 
 template <typename T>

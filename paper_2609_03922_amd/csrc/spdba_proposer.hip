@@ -294,10 +294,22 @@ __global__ void k_miss(const uint8_t *skip, const uint8_t *mask, int64_t nb, uin
     if ((threadIdx.x & 63) == 0 && n) atomicAdd(count, n);
 }
 
-__global__ void k_skip(const float *prob, int64_t nb, float thr, uint8_t *skip) {
+// skip[b] = prob[b] < thr, or all zero when the gate (a miss count) is set;
+// optionally adds the number of skipped blocks to *count
+__global__ void k_skip(const float *prob, int64_t nb, float thr, const uint32_t *gate, uint8_t *skip,
+                       uint32_t *count) {
+    const bool off = gate != nullptr && *gate != 0u;
+    uint32_t n = 0;
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
-         b += (int64_t)gridDim.x * blockDim.x)
-        skip[b] = prob[b] < thr ? 1 : 0;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        const bool s = !off && prob[b] < thr;
+        skip[b] = s ? 1 : 0;
+        n += s ? 1u : 0u;
+    }
+    if (count) {
+        for (int off2 = 32; off2 >= 1; off2 >>= 1) n += __shfl_xor(n, off2, 64);
+        if ((threadIdx.x & 63) == 0 && n) atomicAdd(count, n);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -567,10 +579,11 @@ spdba_status spdba_proposer_miss(const uint8_t *skip, const uint8_t *mask, int64
     return st(hipGetLastError());
 }
 
-spdba_status spdba_proposer_skip(const float *prob, int64_t nb, float thr, uint8_t *skip,
-                                 void *stream) {
-    if (!prob || !skip || nb < 1) return SPDBA_EINVAL;
-    hipLaunchKernelGGL(k_skip, dim3(grid_n(nb)), dim3(256), 0, (hipStream_t)stream, prob, nb, thr, skip);
+spdba_status spdba_proposer_skip(const float *prob, int64_t nb, float thr, const uint32_t *gate,
+                                 uint8_t *skip, uint32_t *count, void *stream) {
+    if (!prob || !skip || nb < 1 || !(thr == thr)) return SPDBA_EINVAL;
+    hipLaunchKernelGGL(k_skip, dim3(grid_n(nb)), dim3(256), 0, (hipStream_t)stream, prob, nb, thr, gate, skip,
+                       count);
     return st(hipGetLastError());
 }
 

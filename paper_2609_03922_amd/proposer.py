@@ -98,13 +98,48 @@ class Proposer:
         self.threshold = float(np.nextafter(pos[k], -np.inf)) if k < pos.size else 0.0
         return self.threshold
 
+    def choose_threshold_windows(self, X, Y, nb: int, max_miss_windows: float = 0.2):
+        """Threshold from a simulation of the window protocol on held-out
+        windows (X, Y: consecutive windows of nb blocks each).  A threshold t
+        proposes the set p < t for the next window; a window whose set holds a
+        positive block is a miss and the window after it runs the plain rule.
+        Returns the t that maximises the skipped share over all windows, among
+        those whose miss windows are at most `max_miss_windows` of the total
+        (t = 0, nothing skipped, always qualifies)."""
+        p = self.predict(X).cpu().numpy().reshape(-1, nb)
+        y = Y.cpu().numpy().reshape(-1, nb) > 0.5
+        W = p.shape[0]
+        pos = np.sort(p[y])
+        # candidates: just below each of the lowest positive scores, then a
+        # coarse ladder above them
+        cand = [0.0] + [float(np.nextafter(v, -np.inf)) for v in pos[:256]]
+        cand += [float(v) for v in np.quantile(pos, np.linspace(0.001, 0.2, 60))]
+        best, best_gain, table = 0.0, 0.0, []
+        for t in sorted(set(cand)):
+            skip = p < t
+            share = skip.mean(axis=1)
+            miss = (skip & y).any(axis=1)
+            plain_next = np.concatenate([[False], miss[:-1]])  # fallback windows
+            gain = float(np.where(plain_next, 0.0, share).mean())
+            frac = float(miss.mean())
+            table.append((t, gain, frac))
+            if frac <= max_miss_windows and gain > best_gain:
+                best, best_gain = t, gain
+        self.threshold = best
+        self.threshold_table = table
+        return best
+
     def state(self):
         return dict(weights=self.w.cpu().numpy(), threshold=self.threshold)
 
 
 class WindowRunner:
     """Steps a bound plan with the window protocol (or the plain rule when
-    `proposer` is None), keeping the audit snapshots on the device."""
+    `proposer` is None), keeping the audit snapshots on the device.
+
+    Nothing in a window waits for the host: the miss count of the audits gates
+    the next skip set on the device (spdba_proposer_skip), and the per-window
+    miss and skip counts are kept in device arrays that `history` reads once."""
 
     def __init__(self, plan: S.Plan, proposer: Proposer | None, K: int = 10, audit: int = 3,
                  total_steps: int = 500, log_masks: bool = False):
@@ -123,22 +158,30 @@ class WindowRunner:
         self.prob = torch.empty(self.nb, device=dev)
         self.skip = torch.zeros(self.nb, dtype=torch.uint8, device=dev)
         self.miss = torch.zeros(1, dtype=torch.int32, device=dev)
+        cap = total_steps // K + 2
+        self.miss_hist = torch.zeros(cap, dtype=torch.int32, device=dev)  # misses found in window w
+        self.skip_hist = torch.zeros(cap, dtype=torch.int32, device=dev)  # blocks skipped in window w
         self.fscr = torch.empty(max(4096, 520 * n_inst), dtype=torch.uint8, device=dev)
         self.ab_addr, self.mask_addr, self.g_addr, _ = plan.device_views()
         self.step_no = 0
-        self.proposing = False  # a skip set is armed for the current window
+        self.window = 0
+        self.proposing = False  # a (possibly empty) skip set is armed for the current window
         self.log_masks = log_masks
         self.win_masks = torch.zeros(K, self.nb, dtype=torch.uint8, device=dev)
         self.windows = []  # (features of window w) for training
-        self.history = dict(windows=0, misses=0, fallbacks=0, skipped_block_steps=0, steps=0)
-        self._skip_count = 0
+
+    def _grow(self):
+        torch = self.torch
+        if self.window + 1 >= self.miss_hist.numel():
+            z = torch.zeros_like(self.miss_hist)
+            self.miss_hist = torch.cat([self.miss_hist, z])
+            self.skip_hist = torch.cat([self.skip_hist, z.clone()])
 
     def _snapshot(self, slot):
         _copy_from_addr(self.ab[slot], self.ab_addr, self.nb * 8, self.plan.stream)
         _copy_from_addr(self.G[slot], self.g_addr, self.G.shape[1] * 8, self.plan.stream)
 
     def step(self, n: int = 1):
-        torch = self.torch
         for _ in range(n):
             pos = self.step_no % self.K
             audit = pos >= self.K - self.audit
@@ -152,9 +195,6 @@ class WindowRunner:
                 self.plan.set_skip(None)
                 self.plan.set_block_energy(None)
             self.plan.step(1)
-            self.history["steps"] += 1
-            if self.proposing and not audit:
-                self.history["skipped_block_steps"] += int(self._skip_count)
             if self.log_masks:
                 _copy_from_addr(self.win_masks[pos], self.mask_addr, self.nb, self.plan.stream)
             if audit:
@@ -168,31 +208,40 @@ class WindowRunner:
 
     def _end_window(self):
         torch = self.torch
-        self.history["windows"] += 1
-        missed = False
-        if self.proposing:
-            self.plan.synchronize()
-            missed = int(self.miss.item()) > 0
-            self.miss.zero_()
-            if missed:
-                self.history["misses"] += 1
+        st = self.plan.stream
+        self._grow()
         frac = self.step_no / float(self.total)
         S.spdba_proposer_features(self.plan, [self.ab[0], self.ab[1], self.ab[2]],
                                   [self.G[0], self.G[1], self.G[2]], self.mask_addr, self.eb, frac,
-                                  self.x, self.fscr, stream=self.plan.stream)
+                                  self.x, self.fscr, stream=st)
         if self.log_masks:
-            self.windows.append((self.x.clone(), self.win_masks.clone()))
-        if self.prop is None or missed:
-            if missed:
-                self.history["fallbacks"] += 1
-            self.proposing = False
-            return
+            with torch.cuda.stream(st):
+                self.windows.append((self.x.clone(), self.win_masks.clone()))
+        if self.prop is not None:
+            self.prop.predict(self.x, self.prob, stream=st)
+            # a miss in this window's audits leaves the next window's set empty
+            S.spdba_proposer_skip(self.prob, self.prop.threshold, self.skip, gate=self.miss,
+                                  count=self.skip_hist[self.window + 1:self.window + 2], stream=st)
+            self.proposing = True
+        with torch.cuda.stream(st):
+            self.miss_hist[self.window:self.window + 1].copy_(self.miss)
+            self.miss.zero_()
+        self.window += 1
+
+    @property
+    def history(self):
+        """Window counts (one device read): windows, windows whose audits found
+        a proposed-skip block active (each makes the next window plain),
+        skipped block-steps (skip set size times the window's proposal steps)."""
         self.plan.synchronize()
-        self.prop.predict(self.x, self.prob)
-        S.spdba_proposer_skip(self.prob, self.prop.threshold, self.skip)
-        torch.cuda.synchronize()
-        self._skip_count = int(self.skip.sum().item())
-        self.proposing = True
+        m = self.miss_hist[:self.window].cpu().numpy()
+        sk = self.skip_hist[:self.window + 1].cpu().numpy().astype(np.int64)
+        # the set armed at the end of window w acts in window w + 1, on its
+        # non-audit steps that have run
+        steps_in = [min(self.K - self.audit, max(0, self.step_no - w * self.K)) for w in range(len(sk))]
+        misses = int((m > 0).sum())
+        return dict(windows=self.window, misses=misses, fallbacks=misses,
+                    skipped_block_steps=int(sum(int(a) * b for a, b in zip(sk, steps_in))), steps=self.step_no)
 
     def dataset(self):
         """(X, Y) pairs: features at the end of window w, labels = union of
@@ -202,9 +251,9 @@ class WindowRunner:
         for w in range(len(self.windows) - 1):
             X.append(self.windows[w][0])
             y = torch.empty(self.nb, device="cuda")
-            S.spdba_proposer_labels(self.windows[w + 1][1], y)
+            S.spdba_proposer_labels(self.windows[w + 1][1], y, stream=self.plan.stream)
             Y.append(y)
-        torch.cuda.synchronize()
+        self.plan.synchronize()
         return torch.cat(X), torch.cat(Y)
 
 

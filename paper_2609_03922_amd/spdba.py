@@ -121,7 +121,7 @@ def load():
         "spdba_mlp_to_bf16": [P, P, I64, P],
         "spdba_proposer_features": [P, P, P, P, P, ctypes.c_float, P, P, P],
         "spdba_proposer_labels": [P, I32, I64, P, P],
-        "spdba_proposer_skip": [P, I64, ctypes.c_float, P, P],
+        "spdba_proposer_skip": [P, I64, ctypes.c_float, P, P, P, P],
         "spdba_proposer_miss": [P, P, I64, P, P],
         "spdba_set_block_energy": [P, P],
     }
@@ -462,9 +462,9 @@ def spdba_proposer_labels(masks, y, stream=None):
         "spdba_proposer_labels")
 
 
-def spdba_proposer_skip(prob, threshold, skip, stream=None):
-    _ck(load().spdba_proposer_skip(_p(prob), prob.numel(), float(threshold), _p(skip), _sp(stream)),
-        "spdba_proposer_skip")
+def spdba_proposer_skip(prob, threshold, skip, gate=None, count=None, stream=None):
+    _ck(load().spdba_proposer_skip(_p(prob), prob.numel(), float(threshold), _p(gate), _p(skip), _p(count),
+                                   _sp(stream)), "spdba_proposer_skip")
 
 
 def spdba_proposer_miss(skip, mask_addr, nb, count, stream=None):

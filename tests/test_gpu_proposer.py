@@ -186,10 +186,16 @@ def test_features_labels_skip_miss_match_reference():
     assert np.array_equal(y.cpu().numpy(), mlp.labels(masks))
     p = np.random.default_rng(3).random(nb).astype(np.float32)
     sk = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    S.spdba_proposer_skip(T(p), 0.4, sk)
+    nsk = torch.zeros(1, dtype=torch.int32, device="cuda")
+    S.spdba_proposer_skip(T(p), 0.4, sk, count=nsk)
     cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
     S.spdba_proposer_miss(sk, T(ref["mask"]), nb, cnt)
     torch.cuda.synchronize()
     assert np.array_equal(sk.cpu().numpy(), (p < 0.4).astype(np.uint8))
+    assert nsk.item() == int(np.sum(p < 0.4))
     assert cnt.item() == int(np.sum((p < 0.4) & (ref["mask"] > 0)))
+    # a set gate (a miss count) clears the whole set and counts nothing
+    S.spdba_proposer_skip(T(p), 0.4, sk, gate=cnt if cnt.item() else torch.ones_like(cnt), count=nsk)
+    torch.cuda.synchronize()
+    assert int(sk.sum().item()) == 0 and nsk.item() == int(np.sum(p < 0.4))
     plan.destroy()
