@@ -150,7 +150,7 @@ def main():
             dd, _ = build_descs(cfg, S, inputs, dense=dense, timing=True)
             return S.Plan(dd)
         choice, timings = autotune.tune(make_plan, lambda p: init_fields(p, cfg, sizes, inputs, np, torch),
-                                        arch=arch, warm=K // 2)
+                                        arch=arch, warm=min(cfg["steps"], 500) // 2)
         print("launch tuning (stage ms):", json.dumps(timings), file=sys.stderr, flush=True)
         tuned = {str(k): v for k, v in choice.items()}
 
