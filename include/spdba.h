@@ -118,6 +118,10 @@ typedef struct {
     int32_t input_preserving_fft; /* 1 if out-of-place inverse transforms keep their
                                      input (probed at bind), 0 if a copy is used    */
     int32_t graph_replay;     /* 1 if spdba_step replays a captured HIP graph       */
+    double indicator_kernel_ms; /* SPDBA_FLAG_TIMING: mean indicator kernel time per
+                                   step (sum of both half steps for NLSE), from
+                                   events recorded at the dispatch's own start and
+                                   end (no queue gap); 0 when not available         */
 } spdba_stats_t;
 
 typedef struct spdba_plan_s *spdba_plan;

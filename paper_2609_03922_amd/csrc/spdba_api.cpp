@@ -86,6 +86,7 @@ struct spdba_plan_s {
     // stage events: a ring of per-step sets, read only after the stream drained
     static constexpr int kRing = 64;
     hipEvent_t ev[kRing][12] = {};
+    hipEvent_t evk[kRing][4] = {};  // indicator dispatch start/stop, per half step
     bool have_events = false;
     int ring = 0;         // set used by the step being enqueued
     int ring_filled = 0;  // sets holding a complete step
@@ -215,7 +216,13 @@ spdba_status update_stage(spdba_plan p, int ev_base) {
         p->last_dense = true;
         return SPDBA_OK;
     }
-    TRY_HIP(launch_indicator(p->ctx, d, p->ind_waves, p->stream));
+    hipEvent_t k0 = nullptr, k1 = nullptr;
+    if (p->timing && p->have_events && !p->use_graph) {
+        const int h = ev_base == 8 ? 2 : 0;  // second NLSE half step
+        k0 = p->evk[p->ring][h];
+        k1 = p->evk[p->ring][h + 1];
+    }
+    TRY_HIP(launch_indicator(p->ctx, d, p->ind_waves, p->stream, k0, k1));
     record(p, ev_base);
     if (p->upd_mode == 1) {
         // threshold, mask and update in one pass; the ordered list is built
@@ -599,6 +606,8 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     if (p->timing && !p->have_events) {
         for (auto &set : p->ev)
             for (auto &e : set) TRY_HIP(hipEventCreate(&e));
+        for (auto &set : p->evk)
+            for (auto &e : set) TRY_HIP(hipEventCreate(&e));
         p->have_events = true;
     }
     return SPDBA_OK;
@@ -872,6 +881,7 @@ spdba_status spdba_stats(spdba_plan p, int32_t inst, spdba_stats_t *out) {
         // mean over the completed steps held in the ring (the stream has drained)
         const int nset = p->ring_filled;
         double acc6[6] = {0, 0, 0, 0, 0, 0};
+        double ind_k = 0.0;
         for (int k = 1; k <= nset; ++k) {
             hipEvent_t *ev = p->ev[(p->ring - k + spdba_plan_s::kRing) % spdba_plan_s::kRing];
             auto el = [&](int a0, int b0) {
@@ -904,8 +914,16 @@ spdba_status spdba_stats(spdba_plan p, int32_t inst, spdba_stats_t *out) {
                 st[5] = el(0, 11);
             }
             for (int j = 0; j < 6; ++j) acc6[j] += st[j];
+            if (!p->last_dense) {
+                hipEvent_t *ek = p->evk[(p->ring - k + spdba_plan_s::kRing) % spdba_plan_s::kRing];
+                for (int h = 0; h < (p->op == OP_NLSE ? 2 : 1); ++h) {
+                    float ms = 0.f;
+                    if (hipEventElapsedTime(&ms, ek[2 * h], ek[2 * h + 1]) == hipSuccess) ind_k += ms;
+                }
+            }
         }
         for (int j = 0; j < 6; ++j) out->stage_ms[j] = acc6[j] / nset;
+        out->indicator_kernel_ms = ind_k / nset;
     }
     out->input_preserving_fft = p->inv_preserving ? 1 : 0;
     out->graph_replay = p->graph != nullptr ? 1 : 0;
@@ -944,9 +962,12 @@ spdba_status spdba_destroy(spdba_plan p) {
         destroy_fft(g.inv1_ip);
     }
     if (p->info) rocfft_execution_info_destroy(p->info);
-    if (p->have_events)
+    if (p->have_events) {
         for (auto &set : p->ev)
             for (auto &e : set) (void)hipEventDestroy(e);
+        for (auto &set : p->evk)
+            for (auto &e : set) (void)hipEventDestroy(e);
+    }
     delete p;
     return SPDBA_OK;
 }

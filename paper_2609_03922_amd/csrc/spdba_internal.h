@@ -86,7 +86,8 @@ template <typename T> constexpr int tile_elems() { return sizeof(T) == 4 ? 1024 
 // Launchers (return hipError_t of the launch).  `dbl` selects FP64.
 hipError_t launch_nonlinear(const Ctx &c, bool dbl, int waves, hipStream_t s);
 hipError_t launch_k0_rhs(const Ctx &c, hipStream_t s);
-hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s);
+hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s, hipEvent_t e0 = nullptr,
+                            hipEvent_t e1 = nullptr);
 hipError_t launch_compact(const Ctx &c, hipStream_t s, int from_mask = 0);
 hipError_t launch_compact_append(const Ctx &c, hipStream_t s);
 hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_t s);

@@ -21,6 +21,8 @@
 
 #include "spdba_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <float.h>
 
 namespace spdba {
@@ -1320,15 +1322,16 @@ hipError_t launch_k0_rhs(const Ctx &c, hipStream_t s) {
 }
 
 template <typename T>
-static hipError_t ind_launch(const Ctx &c, int waves, hipStream_t s) {
+static hipError_t ind_launch(const Ctx &c, int waves, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     dim3 grid((unsigned)c.n_strips), block(64 * waves);
-    if (c.op == OP_CH) hipLaunchKernelGGL((k_indicator<T, OP_CH>), grid, block, 0, s, c);
-    else if (c.op == OP_GS) hipLaunchKernelGGL((k_indicator<T, OP_GS>), grid, block, 0, s, c);
-    else hipLaunchKernelGGL((k_indicator<T, OP_NLSE>), grid, block, 0, s, c);
+    // with an event pair the dispatch itself stamps its start and end
+    if (c.op == OP_CH) hipExtLaunchKernelGGL((k_indicator<T, OP_CH>), grid, block, 0, s, e0, e1, 0, c);
+    else if (c.op == OP_GS) hipExtLaunchKernelGGL((k_indicator<T, OP_GS>), grid, block, 0, s, e0, e1, 0, c);
+    else hipExtLaunchKernelGGL((k_indicator<T, OP_NLSE>), grid, block, 0, s, e0, e1, 0, c);
     return hipGetLastError();
 }
-hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s) {
-    return dbl ? ind_launch<double>(c, waves, s) : ind_launch<float>(c, waves, s);
+hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    return dbl ? ind_launch<double>(c, waves, s, e0, e1) : ind_launch<float>(c, waves, s, e0, e1);
 }
 
 hipError_t launch_compact_append(const Ctx &c, hipStream_t s) {

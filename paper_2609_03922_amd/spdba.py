@@ -75,6 +75,7 @@ class Stats(ctypes.Structure):
         ("stage_ms", ctypes.c_double * 6),
         ("input_preserving_fft", ctypes.c_int32),
         ("graph_replay", ctypes.c_int32),
+        ("indicator_kernel_ms", ctypes.c_double),
     ]
 
 
@@ -378,7 +379,8 @@ class Plan:
         _ck(load().spdba_stats(self.h, i, ctypes.byref(s)), "spdba_stats")
         return dict(steps=s.steps, active_blocks=s.active_blocks, total_blocks=s.total_blocks,
                     G=s.G, mean=list(s.mean), energy=s.energy, stage_ms=list(s.stage_ms),
-                    input_preserving_fft=s.input_preserving_fft, graph_replay=s.graph_replay)
+                    input_preserving_fft=s.input_preserving_fft, graph_replay=s.graph_replay,
+                    indicator_kernel_ms=s.indicator_kernel_ms)
 
     def destroy(self):
         if self.h is not None and self.h.value:
