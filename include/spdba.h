@@ -183,7 +183,10 @@ spdba_status spdba_set_skip(spdba_plan plan, const uint8_t *d_skip);
 
 /* Synchronising read-backs of the last update of instance `inst` (host arrays):
  * the 0/1 mask (n >= blocks), a_b values and G (n >= blocks), and the ordered
- * active-block worklist as instance-local block ids (n >= blocks). */
+ * active-block worklist as instance-local block ids (n >= blocks).  The update
+ * itself needs no order (it walks an unordered append list, or the strips);
+ * the first spdba_worklist call after an update builds the ascending list
+ * from the mask, once. */
 spdba_status spdba_active_mask(spdba_plan plan, int32_t inst, uint8_t *host_out, size_t n);
 spdba_status spdba_indicator(spdba_plan plan, int32_t inst, double *host_ab, size_t n, double *host_G);
 spdba_status spdba_worklist(spdba_plan plan, int32_t inst, uint32_t *host_out, size_t n, int64_t *count);
@@ -202,8 +205,9 @@ spdba_status spdba_stats(spdba_plan plan, int32_t inst, spdba_stats_t *out);
  * indicator (value = waves per workgroup, power of two 1..16), 1 = persistent
  * active update (workgroups per compute unit, 1..64; both the block-list walk
  * and the strip walk), 2 = dense update (threads per workgroup, power of two
- * 64..1024), 3 = active-update variant (0 = persistent walk of the ordered
- * block list, 1 = persistent strip walk that applies the threshold itself and
+ * 64..1024), 3 = active-update variant (0 = persistent walk of the block list
+ * appended by a one-pass threshold kernel, 1 = persistent strip walk that
+ * applies the threshold itself and
  * skips strips whose largest block value is at or below it, 2 = block-list
  * walk with four entries in flight per workgroup; default 1), 4 = strip-walk
  * update (waves per workgroup, power of two 1..16).

@@ -55,6 +55,17 @@ def test_proposer_trains_and_skips_with_bounded_error():
           f"threshold {thr:.4f}, recall {recall:.4f}, proposed skip share {skip_share:.3f}", flush=True)
     assert losses[-1] < losses[0]
     assert recall == 1.0
+    # the protocol-simulating threshold: the chosen entry respects the cap on
+    # miss windows and is the best gain among those that do
+    nb = (N // B) ** 3
+    thr_w = prop.choose_threshold_windows(Xh, Yh, nb, max_miss_windows=0.2)
+    tab = prop.threshold_table
+    chosen = [r for r in tab if r[0] == thr_w][0]
+    ok = [r for r in tab if r[2] <= 0.2]
+    print(f"window-simulation threshold {thr_w:.4f}: held-out skip share {chosen[1]:.3f}, "
+          f"miss windows {chosen[2]:.3f}", flush=True)
+    assert chosen[2] <= 0.2 and chosen[1] >= max(r[1] for r in ok) - 1e-12
+    prop.threshold = thr
 
     # unseen seed: plain, proposer, dense
     fields = {}

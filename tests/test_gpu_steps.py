@@ -232,3 +232,37 @@ def test_determinism_and_batched_equals_singles():
         print(f"batched vs single, instance {i}: rel-L2 {err:.3e}", flush=True)
         assert err < 1e-5
         p.destroy()
+
+
+def test_stage_timing_and_update_variants_agree():
+    """With timing on, the indicator's dispatch-stamped time is positive and
+    fits inside its event-bracketed stage; the three update variants (and the
+    strip walk at another persistent grid size) produce the same bits step
+    after step.  Grids with more strips than workgroups are covered by the
+    full-size parity cases."""
+    import torch
+
+    f = inputs.uniform_field(1002, 9, (64, 64, 64), 0.1, 0.02, dtype=np.float32).ravel()
+    plans = []
+    for variant, per_cu in ((0, 4), (1, 4), (2, 4), (1, 1)):
+        p = S.Plan([ch_desc("f32", 3, 64, 8, 1e-5, timing=True)])
+        p.set_launch(3, variant)
+        p.set_launch(1, per_cu)
+        p.set_field(0, torch.from_numpy(f))
+        plans.append(p)
+    for rep in range(4):
+        for p in plans:
+            p.step(5)
+        ref, kref = plans[0].get_spectrum(0)
+        for j, p in enumerate(plans[1:], 1):
+            a, ka = p.get_spectrum(0)
+            assert_bits_equal(a.cpu().numpy(), ref.cpu().numpy(), f"variant plan {j} after {5 * (rep + 1)} steps")
+            assert_bits_equal(ka, kref, f"variant plan {j} k0")
+            assert np.array_equal(p.active_mask(0), plans[0].active_mask(0))
+            assert np.array_equal(p.worklist(0), plans[0].worklist(0))
+    for p in plans:
+        st = p.stats(0)
+        ik, stage = st["indicator_kernel_ms"], st["stage_ms"][2]
+        print(f"indicator kernel {ik * 1e3:.1f} us, stage {stage * 1e3:.1f} us", flush=True)
+        assert 0.0 < ik <= stage * 1.05 + 1e-3
+        p.destroy()
