@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--tune", action="store_true", help="re-run the launch autotuner first")
     ap.add_argument("--no-equal-error", action="store_true",
                     help="skip the threshold sweep at equal L2 error against the FP64 dense run")
+    ap.add_argument("--cpu-one-core", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -104,6 +105,16 @@ def profiled_traffic(workload: str):
 
 def main():
     args = parse()
+    if args.cpu_one_core:  # child of the CPU-baseline leg: oracle only, no GPU
+        import numpy as np
+
+        from paper_2609_03922_amd import configs, inputs
+        from paper_2609_03922_amd import spdba as S
+
+        cfg = configs.BY_NAME[args.config]
+        descs, sizes = build_descs(cfg, S, inputs)
+        print(json.dumps(oracle_baseline(cfg, descs, sizes, inputs, np, budget=8.0, one_core=False)))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is "
                                    "described in DESIGN.md and not built", "n_gpus": args.gpus}))
@@ -290,9 +301,12 @@ def equal_error(cfg, sizes, K, W, S, inputs, autotune, arch, np, torch,
         init_fields(p, cfg, sizes, inputs, np, torch, ic_dtype=np.float32)
         return p
 
+    cdt = torch.complex128 if cfg["op"] == "nlse" else torch.float64
+    every = max(25, K // 5)  # error-curve checkpoints
+
     def run(dtype, tau, dense):
         p = make(dtype, tau, dense)
-        acts = []
+        acts, curve = [], []
         done = 0
         while done < K:
             n = min(25, K - done)
@@ -300,10 +314,11 @@ def equal_error(cfg, sizes, K, W, S, inputs, autotune, arch, np, torch,
             done += n
             acts.append(sum(p.stats(i)["active_blocks"] for i in range(len(sizes))) /
                         sum(d.n_blocks for d in p.descs))
-        f = [p.get_field(i).to(torch.complex128 if cfg["op"] == "nlse" else torch.float64)
-             for i in range(len(sizes))]
+            if done % every == 0 and done < K:
+                curve.append([p.get_field(i).to(cdt) for i in range(len(sizes))])
+        f = [p.get_field(i).to(cdt) for i in range(len(sizes))]
         p.destroy()
-        return f, acts
+        return f, acts, curve
 
     def timed(tau, dense):
         p = make("f32", tau, dense, graph=True)
@@ -319,12 +334,31 @@ def equal_error(cfg, sizes, K, W, S, inputs, autotune, arch, np, torch,
         p.destroy()
         return sorted(ts)[1]
 
-    truth, _ = run("f64", cfg["tau"], True)
+    truth, _, tcurve = run("f64", cfg["tau"], True)
     centred = cfg["op"] != "nlse"
-    nrm = sum(float(torch.linalg.norm(t - (t.mean() if centred else 0.0))) ** 2 for t in truth) ** 0.5
-    err = lambda fs: sum(float(torch.linalg.norm(f - t)) ** 2 for f, t in zip(fs, truth)) ** 0.5 / nrm
-    fd, _ = run("f32", cfg["tau"], True)
+
+    def err(fs, ts=None):
+        ts = truth if ts is None else ts
+        nrm = sum(float(torch.linalg.norm(t - (t.mean() if centred else 0.0))) ** 2 for t in ts) ** 0.5
+        return sum(float(torch.linalg.norm(f - t)) ** 2 for f, t in zip(fs, ts)) ** 0.5 / nrm
+
+    def extra(fs, curve):
+        """Error over the run (checkpoints, then the end); NLSE also as NMSE
+        in dB and correlation, the paper's back-propagation metrics (S5.3)."""
+        e = {"rel_l2_curve": [float(f"{err(c, tc):.4g}") for c, tc in zip(curve, tcurve)] + [float(f"{err(fs):.4g}")],
+             "curve_steps": [every * (j + 1) for j in range(len(curve))] + [K]}
+        if cfg["op"] == "nlse":
+            num = sum(float(torch.linalg.norm(f - t)) ** 2 for f, t in zip(fs, truth))
+            den = sum(float(torch.linalg.norm(t)) ** 2 for t in truth)
+            dot = sum(complex(torch.sum(torch.conj(t) * f).item()) for f, t in zip(fs, truth))
+            nf = sum(float(torch.linalg.norm(f)) ** 2 for f in fs) ** 0.5
+            e["nmse_db"] = round(10.0 * float(np.log10(num / den)), 3)
+            e["corr"] = round(abs(dot) / (nf * den ** 0.5), 9)
+        return e
+
+    fd, _, dcurve = run("f32", cfg["tau"], True)
     e_d = err(fd)
+    dense_extra = extra(fd, dcurve)
     Td = timed(cfg["tau"], True)
 
     def s_est(alpha):
@@ -335,14 +369,17 @@ def equal_error(cfg, sizes, K, W, S, inputs, autotune, arch, np, torch,
 
     sweep = []
     for tau in taus:
-        f, acts = run("f32", tau, False)
+        f, acts, curve = run("f32", tau, False)
         am = float(np.mean(acts))
-        sweep.append({"tau": tau, "rel_l2": err(f), "active_fraction_last_step": round(acts[-1], 4),
-                      "active_fraction_mean": round(am, 4), "s_estimate": s_est(am)})
+        row = {"tau": tau, "rel_l2": err(f), "active_fraction_last_step": round(acts[-1], 4),
+               "active_fraction_mean": round(am, 4), "s_estimate": s_est(am)}
+        row.update(extra(f, curve))
+        sweep.append(row)
     ok = [r for r in sweep if r["rel_l2"] <= 1.1 * e_d]
     tau_star = max(r["tau"] for r in ok) if ok else None
     res = {"truth": "FP64 dense run on the GPU", "steps": K, "timing": "HIP graph replay, median of 3",
-           "dense_f32_rel_l2": e_d, "sweep": sweep, "tau_star": tau_star, "dense_steps_per_s": K / Td}
+           "dense_f32_rel_l2": e_d, "dense_f32": dense_extra, "sweep": sweep, "tau_star": tau_star,
+           "dense_steps_per_s": K / Td}
     if tau_star is not None:
         Ts = timed(tau_star, False)
         row = [r for r in sweep if r["tau"] == tau_star][0]
@@ -519,7 +556,12 @@ def proposer_bench(args, cfg):
     print(json.dumps(out), flush=True)
 
 
-def oracle_baseline(cfg, descs, sizes, inputs, np):
+def oracle_baseline(cfg, descs, sizes, inputs, np, budget=10.0, one_core=True):
+    """The CPU oracle on the host's cores over a bounded sample of the
+    workload (grown until about `budget` seconds), plus the same on one core
+    in a child process (OMP_NUM_THREADS=1; the child never touches the GPU)."""
+    import subprocess
+
     import oracle as O
 
     d = descs[0]
@@ -542,14 +584,29 @@ def oracle_baseline(cfg, descs, sizes, inputs, np):
         t0 = time.perf_counter()
         st = O.step(inst, st, steps)["state"]
         elapsed = time.perf_counter() - t0
-        if elapsed >= 10.0 or steps >= 64:
+        if elapsed >= budget or steps >= 64:
             break
-        steps *= 4 if elapsed < 2.5 else 2
+        steps *= 4 if elapsed < budget / 4 else 2
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(d.n_modes * steps / elapsed / 1e9, 6), "unit": "Gpts/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{steps} full FP64 steps of instance 0 ({n}^{cfg['ndim']}) of {cfg['name']}, "
-                      f"{elapsed:.1f} s"}
+    out = {"value": round(d.n_modes * steps / elapsed / 1e9, 6), "unit": "Gpts/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{steps} full FP64 steps of instance 0 ({n}^{cfg['ndim']}) of {cfg['name']}, "
+                     f"{elapsed:.1f} s"}
+    if one_core:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        try:
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-one-core", "--config",
+                                cfg["name"]], env=env, capture_output=True, text=True, timeout=180)
+            one = json.loads([l for l in r.stdout.splitlines() if l.startswith("{")][-1])
+            out["value_1core"] = one["value"]
+            out["sample_1core"] = one["sample"]
+        except Exception as e:  # the one-core figure is context only
+            out["value_1core"] = None
+            out["sample_1core"] = f"not measured ({type(e).__name__})"
+        out["host_cpus"] = os.cpu_count()
+        out["cpu_model"] = next((l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo")
+                                 if l.startswith("model name")), None)
+    return out
 
 
 if __name__ == "__main__":
