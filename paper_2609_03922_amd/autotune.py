@@ -24,8 +24,8 @@ CANDIDATES = {
     4: (2, 4, 8),              # strip-walk update: waves per workgroup
 }
 DEFAULTS = {0: 4, 1: 4, 2: 256, 3: 1, 4: 4}
-# stage_ms indices each kernel is judged on; the update modes are compared on
-# compaction + update, since the strip walk folds the threshold pass in
+# stage_ms entries a candidate is timed by: the update variants by compaction
+# plus update, since the strip walk folds the threshold pass into the update
 STAGE_OF = {0: (2,), 1: (3, 4), 2: (4,), 4: (3, 4)}
 
 
