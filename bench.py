@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--config", default="ch3d_256_f32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense comparison run")
-    ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph per step")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager steps instead of HIP-graph replay (the stage breakdown is always eager)")
     ap.add_argument("--tune", action="store_true", help="re-run the launch autotuner first")
     ap.add_argument("--no-equal-error", action="store_true",
                     help="skip the threshold sweep at equal L2 error against the FP64 dense run")
@@ -152,7 +153,7 @@ def main():
         return proposer_bench(args, cfg)
     K = args.steps if args.steps is not None else min(cfg["steps"], 500)
     W = args.warmup
-    descs, sizes = build_descs(cfg, S, inputs, timing=not args.graph, graph=args.graph)
+    descs, sizes = build_descs(cfg, S, inputs)
     total_modes = sum(d.n_modes for d in descs)
 
     from paper_2609_03922_amd import autotune
@@ -168,69 +169,71 @@ def main():
         print("launch tuning (stage ms):", json.dumps(timings), file=sys.stderr, flush=True)
         tuned = {str(k): v for k, v in choice.items()}
 
-    # ---- sp-DBA run (timed) --------------------------------------------
-    plan = S.Plan(descs)
-    entry = autotune.apply_cached(plan, arch)
+    # ---- sp-DBA: timed run (HIP-graph replay of whole steps), then the same
+    # steps eager with per-stage HIP events for the breakdown and the roofline
+    def timed_run(dense_flag, graph):
+        dd, _ = build_descs(cfg, S, inputs, dense=dense_flag, timing=not graph, graph=graph)
+        p = S.Plan(dd)
+        entry = autotune.apply_cached(p, arch)
+        init_fields(p, cfg, sizes, inputs, np, torch)
+        p.step(W)
+        torch.cuda.synchronize()
+        init_fields(p, cfg, sizes, inputs, np, torch)  # timed steps are the workload's steps 0..K-1
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.step(K)
+        torch.cuda.synchronize()
+        return p, time.perf_counter() - t0, entry
+
+    graph = not args.no_graph
+    plan, T, entry = timed_run(False, graph)
     if entry:
         tuned = entry["choice"]
-    init_fields(plan, cfg, sizes, inputs, np, torch)
-    plan.step(W)
-    torch.cuda.synchronize()
-    init_fields(plan, cfg, sizes, inputs, np, torch)  # timed steps are the workload's steps 0..K-1
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.step(K)
-    torch.cuda.synchronize()
-    T = time.perf_counter() - t0
-    s0 = plan.stats(0)  # stage means over the last (up to 64) timed steps
     active = sum(plan.stats(i)["active_blocks"] for i in range(len(descs)))
     nblocks = sum(d.n_blocks for d in descs)
     sp_field = [plan.get_field(i) for i in range(len(descs))]
-    stage_ms = None
-    roof = None
-    if not args.graph:
-        names = ("fft", "nonlinear", "indicator", "compaction", "update", "step")
-        stage_ms = {k: float(v) for k, v in zip(names, s0["stage_ms"])}
-        ib = indicator_bytes(cfg, descs)
-        # the indicator dispatch's own start/stop stamps (HIP events through
-        # the extension launch), so the figure matches a kernel trace
-        ind_s = s0["indicator_kernel_ms"] * 1e-3
-        ach = ib / ind_s / 1e9
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(cfg["name"]),
-                "kernel": "k_indicator",
-                "bytes_per_launch": ib, "avg_launch_us": round(ind_s * 1e6, 2),
-                "copy_achievable_gbs": copy_peak(torch)}
+    T_eager = T
+    if graph:  # the same steps again, eager, with the stage events
+        plan.destroy()
+        plan, T_eager, _ = timed_run(False, False)
+    s0 = plan.stats(0)  # stage means over the last (up to 64) steps of the eager run
+    names = ("fft", "nonlinear", "indicator", "compaction", "update", "step")
+    stage_ms = {k: float(v) for k, v in zip(names, s0["stage_ms"])}
+    ib = indicator_bytes(cfg, descs)
+    # the indicator dispatch's own start/stop stamps (HIP events through the
+    # extension launch), so the figure matches a kernel trace
+    ind_s = s0["indicator_kernel_ms"] * 1e-3
+    ach = ib / ind_s / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(cfg["name"]),
+            "kernel": "k_indicator",
+            "bytes_per_launch": ib, "avg_launch_us": round(ind_s * 1e6, 2),
+            "copy_achievable_gbs": copy_peak(torch)}
     plan.destroy()
 
     # ---- dense (Regular) run on the same input ----------------------------
     dense = None
     if not args.no_dense:
-        ddescs, _ = build_descs(cfg, S, inputs, dense=True, timing=not args.graph, graph=args.graph)
-        dp = S.Plan(ddescs)
-        autotune.apply_cached(dp, arch)
-        init_fields(dp, cfg, sizes, inputs, np, torch)
-        dp.step(W)
-        init_fields(dp, cfg, sizes, inputs, np, torch)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        dp.step(K)
-        torch.cuda.synchronize()
-        TD = time.perf_counter() - t1
-        dst = dp.stats(0)["stage_ms"]
+        dp, TD, _ = timed_run(True, graph)
         num = den = 0.0
-        for i in range(len(ddescs)):
+        for i in range(len(descs)):
             a = sp_field[i].double().cpu()
-            b = dp.get_field(i).double().cpu()
+            bb = dp.get_field(i).double().cpu()
             if cfg["op"] == "ch":
-                a = a - b.mean()
-                b = b - b.mean()
-            num += float(torch.sum(torch.abs(a - b) ** 2))
-            den += float(torch.sum(torch.abs(b) ** 2))
+                a = a - bb.mean()
+                bb = bb - bb.mean()
+            num += float(torch.sum(torch.abs(a - bb) ** 2))
+            den += float(torch.sum(torch.abs(bb) ** 2))
         dense = {"steps_per_s": K / TD, "wall_s": TD, "rel_l2_spdba_vs_dense": (num / max(den, 1e-300)) ** 0.5}
-        if not args.graph:
-            dense["stage_ms"] = {"fft": dst[0], "nonlinear": dst[1], "update": dst[4], "step": dst[5]}
-        dp.destroy()
+        if graph:
+            dp.destroy()
+            dpe, TDe, _ = timed_run(True, False)
+        else:
+            dpe, TDe = dp, TD
+        dst = dpe.stats(0)["stage_ms"]
+        dense["eager_steps_per_s"] = K / TDe
+        dense["stage_ms"] = {"fft": dst[0], "nonlinear": dst[1], "update": dst[4], "step": dst[5]}
+        dpe.destroy()
 
     # ---- equal-L2-error protocol ----------------------------------------------
     eq = None
@@ -259,8 +262,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"], "grid": f"{cfg.get('n', 'batch')}^{cfg['ndim']}",
                    "block": cfg["block"], "tau": cfg["tau"], "instances": len(descs),
-                   "modes": total_modes, "parallelism": "single-gpu", "hip_graph": bool(args.graph)},
+                   "modes": total_modes, "parallelism": "single-gpu", "hip_graph": graph},
         "steps_per_s": round(steps_per_s, 3),
+        "eager_steps_per_s": round(K / T_eager, 3),
         "active_fraction_last_step": round(active / nblocks, 4),
         "launch": tuned,
     }

@@ -533,11 +533,13 @@ __device__ __forceinline__ void indicator_rows(const Ctx &c, const InstDev &I, i
     }
 }
 
-template <typename T, int OP>
+// EB: per-block energies requested (c.e_b set; proposer audits).  Without
+// them the kernel carries neither the accumulation nor its LDS array.
+template <typename T, int OP, bool EB>
 __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
     constexpr int V = CV<T>::V;
     __shared__ double lds_max[16][64];
-    __shared__ double lds_eb[16][64];
+    __shared__ double lds_eb[EB ? 16 : 1][64];
     __shared__ double lds_sum[16];
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     // wave index made scalar: the row loop is then uniform per wave and
@@ -564,7 +566,7 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
     const bool k0_lane = I.k0path && ls == 0 && lane == 0;
 
     double amax = 0.0, esum = 0.0, ebs = 0.0;
-    const bool want_eb = c.e_b != nullptr;
+    constexpr bool want_eb = EB;
     bool bad = false;
     if (chunks > 1)
         indicator_rows<T, OP, true>(c, I, ii, sbz, sby, x_lane, lane_on, k0_lane, w, nw, want_eb, amax, esum,
@@ -1325,9 +1327,15 @@ template <typename T>
 static hipError_t ind_launch(const Ctx &c, int waves, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     dim3 grid((unsigned)c.n_strips), block(64 * waves);
     // with an event pair the dispatch itself stamps its start and end
-    if (c.op == OP_CH) hipExtLaunchKernelGGL((k_indicator<T, OP_CH>), grid, block, 0, s, e0, e1, 0, c);
-    else if (c.op == OP_GS) hipExtLaunchKernelGGL((k_indicator<T, OP_GS>), grid, block, 0, s, e0, e1, 0, c);
-    else hipExtLaunchKernelGGL((k_indicator<T, OP_NLSE>), grid, block, 0, s, e0, e1, 0, c);
+    if (c.e_b) {
+        if (c.op == OP_CH) hipExtLaunchKernelGGL((k_indicator<T, OP_CH, true>), grid, block, 0, s, e0, e1, 0, c);
+        else if (c.op == OP_GS) hipExtLaunchKernelGGL((k_indicator<T, OP_GS, true>), grid, block, 0, s, e0, e1, 0, c);
+        else hipExtLaunchKernelGGL((k_indicator<T, OP_NLSE, true>), grid, block, 0, s, e0, e1, 0, c);
+    } else {
+        if (c.op == OP_CH) hipExtLaunchKernelGGL((k_indicator<T, OP_CH, false>), grid, block, 0, s, e0, e1, 0, c);
+        else if (c.op == OP_GS) hipExtLaunchKernelGGL((k_indicator<T, OP_GS, false>), grid, block, 0, s, e0, e1, 0, c);
+        else hipExtLaunchKernelGGL((k_indicator<T, OP_NLSE, false>), grid, block, 0, s, e0, e1, 0, c);
+    }
     return hipGetLastError();
 }
 hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
