@@ -22,6 +22,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 OP_CH, OP_GS, OP_NLSE = 1, 2, 3
 FLAG_DENSE, FLAG_PIN_K0 = 1, 2
+FLAG_TRANSITION, FLAG_REFRESH, FLAG_DYN_TAU = 4, 8, 16  # consistency control (S1.1, S1.3)
 OK, EINVAL, ENONFINITE = 0, 1, 6
 
 
@@ -40,6 +41,12 @@ class _Inst(ctypes.Structure):
         ("dx", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("p", ctypes.c_double * 8),
+        ("refresh_period", ctypes.c_int32),
+        ("full_steps", ctypes.c_int32),
+        ("interval", ctypes.c_int32),
+        ("full_now", ctypes.c_int32),
+        ("target_ratio", ctypes.c_double),
+        ("deadband", ctypes.c_double),
     ]
 
 
@@ -60,6 +67,13 @@ class Inst:
     dt: float
     p: tuple = ()
     flags: int = FLAG_PIN_K0
+    # consistency control (Supplementary S1.1, S1.3); see spdba_oracle.h
+    refresh_period: int = 0
+    full_steps: int = 0
+    interval: int = 0
+    target_ratio: float = 0.0
+    deadband: float = 0.0
+    full_now: int = 0  # apply(): this update activates every block
 
     @property
     def n_modes(self) -> int:
@@ -84,6 +98,9 @@ class Inst:
         pp = list(self.p) + [0.0] * (8 - len(self.p))
         for i in range(8):
             s.p[i] = float(pp[i])
+        s.refresh_period, s.full_steps = int(self.refresh_period), int(self.full_steps)
+        s.interval, s.full_now = int(self.interval), int(self.full_now)
+        s.target_ratio, s.deadband = float(self.target_ratio), float(self.deadband)
         return s
 
 
@@ -104,6 +121,8 @@ def _load():
         lib.or_apply_f64.argtypes = [P, P, P, P, P, P, P, P, P]
         lib.or_apply_f32.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
         lib.or_step_f64.argtypes = [P, ctypes.c_int64, P, P, P, P, P]
+        lib.or_step_ctl_f64.argtypes = [P, ctypes.c_int64, P, P, P, P, P, P]
+        lib.or_taper.argtypes = [ctypes.c_int64, P]
         lib.or_ch_energy.argtypes = [P, P, P, P]
         _lib = lib
     return _lib
@@ -173,8 +192,11 @@ def apply(inst: Inst, q, rhs=None, *, dtype="f64", k0=None, rhs_k0=None, skip=No
 
 def step(inst: Inst, state, nsteps: int, *, masks=False, diag=False, ab=False):
     """nsteps full FP64 steps.  state: CH c-hat; GS u-hat|v-hat; NLSE E(t).
+    The consistency-control schedule of the instance (refresh, full steps,
+    threshold control) applies.
 
-    Returns dict(state, masks [nsteps, per, nb], diag [nsteps, 4], ab, active_steps).
+    Returns dict(state, masks [nsteps, per, nb], diag [nsteps, 4], ab,
+    active_steps (non-frozen updates per block), tau [nsteps]).
     """
     lib = _load()
     c = inst._c()
@@ -185,9 +207,17 @@ def step(inst: Inst, state, nsteps: int, *, masks=False, diag=False, ab=False):
     dg = np.zeros((nsteps, 4), np.float64) if diag else None
     abv = np.zeros((nsteps, per, nb), np.float64) if ab else None
     act = np.zeros(nb, np.int64)
-    _check(lib.or_step_f64(ctypes.byref(c), int(nsteps), _ptr(st), _ptr(mk), _ptr(dg),
-                           _ptr(abv), _ptr(act)))
-    return dict(state=st, masks=mk, diag=dg, ab=abv, active_steps=act)
+    tau = np.zeros(max(nsteps, 1), np.float64)
+    _check(lib.or_step_ctl_f64(ctypes.byref(c), int(nsteps), _ptr(st), _ptr(mk), _ptr(dg),
+                               _ptr(abv), _ptr(act), _ptr(tau)))
+    return dict(state=st, masks=mk, diag=dg, ab=abv, active_steps=act, tau=tau[:nsteps])
+
+
+def taper(B: int):
+    """The transition taper w(i), i = 0 .. B-1 (Supplementary S1.1)."""
+    w = np.zeros(max(int(B), 1), np.float64)
+    _load().or_taper(int(B), _ptr(w))
+    return w
 
 
 def ch_energy(inst: Inst, chat):

@@ -296,6 +296,103 @@ static inline void nlse_coef(const consts_t *c, int64_t m2, double *hr, double *
 /* squared increment, FP64, no contraction */
 static inline double sq2(double dr, double di) { return dr * dr + di * di; }
 
+/* ------------------------------------------------------------------------ */
+/* consistency control: block states and transition weights (S1.1)          */
+/* ------------------------------------------------------------------------ */
+
+#define OR_PI 3.141592653589793238462643383279
+
+void or_taper(int64_t B, double *w) {
+    if (B <= 1) {
+        w[0] = 1.0;
+        return;
+    }
+    for (int64_t i = 0; i < B; ++i) {
+        double sn, cs;
+        or_sincos((OR_PI * (double)i) / (double)(B - 1), &sn, &cs);
+        w[i] = 0.5 * (1.0 - cs);
+    }
+}
+
+typedef struct {
+    double *w[3]; /* taper per axis, length b[a] */
+} tapers_t;
+
+static void make_tapers(const geom_t *g, tapers_t *t) {
+    for (int a = 0; a < 3; ++a) {
+        t->w[a] = (double *)malloc(sizeof(double) * (size_t)g->b[a]);
+        or_taper(g->b[a], t->w[a]);
+    }
+}
+static void free_tapers(tapers_t *t) {
+    for (int a = 0; a < 3; ++a) free(t->w[a]);
+}
+
+static inline int64_t block_id3(const geom_t *g, const int64_t bc[3]) {
+    return (bc[0] * g->nb3[1] + bc[1]) * g->nb3[2] + bc[2];
+}
+
+/* states from the active decisions: a block that is not active and has an
+ * active face neighbour becomes 2 (transition).  Axes with one block have
+ * no neighbours; the block grid is periodic. */
+static void add_transition(const geom_t *g, uint8_t *mask) {
+    for (int64_t b = 0; b < g->nb; ++b) {
+        if (mask[b] != 0) continue;
+        const int64_t bc[3] = {b / (g->nb3[1] * g->nb3[2]), (b / g->nb3[2]) % g->nb3[1], b % g->nb3[2]};
+        int near = 0;
+        for (int a = 0; a < 3 && !near; ++a) {
+            if (g->nb3[a] < 2) continue;
+            for (int side = -1; side <= 1; side += 2) {
+                int64_t nc[3] = {bc[0], bc[1], bc[2]};
+                nc[a] = (bc[a] + side + g->nb3[a]) % g->nb3[a];
+                if (mask[block_id3(g, nc)] == 1) near = 1;
+            }
+        }
+        if (near) mask[b] = 2;
+    }
+}
+
+/* transition weight of mode (iz, iy, ix) of block b: product over the faces
+ * that border frozen blocks, in the order z low, z high, y low, y high,
+ * x low, x high */
+static double sigma_of(const geom_t *g, const tapers_t *t, const uint8_t *mask, int64_t b, int64_t iz,
+                       int64_t iy, int64_t ix) {
+    const int64_t bc[3] = {b / (g->nb3[1] * g->nb3[2]), (b / g->nb3[2]) % g->nb3[1], b % g->nb3[2]};
+    const int64_t li[3] = {iz % g->b[0], iy % g->b[1], ix % g->b[2]};
+    double s = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        if (g->nb3[a] < 2) continue;
+        int64_t lo[3] = {bc[0], bc[1], bc[2]}, hi[3] = {bc[0], bc[1], bc[2]};
+        lo[a] = (bc[a] - 1 + g->nb3[a]) % g->nb3[a];
+        hi[a] = (bc[a] + 1) % g->nb3[a];
+        if (mask[block_id3(g, lo)] == 0) s = s * t->w[a][li[a]];
+        if (mask[block_id3(g, hi)] == 0) s = s * t->w[a][g->b[a] - 1 - li[a]];
+    }
+    return s;
+}
+
+/* the per-block decision shared by both precisions; returns the number of
+ * non-frozen blocks and lists them ascending in wl */
+static int64_t block_states(const or_inst *d, const geom_t *g, const double *a_b, double thr,
+                            const uint8_t *skip, uint8_t *mask, uint32_t *wl) {
+    const int dense = (d->flags & OR_FLAG_DENSE) != 0;
+    const int pin = (d->flags & OR_FLAG_PIN_K0) != 0;
+    const int full = d->full_now != 0;
+    for (int64_t b = 0; b < g->nb; ++b) {
+        int on;
+        if (dense || full) on = 1;
+        else if (pin && b == 0) on = 1;
+        else if (skip && skip[b]) on = 0;
+        else on = a_b[b] > thr;
+        mask[b] = (uint8_t)on;
+    }
+    if ((d->flags & OR_FLAG_TRANSITION) && !dense && !full) add_transition(g, mask);
+    int64_t cnt = 0;
+    for (int64_t b = 0; b < g->nb; ++b)
+        if (mask[b]) wl[cnt++] = (uint32_t)b;
+    return cnt;
+}
+
 int or_apply_f64(const or_inst *d, double *q, const double *rhs, const uint8_t *skip,
                  double *a_b, double *G, uint8_t *mask, uint32_t *wl, int64_t *count) {
     geom_t g;
@@ -369,29 +466,31 @@ int or_apply_f64(const or_inst *d, double *q, const double *rhs, const uint8_t *
         for (int64_t b = 0; b < g.nb; ++b)
             if (a_b[b] > gmax) gmax = a_b[b];
     double thr = (d->tau * d->tau) * gmax;
-    int64_t cnt = 0;
-    for (int64_t b = 0; b < g.nb; ++b) {
-        int on;
-        if (dense) on = 1;
-        else if (pin && b == 0) on = 1;
-        else if (skip && skip[b]) on = 0;
-        else on = a_b[b] > thr;
-        mask[b] = (uint8_t)on;
-        if (on) wl[cnt++] = (uint32_t)b;
-    }
+    *count = block_states(d, &g, a_b, thr, skip, mask, wl);
     *G = gmax;
-    *count = cnt;
 
-    /* step 5: active blocks take the candidate, frozen blocks keep q */
+    /* step 5: active blocks take the candidate, transition blocks the
+     * weighted increment q + sigma (q' - q), frozen blocks keep q */
+    tapers_t tp;
+    make_tapers(&g, &tp);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
-        if (!mask[block_of(&g, iz, iy, ix)]) continue;
+        const int64_t b = block_of(&g, iz, iy, ix);
+        if (!mask[b]) continue;
+        const double sig = mask[b] == 2 ? sigma_of(&g, &tp, mask, b, iz, iy, ix) : 1.0;
         for (int s = 0; s < g.nspec; ++s) {
-            q[2 * (s * N + i)] = cand[2 * (s * N + i)];
-            q[2 * (s * N + i) + 1] = cand[2 * (s * N + i) + 1];
+            const int64_t j = 2 * (s * N + i);
+            if (mask[b] == 1) {
+                q[j] = cand[j];
+                q[j + 1] = cand[j + 1];
+            } else {
+                q[j] = fma(sig, cand[j] - q[j], q[j]);
+                q[j + 1] = fma(sig, cand[j + 1] - q[j + 1], q[j + 1]);
+            }
         }
     }
+    free_tapers(&tp);
     free(cand);
     free(ak);
     return (bad && !dense) ? OR_ENONFINITE : OR_OK;
@@ -494,36 +593,44 @@ int or_apply_f32(const or_inst *d, float *q, const float *rhs, double *k0,
         for (int64_t b = 0; b < g.nb; ++b)
             if (a_b[b] > gmax) gmax = a_b[b];
     double thr = (d->tau * d->tau) * gmax;
-    int64_t cnt = 0;
-    for (int64_t b = 0; b < g.nb; ++b) {
-        int on;
-        if (dense) on = 1;
-        else if (pin && b == 0) on = 1;
-        else if (skip && skip[b]) on = 0;
-        else on = a_b[b] > thr;
-        mask[b] = (uint8_t)on;
-        if (on) wl[cnt++] = (uint32_t)b;
-    }
+    *count = block_states(d, &g, a_b, thr, skip, mask, wl);
     *G = gmax;
-    *count = cnt;
 
+    /* transition increments in FP32: delta = q' - q, then fma(fl32(sigma), delta, q) */
+    tapers_t tp;
+    make_tapers(&g, &tp);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
-        if (!mask[block_of(&g, iz, iy, ix)]) continue;
+        const int64_t b = block_of(&g, iz, iy, ix);
+        if (!mask[b]) continue;
+        const float sig = mask[b] == 2 ? (float)sigma_of(&g, &tp, mask, b, iz, iy, ix) : 1.0f;
         for (int s = 0; s < g.nspec; ++s) {
-            q[2 * (s * N + i)] = cand[2 * (s * N + i)];
-            q[2 * (s * N + i) + 1] = cand[2 * (s * N + i) + 1];
+            const int64_t j = 2 * (s * N + i);
+            if (mask[b] == 1) {
+                q[j] = cand[j];
+                q[j + 1] = cand[j + 1];
+            } else {
+                const float dr = cand[j] - q[j], di = cand[j + 1] - q[j + 1];
+                q[j] = fmaf(sig, dr, q[j]);
+                q[j + 1] = fmaf(sig, di, q[j + 1]);
+            }
         }
     }
     if (k0path) {
-        if (mask[0])
+        if (mask[0] == 1)
             for (int s = 0; s < g.nspec; ++s) k0[s] = k0c[s];
+        else if (mask[0] == 2) {
+            /* block 0 in transition: the FP64 k = 0 value takes its weighted increment */
+            const double sig0 = sigma_of(&g, &tp, mask, 0, 0, 0, 0);
+            for (int s = 0; s < g.nspec; ++s) k0[s] = fma(sig0, k0c[s] - k0[s], k0[s]);
+        }
         for (int s = 0; s < g.nspec; ++s) {
             q[2 * (s * N)] = 0.0f;
             q[2 * (s * N) + 1] = 0.0f;
         }
     }
+    free_tapers(&tp);
     free(cand);
     free(ak);
     return (bad && !dense) ? OR_ENONFINITE : OR_OK;
@@ -565,9 +672,25 @@ int or_ch_energy(const or_inst *d, const double *chat, double *energy, double *m
 
 int or_step_f64(const or_inst *d, int64_t nsteps, double *state, uint8_t *masks,
                 double *diag, double *ab, int64_t *active_steps) {
+    return or_step_ctl_f64(d, nsteps, state, masks, diag, ab, active_steps, NULL);
+}
+
+int or_step_ctl_f64(const or_inst *d0, int64_t nsteps, double *state, uint8_t *masks,
+                    double *diag, double *ab, int64_t *active_steps, double *tau_trace) {
     geom_t g;
-    int rc = make_geom(d, &g);
+    int rc = make_geom(d0, &g);
     if (rc) return rc;
+    const int refresh = (d0->flags & OR_FLAG_REFRESH) != 0;
+    const int dyn = (d0->flags & OR_FLAG_DYN_TAU) != 0;
+    if (refresh && d0->refresh_period < 1) return OR_EINVAL;
+    if (d0->full_steps < 0) return OR_EINVAL;
+    if (dyn && (d0->interval < 1 || !(d0->target_ratio > 0.0 && d0->target_ratio <= 1.0) ||
+                !(d0->deadband >= 0.0 && d0->deadband < 1.0)))
+        return OR_EINVAL;
+    or_inst dd = *d0; /* per step: the current tau and the full flag */
+    const or_inst *d = &dd;
+    double ctl_sum = 0.0;
+    int64_t ctl_n = 0;
     const int64_t N = g.N, nb = g.nb;
     const int per = (d->op == OR_OP_NLSE) ? 2 : 1;
     double *w = (double *)malloc(sizeof(double) * 2 * (size_t)(N * g.nspec));
@@ -577,9 +700,15 @@ int or_step_f64(const or_inst *d, int64_t nsteps, double *state, uint8_t *masks,
     if (active_steps)
         for (int64_t b = 0; b < nb; ++b) active_steps[b] = 0;
     rc = OR_OK;
+    int64_t nonfrozen = 0; /* non-frozen blocks over the current step's updates */
     for (int64_t st = 0; st < nsteps && rc == OR_OK; ++st) {
         double G;
         int64_t cnt;
+        /* the step schedule (Supplementary S1.3) */
+        const int full = st < d0->full_steps || (refresh && (st + 1) % d0->refresh_period == 0);
+        dd.full_now = full;
+        if (tau_trace) tau_trace[st] = dd.tau;
+        nonfrozen = 0;
         if (d->op == OR_OP_CH) {
             if (diag) {
                 double F, m;
@@ -641,10 +770,11 @@ int or_step_f64(const or_inst *d, int64_t nsteps, double *state, uint8_t *masks,
                 or_fft(state, g.n, -1);
                 rc = or_apply_f64(d, state, NULL, NULL, a_b, &G, mk, wl, &cnt);
                 or_fft(state, g.n, +1);
+                nonfrozen += cnt;
                 if (masks) memcpy(masks + (st * per + half) * nb, mk, (size_t)nb);
                 if (ab) memcpy(ab + (st * per + half) * nb, a_b, sizeof(double) * (size_t)nb);
                 if (active_steps)
-                    for (int64_t b = 0; b < nb; ++b) active_steps[b] += mk[b];
+                    for (int64_t b = 0; b < nb; ++b) active_steps[b] += mk[b] != 0;
                 if (half == 0) {
                     for (int64_t i = 0; i < N; ++i) {
                         double er = state[2 * i], ei = state[2 * i + 1];
@@ -655,12 +785,27 @@ int or_step_f64(const or_inst *d, int64_t nsteps, double *state, uint8_t *masks,
                     }
                 }
             }
-            continue;
         }
+        if (d->op != OR_OP_NLSE) nonfrozen = cnt;
+        /* threshold control on the steps that are not full */
+        if (dyn && !full && rc == OR_OK) {
+            ctl_sum += (double)nonfrozen / (double)(nb * per);
+            if (++ctl_n == d0->interval) {
+                const double rho = (ctl_sum / (double)d0->interval) / d0->target_ratio;
+                const double eta = d0->deadband;
+                if (rho > 2.0) dd.tau = dd.tau * 2.0;
+                else if (rho > 1.0 + eta) dd.tau = dd.tau * (1.0 + eta);
+                else if (rho < 0.5) dd.tau = dd.tau * 0.5;
+                else if (rho < 1.0 - eta) dd.tau = dd.tau * (1.0 - eta);
+                ctl_sum = 0.0;
+                ctl_n = 0;
+            }
+        }
+        if (d->op == OR_OP_NLSE) continue;
         if (masks) memcpy(masks + st * nb, mk, (size_t)nb);
         if (ab) memcpy(ab + st * nb, a_b, sizeof(double) * (size_t)nb);
         if (active_steps)
-            for (int64_t b = 0; b < nb; ++b) active_steps[b] += mk[b];
+            for (int64_t b = 0; b < nb; ++b) active_steps[b] += mk[b] != 0;
     }
     free(w);
     free(a_b);

@@ -24,6 +24,10 @@
 
 #define OR_FLAG_DENSE 1u  /* Regular mode: every block updated, no indicator */
 #define OR_FLAG_PIN_K0 2u /* the block holding k = 0 is always active        */
+/* consistency control (Supplementary S1.1, S1.3) */
+#define OR_FLAG_TRANSITION 4u /* frozen face neighbours of active blocks take a tapered increment */
+#define OR_FLAG_REFRESH 8u    /* every refresh_period-th step activates every block            */
+#define OR_FLAG_DYN_TAU 16u   /* the threshold follows a target ratio of non-frozen blocks      */
 
 /* Errors returned by the oracle (0 = success). */
 #define OR_OK 0
@@ -40,6 +44,13 @@ typedef struct {
     double dx;        /* grid spacing (NLSE: sample spacing)             */
     double dt;        /* time step (NLSE: propagation step h)            */
     double p[8];      /* CH {M, kappa}; GS {Du, Dv, F, k}; NLSE {beta2, gamma, alpha} */
+    /* consistency control */
+    int32_t refresh_period; /* REFRESH: steps n with (n + 1) % refresh_period == 0 are full */
+    int32_t full_steps;     /* steps n < full_steps are full (every block active)             */
+    int32_t interval;       /* DYN_TAU: controlled steps per control interval (>= 1)          */
+    int32_t full_now;       /* apply only: 1 = this update activates every block              */
+    double target_ratio;    /* DYN_TAU: target mean ratio of non-frozen blocks, (0, 1]        */
+    double deadband;        /* DYN_TAU: relative deadband eta, [0, 1)                          */
 } or_inst;
 
 /* n-D complex FFT in place. sign = -1 forward (unnormalised), +1 inverse (1/N). */
@@ -47,6 +58,15 @@ int or_fft(double *a, const int64_t dims[3], int sign);
 
 /* sin and cos of x by Cody-Waite reduction and Taylor polynomials. */
 void or_sincos(double x, double *s, double *c);
+
+/* Block states (values of mask[]): 0 frozen, 1 active, 2 transition.  With
+ * OR_FLAG_TRANSITION a block that is not active but has an active face
+ * neighbour (periodic block grid, axes with more than one block) is a
+ * transition block; it takes q + sigma (q' - q), sigma being the product over
+ * its faces that border frozen blocks of the taper w(i) = (1 - cos(pi i /
+ * (B - 1))) / 2 (w = 1 for B = 1), i the mode's index within the block
+ * counted from that face (Supplementary S1.1).  wl lists the non-frozen
+ * blocks, ascending.  d->full_now = 1 makes every block active. */
 
 /* Kernel-level adaptive (or dense) update of one instance, FP64 arithmetic.
  *   q     : state, nspec x N complex128, updated in place on active blocks
@@ -76,6 +96,20 @@ int or_apply_f32(const or_inst *d, float *q, const float *rhs, double *k0,
  *   active_steps: optional out [nb], number of steps each block was active  */
 int or_step_f64(const or_inst *d, int64_t nsteps, double *state, uint8_t *masks,
                 double *diag, double *ab, int64_t *active_steps);
+
+/* The same with the step schedule of consistency control (Supplementary
+ * S1.3).  Step n (from 0) is full when n < full_steps or, with REFRESH,
+ * (n + 1) % refresh_period == 0.  With DYN_TAU, every step that is not full
+ * contributes r_n = (non-frozen blocks over the step's updates) / (blocks x
+ * updates per step); after `interval` such steps the mean r of the interval,
+ * rho = r / target_ratio, sets tau <- 2 tau (rho > 2), tau (1 + eta) (rho >
+ * 1 + eta), tau / 2 (rho < 1/2), tau (1 - eta) (rho < 1 - eta), else tau.
+ * tau_trace: optional out [nsteps], the tau each step used. */
+int or_step_ctl_f64(const or_inst *d, int64_t nsteps, double *state, uint8_t *masks,
+                    double *diag, double *ab, int64_t *active_steps, double *tau_trace);
+
+/* The taper w(i), i = 0 .. B-1, of block edge B (FP64; Supplementary S1.1). */
+void or_taper(int64_t B, double *w);
 
 /* Free energy and mass of a CH spectrum (FP64). */
 int or_ch_energy(const or_inst *d, const double *chat, double *energy, double *mass);
