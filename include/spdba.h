@@ -84,7 +84,25 @@ enum {
     SPDBA_FLAG_DENSE = 1u << 0,        /* Regular mode (paper mode 0): update every block */
     SPDBA_FLAG_PIN_K0 = 1u << 1,       /* block 0 (k = 0) always active                    */
     SPDBA_FLAG_GRAPH = 1u << 2,        /* spdba_step replays a captured HIP graph          */
-    SPDBA_FLAG_TIMING = 1u << 3        /* record per-stage HIP events (stats.stage_ms)     */
+    SPDBA_FLAG_TIMING = 1u << 3,       /* record per-stage HIP events (stats.stage_ms)     */
+    /* consistency control (Supplementary S1.1, S1.3); the update then walks
+     * the block list (launch variant 3 is ignored) */
+    SPDBA_FLAG_TRANSITION = 1u << 4,   /* non-active face neighbours of active blocks
+                                          (periodic block grid) are transition blocks:
+                                          q + sigma (q' - q), sigma the product of the
+                                          roll-off w(i) = (1 - cos(pi i/(B-1)))/2 over
+                                          the faces that border frozen blocks (w = 1
+                                          for B = 1), i counted from that face; FP32:
+                                          fmaf(fl32(sigma), q' - q, q)                 */
+    SPDBA_FLAG_REFRESH = 1u << 5,      /* steps n with (n + 1) % refresh_period == 0
+                                          update every block                          */
+    SPDBA_FLAG_DYN_THRESHOLD = 1u << 6 /* tau follows target_ratio: after every
+                                          control_interval steps that are not full, the
+                                          mean ratio r of non-frozen blocks (over the
+                                          step's updates) gives rho = r / target_ratio
+                                          and tau <- 2 tau (rho > 2), tau (1 + eta)
+                                          (rho > 1 + eta), tau / 2 (rho < 1/2),
+                                          tau (1 - eta) (rho < 1 - eta), eta = deadband */
 };
 
 typedef struct {
@@ -99,6 +117,17 @@ typedef struct {
     double dx;             /* grid spacing (NLSE: sample spacing)                 */
     double dt;             /* time step (NLSE: propagation step h)                */
     double op_params[8];   /* see the operator list above; unused entries 0       */
+    /* consistency control.  Step n counts the steps of this instance since
+     * its last spdba_set_field / spdba_set_spectrum (which also restore tau):
+     * one spdba_step step, or one spdba_apply call (CH, GS) / two calls (NLSE,
+     * one per linear half step).  Steps n < full_steps update every block
+     * (with or without the flags).  Not with SPDBA_FLAG_DENSE (EUNSUPPORTED). */
+    int32_t refresh_period;   /* SPDBA_FLAG_REFRESH: >= 1                          */
+    int32_t full_steps;       /* >= 0                                              */
+    int32_t control_interval; /* SPDBA_FLAG_DYN_THRESHOLD: >= 1                    */
+    int32_t reserved2;        /* must be 0                                         */
+    double target_ratio;      /* SPDBA_FLAG_DYN_THRESHOLD: in (0, 1]                */
+    double deadband;          /* SPDBA_FLAG_DYN_THRESHOLD: in [0, 1)                */
 } spdba_instance_desc;
 
 typedef struct {
@@ -122,6 +151,10 @@ typedef struct {
                                    step (sum of both half steps for NLSE), from
                                    events recorded at the dispatch's own start and
                                    end (no queue gap); 0 when not available         */
+    int64_t transition_blocks;  /* transition blocks of this instance in the last
+                                   update (active_blocks counts active ones)        */
+    double tau;                 /* threshold in use for the next step              */
+    int64_t control_step;       /* consistency-control step counter                */
 } spdba_stats_t;
 
 typedef struct spdba_plan_s *spdba_plan;
@@ -182,7 +215,7 @@ spdba_status spdba_apply(spdba_plan plan, const void *d_rhs_hat, const double *h
 spdba_status spdba_set_skip(spdba_plan plan, const uint8_t *d_skip);
 
 /* Synchronising read-backs of the last update of instance `inst` (host arrays):
- * the 0/1 mask (n >= blocks), a_b values and G (n >= blocks), and the ordered
+ * the mask (n >= blocks; 0 frozen, 1 active, 2 transition), a_b values and G (n >= blocks), and the ordered
  * active-block worklist as instance-local block ids (n >= blocks).  The update
  * itself needs no order (it walks an unordered append list, or the strips);
  * the first spdba_worklist call after an update builds the ascending list

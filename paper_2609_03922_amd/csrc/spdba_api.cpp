@@ -58,15 +58,18 @@ struct spdba_plan_s {
     std::vector<Group> groups;
     int n_inst = 0, op = 0, nspec = 1, ndim = 1;
     bool dbl = false, dense = false, pin = false, use_graph = false, timing = false;
+    bool ctl = false;    // consistency control: states kernel and control kernel per update
+    bool trans = false;  // transition blocks
     hipStream_t stream = nullptr;
     int64_t total_elems = 0, nb_total = 0, n_strips = 0, n_tiles = 0, n_chunks = 0;
     size_t esize = 8;  // bytes per complex element
     size_t fft_work = 0;
     // buffer layout
-    size_t st_spec = 0, st_k0 = 0, state_bytes = 0;
+    size_t st_spec = 0, st_k0 = 0, st_ctl = 0, state_bytes = 0;
     size_t w_W = 0, w_R = 0, w_fft = 0, w_ab = 0, w_mask = 0, w_wl = 0, w_chunk = 0, w_cnt = 0, w_G = 0,
            w_Glast = 0, w_rk0 = 0, w_nl = 0, w_ind = 0, w_smax = 0, w_dense = 0, w_binst = 0, w_table = 0,
-           w_probe = 0, work_bytes = 0;
+           w_taper = 0, w_probe = 0, work_bytes = 0;
+    int64_t n_taper = 0;  // roll-off values over all instances
     bool bound = false;
     char *d_state = nullptr, *d_work = nullptr;
     Ctx ctx{};
@@ -109,6 +112,11 @@ spdba_status dev_err(hipError_t e) { return e == hipSuccess ? SPDBA_OK : SPDBA_E
         if (_s != SPDBA_OK) return _s;    \
     } while (0)
 
+bool has_control(const spdba_instance_desc &x) {
+    return (x.flags & (SPDBA_FLAG_TRANSITION | SPDBA_FLAG_REFRESH | SPDBA_FLAG_DYN_THRESHOLD)) != 0 ||
+           x.full_steps > 0;
+}
+
 spdba_status validate(const spdba_instance_desc *d, int32_t n, void *) {
     if (!d || n < 1 || n > 65535) return SPDBA_EINVAL;
     for (int i = 0; i < n; ++i) {
@@ -142,8 +150,18 @@ spdba_status validate(const spdba_instance_desc *d, int32_t n, void *) {
         if (x.op < SPDBA_OP_CAHN_HILLIARD || x.op > SPDBA_OP_NLSE) return SPDBA_EUNSUPPORTED;
         if (x.dtype != SPDBA_F32 && x.dtype != SPDBA_F64) return SPDBA_EUNSUPPORTED;
         if (x.flags & ~uint32_t(SPDBA_FLAG_DENSE | SPDBA_FLAG_PIN_K0 | SPDBA_FLAG_GRAPH |
-                                SPDBA_FLAG_TIMING))
+                                SPDBA_FLAG_TIMING | SPDBA_FLAG_TRANSITION | SPDBA_FLAG_REFRESH |
+                                SPDBA_FLAG_DYN_THRESHOLD))
             return SPDBA_EUNSUPPORTED;
+        // consistency control: schedule and controller parameters
+        if (x.reserved2 != 0 || x.full_steps < 0) return SPDBA_EINVAL;
+        if ((x.flags & SPDBA_FLAG_REFRESH) && x.refresh_period < 1) return SPDBA_EINVAL;
+        if ((x.flags & SPDBA_FLAG_DYN_THRESHOLD) &&
+            (x.control_interval < 1 || !(x.target_ratio > 0.0 && x.target_ratio <= 1.0) ||
+             !(x.deadband >= 0.0 && x.deadband < 1.0)))
+            return SPDBA_EINVAL;
+        // Regular mode has no threshold rule to control
+        if ((x.flags & SPDBA_FLAG_DENSE) && (has_control(x))) return SPDBA_EUNSUPPORTED;
         // a lane reads 16 bytes: the x block edge must hold whole lanes
         const int V = x.dtype == SPDBA_F32 ? 2 : 1;
         if (x.block[2] < V) return SPDBA_EUNSUPPORTED;
@@ -224,6 +242,23 @@ spdba_status update_stage(spdba_plan p, int ev_base) {
     }
     TRY_HIP(launch_indicator(p->ctx, d, p->ind_waves, p->stream, k0, k1));
     record(p, ev_base);
+    if (p->ctl) {
+        // consistency control: threshold mask (controlled threshold, full
+        // steps), then block states and the append of every non-frozen block,
+        // the list walk (the strip walk has no neighbour information), and
+        // the end-of-update control kernel
+        TRY_HIP(launch_compact_append(p->ctx, p->stream, true));
+        TRY_HIP(launch_states(p->ctx, p->stream));
+        record(p, ev_base + 1);
+        p->list_stale = true;
+        const int grid = ((p->cu_count * p->upd_per_cu + 7) / 8) * 8;
+        const int multi = (p->upd_mode == 2 && !p->trans && p->max_slots <= 256) ? 1 : 0;
+        TRY_HIP(launch_update(p->ctx, d, grid, multi, p->stream, p->trans));
+        TRY_HIP(launch_control(p->ctx, p->stream));
+        record(p, ev_base + 2);
+        p->last_dense = false;
+        return SPDBA_OK;
+    }
     if (p->upd_mode == 1) {
         // threshold, mask and update in one pass; the ordered list is built
         // from the mask only when it is read back
@@ -353,6 +388,8 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     p->pin = (inst[0].flags & SPDBA_FLAG_PIN_K0) != 0;
     p->use_graph = (inst[0].flags & SPDBA_FLAG_GRAPH) != 0;
     p->timing = (inst[0].flags & SPDBA_FLAG_TIMING) != 0;
+    p->trans = (inst[0].flags & SPDBA_FLAG_TRANSITION) != 0;
+    for (int i = 0; i < n_inst; ++i) p->ctl = p->ctl || has_control(inst[i]);
     p->nspec = p->op == OP_GS ? 2 : 1;
     p->stream = reinterpret_cast<hipStream_t>(stream);
     p->esize = p->dbl ? 16 : 8;
@@ -385,7 +422,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     p->total_elems = acc;
 
     // per-instance table in original order
-    int64_t blk = 0, strip = 0, tile = 0;
+    int64_t blk = 0, strip = 0, tile = 0, taper = 0;
     p->hinst.resize(n_inst);
     for (int i = 0; i < n_inst; ++i) {
         const spdba_instance_desc &x = inst[i];
@@ -443,9 +480,19 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
             I.c1 = std::exp(-(x.op_params[2] * x.dt) * 0.25);
             I.q0 = x.op_params[1] * x.dt;
         }
+        I.tw_off = taper;
+        taper += (int64_t)I.b[0] + I.b[1] + I.b[2];
+        I.full_steps = x.full_steps;
+        I.refresh = (x.flags & SPDBA_FLAG_REFRESH) ? x.refresh_period : 0;
+        I.interval = (x.flags & SPDBA_FLAG_DYN_THRESHOLD) ? x.control_interval : 0;
+        I.per = p->op == OP_NLSE ? 2 : 1;
+        I.tau0 = x.threshold;
+        I.target = x.target_ratio;
+        I.deadband = x.deadband;
         p->hinst[i] = I;
     }
     p->nb_total = blk;
+    p->n_taper = taper;
     p->n_strips = strip;
     p->n_tiles = tile;
     p->n_chunks = (blk + CHUNK_BLOCKS - 1) / CHUNK_BLOCKS;
@@ -493,6 +540,8 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     o = align256(o + (size_t)p->total_elems * p->esize);
     p->st_k0 = o;
     o = align256(o + (size_t)n_inst * 2 * sizeof(double));
+    p->st_ctl = o;
+    o = align256(o + (size_t)n_inst * sizeof(CtlDev));
     p->state_bytes = o;
     o = 0;
     auto take = [&o](size_t bytes) {
@@ -517,6 +566,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     p->w_dense = take((size_t)tile * sizeof(double));
     p->w_binst = take((size_t)blk * sizeof(uint16_t));
     p->w_table = take((size_t)n_inst * sizeof(InstDev));
+    p->w_taper = take((size_t)p->n_taper * sizeof(double));
     p->w_probe = take(8);
     p->work_bytes = o;
     *out = p;
@@ -567,6 +617,9 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     c.blk_inst = reinterpret_cast<const uint16_t *>(p->d_work + p->w_binst);
     c.skip = p->d_skip;
     c.e_b = p->d_eb;
+    c.ctl = reinterpret_cast<CtlDev *>(p->d_state + p->st_ctl);
+    c.taper = reinterpret_cast<const double *>(p->d_work + p->w_taper);
+    c.trans = p->trans ? 1 : 0;
     c.nb_total = p->nb_total;
     c.n_strips = p->n_strips;
     c.n_tiles = p->n_tiles;
@@ -581,6 +634,8 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     TRY_HIP(hipMemsetAsync(c.mask, 0, (size_t)p->nb_total, p->stream));
     TRY_HIP(hipMemsetAsync(c.a_b, 0, (size_t)p->nb_total * sizeof(double), p->stream));
     TRY_HIP(launch_reset(c, p->stream));
+    TRY_HIP(launch_tapers(c, p->stream));
+    TRY_HIP(launch_ctl_reset(c, -1, p->stream));
     if (p->dense) {  // Regular mode: every block active, the list is every block
         std::vector<uint32_t> all((size_t)p->nb_total);
         std::iota(all.begin(), all.end(), 0u);
@@ -618,6 +673,7 @@ spdba_status spdba_set_field(spdba_plan p, int32_t inst, const void *d_real) {
     if (!p->bound) return SPDBA_ESTATE;
     const InstDev &I = p->hinst[inst];
     const int64_t n = I.N * p->nspec;
+    TRY_HIP(launch_ctl_reset(p->ctx, inst, p->stream));
     if (p->op == OP_NLSE) {
         TRY_HIP(launch_scale_copy(p->dbl, d_real, state_ptr(p, I.off), n, (double)I.N, p->stream));
         return SPDBA_OK;
@@ -652,6 +708,7 @@ spdba_status spdba_set_spectrum(spdba_plan p, int32_t inst, const void *d_hat, c
     const InstDev &I = p->hinst[inst];
     const int64_t n = I.N * p->nspec;
     double *k0 = p->ctx.k0 + 2 * inst;
+    TRY_HIP(launch_ctl_reset(p->ctx, inst, p->stream));
     TRY_HIP(launch_copy_spectrum(p->ctx, p->dbl, inst, d_hat, state_ptr(p, I.off), n, I.k0path,
                                  (I.k0path && !h_k0) ? k0 : nullptr, p->stream));
     if (I.k0path && h_k0) {
@@ -841,6 +898,8 @@ spdba_status spdba_stats(spdba_plan p, int32_t inst, spdba_stats_t *out) {
     TRY_HIP(hipMemcpyAsync(&g, p->ctx.G_last + inst, 8, hipMemcpyDeviceToHost, p->stream));
     double k0[2] = {0.0, 0.0};
     TRY_HIP(hipMemcpyAsync(k0, p->ctx.k0 + 2 * inst, 16, hipMemcpyDeviceToHost, p->stream));
+    CtlDev C;
+    TRY_HIP(hipMemcpyAsync(&C, p->ctx.ctl + inst, sizeof(CtlDev), hipMemcpyDeviceToHost, p->stream));
     double slot0[2][2] = {{0, 0}, {0, 0}};
     if (p->dbl && p->op != OP_NLSE)
         for (int s = 0; s < p->nspec; ++s)
@@ -864,9 +923,15 @@ spdba_status spdba_stats(spdba_plan p, int32_t inst, spdba_stats_t *out) {
     TRY_HIP(hipStreamSynchronize(p->stream));
     out->steps = p->steps;
     out->total_blocks = I.nb;
-    int64_t a = 0;
-    for (uint8_t v : mk) a += v;
+    int64_t a = 0, tr = 0;
+    for (uint8_t v : mk) {
+        a += v == 1;
+        tr += v == 2;
+    }
     out->active_blocks = a;
+    out->transition_blocks = tr;
+    out->tau = C.tau;
+    out->control_step = C.step;
     std::memcpy(&out->G, &g, 8);
     for (int s = 0; s < p->nspec; ++s)
         out->mean[s] = p->op == OP_NLSE ? 0.0 : (I.k0path ? k0[s] : slot0[s][0]) * I.invN;

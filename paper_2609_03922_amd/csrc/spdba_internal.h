@@ -41,6 +41,29 @@ struct InstDev {
     double invN;        // 1/N (exact power of two)
     double q0, q1;      // nonlinear parameters: GS F, k; NLSE gamma*h, -
     double dvol;        // dx^d
+    // consistency control (schedule and threshold controller)
+    int64_t tw_off;     // first roll-off value: tables for z, y, x of b[0], b[1], b[2] values
+    int32_t full_steps; // steps 0..full_steps-1 update every block
+    int32_t refresh;    // period of full steps (0: off)
+    int32_t interval;   // controller interval in steps (0: fixed threshold)
+    int32_t per;        // updates per step (NLSE: two half steps)
+    double tau0;        // threshold after a reset
+    double target, deadband;
+};
+
+// Per-instance control state, in the state buffer: it persists across steps
+// (and graph replays) and is reset with the field.
+struct CtlDev {
+    double tau, tau2;   // threshold of the current step and fl(tau*tau)
+    double sum;         // controller: sum of the per-step ratios of the interval
+    int64_t step;       // completed steps since the reset
+    int32_t full;       // the current step updates every block
+    int32_t upd;        // updates done in the current step
+    int32_t n;          // steps accumulated in sum
+    int32_t pad0;
+    uint32_t nf_step;   // non-frozen blocks over the current step's updates
+    uint32_t nf_upd;    // non-frozen blocks of the update in flight
+    uint32_t pad1[2];
 };
 
 // Everything a kernel needs, passed by value.
@@ -71,6 +94,9 @@ struct Ctx {
     const uint16_t *blk_inst;  // [nb_total] owning instance of each block
     const uint8_t *skip;       // [nb_total] or nullptr
     double *e_b;               // [nb_total] per-block energies or nullptr
+    CtlDev *ctl;               // [n_inst] control state
+    const double *taper;       // roll-off tables (InstDev::tw_off)
+    int32_t trans;             // transition blocks on
     int64_t nb_total;
     int64_t n_strips;
     int64_t n_tiles;
@@ -89,8 +115,12 @@ hipError_t launch_k0_rhs(const Ctx &c, hipStream_t s);
 hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s, hipEvent_t e0 = nullptr,
                             hipEvent_t e1 = nullptr);
 hipError_t launch_compact(const Ctx &c, hipStream_t s, int from_mask = 0);
-hipError_t launch_compact_append(const Ctx &c, hipStream_t s);
-hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_t s);
+hipError_t launch_compact_append(const Ctx &c, hipStream_t s, bool ctl = false);
+hipError_t launch_states(const Ctx &c, hipStream_t s);
+hipError_t launch_control(const Ctx &c, hipStream_t s);
+hipError_t launch_ctl_reset(const Ctx &c, int only_inst, hipStream_t s);
+hipError_t launch_tapers(const Ctx &c, hipStream_t s);
+hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_t s, bool tr = false);
 hipError_t launch_update_strip(const Ctx &c, bool dbl, int waves, int grid, hipStream_t s);
 hipError_t launch_dense(const Ctx &c, bool dbl, int threads, hipStream_t s);
 hipError_t launch_reset(const Ctx &c, hipStream_t s);

@@ -632,15 +632,18 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
 // compaction: chunk counts, then ordered write of the active-block list
 // -------------------------------------------------------------------------
 
+// CTL: the threshold and the full-step flag come from the control state
+template <bool CTL>
 __device__ __forceinline__ bool block_active(const Ctx &c, int64_t gb) {
     const int ii = c.blk_inst[gb];
     const InstDev &I = c.inst[ii];
     const int64_t lb = gb - I.blk_off;
     if (c.dense) return true;
+    if (CTL && c.ctl[ii].full) return true;
     if (I.pin && lb == 0) return true;
     if (c.skip && c.skip[gb]) return false;
     const double G = __longlong_as_double((long long)c.G[ii]);
-    const double thr = I.tau2 * G;
+    const double thr = (CTL ? c.ctl[ii].tau2 : I.tau2) * G;
     return c.a_b[gb] > thr;
 }
 
@@ -656,7 +659,7 @@ __global__ void __launch_bounds__(256) k_compact_count(Ctx c, int from_mask) {
             if (from_mask) {
                 on = c.mask[gb] != 0;
             } else {
-                on = block_active(c, gb);
+                on = block_active<false>(c, gb);
                 c.mask[gb] = on ? 1 : 0;
             }
             n += on ? 1u : 0u;
@@ -704,29 +707,13 @@ __global__ void __launch_bounds__(256) k_compact_write(Ctx c) {
     if (chunk == c.n_chunks - 1 && threadIdx.x == 255) *c.count = offset + scan[255];
 }
 
-// One-pass compaction for the update: threshold and mask of a chunk of 1024
-// blocks, then one atomic append of the chunk's active blocks (ascending
-// within the chunk).  The update needs no global order; the ordered list the
-// API returns is rebuilt from the mask when it is read.  The last workgroup to
-// arrive hands G over, as the strip walk does.  The indicator clears the
-// counter.
-__global__ void __launch_bounds__(256) k_compact_append(Ctx c) {
-    __shared__ uint32_t wsum[4];
-    __shared__ uint32_t base;
+// Append the blocks flagged in `bits` (thread t owns blocks b0..b0+3) to the
+// unordered list: exclusive prefix within the wave (shift-up scan), then
+// across the four waves, then one atomic per workgroup.
+__device__ __forceinline__ void append_bits(const Ctx &c, uint32_t bits, int64_t b0, uint32_t *wsum,
+                                            uint32_t &base) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t b0 = (int64_t)blockIdx.x * CHUNK_BLOCKS + 4 * threadIdx.x;
-    uint32_t bits = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int64_t gb = b0 + k;
-        if (gb < c.nb_total) {
-            const bool on = block_active(c, gb);
-            c.mask[gb] = on ? 1 : 0;
-            bits |= (on ? 1u : 0u) << k;
-        }
-    }
     const uint32_t mine = __popc(bits);
-    // exclusive prefix within the wave (shift-up scan), then across waves
     uint32_t incl = mine;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -745,6 +732,31 @@ __global__ void __launch_bounds__(256) k_compact_append(Ctx c) {
 #pragma unroll
     for (int k = 0; k < 4; ++k)
         if (bits & (1u << k)) c.worklist[pos++] = (uint32_t)(b0 + k);
+}
+
+// One-pass compaction for the update: threshold and mask of a chunk of 1024
+// blocks, then one atomic append of the chunk's active blocks (ascending
+// within the chunk).  The update needs no global order; the ordered list the
+// API returns is rebuilt from the mask when it is read.  The last workgroup to
+// arrive hands G over, as the strip walk does.  The indicator clears the
+// counter.  CTL (consistency control): the mask only; k_states appends.
+template <bool CTL>
+__global__ void __launch_bounds__(256) k_compact_append(Ctx c) {
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t base;
+    const int64_t b0 = (int64_t)blockIdx.x * CHUNK_BLOCKS + 4 * threadIdx.x;
+    uint32_t bits = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t gb = b0 + k;
+        if (gb < c.nb_total) {
+            const bool on = block_active<CTL>(c, gb);
+            c.mask[gb] = on ? 1 : 0;
+            bits |= (on ? 1u : 0u) << k;
+        }
+    }
+    if (!CTL) append_bits(c, bits, b0, wsum, base);
+    else __syncthreads();
     // every G read of this workgroup happened before the barriers above
     if (threadIdx.x == 0) {
         const unsigned int done = atomicAdd(c.done, 1u);
@@ -759,12 +771,200 @@ __global__ void __launch_bounds__(256) k_compact_append(Ctx c) {
 }
 
 // -------------------------------------------------------------------------
+// consistency control (Supplementary S1.1, S1.3): transition blocks, the
+// roll-off weights, the step schedule and the threshold controller
+// -------------------------------------------------------------------------
+
+// instance-local block id from block coordinates (power-of-two block grid)
+__device__ __forceinline__ int64_t blk_id(const InstDev &I, int bz, int by, int bx) {
+    return ((((int64_t)bz << I.lnbk[1]) + by) << I.lnbk[2]) + bx;
+}
+
+// Faces of block (bz, by, bx) whose neighbour on the periodic block grid is
+// frozen (mask 0): bit 2a = low face of axis a (z, y, x), bit 2a + 1 = high
+// face.  Axes with one block have no neighbours.
+__device__ __forceinline__ uint32_t frozen_faces(const Ctx &c, const InstDev &I, int bz, int by, int bx) {
+    const uint8_t *m = c.mask + I.blk_off;
+    uint32_t f = 0;
+    if (I.nbk[0] > 1) {
+        const int k = I.nbk[0] - 1;
+        f |= m[blk_id(I, (bz - 1) & k, by, bx)] == 0 ? 1u : 0u;
+        f |= m[blk_id(I, (bz + 1) & k, by, bx)] == 0 ? 2u : 0u;
+    }
+    if (I.nbk[1] > 1) {
+        const int k = I.nbk[1] - 1;
+        f |= m[blk_id(I, bz, (by - 1) & k, bx)] == 0 ? 4u : 0u;
+        f |= m[blk_id(I, bz, (by + 1) & k, bx)] == 0 ? 8u : 0u;
+    }
+    if (I.nbk[2] > 1) {
+        const int k = I.nbk[2] - 1;
+        f |= m[blk_id(I, bz, by, (bx - 1) & k)] == 0 ? 16u : 0u;
+        f |= m[blk_id(I, bz, by, (bx + 1) & k)] == 0 ? 32u : 0u;
+    }
+    return f;
+}
+
+// a non-active block with an active face neighbour
+__device__ __forceinline__ bool near_active(const Ctx &c, const InstDev &I, int64_t lb) {
+    const int bx = (int)(lb & (I.nbk[2] - 1));
+    const int64_t t = lb >> I.lnbk[2];
+    const int by = (int)(t & (I.nbk[1] - 1));
+    const int bz = (int)(t >> I.lnbk[1]);
+    const uint8_t *m = c.mask + I.blk_off;
+    bool nr = false;
+    if (I.nbk[0] > 1) {
+        const int k = I.nbk[0] - 1;
+        nr |= m[blk_id(I, (bz - 1) & k, by, bx)] == 1;
+        nr |= m[blk_id(I, (bz + 1) & k, by, bx)] == 1;
+    }
+    if (I.nbk[1] > 1) {
+        const int k = I.nbk[1] - 1;
+        nr |= m[blk_id(I, bz, (by - 1) & k, bx)] == 1;
+        nr |= m[blk_id(I, bz, (by + 1) & k, bx)] == 1;
+    }
+    if (I.nbk[2] > 1) {
+        const int k = I.nbk[2] - 1;
+        nr |= m[blk_id(I, bz, by, (bx - 1) & k)] == 1;
+        nr |= m[blk_id(I, bz, by, (bx + 1) & k)] == 1;
+    }
+    return nr;
+}
+
+// Weight of the mode at block-local position (lz, ly, lx): the product of the
+// roll-off values of the frozen faces, z low first and x high last (a fixed
+// order, so the rounding is reproducible).  tw: the instance's tables.
+__device__ __forceinline__ double sigma_at(const InstDev &I, const double *tw, uint32_t f, int lz, int ly,
+                                           int lx) {
+    const double *wz = tw, *wy = tw + I.b[0], *wx = tw + I.b[0] + I.b[1];
+    double s = 1.0;
+    if (f & 1u) s = s * wz[lz];
+    if (f & 2u) s = s * wz[I.b[0] - 1 - lz];
+    if (f & 4u) s = s * wy[ly];
+    if (f & 8u) s = s * wy[I.b[1] - 1 - ly];
+    if (f & 16u) s = s * wx[lx];
+    if (f & 32u) s = s * wx[I.b[2] - 1 - lx];
+    return s;
+}
+
+// Block states after the threshold mask: a frozen block next to an active one
+// becomes a transition block (mask 2), then every non-frozen block is
+// appended to the update list and counted per instance for the controller.
+// Marking in place is race-free: only 0 turns into 2, and the neighbour test
+// reads "active" (1) alone.
+__global__ void __launch_bounds__(256) k_states(Ctx c) {
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t base;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t b0 = (int64_t)blockIdx.x * CHUNK_BLOCKS + 4 * threadIdx.x;
+    // the instance of the wave's first block collects the wave's count
+    const int64_t wb = min((int64_t)blockIdx.x * CHUNK_BLOCKS + 256 * w, c.nb_total - 1);
+    const int iw = c.blk_inst[wb];
+    uint32_t bits = 0, own = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t gb = b0 + k;
+        if (gb >= c.nb_total) break;
+        uint8_t st = c.mask[gb];
+        const int ii = c.blk_inst[gb];
+        if (st == 0 && c.trans) {
+            const InstDev &I = c.inst[ii];
+            if (near_active(c, I, gb - I.blk_off)) {
+                st = 2;
+                c.mask[gb] = 2;
+            }
+        }
+        if (st) {
+            bits |= 1u << k;
+            if (ii == iw) ++own;
+            else atomicAdd(&c.ctl[ii].nf_upd, 1u);
+        }
+    }
+    append_bits(c, bits, b0, wsum, base);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) own += __shfl_xor(own, off, 64);
+    if (lane == 0 && own) atomicAdd(&c.ctl[iw].nf_upd, own);
+}
+
+// End of every update: fold the update's count into the step; at the end of
+// a step, the threshold controller (steps that are not full) and the
+// schedule of the next step.  One workgroup.
+__global__ void __launch_bounds__(64) k_control(Ctx c) {
+    for (int i = threadIdx.x; i < c.n_inst; i += blockDim.x) {
+        const InstDev &I = c.inst[i];
+        CtlDev &C = c.ctl[i];
+        C.nf_step += C.nf_upd;
+        C.nf_upd = 0u;
+        if (++C.upd < I.per) continue;
+        C.upd = 0;
+        if (I.interval > 0 && !C.full) {
+            C.sum += (double)C.nf_step / (double)(I.nb * I.per);
+            if (++C.n == I.interval) {
+                const double rho = (C.sum / (double)I.interval) / I.target;
+                const double eta = I.deadband;
+                if (rho > 2.0) C.tau = C.tau * 2.0;
+                else if (rho > 1.0 + eta) C.tau = C.tau * (1.0 + eta);
+                else if (rho < 0.5) C.tau = C.tau * 0.5;
+                else if (rho < 1.0 - eta) C.tau = C.tau * (1.0 - eta);
+                C.sum = 0.0;
+                C.n = 0;
+            }
+        }
+        C.nf_step = 0u;
+        C.step += 1;
+        C.full = (C.step < I.full_steps || (I.refresh > 0 && (C.step + 1) % I.refresh == 0)) ? 1 : 0;
+        C.tau2 = C.tau * C.tau;
+    }
+}
+
+// control state of one instance (only >= 0) or of all after a field load
+__global__ void __launch_bounds__(64) k_ctl_reset(Ctx c, int only) {
+    for (int i = threadIdx.x; i < c.n_inst; i += blockDim.x) {
+        if (only >= 0 && i != only) continue;
+        const InstDev &I = c.inst[i];
+        CtlDev &C = c.ctl[i];
+        C.tau = I.tau0;
+        C.tau2 = I.tau0 * I.tau0;
+        C.sum = 0.0;
+        C.step = 0;
+        C.full = (I.full_steps > 0 || I.refresh == 1) ? 1 : 0;
+        C.upd = 0;
+        C.n = 0;
+        C.pad0 = 0;
+        C.nf_step = 0u;
+        C.nf_upd = 0u;
+        C.pad1[0] = C.pad1[1] = 0u;
+    }
+}
+
+// Roll-off tables w(i) = (1 - cos(pi i / (B - 1))) / 2 of every instance and
+// axis (w = 1 for B = 1), one workgroup per instance.
+__global__ void __launch_bounds__(256) k_tapers(Ctx c, double *tw_all) {
+    const InstDev &I = c.inst[blockIdx.x];
+    double *tw = tw_all + I.tw_off;
+    for (int a = 0, o = 0; a < 3; o += I.b[a], ++a) {
+        const int B = I.b[a];
+        for (int i = threadIdx.x; i < B; i += blockDim.x) {
+            double v = 1.0;
+            if (B > 1) {
+                double sn, cs;
+                sincos_cw((3.141592653589793 * (double)i) / (double)(B - 1), sn, cs);
+                v = 0.5 * (1.0 - cs);
+            }
+            tw[o + i] = v;
+        }
+    }
+}
+
+// -------------------------------------------------------------------------
 // active-block update: persistent workgroups walk the ordered list.  The list
 // is cut into 8 contiguous segments, one per XCD (workgroup id mod 8), so
 // x-adjacent active blocks that share cache lines meet in the same L2.
 // -------------------------------------------------------------------------
 
-template <typename T, int OP>
+// TR: the list may hold transition blocks (mask 2), which take
+// q + sigma (q' - q) with sigma from the roll-off tables; FP32 forms the
+// increment in FP32 and applies fl32(sigma) with one fma.
+template <typename T, int OP, bool TR>
 __device__ __forceinline__ void update_block(const Ctx &c, int64_t gb) {
     constexpr int V = CV<T>::V;
     const int ii = c.blk_inst[gb];
@@ -785,6 +985,9 @@ __device__ __forceinline__ void update_block(const Ctx &c, int64_t gb) {
     T *q1p = q0p + 2 * I.N;
     const T *r1p = r0p + 2 * I.N;
     const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
+    const bool trn = TR && c.mask[gb] == 2;
+    const uint32_t faces = trn ? frozen_faces(c, I, bz, by, bx) : 0u;
+    const double *tw = c.taper + I.tw_off;
     for (int s = threadIdx.x; s < slots; s += blockDim.x) {
         const int r = s >> llpr, l = s & ((1 << llpr) - 1);
         const int z = g.z0 + (r >> g.lb1);
@@ -803,25 +1006,36 @@ __device__ __forceinline__ void update_block(const Ctx &c, int64_t gb) {
         for (int v = 0; v < V; ++v) {
             const double mx = (double)sidx(x0 + v, g.n2);
             const double m2 = __builtin_fma(mx, mx, myz);
-            T cr, ci;
+            T cr, ci, dr = (T)0, di = (T)0;
             if (OP == OP_CH) {
                 T sc, f;
                 ch_coef<T>(K, m2, sc, f);
                 ch_cand<T>(sc, f, qr[v], qi[v], nr[v], ni[v], cr, ci);
             } else if (OP == OP_GS) {
-                T au, av, dr, di;
+                T au, av;
                 gs_coef<T>(K, m2, au, av);
                 gs_cand<T>(dt, au, qr[v], qi[v], nr[v], ni[v], cr, ci);
                 gs_cand<T>(dt, av, q2r[v], q2i[v], n2r[v], n2i[v], dr, di);
-                q2r[v] = dr;
-                q2i[v] = di;
             } else {
                 T hr, hi;
                 nlse_coef<T>(K, m2, hr, hi);
                 nlse_cand<T>(hr, hi, qr[v], qi[v], cr, ci);
             }
+            if (TR && trn) {
+                const T sg = (T)sigma_at(I, tw, faces, r >> g.lb1, r & g.b1m, l * V + v);
+                cr = fmat(sg, cr - qr[v], qr[v]);
+                ci = fmat(sg, ci - qi[v], qi[v]);
+                if (OP == OP_GS) {
+                    dr = fmat(sg, dr - q2r[v], q2r[v]);
+                    di = fmat(sg, di - q2i[v], q2i[v]);
+                }
+            }
             qr[v] = cr;
             qi[v] = ci;
+            if (OP == OP_GS) {
+                q2r[v] = dr;
+                q2i[v] = di;
+            }
         }
         // the FP32 slot of k = 0 stays zero (its value lives in FP64)
         if (k0_blk && s == 0) {
@@ -834,20 +1048,25 @@ __device__ __forceinline__ void update_block(const Ctx &c, int64_t gb) {
     if (k0_blk && threadIdx.x == 0) {
         double tmp[2];
         k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+        if (TR && trn) {  // block 0 in transition: the weighted increment in FP64
+            const double s0 = sigma_at(I, tw, faces, 0, 0, 0);
+            tmp[0] = __builtin_fma(s0, tmp[0] - c.k0[2 * ii], c.k0[2 * ii]);
+            if (OP == OP_GS) tmp[1] = __builtin_fma(s0, tmp[1] - c.k0[2 * ii + 1], c.k0[2 * ii + 1]);
+        }
         c.k0[2 * ii] = tmp[0];
         if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
     }
 }
 
 
-template <typename T, int OP>
+template <typename T, int OP, bool TR>
 __global__ void __launch_bounds__(256) k_update(Ctx c) {
     const uint32_t total = *c.count;
     const int P = gridDim.x;  // multiple of 8
     const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per = P >> 3;
     const uint32_t seg = (total + 7) / 8;
     const uint32_t lo = min(total, seg * xcd), hi = min(total, seg * (xcd + 1));
-    for (uint32_t e = lo + local; e < hi; e += per) update_block<T, OP>(c, c.worklist[e]);
+    for (uint32_t e = lo + local; e < hi; e += per) update_block<T, OP, TR>(c, c.worklist[e]);
 }
 
 // several list entries per workgroup iteration: all their loads are issued
@@ -1342,8 +1561,29 @@ hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s, hi
     return dbl ? ind_launch<double>(c, waves, s, e0, e1) : ind_launch<float>(c, waves, s, e0, e1);
 }
 
-hipError_t launch_compact_append(const Ctx &c, hipStream_t s) {
-    hipLaunchKernelGGL(k_compact_append, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c);
+hipError_t launch_compact_append(const Ctx &c, hipStream_t s, bool ctl) {
+    if (ctl) hipLaunchKernelGGL(k_compact_append<true>, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c);
+    else hipLaunchKernelGGL(k_compact_append<false>, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_states(const Ctx &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_states, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_control(const Ctx &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(64), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_reset(const Ctx &c, int only_inst, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, c, only_inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_tapers(const Ctx &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_tapers, dim3((unsigned)c.n_inst), dim3(256), 0, s, c, const_cast<double *>(c.taper));
     return hipGetLastError();
 }
 
@@ -1356,19 +1596,20 @@ hipError_t launch_compact(const Ctx &c, hipStream_t s, int from_mask) {
 }
 
 template <typename T, int OP>
-static void upd_launch_op(const Ctx &c, int grid, int multi, hipStream_t s) {
-    if (multi) hipLaunchKernelGGL((k_update_multi<T, OP, 4>), dim3(grid), dim3(256), 0, s, c);
-    else hipLaunchKernelGGL((k_update<T, OP>), dim3(grid), dim3(256), 0, s, c);
+static void upd_launch_op(const Ctx &c, int grid, int multi, bool tr, hipStream_t s) {
+    if (multi && !tr) hipLaunchKernelGGL((k_update_multi<T, OP, 4>), dim3(grid), dim3(256), 0, s, c);
+    else if (tr) hipLaunchKernelGGL((k_update<T, OP, true>), dim3(grid), dim3(256), 0, s, c);
+    else hipLaunchKernelGGL((k_update<T, OP, false>), dim3(grid), dim3(256), 0, s, c);
 }
 template <typename T>
-static hipError_t upd_launch(const Ctx &c, int grid, int multi, hipStream_t s) {
-    if (c.op == OP_CH) upd_launch_op<T, OP_CH>(c, grid, multi, s);
-    else if (c.op == OP_GS) upd_launch_op<T, OP_GS>(c, grid, multi, s);
-    else upd_launch_op<T, OP_NLSE>(c, grid, multi, s);
+static hipError_t upd_launch(const Ctx &c, int grid, int multi, bool tr, hipStream_t s) {
+    if (c.op == OP_CH) upd_launch_op<T, OP_CH>(c, grid, multi, tr, s);
+    else if (c.op == OP_GS) upd_launch_op<T, OP_GS>(c, grid, multi, tr, s);
+    else upd_launch_op<T, OP_NLSE>(c, grid, multi, tr, s);
     return hipGetLastError();
 }
-hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_t s) {
-    return dbl ? upd_launch<double>(c, grid, multi, s) : upd_launch<float>(c, grid, multi, s);
+hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_t s, bool tr) {
+    return dbl ? upd_launch<double>(c, grid, multi, tr, s) : upd_launch<float>(c, grid, multi, tr, s);
 }
 
 template <typename T>

@@ -22,6 +22,7 @@ SPDBA_EDEVICE, SPDBA_EFFT, SPDBA_ENONFINITE = 4, 5, 6
 SPDBA_OP_CAHN_HILLIARD, SPDBA_OP_GRAY_SCOTT, SPDBA_OP_NLSE = 1, 2, 3
 SPDBA_F32, SPDBA_F64 = 0, 1
 SPDBA_FLAG_DENSE, SPDBA_FLAG_PIN_K0, SPDBA_FLAG_GRAPH, SPDBA_FLAG_TIMING = 1, 2, 4, 8
+SPDBA_FLAG_TRANSITION, SPDBA_FLAG_REFRESH, SPDBA_FLAG_DYN_THRESHOLD = 16, 32, 64
 
 OPS = {"ch": SPDBA_OP_CAHN_HILLIARD, "gs": SPDBA_OP_GRAY_SCOTT, "nlse": SPDBA_OP_NLSE}
 DTYPES = {"f32": SPDBA_F32, "f64": SPDBA_F64}
@@ -61,6 +62,12 @@ class InstanceDesc(ctypes.Structure):
         ("dx", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("op_params", ctypes.c_double * 8),
+        ("refresh_period", ctypes.c_int32),
+        ("full_steps", ctypes.c_int32),
+        ("control_interval", ctypes.c_int32),
+        ("reserved2", ctypes.c_int32),
+        ("target_ratio", ctypes.c_double),
+        ("deadband", ctypes.c_double),
     ]
 
 
@@ -76,6 +83,9 @@ class Stats(ctypes.Structure):
         ("input_preserving_fft", ctypes.c_int32),
         ("graph_replay", ctypes.c_int32),
         ("indicator_kernel_ms", ctypes.c_double),
+        ("transition_blocks", ctypes.c_int64),
+        ("tau", ctypes.c_double),
+        ("control_step", ctypes.c_int64),
     ]
 
 
@@ -161,6 +171,15 @@ class Desc:
     pin_k0: bool = True
     graph: bool = False
     timing: bool = False
+    # consistency control (Supplementary S1.1, S1.3): transition blocks, a
+    # full step every `refresh` steps (0: off), `full_steps` initial full
+    # steps, and the threshold controller when target_ratio > 0
+    transition: bool = False
+    refresh: int = 0
+    full_steps: int = 0
+    target_ratio: float = 0.0
+    control_interval: int = 0
+    deadband: float = 0.0
 
     @property
     def dims3(self):
@@ -191,13 +210,22 @@ class Desc:
             d.block[a] = self.block3[a]
         d.dtype = DTYPES[self.dtype]
         d.flags = ((SPDBA_FLAG_DENSE if self.dense else 0) | (SPDBA_FLAG_PIN_K0 if self.pin_k0 else 0)
-                   | (SPDBA_FLAG_GRAPH if self.graph else 0) | (SPDBA_FLAG_TIMING if self.timing else 0))
+                   | (SPDBA_FLAG_GRAPH if self.graph else 0) | (SPDBA_FLAG_TIMING if self.timing else 0)
+                   | (SPDBA_FLAG_TRANSITION if self.transition else 0)
+                   | (SPDBA_FLAG_REFRESH if self.refresh else 0)
+                   | (SPDBA_FLAG_DYN_THRESHOLD if self.target_ratio else 0))
         d.reserved = 0
         d.threshold = float(self.tau)
         d.dx, d.dt = float(self.dx), float(self.dt)
         pp = list(self.params) + [0.0] * (8 - len(self.params))
         for i in range(8):
             d.op_params[i] = float(pp[i])
+        d.refresh_period = int(self.refresh)
+        d.full_steps = int(self.full_steps)
+        d.control_interval = int(self.control_interval)
+        d.reserved2 = 0
+        d.target_ratio = float(self.target_ratio)
+        d.deadband = float(self.deadband)
         return d
 
 
@@ -380,7 +408,8 @@ class Plan:
         return dict(steps=s.steps, active_blocks=s.active_blocks, total_blocks=s.total_blocks,
                     G=s.G, mean=list(s.mean), energy=s.energy, stage_ms=list(s.stage_ms),
                     input_preserving_fft=s.input_preserving_fft, graph_replay=s.graph_replay,
-                    indicator_kernel_ms=s.indicator_kernel_ms)
+                    indicator_kernel_ms=s.indicator_kernel_ms, transition_blocks=s.transition_blocks,
+                    tau=s.tau, control_step=s.control_step)
 
     def destroy(self):
         if self.h is not None and self.h.value:

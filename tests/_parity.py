@@ -11,10 +11,14 @@ from paper_2609_03922_amd import spdba as S
 OPMAP = {"ch": O.OP_CH, "gs": O.OP_GS, "nlse": O.OP_NLSE}
 
 
-def oracle_inst(d: S.Desc) -> O.Inst:
-    flags = (O.FLAG_DENSE if d.dense else 0) | (O.FLAG_PIN_K0 if d.pin_k0 else 0)
+def oracle_inst(d: S.Desc, full_now: int = 0) -> O.Inst:
+    flags = ((O.FLAG_DENSE if d.dense else 0) | (O.FLAG_PIN_K0 if d.pin_k0 else 0)
+             | (O.FLAG_TRANSITION if d.transition else 0) | (O.FLAG_REFRESH if d.refresh else 0)
+             | (O.FLAG_DYN_TAU if d.target_ratio else 0))
     return O.Inst(op=OPMAP[d.op], dims=d.dims3, block=d.block3, tau=d.tau, dx=d.dx, dt=d.dt,
-                  p=tuple(d.params), flags=flags)
+                  p=tuple(d.params), flags=flags, refresh_period=d.refresh, full_steps=d.full_steps,
+                  interval=d.control_interval, target_ratio=d.target_ratio, deadband=d.deadband,
+                  full_now=full_now)
 
 
 def k0path(d: S.Desc) -> bool:
@@ -38,8 +42,10 @@ def draw_apply_inputs(d: S.Desc, seed: int, idx: int, width_frac: float = 1 / 12
     return q, r, k0, rk0
 
 
-def oracle_apply(d: S.Desc, q, r, k0, rk0, skip=None):
-    inst = oracle_inst(d)
+def oracle_apply(d: S.Desc, q, r, k0, rk0, skip=None, full_now=0, tau=None):
+    inst = oracle_inst(d, full_now)
+    if tau is not None:
+        inst.tau = tau
     if d.dtype == "f64":
         return O.apply(inst, q, None if d.op == "nlse" else r, skip=skip)
     if d.op == "nlse":

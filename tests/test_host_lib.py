@@ -62,6 +62,24 @@ def _good(**kw):
     (lambda c: setattr(c, "dtype", 7), spdba.SPDBA_EUNSUPPORTED),
     (lambda c: setattr(c, "flags", 1 << 20), spdba.SPDBA_EUNSUPPORTED),
     (lambda c: (c.block.__setitem__(2, 1)), spdba.SPDBA_EUNSUPPORTED),  # FP32 lane needs 2 values
+    # consistency control parameters
+    (lambda c: setattr(c, "reserved2", 3), spdba.SPDBA_EINVAL),
+    (lambda c: setattr(c, "full_steps", -1), spdba.SPDBA_EINVAL),
+    (lambda c: (setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_REFRESH),
+                setattr(c, "refresh_period", 0)), spdba.SPDBA_EINVAL),
+    (lambda c: (setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_DYN_THRESHOLD),
+                setattr(c, "control_interval", 0), setattr(c, "target_ratio", 0.3)), spdba.SPDBA_EINVAL),
+    (lambda c: (setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_DYN_THRESHOLD),
+                setattr(c, "control_interval", 4), setattr(c, "target_ratio", 1.5)), spdba.SPDBA_EINVAL),
+    (lambda c: (setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_DYN_THRESHOLD),
+                setattr(c, "control_interval", 4), setattr(c, "target_ratio", 0.0)), spdba.SPDBA_EINVAL),
+    (lambda c: (setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_DYN_THRESHOLD),
+                setattr(c, "control_interval", 4), setattr(c, "target_ratio", 0.3),
+                setattr(c, "deadband", 1.0)), spdba.SPDBA_EINVAL),
+    (lambda c: setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_DENSE | spdba.SPDBA_FLAG_TRANSITION),
+     spdba.SPDBA_EUNSUPPORTED),
+    (lambda c: (setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_DENSE), setattr(c, "full_steps", 2)),
+     spdba.SPDBA_EUNSUPPORTED),
 ])
 def test_invalid_descriptors_rejected_without_device(mutate, expect):
     c = _good().to_c()
