@@ -87,7 +87,9 @@ enum {
     SPDBA_FLAG_TIMING = 1u << 3,       /* record per-stage HIP events (stats.stage_ms)     */
     /* consistency control (Supplementary S1.1, S1.3); the update then walks
      * the block list (launch variant 3 is ignored) */
-    SPDBA_FLAG_TRANSITION = 1u << 4,   /* non-active face neighbours of active blocks
+    SPDBA_FLAG_TRANSITION = 1u << 4,   /* (EUNSUPPORTED for a block edge above 4096 or
+                                          2^25 or more blocks over the plan)
+                                          non-active face neighbours of active blocks
                                           (periodic block grid) are transition blocks:
                                           q + sigma (q' - q), sigma the product of the
                                           roll-off w(i) = (1 - cos(pi i/(B-1)))/2 over
@@ -155,6 +157,10 @@ typedef struct {
                                    update (active_blocks counts active ones)        */
     double tau;                 /* threshold in use for the next step              */
     int64_t control_step;       /* consistency-control step counter                */
+    double nonfrozen_ratio_mean; /* plans with consistency control: non-frozen
+                                    (active + transition) blocks over all updates
+                                    since the reset / (blocks x updates); NaN
+                                    otherwise                                        */
 } spdba_stats_t;
 
 typedef struct spdba_plan_s *spdba_plan;

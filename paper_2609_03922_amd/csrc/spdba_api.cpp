@@ -24,6 +24,7 @@ using namespace spdba;
 namespace {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr int64_t kMaxSigBytes = 65536;  // LDS of the transition update per workgroup
 
 std::once_flag g_rocfft_once;
 rocfft_status g_rocfft_setup = rocfft_status_success;
@@ -69,7 +70,7 @@ struct spdba_plan_s {
     size_t w_W = 0, w_R = 0, w_fft = 0, w_ab = 0, w_mask = 0, w_wl = 0, w_chunk = 0, w_cnt = 0, w_G = 0,
            w_Glast = 0, w_rk0 = 0, w_nl = 0, w_ind = 0, w_smax = 0, w_dense = 0, w_binst = 0, w_table = 0,
            w_taper = 0, w_probe = 0, work_bytes = 0;
-    int64_t n_taper = 0;  // roll-off values over all instances
+    int64_t n_taper = 0;  // roll-off table length: 2 x the largest block edge
     bool bound = false;
     char *d_state = nullptr, *d_work = nullptr;
     Ctx ctx{};
@@ -162,6 +163,11 @@ spdba_status validate(const spdba_instance_desc *d, int32_t n, void *) {
             return SPDBA_EINVAL;
         // Regular mode has no threshold rule to control
         if ((x.flags & SPDBA_FLAG_DENSE) && (has_control(x))) return SPDBA_EUNSUPPORTED;
+        // the transition update keeps the roll-off tables (2 B doubles for the
+        // largest edge B) in LDS
+        if ((x.flags & SPDBA_FLAG_TRANSITION) &&
+            2 * 8 * (int64_t)std::max({x.block[0], x.block[1], x.block[2]}) > kMaxSigBytes)
+            return SPDBA_EUNSUPPORTED;
         // a lane reads 16 bytes: the x block edge must hold whole lanes
         const int V = x.dtype == SPDBA_F32 ? 2 : 1;
         if (x.block[2] < V) return SPDBA_EUNSUPPORTED;
@@ -243,18 +249,15 @@ spdba_status update_stage(spdba_plan p, int ev_base) {
     TRY_HIP(launch_indicator(p->ctx, d, p->ind_waves, p->stream, k0, k1));
     record(p, ev_base);
     if (p->ctl) {
-        // consistency control: threshold mask (controlled threshold, full
-        // steps), then block states and the append of every non-frozen block,
-        // the list walk (the strip walk has no neighbour information), and
-        // the end-of-update control kernel
-        TRY_HIP(launch_compact_append(p->ctx, p->stream, true));
-        TRY_HIP(launch_states(p->ctx, p->stream));
+        // consistency control: block states (controlled threshold, full
+        // steps, transition blocks) and the append of every non-frozen block,
+        // then the block-list walk (the strip walk has no neighbour
+        // information), which also closes the update's control step
+        TRY_HIP(launch_compact_states(p->ctx, p->stream));
         record(p, ev_base + 1);
         p->list_stale = true;
         const int grid = ((p->cu_count * p->upd_per_cu + 7) / 8) * 8;
-        const int multi = (p->upd_mode == 2 && !p->trans && p->max_slots <= 256) ? 1 : 0;
-        TRY_HIP(launch_update(p->ctx, d, grid, multi, p->stream, p->trans));
-        TRY_HIP(launch_control(p->ctx, p->stream));
+        TRY_HIP(launch_update(p->ctx, d, grid, 0, p->stream, p->trans, true));
         record(p, ev_base + 2);
         p->last_dense = false;
         return SPDBA_OK;
@@ -480,8 +483,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
             I.c1 = std::exp(-(x.op_params[2] * x.dt) * 0.25);
             I.q0 = x.op_params[1] * x.dt;
         }
-        I.tw_off = taper;
-        taper += (int64_t)I.b[0] + I.b[1] + I.b[2];
+        for (int a = 0; a < 3; ++a) taper = std::max<int64_t>(taper, 2 * (int64_t)I.b[a]);
         I.full_steps = x.full_steps;
         I.refresh = (x.flags & SPDBA_FLAG_REFRESH) ? x.refresh_period : 0;
         I.interval = (x.flags & SPDBA_FLAG_DYN_THRESHOLD) ? x.control_interval : 0;
@@ -496,7 +498,9 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     p->n_strips = strip;
     p->n_tiles = tile;
     p->n_chunks = (blk + CHUNK_BLOCKS - 1) / CHUNK_BLOCKS;
-    if (blk > 0xFFFFFFFFll) {
+    // list entries hold a block id (transition plans: 25 bits beside the
+    // face bits)
+    if (blk > 0xFFFFFFFFll || (p->trans && blk > (int64_t)kEntryId)) {
         delete p;
         return SPDBA_EUNSUPPORTED;
     }
@@ -620,6 +624,10 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     c.ctl = reinterpret_cast<CtlDev *>(p->d_state + p->st_ctl);
     c.taper = reinterpret_cast<const double *>(p->d_work + p->w_taper);
     c.trans = p->trans ? 1 : 0;
+    c.sig_bytes = (int32_t)(p->n_taper * sizeof(double));
+    c.taper_bs = 0;
+    for (const InstDev &I : p->hinst)
+        for (int a = 0; a < 3; ++a) c.taper_bs |= 1u << I.lb[a];
     c.nb_total = p->nb_total;
     c.n_strips = p->n_strips;
     c.n_tiles = p->n_tiles;
@@ -932,6 +940,8 @@ spdba_status spdba_stats(spdba_plan p, int32_t inst, spdba_stats_t *out) {
     out->transition_blocks = tr;
     out->tau = C.tau;
     out->control_step = C.step;
+    const int64_t updates = C.step * I.per + C.upd;
+    out->nonfrozen_ratio_mean = (p->ctl && updates > 0) ? (double)C.nf_total / ((double)I.nb * (double)updates) : NAN;
     std::memcpy(&out->G, &g, 8);
     for (int s = 0; s < p->nspec; ++s)
         out->mean[s] = p->op == OP_NLSE ? 0.0 : (I.k0path ? k0[s] : slot0[s][0]) * I.invN;

@@ -42,7 +42,6 @@ struct InstDev {
     double q0, q1;      // nonlinear parameters: GS F, k; NLSE gamma*h, -
     double dvol;        // dx^d
     // consistency control (schedule and threshold controller)
-    int64_t tw_off;     // first roll-off value: tables for z, y, x of b[0], b[1], b[2] values
     int32_t full_steps; // steps 0..full_steps-1 update every block
     int32_t refresh;    // period of full steps (0: off)
     int32_t interval;   // controller interval in steps (0: fixed threshold)
@@ -63,7 +62,7 @@ struct CtlDev {
     int32_t pad0;
     uint32_t nf_step;   // non-frozen blocks over the current step's updates
     uint32_t nf_upd;    // non-frozen blocks of the update in flight
-    uint32_t pad1[2];
+    uint64_t nf_total;  // non-frozen blocks summed over every update since the reset
 };
 
 // Everything a kernel needs, passed by value.
@@ -95,8 +94,10 @@ struct Ctx {
     const uint8_t *skip;       // [nb_total] or nullptr
     double *e_b;               // [nb_total] per-block energies or nullptr
     CtlDev *ctl;               // [n_inst] control state
-    const double *taper;       // roll-off tables (InstDev::tw_off)
+    const double *taper;       // roll-off tables: edge B at [B, 2B)
+    uint32_t taper_bs;         // bit k: block edge 2^k in use
     int32_t trans;             // transition blocks on
+    int32_t sig_bytes;         // LDS of the transition update: the tables, 2 B_max doubles
     int64_t nb_total;
     int64_t n_strips;
     int64_t n_tiles;
@@ -104,6 +105,7 @@ struct Ctx {
 };
 
 constexpr int TILE_THREADS = 256;
+constexpr uint32_t kEntryId = (1u << 25) - 1;  // block-id field of a transition plan's list entry
 constexpr int CHUNK_BLOCKS = 1024;  // compaction chunk
 
 // elementwise tile size in complex elements per dtype (FP32: 4 per thread, FP64: 2)
@@ -115,12 +117,14 @@ hipError_t launch_k0_rhs(const Ctx &c, hipStream_t s);
 hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s, hipEvent_t e0 = nullptr,
                             hipEvent_t e1 = nullptr);
 hipError_t launch_compact(const Ctx &c, hipStream_t s, int from_mask = 0);
-hipError_t launch_compact_append(const Ctx &c, hipStream_t s, bool ctl = false);
-hipError_t launch_states(const Ctx &c, hipStream_t s);
-hipError_t launch_control(const Ctx &c, hipStream_t s);
+hipError_t launch_compact_append(const Ctx &c, hipStream_t s);
+// consistency control: block states and list; reset; roll-off tables
+hipError_t launch_compact_states(const Ctx &c, hipStream_t s);
 hipError_t launch_ctl_reset(const Ctx &c, int only_inst, hipStream_t s);
 hipError_t launch_tapers(const Ctx &c, hipStream_t s);
-hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_t s, bool tr = false);
+// tr: transition weights; ctl: end-of-update control in the last workgroup
+hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_t s, bool tr = false,
+                         bool ctl = false);
 hipError_t launch_update_strip(const Ctx &c, bool dbl, int waves, int grid, hipStream_t s);
 hipError_t launch_dense(const Ctx &c, bool dbl, int threads, hipStream_t s);
 hipError_t launch_reset(const Ctx &c, hipStream_t s);

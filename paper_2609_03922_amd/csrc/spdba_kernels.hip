@@ -632,18 +632,15 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
 // compaction: chunk counts, then ordered write of the active-block list
 // -------------------------------------------------------------------------
 
-// CTL: the threshold and the full-step flag come from the control state
-template <bool CTL>
 __device__ __forceinline__ bool block_active(const Ctx &c, int64_t gb) {
     const int ii = c.blk_inst[gb];
     const InstDev &I = c.inst[ii];
     const int64_t lb = gb - I.blk_off;
     if (c.dense) return true;
-    if (CTL && c.ctl[ii].full) return true;
     if (I.pin && lb == 0) return true;
     if (c.skip && c.skip[gb]) return false;
     const double G = __longlong_as_double((long long)c.G[ii]);
-    const double thr = (CTL ? c.ctl[ii].tau2 : I.tau2) * G;
+    const double thr = I.tau2 * G;
     return c.a_b[gb] > thr;
 }
 
@@ -659,7 +656,7 @@ __global__ void __launch_bounds__(256) k_compact_count(Ctx c, int from_mask) {
             if (from_mask) {
                 on = c.mask[gb] != 0;
             } else {
-                on = block_active<false>(c, gb);
+                on = block_active(c, gb);
                 c.mask[gb] = on ? 1 : 0;
             }
             n += on ? 1u : 0u;
@@ -739,8 +736,7 @@ __device__ __forceinline__ void append_bits(const Ctx &c, uint32_t bits, int64_t
 // within the chunk).  The update needs no global order; the ordered list the
 // API returns is rebuilt from the mask when it is read.  The last workgroup to
 // arrive hands G over, as the strip walk does.  The indicator clears the
-// counter.  CTL (consistency control): the mask only; k_states appends.
-template <bool CTL>
+// counter.
 __global__ void __launch_bounds__(256) k_compact_append(Ctx c) {
     __shared__ uint32_t wsum[4];
     __shared__ uint32_t base;
@@ -750,13 +746,12 @@ __global__ void __launch_bounds__(256) k_compact_append(Ctx c) {
     for (int k = 0; k < 4; ++k) {
         const int64_t gb = b0 + k;
         if (gb < c.nb_total) {
-            const bool on = block_active<CTL>(c, gb);
+            const bool on = block_active(c, gb);
             c.mask[gb] = on ? 1 : 0;
             bits |= (on ? 1u : 0u) << k;
         }
     }
-    if (!CTL) append_bits(c, bits, b0, wsum, base);
-    else __syncthreads();
+    append_bits(c, bits, b0, wsum, base);
     // every G read of this workgroup happened before the barriers above
     if (threadIdx.x == 0) {
         const unsigned int done = atomicAdd(c.done, 1u);
@@ -780,140 +775,174 @@ __device__ __forceinline__ int64_t blk_id(const InstDev &I, int bz, int by, int 
     return ((((int64_t)bz << I.lnbk[1]) + by) << I.lnbk[2]) + bx;
 }
 
-// Faces of block (bz, by, bx) whose neighbour on the periodic block grid is
-// frozen (mask 0): bit 2a = low face of axis a (z, y, x), bit 2a + 1 = high
-// face.  Axes with one block have no neighbours.
-__device__ __forceinline__ uint32_t frozen_faces(const Ctx &c, const InstDev &I, int bz, int by, int bx) {
-    const uint8_t *m = c.mask + I.blk_off;
-    uint32_t f = 0;
-    if (I.nbk[0] > 1) {
-        const int k = I.nbk[0] - 1;
-        f |= m[blk_id(I, (bz - 1) & k, by, bx)] == 0 ? 1u : 0u;
-        f |= m[blk_id(I, (bz + 1) & k, by, bx)] == 0 ? 2u : 0u;
-    }
-    if (I.nbk[1] > 1) {
-        const int k = I.nbk[1] - 1;
-        f |= m[blk_id(I, bz, (by - 1) & k, bx)] == 0 ? 4u : 0u;
-        f |= m[blk_id(I, bz, (by + 1) & k, bx)] == 0 ? 8u : 0u;
-    }
-    if (I.nbk[2] > 1) {
-        const int k = I.nbk[2] - 1;
-        f |= m[blk_id(I, bz, by, (bx - 1) & k)] == 0 ? 16u : 0u;
-        f |= m[blk_id(I, bz, by, (bx + 1) & k)] == 0 ? 32u : 0u;
-    }
-    return f;
+// Threshold rule of a control plan for instance-local block lb: every block
+// in a full step, the pinned k = 0 block, else a_b > fl(tau^2 G) with the
+// controlled threshold (skipped blocks never).
+__device__ __forceinline__ bool active_ctl(const Ctx &c, const InstDev &I, int64_t lb, double thr, bool full) {
+    if (full) return true;
+    if (I.pin && lb == 0) return true;
+    const int64_t gb = I.blk_off + lb;
+    if (c.skip && c.skip[gb]) return false;
+    return c.a_b[gb] > thr;
 }
 
-// a non-active block with an active face neighbour
-__device__ __forceinline__ bool near_active(const Ctx &c, const InstDev &I, int64_t lb) {
+// threshold rule of a neighbour (never in a full step: there no block is
+// left inactive); a_b is loaded unconditionally so that the six neighbour
+// loads issue together
+__device__ __forceinline__ bool nb_on(const Ctx &c, const InstDev &I, int64_t lb, double thr) {
+    const int64_t gb = I.blk_off + lb;
+    bool on = c.a_b[gb] > thr;
+    if (c.skip) on = on && !c.skip[gb];
+    return on || (I.pin && lb == 0);
+}
+
+// a block with an active face neighbour (periodic block grid)
+__device__ __forceinline__ bool near_active(const Ctx &c, const InstDev &I, int64_t lb, double thr) {
     const int bx = (int)(lb & (I.nbk[2] - 1));
     const int64_t t = lb >> I.lnbk[2];
     const int by = (int)(t & (I.nbk[1] - 1));
     const int bz = (int)(t >> I.lnbk[1]);
-    const uint8_t *m = c.mask + I.blk_off;
     bool nr = false;
     if (I.nbk[0] > 1) {
         const int k = I.nbk[0] - 1;
-        nr |= m[blk_id(I, (bz - 1) & k, by, bx)] == 1;
-        nr |= m[blk_id(I, (bz + 1) & k, by, bx)] == 1;
+        nr = nr | nb_on(c, I, blk_id(I, (bz - 1) & k, by, bx), thr);
+        nr = nr | nb_on(c, I, blk_id(I, (bz + 1) & k, by, bx), thr);
     }
     if (I.nbk[1] > 1) {
         const int k = I.nbk[1] - 1;
-        nr |= m[blk_id(I, bz, (by - 1) & k, bx)] == 1;
-        nr |= m[blk_id(I, bz, (by + 1) & k, bx)] == 1;
+        nr = nr | nb_on(c, I, blk_id(I, bz, (by - 1) & k, bx), thr);
+        nr = nr | nb_on(c, I, blk_id(I, bz, (by + 1) & k, bx), thr);
     }
     if (I.nbk[2] > 1) {
         const int k = I.nbk[2] - 1;
-        nr |= m[blk_id(I, bz, by, (bx - 1) & k)] == 1;
-        nr |= m[blk_id(I, bz, by, (bx + 1) & k)] == 1;
+        nr = nr | nb_on(c, I, blk_id(I, bz, by, (bx - 1) & k), thr);
+        nr = nr | nb_on(c, I, blk_id(I, bz, by, (bx + 1) & k), thr);
     }
     return nr;
 }
 
-// Weight of the mode at block-local position (lz, ly, lx): the product of the
-// roll-off values of the frozen faces, z low first and x high last (a fixed
-// order, so the rounding is reproducible).  tw: the instance's tables.
-__device__ __forceinline__ double sigma_at(const InstDev &I, const double *tw, uint32_t f, int lz, int ly,
+// Transition weight of the mode at block-local (lz, ly, lx): the product of
+// the roll-off values over the faces that border frozen blocks, in the fixed
+// order z low, z high, y low, y high, x low, x high; a face without a frozen
+// neighbour contributes an exact factor 1.  w: the roll-off tables (table of
+// edge B at [B, 2B)), b: the block edges.
+__device__ __forceinline__ double sigma_at(const double *w, uint32_t f, int b0, int b1, int b2, int lz, int ly,
                                            int lx) {
-    const double *wz = tw, *wy = tw + I.b[0], *wx = tw + I.b[0] + I.b[1];
-    double s = 1.0;
-    if (f & 1u) s = s * wz[lz];
-    if (f & 2u) s = s * wz[I.b[0] - 1 - lz];
-    if (f & 4u) s = s * wy[ly];
-    if (f & 8u) s = s * wy[I.b[1] - 1 - ly];
-    if (f & 16u) s = s * wx[lx];
-    if (f & 32u) s = s * wx[I.b[2] - 1 - lx];
-    return s;
+    const double zl = (f & 1u) ? w[b0 + lz] : 1.0;
+    const double zh = (f & 2u) ? w[2 * b0 - 1 - lz] : 1.0;
+    const double yl = (f & 4u) ? w[b1 + ly] : 1.0;
+    const double yh = (f & 8u) ? w[2 * b1 - 1 - ly] : 1.0;
+    const double xl = (f & 16u) ? w[b2 + lx] : 1.0;
+    const double xh = (f & 32u) ? w[2 * b2 - 1 - lx] : 1.0;
+    return ((((zl * zh) * yl) * yh) * xl) * xh;
 }
 
-// Block states after the threshold mask: a frozen block next to an active one
-// becomes a transition block (mask 2), then every non-frozen block is
-// appended to the update list and counted per instance for the controller.
-// Marking in place is race-free: only 0 turns into 2, and the neighbour test
-// reads "active" (1) alone.
-__global__ void __launch_bounds__(256) k_states(Ctx c) {
-    __shared__ uint32_t wsum[4];
+// Update-list entry of a control plan with transition blocks: the global
+// block id in the low 25 bits (kEntryId), the frozen-face bits in bits
+// 25..30 (bit 25 + 2a: the low face of axis a = z, y, x borders a frozen
+// block; bit 26 + 2a: the high face) and the transition flag in bit 31.
+
+// Compaction of a control plan, one block per thread: the state of the block
+// (1 active, 2 transition: not active with an active face neighbour, 0
+// frozen) from the threshold rule of the block and of its neighbours (no
+// grid-wide wait for a finished mask); a transition block also gets the
+// frozen-face bits of its update, from the neighbours' own states.  The
+// non-frozen blocks are appended to the update list and counted per instance
+// for the controller (one atomic per workgroup when the chunk lies in one
+// instance).  G is handed over by the update kernel, which reads none of it.
+__global__ void __launch_bounds__(256) k_compact_states(Ctx c) {
+    __shared__ uint32_t wsum[4], wown[4];
     __shared__ uint32_t base;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t b0 = (int64_t)blockIdx.x * CHUNK_BLOCKS + 4 * threadIdx.x;
-    // the instance of the wave's first block collects the wave's count
-    const int64_t wb = min((int64_t)blockIdx.x * CHUNK_BLOCKS + 256 * w, c.nb_total - 1);
-    const int iw = c.blk_inst[wb];
-    uint32_t bits = 0, own = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int64_t gb = b0 + k;
-        if (gb >= c.nb_total) break;
-        uint8_t st = c.mask[gb];
-        const int ii = c.blk_inst[gb];
-        if (st == 0 && c.trans) {
-            const InstDev &I = c.inst[ii];
-            if (near_active(c, I, gb - I.blk_off)) {
-                st = 2;
-                c.mask[gb] = 2;
+    const int64_t gb = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    // the instance of the chunk's first block collects the chunk's count
+    const int64_t g0 = (int64_t)blockIdx.x * 256;
+    const int iw = c.blk_inst[g0];
+    const bool one = c.blk_inst[min(g0 + 255, c.nb_total - 1)] == iw;  // blocks of an instance are contiguous
+    bool on = false;
+    int ii = iw;
+    uint32_t entry = 0;
+    if (gb < c.nb_total) {
+        ii = c.blk_inst[gb];
+        const InstDev &I = c.inst[ii];
+        const CtlDev &C = c.ctl[ii];
+        const double thr = C.tau2 * __longlong_as_double((long long)c.G[ii]);
+        const int64_t lb = gb - I.blk_off;
+        uint8_t st = active_ctl(c, I, lb, thr, C.full != 0) ? 1 : 0;
+        entry = (uint32_t)gb;
+        if (!st && c.trans && near_active(c, I, lb, thr)) {
+            st = 2;
+            // a neighbour is frozen when neither it nor any of its own
+            // neighbours passes the threshold rule
+            const int bx = (int)(lb & (I.nbk[2] - 1));
+            const int64_t t = lb >> I.lnbk[2];
+            const int by = (int)(t & (I.nbk[1] - 1));
+            const int bz = (int)(t >> I.lnbk[1]);
+            uint32_t f = 0;
+            for (int a = 0; a < 3; ++a) {
+                if (I.nbk[a] < 2) continue;
+                const int k = I.nbk[a] - 1;
+                for (int side = 0; side < 2; ++side) {
+                    const int d = side ? 1 : -1;
+                    const int64_t nb = a == 0 ? blk_id(I, (bz + d) & k, by, bx)
+                                     : a == 1 ? blk_id(I, bz, (by + d) & k, bx)
+                                              : blk_id(I, bz, by, (bx + d) & k);
+                    const bool fr = !(nb_on(c, I, nb, thr) | near_active(c, I, nb, thr));
+                    f |= fr ? 1u << (2 * a + side) : 0u;
+                }
             }
+            entry |= (f << 25) | (1u << 31);
         }
-        if (st) {
-            bits |= 1u << k;
-            if (ii == iw) ++own;
-            else atomicAdd(&c.ctl[ii].nf_upd, 1u);
-        }
+        c.mask[gb] = st;
+        on = st != 0;
     }
-    append_bits(c, bits, b0, wsum, base);
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) own += __shfl_xor(own, off, 64);
-    if (lane == 0 && own) atomicAdd(&c.ctl[iw].nf_upd, own);
+    const uint64_t bal = __ballot(on);
+    const uint32_t pre = __popcll(bal & ((1ull << lane) - 1));
+    if (lane == 0) wsum[w] = __popcll(bal);
+    if (!one && on && ii != iw) atomicAdd(&c.ctl[ii].nf_upd, 1u);
+    const uint64_t mine = __ballot(on && ii == iw);  // every lane votes
+    if (lane == 0) wown[w] = (uint32_t)__popcll(mine);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        base = tot ? atomicAdd(c.count, tot) : 0u;
+        const uint32_t own = wown[0] + wown[1] + wown[2] + wown[3];
+        if (own) atomicAdd(&c.ctl[iw].nf_upd, own);
+    }
+    __syncthreads();
+    uint32_t pos = base + pre;
+    for (int i = 0; i < w; ++i) pos += wsum[i];
+    if (on) c.worklist[pos] = entry;
 }
 
-// End of every update: fold the update's count into the step; at the end of
-// a step, the threshold controller (steps that are not full) and the
-// schedule of the next step.  One workgroup.
-__global__ void __launch_bounds__(64) k_control(Ctx c) {
-    for (int i = threadIdx.x; i < c.n_inst; i += blockDim.x) {
-        const InstDev &I = c.inst[i];
-        CtlDev &C = c.ctl[i];
-        C.nf_step += C.nf_upd;
-        C.nf_upd = 0u;
-        if (++C.upd < I.per) continue;
-        C.upd = 0;
-        if (I.interval > 0 && !C.full) {
-            C.sum += (double)C.nf_step / (double)(I.nb * I.per);
-            if (++C.n == I.interval) {
-                const double rho = (C.sum / (double)I.interval) / I.target;
-                const double eta = I.deadband;
-                if (rho > 2.0) C.tau = C.tau * 2.0;
-                else if (rho > 1.0 + eta) C.tau = C.tau * (1.0 + eta);
-                else if (rho < 0.5) C.tau = C.tau * 0.5;
-                else if (rho < 1.0 - eta) C.tau = C.tau * (1.0 - eta);
-                C.sum = 0.0;
-                C.n = 0;
-            }
+// End of an update of instance i: fold the update's count into the step; at
+// the end of a step, the threshold controller (steps that are not full) and
+// the schedule of the next step.
+__device__ __forceinline__ void control_inst(const Ctx &c, int i) {
+    const InstDev &I = c.inst[i];
+    CtlDev &C = c.ctl[i];
+    C.nf_step += C.nf_upd;
+    C.nf_total += C.nf_upd;
+    C.nf_upd = 0u;
+    if (++C.upd < I.per) return;
+    C.upd = 0;
+    if (I.interval > 0 && !C.full) {
+        C.sum += (double)C.nf_step / (double)(I.nb * I.per);
+        if (++C.n == I.interval) {
+            const double rho = (C.sum / (double)I.interval) / I.target;
+            const double eta = I.deadband;
+            if (rho > 2.0) C.tau = C.tau * 2.0;
+            else if (rho > 1.0 + eta) C.tau = C.tau * (1.0 + eta);
+            else if (rho < 0.5) C.tau = C.tau * 0.5;
+            else if (rho < 1.0 - eta) C.tau = C.tau * (1.0 - eta);
+            C.sum = 0.0;
+            C.n = 0;
         }
-        C.nf_step = 0u;
-        C.step += 1;
-        C.full = (C.step < I.full_steps || (I.refresh > 0 && (C.step + 1) % I.refresh == 0)) ? 1 : 0;
-        C.tau2 = C.tau * C.tau;
     }
+    C.nf_step = 0u;
+    C.step += 1;
+    C.full = (C.step < I.full_steps || (I.refresh > 0 && (C.step + 1) % I.refresh == 0)) ? 1 : 0;
+    C.tau2 = C.tau * C.tau;
 }
 
 // control state of one instance (only >= 0) or of all after a field load
@@ -932,26 +961,23 @@ __global__ void __launch_bounds__(64) k_ctl_reset(Ctx c, int only) {
         C.pad0 = 0;
         C.nf_step = 0u;
         C.nf_upd = 0u;
-        C.pad1[0] = C.pad1[1] = 0u;
+        C.nf_total = 0ull;
     }
 }
 
-// Roll-off tables w(i) = (1 - cos(pi i / (B - 1))) / 2 of every instance and
-// axis (w = 1 for B = 1), one workgroup per instance.
-__global__ void __launch_bounds__(256) k_tapers(Ctx c, double *tw_all) {
-    const InstDev &I = c.inst[blockIdx.x];
-    double *tw = tw_all + I.tw_off;
-    for (int a = 0, o = 0; a < 3; o += I.b[a], ++a) {
-        const int B = I.b[a];
-        for (int i = threadIdx.x; i < B; i += blockDim.x) {
-            double v = 1.0;
-            if (B > 1) {
-                double sn, cs;
-                sincos_cw((3.141592653589793 * (double)i) / (double)(B - 1), sn, cs);
-                v = 0.5 * (1.0 - cs);
-            }
-            tw[o + i] = v;
+// Roll-off tables w(i) = (1 - cos(pi i / (B - 1))) / 2 (w = 1 for B = 1) of
+// every block edge B = 2^blockIdx.x in use, stored at [B, 2B).
+__global__ void __launch_bounds__(256) k_tapers(Ctx c, double *w) {
+    if (!((c.taper_bs >> blockIdx.x) & 1u)) return;
+    const int B = 1 << blockIdx.x;
+    for (int i = threadIdx.x; i < B; i += blockDim.x) {
+        double v = 1.0;
+        if (B > 1) {
+            double sn, cs;
+            sincos_cw((3.141592653589793 * (double)i) / (double)(B - 1), sn, cs);
+            v = 0.5 * (1.0 - cs);
         }
+        w[B + i] = v;
     }
 }
 
@@ -965,7 +991,9 @@ __global__ void __launch_bounds__(256) k_tapers(Ctx c, double *tw_all) {
 // q + sigma (q' - q) with sigma from the roll-off tables; FP32 forms the
 // increment in FP32 and applies fl32(sigma) with one fma.
 template <typename T, int OP, bool TR>
-__device__ __forceinline__ void update_block(const Ctx &c, int64_t gb) {
+__device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, double *sig) {
+    // TR: entries carry the transition flag and the frozen-face bits
+    const int64_t gb = TR ? (int64_t)(entry & kEntryId) : (int64_t)entry;
     constexpr int V = CV<T>::V;
     const int ii = c.blk_inst[gb];
     const InstDev &I = c.inst[ii];
@@ -985,9 +1013,9 @@ __device__ __forceinline__ void update_block(const Ctx &c, int64_t gb) {
     T *q1p = q0p + 2 * I.N;
     const T *r1p = r0p + 2 * I.N;
     const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
-    const bool trn = TR && c.mask[gb] == 2;
-    const uint32_t faces = trn ? frozen_faces(c, I, bz, by, bx) : 0u;
-    const double *tw = c.taper + I.tw_off;
+    const bool trn = TR && (entry >> 31);  // workgroup-uniform
+    const uint32_t faces = (entry >> 25) & 63u;
+    const int b0 = I.b[0], b1 = I.b[1], b2 = I.b[2];
     for (int s = threadIdx.x; s < slots; s += blockDim.x) {
         const int r = s >> llpr, l = s & ((1 << llpr) - 1);
         const int z = g.z0 + (r >> g.lb1);
@@ -1022,7 +1050,7 @@ __device__ __forceinline__ void update_block(const Ctx &c, int64_t gb) {
                 nlse_cand<T>(hr, hi, qr[v], qi[v], cr, ci);
             }
             if (TR && trn) {
-                const T sg = (T)sigma_at(I, tw, faces, r >> g.lb1, r & g.b1m, l * V + v);
+                const T sg = (T)sigma_at(sig, faces, b0, b1, b2, r >> g.lb1, r & g.b1m, l * V + v);
                 cr = fmat(sg, cr - qr[v], qr[v]);
                 ci = fmat(sg, ci - qi[v], qi[v]);
                 if (OP == OP_GS) {
@@ -1049,7 +1077,7 @@ __device__ __forceinline__ void update_block(const Ctx &c, int64_t gb) {
         double tmp[2];
         k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
         if (TR && trn) {  // block 0 in transition: the weighted increment in FP64
-            const double s0 = sigma_at(I, tw, faces, 0, 0, 0);
+            const double s0 = sigma_at(sig, faces, b0, b1, b2, 0, 0, 0);
             tmp[0] = __builtin_fma(s0, tmp[0] - c.k0[2 * ii], c.k0[2 * ii]);
             if (OP == OP_GS) tmp[1] = __builtin_fma(s0, tmp[1] - c.k0[2 * ii + 1], c.k0[2 * ii + 1]);
         }
@@ -1059,14 +1087,34 @@ __device__ __forceinline__ void update_block(const Ctx &c, int64_t gb) {
 }
 
 
-template <typename T, int OP, bool TR>
+// CTL: workgroup 0 first closes the update's control step for every
+// instance (one wave) and hands G over (G_last, then zero for the next
+// indicator).  Nothing in this kernel reads the control state or G, and the
+// counts it folds were completed by the compaction kernel, so no other
+// workgroup waits for it.  TR: the roll-off tables of the plan's block
+// edges are copied into dynamic LDS once per workgroup.
+template <typename T, int OP, bool TR, bool CTL>
 __global__ void __launch_bounds__(256) k_update(Ctx c) {
+    extern __shared__ double sig[];
+    if (CTL && blockIdx.x == 0 && threadIdx.x < 64)
+        for (int i = threadIdx.x; i < c.n_inst; i += 64) {
+            control_inst(c, i);
+            c.G_last[i] = c.G[i];
+            c.G[i] = 0ull;
+        }
+    if (TR) {
+        for (uint32_t bs = c.taper_bs; bs; bs &= bs - 1) {
+            const int B = 1 << __builtin_ctz(bs);
+            for (int i = threadIdx.x; i < B; i += blockDim.x) sig[B + i] = c.taper[B + i];
+        }
+        __syncthreads();
+    }
     const uint32_t total = *c.count;
     const int P = gridDim.x;  // multiple of 8
     const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per = P >> 3;
     const uint32_t seg = (total + 7) / 8;
     const uint32_t lo = min(total, seg * xcd), hi = min(total, seg * (xcd + 1));
-    for (uint32_t e = lo + local; e < hi; e += per) update_block<T, OP, TR>(c, c.worklist[e]);
+    for (uint32_t e = lo + local; e < hi; e += per) update_block<T, OP, TR>(c, c.worklist[e], sig);
 }
 
 // several list entries per workgroup iteration: all their loads are issued
@@ -1561,19 +1609,13 @@ hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s, hi
     return dbl ? ind_launch<double>(c, waves, s, e0, e1) : ind_launch<float>(c, waves, s, e0, e1);
 }
 
-hipError_t launch_compact_append(const Ctx &c, hipStream_t s, bool ctl) {
-    if (ctl) hipLaunchKernelGGL(k_compact_append<true>, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c);
-    else hipLaunchKernelGGL(k_compact_append<false>, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c);
+hipError_t launch_compact_append(const Ctx &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_compact_append, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c);
     return hipGetLastError();
 }
 
-hipError_t launch_states(const Ctx &c, hipStream_t s) {
-    hipLaunchKernelGGL(k_states, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c);
-    return hipGetLastError();
-}
-
-hipError_t launch_control(const Ctx &c, hipStream_t s) {
-    hipLaunchKernelGGL(k_control, dim3(1), dim3(64), 0, s, c);
+hipError_t launch_compact_states(const Ctx &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_compact_states, dim3((unsigned)((c.nb_total + 255) / 256)), dim3(256), 0, s, c);
     return hipGetLastError();
 }
 
@@ -1583,7 +1625,7 @@ hipError_t launch_ctl_reset(const Ctx &c, int only_inst, hipStream_t s) {
 }
 
 hipError_t launch_tapers(const Ctx &c, hipStream_t s) {
-    hipLaunchKernelGGL(k_tapers, dim3((unsigned)c.n_inst), dim3(256), 0, s, c, const_cast<double *>(c.taper));
+    hipLaunchKernelGGL(k_tapers, dim3(32), dim3(256), 0, s, c, const_cast<double *>(c.taper));
     return hipGetLastError();
 }
 
@@ -1596,20 +1638,22 @@ hipError_t launch_compact(const Ctx &c, hipStream_t s, int from_mask) {
 }
 
 template <typename T, int OP>
-static void upd_launch_op(const Ctx &c, int grid, int multi, bool tr, hipStream_t s) {
-    if (multi && !tr) hipLaunchKernelGGL((k_update_multi<T, OP, 4>), dim3(grid), dim3(256), 0, s, c);
-    else if (tr) hipLaunchKernelGGL((k_update<T, OP, true>), dim3(grid), dim3(256), 0, s, c);
-    else hipLaunchKernelGGL((k_update<T, OP, false>), dim3(grid), dim3(256), 0, s, c);
+static void upd_launch_op(const Ctx &c, int grid, int multi, bool tr, bool ctl, hipStream_t s) {
+    if (ctl && tr)
+        hipLaunchKernelGGL((k_update<T, OP, true, true>), dim3(grid), dim3(256), (size_t)c.sig_bytes, s, c);
+    else if (ctl) hipLaunchKernelGGL((k_update<T, OP, false, true>), dim3(grid), dim3(256), 0, s, c);
+    else if (multi) hipLaunchKernelGGL((k_update_multi<T, OP, 4>), dim3(grid), dim3(256), 0, s, c);
+    else hipLaunchKernelGGL((k_update<T, OP, false, false>), dim3(grid), dim3(256), 0, s, c);
 }
 template <typename T>
-static hipError_t upd_launch(const Ctx &c, int grid, int multi, bool tr, hipStream_t s) {
-    if (c.op == OP_CH) upd_launch_op<T, OP_CH>(c, grid, multi, tr, s);
-    else if (c.op == OP_GS) upd_launch_op<T, OP_GS>(c, grid, multi, tr, s);
-    else upd_launch_op<T, OP_NLSE>(c, grid, multi, tr, s);
+static hipError_t upd_launch(const Ctx &c, int grid, int multi, bool tr, bool ctl, hipStream_t s) {
+    if (c.op == OP_CH) upd_launch_op<T, OP_CH>(c, grid, multi, tr, ctl, s);
+    else if (c.op == OP_GS) upd_launch_op<T, OP_GS>(c, grid, multi, tr, ctl, s);
+    else upd_launch_op<T, OP_NLSE>(c, grid, multi, tr, ctl, s);
     return hipGetLastError();
 }
-hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_t s, bool tr) {
-    return dbl ? upd_launch<double>(c, grid, multi, tr, s) : upd_launch<float>(c, grid, multi, tr, s);
+hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_t s, bool tr, bool ctl) {
+    return dbl ? upd_launch<double>(c, grid, multi, tr, ctl, s) : upd_launch<float>(c, grid, multi, tr, ctl, s);
 }
 
 template <typename T>

@@ -86,6 +86,7 @@ class Stats(ctypes.Structure):
         ("transition_blocks", ctypes.c_int64),
         ("tau", ctypes.c_double),
         ("control_step", ctypes.c_int64),
+        ("nonfrozen_ratio_mean", ctypes.c_double),
     ]
 
 
@@ -409,7 +410,7 @@ class Plan:
                     G=s.G, mean=list(s.mean), energy=s.energy, stage_ms=list(s.stage_ms),
                     input_preserving_fft=s.input_preserving_fft, graph_replay=s.graph_replay,
                     indicator_kernel_ms=s.indicator_kernel_ms, transition_blocks=s.transition_blocks,
-                    tau=s.tau, control_step=s.control_step)
+                    tau=s.tau, control_step=s.control_step, nonfrozen_ratio_mean=s.nonfrozen_ratio_mean)
 
     def destroy(self):
         if self.h is not None and self.h.value:

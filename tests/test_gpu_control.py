@@ -193,6 +193,8 @@ def check_trajectory(d, field0, steps, oracle_state0):
         seen |= set(np.unique(m).tolist())
         s = plan.stats(0)
         assert s["control_step"] == st + 1
+        nf = int((ref["masks"][: st + 1] != 0).sum())
+        assert s["nonfrozen_ratio_mean"] == nf / (d.n_blocks * per * (st + 1))
         if st + 1 < steps:
             assert s["tau"] == ref["tau"][st + 1], (st, s["tau"], ref["tau"][st + 1])
     taus = ref["tau"]

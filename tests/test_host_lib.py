@@ -80,6 +80,11 @@ def _good(**kw):
      spdba.SPDBA_EUNSUPPORTED),
     (lambda c: (setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_DENSE), setattr(c, "full_steps", 2)),
      spdba.SPDBA_EUNSUPPORTED),
+    # the transition factors of a block must fit the LDS budget (here 1-D blocks of 8192)
+    (lambda c: (setattr(c, "ndim", 1), [c.dims.__setitem__(a, 1) for a in (0, 1)],
+                [c.block.__setitem__(a, 1) for a in (0, 1)], c.dims.__setitem__(2, 65536),
+                c.block.__setitem__(2, 8192), setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_TRANSITION)),
+     spdba.SPDBA_EUNSUPPORTED),
 ])
 def test_invalid_descriptors_rejected_without_device(mutate, expect):
     c = _good().to_c()
