@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--tune", action="store_true", help="re-run the launch autotuner first")
     ap.add_argument("--no-equal-error", action="store_true",
                     help="skip the threshold sweep at equal L2 error against the FP64 dense run")
+    ap.add_argument("--control", action="store_true",
+                    help="time the sp-DBA steps with consistency control (transition blocks and the "
+                         "threshold controller, target non-frozen ratio 0.2)")
     ap.add_argument("--cpu-one-core", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
@@ -171,8 +174,14 @@ def main():
 
     # ---- sp-DBA: timed run (HIP-graph replay of whole steps), then the same
     # steps eager with per-stage HIP events for the breakdown and the roofline
+    # consistency control (Supplementary S1.1, S1.3): the controller setting
+    # of the control sweep, with an initial full-activation window of K/10 steps
+    ctl = (dict(transition=True, target_ratio=0.2, control_interval=10, deadband=0.05,
+                full_steps=max(1, K // 10)) if args.control else {})
+
     def timed_run(dense_flag, graph):
-        dd, _ = build_descs(cfg, S, inputs, dense=dense_flag, timing=not graph, graph=graph)
+        dd, _ = build_descs(cfg, S, inputs, dense=dense_flag, timing=not graph, graph=graph,
+                            **({} if dense_flag else ctl))
         p = S.Plan(dd)
         entry = autotune.apply_cached(p, arch)
         init_fields(p, cfg, sizes, inputs, np, torch)
@@ -190,6 +199,14 @@ def main():
     if entry:
         tuned = entry["choice"]
     active = sum(plan.stats(i)["active_blocks"] for i in range(len(descs)))
+    ctl_stats = None
+    if ctl:
+        sts = [plan.stats(i) for i in range(len(descs))]
+        w = [d.n_blocks for d in descs]
+        ctl_stats = {"nonfrozen_fraction_mean": round(sum(st["nonfrozen_ratio_mean"] * b for st, b in zip(sts, w))
+                                                      / sum(w), 4),
+                     "transition_fraction_last_step": round(sum(st["transition_blocks"] for st in sts) / sum(w), 4),
+                     "tau_final": sts[0]["tau"]}
     nblocks = sum(d.n_blocks for d in descs)
     sp_field = [plan.get_field(i) for i in range(len(descs))]
     T_eager = T
@@ -268,6 +285,9 @@ def main():
         "active_fraction_last_step": round(active / nblocks, 4),
         "launch": tuned,
     }
+    if ctl:
+        out["config"]["control"] = ctl
+        out["control"] = ctl_stats
     if stage_ms is not None:
         upd_stage_ms = stage_ms["indicator"] + stage_ms["compaction"] + stage_ms["update"]
         out["stage_ms"] = {k: round(v, 4) for k, v in stage_ms.items()}
