@@ -69,8 +69,9 @@ struct spdba_plan_s {
     size_t st_spec = 0, st_k0 = 0, st_ctl = 0, state_bytes = 0;
     size_t w_W = 0, w_R = 0, w_fft = 0, w_ab = 0, w_mask = 0, w_wl = 0, w_chunk = 0, w_cnt = 0, w_G = 0,
            w_Glast = 0, w_rk0 = 0, w_nl = 0, w_ind = 0, w_smax = 0, w_dense = 0, w_binst = 0, w_table = 0,
-           w_taper = 0, w_probe = 0, work_bytes = 0;
+           w_taper = 0, w_htab = 0, w_probe = 0, work_bytes = 0;
     int64_t n_taper = 0;  // roll-off table length: 2 x the largest block edge
+    int64_t n_htab = 0;   // NLSE H(|m|) table entries over all instances
     bool bound = false;
     char *d_state = nullptr, *d_work = nullptr;
     Ctx ctx{};
@@ -425,7 +426,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     p->total_elems = acc;
 
     // per-instance table in original order
-    int64_t blk = 0, strip = 0, tile = 0, taper = 0;
+    int64_t blk = 0, strip = 0, tile = 0, taper = 0, htab = 0;
     p->hinst.resize(n_inst);
     for (int i = 0; i < n_inst; ++i) {
         const spdba_instance_desc &x = inst[i];
@@ -489,12 +490,18 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
         I.interval = (x.flags & SPDBA_FLAG_DYN_THRESHOLD) ? x.control_interval : 0;
         I.per = p->op == OP_NLSE ? 2 : 1;
         I.tau0 = x.threshold;
+        I.ht_off = -1;
+        if (p->op == OP_NLSE && x.ndim == 1) {  // H depends on |m| only: one table entry per |m|
+            I.ht_off = htab;
+            htab += x.dims[2] / 2 + 1;
+        }
         I.target = x.target_ratio;
         I.deadband = x.deadband;
         p->hinst[i] = I;
     }
     p->nb_total = blk;
     p->n_taper = taper;
+    p->n_htab = htab;
     p->n_strips = strip;
     p->n_tiles = tile;
     p->n_chunks = (blk + CHUNK_BLOCKS - 1) / CHUNK_BLOCKS;
@@ -571,6 +578,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     p->w_binst = take((size_t)blk * sizeof(uint16_t));
     p->w_table = take((size_t)n_inst * sizeof(InstDev));
     p->w_taper = take((size_t)p->n_taper * sizeof(double));
+    p->w_htab = take((size_t)p->n_htab * p->esize);
     p->w_probe = take(8);
     p->work_bytes = o;
     *out = p;
@@ -623,7 +631,10 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     c.e_b = p->d_eb;
     c.ctl = reinterpret_cast<CtlDev *>(p->d_state + p->st_ctl);
     c.taper = reinterpret_cast<const double *>(p->d_work + p->w_taper);
+    c.htab = p->d_work + p->w_htab;
     c.trans = p->trans ? 1 : 0;
+    c.wave_ind = 1;
+    for (const InstDev &I : p->hinst) c.wave_ind = c.wave_ind && I.chunks > 1;
     c.sig_bytes = (int32_t)(p->n_taper * sizeof(double));
     c.taper_bs = 0;
     for (const InstDev &I : p->hinst)
@@ -643,6 +654,7 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     TRY_HIP(hipMemsetAsync(c.a_b, 0, (size_t)p->nb_total * sizeof(double), p->stream));
     TRY_HIP(launch_reset(c, p->stream));
     TRY_HIP(launch_tapers(c, p->stream));
+    if (p->n_htab > 0) TRY_HIP(launch_htable(c, p->dbl, p->stream));
     TRY_HIP(launch_ctl_reset(c, -1, p->stream));
     if (p->dense) {  // Regular mode: every block active, the list is every block
         std::vector<uint32_t> all((size_t)p->nb_total);

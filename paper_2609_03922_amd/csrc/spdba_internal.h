@@ -48,6 +48,7 @@ struct InstDev {
     int32_t per;        // updates per step (NLSE: two half steps)
     double tau0;        // threshold after a reset
     double target, deadband;
+    int64_t ht_off;     // NLSE in one dimension: first entry of the H(|m|) table (complex); else -1
 };
 
 // Per-instance control state, in the state buffer: it persists across steps
@@ -94,8 +95,10 @@ struct Ctx {
     const uint8_t *skip;       // [nb_total] or nullptr
     double *e_b;               // [nb_total] per-block energies or nullptr
     CtlDev *ctl;               // [n_inst] control state
+    const void *htab;          // NLSE H(|m|) tables (complex, working precision)
     const double *taper;       // roll-off tables: edge B at [B, 2B)
     uint32_t taper_bs;         // bit k: block edge 2^k in use
+    int32_t wave_ind;          // every block row spans several wave rows: one wave per strip
     int32_t trans;             // transition blocks on
     int32_t sig_bytes;         // LDS of the transition update: the tables, 2 B_max doubles
     int64_t nb_total;
@@ -122,6 +125,7 @@ hipError_t launch_compact_append(const Ctx &c, hipStream_t s);
 hipError_t launch_compact_states(const Ctx &c, hipStream_t s);
 hipError_t launch_ctl_reset(const Ctx &c, int only_inst, hipStream_t s);
 hipError_t launch_tapers(const Ctx &c, hipStream_t s);
+hipError_t launch_htable(const Ctx &c, bool dbl, hipStream_t s);
 // tr: transition weights; ctl: end-of-update control in the last workgroup
 hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_t s, bool tr = false,
                          bool ctl = false);

@@ -163,6 +163,20 @@ __device__ __forceinline__ void nlse_coef(const Coef &K, double m2, T &hr, T &hi
     hi = (T)(K.c1 * sn);
 }
 
+// NLSE, one dimension: the propagator H depends on |m| only, so it is read
+// from a per-instance table built by k_htable with nlse_coef itself (same
+// bits as evaluating it here).  x: grid index, n: length; |m| = x for
+// x <= n/2, n - x above.
+template <typename T>
+__device__ __forceinline__ void nlse_tab_ld(const T *tab, int x, int n, T (&hr)[CV<T>::V], T (&hi)[CV<T>::V]) {
+#pragma unroll
+    for (int v = 0; v < CV<T>::V; ++v) {
+        const int j = (2 * (x + v) <= n) ? x + v : n - x - v;
+        hr[v] = tab[2 * j];
+        hi[v] = tab[2 * j + 1];
+    }
+}
+
 // |m|^2 parts as exact doubles (integers far below 2^53)
 __device__ __forceinline__ double sq_d(int m) {
     const double d = (double)m;
@@ -456,6 +470,9 @@ __device__ __forceinline__ void indicator_rows(const Ctx &c, const InstDev &I, i
     const T *q1p = q0p + 2 * I.N;
     const T *r1p = r0p + 2 * I.N;
     const T c0s = (OP == OP_GS) ? (T)K.c0 : (T)0;
+    // NLSE in one dimension: H from the table, into the (otherwise unused)
+    // right-hand-side registers
+    const T *htab = (OP == OP_NLSE && I.ht_off >= 0) ? reinterpret_cast<const T *>(c.htab) + 2 * I.ht_off : nullptr;
     double mx2[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) mx2[v] = sq_d(sidx(x_lane + v, g.n2));
@@ -483,6 +500,7 @@ __device__ __forceinline__ void indicator_rows(const Ctx &c, const InstDev &I, i
                 const int64_t e = ((((int64_t)z << g.ln1) + y) << g.ln2) + x;
                 CV<T>::ld(q0p + 2 * e, qr[u], qi[u]);
                 if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr[u], ni[u]);
+                else if (htab) nlse_tab_ld<T>(htab, x, g.n2, nr[u], ni[u]);
                 if (OP == OP_GS) {
                     CV<T>::ld(q1p + 2 * e, q2r[u], q2i[u]);
                     CV<T>::ld(r1p + 2 * e, n2r[u], n2i[u]);
@@ -513,8 +531,8 @@ __device__ __forceinline__ void indicator_rows(const Ctx &c, const InstDev &I, i
                     a = gs_cand<T>(c0s, au, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
                     a = a + gs_cand<T>(c0s, av, q2r[u][v], q2i[u][v], n2r[u][v], n2i[u][v], cr, ci);
                 } else {
-                    T hr, hi, cr, ci;
-                    nlse_coef<T>(K, m2, hr, hi);
+                    T hr = nr[u][v], hi = ni[u][v], cr, ci;
+                    if (!htab) nlse_coef<T>(K, m2, hr, hi);
                     a = nlse_cand<T>(hr, hi, qr[u][v], qi[u][v], cr, ci);
                 }
                 // the FP32 slot of k = 0 (real-field operators) is held at
@@ -625,6 +643,52 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
             for (int i = 0; i < nw; ++i) tsum += lds_sum[i];
             c.ind_part[strip] = tsum;
         }
+    }
+}
+
+// Indicator for plans whose block rows span several wave rows (1-D blocks of
+// 1024 bins, say): each such strip is one block, and one wave takes a whole
+// strip -- every row and chunk, four in flight -- so no LDS, no barrier and
+// one G atomic per block.  The workgroup only groups waves.
+template <typename T, int OP, bool EB>
+__global__ void __launch_bounds__(1024) k_indicator_wave(Ctx c) {
+    const int lane = threadIdx.x & 63;
+    const int64_t strip = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (strip >= c.n_strips) return;  // the whole wave
+    const int ii = find_by_offset(c.inst, c.n_inst, strip, 0);
+    const InstDev &I = c.inst[ii];
+    const int64_t ls = strip - I.strip_off;  // one block per strip here
+    const int sx = (int)(ls & ((1 << I.lnbk[2]) - 1));
+    const int64_t t = ls >> I.lnbk[2];
+    const int sby = (int)(t & ((1 << I.lnbk[1]) - 1));
+    const int sbz = (int)(t >> I.lnbk[1]);
+    const int x_lane = (sx << I.lb[2]) + lane * CV<T>::V;
+    const int64_t gb = I.blk_off + ls;
+    const bool skipped = c.skip && c.skip[gb] && !(I.pin && ls == 0);
+    const bool k0_lane = I.k0path && ls == 0 && lane == 0;
+    double amax = 0.0, esum = 0.0, ebs = 0.0;
+    bool bad = false;
+    indicator_rows<T, OP, true>(c, I, ii, sbz, sby, x_lane, !skipped, k0_lane, 0, 1, EB, amax, esum, ebs, bad);
+    if (k0_lane) {
+        double tmp[2];
+        const double a = k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+        bad |= !(a <= DBL_MAX);
+        amax = fmax(amax, a);
+        if (EB)
+            for (int sp = 0; sp < I.nspec; ++sp) ebs += c.k0[2 * ii + sp] * c.k0[2 * ii + sp];
+    }
+    amax = wave_max(amax);
+    if (OP == OP_CH) esum = wave_sum(esum);
+    if (EB) ebs = wave_sum(ebs);
+    if (__any(bad) && lane == 0) atomicOr(c.nonfinite, 1u);
+    if (lane == 0) {
+        const double m = skipped ? 0.0 : amax;
+        c.a_b[gb] = m;
+        if (EB) c.e_b[gb] = skipped ? 0.0 : ebs;
+        if (strip == 0) *c.count = 0u;  // the one-pass compaction appends to it
+        c.strip_max[strip] = m;
+        if (m > 0.0) atomicMax(c.G + ii, (unsigned long long)__double_as_longlong(m));
+        if (OP == OP_CH) c.ind_part[strip] = esum;
     }
 }
 
@@ -945,6 +1009,23 @@ __device__ __forceinline__ void control_inst(const Ctx &c, int i) {
     C.tau2 = C.tau * C.tau;
 }
 
+// NLSE in one dimension: H(|m|) for |m| = 0..n/2 of every instance with a
+// table, by nlse_coef (so a table read equals the evaluation).
+template <typename T>
+__global__ void __launch_bounds__(256) k_htable(Ctx c) {
+    const InstDev &I = c.inst[blockIdx.y];
+    if (I.ht_off < 0) return;
+    const Coef K = Coef::of(I);
+    T *tab = reinterpret_cast<T *>(const_cast<void *>(c.htab)) + 2 * I.ht_off;
+    const int half = I.n[2] >> 1;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j <= half; j += gridDim.x * blockDim.x) {
+        T hr, hi;
+        nlse_coef<T>(K, sq_d(j), hr, hi);
+        tab[2 * j] = hr;
+        tab[2 * j + 1] = hi;
+    }
+}
+
 // control state of one instance (only >= 0) or of all after a field load
 __global__ void __launch_bounds__(64) k_ctl_reset(Ctx c, int only) {
     for (int i = threadIdx.x; i < c.n_inst; i += blockDim.x) {
@@ -1013,6 +1094,7 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
     T *q1p = q0p + 2 * I.N;
     const T *r1p = r0p + 2 * I.N;
     const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
+    const T *htab = (OP == OP_NLSE && I.ht_off >= 0) ? reinterpret_cast<const T *>(c.htab) + 2 * I.ht_off : nullptr;
     const bool trn = TR && (entry >> 31);  // workgroup-uniform
     const uint32_t faces = (entry >> 25) & 63u;
     const int b0 = I.b[0], b1 = I.b[1], b2 = I.b[2];
@@ -1026,6 +1108,7 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
         T qr[V], qi[V], nr[V], ni[V], q2r[V], q2i[V], n2r[V], n2i[V];
         CV<T>::ld(q0p + 2 * e, qr, qi);
         if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr, ni);
+        else if (htab) nlse_tab_ld<T>(htab, x0, g.n2, nr, ni);
         if (OP == OP_GS) {
             CV<T>::ld(q1p + 2 * e, q2r, q2i);
             CV<T>::ld(r1p + 2 * e, n2r, n2i);
@@ -1045,8 +1128,8 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
                 gs_cand<T>(dt, au, qr[v], qi[v], nr[v], ni[v], cr, ci);
                 gs_cand<T>(dt, av, q2r[v], q2i[v], n2r[v], n2i[v], dr, di);
             } else {
-                T hr, hi;
-                nlse_coef<T>(K, m2, hr, hi);
+                T hr = nr[v], hi = ni[v];
+                if (!htab) nlse_coef<T>(K, m2, hr, hi);
                 nlse_cand<T>(hr, hi, qr[v], qi[v], cr, ci);
             }
             if (TR && trn) {
@@ -1163,6 +1246,8 @@ __global__ void __launch_bounds__(256) k_update_multi(Ctx c) {
             const T *r0p = reinterpret_cast<const T *>(c.rhs) + base[u];
             CV<T>::ld(q0p + 2 * el, qr[u], qi[u]);
             if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * el, nr[u], ni[u]);
+            else if (I.ht_off >= 0)
+                nlse_tab_ld<T>(reinterpret_cast<const T *>(c.htab) + 2 * I.ht_off, x0, I.n[2], nr[u], ni[u]);
             if (OP == OP_GS) {
                 CV<T>::ld(q0p + 2 * I.N + 2 * el, q2r[u], q2i[u]);
                 CV<T>::ld(r0p + 2 * I.N + 2 * el, n2r[u], n2i[u]);
@@ -1196,8 +1281,8 @@ __global__ void __launch_bounds__(256) k_update_multi(Ctx c) {
                     q2r[u][v] = dr;
                     q2i[u][v] = di;
                 } else {
-                    T hr, hi2;
-                    nlse_coef<T>(K, m2, hr, hi2);
+                    T hr = nr[u][v], hi2 = ni[u][v];
+                    if (I.ht_off < 0) nlse_coef<T>(K, m2, hr, hi2);
                     nlse_cand<T>(hr, hi2, qr[u][v], qi[u][v], cr, ci);
                 }
                 qr[u][v] = cr;
@@ -1246,6 +1331,7 @@ __device__ __forceinline__ void update_strip_body(const Ctx &c, const InstDev &I
     T *q1p = q0p + 2 * I.N;
     const T *r1p = r0p + 2 * I.N;
     const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
+    const T *htab = (OP == OP_NLSE && I.ht_off >= 0) ? reinterpret_cast<const T *>(c.htab) + 2 * I.ht_off : nullptr;
     // frozen lanes never load or store; their registers are set once so that
     // the unconditional arithmetic below reads defined values
     T qr[U][V], qi[U][V], nr[U][V], ni[U][V], q2r[U][V], q2i[U][V], n2r[U][V], n2i[U][V];
@@ -1274,6 +1360,7 @@ __device__ __forceinline__ void update_strip_body(const Ctx &c, const InstDev &I
                 const int64_t e = eidx[u];
                 CV<T>::ld(q0p + 2 * e, qr[u], qi[u]);
                 if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr[u], ni[u]);
+                else if (htab) nlse_tab_ld<T>(htab, x, g.n2, nr[u], ni[u]);
                 if (OP == OP_GS) {
                     CV<T>::ld(q1p + 2 * e, q2r[u], q2i[u]);
                     CV<T>::ld(r1p + 2 * e, n2r[u], n2i[u]);
@@ -1301,8 +1388,8 @@ __device__ __forceinline__ void update_strip_body(const Ctx &c, const InstDev &I
                     cq2[v] = dr;
                     cq2i[v] = di;
                 } else {
-                    T hr, hi;
-                    nlse_coef<T>(K, m2, hr, hi);
+                    T hr = nr[u][v], hi = ni[u][v];
+                    if (!htab) nlse_coef<T>(K, m2, hr, hi);
                     nlse_cand<T>(hr, hi, qr[u][v], qi[u][v], cr, ci);
                 }
                 cq[v] = cr;
@@ -1408,6 +1495,7 @@ __global__ void __launch_bounds__(1024) k_dense(Ctx c) {
     T *q1p = q0p + 2 * N;
     const T *r1p = r0p + 2 * N;
     const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
+    const T *htab = (OP == OP_NLSE && I.ht_off >= 0) ? reinterpret_cast<const T *>(c.htab) + 2 * I.ht_off : nullptr;
     double acc[1] = {0.0};
     const int jstep = blockDim.x * V;
     for (int j = threadIdx.x * V; j < TE; j += jstep) {
@@ -1421,6 +1509,7 @@ __global__ void __launch_bounds__(1024) k_dense(Ctx c) {
         T qr[V], qi[V], nr[V], ni[V], q2r[V], q2i[V], n2r[V], n2i[V];
         CV<T>::ld(q0p + 2 * e, qr, qi);
         if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr, ni);
+        else if (htab) nlse_tab_ld<T>(htab, x0, n2, nr, ni);
         if (OP == OP_GS) {
             CV<T>::ld(q1p + 2 * e, q2r, q2i);
             CV<T>::ld(r1p + 2 * e, n2r, n2i);
@@ -1444,8 +1533,8 @@ __global__ void __launch_bounds__(1024) k_dense(Ctx c) {
                 q2r[v] = dr;
                 q2i[v] = di;
             } else {
-                T hr, hi;
-                nlse_coef<T>(K, m2, hr, hi);
+                T hr = nr[v], hi = ni[v];
+                if (!htab) nlse_coef<T>(K, m2, hr, hi);
                 nlse_cand<T>(hr, hi, qr[v], qi[v], cr, ci);
             }
             qr[v] = cr;
@@ -1594,6 +1683,19 @@ template <typename T>
 static hipError_t ind_launch(const Ctx &c, int waves, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     dim3 grid((unsigned)c.n_strips), block(64 * waves);
     // with an event pair the dispatch itself stamps its start and end
+    if (c.wave_ind) {  // one wave per strip, `waves` strips per workgroup
+        const dim3 gw((unsigned)((c.n_strips + waves - 1) / waves));
+        if (c.e_b) {
+            if (c.op == OP_CH) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_CH, true>), gw, block, 0, s, e0, e1, 0, c);
+            else if (c.op == OP_GS) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_GS, true>), gw, block, 0, s, e0, e1, 0, c);
+            else hipExtLaunchKernelGGL((k_indicator_wave<T, OP_NLSE, true>), gw, block, 0, s, e0, e1, 0, c);
+        } else {
+            if (c.op == OP_CH) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_CH, false>), gw, block, 0, s, e0, e1, 0, c);
+            else if (c.op == OP_GS) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_GS, false>), gw, block, 0, s, e0, e1, 0, c);
+            else hipExtLaunchKernelGGL((k_indicator_wave<T, OP_NLSE, false>), gw, block, 0, s, e0, e1, 0, c);
+        }
+        return hipGetLastError();
+    }
     if (c.e_b) {
         if (c.op == OP_CH) hipExtLaunchKernelGGL((k_indicator<T, OP_CH, true>), grid, block, 0, s, e0, e1, 0, c);
         else if (c.op == OP_GS) hipExtLaunchKernelGGL((k_indicator<T, OP_GS, true>), grid, block, 0, s, e0, e1, 0, c);
@@ -1621,6 +1723,13 @@ hipError_t launch_compact_states(const Ctx &c, hipStream_t s) {
 
 hipError_t launch_ctl_reset(const Ctx &c, int only_inst, hipStream_t s) {
     hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, c, only_inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_htable(const Ctx &c, bool dbl, hipStream_t s) {
+    const dim3 grid(64, (unsigned)c.n_inst);
+    if (dbl) hipLaunchKernelGGL(k_htable<double>, grid, dim3(256), 0, s, c);
+    else hipLaunchKernelGGL(k_htable<float>, grid, dim3(256), 0, s, c);
     return hipGetLastError();
 }
 

@@ -82,6 +82,8 @@ CASES = [
     ([D("nlse", "f32", 1, n, 64, 1e-3) for n in (2048, 1024)], 15),
     ([D("nlse", "f64", 1, 4096, 256, 1e-5)], 16),
     ([D("nlse", "f32", 1, 4096, 256, 1e-4, dense=True)], 17),
+    ([D("ch", "f32", 2, 512, 256, 1e-3)], 18),    # 2-D blocks whose rows span two wave rows
+    ([D("gs", "f32", 2, 512, 256, 1e-3), D("gs", "f32", 2, 1024, 256, 1e-3)], 19),
 ]
 
 
