@@ -633,7 +633,12 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     c.taper = reinterpret_cast<const double *>(p->d_work + p->w_taper);
     c.htab = p->d_work + p->w_htab;
     c.trans = p->trans ? 1 : 0;
-    c.wave_ind = 1;
+    c.htab_all = 1;
+    for (const InstDev &I : p->hinst) c.htab_all = c.htab_all && I.ht_off >= 0;
+    // the wave-per-strip indicator, for block rows wider than a wave row (NLSE
+    // only with its H tables: the evaluated propagator needs the registers of
+    // the workgroup-per-strip kernel)
+    c.wave_ind = (p->op != OP_NLSE || c.htab_all) ? 1 : 0;
     for (const InstDev &I : p->hinst) c.wave_ind = c.wave_ind && I.chunks > 1;
     c.sig_bytes = (int32_t)(p->n_taper * sizeof(double));
     c.taper_bs = 0;

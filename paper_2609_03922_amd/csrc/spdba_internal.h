@@ -99,6 +99,7 @@ struct Ctx {
     const double *taper;       // roll-off tables: edge B at [B, 2B)
     uint32_t taper_bs;         // bit k: block edge 2^k in use
     int32_t wave_ind;          // every block row spans several wave rows: one wave per strip
+    int32_t htab_all;          // every instance has an NLSE H table
     int32_t trans;             // transition blocks on
     int32_t sig_bytes;         // LDS of the transition update: the tables, 2 B_max doubles
     int64_t nb_total;

@@ -452,7 +452,9 @@ struct Geo {
 // the whole strip and its |m_x|^2 is computed once.  Lanes that are off
 // (beyond a narrow strip, or in the skip set) never load: their registers stay
 // zero, which every operator maps to a zero increment and zero energy.
-template <typename T, int OP, bool MC>
+// HT: every instance has an H table (one-dimensional NLSE plans), so the
+// evaluation path is not compiled in.
+template <typename T, int OP, bool MC, bool HT = false>
 __device__ __forceinline__ void indicator_rows(const Ctx &c, const InstDev &I, int ii, int sbz, int sby,
                                                int x_lane, bool lane_on, bool k0_lane, int w, int nw,
                                                bool want_eb, double &amax, double &esum, double &ebs,
@@ -472,7 +474,8 @@ __device__ __forceinline__ void indicator_rows(const Ctx &c, const InstDev &I, i
     const T c0s = (OP == OP_GS) ? (T)K.c0 : (T)0;
     // NLSE in one dimension: H from the table, into the (otherwise unused)
     // right-hand-side registers
-    const T *htab = (OP == OP_NLSE && I.ht_off >= 0) ? reinterpret_cast<const T *>(c.htab) + 2 * I.ht_off : nullptr;
+    const T *htab = (OP == OP_NLSE && (HT || I.ht_off >= 0)) ? reinterpret_cast<const T *>(c.htab) + 2 * I.ht_off
+                                                             : nullptr;
     double mx2[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) mx2[v] = sq_d(sidx(x_lane + v, g.n2));
@@ -532,7 +535,7 @@ __device__ __forceinline__ void indicator_rows(const Ctx &c, const InstDev &I, i
                     a = a + gs_cand<T>(c0s, av, q2r[u][v], q2i[u][v], n2r[u][v], n2i[u][v], cr, ci);
                 } else {
                     T hr = nr[u][v], hi = ni[u][v], cr, ci;
-                    if (!htab) nlse_coef<T>(K, m2, hr, hi);
+                    if (!HT && !htab) nlse_coef<T>(K, m2, hr, hi);
                     a = nlse_cand<T>(hr, hi, qr[u][v], qi[u][v], cr, ci);
                 }
                 // the FP32 slot of k = 0 (real-field operators) is held at
@@ -648,47 +651,76 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
 
 // Indicator for plans whose block rows span several wave rows (1-D blocks of
 // 1024 bins, say): each such strip is one block, and one wave takes a whole
-// strip -- every row and chunk, four in flight -- so no LDS, no barrier and
-// one G atomic per block.  The workgroup only groups waves.
-template <typename T, int OP, bool EB>
-__global__ void __launch_bounds__(1024) k_indicator_wave(Ctx c) {
-    const int lane = threadIdx.x & 63;
-    const int64_t strip = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (strip >= c.n_strips) return;  // the whole wave
-    const int ii = find_by_offset(c.inst, c.n_inst, strip, 0);
-    const InstDev &I = c.inst[ii];
-    const int64_t ls = strip - I.strip_off;  // one block per strip here
-    const int sx = (int)(ls & ((1 << I.lnbk[2]) - 1));
-    const int64_t t = ls >> I.lnbk[2];
-    const int sby = (int)(t & ((1 << I.lnbk[1]) - 1));
-    const int sbz = (int)(t >> I.lnbk[1]);
-    const int x_lane = (sx << I.lb[2]) + lane * CV<T>::V;
-    const int64_t gb = I.blk_off + ls;
-    const bool skipped = c.skip && c.skip[gb] && !(I.pin && ls == 0);
-    const bool k0_lane = I.k0path && ls == 0 && lane == 0;
-    double amax = 0.0, esum = 0.0, ebs = 0.0;
-    bool bad = false;
-    indicator_rows<T, OP, true>(c, I, ii, sbz, sby, x_lane, !skipped, k0_lane, 0, 1, EB, amax, esum, ebs, bad);
-    if (k0_lane) {
-        double tmp[2];
-        const double a = k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
-        bad |= !(a <= DBL_MAX);
-        amax = fmax(amax, a);
-        if (EB)
-            for (int sp = 0; sp < I.nspec; ++sp) ebs += c.k0[2 * ii + sp] * c.k0[2 * ii + sp];
+// strip -- every row and chunk, four in flight -- so the data path has no LDS
+// and no barrier.  The instance maxima of the workgroup's waves are combined
+// in LDS and sent with one atomic per instance: device-scope atomics on G
+// serialise (all instances' G share a cache line), so one per strip would cap
+// the rate at short strips.
+template <typename T, int OP, bool EB, bool HT>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) k_indicator_wave(Ctx c) {
+    __shared__ double s_m[16];
+    __shared__ int s_i[16];
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t strip = (int64_t)blockIdx.x * nw + w;
+    double m = 0.0;
+    int ii = -1;
+    if (strip < c.n_strips) {  // wave-uniform
+        // one block per strip: strip ids are block ids, so the owning
+        // instance is one table read (no search over the instances)
+        ii = __builtin_amdgcn_readfirstlane(c.blk_inst[strip]);
+        const InstDev &I = c.inst[ii];
+        const int64_t ls = strip - I.strip_off;
+        const int sx = (int)(ls & ((1 << I.lnbk[2]) - 1));
+        const int64_t t = ls >> I.lnbk[2];
+        const int sby = (int)(t & ((1 << I.lnbk[1]) - 1));
+        const int sbz = (int)(t >> I.lnbk[1]);
+        const int x_lane = (sx << I.lb[2]) + lane * CV<T>::V;
+        const int64_t gb = I.blk_off + ls;
+        const bool skipped = c.skip && c.skip[gb] && !(I.pin && ls == 0);
+        const bool k0_lane = I.k0path && ls == 0 && lane == 0;
+        double amax = 0.0, esum = 0.0, ebs = 0.0;
+        bool bad = false;
+        indicator_rows<T, OP, true, HT>(c, I, ii, sbz, sby, x_lane, !skipped, k0_lane, 0, 1, EB, amax, esum, ebs,
+                                        bad);
+        if (k0_lane) {
+            double tmp[2];
+            const double a = k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+            bad |= !(a <= DBL_MAX);
+            amax = fmax(amax, a);
+            if (EB)
+                for (int sp = 0; sp < I.nspec; ++sp) ebs += c.k0[2 * ii + sp] * c.k0[2 * ii + sp];
+        }
+        amax = wave_max(amax);
+        if (OP == OP_CH) esum = wave_sum(esum);
+        if (EB) ebs = wave_sum(ebs);
+        if (__any(bad) && lane == 0) atomicOr(c.nonfinite, 1u);
+        m = skipped ? 0.0 : amax;
+        if (lane == 0) {
+            c.a_b[gb] = m;
+            if (EB) c.e_b[gb] = skipped ? 0.0 : ebs;
+            if (strip == 0) *c.count = 0u;  // the one-pass compaction appends to it
+            c.strip_max[strip] = m;
+            if (OP == OP_CH) c.ind_part[strip] = esum;
+        }
     }
-    amax = wave_max(amax);
-    if (OP == OP_CH) esum = wave_sum(esum);
-    if (EB) ebs = wave_sum(ebs);
-    if (__any(bad) && lane == 0) atomicOr(c.nonfinite, 1u);
     if (lane == 0) {
-        const double m = skipped ? 0.0 : amax;
-        c.a_b[gb] = m;
-        if (EB) c.e_b[gb] = skipped ? 0.0 : ebs;
-        if (strip == 0) *c.count = 0u;  // the one-pass compaction appends to it
-        c.strip_max[strip] = m;
-        if (m > 0.0) atomicMax(c.G + ii, (unsigned long long)__double_as_longlong(m));
-        if (OP == OP_CH) c.ind_part[strip] = esum;
+        s_m[w] = m;
+        s_i[w] = ii;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // runs of one instance (its strips are contiguous)
+        int cur = -1;
+        double cm = 0.0;
+        for (int k = 0; k <= nw; ++k) {
+            const int ik = k < nw ? s_i[k] : -1;
+            if (ik != cur) {
+                if (cur >= 0 && cm > 0.0) atomicMax(c.G + cur, (unsigned long long)__double_as_longlong(cm));
+                cur = ik;
+                cm = 0.0;
+            }
+            if (k < nw) cm = fmax(cm, s_m[k]);
+        }
     }
 }
 
@@ -1683,16 +1715,20 @@ template <typename T>
 static hipError_t ind_launch(const Ctx &c, int waves, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     dim3 grid((unsigned)c.n_strips), block(64 * waves);
     // with an event pair the dispatch itself stamps its start and end
-    if (c.wave_ind) {  // one wave per strip, `waves` strips per workgroup
-        const dim3 gw((unsigned)((c.n_strips + waves - 1) / waves));
+    if (c.wave_ind) {  // one wave per strip, 16 strips per workgroup
+        (void)waves;
+        block = dim3(1024);
+        const dim3 gw((unsigned)((c.n_strips + 15) / 16));
         if (c.e_b) {
-            if (c.op == OP_CH) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_CH, true>), gw, block, 0, s, e0, e1, 0, c);
-            else if (c.op == OP_GS) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_GS, true>), gw, block, 0, s, e0, e1, 0, c);
-            else hipExtLaunchKernelGGL((k_indicator_wave<T, OP_NLSE, true>), gw, block, 0, s, e0, e1, 0, c);
+            if (c.op == OP_CH) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_CH, true, false>), gw, block, 0, s, e0, e1, 0, c);
+            else if (c.op == OP_GS) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_GS, true, false>), gw, block, 0, s, e0, e1, 0, c);
+            else if (c.htab_all) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_NLSE, true, true>), gw, block, 0, s, e0, e1, 0, c);
+            else hipExtLaunchKernelGGL((k_indicator_wave<T, OP_NLSE, true, false>), gw, block, 0, s, e0, e1, 0, c);
         } else {
-            if (c.op == OP_CH) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_CH, false>), gw, block, 0, s, e0, e1, 0, c);
-            else if (c.op == OP_GS) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_GS, false>), gw, block, 0, s, e0, e1, 0, c);
-            else hipExtLaunchKernelGGL((k_indicator_wave<T, OP_NLSE, false>), gw, block, 0, s, e0, e1, 0, c);
+            if (c.op == OP_CH) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_CH, false, false>), gw, block, 0, s, e0, e1, 0, c);
+            else if (c.op == OP_GS) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_GS, false, false>), gw, block, 0, s, e0, e1, 0, c);
+            else if (c.htab_all) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_NLSE, false, true>), gw, block, 0, s, e0, e1, 0, c);
+            else hipExtLaunchKernelGGL((k_indicator_wave<T, OP_NLSE, false, false>), gw, block, 0, s, e0, e1, 0, c);
         }
         return hipGetLastError();
     }
