@@ -23,6 +23,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 OP_CH, OP_GS, OP_NLSE = 1, 2, 3
 FLAG_DENSE, FLAG_PIN_K0 = 1, 2
 FLAG_TRANSITION, FLAG_REFRESH, FLAG_DYN_TAU = 4, 8, 16  # consistency control (S1.1, S1.3)
+FLAG_STATE = 32  # state-amplitude activity measure (main text; S4.2; S5.3)
 OK, EINVAL, ENONFINITE = 0, 1, 6
 
 

@@ -446,6 +446,11 @@ int or_apply_f64(const or_inst *d, double *q, const double *rhs, const uint8_t *
             cand[2 * i + 1] = ci;
             a = sq2(cr - er, ci - ei);
         }
+        if (d->flags & OR_FLAG_STATE) { /* the state amplitude instead of the increment */
+            a = 0.0;
+            if (i != 0)
+                for (int s = 0; s < g.nspec; ++s) a = a + sq2(q[2 * (s * N + i)], q[2 * (s * N + i) + 1]);
+        }
         if (!(a <= DBL_MAX)) bad |= 1;
         ak[i] = a;
     }
@@ -574,6 +579,12 @@ int or_apply_f32(const or_inst *d, float *q, const float *rhs, double *k0,
             cand[2 * i] = cr;
             cand[2 * i + 1] = ci;
             a = sq2((double)cr - (double)er, (double)ci - (double)ei);
+        }
+        if (d->flags & OR_FLAG_STATE) { /* the state amplitude instead of the increment */
+            a = 0.0;
+            if (i != 0)
+                for (int s = 0; s < g.nspec; ++s)
+                    a = a + sq2((double)q[2 * (s * N + i)], (double)q[2 * (s * N + i) + 1]);
         }
         if (!(a <= DBL_MAX)) bad |= 1;
         ak[i] = a;

@@ -28,6 +28,13 @@
 #define OR_FLAG_TRANSITION 4u /* frozen face neighbours of active blocks take a tapered increment */
 #define OR_FLAG_REFRESH 8u    /* every refresh_period-th step activates every block            */
 #define OR_FLAG_DYN_TAU 16u   /* the threshold follows a target ratio of non-frozen blocks      */
+/* state-amplitude measure (the paper's state-based indicators: block energy
+ * in the main text's XPFC section, the component RMS amplitude of S4.2 with
+ * "any mode above", the modal spectral power of S5.3): a(k) = sum over
+ * species of |q(k)|^2 of the state entering the update, a_b its block
+ * maximum; the k = 0 mode is left out (it carries the mean; its block is
+ * pinned) */
+#define OR_FLAG_STATE 32u
 
 /* Errors returned by the oracle (0 = success). */
 #define OR_OK 0
