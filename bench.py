@@ -429,7 +429,37 @@ def equal_error(cfg, sizes, K, W, S, inputs, autotune, arch, np, torch,
     T6 = timed(cfg["tau"], False)
     res.update({"spdba_steps_per_s_at_config_tau": K / T6, "speedup_steps_vs_dense_at_config_tau": Td / T6})
     res["control"] = control_sweep(cfg, K, run, timed, make, err, e_d, Td, s_est, np, torch, tau_star)
+    res["state_indicator"] = state_sweep(cfg, K, run, timed, make, err, e_d, Td, s_est, np, torch)
     return res
+
+
+def state_sweep(cfg, K, run, timed, make, err, e_d, Td, s_est, np, torch,
+                taus=(1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7)):
+    """The state-amplitude activity measure (a(k) = sum over species of |q|^2,
+    k = 0 left out) against the same FP64 truth: threshold sweep, the largest
+    threshold within the equal-error bar, its graph-replay speed against dense
+    and its eager stage times."""
+    rows = []
+    for tau in taus:
+        f, acts, _ = run("f32", tau, False, state_indicator=True)
+        am = float(np.mean(acts))
+        rows.append({"tau": tau, "rel_l2": err(f), "active_fraction_mean": round(am, 4),
+                     "active_fraction_last_step": round(acts[-1], 4), "s_estimate": s_est(am)})
+    ok = [r for r in rows if r["rel_l2"] <= 1.1 * e_d]
+    out = {"sweep": rows, "tau_star": max(r["tau"] for r in ok) if ok else None}
+    if ok:
+        t = out["tau_star"]
+        Ts = timed(t, False, state_indicator=True)
+        p = make("f32", t, False, timing=True, state_indicator=True)
+        p.step(K)
+        torch.cuda.synchronize()
+        st = p.stats(0)
+        p.destroy()
+        names = ("fft", "nonlinear", "indicator", "compaction", "update", "step")
+        out.update({"steps_per_s_at_tau_star": K / Ts, "speedup_steps_vs_dense_at_equal_error": Td / Ts,
+                    "stage_ms": {k: round(float(v), 4) for k, v in zip(names, st["stage_ms"])},
+                    "indicator_kernel_ms": round(float(st["indicator_kernel_ms"]), 4)})
+    return out
 
 
 def control_settings(cfg, K, tau_star):

@@ -98,6 +98,14 @@ enum {
                                           fmaf(fl32(sigma), q' - q, q)                 */
     SPDBA_FLAG_REFRESH = 1u << 5,      /* steps n with (n + 1) % refresh_period == 0
                                           update every block                          */
+    SPDBA_FLAG_STATE_INDICATOR = 1u << 7, /* activity measure a(k) = sum over species of
+                                          |q(k)|^2 of the state entering the update
+                                          (the paper's state-based indicators: block
+                                          energy, main text; component RMS amplitude
+                                          with any mode above, S4.2; modal spectral
+                                          power, S5.3) instead of the increment; k = 0
+                                          is left out of a_b and G; no right-hand side
+                                          is read                                      */
     SPDBA_FLAG_DYN_THRESHOLD = 1u << 6 /* tau follows target_ratio: after every
                                           control_interval steps that are not full, the
                                           mean ratio r of non-frozen blocks (over the

@@ -60,6 +60,8 @@ struct spdba_plan_s {
     int n_inst = 0, op = 0, nspec = 1, ndim = 1;
     bool dbl = false, dense = false, pin = false, use_graph = false, timing = false;
     bool ctl = false;    // consistency control: states kernel and control kernel per update
+    bool ab_inc = false; // state measure kept by the update kernel (CH, GS)
+    bool ab_valid = false;  // a_b and a_next hold the measure of the current state
     bool trans = false;  // transition blocks
     hipStream_t stream = nullptr;
     int64_t total_elems = 0, nb_total = 0, n_strips = 0, n_tiles = 0, n_chunks = 0;
@@ -69,7 +71,7 @@ struct spdba_plan_s {
     size_t st_spec = 0, st_k0 = 0, st_ctl = 0, state_bytes = 0;
     size_t w_W = 0, w_R = 0, w_fft = 0, w_ab = 0, w_mask = 0, w_wl = 0, w_chunk = 0, w_cnt = 0, w_G = 0,
            w_Glast = 0, w_rk0 = 0, w_nl = 0, w_ind = 0, w_smax = 0, w_dense = 0, w_binst = 0, w_table = 0,
-           w_taper = 0, w_htab = 0, w_probe = 0, work_bytes = 0;
+           w_taper = 0, w_htab = 0, w_anext = 0, w_probe = 0, work_bytes = 0;
     int64_t n_taper = 0;  // roll-off table length: 2 x the largest block edge
     int64_t n_htab = 0;   // NLSE H(|m|) table entries over all instances
     bool bound = false;
@@ -78,6 +80,7 @@ struct spdba_plan_s {
     rocfft_execution_info info = nullptr;
     int64_t steps = 0;
     bool last_dense = false;
+    bool last_inc = false;  // the last update took the kept state measure (no energy partials)
     bool inv_preserving = true;
     // launch geometry
     int ind_waves = 4, nl_waves = 4, upd_per_cu = 4, dense_threads = 256, cu_count = 256;
@@ -153,7 +156,7 @@ spdba_status validate(const spdba_instance_desc *d, int32_t n, void *) {
         if (x.dtype != SPDBA_F32 && x.dtype != SPDBA_F64) return SPDBA_EUNSUPPORTED;
         if (x.flags & ~uint32_t(SPDBA_FLAG_DENSE | SPDBA_FLAG_PIN_K0 | SPDBA_FLAG_GRAPH |
                                 SPDBA_FLAG_TIMING | SPDBA_FLAG_TRANSITION | SPDBA_FLAG_REFRESH |
-                                SPDBA_FLAG_DYN_THRESHOLD))
+                                SPDBA_FLAG_DYN_THRESHOLD | SPDBA_FLAG_STATE_INDICATOR))
             return SPDBA_EUNSUPPORTED;
         // consistency control: schedule and controller parameters
         if (x.reserved2 != 0 || x.full_steps < 0) return SPDBA_EINVAL;
@@ -247,7 +250,15 @@ spdba_status update_stage(spdba_plan p, int ev_base) {
         k0 = p->evk[p->ring][h];
         k1 = p->evk[p->ring][h + 1];
     }
-    TRY_HIP(launch_indicator(p->ctx, d, p->ind_waves, p->stream, k0, k1));
+    // state measure kept by the last update: only G (and the merge of the
+    // stored blocks' measures) is left to do
+    const bool inc = p->ab_inc && p->ab_valid && !p->d_skip;
+    if (inc) TRY_HIP(launch_gmax(p->ctx, p->stream, k0, k1));
+    else TRY_HIP(launch_indicator(p->ctx, d, p->ind_waves, p->stream, k0, k1));
+    // the next update may continue incrementally only from a step without a
+    // skip set (skipped blocks report a_b = 0, not their measure)
+    p->ab_valid = p->ab_inc && !p->d_skip;
+    p->last_inc = inc;
     record(p, ev_base);
     if (p->ctl) {
         // consistency control: block states (controlled threshold, full
@@ -263,7 +274,7 @@ spdba_status update_stage(spdba_plan p, int ev_base) {
         p->last_dense = false;
         return SPDBA_OK;
     }
-    if (p->upd_mode == 1) {
+    if (p->upd_mode == 1 && !p->ab_inc) {
         // threshold, mask and update in one pass; the ordered list is built
         // from the mask only when it is read back
         record(p, ev_base + 1);
@@ -279,7 +290,7 @@ spdba_status update_stage(spdba_plan p, int ev_base) {
         // a multiple of 8: the update splits its list into one segment per XCD
         const int grid = ((p->cu_count * p->upd_per_cu + 7) / 8) * 8;
         // four entries in flight need blocks of at most one slot per thread
-        const int multi = (p->upd_mode == 2 && p->max_slots <= 256) ? 1 : 0;
+        const int multi = (p->upd_mode == 2 && p->max_slots <= 256 && !p->ab_inc) ? 1 : 0;
         TRY_HIP(launch_update(p->ctx, d, grid, multi, p->stream));
     }
     record(p, ev_base + 2);
@@ -579,6 +590,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     p->w_table = take((size_t)n_inst * sizeof(InstDev));
     p->w_taper = take((size_t)p->n_taper * sizeof(double));
     p->w_htab = take((size_t)p->n_htab * p->esize);
+    p->w_anext = take((size_t)blk * sizeof(double));
     p->w_probe = take(8);
     p->work_bytes = o;
     *out = p;
@@ -633,6 +645,14 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     c.taper = reinterpret_cast<const double *>(p->d_work + p->w_taper);
     c.htab = p->d_work + p->w_htab;
     c.trans = p->trans ? 1 : 0;
+    c.state_ind = (p->desc[0].flags & SPDBA_FLAG_STATE_INDICATOR) ? 1 : 0;
+    // the state entering a CH or GS update is the state the last one stored:
+    // its measure can be kept by the update kernel (NLSE: the Kerr step
+    // changes every mode between the updates)
+    p->ab_inc = c.state_ind && p->op != OP_NLSE && !p->dense;
+    c.ab_inc = p->ab_inc ? 1 : 0;
+    c.a_next = reinterpret_cast<double *>(p->d_work + p->w_anext);
+    p->ab_valid = false;
     c.htab_all = 1;
     for (const InstDev &I : p->hinst) c.htab_all = c.htab_all && I.ht_off >= 0;
     // the wave-per-strip indicator, for block rows wider than a wave row (NLSE
@@ -699,6 +719,7 @@ spdba_status spdba_set_field(spdba_plan p, int32_t inst, const void *d_real) {
     const InstDev &I = p->hinst[inst];
     const int64_t n = I.N * p->nspec;
     TRY_HIP(launch_ctl_reset(p->ctx, inst, p->stream));
+    p->ab_valid = false;
     if (p->op == OP_NLSE) {
         TRY_HIP(launch_scale_copy(p->dbl, d_real, state_ptr(p, I.off), n, (double)I.N, p->stream));
         return SPDBA_OK;
@@ -734,6 +755,7 @@ spdba_status spdba_set_spectrum(spdba_plan p, int32_t inst, const void *d_hat, c
     const int64_t n = I.N * p->nspec;
     double *k0 = p->ctx.k0 + 2 * inst;
     TRY_HIP(launch_ctl_reset(p->ctx, inst, p->stream));
+    p->ab_valid = false;
     TRY_HIP(launch_copy_spectrum(p->ctx, p->dbl, inst, d_hat, state_ptr(p, I.off), n, I.k0path,
                                  (I.k0path && !h_k0) ? k0 : nullptr, p->stream));
     if (I.k0path && h_k0) {
@@ -765,6 +787,13 @@ spdba_status spdba_step(spdba_plan p, int32_t n_steps) {
     if (!p || n_steps < 0) return SPDBA_EINVAL;
     if (!p->bound) return SPDBA_ESTATE;
     if (n_steps == 0) return SPDBA_OK;
+    // a graph holds the kept-measure update stage: after a field load the
+    // measure is first evaluated in full by one eager step
+    if (p->use_graph && p->ab_inc && !p->ab_valid) {
+        TRY(enqueue_step(p));
+        p->steps++;
+        if (--n_steps == 0) return SPDBA_OK;
+    }
     if (p->use_graph && !p->graph_failed) {
         if (!p->graph) {
             hipGraph_t gr = nullptr;
@@ -828,6 +857,7 @@ spdba_status spdba_set_skip(spdba_plan p, const uint8_t *d_skip) {
     if (!p) return SPDBA_EINVAL;
     p->d_skip = d_skip;
     p->ctx.skip = d_skip;
+    p->ab_valid = false;
     if (p->graph) {  // the captured graph holds the old pointer
         (void)hipGraphExecDestroy(p->graph);
         p->graph = nullptr;
@@ -931,7 +961,7 @@ spdba_status spdba_stats(spdba_plan p, int32_t inst, spdba_stats_t *out) {
             TRY_HIP(hipMemcpyAsync(slot0[s], state_ptr(p, I.off + s * I.N), 16, hipMemcpyDeviceToHost,
                                    p->stream));
     std::vector<double> nlp, egp;
-    if (p->op == OP_CH && p->steps > 0) {
+    if (p->op == OP_CH && p->steps > 0 && !p->last_inc) {
         nlp.resize((size_t)I.ntiles * 2);
         TRY_HIP(hipMemcpyAsync(nlp.data(), p->ctx.nl_part + 2 * I.tile_off, nlp.size() * 8,
                                hipMemcpyDeviceToHost, p->stream));

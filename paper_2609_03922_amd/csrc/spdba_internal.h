@@ -79,6 +79,7 @@ struct Ctx {
     double *k0;                // [n_inst][2] FP64 k = 0 state
     double *rhs_k0;            // [n_inst][2]
     double *a_b;               // [nb_total]
+    double *a_next;            // [nb_total] state measure of the blocks the last update stored (ab_inc)
     unsigned long long *G;     // [n_inst] bits of a non-negative double
     unsigned long long *G_last;// [n_inst] G of the last completed update
     uint8_t *mask;             // [nb_total]
@@ -100,6 +101,8 @@ struct Ctx {
     uint32_t taper_bs;         // bit k: block edge 2^k in use
     int32_t wave_ind;          // every block row spans several wave rows: one wave per strip
     int32_t htab_all;          // every instance has an NLSE H table
+    int32_t state_ind;         // state-amplitude activity measure
+    int32_t ab_inc;            // the update rewrites a_b of the blocks it stores (state measure, CH/GS)
     int32_t trans;             // transition blocks on
     int32_t sig_bytes;         // LDS of the transition update: the tables, 2 B_max doubles
     int64_t nb_total;
@@ -124,6 +127,7 @@ hipError_t launch_compact(const Ctx &c, hipStream_t s, int from_mask = 0);
 hipError_t launch_compact_append(const Ctx &c, hipStream_t s);
 // consistency control: block states and list; reset; roll-off tables
 hipError_t launch_compact_states(const Ctx &c, hipStream_t s);
+hipError_t launch_gmax(const Ctx &c, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_ctl_reset(const Ctx &c, int only_inst, hipStream_t s);
 hipError_t launch_tapers(const Ctx &c, hipStream_t s);
 hipError_t launch_htable(const Ctx &c, bool dbl, hipStream_t s);

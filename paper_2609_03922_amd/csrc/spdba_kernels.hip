@@ -453,12 +453,14 @@ struct Geo {
 // (beyond a narrow strip, or in the skip set) never load: their registers stay
 // zero, which every operator maps to a zero increment and zero energy.
 // HT: every instance has an H table (one-dimensional NLSE plans), so the
-// evaluation path is not compiled in.
-template <typename T, int OP, bool MC, bool HT = false>
+// evaluation path is not compiled in.  SI: the state-amplitude measure
+// a(k) = sum over species of |q(k)|^2 (no right-hand side read, no
+// candidate); z_lane marks the lane holding k = 0, which it leaves out.
+template <typename T, int OP, bool MC, bool HT = false, bool SI = false>
 __device__ __forceinline__ void indicator_rows(const Ctx &c, const InstDev &I, int ii, int sbz, int sby,
                                                int x_lane, bool lane_on, bool k0_lane, int w, int nw,
                                                bool want_eb, double &amax, double &esum, double &ebs,
-                                               bool &bad) {
+                                               bool &bad, bool z_lane = false) {
     constexpr int V = CV<T>::V;
     constexpr int U = OP == OP_GS ? 2 : 4;  // rows in flight per wave (GS: two species, half)
     // every instance field the row loop needs, read once (fields first read
@@ -502,11 +504,12 @@ __device__ __forceinline__ void indicator_rows(const Ctx &c, const InstDev &I, i
             if (it < total_it && lane_on) {
                 const int64_t e = ((((int64_t)z << g.ln1) + y) << g.ln2) + x;
                 CV<T>::ld(q0p + 2 * e, qr[u], qi[u]);
-                if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr[u], ni[u]);
+                if (SI) {
+                } else if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr[u], ni[u]);
                 else if (htab) nlse_tab_ld<T>(htab, x, g.n2, nr[u], ni[u]);
                 if (OP == OP_GS) {
                     CV<T>::ld(q1p + 2 * e, q2r[u], q2i[u]);
-                    CV<T>::ld(r1p + 2 * e, n2r[u], n2i[u]);
+                    if (!SI) CV<T>::ld(r1p + 2 * e, n2r[u], n2i[u]);
                 }
             }
         }
@@ -523,7 +526,12 @@ __device__ __forceinline__ void indicator_rows(const Ctx &c, const InstDev &I, i
                     m2 = myz[u] + mx2[v];
                 }
                 double a;
-                if (OP == OP_CH) {
+                if (SI) {
+                    a = sq2((double)qr[u][v], (double)qi[u][v]);
+                    if (OP == OP_GS) a = a + sq2((double)q2r[u][v], (double)q2i[u][v]);
+                    if (v == 0 && u == 0 && z_lane && it0 == 0) a = 0.0;  // k = 0 is left out
+                    if (OP == OP_CH) esum += (K.K2 * m2) * sq2((double)qr[u][v], (double)qi[u][v]);
+                } else if (OP == OP_CH) {
                     T s, f, cr, ci;
                     ch_coef<T>(K, m2, s, f);
                     a = ch_cand<T>(s, f, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
@@ -556,7 +564,7 @@ __device__ __forceinline__ void indicator_rows(const Ctx &c, const InstDev &I, i
 
 // EB: per-block energies requested (c.e_b set; proposer audits).  Without
 // them the kernel carries neither the accumulation nor its LDS array.
-template <typename T, int OP, bool EB>
+template <typename T, int OP, bool EB, bool SI>
 __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
     constexpr int V = CV<T>::V;
     __shared__ double lds_max[16][64];
@@ -585,19 +593,22 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
     bool lane_on = chunks > 1 || lane * V < (I.S << I.lb[2]);
     if (lane_on && c.skip && c.skip[I.blk_off + lane_lb] && !(I.pin && lane_lb == 0)) lane_on = false;
     const bool k0_lane = I.k0path && ls == 0 && lane == 0;
+    const bool z_lane = ls == 0 && lane == 0;
 
     double amax = 0.0, esum = 0.0, ebs = 0.0;
     constexpr bool want_eb = EB;
     bool bad = false;
     if (chunks > 1)
-        indicator_rows<T, OP, true>(c, I, ii, sbz, sby, x_lane, lane_on, k0_lane, w, nw, want_eb, amax, esum,
-                                    ebs, bad);
+        indicator_rows<T, OP, true, false, SI>(c, I, ii, sbz, sby, x_lane, lane_on, k0_lane, w, nw, want_eb, amax,
+                                               esum, ebs, bad, z_lane);
     else
-        indicator_rows<T, OP, false>(c, I, ii, sbz, sby, x_lane, lane_on, k0_lane, w, nw, want_eb, amax, esum,
-                                     ebs, bad);
+        indicator_rows<T, OP, false, false, SI>(c, I, ii, sbz, sby, x_lane, lane_on, k0_lane, w, nw, want_eb, amax,
+                                                esum, ebs, bad, z_lane);
     if (k0_lane && w == 0) {
         double tmp[2];
-        const double a = k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+        // the state measure leaves k = 0 out; the increment rule takes its
+        // FP64 candidate
+        const double a = SI ? 0.0 : k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
         bad |= !(a <= DBL_MAX);
         amax = fmax(amax, a);
         if (want_eb)
@@ -656,7 +667,7 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
 // in LDS and sent with one atomic per instance: device-scope atomics on G
 // serialise (all instances' G share a cache line), so one per strip would cap
 // the rate at short strips.
-template <typename T, int OP, bool EB, bool HT>
+template <typename T, int OP, bool EB, bool HT, bool SI>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) k_indicator_wave(Ctx c) {
     __shared__ double s_m[16];
     __shared__ int s_i[16];
@@ -681,11 +692,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
         const bool k0_lane = I.k0path && ls == 0 && lane == 0;
         double amax = 0.0, esum = 0.0, ebs = 0.0;
         bool bad = false;
-        indicator_rows<T, OP, true, HT>(c, I, ii, sbz, sby, x_lane, !skipped, k0_lane, 0, 1, EB, amax, esum, ebs,
-                                        bad);
+        indicator_rows<T, OP, true, HT, SI>(c, I, ii, sbz, sby, x_lane, !skipped, k0_lane, 0, 1, EB, amax, esum,
+                                            ebs, bad, ls == 0 && lane == 0);
         if (k0_lane) {
             double tmp[2];
-            const double a = k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+            const double a = SI ? 0.0 : k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
             bad |= !(a <= DBL_MAX);
             amax = fmax(amax, a);
             if (EB)
@@ -721,6 +732,35 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             }
             if (k < nw) cm = fmax(cm, s_m[k]);
         }
+    }
+}
+
+// Incremental state measure: the blocks the previous update stored (mask
+// nonzero) take the measure the update kernel wrote for them, the others keep
+// theirs; G of every instance is the maximum.  One block per thread; a wave
+// inside one instance sends one atomic.  Clears the append counter, as the
+// indicator does.
+__global__ void __launch_bounds__(256) k_gmax(Ctx c) {
+    const int lane = threadIdx.x & 63;
+    const int64_t gb = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gb == 0) *c.count = 0u;
+    double v = 0.0;
+    int ii = -1;
+    if (gb < c.nb_total) {
+        ii = c.blk_inst[gb];
+        if (c.mask[gb]) {
+            v = c.a_next[gb];
+            c.a_b[gb] = v;
+        } else {
+            v = c.a_b[gb];
+        }
+    }
+    const int i0 = __shfl(ii, 0, 64);
+    if (__all(ii == i0 || ii < 0)) {
+        const double m = wave_max(v);
+        if (lane == 0 && i0 >= 0 && m > 0.0) atomicMax(c.G + i0, (unsigned long long)__double_as_longlong(m));
+    } else if (ii >= 0 && v > 0.0) {
+        atomicMax(c.G + ii, (unsigned long long)__double_as_longlong(v));
     }
 }
 
@@ -1103,8 +1143,12 @@ __global__ void __launch_bounds__(256) k_tapers(Ctx c, double *w) {
 // TR: the list may hold transition blocks (mask 2), which take
 // q + sigma (q' - q) with sigma from the roll-off tables; FP32 forms the
 // increment in FP32 and applies fl32(sigma) with one fma.
+// With c.ab_inc (state measure, CH and GS) the workgroup also writes the
+// block's next measure (a_next) from the state it stores, so the next step
+// needs no pass over the frozen blocks (their state, and so their a_b, is
+// unchanged); a_b itself keeps the values that decided this update.
 template <typename T, int OP, bool TR>
-__device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, double *sig) {
+__device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, double *sig, double *red) {
     // TR: entries carry the transition flag and the frozen-face bits
     const int64_t gb = TR ? (int64_t)(entry & kEntryId) : (int64_t)entry;
     constexpr int V = CV<T>::V;
@@ -1130,6 +1174,8 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
     const bool trn = TR && (entry >> 31);  // workgroup-uniform
     const uint32_t faces = (entry >> 25) & 63u;
     const int b0 = I.b[0], b1 = I.b[1], b2 = I.b[2];
+    const bool ab = OP != OP_NLSE && c.ab_inc;  // workgroup-uniform
+    double amax = 0.0;
     for (int s = threadIdx.x; s < slots; s += blockDim.x) {
         const int r = s >> llpr, l = s & ((1 << llpr) - 1);
         const int z = g.z0 + (r >> g.lb1);
@@ -1185,8 +1231,28 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
             qr[0] = qi[0] = (T)0;
             q2r[0] = q2i[0] = (T)0;
         }
+        if (ab) {  // the state measure of what is stored; k = 0 left out
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                double a = sq2((double)qr[v], (double)qi[v]);
+                if (OP == OP_GS) a = a + sq2((double)q2r[v], (double)q2i[v]);
+                if (lb == 0 && s == 0 && v == 0) a = 0.0;
+                amax = fmax(amax, a);
+            }
+        }
         CV<T>::st(q0p + 2 * e, qr, qi);
         if (OP == OP_GS) CV<T>::st(q1p + 2 * e, q2r, q2i);
+    }
+    if (ab) {
+        amax = wave_max(amax);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = red[0];
+            for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, red[k]);
+            c.a_next[gb] = m;
+        }
+        __syncthreads();  // red is free for the next block
     }
     if (k0_blk && threadIdx.x == 0) {
         double tmp[2];
@@ -1211,6 +1277,7 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
 template <typename T, int OP, bool TR, bool CTL>
 __global__ void __launch_bounds__(256) k_update(Ctx c) {
     extern __shared__ double sig[];
+    __shared__ double red[4];
     if (CTL && blockIdx.x == 0 && threadIdx.x < 64)
         for (int i = threadIdx.x; i < c.n_inst; i += 64) {
             control_inst(c, i);
@@ -1229,7 +1296,7 @@ __global__ void __launch_bounds__(256) k_update(Ctx c) {
     const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per = P >> 3;
     const uint32_t seg = (total + 7) / 8;
     const uint32_t lo = min(total, seg * xcd), hi = min(total, seg * (xcd + 1));
-    for (uint32_t e = lo + local; e < hi; e += per) update_block<T, OP, TR>(c, c.worklist[e], sig);
+    for (uint32_t e = lo + local; e < hi; e += per) update_block<T, OP, TR>(c, c.worklist[e], sig, red);
 }
 
 // several list entries per workgroup iteration: all their loads are issued
@@ -1711,36 +1778,36 @@ hipError_t launch_k0_rhs(const Ctx &c, hipStream_t s) {
     return hipGetLastError();
 }
 
+// one indicator dispatch: the kernel variant for (T, OP, EB, SI), with an
+// event pair the dispatch itself stamps its start and end
+template <typename T, int OP, bool EB, bool SI>
+static void ind_launch_v(const Ctx &c, int waves, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (c.wave_ind) {  // one wave per strip, 16 strips per workgroup
+        const dim3 gw((unsigned)((c.n_strips + 15) / 16)), b(1024);
+        if (OP == OP_NLSE && c.htab_all)
+            hipExtLaunchKernelGGL((k_indicator_wave<T, OP, EB, true, SI>), gw, b, 0, s, e0, e1, 0, c);
+        else
+            hipExtLaunchKernelGGL((k_indicator_wave<T, OP, EB, false, SI>), gw, b, 0, s, e0, e1, 0, c);
+        return;
+    }
+    hipExtLaunchKernelGGL((k_indicator<T, OP, EB, SI>), dim3((unsigned)c.n_strips), dim3(64 * waves), 0, s, e0, e1,
+                          0, c);
+}
+template <typename T, int OP>
+static void ind_launch_op(const Ctx &c, int waves, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (c.e_b) {
+        if (c.state_ind) ind_launch_v<T, OP, true, true>(c, waves, s, e0, e1);
+        else ind_launch_v<T, OP, true, false>(c, waves, s, e0, e1);
+    } else {
+        if (c.state_ind) ind_launch_v<T, OP, false, true>(c, waves, s, e0, e1);
+        else ind_launch_v<T, OP, false, false>(c, waves, s, e0, e1);
+    }
+}
 template <typename T>
 static hipError_t ind_launch(const Ctx &c, int waves, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    dim3 grid((unsigned)c.n_strips), block(64 * waves);
-    // with an event pair the dispatch itself stamps its start and end
-    if (c.wave_ind) {  // one wave per strip, 16 strips per workgroup
-        (void)waves;
-        block = dim3(1024);
-        const dim3 gw((unsigned)((c.n_strips + 15) / 16));
-        if (c.e_b) {
-            if (c.op == OP_CH) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_CH, true, false>), gw, block, 0, s, e0, e1, 0, c);
-            else if (c.op == OP_GS) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_GS, true, false>), gw, block, 0, s, e0, e1, 0, c);
-            else if (c.htab_all) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_NLSE, true, true>), gw, block, 0, s, e0, e1, 0, c);
-            else hipExtLaunchKernelGGL((k_indicator_wave<T, OP_NLSE, true, false>), gw, block, 0, s, e0, e1, 0, c);
-        } else {
-            if (c.op == OP_CH) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_CH, false, false>), gw, block, 0, s, e0, e1, 0, c);
-            else if (c.op == OP_GS) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_GS, false, false>), gw, block, 0, s, e0, e1, 0, c);
-            else if (c.htab_all) hipExtLaunchKernelGGL((k_indicator_wave<T, OP_NLSE, false, true>), gw, block, 0, s, e0, e1, 0, c);
-            else hipExtLaunchKernelGGL((k_indicator_wave<T, OP_NLSE, false, false>), gw, block, 0, s, e0, e1, 0, c);
-        }
-        return hipGetLastError();
-    }
-    if (c.e_b) {
-        if (c.op == OP_CH) hipExtLaunchKernelGGL((k_indicator<T, OP_CH, true>), grid, block, 0, s, e0, e1, 0, c);
-        else if (c.op == OP_GS) hipExtLaunchKernelGGL((k_indicator<T, OP_GS, true>), grid, block, 0, s, e0, e1, 0, c);
-        else hipExtLaunchKernelGGL((k_indicator<T, OP_NLSE, true>), grid, block, 0, s, e0, e1, 0, c);
-    } else {
-        if (c.op == OP_CH) hipExtLaunchKernelGGL((k_indicator<T, OP_CH, false>), grid, block, 0, s, e0, e1, 0, c);
-        else if (c.op == OP_GS) hipExtLaunchKernelGGL((k_indicator<T, OP_GS, false>), grid, block, 0, s, e0, e1, 0, c);
-        else hipExtLaunchKernelGGL((k_indicator<T, OP_NLSE, false>), grid, block, 0, s, e0, e1, 0, c);
-    }
+    if (c.op == OP_CH) ind_launch_op<T, OP_CH>(c, waves, s, e0, e1);
+    else if (c.op == OP_GS) ind_launch_op<T, OP_GS>(c, waves, s, e0, e1);
+    else ind_launch_op<T, OP_NLSE>(c, waves, s, e0, e1);
     return hipGetLastError();
 }
 hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
@@ -1749,6 +1816,11 @@ hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s, hi
 
 hipError_t launch_compact_append(const Ctx &c, hipStream_t s) {
     hipLaunchKernelGGL(k_compact_append, dim3((unsigned)c.n_chunks), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_gmax(const Ctx &c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL(k_gmax, dim3((unsigned)((c.nb_total + 255) / 256)), dim3(256), 0, s, e0, e1, 0, c);
     return hipGetLastError();
 }
 

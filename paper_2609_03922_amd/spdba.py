@@ -23,6 +23,7 @@ SPDBA_OP_CAHN_HILLIARD, SPDBA_OP_GRAY_SCOTT, SPDBA_OP_NLSE = 1, 2, 3
 SPDBA_F32, SPDBA_F64 = 0, 1
 SPDBA_FLAG_DENSE, SPDBA_FLAG_PIN_K0, SPDBA_FLAG_GRAPH, SPDBA_FLAG_TIMING = 1, 2, 4, 8
 SPDBA_FLAG_TRANSITION, SPDBA_FLAG_REFRESH, SPDBA_FLAG_DYN_THRESHOLD = 16, 32, 64
+SPDBA_FLAG_STATE_INDICATOR = 128
 
 OPS = {"ch": SPDBA_OP_CAHN_HILLIARD, "gs": SPDBA_OP_GRAY_SCOTT, "nlse": SPDBA_OP_NLSE}
 DTYPES = {"f32": SPDBA_F32, "f64": SPDBA_F64}
@@ -181,6 +182,8 @@ class Desc:
     target_ratio: float = 0.0
     control_interval: int = 0
     deadband: float = 0.0
+    # activity measure from the state amplitude instead of the increment
+    state_indicator: bool = False
 
     @property
     def dims3(self):
@@ -214,7 +217,8 @@ class Desc:
                    | (SPDBA_FLAG_GRAPH if self.graph else 0) | (SPDBA_FLAG_TIMING if self.timing else 0)
                    | (SPDBA_FLAG_TRANSITION if self.transition else 0)
                    | (SPDBA_FLAG_REFRESH if self.refresh else 0)
-                   | (SPDBA_FLAG_DYN_THRESHOLD if self.target_ratio else 0))
+                   | (SPDBA_FLAG_DYN_THRESHOLD if self.target_ratio else 0)
+                   | (SPDBA_FLAG_STATE_INDICATOR if self.state_indicator else 0))
         d.reserved = 0
         d.threshold = float(self.tau)
         d.dx, d.dt = float(self.dx), float(self.dt)

@@ -136,6 +136,25 @@ def _full_cases():
     ]
 
 
+STATE_CASES = [
+    ([D("ch", "f64", 2, 64, 16, 1e-3, state_indicator=True)], 41),
+    ([D("ch", "f32", 3, 32, 8, 1e-2, state_indicator=True)], 42),
+    ([D("ch", "f32", 3, 32, 8, 1e-2, state_indicator=True, pin_k0=False)], 43),
+    ([D("gs", "f32", 2, n, 32, 1e-2, state_indicator=True) for n in (128, 64, 256)], 44),
+    ([D("gs", "f64", 2, 64, 16, 1e-2, state_indicator=True)], 45),
+    ([D("nlse", "f32", 1, n, 1024, 1e-2, state_indicator=True) for n in (4096, 16384)], 46),
+    ([D("nlse", "f64", 1, 4096, 256, 1e-2, state_indicator=True)], 47),
+    ([D("ch", "f32", 1, 4096, 1024, 1e-2, state_indicator=True)], 48),
+]
+
+
+@pytest.mark.parametrize("variant", [1, 0], ids=["strip_walk", "block_list"])
+@pytest.mark.parametrize("descs,seed", STATE_CASES, ids=[f"case{c[1]}" for c in STATE_CASES])
+def test_apply_state_indicator_bit_exact(descs, seed, variant):
+    print(f"state-indicator apply case {seed} variant {variant}", flush=True)
+    run_case(descs, seed, update_variant=variant)
+
+
 FULL = _full_cases()
 
 
