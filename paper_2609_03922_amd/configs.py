@@ -2,6 +2,9 @@
 
 Each workload is named by what it is.  Operator parameter order follows the
 library's descriptor: CH (M, kappa); GS (Du, Dv, F, k); NLSE (beta2, gamma, alpha).
+``measure`` is the activity measure of the timed sp-DBA runs: the candidate
+increment |dq|^2 where the workload prescribes it, else the state amplitude
+|q|^2 (the paper's own state-based measures).
 Sizes of batched workloads are drawn from the workload's seed by
 ``inputs.instance_sizes``.
 """
@@ -10,35 +13,35 @@ from __future__ import annotations
 CH2D_128_F64 = dict(
     name="ch2d_128_f64",
     op="ch", dtype="f64", ndim=2, n=128, block=16, tau=1e-6,
-    dx=1.0, dt=0.01, params=(1.0, 1.0), steps=2000, seed=1001,
+    dx=1.0, dt=0.01, params=(1.0, 1.0), steps=2000, seed=1001, measure="increment",
     ic=dict(kind="uniform", mean=0.0, half_width=0.05),
 )
 
 CH3D_256_F32 = dict(
     name="ch3d_256_f32",
     op="ch", dtype="f32", ndim=3, n=256, block=8, tau=1e-6,
-    dx=1.0, dt=0.01, params=(1.0, 1.0), steps=500, seed=1002,
+    dx=1.0, dt=0.01, params=(1.0, 1.0), steps=500, seed=1002, measure="state",
     ic=dict(kind="uniform", mean=0.1, half_width=0.02),
 )
 
 NLSE1D_BATCH48_F32 = dict(
     name="nlse1d_batch48_f32",
     op="nlse", dtype="f32", ndim=1, n_instances=48, log2_min=14, log2_max=20, block=1024,
-    tau=1e-6, dx=15.625, dt=0.8, params=(-21.7, 1.3, 0.0), steps=100, seed=1003,
+    tau=1e-6, dx=15.625, dt=0.8, params=(-21.7, 1.3, 0.0), steps=100, seed=1003, measure="state",
     ic=dict(kind="qam16_rrc", sps=2, rolloff=0.1, power_w=1e-3),
 )
 
 GS2D_BATCH32_F32 = dict(
     name="gs2d_batch32_f32",
     op="gs", dtype="f32", ndim=2, n_instances=32, sizes=(256, 512, 1024), block=32,
-    tau=1e-6, dx=1.0, dt=1.0, params=(0.16, 0.08, 0.035, 0.060), steps=5000, seed=1004,
+    tau=1e-6, dx=1.0, dt=1.0, params=(0.16, 0.08, 0.035, 0.060), steps=5000, seed=1004, measure="state",
     ic=dict(kind="gs_patches", patches=10, patch=8, u=0.5, v=0.25),
 )
 
 CH3D_512_F32_PROPOSER = dict(
     name="ch3d_512_f32_proposer",
     op="ch", dtype="f32", ndim=3, n=512, block=8, tau=1e-6,
-    dx=1.0, dt=0.01, params=(1.0, 1.0), steps=500, seed=1005,
+    dx=1.0, dt=0.01, params=(1.0, 1.0), steps=500, seed=1005, measure="increment",
     ic=dict(kind="uniform", mean=0.1, half_width=0.02),
     proposer=dict(K=10, audit_steps=3, train_n=256, train_seeds=tuple(range(2001, 2009))),
 )
