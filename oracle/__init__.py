@@ -24,6 +24,7 @@ OP_CH, OP_GS, OP_NLSE = 1, 2, 3
 FLAG_DENSE, FLAG_PIN_K0 = 1, 2
 FLAG_TRANSITION, FLAG_REFRESH, FLAG_DYN_TAU = 4, 8, 16  # consistency control (S1.1, S1.3)
 FLAG_STATE = 32  # state-amplitude activity measure (main text; S4.2; S5.3)
+FLAG_HALF = 64  # half-spectrum layout of a real field (S1.2)
 OK, EINVAL, ENONFINITE = 0, 1, 6
 
 
@@ -77,12 +78,25 @@ class Inst:
     full_now: int = 0  # apply(): this update activates every block
 
     @property
+    def half(self) -> bool:
+        return bool(self.flags & FLAG_HALF)
+
+    @property
+    def stored_dims(self) -> tuple:
+        """Extents of the stored spectrum (x keeps nx/2 + 1 columns in the half layout)."""
+        d = tuple(int(v) for v in self.dims)
+        return d[:2] + (d[2] // 2 + 1,) if self.half else d
+
+    @property
     def n_modes(self) -> int:
-        return int(np.prod(self.dims))
+        return int(np.prod(self.stored_dims))
 
     @property
     def n_blocks(self) -> int:
-        return int(np.prod([d // b for d, b in zip(self.dims, self.block)]))
+        nb = [d // b for d, b in zip(self.dims, self.block)]
+        if self.half:  # columns below nx/2, then one block per (z, y) block row for nx/2
+            return nb[0] * nb[1] * (self.dims[2] // (2 * self.block[2]) + 1)
+        return int(np.prod(nb))
 
     @property
     def n_species(self) -> int:
@@ -125,6 +139,8 @@ def _load():
         lib.or_step_ctl_f64.argtypes = [P, ctypes.c_int64, P, P, P, P, P, P]
         lib.or_taper.argtypes = [ctypes.c_int64, P]
         lib.or_ch_energy.argtypes = [P, P, P, P]
+        lib.or_r2c.argtypes = [ctypes.POINTER(ctypes.c_int64), P, P]
+        lib.or_c2r.argtypes = [ctypes.POINTER(ctypes.c_int64), P, P]
         _lib = lib
     return _lib
 
@@ -147,6 +163,27 @@ def fft(a: np.ndarray, sign: int) -> np.ndarray:
     dims = (ctypes.c_int64 * 3)(*([1] * (3 - len(shape)) + shape))
     _check(_load().or_fft(_ptr(a), dims, int(sign)))
     return a
+
+
+def rfft(real: np.ndarray) -> np.ndarray:
+    """Half spectrum (columns 0 .. nx/2 of the forward transform) of a real array."""
+    a = np.ascontiguousarray(real, dtype=np.float64)
+    shape = [1] * (3 - a.ndim) + list(a.shape)
+    out = np.zeros(tuple(shape[:2]) + (shape[2] // 2 + 1,), np.complex128)
+    _check(_load().or_r2c((ctypes.c_int64 * 3)(*shape), _ptr(a), _ptr(out)))
+    return out.reshape(a.shape[:-1] + (a.shape[-1] // 2 + 1,))
+
+
+def irfft(half: np.ndarray, shape) -> np.ndarray:
+    """Real field of a half spectrum (the omitted columns by conjugate symmetry)."""
+    shape = tuple(int(v) for v in shape)
+    full = [1] * (3 - len(shape)) + list(shape)
+    h = np.ascontiguousarray(half, dtype=np.complex128).reshape(-1)
+    if h.size != full[0] * full[1] * (full[2] // 2 + 1):
+        raise ValueError("half spectrum size does not match the shape")
+    out = np.zeros(shape, np.float64)
+    _check(_load().or_c2r((ctypes.c_int64 * 3)(*full), _ptr(h), _ptr(out)))
+    return out
 
 
 def sincos(x: float):

@@ -54,9 +54,19 @@ typedef struct {
     int64_t b[3];   /* block edges        */
     int64_t nb3[3]; /* blocks per axis    */
     int64_t nb;     /* number of blocks   */
-    int64_t N;      /* number of modes    */
+    int64_t N;      /* number of stored modes per species */
     int64_t ext;    /* common extent of the used axes */
     int nspec;      /* species per mode   */
+    /* half-spectrum layout (real fields, Supplementary S1.2): x keeps the
+     * columns 0 .. nx/2 of each row; the blocks of the columns below nx/2 come
+     * first in C order over (z, y, x) block coordinates, then one block per
+     * (z, y) block row for the column nx/2.  Full layout: xs = nx, no such
+     * blocks. */
+    int half;
+    int64_t xs;     /* stored x extent (row length) */
+    int64_t nbxm;   /* blocks along x below the column nx/2 */
+    int64_t nbm;    /* blocks of those columns */
+    int64_t Nreal;  /* grid points per species */
 } geom_t;
 
 static int make_geom(const or_inst *d, geom_t *g) {
@@ -81,15 +91,41 @@ static int make_geom(const or_inst *d, geom_t *g) {
     g->ext = ext ? ext : 1;
     g->nspec = (d->op == OR_OP_GS) ? 2 : 1;
     if (!(d->tau >= 0.0) || !(d->dt > 0.0) || !(d->dx > 0.0)) return OR_EINVAL;
+    g->half = (d->flags & OR_FLAG_HALF) != 0;
+    g->Nreal = g->N;
+    g->xs = g->n[2];
+    g->nbxm = g->nb3[2];
+    g->nbm = g->nb;
+    if (g->half) {
+        /* real fields only; the transition states are not defined on this layout here */
+        if (d->op == OR_OP_NLSE || (d->flags & OR_FLAG_TRANSITION)) return OR_EINVAL;
+        if (g->n[2] < 2 || (g->n[2] / 2) % g->b[2] != 0) return OR_EINVAL;
+        g->xs = g->n[2] / 2 + 1;
+        g->nbxm = g->n[2] / (2 * g->b[2]);
+        g->nbm = g->nb3[0] * g->nb3[1] * g->nbxm;
+        g->nb = g->nbm + g->nb3[0] * g->nb3[1];
+        g->N = g->n[0] * g->n[1] * g->xs;
+    }
     return OR_OK;
+}
+
+/* grid indices of stored mode i (rows of xs columns) */
+static inline void mode_idx(const geom_t *g, int64_t i, int64_t *iz, int64_t *iy, int64_t *ix) {
+    *ix = i % g->xs;
+    *iy = (i / g->xs) % g->n[1];
+    *iz = i / (g->xs * g->n[1]);
 }
 
 /* m = i for i < n/2, else i - n (the Nyquist index maps to -n/2; n = 1 gives 0) */
 static inline int64_t signed_index(int64_t i, int64_t n) { return (2 * i < n) ? i : i - n; }
 
-/* block id of mode (iz, iy, ix) in C order over the block grid */
+/* block id of mode (iz, iy, ix): C order over the block grid; in the half
+ * layout the column nx/2 forms one block per (z, y) block row, numbered after
+ * all others */
 static inline int64_t block_of(const geom_t *g, int64_t iz, int64_t iy, int64_t ix) {
-    return ((iz / g->b[0]) * g->nb3[1] + iy / g->b[1]) * g->nb3[2] + ix / g->b[2];
+    const int64_t row = (iz / g->b[0]) * g->nb3[1] + iy / g->b[1];
+    if (g->half && 2 * ix == g->n[2]) return g->nbm + row;
+    return row * g->nbxm + ix / g->b[2];
 }
 
 /* k^2 = (2 pi / (n dx))^2 * (mz^2 + my^2 + mx^2), the integer sum exact */
@@ -411,7 +447,8 @@ int or_apply_f64(const or_inst *d, double *q, const double *rhs, const uint8_t *
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int64_t i = 0; i < N; ++i) {
-        int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
+        int64_t iz, iy, ix;
+        mode_idx(&g, i, &iz, &iy, &ix);
         int64_t m2 = m2_of(&g, iz, iy, ix);
         double a;
         if (d->op == OR_OP_CH) {
@@ -460,7 +497,8 @@ int or_apply_f64(const or_inst *d, double *q, const double *rhs, const uint8_t *
     for (int64_t b = 0; b < g.nb; ++b) a_b[b] = 0.0;
     if (!dense) {
         for (int64_t i = 0; i < N; ++i) {
-            int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
+            int64_t iz, iy, ix;
+            mode_idx(&g, i, &iz, &iy, &ix);
             int64_t b = block_of(&g, iz, iy, ix);
             if (skip && skip[b] && !(pin && b == 0)) continue;
             if (ak[i] > a_b[b]) a_b[b] = ak[i];
@@ -480,7 +518,8 @@ int or_apply_f64(const or_inst *d, double *q, const double *rhs, const uint8_t *
     make_tapers(&g, &tp);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
-        int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
+        int64_t iz, iy, ix;
+        mode_idx(&g, i, &iz, &iy, &ix);
         const int64_t b = block_of(&g, iz, iy, ix);
         if (!mask[b]) continue;
         const double sig = mask[b] == 2 ? sigma_of(&g, &tp, mask, b, iz, iy, ix) : 1.0;
@@ -522,7 +561,8 @@ int or_apply_f32(const or_inst *d, float *q, const float *rhs, double *k0,
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int64_t i = 0; i < N; ++i) {
-        int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
+        int64_t iz, iy, ix;
+        mode_idx(&g, i, &iz, &iy, &ix);
         int64_t m2 = m2_of(&g, iz, iy, ix);
         double a;
         if (k0path && i == 0) {
@@ -593,7 +633,8 @@ int or_apply_f32(const or_inst *d, float *q, const float *rhs, double *k0,
     for (int64_t b = 0; b < g.nb; ++b) a_b[b] = 0.0;
     if (!dense) {
         for (int64_t i = 0; i < N; ++i) {
-            int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
+            int64_t iz, iy, ix;
+            mode_idx(&g, i, &iz, &iy, &ix);
             int64_t b = block_of(&g, iz, iy, ix);
             if (skip && skip[b] && !(pin && b == 0)) continue;
             if (ak[i] > a_b[b]) a_b[b] = ak[i];
@@ -612,7 +653,8 @@ int or_apply_f32(const or_inst *d, float *q, const float *rhs, double *k0,
     make_tapers(&g, &tp);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
-        int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
+        int64_t iz, iy, ix;
+        mode_idx(&g, i, &iz, &iy, &ix);
         const int64_t b = block_of(&g, iz, iy, ix);
         if (!mask[b]) continue;
         const float sig = mask[b] == 2 ? (float)sigma_of(&g, &tp, mask, b, iz, iy, ix) : 1.0f;
@@ -651,33 +693,95 @@ int or_apply_f32(const or_inst *d, float *q, const float *rhs, double *k0,
 /* Full FP64 steps                                                           */
 /* ------------------------------------------------------------------------ */
 
+/* Real field of a half spectrum (Supplementary S1.2): the omitted columns
+ * nx/2 + 1 .. nx - 1 are filled by q(-k) = conj q(k) from the stored ones,
+ * the stored columns 0 and nx/2 are taken as they are, and the real part of
+ * the complex inverse is returned (1/N included). */
+int or_c2r(const int64_t dims[3], const double *half, double *real) {
+    const int64_t nz = dims[0], ny = dims[1], nx = dims[2];
+    if (nx < 2 || !is_pow2(nx)) return OR_EINVAL;
+    const int64_t xs = nx / 2 + 1, N = nz * ny * nx;
+    double *w = (double *)malloc(sizeof(double) * 2 * (size_t)N);
+    for (int64_t iz = 0; iz < nz; ++iz)
+        for (int64_t iy = 0; iy < ny; ++iy)
+            for (int64_t ix = 0; ix < nx; ++ix) {
+                double *o = w + 2 * ((iz * ny + iy) * nx + ix);
+                if (ix < xs) {
+                    const double *src = half + 2 * ((iz * ny + iy) * xs + ix);
+                    o[0] = src[0];
+                    o[1] = src[1];
+                } else {
+                    const int64_t jz = (nz - iz) % nz, jy = (ny - iy) % ny, jx = nx - ix;
+                    const double *src = half + 2 * ((jz * ny + jy) * xs + jx);
+                    o[0] = src[0];
+                    o[1] = -src[1];
+                }
+            }
+    int rc = or_fft(w, dims, +1);
+    for (int64_t i = 0; i < N; ++i) real[i] = w[2 * i];
+    free(w);
+    return rc;
+}
+
+/* Half spectrum of a real field: the forward transform, columns 0 .. nx/2. */
+int or_r2c(const int64_t dims[3], const double *real, double *half) {
+    const int64_t nz = dims[0], ny = dims[1], nx = dims[2];
+    if (nx < 2 || !is_pow2(nx)) return OR_EINVAL;
+    const int64_t xs = nx / 2 + 1, N = nz * ny * nx;
+    double *w = (double *)malloc(sizeof(double) * 2 * (size_t)N);
+    for (int64_t i = 0; i < N; ++i) {
+        w[2 * i] = real[i];
+        w[2 * i + 1] = 0.0;
+    }
+    int rc = or_fft(w, dims, -1);
+    for (int64_t r = 0; r < nz * ny; ++r)
+        for (int64_t ix = 0; ix < xs; ++ix) {
+            half[2 * (r * xs + ix)] = w[2 * (r * nx + ix)];
+            half[2 * (r * xs + ix) + 1] = w[2 * (r * nx + ix) + 1];
+        }
+    free(w);
+    return rc;
+}
+
 int or_ch_energy(const or_inst *d, const double *chat, double *energy, double *mass) {
     /* F = dx^d sum_x f(c) + (kappa/2) (dx^d / N) sum_k k^2 |c_k|^2,
-     * f(c) = (c^2 - 1)^2 / 4 (so f'(c) = c^3 - c); mass = mean of c. */
+     * f(c) = (c^2 - 1)^2 / 4 (so f'(c) = c^3 - c); mass = mean of c.
+     * Half layout: c from or_c2r; the stored columns 1 .. nx/2 - 1 stand for
+     * themselves and their conjugate partners, so they count twice. */
     geom_t g;
     int rc = make_geom(d, &g);
     if (rc) return rc;
-    const int64_t N = g.N;
+    const int64_t N = g.N, NR = g.Nreal;
     int ndim = (g.n[0] > 1) + (g.n[1] > 1) + (g.n[2] > 1);
     if (ndim == 0) ndim = 1;
     double dvol = 1.0;
     for (int k = 0; k < ndim; ++k) dvol *= d->dx;
-    double *w = (double *)malloc(sizeof(double) * 2 * (size_t)N);
-    memcpy(w, chat, sizeof(double) * 2 * (size_t)N);
-    or_fft(w, g.n, +1);
+    double *c = (double *)malloc(sizeof(double) * (size_t)NR);
+    if (g.half) {
+        or_c2r(g.n, chat, c);
+    } else {
+        double *w = (double *)malloc(sizeof(double) * 2 * (size_t)N);
+        memcpy(w, chat, sizeof(double) * 2 * (size_t)N);
+        or_fft(w, g.n, +1);
+        for (int64_t i = 0; i < N; ++i) c[i] = w[2 * i];
+        free(w);
+    }
     double K2 = kk_base(&g, d->dx);
     double bulk = 0.0, grad = 0.0;
-    for (int64_t i = 0; i < N; ++i) {
-        double cc = w[2 * i];
-        double t = cc * cc - 1.0;
+    for (int64_t i = 0; i < NR; ++i) {
+        double t = c[i] * c[i] - 1.0;
         bulk += 0.25 * t * t;
-        int64_t ix = i % g.n[2], iy = (i / g.n[2]) % g.n[1], iz = i / (g.n[2] * g.n[1]);
-        double k2 = K2 * (double)m2_of(&g, iz, iy, ix);
-        grad += k2 * (chat[2 * i] * chat[2 * i] + chat[2 * i + 1] * chat[2 * i + 1]);
     }
-    free(w);
-    *energy = dvol * bulk + 0.5 * d->p[1] * (dvol / (double)N) * grad;
-    *mass = chat[0] / (double)N;
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t iz, iy, ix;
+        mode_idx(&g, i, &iz, &iy, &ix);
+        double k2 = K2 * (double)m2_of(&g, iz, iy, ix);
+        double wgt = (g.half && ix != 0 && 2 * ix != g.n[2]) ? 2.0 : 1.0;
+        grad += wgt * (k2 * (chat[2 * i] * chat[2 * i] + chat[2 * i + 1] * chat[2 * i + 1]));
+    }
+    free(c);
+    *energy = dvol * bulk + 0.5 * d->p[1] * (dvol / (double)NR) * grad;
+    *mass = chat[0] / (double)NR;
     return OR_OK;
 }
 
@@ -705,6 +809,7 @@ int or_step_ctl_f64(const or_inst *d0, int64_t nsteps, double *state, uint8_t *m
     const int64_t N = g.N, nb = g.nb;
     const int per = (d->op == OR_OP_NLSE) ? 2 : 1;
     double *w = (double *)malloc(sizeof(double) * 2 * (size_t)(N * g.nspec));
+    double *re = (double *)malloc(sizeof(double) * (size_t)(g.Nreal * g.nspec)); /* half layout */
     double *a_b = (double *)malloc(sizeof(double) * (size_t)nb);
     uint8_t *mk = (uint8_t *)malloc((size_t)nb);
     uint32_t *wl = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)nb);
@@ -730,42 +835,68 @@ int or_step_ctl_f64(const or_inst *d0, int64_t nsteps, double *state, uint8_t *m
                 diag[4 * st + 3] = 0.0;
             }
             /* real space: c = Re F^-1[c-hat]; nonlinear term c^3 - c; N-hat */
-            memcpy(w, state, sizeof(double) * 2 * (size_t)N);
-            or_fft(w, g.n, +1);
-            for (int64_t i = 0; i < N; ++i) {
-                double cc = w[2 * i];
-                w[2 * i] = cc * cc * cc - cc;
-                w[2 * i + 1] = 0.0;
+            if (g.half) {
+                or_c2r(g.n, state, re);
+                for (int64_t i = 0; i < g.Nreal; ++i) re[i] = re[i] * re[i] * re[i] - re[i];
+                or_r2c(g.n, re, w);
+            } else {
+                memcpy(w, state, sizeof(double) * 2 * (size_t)N);
+                or_fft(w, g.n, +1);
+                for (int64_t i = 0; i < N; ++i) {
+                    double cc = w[2 * i];
+                    w[2 * i] = cc * cc * cc - cc;
+                    w[2 * i + 1] = 0.0;
+                }
+                or_fft(w, g.n, -1);
             }
-            or_fft(w, g.n, -1);
             rc = or_apply_f64(d, state, w, NULL, a_b, &G, mk, wl, &cnt);
         } else if (d->op == OR_OP_GS) {
             /* R_u = -u v^2 + F (1 - u), R_v = u v^2 - (F + k) v */
             const double Fp = d->p[2], kp = d->p[3];
-            memcpy(w, state, sizeof(double) * 4 * (size_t)N);
-            or_fft(w, g.n, +1);
-            or_fft(w + 2 * N, g.n, +1);
+            const int64_t NR = g.Nreal;
+            double *ru = re, *rv = re + NR;
+            if (g.half) {
+                or_c2r(g.n, state, ru);
+                or_c2r(g.n, state + 2 * N, rv);
+            } else {
+                memcpy(w, state, sizeof(double) * 4 * (size_t)N);
+                or_fft(w, g.n, +1);
+                or_fft(w + 2 * N, g.n, +1);
+                for (int64_t i = 0; i < N; ++i) {
+                    ru[i] = w[2 * i];
+                    rv[i] = w[2 * N + 2 * i];
+                }
+            }
             if (diag) {
                 double su = 0.0, sv = 0.0;
-                for (int64_t i = 0; i < N; ++i) {
-                    su += w[2 * i];
-                    sv += w[2 * N + 2 * i];
+                for (int64_t i = 0; i < NR; ++i) {
+                    su += ru[i];
+                    sv += rv[i];
                 }
-                diag[4 * st] = su / (double)N;
-                diag[4 * st + 1] = sv / (double)N;
+                diag[4 * st] = su / (double)NR;
+                diag[4 * st + 1] = sv / (double)NR;
                 diag[4 * st + 2] = 0.0;
                 diag[4 * st + 3] = 0.0;
             }
-            for (int64_t i = 0; i < N; ++i) {
-                double u = w[2 * i], v = w[2 * N + 2 * i];
+            for (int64_t i = 0; i < NR; ++i) {
+                double u = ru[i], v = rv[i];
                 double uvv = u * v * v;
-                w[2 * i] = -uvv + Fp * (1.0 - u);
-                w[2 * i + 1] = 0.0;
-                w[2 * N + 2 * i] = uvv - (Fp + kp) * v;
-                w[2 * N + 2 * i + 1] = 0.0;
+                ru[i] = -uvv + Fp * (1.0 - u);
+                rv[i] = uvv - (Fp + kp) * v;
             }
-            or_fft(w, g.n, -1);
-            or_fft(w + 2 * N, g.n, -1);
+            if (g.half) {
+                or_r2c(g.n, ru, w);
+                or_r2c(g.n, rv, w + 2 * N);
+            } else {
+                for (int64_t i = 0; i < N; ++i) {
+                    w[2 * i] = ru[i];
+                    w[2 * i + 1] = 0.0;
+                    w[2 * N + 2 * i] = rv[i];
+                    w[2 * N + 2 * i + 1] = 0.0;
+                }
+                or_fft(w, g.n, -1);
+                or_fft(w + 2 * N, g.n, -1);
+            }
             rc = or_apply_f64(d, state, w, NULL, a_b, &G, mk, wl, &cnt);
         } else {
             /* symmetric split step: linear half, Kerr rotation, linear half */
@@ -819,6 +950,7 @@ int or_step_ctl_f64(const or_inst *d0, int64_t nsteps, double *state, uint8_t *m
             for (int64_t b = 0; b < nb; ++b) active_steps[b] += mk[b] != 0;
     }
     free(w);
+    free(re);
     free(a_b);
     free(mk);
     free(wl);

@@ -35,6 +35,14 @@
  * maximum; the k = 0 mode is left out (it carries the mean; its block is
  * pinned) */
 #define OR_FLAG_STATE 32u
+/* half-spectrum layout of a real field (CH, GS; Supplementary S1.2): each
+ * row keeps the columns x = 0 .. nx/2 of the forward transform (nx/2 + 1
+ * values; the others are q(-k) = conj q(k)).  Blocks: those of the columns
+ * below nx/2, C order over (z, y, x) block coordinates, then one block per
+ * (z, y) block row holding the column nx/2, C order over (z, y).  The inverse
+ * is or_c2r.  Requires nx >= 2 with the x block edge dividing nx/2; not
+ * combined with OR_FLAG_TRANSITION. */
+#define OR_FLAG_HALF 64u
 
 /* Errors returned by the oracle (0 = success). */
 #define OR_OK 0
@@ -63,6 +71,16 @@ typedef struct {
 /* n-D complex FFT in place. sign = -1 forward (unnormalised), +1 inverse (1/N). */
 int or_fft(double *a, const int64_t dims[3], int sign);
 
+/* Half spectrum of a real field (nz*ny*nx doubles in, nz*ny*(nx/2+1)
+ * complex out): the forward transform's columns 0 .. nx/2.  nx a power of
+ * two, at least 2. */
+int or_r2c(const int64_t dims[3], const double *real, double *half);
+
+/* Real field of a half spectrum: the omitted columns are filled with
+ * q(-k) = conj q(k) of the stored ones, the stored columns 0 and nx/2 are
+ * used as given, and the real part of the inverse (1/N) is returned. */
+int or_c2r(const int64_t dims[3], const double *half, double *real);
+
 /* sin and cos of x by Cody-Waite reduction and Taylor polynomials. */
 void or_sincos(double x, double *s, double *c);
 
@@ -77,6 +95,7 @@ void or_sincos(double x, double *s, double *c);
 
 /* Kernel-level adaptive (or dense) update of one instance, FP64 arithmetic.
  *   q     : state, nspec x N complex128, updated in place on active blocks
+ *           (N stored modes: nz*ny*nx, or nz*ny*(nx/2+1) with OR_FLAG_HALF)
  *   rhs   : CH: N-hat; GS: R_u-hat then R_v-hat; NLSE: unused (may be NULL)
  *   skip  : optional per-block skip set (proposer); NULL = none
  *   a_b   : out, per-block indicator (0 for skipped / dense)
@@ -94,7 +113,8 @@ int or_apply_f32(const or_inst *d, float *q, const float *rhs, double *k0,
                  uint8_t *mask, uint32_t *wl, int64_t *count);
 
 /* Full FP64 time steps of one instance.
- *   state: CH: c-hat (N complex); GS: u-hat, v-hat; NLSE: E(t) (time domain)
+ *   state: CH: c-hat (N complex); GS: u-hat, v-hat; NLSE: E(t) (time domain);
+ *          with OR_FLAG_HALF the half spectra, real space by or_c2r / or_r2c
  *   masks: optional out [nsteps][mask_per_step][nb]   (NLSE: 2 per step)
  *   diag : optional out [nsteps][4], diagnostics of the state entering the step:
  *          CH {mass, free energy, 0, 0}; GS {mean u, mean v, 0, 0};
@@ -118,7 +138,8 @@ int or_step_ctl_f64(const or_inst *d, int64_t nsteps, double *state, uint8_t *ma
 /* The taper w(i), i = 0 .. B-1, of block edge B (FP64; Supplementary S1.1). */
 void or_taper(int64_t B, double *w);
 
-/* Free energy and mass of a CH spectrum (FP64). */
+/* Free energy and mass of a CH spectrum (FP64).  Half layout: the gradient
+ * sum counts the stored columns 1 .. nx/2 - 1 twice (their partners). */
 int or_ch_energy(const or_inst *d, const double *chat, double *energy, double *mass);
 
 #endif
