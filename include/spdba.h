@@ -106,6 +106,20 @@ enum {
                                           power, S5.3) instead of the increment; k = 0
                                           is left out of a_b and G; no right-hand side
                                           is read                                      */
+    SPDBA_FLAG_HALF_SPECTRUM = 1u << 8, /* real fields (CH, GS; ndim 2 or 3) store the
+                                          half spectrum of Supplementary S1.2: each row
+                                          keeps the columns x = 0 .. nx/2 (n = nz*ny*
+                                          (nx/2 + 1) stored modes per species; the
+                                          others are conj q(-k)); transforms are rocFFT
+                                          real-to-complex / complex-to-real.  Blocks:
+                                          those of the columns below nx/2, C order over
+                                          (z, y, x) block coordinates, then one block
+                                          per (z, y) block row for the column nx/2, C
+                                          order over (z, y).  The x block edge must
+                                          divide nx/2 and nx/(2 block[2]) + 1 <= 2048;
+                                          not with consistency control; the update
+                                          walks the block list (variant 3 is ignored)
+                                          (otherwise EUNSUPPORTED)                     */
     SPDBA_FLAG_DYN_THRESHOLD = 1u << 6 /* tau follows target_ratio: after every
                                           control_interval steps that are not full, the
                                           mean ratio r of non-frozen blocks (over the
@@ -202,7 +216,7 @@ spdba_status spdba_set_field(spdba_plan plan, int32_t inst, const void *d_real);
 spdba_status spdba_get_field(spdba_plan plan, int32_t inst, void *d_out);
 
 /* Raw access to the stored transform-domain state of `inst` (nspec x n
- * complex, working precision; for NLSE the spectrum that the next update
+ * complex, n the stored modes per species; working precision; for NLSE the spectrum that the next update
  * acts on).  For F32 CH/GS the k = 0 coefficients are exchanged in FP64 via
  * h_k0 (host, nspec doubles; NULL in set_spectrum = take slot 0 of d_hat;
  * get_spectrum then writes slot 0 of d_hat as 0).  get_spectrum synchronises. */

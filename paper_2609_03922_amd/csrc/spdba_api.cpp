@@ -47,6 +47,7 @@ struct Group {
     Fft fwd_oop;           // batched: CH/GS forward work->rhs
     Fft inv_ip;            // batched in-place inverse (NLSE, or CH/GS copy fallback)
     Fft inv1_oop, fwd1_ip, inv1_ip;  // one instance (nspec transforms)
+    Fft fwd1_oop;                    // half layout: one instance, real W -> R
 };
 
 }  // namespace
@@ -63,6 +64,7 @@ struct spdba_plan_s {
     bool ab_inc = false; // state measure kept by the update kernel (CH, GS)
     bool ab_valid = false;  // a_b and a_next hold the measure of the current state
     bool trans = false;  // transition blocks
+    bool half = false;   // half-spectrum layout (real fields)
     hipStream_t stream = nullptr;
     int64_t total_elems = 0, nb_total = 0, n_strips = 0, n_tiles = 0, n_chunks = 0;
     size_t esize = 8;  // bytes per complex element
@@ -156,8 +158,17 @@ spdba_status validate(const spdba_instance_desc *d, int32_t n, void *) {
         if (x.dtype != SPDBA_F32 && x.dtype != SPDBA_F64) return SPDBA_EUNSUPPORTED;
         if (x.flags & ~uint32_t(SPDBA_FLAG_DENSE | SPDBA_FLAG_PIN_K0 | SPDBA_FLAG_GRAPH |
                                 SPDBA_FLAG_TIMING | SPDBA_FLAG_TRANSITION | SPDBA_FLAG_REFRESH |
-                                SPDBA_FLAG_DYN_THRESHOLD | SPDBA_FLAG_STATE_INDICATOR))
+                                SPDBA_FLAG_DYN_THRESHOLD | SPDBA_FLAG_STATE_INDICATOR |
+                                SPDBA_FLAG_HALF_SPECTRUM))
             return SPDBA_EUNSUPPORTED;
+        if (x.flags & SPDBA_FLAG_HALF_SPECTRUM) {
+            // real fields of two or three dimensions; the x block edge divides
+            // nx/2 (the column nx/2 forms blocks of its own); no consistency
+            // control; the indicator keeps 4 x (blocks per block row) doubles in LDS
+            if (x.op == SPDBA_OP_NLSE || x.ndim < 2 || has_control(x)) return SPDBA_EUNSUPPORTED;
+            if ((x.dims[2] / 2) % x.block[2] != 0) return SPDBA_EUNSUPPORTED;
+            if (4 * 8 * (x.dims[2] / (2 * x.block[2]) + 1) > kMaxSigBytes) return SPDBA_EUNSUPPORTED;
+        }
         // consistency control: schedule and controller parameters
         if (x.reserved2 != 0 || x.full_steps < 0) return SPDBA_EINVAL;
         if ((x.flags & SPDBA_FLAG_REFRESH) && x.refresh_period < 1) return SPDBA_EINVAL;
@@ -200,6 +211,42 @@ spdba_status create_fft(spdba_plan p, const InstDev &I, Fft &f, bool forward, bo
     return SPDBA_OK;
 }
 
+// Real-to-complex (forward) or complex-to-real (inverse) plan of the half
+// layout, out of place: the real fields follow each other at nz*ny*nx values
+// (rocFFT's default; its two-dimensional batched complex-to-real plans accept
+// no other distance), the half spectra at N complex values.
+spdba_status create_fft_half(spdba_plan p, const InstDev &I, Fft &f, bool forward, int64_t batch) {
+    const int nd = p->ndim;
+    size_t len[3], rs[3], cs[3];
+    for (int a = 0; a < nd; ++a) len[a] = (size_t)I.n[2 - a];  // fastest first
+    rs[0] = cs[0] = 1;
+    for (int a = 1; a < nd; ++a) {
+        rs[a] = rs[a - 1] * len[a - 1];
+        cs[a] = cs[a - 1] * (a == 1 ? (size_t)I.xs : len[a - 1]);
+    }
+    const size_t rdist = (size_t)I.Nreal, cdist = (size_t)I.N;
+    rocfft_plan_description desc = nullptr;
+    if (rocfft_plan_description_create(&desc) != rocfft_status_success) return SPDBA_EFFT;
+    rocfft_status st =
+        forward ? rocfft_plan_description_set_data_layout(desc, rocfft_array_type_real,
+                                                          rocfft_array_type_hermitian_interleaved, nullptr,
+                                                          nullptr, (size_t)nd, rs, rdist, (size_t)nd, cs, cdist)
+                : rocfft_plan_description_set_data_layout(desc, rocfft_array_type_hermitian_interleaved,
+                                                          rocfft_array_type_real, nullptr, nullptr, (size_t)nd,
+                                                          cs, cdist, (size_t)nd, rs, rdist);
+    if (st == rocfft_status_success)
+        st = rocfft_plan_create(&f.plan, rocfft_placement_notinplace,
+                                forward ? rocfft_transform_type_real_forward : rocfft_transform_type_real_inverse,
+                                p->dbl ? rocfft_precision_double : rocfft_precision_single, (size_t)nd, len,
+                                (size_t)batch, desc);
+    rocfft_plan_description_destroy(desc);
+    if (st != rocfft_status_success) return SPDBA_EFFT;
+    size_t wb = 0;
+    if (rocfft_plan_get_work_buffer_size(f.plan, &wb) != rocfft_status_success) return SPDBA_EFFT;
+    p->fft_work = std::max(p->fft_work, wb);
+    return SPDBA_OK;
+}
+
 void destroy_fft(Fft &f) {
     if (f.plan) rocfft_plan_destroy(f.plan);
     f.plan = nullptr;
@@ -215,6 +262,8 @@ spdba_status exec_fft(spdba_plan p, const Fft &f, void *in, void *out) {
 char *state_ptr(spdba_plan p, int64_t elem_off) { return p->d_state + p->st_spec + elem_off * p->esize; }
 char *work_ptr(spdba_plan p, int64_t elem_off) { return p->d_work + p->w_W + elem_off * p->esize; }
 char *rhs_ptr(spdba_plan p, int64_t elem_off) { return p->d_work + p->w_R + elem_off * p->esize; }
+// half layout: a real field in W (offset in real values)
+char *wreal_ptr(spdba_plan p, int64_t real_off) { return p->d_work + p->w_W + real_off * (p->esize / 2); }
 
 // inverse transform of a state region into the work buffer, keeping the state
 spdba_status inverse_keep(spdba_plan p, const Fft &oop, const Fft &ip, int64_t off, int64_t n_elems) {
@@ -222,6 +271,15 @@ spdba_status inverse_keep(spdba_plan p, const Fft &oop, const Fft &ip, int64_t o
     TRY_HIP(hipMemcpyAsync(work_ptr(p, off), state_ptr(p, off), (size_t)n_elems * p->esize,
                            hipMemcpyDeviceToDevice, p->stream));
     return exec_fft(p, ip, work_ptr(p, off), nullptr);
+}
+
+// half layout: inverse of stored spectra into the real slots of W, keeping
+// the state (through a copy in R when the plan overwrites its input)
+spdba_status inverse_half(spdba_plan p, const Fft &oop, int64_t off, int64_t roff, int64_t n_elems) {
+    if (oop.preserves) return exec_fft(p, oop, state_ptr(p, off), wreal_ptr(p, roff));
+    TRY_HIP(hipMemcpyAsync(rhs_ptr(p, off), state_ptr(p, off), (size_t)n_elems * p->esize,
+                           hipMemcpyDeviceToDevice, p->stream));
+    return exec_fft(p, oop, rhs_ptr(p, off), wreal_ptr(p, roff));
 }
 
 void record(spdba_plan p, int i) {
@@ -274,7 +332,7 @@ spdba_status update_stage(spdba_plan p, int ev_base) {
         p->last_dense = false;
         return SPDBA_OK;
     }
-    if (p->upd_mode == 1 && !p->ab_inc) {
+    if (p->upd_mode == 1 && !p->ab_inc && !p->half) {
         // threshold, mask and update in one pass; the ordered list is built
         // from the mask only when it is read back
         record(p, ev_base + 1);
@@ -290,7 +348,7 @@ spdba_status update_stage(spdba_plan p, int ev_base) {
         // a multiple of 8: the update splits its list into one segment per XCD
         const int grid = ((p->cu_count * p->upd_per_cu + 7) / 8) * 8;
         // four entries in flight need blocks of at most one slot per thread
-        const int multi = (p->upd_mode == 2 && p->max_slots <= 256 && !p->ab_inc) ? 1 : 0;
+        const int multi = (p->upd_mode == 2 && p->max_slots <= 256 && !p->ab_inc && !p->half) ? 1 : 0;
         TRY_HIP(launch_update(p->ctx, d, grid, multi, p->stream));
     }
     record(p, ev_base + 2);
@@ -303,8 +361,10 @@ spdba_status enqueue_step(spdba_plan p) {
     const bool d = p->dbl;
     if (p->op != OP_NLSE) {
         record(p, 0);
-        for (auto &g : p->groups)
-            TRY(inverse_keep(p, g.inv_oop, g.inv_ip, g.off, g.N * g.count * p->nspec));
+        for (auto &g : p->groups) {
+            if (p->half) TRY(inverse_half(p, g.inv_oop, g.off, 2 * g.off, g.N * g.count * p->nspec));
+            else TRY(inverse_keep(p, g.inv_oop, g.inv_ip, g.off, g.N * g.count * p->nspec));
+        }
         record(p, 1);
         TRY_HIP(launch_nonlinear(p->ctx, d, p->nl_waves, p->stream));
         record(p, 2);
@@ -404,6 +464,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     p->use_graph = (inst[0].flags & SPDBA_FLAG_GRAPH) != 0;
     p->timing = (inst[0].flags & SPDBA_FLAG_TIMING) != 0;
     p->trans = (inst[0].flags & SPDBA_FLAG_TRANSITION) != 0;
+    p->half = (inst[0].flags & SPDBA_FLAG_HALF_SPECTRUM) != 0;
     for (int i = 0; i < n_inst; ++i) p->ctl = p->ctl || has_control(inst[i]);
     p->nspec = p->op == OP_GS ? 2 : 1;
     p->stream = reinterpret_cast<hipStream_t>(stream);
@@ -415,7 +476,10 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     // memory order: larger grids first, original order within a size
     std::vector<int> order(n_inst);
     std::iota(order.begin(), order.end(), 0);
-    auto Nof = [&](int i) { return inst[i].dims[0] * inst[i].dims[1] * inst[i].dims[2]; };
+    // stored modes per species (half layout: nx/2 + 1 columns per row)
+    auto Nof = [&](int i) {
+        return inst[i].dims[0] * inst[i].dims[1] * (p->half ? inst[i].dims[2] / 2 + 1 : inst[i].dims[2]);
+    };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return Nof(a) > Nof(b); });
     std::vector<int64_t> mem_off(n_inst);
     int64_t acc = 0;
@@ -445,12 +509,23 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
         std::memset(&I, 0, sizeof(I));
         I.off = mem_off[i];
         I.N = Nof(i);
+        {  // half layout: reals of the batch packed from twice the group's offset
+            const Group &gg = p->groups[p->group_of[i]];
+            const int64_t pos = (mem_off[i] - gg.off) / (I.N * p->nspec);
+            I.roff = 2 * gg.off + pos * p->nspec * x.dims[0] * x.dims[1] * x.dims[2];
+        }
         for (int a = 0; a < 3; ++a) {
             I.n[a] = (int32_t)x.dims[a];
             I.b[a] = x.block[a];
             I.nbk[a] = (int32_t)(x.dims[a] / x.block[a]);
         }
         I.nb = (int64_t)I.nbk[0] * I.nbk[1] * I.nbk[2];
+        I.half = p->half ? 1 : 0;
+        I.Nreal = x.dims[0] * x.dims[1] * x.dims[2];
+        I.xs = (int32_t)(p->half ? x.dims[2] / 2 + 1 : x.dims[2]);
+        I.nbxm = p->half ? (int32_t)(x.dims[2] / (2 * x.block[2])) : I.nbk[2];
+        I.nbm = (int64_t)I.nbk[0] * I.nbk[1] * I.nbxm;
+        if (p->half) I.nb = I.nbm + (int64_t)I.nbk[0] * I.nbk[1];
         I.blk_off = blk;
         blk += I.nb;
         I.S = std::min<int>(I.nbk[2], std::max(1, 64 * V / I.b[2]));
@@ -463,11 +538,15 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
         }
         I.lS = lg(I.S);
         I.lchunks = lg(I.chunks);
+        I.lnbxm = lg(I.nbxm);
         p->max_slots = std::max(p->max_slots, I.b[0] * I.b[1] * (I.b[2] / V));
-        I.nstrips = (int64_t)I.nbk[0] * I.nbk[1] * (I.nbk[2] / I.S);
+        // half layout: one indicator strip per (z, y) block row; tiles of TE
+        // reals for the nonlinear term (enough for the dense update's tiles of
+        // TE stored values as well)
+        I.nstrips = p->half ? (int64_t)I.nbk[0] * I.nbk[1] : (int64_t)I.nbk[0] * I.nbk[1] * (I.nbk[2] / I.S);
         I.strip_off = strip;
         strip += I.nstrips;
-        I.ntiles = (I.N + TE - 1) / TE;
+        I.ntiles = ((p->half ? I.Nreal : I.N) + TE - 1) / TE;
         I.tile_off = tile;
         tile += I.ntiles;
         I.nspec = p->nspec;
@@ -477,7 +556,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
         const double K = kTwoPi / ((double)ext * x.dx);
         I.K2 = K * K;
         I.tau2 = x.threshold * x.threshold;
-        I.invN = 1.0 / (double)I.N;
+        I.invN = 1.0 / (double)I.Nreal;
         double dvol = 1.0;
         for (int a = 0; a < x.ndim; ++a) dvol *= x.dx;
         I.dvol = dvol;
@@ -537,6 +616,11 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
         if (p->op == OP_NLSE) {
             if ((st = create_fft(p, I, g.fwd_ip, true, true, batch))) break;
             if ((st = create_fft(p, I, g.inv_ip, false, true, batch))) break;
+        } else if (p->half) {
+            if ((st = create_fft_half(p, I, g.inv_oop, false, batch))) break;
+            if ((st = create_fft_half(p, I, g.fwd_oop, true, batch))) break;
+            if ((st = create_fft_half(p, I, g.inv1_oop, false, p->nspec))) break;
+            if ((st = create_fft_half(p, I, g.fwd1_oop, true, p->nspec))) break;
         } else {
             if ((st = create_fft(p, I, g.inv_oop, false, false, batch))) break;
             if ((st = create_fft(p, I, g.fwd_oop, true, false, batch))) break;
@@ -658,7 +742,10 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     // the wave-per-strip indicator, for block rows wider than a wave row (NLSE
     // only with its H tables: the evaluated propagator needs the registers of
     // the workgroup-per-strip kernel)
-    c.wave_ind = (p->op != OP_NLSE || c.htab_all) ? 1 : 0;
+    c.wave_ind = (p->op != OP_NLSE || c.htab_all) && !p->half ? 1 : 0;
+    c.half = p->half ? 1 : 0;
+    c.half_nb = 0;
+    for (const InstDev &I : p->hinst) c.half_nb = std::max(c.half_nb, I.nbxm + 1);
     for (const InstDev &I : p->hinst) c.wave_ind = c.wave_ind && I.chunks > 1;
     c.sig_bytes = (int32_t)(p->n_taper * sizeof(double));
     c.taper_bs = 0;
@@ -725,6 +812,14 @@ spdba_status spdba_set_field(spdba_plan p, int32_t inst, const void *d_real) {
         return SPDBA_OK;
     }
     const Group &g = p->groups[p->group_of[inst]];
+    if (p->half) {  // real slots of W, forward into R, then the state
+        TRY_HIP(launch_real_to_complex(p->ctx, p->dbl, inst, d_real, I.Nreal * p->nspec, p->stream));
+        TRY(exec_fft(p, g.fwd1_oop, wreal_ptr(p, I.roff), rhs_ptr(p, I.off)));
+        TRY_HIP(launch_copy_spectrum(p->ctx, p->dbl, inst, rhs_ptr(p, I.off), state_ptr(p, I.off), n,
+                                     I.k0path, nullptr, p->stream));
+        if (I.k0path) TRY_HIP(launch_real_sums_to_k0(p->ctx, p->dbl, inst, d_real, I.ntiles, p->stream));
+        return SPDBA_OK;
+    }
     TRY_HIP(launch_real_to_complex(p->ctx, p->dbl, inst, d_real, n, p->stream));
     TRY(exec_fft(p, g.fwd1_ip, work_ptr(p, I.off), nullptr));
     TRY_HIP(launch_copy_spectrum(p->ctx, p->dbl, inst, work_ptr(p, I.off), state_ptr(p, I.off), n,
@@ -743,6 +838,11 @@ spdba_status spdba_get_field(spdba_plan p, int32_t inst, void *d_out) {
         return SPDBA_OK;
     }
     const Group &g = p->groups[p->group_of[inst]];
+    if (p->half) {
+        TRY(inverse_half(p, g.inv1_oop, I.off, I.roff, n));
+        TRY_HIP(launch_work_to_real(p->ctx, p->dbl, inst, d_out, I.Nreal * p->nspec, p->stream));
+        return SPDBA_OK;
+    }
     TRY(inverse_keep(p, g.inv1_oop, g.inv1_ip, I.off, n));
     TRY_HIP(launch_work_to_real(p->ctx, p->dbl, inst, d_out, n, p->stream));
     return SPDBA_OK;
@@ -867,6 +967,7 @@ spdba_status spdba_set_skip(spdba_plan p, const uint8_t *d_skip) {
 
 spdba_status spdba_set_block_energy(spdba_plan p, double *d_eb) {
     if (!p) return SPDBA_EINVAL;
+    if (p->half && d_eb) return SPDBA_EUNSUPPORTED;
     p->d_eb = d_eb;
     p->ctx.e_b = d_eb;
     if (p->graph) {
@@ -1082,6 +1183,7 @@ spdba_status spdba_destroy(spdba_plan p) {
         destroy_fft(g.inv1_oop);
         destroy_fft(g.fwd1_ip);
         destroy_fft(g.inv1_ip);
+        destroy_fft(g.fwd1_oop);
     }
     if (p->info) rocfft_execution_info_destroy(p->info);
     if (p->have_events) {

@@ -49,6 +49,18 @@ struct InstDev {
     double tau0;        // threshold after a reset
     double target, deadband;
     int64_t ht_off;     // NLSE in one dimension: first entry of the H(|m|) table (complex); else -1
+    // half-spectrum layout (real fields): rows of xs = nx/2 + 1 stored columns;
+    // the blocks of the columns below nx/2 first (nbm of them, nbxm along x),
+    // then one block per (z, y) block row for the column nx/2
+    int32_t half;
+    int32_t xs;         // stored row length (nx in the full layout)
+    int32_t nbxm;       // blocks along x below the column nx/2
+    int32_t lnbxm;      // log2 nbxm
+    int64_t nbm;        // blocks of the columns below nx/2 (nb in the full layout)
+    int64_t Nreal;      // grid points per species (N in the full layout)
+    int64_t roff;       // half: first real of species 0 in W; the species and
+                        // the instances of one transform batch follow each
+                        // other at Nreal values (the real transforms' default)
 };
 
 // Per-instance control state, in the state buffer: it persists across steps
@@ -105,6 +117,8 @@ struct Ctx {
     int32_t ab_inc;            // the update rewrites a_b of the blocks it stores (state measure, CH/GS)
     int32_t trans;             // transition blocks on
     int32_t sig_bytes;         // LDS of the transition update: the tables, 2 B_max doubles
+    int32_t half;              // half-spectrum layout
+    int32_t half_nb;           // half: largest number of blocks of one (z, y) block row
     int64_t nb_total;
     int64_t n_strips;
     int64_t n_tiles;

@@ -1690,9 +1690,9 @@ __global__ void __launch_bounds__(256) k_real_tile_sums(Ctx c, int ii, const T *
     double acc[2] = {0.0, 0.0};
     for (int j = threadIdx.x; j < TE; j += blockDim.x) {
         const int64_t e = t0 + j;
-        if (e >= I.N) break;
+        if (e >= I.Nreal) break;
         acc[0] += (double)real[e];
-        if (I.nspec > 1) acc[1] += (double)real[I.N + e];
+        if (I.nspec > 1) acc[1] += (double)real[I.Nreal + e];
     }
     block_sum<2>(acc, lds);
     if (threadIdx.x == 0) {
@@ -1758,12 +1758,550 @@ __global__ void k_check_pattern(const T *buf, int64_t n, uint32_t *bad) {
 }
 
 // -------------------------------------------------------------------------
+// half-spectrum layout of the real fields (CH, GS; Supplementary S1.2)
+// -------------------------------------------------------------------------
+// A species holds nz*ny rows of xs = nx/2 + 1 complex values, the columns
+// 0 .. nx/2 of the forward transform; the omitted columns are the conjugates
+// of stored ones and are never touched.  Blocks of the columns below nx/2
+// come first (C order over (z, y, x) block coordinates), then one block per
+// (z, y) block row for the column nx/2.  With nx/2 + 1 values per row, rows
+// start on 8-byte boundaries only (FP32), so a lane moves one complex value.
+// The real fields between the transforms are plain arrays of nz*ny*nx values
+// per species in W, from the instance's first real (roff) on.
+
+template <typename T> struct RV;
+template <> struct RV<float> {
+    static constexpr int V = 4;  // reals per 16-byte lane access
+    __device__ static void ld(const float *p, float (&v)[4]) {
+        const float4 x = *reinterpret_cast<const float4 *>(p);
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    }
+    __device__ static void st(float *p, const float (&v)[4]) {
+        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+};
+template <> struct RV<double> {
+    static constexpr int V = 2;
+    __device__ static void ld(const double *p, double (&v)[2]) {
+        const double2 x = *reinterpret_cast<const double2 *>(p);
+        v[0] = x.x; v[1] = x.y;
+    }
+    __device__ static void st(double *p, const double (&v)[2]) {
+        *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void ld1(const T *p, T &re, T &im) {
+    if (sizeof(T) == 4) {
+        const float2 v = *reinterpret_cast<const float2 *>(p);
+        re = (T)v.x;
+        im = (T)v.y;
+    } else {
+        const double2 v = *reinterpret_cast<const double2 *>(p);
+        re = (T)v.x;
+        im = (T)v.y;
+    }
+}
+template <typename T>
+__device__ __forceinline__ void st1(T *p, T re, T im) {
+    if (sizeof(T) == 4) *reinterpret_cast<float2 *>(p) = make_float2((float)re, (float)im);
+    else *reinterpret_cast<double2 *>(p) = make_double2((double)re, (double)im);
+}
+
+// Fused nonlinear term on the real fields: the per-element arithmetic and the
+// FP64 sums of k_nonlinear, on tiles of tile_elems reals.
+template <typename T, int OP>
+__global__ void __launch_bounds__(1024) k_nonlinear_h(Ctx c) {
+    constexpr int V = RV<T>::V;
+    constexpr int TE = tile_elems<T>();
+    __shared__ double lds[2 * 16];
+    const int64_t tile = blockIdx.x;
+    const int ii = find_by_offset(c.inst, c.n_inst, tile, 1);
+    const InstDev &I = c.inst[ii];
+    const int64_t t0 = (tile - I.tile_off) * TE;
+    const int64_t NR = I.Nreal;
+    T *base = reinterpret_cast<T *>(c.work) + I.roff;
+    double acc[2] = {0.0, 0.0};
+    const T invN = (T)I.invN;
+    if (OP == OP_CH) {
+        if (I.k0path) {
+            // W holds N (c - cbar): expanded about the FP64 mean (as k_nonlinear)
+            const double cbar = c.k0[2 * ii] * I.invN;
+            const T A1 = (T)(3.0 * cbar * cbar - 1.0), A2 = (T)(3.0 * cbar);
+            for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
+                const int64_t e = t0 + j;
+                if (e >= NR) break;
+                T r[V];
+                RV<T>::ld(base + e, r);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const T d = r[v] * invN;
+                    r[v] = d * (A1 + d * (A2 + d));
+                    const double cd = cbar + (double)d;
+                    const double t = cd * cd - 1.0;
+                    acc[0] += 0.25 * (t * t);
+                    acc[1] += cd * cd * cd - cd;
+                }
+                RV<T>::st(base + e, r);
+            }
+        } else {
+            for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
+                const int64_t e = t0 + j;
+                if (e >= NR) break;
+                T r[V];
+                RV<T>::ld(base + e, r);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const T cc = r[v] * invN;
+                    r[v] = cc * cc * cc - cc;
+                    const double cd = (double)cc;
+                    const double t = cd * cd - 1.0;
+                    acc[0] += 0.25 * (t * t);
+                    acc[1] += (double)r[v];
+                }
+                RV<T>::st(base + e, r);
+            }
+        }
+    } else {
+        const T F = (T)I.q0, Fk = (T)(I.q0 + I.q1);
+        T *bu = base, *bv = base + NR;
+        if (I.k0path) {
+            const double ub = c.k0[2 * ii] * I.invN, vb = c.k0[2 * ii + 1] * I.invN;
+            const T Uf = (T)ub, Vf = (T)vb, V2 = (T)(2.0 * vb);
+            for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
+                const int64_t e = t0 + j;
+                if (e >= NR) break;
+                T ur[V], vr[V];
+                RV<T>::ld(bu + e, ur);
+                RV<T>::ld(bv + e, vr);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const T du = ur[v] * invN, dv = vr[v] * invN;
+                    const T vv = Vf + dv;
+                    const T P = Uf * (dv * (V2 + dv)) + du * (vv * vv);
+                    ur[v] = -P - F * du;
+                    vr[v] = P - Fk * dv;
+                    const double u64 = ub + (double)du, v64 = vb + (double)dv;
+                    const double uvv = u64 * v64 * v64;
+                    acc[0] += -uvv + I.q0 * (1.0 - u64);
+                    acc[1] += uvv - (I.q0 + I.q1) * v64;
+                }
+                RV<T>::st(bu + e, ur);
+                RV<T>::st(bv + e, vr);
+            }
+        } else {
+            for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
+                const int64_t e = t0 + j;
+                if (e >= NR) break;
+                T ur[V], vr[V];
+                RV<T>::ld(bu + e, ur);
+                RV<T>::ld(bv + e, vr);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const T u = ur[v] * invN;
+                    const T w = vr[v] * invN;
+                    const T uvv = u * w * w;
+                    ur[v] = -uvv + F * ((T)1 - u);
+                    vr[v] = uvv - Fk * w;
+                    acc[0] += (double)ur[v];
+                    acc[1] += (double)vr[v];
+                }
+                RV<T>::st(bu + e, ur);
+                RV<T>::st(bv + e, vr);
+            }
+        }
+    }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+        c.nl_part[2 * tile] = acc[0];
+        c.nl_part[2 * tile + 1] = acc[1];
+    }
+}
+
+// Candidate and measure of one stored mode (CH or GS); returns a(k).
+template <typename T, int OP, bool SI>
+__device__ __forceinline__ double half_mode(const Coef &K, T c0s, double m2, T qr, T qi, T nr, T ni, T q2r,
+                                            T q2i, T n2r, T n2i) {
+    if (SI) {
+        double a = sq2((double)qr, (double)qi);
+        if (OP == OP_GS) a = a + sq2((double)q2r, (double)q2i);
+        return a;
+    }
+    T cr, ci;
+    if (OP == OP_CH) {
+        T s, f;
+        ch_coef<T>(K, m2, s, f);
+        return ch_cand<T>(s, f, qr, qi, nr, ni, cr, ci);
+    }
+    T au, av;
+    gs_coef<T>(K, m2, au, av);
+    double a = gs_cand<T>(c0s, au, qr, qi, nr, ni, cr, ci);
+    return a + gs_cand<T>(c0s, av, q2r, q2i, n2r, n2i, cr, ci);
+}
+
+// Indicator on the half layout: one workgroup per (z, y) block row of one
+// instance.  Lanes take 64 consecutive columns below nx/2, the waves split
+// the rows (four in flight); each lane keeps the maximum of its column, the
+// lanes of one block combine by shuffles, the waves in LDS (dynamic: waves x
+// half_nb doubles).  The column nx/2 is one value per row: there the lanes
+// take rows.  CH also sums the FP64 gradient energy of the state, each stored
+// column below nx/2 other than 0 counted twice (its omitted partner).
+template <typename T, int OP, bool SI>
+__global__ void __launch_bounds__(256) k_indicator_h(Ctx c) {
+    extern __shared__ double hred[];  // [waves][half_nb]
+    __shared__ double s_sum[4], s_max[4];
+    constexpr int U = 4;
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int NB = c.half_nb;
+    const int64_t strip = blockIdx.x;
+    const int ii = find_by_offset(c.inst, c.n_inst, strip, 0);
+    const InstDev &I = c.inst[ii];
+    const int64_t rb = strip - I.strip_off;  // (z, y) block row
+    const int by = (int)(rb & (I.nbk[1] - 1));
+    const int bz = (int)(rb >> I.lnbk[1]);
+    const Coef K = Coef::of(I);
+    const int lb1 = I.lb[1], b1m = I.b[1] - 1, ln1 = I.ln[1];
+    const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2];
+    const int z0 = bz << I.lb[0], y0 = by << lb1;
+    const int R = I.b[0] * I.b[1];
+    const int xs = I.xs, xh = n2 >> 1;
+    const int nbxm = I.nbxm;
+    const T *q0p = reinterpret_cast<const T *>(c.state) + 2 * I.off;
+    const T *r0p = reinterpret_cast<const T *>(c.rhs) + 2 * I.off;
+    const T *q1p = q0p + 2 * I.N;
+    const T *r1p = r0p + 2 * I.N;
+    const T c0s = (OP == OP_GS) ? (T)K.c0 : (T)0;
+    const int64_t row_lb = rb * nbxm;  // local id of the row's first block
+    for (int i = threadIdx.x; i < nw * NB; i += blockDim.x) hred[i] = 0.0;
+    __syncthreads();
+    double esum = 0.0;
+    bool bad = false;
+    const int LB = I.b[2] < 64 ? I.b[2] : 64;  // lanes of one block in a chunk
+    for (int x0 = 0; x0 < xh; x0 += 64) {
+        const int x = x0 + lane;
+        const int bx = x >> I.lb[2];
+        bool on = x < xh;
+        if (on && c.skip && c.skip[I.blk_off + row_lb + bx] && !(I.pin && row_lb + bx == 0)) on = false;
+        const double mx2 = sq_d(x);
+        const double wgt = x == 0 ? 1.0 : 2.0;
+        const bool zl = rb == 0 && x == 0;  // the lane of k = 0 (row 0)
+        double amax = 0.0;
+        for (int r0 = w; r0 < R; r0 += nw * U) {
+            T qr[U], qi[U], nr[U], ni[U], q2r[U], q2i[U], n2r[U], n2i[U];
+            double myz[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                qr[u] = qi[u] = nr[u] = ni[u] = q2r[u] = q2i[u] = n2r[u] = n2i[u] = (T)0;
+                const int r = r0 + u * nw;  // wave-uniform
+                const int z = z0 + (r >> lb1), y = y0 + (r & b1m);
+                myz[u] = sq_d(sidx(z, n0)) + sq_d(sidx(y, n1));
+                if (r < R && on) {
+                    const int64_t e = ((int64_t)((z << ln1) + y)) * xs + x;
+                    ld1<T>(q0p + 2 * e, qr[u], qi[u]);
+                    if (!SI) ld1<T>(r0p + 2 * e, nr[u], ni[u]);
+                    if (OP == OP_GS) {
+                        ld1<T>(q1p + 2 * e, q2r[u], q2i[u]);
+                        if (!SI) ld1<T>(r1p + 2 * e, n2r[u], n2i[u]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (r0 + u * nw >= R) continue;  // wave-uniform
+                const double m2 = myz[u] + mx2;
+                double a = half_mode<T, OP, SI>(K, c0s, m2, qr[u], qi[u], nr[u], ni[u], q2r[u], q2i[u], n2r[u],
+                                                n2i[u]);
+                // k = 0: left out of the state measure; for FP32 its slot is
+                // zero and the increment comes from the FP64 side path
+                if (zl && r0 == 0 && u == 0 && (SI || I.k0path)) a = 0.0;
+                bad |= !(a <= DBL_MAX);
+                amax = fmax(amax, a);
+                if (OP == OP_CH) esum += wgt * ((K.K2 * m2) * sq2((double)qr[u], (double)qi[u]));
+            }
+        }
+        for (int off = 1; off < LB; off <<= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+        if (x < xh && (lane & (LB - 1)) == 0) hred[w * NB + bx] = fmax(hred[w * NB + bx], amax);
+    }
+    if (!SI && I.k0path && rb == 0 && threadIdx.x == 0) {  // the FP64 k = 0 candidate
+        double tmp[2];
+        const double a = k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+        bad |= !(a <= DBL_MAX);
+        hred[0] = fmax(hred[0], a);
+    }
+    {  // the column nx/2: lanes over rows
+        const int64_t gq = I.blk_off + I.nbm + rb;
+        const bool qon = !(c.skip && c.skip[gq]);
+        const double mx2 = sq_d(xh);
+        double amax = 0.0;
+        for (int r = threadIdx.x; r < R && qon; r += blockDim.x) {
+            const int z = z0 + (r >> lb1), y = y0 + (r & b1m);
+            const int64_t e = ((int64_t)((z << ln1) + y)) * xs + xh;
+            T qr, qi, nr = (T)0, ni = (T)0, q2r = (T)0, q2i = (T)0, n2r = (T)0, n2i = (T)0;
+            ld1<T>(q0p + 2 * e, qr, qi);
+            if (!SI) ld1<T>(r0p + 2 * e, nr, ni);
+            if (OP == OP_GS) {
+                ld1<T>(q1p + 2 * e, q2r, q2i);
+                if (!SI) ld1<T>(r1p + 2 * e, n2r, n2i);
+            }
+            const double m2 = sq_d(sidx(z, n0)) + sq_d(sidx(y, n1)) + mx2;
+            const double a = half_mode<T, OP, SI>(K, c0s, m2, qr, qi, nr, ni, q2r, q2i, n2r, n2i);
+            bad |= !(a <= DBL_MAX);
+            amax = fmax(amax, a);
+            if (OP == OP_CH) esum += (K.K2 * m2) * sq2((double)qr, (double)qi);
+        }
+        amax = wave_max(amax);
+        if (lane == 0) hred[w * NB + nbxm] = fmax(hred[w * NB + nbxm], amax);
+    }
+    if (OP == OP_CH) {
+        esum = wave_sum(esum);
+        if (lane == 0) s_sum[w] = esum;
+    }
+    if (bad) atomicOr(c.nonfinite, 1u);
+    __syncthreads();
+    double gm = 0.0;
+    for (int t = threadIdx.x; t <= nbxm; t += blockDim.x) {
+        double m = hred[t];
+        for (int k = 1; k < nw; ++k) m = fmax(m, hred[k * NB + t]);
+        const int64_t lb = t < nbxm ? row_lb + t : I.nbm + rb;
+        const int64_t gb = I.blk_off + lb;
+        if (c.skip && c.skip[gb] && !(I.pin && lb == 0)) m = 0.0;
+        c.a_b[gb] = m;
+        gm = fmax(gm, m);
+    }
+    gm = wave_max(gm);
+    if (lane == 0) s_max[w] = gm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = s_max[0];
+        for (int k = 1; k < nw; ++k) m = fmax(m, s_max[k]);
+        if (strip == 0) *c.count = 0u;  // the one-pass compaction appends to it
+        if (m > 0.0) atomicMax(c.G + ii, (unsigned long long)__double_as_longlong(m));
+        if (OP == OP_CH) {
+            double ts = 0.0;
+            for (int k = 0; k < nw; ++k) ts += s_sum[k];
+            c.ind_part[strip] = ts;
+        }
+    }
+}
+
+// Update of one listed block on the half layout (as update_block, one
+// complex value per lane; the column-nx/2 blocks are one column wide).
+template <typename T, int OP>
+__device__ __forceinline__ void update_block_h(const Ctx &c, uint32_t entry, double *red) {
+    const int64_t gb = (int64_t)entry;
+    const int ii = c.blk_inst[gb];
+    const InstDev &I = c.inst[ii];
+    const int64_t lb = gb - I.blk_off;
+    const bool nyq = lb >= I.nbm;  // workgroup-uniform
+    int bz, by, x_blk, lbx;
+    if (!nyq) {
+        const int64_t t = lb >> I.lnbxm;
+        x_blk = (int)(lb & (I.nbxm - 1)) << I.lb[2];
+        by = (int)(t & (I.nbk[1] - 1));
+        bz = (int)(t >> I.lnbk[1]);
+        lbx = I.lb[2];
+    } else {
+        const int64_t j = lb - I.nbm;
+        by = (int)(j & (I.nbk[1] - 1));
+        bz = (int)(j >> I.lnbk[1]);
+        x_blk = I.n[2] >> 1;
+        lbx = 0;
+    }
+    const int slots = (I.b[0] * I.b[1]) << lbx;
+    const Coef K = Coef::of(I);
+    const int lb1 = I.lb[1], b1m = I.b[1] - 1, ln1 = I.ln[1];
+    const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2], xs = I.xs;
+    const int z0 = bz << I.lb[0], y0 = by << lb1;
+    const bool k0_blk = I.k0path && lb == 0;
+    T *q0p = reinterpret_cast<T *>(c.state) + 2 * I.off;
+    const T *r0p = reinterpret_cast<const T *>(c.rhs) + 2 * I.off;
+    T *q1p = q0p + 2 * I.N;
+    const T *r1p = r0p + 2 * I.N;
+    const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
+    const bool ab = c.ab_inc;  // workgroup-uniform
+    double amax = 0.0;
+    for (int s = threadIdx.x; s < slots; s += blockDim.x) {
+        const int r = s >> lbx, l = s & ((1 << lbx) - 1);
+        const int z = z0 + (r >> lb1), y = y0 + (r & b1m), x = x_blk + l;
+        const int64_t e = ((int64_t)((z << ln1) + y)) * xs + x;
+        const double mx = (double)sidx(x, n2);
+        const double m2 = __builtin_fma(mx, mx, sq_d(sidx(z, n0)) + sq_d(sidx(y, n1)));
+        T qr, qi, nr, ni, q2r = (T)0, q2i = (T)0, n2r, n2i;
+        ld1<T>(q0p + 2 * e, qr, qi);
+        ld1<T>(r0p + 2 * e, nr, ni);
+        if (OP == OP_GS) {
+            ld1<T>(q1p + 2 * e, q2r, q2i);
+            ld1<T>(r1p + 2 * e, n2r, n2i);
+        }
+        T cr, ci, dr = (T)0, di = (T)0;
+        if (OP == OP_CH) {
+            T sc, f;
+            ch_coef<T>(K, m2, sc, f);
+            ch_cand<T>(sc, f, qr, qi, nr, ni, cr, ci);
+        } else {
+            T au, av;
+            gs_coef<T>(K, m2, au, av);
+            gs_cand<T>(dt, au, qr, qi, nr, ni, cr, ci);
+            gs_cand<T>(dt, av, q2r, q2i, n2r, n2i, dr, di);
+        }
+        if (k0_blk && s == 0) {  // the FP32 slot of k = 0 stays zero
+            cr = ci = dr = di = (T)0;
+        }
+        if (ab) {  // the state measure of what is stored; k = 0 left out
+            double a = sq2((double)cr, (double)ci);
+            if (OP == OP_GS) a = a + sq2((double)dr, (double)di);
+            if (lb == 0 && s == 0) a = 0.0;
+            amax = fmax(amax, a);
+        }
+        st1<T>(q0p + 2 * e, cr, ci);
+        if (OP == OP_GS) st1<T>(q1p + 2 * e, dr, di);
+    }
+    if (ab) {
+        amax = wave_max(amax);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = red[0];
+            for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, red[k]);
+            c.a_next[gb] = m;
+        }
+        __syncthreads();  // red is free for the next block
+    }
+    if (k0_blk && threadIdx.x == 0) {
+        double tmp[2];
+        k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+        c.k0[2 * ii] = tmp[0];
+        if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
+    }
+}
+
+// persistent walk of the appended list, one segment per XCD (as k_update)
+template <typename T, int OP>
+__global__ void __launch_bounds__(256) k_update_h(Ctx c) {
+    __shared__ double red[4];
+    const uint32_t total = *c.count;
+    const int P = gridDim.x;  // multiple of 8
+    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per = P >> 3;
+    const uint32_t seg = (total + 7) / 8;
+    const uint32_t lo = min(total, seg * xcd), hi = min(total, seg * (xcd + 1));
+    for (uint32_t e = lo + local; e < hi; e += per) update_block_h<T, OP>(c, c.worklist[e], red);
+}
+
+// Regular mode on the half layout: every stored mode, tiles of tile_elems
+// consecutive values (rows are contiguous); FP64 gradient-energy partials
+// per tile for CH (every tile writes its partial, zero past the data).
+template <typename T, int OP>
+__global__ void __launch_bounds__(1024) k_dense_h(Ctx c) {
+    constexpr int TE = tile_elems<T>();
+    __shared__ double lds[16];
+    const int64_t tile = blockIdx.x;
+    const int ii = find_by_offset(c.inst, c.n_inst, tile, 1);
+    const InstDev &I = c.inst[ii];
+    const int64_t t0 = (tile - I.tile_off) * TE;
+    const Coef K = Coef::of(I);
+    const int64_t N = I.N;
+    const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2], ln1 = I.ln[1], xs = I.xs, xh = n2 >> 1;
+    const bool k0_tile = I.k0path && t0 == 0;
+    T *q0p = reinterpret_cast<T *>(c.state) + 2 * I.off;
+    const T *r0p = reinterpret_cast<const T *>(c.rhs) + 2 * I.off;
+    T *q1p = q0p + 2 * N;
+    const T *r1p = r0p + 2 * N;
+    const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
+    double acc[1] = {0.0};
+    // (row, x) of this thread's first value, then a fixed stride
+    const int64_t e0 = t0 + threadIdx.x;
+    int64_t row = e0 / xs;
+    int x = (int)(e0 - row * xs);
+    const int drow = (int)(blockDim.x / xs), dx = (int)(blockDim.x - drow * xs);
+    for (int j = threadIdx.x; j < TE; j += blockDim.x) {
+        const int64_t e = t0 + j;
+        if (e >= N) break;
+        const int y = (int)(row & (n1 - 1));
+        const int z = (int)(row >> ln1);
+        const double mx = (double)sidx(x, n2);
+        const double m2 = __builtin_fma(mx, mx, sq_d(sidx(z, n0)) + sq_d(sidx(y, n1)));
+        T qr, qi, nr, ni, q2r = (T)0, q2i = (T)0, n2r, n2i;
+        ld1<T>(q0p + 2 * e, qr, qi);
+        ld1<T>(r0p + 2 * e, nr, ni);
+        if (OP == OP_GS) {
+            ld1<T>(q1p + 2 * e, q2r, q2i);
+            ld1<T>(r1p + 2 * e, n2r, n2i);
+        }
+        T cr, ci, dr = (T)0, di = (T)0;
+        if (OP == OP_CH) {
+            T s, f;
+            ch_coef<T>(K, m2, s, f);
+            const double wgt = (x == 0 || x == xh) ? 1.0 : 2.0;
+            acc[0] += wgt * ((K.K2 * m2) * sq2((double)qr, (double)qi));
+            ch_cand<T>(s, f, qr, qi, nr, ni, cr, ci);
+        } else {
+            T au, av;
+            gs_coef<T>(K, m2, au, av);
+            gs_cand<T>(dt, au, qr, qi, nr, ni, cr, ci);
+            gs_cand<T>(dt, av, q2r, q2i, n2r, n2i, dr, di);
+        }
+        if (k0_tile && j == 0) cr = ci = dr = di = (T)0;  // the FP32 slot of k = 0 stays zero
+        st1<T>(q0p + 2 * e, cr, ci);
+        if (OP == OP_GS) st1<T>(q1p + 2 * e, dr, di);
+        x += dx;
+        row += drow;
+        if (x >= xs) {
+            x -= xs;
+            ++row;
+        }
+    }
+    if (k0_tile && threadIdx.x == 0) {
+        double tmp[2];
+        k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+        c.k0[2 * ii] = tmp[0];
+        if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
+    }
+    if (OP == OP_CH) {
+        block_sum<1>(acc, lds);
+        if (threadIdx.x == 0) c.dense_part[tile] = acc[0];
+    }
+}
+
+// real field (nspec x Nreal values, caller's array) -> the instance's reals in W
+template <typename T>
+__global__ void k_real_to_slots(Ctx c, int ii, const T *real) {
+    const InstDev &I = c.inst[ii];
+    T *w = reinterpret_cast<T *>(c.work) + I.roff;
+    const int64_t n = I.Nreal * I.nspec;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        w[i] = real[i];
+}
+
+// out[s][i] = W_s[i] / N + mean_s (the inverse of the half spectrum in W)
+template <typename T>
+__global__ void k_slots_to_real(Ctx c, int ii, T *out) {
+    const InstDev &I = c.inst[ii];
+    const T *w = reinterpret_cast<const T *>(c.work) + I.roff;
+    const int64_t n = I.Nreal * I.nspec;
+    const T invN = (T)I.invN;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = i / I.Nreal;
+        const T mean = I.k0path ? (T)(c.k0[2 * ii + s] * I.invN) : (T)0;
+        out[i] = w[i] * invN + mean;
+    }
+}
+
+// -------------------------------------------------------------------------
 // launchers
 // -------------------------------------------------------------------------
 
 template <typename T>
 static hipError_t nl_launch(const Ctx &c, int waves, hipStream_t s) {
     dim3 grid((unsigned)c.n_tiles), block(64 * waves);
+    if (c.half) {
+        if (c.op == OP_CH) hipLaunchKernelGGL((k_nonlinear_h<T, OP_CH>), grid, block, 0, s, c);
+        else hipLaunchKernelGGL((k_nonlinear_h<T, OP_GS>), grid, block, 0, s, c);
+        return hipGetLastError();
+    }
     if (c.op == OP_CH) hipLaunchKernelGGL((k_nonlinear<T, OP_CH>), grid, block, 0, s, c);
     else if (c.op == OP_GS) hipLaunchKernelGGL((k_nonlinear<T, OP_GS>), grid, block, 0, s, c);
     else hipLaunchKernelGGL((k_nonlinear<T, OP_NLSE>), grid, block, 0, s, c);
@@ -1803,8 +2341,20 @@ static void ind_launch_op(const Ctx &c, int waves, hipStream_t s, hipEvent_t e0,
         else ind_launch_v<T, OP, false, false>(c, waves, s, e0, e1);
     }
 }
+template <typename T, int OP>
+static void ind_launch_half(const Ctx &c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const dim3 grid((unsigned)c.n_strips), block(256);
+    const size_t lds = (size_t)4 * c.half_nb * sizeof(double);
+    if (c.state_ind) hipExtLaunchKernelGGL((k_indicator_h<T, OP, true>), grid, block, lds, s, e0, e1, 0, c);
+    else hipExtLaunchKernelGGL((k_indicator_h<T, OP, false>), grid, block, lds, s, e0, e1, 0, c);
+}
 template <typename T>
 static hipError_t ind_launch(const Ctx &c, int waves, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (c.half) {  // four waves per workgroup
+        if (c.op == OP_CH) ind_launch_half<T, OP_CH>(c, s, e0, e1);
+        else ind_launch_half<T, OP_GS>(c, s, e0, e1);
+        return hipGetLastError();
+    }
     if (c.op == OP_CH) ind_launch_op<T, OP_CH>(c, waves, s, e0, e1);
     else if (c.op == OP_GS) ind_launch_op<T, OP_GS>(c, waves, s, e0, e1);
     else ind_launch_op<T, OP_NLSE>(c, waves, s, e0, e1);
@@ -1864,6 +2414,11 @@ static void upd_launch_op(const Ctx &c, int grid, int multi, bool tr, bool ctl, 
 }
 template <typename T>
 static hipError_t upd_launch(const Ctx &c, int grid, int multi, bool tr, bool ctl, hipStream_t s) {
+    if (c.half) {  // the block-list walk only
+        if (c.op == OP_CH) hipLaunchKernelGGL((k_update_h<T, OP_CH>), dim3(grid), dim3(256), 0, s, c);
+        else hipLaunchKernelGGL((k_update_h<T, OP_GS>), dim3(grid), dim3(256), 0, s, c);
+        return hipGetLastError();
+    }
     if (c.op == OP_CH) upd_launch_op<T, OP_CH>(c, grid, multi, tr, ctl, s);
     else if (c.op == OP_GS) upd_launch_op<T, OP_GS>(c, grid, multi, tr, ctl, s);
     else upd_launch_op<T, OP_NLSE>(c, grid, multi, tr, ctl, s);
@@ -1888,6 +2443,11 @@ hipError_t launch_update_strip(const Ctx &c, bool dbl, int waves, int grid, hipS
 template <typename T>
 static hipError_t dense_launch(const Ctx &c, int threads, hipStream_t s) {
     dim3 grid((unsigned)c.n_tiles), block(threads);
+    if (c.half) {
+        if (c.op == OP_CH) hipLaunchKernelGGL((k_dense_h<T, OP_CH>), grid, block, 0, s, c);
+        else hipLaunchKernelGGL((k_dense_h<T, OP_GS>), grid, block, 0, s, c);
+        return hipGetLastError();
+    }
     if (c.op == OP_CH) hipLaunchKernelGGL((k_dense<T, OP_CH>), grid, block, 0, s, c);
     else if (c.op == OP_GS) hipLaunchKernelGGL((k_dense<T, OP_GS>), grid, block, 0, s, c);
     else hipLaunchKernelGGL((k_dense<T, OP_NLSE>), grid, block, 0, s, c);
@@ -1909,6 +2469,11 @@ static unsigned grid_for(int64_t n) {
 
 hipError_t launch_real_to_complex(const Ctx &c, bool dbl, int inst, const void *real, int64_t n,
                                   hipStream_t s) {
+    if (c.half) {  // n = nspec x grid points
+        if (dbl) hipLaunchKernelGGL(k_real_to_slots<double>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (const double *)real);
+        else hipLaunchKernelGGL(k_real_to_slots<float>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (const float *)real);
+        return hipGetLastError();
+    }
     if (dbl) hipLaunchKernelGGL(k_real_to_complex<double>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (const double *)real);
     else hipLaunchKernelGGL(k_real_to_complex<float>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (const float *)real);
     return hipGetLastError();
@@ -1926,6 +2491,11 @@ hipError_t launch_real_sums_to_k0(const Ctx &c, bool dbl, int inst, const void *
 
 hipError_t launch_work_to_real(const Ctx &c, bool dbl, int inst, void *out, int64_t n,
                                hipStream_t s) {
+    if (c.half) {  // n = nspec x grid points
+        if (dbl) hipLaunchKernelGGL(k_slots_to_real<double>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (double *)out);
+        else hipLaunchKernelGGL(k_slots_to_real<float>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (float *)out);
+        return hipGetLastError();
+    }
     if (dbl) hipLaunchKernelGGL(k_work_to_real<double>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (double *)out);
     else hipLaunchKernelGGL(k_work_to_real<float>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (float *)out);
     return hipGetLastError();

@@ -536,6 +536,7 @@ spdba_status spdba_proposer_features(spdba_plan plan, const double *const ab[3],
         if (!ab[j] || !G[j]) return SPDBA_EINVAL;
     const Ctx *c = plan_ctx(plan);
     if (!c) return SPDBA_ESTATE;
+    if (c->half) return SPDBA_EUNSUPPORTED;  // features read the full layout's block grid
     hipStream_t s = (hipStream_t)stream;
     double *part = reinterpret_cast<double *>(scratch);
     double *etot = part + (int64_t)c->n_inst * EB_SPLIT;

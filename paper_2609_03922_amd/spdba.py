@@ -24,6 +24,7 @@ SPDBA_F32, SPDBA_F64 = 0, 1
 SPDBA_FLAG_DENSE, SPDBA_FLAG_PIN_K0, SPDBA_FLAG_GRAPH, SPDBA_FLAG_TIMING = 1, 2, 4, 8
 SPDBA_FLAG_TRANSITION, SPDBA_FLAG_REFRESH, SPDBA_FLAG_DYN_THRESHOLD = 16, 32, 64
 SPDBA_FLAG_STATE_INDICATOR = 128
+SPDBA_FLAG_HALF_SPECTRUM = 256
 
 OPS = {"ch": SPDBA_OP_CAHN_HILLIARD, "gs": SPDBA_OP_GRAY_SCOTT, "nlse": SPDBA_OP_NLSE}
 DTYPES = {"f32": SPDBA_F32, "f64": SPDBA_F64}
@@ -184,6 +185,8 @@ class Desc:
     deadband: float = 0.0
     # activity measure from the state amplitude instead of the increment
     state_indicator: bool = False
+    # half-spectrum layout of a real field (Supplementary S1.2)
+    half: bool = False
 
     @property
     def dims3(self):
@@ -194,12 +197,28 @@ class Desc:
         return tuple([1] * (3 - self.ndim) + [self.block] * self.ndim)
 
     @property
-    def n_modes(self):
+    def n_points(self):
+        """Grid points per species (the real-space field)."""
         return self.n ** self.ndim
 
     @property
+    def stored_dims(self):
+        """Extents of the stored spectrum (x keeps n/2 + 1 columns in the half layout)."""
+        d = self.dims3
+        return d[:2] + (d[2] // 2 + 1,) if self.half else d
+
+    @property
+    def n_modes(self):
+        """Stored modes per species."""
+        return int(np.prod(self.stored_dims))
+
+    @property
     def n_blocks(self):
-        return (self.n // self.block) ** self.ndim
+        nb = self.n // self.block
+        if self.half:  # columns below n/2, then one block per (z, y) block row for n/2
+            rows = nb ** (self.ndim - 1)
+            return rows * (self.n // (2 * self.block) + 1)
+        return nb ** self.ndim
 
     @property
     def nspec(self):
@@ -218,7 +237,8 @@ class Desc:
                    | (SPDBA_FLAG_TRANSITION if self.transition else 0)
                    | (SPDBA_FLAG_REFRESH if self.refresh else 0)
                    | (SPDBA_FLAG_DYN_THRESHOLD if self.target_ratio else 0)
-                   | (SPDBA_FLAG_STATE_INDICATOR if self.state_indicator else 0))
+                   | (SPDBA_FLAG_STATE_INDICATOR if self.state_indicator else 0)
+                   | (SPDBA_FLAG_HALF_SPECTRUM if self.half else 0))
         d.reserved = 0
         d.threshold = float(self.tau)
         d.dx, d.dt = float(self.dx), float(self.dt)
@@ -303,7 +323,7 @@ class Plan:
         d = self.descs[i]
         want = self._cplx_dtype(i) if d.op == "nlse" else self._real_dtype(i)
         field = field.to(device="cuda", dtype=want).contiguous()
-        assert field.numel() == d.n_modes * d.nspec
+        assert field.numel() == d.n_points * d.nspec
         self._enter()
         _ck(load().spdba_set_field(self.h, i, ctypes.c_void_p(field.data_ptr())), "spdba_set_field")
         self.stream.synchronize()
@@ -311,7 +331,7 @@ class Plan:
     def get_field(self, i):
         d = self.descs[i]
         want = self._cplx_dtype(i) if d.op == "nlse" else self._real_dtype(i)
-        out = self.torch.empty(d.n_modes * d.nspec, dtype=want, device="cuda")
+        out = self.torch.empty(d.n_points * d.nspec, dtype=want, device="cuda")
         self._enter()
         _ck(load().spdba_get_field(self.h, i, ctypes.c_void_p(out.data_ptr())), "spdba_get_field")
         self.stream.synchronize()

@@ -14,7 +14,8 @@ OPMAP = {"ch": O.OP_CH, "gs": O.OP_GS, "nlse": O.OP_NLSE}
 def oracle_inst(d: S.Desc, full_now: int = 0) -> O.Inst:
     flags = ((O.FLAG_DENSE if d.dense else 0) | (O.FLAG_PIN_K0 if d.pin_k0 else 0)
              | (O.FLAG_TRANSITION if d.transition else 0) | (O.FLAG_REFRESH if d.refresh else 0)
-             | (O.FLAG_DYN_TAU if d.target_ratio else 0) | (O.FLAG_STATE if d.state_indicator else 0))
+             | (O.FLAG_DYN_TAU if d.target_ratio else 0) | (O.FLAG_STATE if d.state_indicator else 0)
+             | (O.FLAG_HALF if d.half else 0))
     return O.Inst(op=OPMAP[d.op], dims=d.dims3, block=d.block3, tau=d.tau, dx=d.dx, dt=d.dt,
                   p=tuple(d.params), flags=flags, refresh_period=d.refresh, full_steps=d.full_steps,
                   interval=d.control_interval, target_ratio=d.target_ratio, deadband=d.deadband,
@@ -31,10 +32,11 @@ def draw_apply_inputs(d: S.Desc, seed: int, idx: int, width_frac: float = 1 / 12
     cd = np.complex128 if d.dtype == "f64" else np.complex64
     shape = d.dims3[3 - d.ndim:]
     w = max(1.0, d.n * width_frac)
-    q = np.concatenate([inputs.shaped_spectrum(seed, 10 * idx + s, shape, w, floor=floor).ravel()
+    xs = d.stored_dims[2]  # half layout: the stored columns of the full spectrum
+    q = np.concatenate([inputs.shaped_spectrum(seed, 10 * idx + s, shape, w, floor=floor)[..., :xs].ravel()
                         for s in range(d.nspec)]).astype(cd)
     r = np.concatenate([inputs.shaped_spectrum(seed, 10 * idx + 5 + s, shape, 0.8 * w, floor=floor,
-                                               scale=3.0).ravel()
+                                               scale=3.0)[..., :xs].ravel()
                         for s in range(d.nspec)]).astype(cd)
     rng = inputs.rng_for(seed, 99, idx)
     k0 = rng.uniform(-1.0, 1.0, d.nspec) * d.n_modes

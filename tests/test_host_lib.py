@@ -85,6 +85,23 @@ def _good(**kw):
                 [c.block.__setitem__(a, 1) for a in (0, 1)], c.dims.__setitem__(2, 65536),
                 c.block.__setitem__(2, 8192), setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_TRANSITION)),
      spdba.SPDBA_EUNSUPPORTED),
+    # half-spectrum layout: real fields of two or three dimensions, x block edge
+    # dividing nx/2, no consistency control, LDS of the indicator
+    (lambda c: (setattr(c, "op", spdba.OPS["nlse"]), setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_HALF_SPECTRUM)),
+     spdba.SPDBA_EUNSUPPORTED),
+    (lambda c: (setattr(c, "ndim", 1), [c.dims.__setitem__(a, 1) for a in (0, 1)],
+                [c.block.__setitem__(a, 1) for a in (0, 1)], setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_HALF_SPECTRUM)),
+     spdba.SPDBA_EUNSUPPORTED),
+    (lambda c: (c.block.__setitem__(2, 32), setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_HALF_SPECTRUM)),
+     spdba.SPDBA_EUNSUPPORTED),  # 32 does not divide 16
+    (lambda c: setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_HALF_SPECTRUM | spdba.SPDBA_FLAG_TRANSITION),
+     spdba.SPDBA_EUNSUPPORTED),
+    (lambda c: (setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_HALF_SPECTRUM | spdba.SPDBA_FLAG_REFRESH),
+                setattr(c, "refresh_period", 5)), spdba.SPDBA_EUNSUPPORTED),
+    (lambda c: (setattr(c, "ndim", 2), c.dims.__setitem__(0, 1), c.block.__setitem__(0, 1),
+                c.dims.__setitem__(1, 8192), c.dims.__setitem__(2, 8192), c.block.__setitem__(1, 2),
+                c.block.__setitem__(2, 2), setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_HALF_SPECTRUM)),
+     spdba.SPDBA_EUNSUPPORTED),  # 2049 blocks per block row
 ])
 def test_invalid_descriptors_rejected_without_device(mutate, expect):
     c = _good().to_c()
