@@ -48,6 +48,8 @@ def parse():
                          "threshold controller, target non-frozen ratio 0.2)")
     ap.add_argument("--measure", choices=("increment", "state"), default=None,
                     help="activity measure of the timed sp-DBA runs (default: the workload's)")
+    ap.add_argument("--layout", choices=("full", "half"), default=None,
+                    help="stored spectrum of the real fields (default: the workload's)")
     ap.add_argument("--cpu-one-core", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
@@ -89,12 +91,12 @@ def indicator_bytes(cfg, descs):
     return tot
 
 
-def profiled_traffic(workload: str):
+def profiled_traffic(kernel: str, workload: str):
     """HBM bytes per indicator launch from the committed rocprofv3 PMC summary,
     or None when the kernel source changed since the counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"k_indicator_{workload}.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
     src = os.path.join(ROOT, "paper_2609_03922_amd", "csrc", "spdba_kernels.hip")
     if not os.path.exists(path):
         return None
@@ -118,6 +120,8 @@ def main():
         from paper_2609_03922_amd import spdba as S
 
         cfg = configs.BY_NAME[args.config]
+        if args.layout:
+            cfg = dict(cfg, layout=args.layout)
         descs, sizes = build_descs(cfg, S, inputs)
         print(json.dumps(oracle_baseline(cfg, descs, sizes, inputs, np, budget=8.0, one_core=False,
                                          measure=args.measure or cfg.get("measure", "increment"))))
@@ -157,10 +161,14 @@ def main():
     cfg = configs.BY_NAME[args.config]
     if "proposer" in cfg:
         return proposer_bench(args, cfg)
+    if args.layout:
+        cfg = dict(cfg, layout=args.layout)
+    layout = cfg.get("layout", "full")
     K = args.steps if args.steps is not None else min(cfg["steps"], 500)
     W = args.warmup
     descs, sizes = build_descs(cfg, S, inputs)
-    total_modes = sum(d.n_modes for d in descs)
+    total_points = sum(d.n_points for d in descs)  # grid points per step (the metric's unit)
+    total_modes = sum(d.n_modes for d in descs)    # stored modes
 
     from paper_2609_03922_amd import autotune
 
@@ -179,6 +187,9 @@ def main():
     # steps eager with per-stage HIP events for the breakdown and the roofline
     # consistency control (Supplementary S1.1, S1.3): the controller setting
     # of the control sweep, with an initial full-activation window of K/10 steps
+    if args.control and layout == "half":
+        print(json.dumps({"error": "consistency control runs on the full layout: add --layout full"}))
+        sys.exit(2)
     ctl = (dict(transition=True, target_ratio=0.2, control_interval=10, deadband=0.05,
                 full_steps=max(1, K // 10)) if args.control else {})
 
@@ -238,11 +249,14 @@ def main():
     launches = 2 if cfg["op"] == "nlse" else 1
     ind_s = s0["indicator_kernel_ms"] * 1e-3 / launches
     ach = ib / ind_s / 1e9
+    # half layout: one workgroup per block row; full layout: block rows wider
+    # than a wave row (1 KiB) take the wave-per-strip kernel
+    kname = ("k_indicator_h" if layout == "half" else
+             "k_indicator_wave" if all(d.block * (16 if d.dtype == "f64" else 8) > 1024 for d in descs)
+             else "k_indicator")
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(cfg["name"]),
-            # block rows wider than a wave row (1 KiB) take the wave-per-strip kernel
-            "kernel": ("k_indicator_wave" if all(d.block * (16 if d.dtype == "f64" else 8) > 1024 for d in descs)
-                       else "k_indicator"),
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(kname, cfg["name"]),
+            "kernel": kname,
             "launches_per_step": launches,
             "run": "increment measure, eager" if measure == "state" else "the timed workload, eager",
             "bytes_per_launch": ib, "avg_launch_us": round(ind_s * 1e6, 2),
@@ -287,7 +301,7 @@ def main():
     steps_per_s = K / T
     out = {
         "metric": METRIC,
-        "value": round(total_modes * K / T / 1e9, 4),
+        "value": round(total_points * K / T / 1e9, 4),
         "unit": "Gpts/s",
         "n_gpus": 1,
         "steps": K,
@@ -299,8 +313,9 @@ def main():
         "dtype": "f32" if descs[0].dtype == "f32" else "f64",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "grid": f"{cfg.get('n', 'batch')}^{cfg['ndim']}",
-                   "block": cfg["block"], "tau": cfg["tau"], "measure": measure, "instances": len(descs),
-                   "modes": total_modes, "parallelism": "single-gpu", "hip_graph": graph},
+                   "block": cfg["block"], "tau": cfg["tau"], "measure": measure, "layout": layout,
+                   "instances": len(descs), "grid_points": total_points, "stored_modes": total_modes,
+                   "parallelism": "single-gpu", "hip_graph": graph},
         "steps_per_s": round(steps_per_s, 3),
         "eager_steps_per_s": round(K / T_eager, 3),
         "active_fraction_last_step": round(active / nblocks, 4),
@@ -312,7 +327,7 @@ def main():
     if stage_ms is not None:
         upd_stage_ms = stage_ms["indicator"] + stage_ms["compaction"] + stage_ms["update"]
         out["stage_ms"] = {k: round(v, 4) for k, v in stage_ms.items()}
-        out["update_stage_gpts_s"] = round(total_modes / (upd_stage_ms * 1e-3) / 1e9, 3)
+        out["update_stage_gpts_s"] = round(total_points / (upd_stage_ms * 1e-3) / 1e9, 3)
         out["roofline"] = roof
     if dense is not None:
         out["dense"] = {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in dense.items()}
@@ -530,6 +545,8 @@ def control_sweep(cfg, K, run, timed, make, err, e_d, Td, s_est, np, torch, tau_
     """Error, non-frozen fraction and graph-replay speed of each control
     setting against the same FP64 truth; the fastest setting within the
     equal-error bar is reported against dense, with its eager stage times."""
+    if cfg.get("layout", "full") == "half":
+        return {"skipped": "consistency control runs on the full layout (bench.py --layout full)"}
     rows = []
     for name, tau, ctl in control_settings(cfg, K, tau_star):
         info = {}
@@ -744,15 +761,17 @@ def oracle_baseline(cfg, descs, sizes, inputs, np, budget=10.0, one_core=True, m
     d = descs[0]
     opmap = {"ch": O.OP_CH, "gs": O.OP_GS, "nlse": O.OP_NLSE}
     inst = O.Inst(op=opmap[d.op], dims=d.dims3, block=d.block3, tau=d.tau, dx=d.dx, dt=d.dt,
-                  p=tuple(d.params), flags=O.FLAG_PIN_K0 | (O.FLAG_STATE if measure == "state" else 0))
+                  p=tuple(d.params), flags=O.FLAG_PIN_K0 | (O.FLAG_STATE if measure == "state" else 0)
+                  | (O.FLAG_HALF if d.half else 0))
     n = sizes[0]
+    fwd = (lambda a: O.rfft(a)) if d.half else (lambda a: O.fft(a, -1))
     if cfg["op"] == "ch":
         ic = cfg["ic"]
         f = inputs.uniform_field(cfg["seed"], 0, (n,) * cfg["ndim"], ic["mean"], ic["half_width"])
-        st = O.fft(f, -1)
+        st = fwd(f)
     elif cfg["op"] == "gs":
         u, v = inputs.gs_patch_field(cfg["seed"], 0, n, dtype=np.float64)
-        st = np.concatenate([O.fft(u, -1).ravel(), O.fft(v, -1).ravel()])
+        st = np.concatenate([fwd(u).ravel(), fwd(v).ravel()])
     else:
         st = inputs.qam16_rrc_signal(cfg["seed"], 0, n).astype(np.complex128)
     # grow the sample until it takes about 10 s of CPU work
@@ -765,15 +784,16 @@ def oracle_baseline(cfg, descs, sizes, inputs, np, budget=10.0, one_core=True, m
             break
         steps *= 4 if elapsed < budget / 4 else 2
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    out = {"value": round(d.n_modes * steps / elapsed / 1e9, 6), "unit": "Gpts/s", "cores": threads,
+    out = {"value": round(d.n_points * steps / elapsed / 1e9, 6), "unit": "Gpts/s", "cores": threads,
            "kind": "oracle",
-           "sample": f"{steps} full FP64 steps of instance 0 ({n}^{cfg['ndim']}) of {cfg['name']}, "
-                     f"{elapsed:.1f} s"}
+           "sample": f"{steps} full FP64 steps of instance 0 ({n}^{cfg['ndim']}, "
+                     f"{'half' if d.half else 'full'} spectrum) of {cfg['name']}, {elapsed:.1f} s"}
     if one_core:
         env = dict(os.environ, OMP_NUM_THREADS="1")
         try:
             r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-one-core", "--config",
-                                cfg["name"], "--measure", measure], env=env, capture_output=True, text=True,
+                                cfg["name"], "--measure", measure, "--layout", "half" if d.half else "full"],
+                               env=env, capture_output=True, text=True,
                                timeout=180)
             one = json.loads([l for l in r.stdout.splitlines() if l.startswith("{")][-1])
             out["value_1core"] = one["value"]

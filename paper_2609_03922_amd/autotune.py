@@ -5,7 +5,8 @@ active update (strip walk: waves per workgroup and persistent workgroups per
 compute unit; block-list walk: workgroups per compute unit) and the dense
 update (threads per workgroup) with the library's per-stage HIP events, keeps the
 fastest, and caches the choice in a JSON file keyed by GPU architecture,
-operator, precision, block shape and the multiset of grid sizes.  Launch shape
+operator, precision, block shape, the multiset of grid sizes and the stored
+layout.  Launch shape
 never changes results (the reductions it touches are order-free maxima), so
 tuning is safe between runs.  The activation block shape is not tuned: it
 changes the masks.
@@ -32,7 +33,8 @@ STAGE_OF = {0: (2,), 1: (3, 4), 2: (4,), 4: (3, 4)}
 def cache_key(descs, arch: str) -> str:
     d = descs[0]
     sizes = ",".join(str(x) for x in sorted((x.n for x in descs), reverse=True))
-    return f"{arch}|{d.op}|{d.dtype}|nd{d.ndim}|b{d.block}|n[{sizes}]"
+    layout = "|half" if getattr(d, "half", False) else ""
+    return f"{arch}|{d.op}|{d.dtype}|nd{d.ndim}|b{d.block}|n[{sizes}]{layout}"
 
 
 def load_cache(path: str = CACHE_PATH) -> dict:

@@ -4,7 +4,10 @@ Each workload is named by what it is.  Operator parameter order follows the
 library's descriptor: CH (M, kappa); GS (Du, Dv, F, k); NLSE (beta2, gamma, alpha).
 ``measure`` is the activity measure of the timed sp-DBA runs: the candidate
 increment |dq|^2 where the workload prescribes it, else the state amplitude
-|q|^2 (the paper's own state-based measures).
+|q|^2 (the paper's own state-based measures).  ``layout`` is the stored
+spectrum: "half" (the non-redundant half of a real field's transform, columns
+0 .. n/2, Supplementary S1.2) or "full" (complex fields; the proposer
+workload, whose features read the full block grid).
 Sizes of batched workloads are drawn from the workload's seed by
 ``inputs.instance_sizes``.
 """
@@ -14,6 +17,7 @@ CH2D_128_F64 = dict(
     name="ch2d_128_f64",
     op="ch", dtype="f64", ndim=2, n=128, block=16, tau=1e-6,
     dx=1.0, dt=0.01, params=(1.0, 1.0), steps=2000, seed=1001, measure="increment",
+    layout="half",
     ic=dict(kind="uniform", mean=0.0, half_width=0.05),
 )
 
@@ -21,6 +25,7 @@ CH3D_256_F32 = dict(
     name="ch3d_256_f32",
     op="ch", dtype="f32", ndim=3, n=256, block=8, tau=1e-6,
     dx=1.0, dt=0.01, params=(1.0, 1.0), steps=500, seed=1002, measure="state",
+    layout="half",
     ic=dict(kind="uniform", mean=0.1, half_width=0.02),
 )
 
@@ -28,6 +33,7 @@ NLSE1D_BATCH48_F32 = dict(
     name="nlse1d_batch48_f32",
     op="nlse", dtype="f32", ndim=1, n_instances=48, log2_min=14, log2_max=20, block=1024,
     tau=1e-6, dx=15.625, dt=0.8, params=(-21.7, 1.3, 0.0), steps=100, seed=1003, measure="state",
+    layout="full",
     ic=dict(kind="qam16_rrc", sps=2, rolloff=0.1, power_w=1e-3),
 )
 
@@ -35,6 +41,7 @@ GS2D_BATCH32_F32 = dict(
     name="gs2d_batch32_f32",
     op="gs", dtype="f32", ndim=2, n_instances=32, sizes=(256, 512, 1024), block=32,
     tau=1e-6, dx=1.0, dt=1.0, params=(0.16, 0.08, 0.035, 0.060), steps=5000, seed=1004, measure="state",
+    layout="half",
     ic=dict(kind="gs_patches", patches=10, patch=8, u=0.5, v=0.25),
 )
 
@@ -42,6 +49,7 @@ CH3D_512_F32_PROPOSER = dict(
     name="ch3d_512_f32_proposer",
     op="ch", dtype="f32", ndim=3, n=512, block=8, tau=1e-6,
     dx=1.0, dt=0.01, params=(1.0, 1.0), steps=500, seed=1005, measure="increment",
+    layout="full",
     ic=dict(kind="uniform", mean=0.1, half_width=0.02),
     proposer=dict(K=10, audit_steps=3, train_n=256, train_seeds=tuple(range(2001, 2009))),
 )

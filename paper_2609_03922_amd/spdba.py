@@ -456,7 +456,8 @@ def desc_from_config(cfg: dict, n: int | None = None, **over) -> Desc:
     from . import inputs  # noqa: F401  (kept beside the configs)
 
     d = Desc(op=cfg["op"], dtype=cfg["dtype"], ndim=cfg["ndim"], n=n if n is not None else cfg["n"],
-             block=cfg["block"], tau=cfg["tau"], dx=cfg["dx"], dt=cfg["dt"], params=tuple(cfg["params"]))
+             block=cfg["block"], tau=cfg["tau"], dx=cfg["dx"], dt=cfg["dt"], params=tuple(cfg["params"]),
+             half=cfg.get("layout", "full") == "half")
     for k, v in over.items():
         setattr(d, k, v)
     return d
