@@ -476,10 +476,13 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     // memory order: larger grids first, original order within a size
     std::vector<int> order(n_inst);
     std::iota(order.begin(), order.end(), 0);
-    // stored modes per species (half layout: nx/2 + 1 columns per row)
-    auto Nof = [&](int i) {
-        return inst[i].dims[0] * inst[i].dims[1] * (p->half ? inst[i].dims[2] / 2 + 1 : inst[i].dims[2]);
+    // stored row pitch: half layout, nx/2 + 1 columns rounded up to 128 bytes
+    const int64_t pq = p->dbl ? 8 : 16;
+    auto pitch = [&](int i) {
+        return p->half ? ((inst[i].dims[2] / 2 + 1 + pq - 1) / pq) * pq : inst[i].dims[2];
     };
+    // stored values per species (with the half layout's padding columns)
+    auto Nof = [&](int i) { return inst[i].dims[0] * inst[i].dims[1] * pitch(i); };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return Nof(a) > Nof(b); });
     std::vector<int64_t> mem_off(n_inst);
     int64_t acc = 0;
@@ -522,7 +525,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
         I.nb = (int64_t)I.nbk[0] * I.nbk[1] * I.nbk[2];
         I.half = p->half ? 1 : 0;
         I.Nreal = x.dims[0] * x.dims[1] * x.dims[2];
-        I.xs = (int32_t)(p->half ? x.dims[2] / 2 + 1 : x.dims[2]);
+        I.xs = (int32_t)pitch(i);
         I.nbxm = p->half ? (int32_t)(x.dims[2] / (2 * x.block[2])) : I.nbk[2];
         I.nbm = (int64_t)I.nbk[0] * I.nbk[1] * I.nbxm;
         if (p->half) I.nb = I.nbm + (int64_t)I.nbk[0] * I.nbk[1];
@@ -541,12 +544,12 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
         I.lnbxm = lg(I.nbxm);
         p->max_slots = std::max(p->max_slots, I.b[0] * I.b[1] * (I.b[2] / V));
         // half layout: one indicator strip per (z, y) block row; tiles of TE
-        // reals for the nonlinear term (enough for the dense update's tiles of
-        // TE stored values as well)
+        // values, enough for the reals of the nonlinear term and for the
+        // stored values (padding included) of the dense update
         I.nstrips = p->half ? (int64_t)I.nbk[0] * I.nbk[1] : (int64_t)I.nbk[0] * I.nbk[1] * (I.nbk[2] / I.S);
         I.strip_off = strip;
         strip += I.nstrips;
-        I.ntiles = ((p->half ? I.Nreal : I.N) + TE - 1) / TE;
+        I.ntiles = ((p->half ? std::max(I.Nreal, I.N) : I.N) + TE - 1) / TE;
         I.tile_off = tile;
         tile += I.ntiles;
         I.nspec = p->nspec;
@@ -856,8 +859,12 @@ spdba_status spdba_set_spectrum(spdba_plan p, int32_t inst, const void *d_hat, c
     double *k0 = p->ctx.k0 + 2 * inst;
     TRY_HIP(launch_ctl_reset(p->ctx, inst, p->stream));
     p->ab_valid = false;
-    TRY_HIP(launch_copy_spectrum(p->ctx, p->dbl, inst, d_hat, state_ptr(p, I.off), n, I.k0path,
+    if (p->half)  // compact rows of nx/2 + 1 into the pitched rows
+        TRY_HIP(launch_copy_half(p->ctx, p->dbl, inst, d_hat, state_ptr(p, I.off), true, I.k0path,
                                  (I.k0path && !h_k0) ? k0 : nullptr, p->stream));
+    else
+        TRY_HIP(launch_copy_spectrum(p->ctx, p->dbl, inst, d_hat, state_ptr(p, I.off), n, I.k0path,
+                                     (I.k0path && !h_k0) ? k0 : nullptr, p->stream));
     if (I.k0path && h_k0) {
         TRY_HIP(hipMemcpyAsync(k0, h_k0, (size_t)p->nspec * sizeof(double), hipMemcpyHostToDevice,
                                p->stream));
@@ -870,8 +877,11 @@ spdba_status spdba_get_spectrum(spdba_plan p, int32_t inst, void *d_hat, double 
     if (!p || !d_hat || inst < 0 || inst >= p->n_inst) return SPDBA_EINVAL;
     if (!p->bound) return SPDBA_ESTATE;
     const InstDev &I = p->hinst[inst];
-    TRY_HIP(hipMemcpyAsync(d_hat, state_ptr(p, I.off), (size_t)(I.N * p->nspec) * p->esize,
-                           hipMemcpyDeviceToDevice, p->stream));
+    if (p->half)
+        TRY_HIP(launch_copy_half(p->ctx, p->dbl, inst, state_ptr(p, I.off), d_hat, false, 0, nullptr, p->stream));
+    else
+        TRY_HIP(hipMemcpyAsync(d_hat, state_ptr(p, I.off), (size_t)(I.N * p->nspec) * p->esize,
+                               hipMemcpyDeviceToDevice, p->stream));
     if (h_k0) {
         double tmp[2] = {0.0, 0.0};
         TRY_HIP(hipMemcpyAsync(tmp, p->ctx.k0 + 2 * inst, 2 * sizeof(double), hipMemcpyDeviceToHost,
@@ -931,12 +941,16 @@ spdba_status spdba_apply(spdba_plan p, const void *d_rhs_hat, const double *h_rh
         int64_t src = 0;
         for (int i = 0; i < p->n_inst; ++i) {
             const InstDev &I = p->hinst[i];
-            const int64_t n = I.N * p->nspec;
             const char *sp = static_cast<const char *>(d_rhs_hat) + src * p->esize;
-            TRY_HIP(launch_copy_spectrum(p->ctx, p->dbl, i, sp, rhs_ptr(p, I.off), n, 0,
-                                         (I.k0path && !h_rhs_k0) ? p->ctx.rhs_k0 + 2 * i : nullptr,
-                                         p->stream));
-            src += n;
+            double *rk0 = (I.k0path && !h_rhs_k0) ? p->ctx.rhs_k0 + 2 * i : nullptr;
+            if (p->half) {  // compact rows of nx/2 + 1
+                TRY_HIP(launch_copy_half(p->ctx, p->dbl, i, sp, rhs_ptr(p, I.off), true, 0, rk0, p->stream));
+                src += (int64_t)I.n[0] * I.n[1] * (I.n[2] / 2 + 1) * p->nspec;
+            } else {
+                const int64_t n = I.N * p->nspec;
+                TRY_HIP(launch_copy_spectrum(p->ctx, p->dbl, i, sp, rhs_ptr(p, I.off), n, 0, rk0, p->stream));
+                src += n;
+            }
         }
         if (h_rhs_k0 && !p->dbl) {
             std::vector<double> tmp((size_t)p->n_inst * 2, 0.0);

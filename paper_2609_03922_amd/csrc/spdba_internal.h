@@ -53,7 +53,10 @@ struct InstDev {
     // the blocks of the columns below nx/2 first (nbm of them, nbxm along x),
     // then one block per (z, y) block row for the column nx/2
     int32_t half;
-    int32_t xs;         // stored row length (nx in the full layout)
+    int32_t xs;         // stored row pitch: nx in the full layout; half: nx/2 + 1
+                        // rounded up to 128 bytes (the columns beyond nx/2 are
+                        // never read or written; rocFFT's passes across rows
+                        // then run on aligned lines)
     int32_t nbxm;       // blocks along x below the column nx/2
     int32_t lnbxm;      // log2 nbxm
     int64_t nbm;        // blocks of the columns below nx/2 (nb in the full layout)
@@ -162,6 +165,10 @@ hipError_t launch_scale_copy(bool dbl, const void *src, void *dst, int64_t n_com
                              hipStream_t s);
 hipError_t launch_copy_spectrum(const Ctx &c, bool dbl, int inst, const void *src, void *dst,
                                 int64_t n, int zero_slot0, double *k0_dst, hipStream_t s);
+// half layout: a compact spectrum (rows of nx/2 + 1) to the pitched stored layout
+// (to_pitched, optionally moving slot 0 of each species to k0_dst and zeroing it) or back
+hipError_t launch_copy_half(const Ctx &c, bool dbl, int inst, const void *src, void *dst, bool to_pitched,
+                            int zero_slot0, double *k0_dst, hipStream_t s);
 // probe helpers
 hipError_t launch_fill_pattern(void *buf, int64_t n_elems, bool dbl, hipStream_t s);
 hipError_t launch_check_pattern(const void *buf, int64_t n_elems, bool dbl, uint32_t *bad, hipStream_t s);

@@ -1701,8 +1701,8 @@ __global__ void __launch_bounds__(256) k_real_tile_sums(Ctx c, int ii, const T *
     }
 }
 
-// copy an instance spectrum src -> dst; optionally zero slot 0 of each species
-// after storing it (widened to FP64) in k0_dst[species]
+// copy an instance spectrum src -> dst; slot 0 of each species is stored
+// (widened to FP64) in k0_dst[species] when given, and zeroed with zero_slot0
 template <typename T>
 __global__ void k_copy_spectrum(Ctx c, int ii, const T *src, T *dst, int zero_slot0, double *k0_dst) {
     const InstDev &I = c.inst[ii];
@@ -1710,10 +1710,12 @@ __global__ void k_copy_spectrum(Ctx c, int ii, const T *src, T *dst, int zero_sl
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         T re = src[2 * i], im = src[2 * i + 1];
-        if (zero_slot0 && (i % I.N) == 0) {
+        if ((i % I.N) == 0) {
             if (k0_dst) k0_dst[i / I.N] = (double)re;
-            re = (T)0;
-            im = (T)0;
+            if (zero_slot0) {
+                re = (T)0;
+                im = (T)0;
+            }
         }
         dst[2 * i] = re;
         dst[2 * i + 1] = im;
@@ -1942,7 +1944,7 @@ __device__ __forceinline__ double half_mode(const Coef &K, T c0s, double m2, T q
 
 // Indicator on the half layout: one workgroup per (z, y) block row of one
 // instance.  Lanes take 64 consecutive columns below nx/2, the waves split
-// the rows (four in flight); each lane keeps the maximum of its column, the
+// the rows (several in flight); each lane keeps the maximum of its column, the
 // lanes of one block combine by shuffles, the waves in LDS (dynamic: waves x
 // half_nb doubles).  The column nx/2 is one value per row: there the lanes
 // take rows.  CH also sums the FP64 gradient energy of the state, each stored
@@ -1951,7 +1953,7 @@ template <typename T, int OP, bool SI>
 __global__ void __launch_bounds__(256) k_indicator_h(Ctx c) {
     extern __shared__ double hred[];  // [waves][half_nb]
     __shared__ double s_sum[4], s_max[4];
-    constexpr int U = 4;
+    constexpr int U = OP == OP_GS ? 4 : 8;  // rows in flight per wave (8-byte lanes)
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int NB = c.half_nb;
@@ -2087,9 +2089,13 @@ __global__ void __launch_bounds__(256) k_indicator_h(Ctx c) {
 }
 
 // Update of one listed block on the half layout (as update_block, one
-// complex value per lane; the column-nx/2 blocks are one column wide).
+// complex value per lane; the column-nx/2 blocks are one column wide).  Each
+// thread issues the loads of two slots before it computes either, so a block
+// of 512 values is one round trip for 256 threads.  red: two sets of per-wave
+// maxima used alternately (par), so one barrier per block suffices.
 template <typename T, int OP>
-__device__ __forceinline__ void update_block_h(const Ctx &c, uint32_t entry, double *red) {
+__device__ __forceinline__ void update_block_h(const Ctx &c, uint32_t entry, double (*red)[4], int par) {
+    constexpr int UB = 2;
     const int64_t gb = (int64_t)entry;
     const int ii = c.blk_inst[gb];
     const InstDev &I = c.inst[ii];
@@ -2122,52 +2128,63 @@ __device__ __forceinline__ void update_block_h(const Ctx &c, uint32_t entry, dou
     const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
     const bool ab = c.ab_inc;  // workgroup-uniform
     double amax = 0.0;
-    for (int s = threadIdx.x; s < slots; s += blockDim.x) {
-        const int r = s >> lbx, l = s & ((1 << lbx) - 1);
-        const int z = z0 + (r >> lb1), y = y0 + (r & b1m), x = x_blk + l;
-        const int64_t e = ((int64_t)((z << ln1) + y)) * xs + x;
-        const double mx = (double)sidx(x, n2);
-        const double m2 = __builtin_fma(mx, mx, sq_d(sidx(z, n0)) + sq_d(sidx(y, n1)));
-        T qr, qi, nr, ni, q2r = (T)0, q2i = (T)0, n2r, n2i;
-        ld1<T>(q0p + 2 * e, qr, qi);
-        ld1<T>(r0p + 2 * e, nr, ni);
-        if (OP == OP_GS) {
-            ld1<T>(q1p + 2 * e, q2r, q2i);
-            ld1<T>(r1p + 2 * e, n2r, n2i);
+    const int step = blockDim.x;
+    for (int s0 = threadIdx.x; s0 < slots; s0 += UB * step) {
+        T qr[UB], qi[UB], nr[UB], ni[UB], q2r[UB], q2i[UB], n2r[UB], n2i[UB];
+        int64_t e[UB];
+        double m2[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            const int s = s0 + u * step;
+            qr[u] = qi[u] = nr[u] = ni[u] = q2r[u] = q2i[u] = n2r[u] = n2i[u] = (T)0;
+            e[u] = -1;
+            if (s >= slots) continue;
+            const int r = s >> lbx, l = s & ((1 << lbx) - 1);
+            const int z = z0 + (r >> lb1), y = y0 + (r & b1m), x = x_blk + l;
+            e[u] = ((int64_t)((z << ln1) + y)) * xs + x;
+            const double mx = (double)sidx(x, n2);
+            m2[u] = __builtin_fma(mx, mx, sq_d(sidx(z, n0)) + sq_d(sidx(y, n1)));
+            ld1<T>(q0p + 2 * e[u], qr[u], qi[u]);
+            ld1<T>(r0p + 2 * e[u], nr[u], ni[u]);
+            if (OP == OP_GS) {
+                ld1<T>(q1p + 2 * e[u], q2r[u], q2i[u]);
+                ld1<T>(r1p + 2 * e[u], n2r[u], n2i[u]);
+            }
         }
-        T cr, ci, dr = (T)0, di = (T)0;
-        if (OP == OP_CH) {
-            T sc, f;
-            ch_coef<T>(K, m2, sc, f);
-            ch_cand<T>(sc, f, qr, qi, nr, ni, cr, ci);
-        } else {
-            T au, av;
-            gs_coef<T>(K, m2, au, av);
-            gs_cand<T>(dt, au, qr, qi, nr, ni, cr, ci);
-            gs_cand<T>(dt, av, q2r, q2i, n2r, n2i, dr, di);
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            if (e[u] < 0) continue;
+            T cr, ci, dr = (T)0, di = (T)0;
+            if (OP == OP_CH) {
+                T sc, f;
+                ch_coef<T>(K, m2[u], sc, f);
+                ch_cand<T>(sc, f, qr[u], qi[u], nr[u], ni[u], cr, ci);
+            } else {
+                T au, av;
+                gs_coef<T>(K, m2[u], au, av);
+                gs_cand<T>(dt, au, qr[u], qi[u], nr[u], ni[u], cr, ci);
+                gs_cand<T>(dt, av, q2r[u], q2i[u], n2r[u], n2i[u], dr, di);
+            }
+            if (k0_blk && e[u] == 0) cr = ci = dr = di = (T)0;  // the FP32 slot of k = 0 stays zero
+            if (ab) {  // the state measure of what is stored; k = 0 left out
+                double a = sq2((double)cr, (double)ci);
+                if (OP == OP_GS) a = a + sq2((double)dr, (double)di);
+                if (lb == 0 && e[u] == 0) a = 0.0;
+                amax = fmax(amax, a);
+            }
+            st1<T>(q0p + 2 * e[u], cr, ci);
+            if (OP == OP_GS) st1<T>(q1p + 2 * e[u], dr, di);
         }
-        if (k0_blk && s == 0) {  // the FP32 slot of k = 0 stays zero
-            cr = ci = dr = di = (T)0;
-        }
-        if (ab) {  // the state measure of what is stored; k = 0 left out
-            double a = sq2((double)cr, (double)ci);
-            if (OP == OP_GS) a = a + sq2((double)dr, (double)di);
-            if (lb == 0 && s == 0) a = 0.0;
-            amax = fmax(amax, a);
-        }
-        st1<T>(q0p + 2 * e, cr, ci);
-        if (OP == OP_GS) st1<T>(q1p + 2 * e, dr, di);
     }
     if (ab) {
         amax = wave_max(amax);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+        if ((threadIdx.x & 63) == 0) red[par][threadIdx.x >> 6] = amax;
         __syncthreads();
         if (threadIdx.x == 0) {
-            double m = red[0];
-            for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, red[k]);
+            double m = red[par][0];
+            for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, red[par][k]);
             c.a_next[gb] = m;
         }
-        __syncthreads();  // red is free for the next block
     }
     if (k0_blk && threadIdx.x == 0) {
         double tmp[2];
@@ -2180,13 +2197,14 @@ __device__ __forceinline__ void update_block_h(const Ctx &c, uint32_t entry, dou
 // persistent walk of the appended list, one segment per XCD (as k_update)
 template <typename T, int OP>
 __global__ void __launch_bounds__(256) k_update_h(Ctx c) {
-    __shared__ double red[4];
+    __shared__ double red[2][4];
     const uint32_t total = *c.count;
     const int P = gridDim.x;  // multiple of 8
     const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per = P >> 3;
     const uint32_t seg = (total + 7) / 8;
     const uint32_t lo = min(total, seg * xcd), hi = min(total, seg * (xcd + 1));
-    for (uint32_t e = lo + local; e < hi; e += per) update_block_h<T, OP>(c, c.worklist[e], red);
+    int par = 0;
+    for (uint32_t e = lo + local; e < hi; e += per, par ^= 1) update_block_h<T, OP>(c, c.worklist[e], red, par);
 }
 
 // Regular mode on the half layout: every stored mode, tiles of tile_elems
@@ -2218,6 +2236,15 @@ __global__ void __launch_bounds__(1024) k_dense_h(Ctx c) {
     for (int j = threadIdx.x; j < TE; j += blockDim.x) {
         const int64_t e = t0 + j;
         if (e >= N) break;
+        if (x > xh) {  // a padding column of the row pitch
+            x += dx;
+            row += drow;
+            if (x >= xs) {
+                x -= xs;
+                ++row;
+            }
+            continue;
+        }
         const int y = (int)(row & (n1 - 1));
         const int z = (int)(row >> ln1);
         const double mx = (double)sidx(x, n2);
@@ -2261,6 +2288,36 @@ __global__ void __launch_bounds__(1024) k_dense_h(Ctx c) {
     if (OP == OP_CH) {
         block_sum<1>(acc, lds);
         if (threadIdx.x == 0) c.dense_part[tile] = acc[0];
+    }
+}
+
+// compact half spectrum (nspec x nz*ny rows of nx/2 + 1) <-> pitched state layout
+template <typename T>
+__global__ void k_copy_half(Ctx c, int ii, const T *src, T *dst, int to_pitched, int zero_slot0, double *k0_dst) {
+    const InstDev &I = c.inst[ii];
+    const int64_t w = (I.n[2] >> 1) + 1;
+    const int64_t nc = (int64_t)I.n[0] * I.n[1] * w;  // compact values per species
+    const int64_t n = nc * I.nspec;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = i / nc, j = i - s * nc;
+        const int64_t row = j / w;
+        const int64_t pi = s * I.N + row * I.xs + (j - row * w);
+        if (to_pitched) {
+            T re = src[2 * i], im = src[2 * i + 1];
+            if (j == 0) {
+                if (k0_dst) k0_dst[s] = (double)re;
+                if (zero_slot0) {
+                    re = (T)0;
+                    im = (T)0;
+                }
+            }
+            dst[2 * pi] = re;
+            dst[2 * pi + 1] = im;
+        } else {
+            dst[2 * i] = src[2 * pi];
+            dst[2 * i + 1] = src[2 * pi + 1];
+        }
     }
 }
 
@@ -2512,6 +2569,14 @@ hipError_t launch_copy_spectrum(const Ctx &c, bool dbl, int inst, const void *sr
                                 int64_t n, int zero_slot0, double *k0_dst, hipStream_t s) {
     if (dbl) hipLaunchKernelGGL(k_copy_spectrum<double>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (const double *)src, (double *)dst, zero_slot0, k0_dst);
     else hipLaunchKernelGGL(k_copy_spectrum<float>, dim3(grid_for(n)), dim3(256), 0, s, c, inst, (const float *)src, (float *)dst, zero_slot0, k0_dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_half(const Ctx &c, bool dbl, int inst, const void *src, void *dst, bool to_pitched,
+                            int zero_slot0, double *k0_dst, hipStream_t s) {
+    const unsigned g = 4096;
+    if (dbl) hipLaunchKernelGGL(k_copy_half<double>, dim3(g), dim3(256), 0, s, c, inst, (const double *)src, (double *)dst, to_pitched ? 1 : 0, zero_slot0, k0_dst);
+    else hipLaunchKernelGGL(k_copy_half<float>, dim3(g), dim3(256), 0, s, c, inst, (const float *)src, (float *)dst, to_pitched ? 1 : 0, zero_slot0, k0_dst);
     return hipGetLastError();
 }
 

@@ -72,6 +72,8 @@ APPLY = [
     ([D("ch", "f64", 2, 64, 16, 0.0, dense=True)], 112),
     ([D("gs", "f32", 2, n, 16, 0.0, dense=True) for n in (64, 128)], 113),
     ([D("ch", "f32", 3, 64, 8, 0.0, dense=True)], 114),
+    ([D("ch", "f32", 2, 8, 2, 0.0, dense=True)], 119),             # row pitch beyond the grid
+    ([D("gs", "f32", 3, 8, 2, 0.1)], 120),
 ]
 
 
