@@ -111,6 +111,70 @@ def profiled_traffic(kernel: str, workload: str):
     return int(float(vals["traffic_bytes_per_launch"]))
 
 
+def modes_per_block(d, np):
+    """Stored modes of each block (half layout: the column-n/2 blocks are one column wide)."""
+    b = d.block3
+    full = b[0] * b[1] * b[2]
+    if not d.half:
+        return np.full(d.n_blocks, full, np.int64)
+    rows = (d.dims3[0] // b[0]) * (d.dims3[1] // b[1])
+    nbm = rows * (d.dims3[2] // (2 * b[2]))
+    return np.concatenate([np.full(nbm, full, np.int64), np.full(rows, b[0] * b[1], np.int64)])
+
+
+def kernel_rooflines(cfg, descs, measure, layout, stage_ms, s_ind, act_modes, act_blocks, torch):
+    """Per-kernel HBM rooflines of the timed workload.  Times: the eager run of
+    the same steps, HIP events on the plan's stream recorded right before and
+    after the nonlinear and update kernels (the stage events: they include one
+    launch gap), and the indicator's own dispatch stamps (for the kept state
+    measure, from an eager run with the increment measure).  Algorithmic bytes
+    per launch: nonlinear term, nspec x grid points x (read + write) in the
+    working precision (CH/GS real fields; NLSE complex); active update, the
+    stored modes of the blocks active in the run's last update x nspec x
+    (state read, right-hand side read, state write) + 12 bytes per active block
+    (list entry, kept measure); indicator, every stored mode's state and
+    right-hand side + 8 bytes per block.  The bench line's roofline is the
+    kernel of the timed step with the largest mean time."""
+    csz = 16 if descs[0].dtype == "f64" else 8
+    rsz = csz // 2
+    nspec = descs[0].nspec
+    launches = 2 if cfg["op"] == "nlse" else 1
+    if cfg["op"] == "nlse":
+        nl_bytes = sum(d.n_points * 2 * csz for d in descs)
+        upd_bytes = act_modes * 2 * csz + act_blocks * 4
+    else:
+        nl_bytes = sum(nspec * d.n_points * 2 * rsz for d in descs)
+        upd_bytes = act_modes * nspec * 3 * csz + act_blocks * 12
+    iname = ("k_indicator_h" if layout == "half" else
+             "k_indicator_wave" if all(d.block * (16 if d.dtype == "f64" else 8) > 1024 for d in descs)
+             else "k_indicator")
+    kn = {"nonlinear": ("k_nonlinear_h" if layout == "half" else "k_nonlinear", nl_bytes, stage_ms["nonlinear"], 1,
+                        "the timed steps, eager, stage events"),
+          "update": ("k_update_h" if layout == "half" else "k_update", upd_bytes, stage_ms["update"], launches,
+                     "the timed steps, eager, stage events"),
+          "indicator": (iname, indicator_bytes(cfg, descs), s_ind["indicator_kernel_ms"], launches,
+                        "increment measure, eager, dispatch stamps" if measure == "state"
+                        else "the timed steps, eager, dispatch stamps")}
+    kernels = {}
+    for role, (name, nbytes, ms, nl, run) in kn.items():
+        us = ms * 1e3 / nl
+        if us <= 0:
+            continue
+        ach = nbytes / (us * 1e-6) / 1e9
+        kernels[role] = {"kernel": name, "avg_launch_us": round(us, 2), "bytes_per_launch": int(nbytes),
+                         "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4), "run": run}
+    # the timed step's kernels (the indicator pass runs in it only without the kept measure)
+    timed = [r for r in kernels if r != "indicator" or measure != "state" or cfg["op"] == "nlse"]
+    role = max(timed, key=lambda r: kernels[r]["avg_launch_us"])
+    k = kernels[role]
+    roof = {"bound": "hbm", "achieved": k["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": k["frac"],
+            "traffic": profiled_traffic(k["kernel"], cfg["name"]), "kernel": k["kernel"], "role": role,
+            "launches_per_step": kn[role][3], "run": k["run"], "bytes_per_launch": k["bytes_per_launch"],
+            "avg_launch_us": k["avg_launch_us"], "active_blocks_last_update": int(act_blocks),
+            "copy_achievable_gbs": copy_peak(torch)}
+    return roof, kernels
+
+
 def main():
     args = parse()
     if args.cpu_one_core:  # child of the CPU-baseline leg: oracle only, no GPU
@@ -197,6 +261,8 @@ def main():
     # increment where it prescribes it, else the paper's state amplitude)
     measure = args.measure or cfg.get("measure", "increment")
 
+    mpb = [modes_per_block(d, np) for d in descs]
+
     def timed_run(dense_flag, graph, meas=None):
         m = dict(state_indicator=(meas or measure) == "state")
         dd, _ = build_descs(cfg, S, inputs, dense=dense_flag, timing=not graph, graph=graph,
@@ -235,33 +301,18 @@ def main():
     s0 = plan.stats(0)  # stage means over the last (up to 64) steps of the eager run
     names = ("fft", "nonlinear", "indicator", "compaction", "update", "step")
     stage_ms = {k: float(v) for k, v in zip(names, s0["stage_ms"])}
+    last_modes = sum(float(mpb[i][plan.active_mask(i) != 0].sum()) for i in range(len(descs)))
+    last_blocks = sum(plan.stats(i)["active_blocks"] for i in range(len(descs)))
+    s_ind = s0
     if measure == "state":
         # the kept state measure evaluates no indicator pass after the first
-        # step: the HBM roofline is taken on the pass that streams every mode,
-        # the increment indicator, in an eager run of the same steps
+        # step: the indicator's roofline is taken in an eager run of the same
+        # steps with the increment measure
         plan.destroy()
         plan, _, _ = timed_run(False, False, meas="increment")
-        s0 = plan.stats(0)
-    ib = indicator_bytes(cfg, descs)
-    # the indicator dispatch's own start/stop stamps (HIP events through the
-    # extension launch), so the figure matches a kernel trace; the stats sum
-    # the launches of a step (two linear half steps for NLSE)
-    launches = 2 if cfg["op"] == "nlse" else 1
-    ind_s = s0["indicator_kernel_ms"] * 1e-3 / launches
-    ach = ib / ind_s / 1e9
-    # half layout: one workgroup per block row; full layout: block rows wider
-    # than a wave row (1 KiB) take the wave-per-strip kernel
-    kname = ("k_indicator_h" if layout == "half" else
-             "k_indicator_wave" if all(d.block * (16 if d.dtype == "f64" else 8) > 1024 for d in descs)
-             else "k_indicator")
-    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(kname, cfg["name"]),
-            "kernel": kname,
-            "launches_per_step": launches,
-            "run": "increment measure, eager" if measure == "state" else "the timed workload, eager",
-            "bytes_per_launch": ib, "avg_launch_us": round(ind_s * 1e6, 2),
-            "copy_achievable_gbs": copy_peak(torch)}
+        s_ind = plan.stats(0)
     plan.destroy()
+    roof, kernels = kernel_rooflines(cfg, descs, measure, layout, stage_ms, s_ind, last_modes, last_blocks, torch)
 
     # ---- dense (Regular) run on the same input ----------------------------
     dense = None
@@ -329,6 +380,7 @@ def main():
         out["stage_ms"] = {k: round(v, 4) for k, v in stage_ms.items()}
         out["update_stage_gpts_s"] = round(total_points / (upd_stage_ms * 1e-3) / 1e9, 3)
         out["roofline"] = roof
+        out["kernels"] = kernels
     if dense is not None:
         out["dense"] = {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in dense.items()}
         out["speedup_steps_vs_dense"] = round(steps_per_s / dense["steps_per_s"], 4)

@@ -97,6 +97,7 @@ struct spdba_plan_s {
     static constexpr int kRing = 64;
     hipEvent_t ev[kRing][12] = {};
     hipEvent_t evk[kRing][4] = {};  // indicator dispatch start/stop, per half step
+    bool evk_set[kRing][2] = {};    // the pair was stamped by an indicator dispatch of that step
     bool have_events = false;
     int ring = 0;         // set used by the step being enqueued
     int ring_filled = 0;  // sets holding a complete step
@@ -293,6 +294,9 @@ void ring_advance(spdba_plan p) {
     }
 }
 
+// the coming update takes the state measure kept by the last one
+bool kept_measure(spdba_plan p) { return !p->dense && p->ab_inc && p->ab_valid && !p->d_skip; }
+
 // update stage: indicator + compaction + active update, or the dense update
 spdba_status update_stage(spdba_plan p, int ev_base) {
     const bool d = p->dbl;
@@ -303,14 +307,15 @@ spdba_status update_stage(spdba_plan p, int ev_base) {
         return SPDBA_OK;
     }
     hipEvent_t k0 = nullptr, k1 = nullptr;
+    const int hs = ev_base == 8 ? 1 : 0;  // second NLSE half step
     if (p->timing && p->have_events && !p->use_graph) {
-        const int h = ev_base == 8 ? 2 : 0;  // second NLSE half step
-        k0 = p->evk[p->ring][h];
-        k1 = p->evk[p->ring][h + 1];
+        k0 = p->evk[p->ring][2 * hs];
+        k1 = p->evk[p->ring][2 * hs + 1];
     }
     // state measure kept by the last update: only G (and the merge of the
     // stored blocks' measures) is left to do
-    const bool inc = p->ab_inc && p->ab_valid && !p->d_skip;
+    const bool inc = kept_measure(p);
+    if (k0) p->evk_set[p->ring][hs] = true;
     if (inc) TRY_HIP(launch_gmax(p->ctx, p->stream, k0, k1));
     else TRY_HIP(launch_indicator(p->ctx, d, p->ind_waves, p->stream, k0, k1));
     // the next update may continue incrementally only from a step without a
@@ -1151,16 +1156,18 @@ spdba_status spdba_stats(spdba_plan p, int32_t inst, spdba_stats_t *out) {
                 st[5] = el(0, 11);
             }
             for (int j = 0; j < 6; ++j) acc6[j] += st[j];
-            if (!p->last_dense) {
-                hipEvent_t *ek = p->evk[(p->ring - k + spdba_plan_s::kRing) % spdba_plan_s::kRing];
-                for (int h = 0; h < (p->op == OP_NLSE ? 2 : 1); ++h) {
-                    float ms = 0.f;
-                    if (hipEventElapsedTime(&ms, ek[2 * h], ek[2 * h + 1]) == hipSuccess) ind_k += ms;
-                }
-            }
+            const int slot = (p->ring - k + spdba_plan_s::kRing) % spdba_plan_s::kRing;
+            auto pair = [](hipEvent_t a, hipEvent_t b) {
+                float ms = 0.f;
+                return hipEventElapsedTime(&ms, a, b) == hipSuccess ? (double)ms : 0.0;
+            };
+            for (int h = 0; h < (p->op == OP_NLSE ? 2 : 1); ++h)
+                if (!p->last_dense && p->evk_set[slot][h]) ind_k += pair(p->evk[slot][2 * h], p->evk[slot][2 * h + 1]);
         }
         for (int j = 0; j < 6; ++j) out->stage_ms[j] = acc6[j] / nset;
         out->indicator_kernel_ms = ind_k / nset;
+        // a failed read above must not surface at the next launch check
+        (void)hipGetLastError();
     }
     out->input_preserving_fft = p->inv_preserving ? 1 : 0;
     out->graph_replay = p->graph != nullptr ? 1 : 0;
