@@ -5,9 +5,9 @@ library's descriptor: CH (M, kappa); GS (Du, Dv, F, k); NLSE (beta2, gamma, alph
 ``measure`` is the activity measure of the timed sp-DBA runs: the candidate
 increment |dq|^2 where the workload prescribes it, else the state amplitude
 |q|^2 (the paper's own state-based measures).  ``layout`` is the stored
-spectrum: "half" (the non-redundant half of a real field's transform, columns
-0 .. n/2, Supplementary S1.2) or "full" (complex fields; the proposer
-workload, whose features read the full block grid).
+spectrum of the timed runs: "full" (the natural c2c spectrum) or "half" (the
+non-redundant half of a real field's transform, columns 0 .. n/2,
+Supplementary S1.2; ``bench.py --layout half``).
 Sizes of batched workloads are drawn from the workload's seed by
 ``inputs.instance_sizes``.
 """
@@ -17,7 +17,7 @@ CH2D_128_F64 = dict(
     name="ch2d_128_f64",
     op="ch", dtype="f64", ndim=2, n=128, block=16, tau=1e-6,
     dx=1.0, dt=0.01, params=(1.0, 1.0), steps=2000, seed=1001, measure="increment",
-    layout="half",
+    layout="full",
     ic=dict(kind="uniform", mean=0.0, half_width=0.05),
 )
 
@@ -25,7 +25,7 @@ CH3D_256_F32 = dict(
     name="ch3d_256_f32",
     op="ch", dtype="f32", ndim=3, n=256, block=8, tau=1e-6,
     dx=1.0, dt=0.01, params=(1.0, 1.0), steps=500, seed=1002, measure="state",
-    layout="half",
+    layout="full",
     ic=dict(kind="uniform", mean=0.1, half_width=0.02),
 )
 
@@ -41,7 +41,7 @@ GS2D_BATCH32_F32 = dict(
     name="gs2d_batch32_f32",
     op="gs", dtype="f32", ndim=2, n_instances=32, sizes=(256, 512, 1024), block=32,
     tau=1e-6, dx=1.0, dt=1.0, params=(0.16, 0.08, 0.035, 0.060), steps=5000, seed=1004, measure="state",
-    layout="half",
+    layout="full",
     ic=dict(kind="gs_patches", patches=10, patch=8, u=0.5, v=0.25),
 )
 
