@@ -91,13 +91,30 @@ def indicator_bytes(cfg, descs):
     return tot
 
 
+def kernel_source_sha(src: str, functions) -> str:
+    """sha256 (16 hex digits) of the source text of the named device functions
+    (each from its template line to its closing brace), in the given order."""
+    import hashlib
+
+    parts = []
+    for name in functions:
+        i = src.index(f" {name}(")
+        j = src.rfind("\ntemplate", 0, i)
+        j = j + 1 if j >= 0 and src.count("\n", j, i) <= 2 else src.rfind("\n", 0, i) + 1
+        k = src.index("\n}\n", i)
+        parts.append(src[j:k + 3])
+    return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
+
+
 def profiled_traffic(kernel: str, workload: str):
-    """HBM bytes per indicator launch from the committed rocprofv3 PMC summary,
-    or None when the kernel source changed since the counters were taken."""
+    """HBM bytes per launch from the committed rocprofv3 PMC summary of the
+    kernel, or None when its source changed since the counters were taken
+    (the summary names the functions whose text it hashed; without that list
+    the whole kernel file is hashed)."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
-    src = os.path.join(ROOT, "paper_2609_03922_amd", "csrc", "spdba_kernels.hip")
+    src_path = os.path.join(ROOT, "paper_2609_03922_amd", "csrc", "spdba_kernels.hip")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -105,7 +122,14 @@ def profiled_traffic(kernel: str, workload: str):
         if ":" in line and not line.startswith(("|", "#", "`")):
             k, _, v = line.partition(":")
             vals[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    src = open(src_path).read()
+    try:
+        if "kernel_source_functions" in vals:
+            sha = kernel_source_sha(src, [f.strip() for f in vals["kernel_source_functions"].split(",")])
+        else:
+            sha = hashlib.sha256(src.encode()).hexdigest()[:16]
+    except ValueError:
+        return None
     if vals.get("kernel_source_sha256_16") != sha or "traffic_bytes_per_launch" not in vals:
         return None
     return int(float(vals["traffic_bytes_per_launch"]))
@@ -128,8 +152,8 @@ def kernel_rooflines(cfg, descs, measure, layout, stage_ms, s_ind, act_modes, ac
     after the nonlinear and update kernels (the stage events: they include one
     launch gap), and the indicator's own dispatch stamps (for the kept state
     measure, from an eager run with the increment measure).  Algorithmic bytes
-    per launch: nonlinear term, nspec x grid points x (read + write) in the
-    working precision (CH/GS real fields; NLSE complex); active update, the
+    per launch: nonlinear term, nspec x grid points x (read + write) of a
+    complex value (full layout, NLSE) or of a real one (half layout); active update, the
     stored modes of the blocks active in the run's last update x nspec x
     (state read, right-hand side read, state write) + 12 bytes per active block
     (list entry, kept measure); indicator, every stored mode's state and
@@ -142,8 +166,8 @@ def kernel_rooflines(cfg, descs, measure, layout, stage_ms, s_ind, act_modes, ac
     if cfg["op"] == "nlse":
         nl_bytes = sum(d.n_points * 2 * csz for d in descs)
         upd_bytes = act_modes * 2 * csz + act_blocks * 4
-    else:
-        nl_bytes = sum(nspec * d.n_points * 2 * rsz for d in descs)
+    else:  # real arrays on the half layout, the complex transform buffer on the full one
+        nl_bytes = sum(nspec * d.n_points * 2 * (rsz if layout == "half" else csz) for d in descs)
         upd_bytes = act_modes * nspec * 3 * csz + act_blocks * 12
     iname = ("k_indicator_h" if layout == "half" else
              "k_indicator_wave" if all(d.block * (16 if d.dtype == "f64" else 8) > 1024 for d in descs)
@@ -791,7 +815,7 @@ def proposer_bench(args, cfg):
                             "dense": results["dense"]["stage_ms_last64"]["update"]},
         "launch": (autotune.load_cache().get(autotune.cache_key([S.desc_from_config(cfg)], arch)) or {}).get("choice"),
         "roofline": {"bound": "hbm", "achieved": round(ib / ind_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ib / ind_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(cfg["name"]),
+                     "frac": round(ib / ind_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": profiled_traffic("k_indicator", cfg["name"]),
                      "kernel": "k_indicator (plain run, all blocks)", "bytes_per_launch": ib,
                      "avg_launch_us": round(ind_s * 1e6, 2)},
         "cpu_baseline": None,
