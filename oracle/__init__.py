@@ -25,6 +25,7 @@ FLAG_DENSE, FLAG_PIN_K0 = 1, 2
 FLAG_TRANSITION, FLAG_REFRESH, FLAG_DYN_TAU = 4, 8, 16  # consistency control (S1.1, S1.3)
 FLAG_STATE = 32  # state-amplitude activity measure (main text; S4.2; S5.3)
 FLAG_HALF = 64  # half-spectrum layout of a real field (S1.2)
+FLAG_ENERGY = 128  # with FLAG_STATE: block energy, the sum instead of the maximum (main text; S5.3)
 OK, EINVAL, ENONFINITE = 0, 1, 6
 
 

@@ -91,6 +91,8 @@ static int make_geom(const or_inst *d, geom_t *g) {
     g->ext = ext ? ext : 1;
     g->nspec = (d->op == OR_OP_GS) ? 2 : 1;
     if (!(d->tau >= 0.0) || !(d->dt > 0.0) || !(d->dx > 0.0)) return OR_EINVAL;
+    /* the block energy sums the state measure */
+    if ((d->flags & OR_FLAG_ENERGY) && !(d->flags & OR_FLAG_STATE)) return OR_EINVAL;
     g->half = (d->flags & OR_FLAG_HALF) != 0;
     g->Nreal = g->N;
     g->xs = g->n[2];
@@ -501,7 +503,8 @@ int or_apply_f64(const or_inst *d, double *q, const double *rhs, const uint8_t *
             mode_idx(&g, i, &iz, &iy, &ix);
             int64_t b = block_of(&g, iz, iy, ix);
             if (skip && skip[b] && !(pin && b == 0)) continue;
-            if (ak[i] > a_b[b]) a_b[b] = ak[i];
+            if (d->flags & OR_FLAG_ENERGY) a_b[b] += ak[i]; /* block energy */
+            else if (ak[i] > a_b[b]) a_b[b] = ak[i];
         }
     }
     double gmax = 0.0;
@@ -637,7 +640,8 @@ int or_apply_f32(const or_inst *d, float *q, const float *rhs, double *k0,
             mode_idx(&g, i, &iz, &iy, &ix);
             int64_t b = block_of(&g, iz, iy, ix);
             if (skip && skip[b] && !(pin && b == 0)) continue;
-            if (ak[i] > a_b[b]) a_b[b] = ak[i];
+            if (d->flags & OR_FLAG_ENERGY) a_b[b] += ak[i]; /* block energy */
+            else if (ak[i] > a_b[b]) a_b[b] = ak[i];
         }
     }
     double gmax = 0.0;

@@ -43,6 +43,11 @@
  * is or_c2r.  Requires nx >= 2 with the x block edge dividing nx/2; not
  * combined with OR_FLAG_TRANSITION. */
 #define OR_FLAG_HALF 64u
+/* block energy (the main text's XPFC indicator; the modal spectral power of
+ * S5.3 for NLSE): with OR_FLAG_STATE, a_b = sum over the block's modes of
+ * a(k) = sum over species of |q(k)|^2 (k = 0 left out) instead of the block
+ * maximum, accumulated in FP64 in ascending mode order */
+#define OR_FLAG_ENERGY 128u
 
 /* Errors returned by the oracle (0 = success). */
 #define OR_OK 0
