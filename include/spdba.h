@@ -120,6 +120,16 @@ enum {
                                           not with consistency control; the update
                                           walks the block list (variant 3 is ignored)
                                           (otherwise EUNSUPPORTED)                     */
+    SPDBA_FLAG_BLOCK_ENERGY = 1u << 9, /* with SPDBA_FLAG_STATE_INDICATOR (else EINVAL):
+                                          a_b = the block's FP64 sum of a(k), the
+                                          block energy of the main text (XPFC) and the
+                                          modal spectral power of S5.3, instead of the
+                                          block maximum; summed per lane over rows in
+                                          order, then over lanes and waves in a fixed
+                                          order (bit-reproducible run to run, equal to
+                                          other summation orders within rounding).
+                                          Every update evaluates it in full.  Not with
+                                          SPDBA_FLAG_HALF_SPECTRUM (EUNSUPPORTED)       */
     SPDBA_FLAG_DYN_THRESHOLD = 1u << 6 /* tau follows target_ratio: after every
                                           control_interval steps that are not full, the
                                           mean ratio r of non-frozen blocks (over the

@@ -160,8 +160,11 @@ spdba_status validate(const spdba_instance_desc *d, int32_t n, void *) {
         if (x.flags & ~uint32_t(SPDBA_FLAG_DENSE | SPDBA_FLAG_PIN_K0 | SPDBA_FLAG_GRAPH |
                                 SPDBA_FLAG_TIMING | SPDBA_FLAG_TRANSITION | SPDBA_FLAG_REFRESH |
                                 SPDBA_FLAG_DYN_THRESHOLD | SPDBA_FLAG_STATE_INDICATOR |
-                                SPDBA_FLAG_HALF_SPECTRUM))
+                                SPDBA_FLAG_HALF_SPECTRUM | SPDBA_FLAG_BLOCK_ENERGY))
             return SPDBA_EUNSUPPORTED;
+        // the block energy sums the state measure; the half layout's indicator keeps maxima only
+        if ((x.flags & SPDBA_FLAG_BLOCK_ENERGY) && !(x.flags & SPDBA_FLAG_STATE_INDICATOR)) return SPDBA_EINVAL;
+        if ((x.flags & SPDBA_FLAG_BLOCK_ENERGY) && (x.flags & SPDBA_FLAG_HALF_SPECTRUM)) return SPDBA_EUNSUPPORTED;
         if (x.flags & SPDBA_FLAG_HALF_SPECTRUM) {
             // real fields of two or three dimensions; the x block edge divides
             // nx/2 (the column nx/2 forms blocks of its own); no consistency
@@ -741,7 +744,10 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     // the state entering a CH or GS update is the state the last one stored:
     // its measure can be kept by the update kernel (NLSE: the Kerr step
     // changes every mode between the updates)
-    p->ab_inc = c.state_ind && p->op != OP_NLSE && !p->dense;
+    // (the block energy is a sum: the full pass computes it every update in
+    // one fixed order, so the update kernel does not keep it)
+    c.ab_sum = (p->desc[0].flags & SPDBA_FLAG_BLOCK_ENERGY) ? 1 : 0;
+    p->ab_inc = c.state_ind && !c.ab_sum && p->op != OP_NLSE && !p->dense;
     c.ab_inc = p->ab_inc ? 1 : 0;
     c.a_next = reinterpret_cast<double *>(p->d_work + p->w_anext);
     p->ab_valid = false;

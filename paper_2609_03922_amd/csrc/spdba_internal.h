@@ -122,6 +122,7 @@ struct Ctx {
     int32_t sig_bytes;         // LDS of the transition update: the tables, 2 B_max doubles
     int32_t half;              // half-spectrum layout
     int32_t half_nb;           // half: largest number of blocks of one (z, y) block row
+    int32_t ab_sum;            // state measure: a_b is the block's sum (block energy), not its maximum
     int64_t nb_total;
     int64_t n_strips;
     int64_t n_tiles;

@@ -551,7 +551,8 @@ __device__ __forceinline__ void indicator_rows(const Ctx &c, const InstDev &I, i
                 const bool k0s = v == 0 && u == 0 && k0_lane && it0 == 0;
                 a = k0s ? 0.0 : a;
                 bad |= !(a <= DBL_MAX);
-                amax = fmax(amax, a);
+                if (SI && c.ab_sum) amax = amax + a;  // block energy: the lane's sum, rows in order
+                else amax = fmax(amax, a);
                 if (want_eb) {
                     double e2 = sq2((double)qr[u][v], (double)qi[u][v]);
                     if (OP == OP_GS) e2 += sq2((double)q2r[u][v], (double)q2i[u][v]);
@@ -614,8 +615,13 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
         if (want_eb)
             for (int s = 0; s < I.nspec; ++s) ebs += c.k0[2 * ii + s] * c.k0[2 * ii + s];
     }
-    // per-block maximum over the lanes of the block, then over the waves
-    for (int off = 1; off < LB; off <<= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+    // per-block maximum (block energy: sum) over the lanes of the block, then
+    // over the waves in wave order
+    const bool esum_b = SI && c.ab_sum;
+    for (int off = 1; off < LB; off <<= 1) {
+        const double o = __shfl_xor(amax, off, 64);
+        amax = esum_b ? amax + o : fmax(amax, o);
+    }
     lds_max[w][lane] = amax;
     if (want_eb) {
         for (int off = 1; off < LB; off <<= 1) ebs += __shfl_xor(ebs, off, 64);
@@ -629,7 +635,7 @@ __global__ void __launch_bounds__(1024) k_indicator(Ctx c) {
     __syncthreads();
     if (w == 0) {
         double m = lds_max[0][lane];
-        for (int i = 1; i < nw; ++i) m = fmax(m, lds_max[i][lane]);
+        for (int i = 1; i < nw; ++i) m = esum_b ? m + lds_max[i][lane] : fmax(m, lds_max[i][lane]);
         const int nblk = chunks > 1 ? 1 : I.S;
         if (lane % LB == 0 && lane / LB < nblk) {
             const int bx = (sx << I.lS) + lane / LB;
@@ -702,7 +708,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             if (EB)
                 for (int sp = 0; sp < I.nspec; ++sp) ebs += c.k0[2 * ii + sp] * c.k0[2 * ii + sp];
         }
-        amax = wave_max(amax);
+        amax = (SI && c.ab_sum) ? wave_sum(amax) : wave_max(amax);  // block energy: the sum
         if (OP == OP_CH) esum = wave_sum(esum);
         if (EB) ebs = wave_sum(ebs);
         if (__any(bad) && lane == 0) atomicOr(c.nonfinite, 1u);

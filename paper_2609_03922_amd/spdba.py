@@ -25,6 +25,7 @@ SPDBA_FLAG_DENSE, SPDBA_FLAG_PIN_K0, SPDBA_FLAG_GRAPH, SPDBA_FLAG_TIMING = 1, 2,
 SPDBA_FLAG_TRANSITION, SPDBA_FLAG_REFRESH, SPDBA_FLAG_DYN_THRESHOLD = 16, 32, 64
 SPDBA_FLAG_STATE_INDICATOR = 128
 SPDBA_FLAG_HALF_SPECTRUM = 256
+SPDBA_FLAG_BLOCK_ENERGY = 512
 
 OPS = {"ch": SPDBA_OP_CAHN_HILLIARD, "gs": SPDBA_OP_GRAY_SCOTT, "nlse": SPDBA_OP_NLSE}
 DTYPES = {"f32": SPDBA_F32, "f64": SPDBA_F64}
@@ -187,6 +188,8 @@ class Desc:
     state_indicator: bool = False
     # half-spectrum layout of a real field (Supplementary S1.2)
     half: bool = False
+    # with state_indicator: block energy (the block's sum of |q|^2) instead of the maximum
+    block_energy: bool = False
 
     @property
     def dims3(self):
@@ -238,7 +241,8 @@ class Desc:
                    | (SPDBA_FLAG_REFRESH if self.refresh else 0)
                    | (SPDBA_FLAG_DYN_THRESHOLD if self.target_ratio else 0)
                    | (SPDBA_FLAG_STATE_INDICATOR if self.state_indicator else 0)
-                   | (SPDBA_FLAG_HALF_SPECTRUM if self.half else 0))
+                   | (SPDBA_FLAG_HALF_SPECTRUM if self.half else 0)
+                   | (SPDBA_FLAG_BLOCK_ENERGY if self.block_energy else 0))
         d.reserved = 0
         d.threshold = float(self.tau)
         d.dx, d.dt = float(self.dx), float(self.dt)

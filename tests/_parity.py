@@ -15,7 +15,7 @@ def oracle_inst(d: S.Desc, full_now: int = 0) -> O.Inst:
     flags = ((O.FLAG_DENSE if d.dense else 0) | (O.FLAG_PIN_K0 if d.pin_k0 else 0)
              | (O.FLAG_TRANSITION if d.transition else 0) | (O.FLAG_REFRESH if d.refresh else 0)
              | (O.FLAG_DYN_TAU if d.target_ratio else 0) | (O.FLAG_STATE if d.state_indicator else 0)
-             | (O.FLAG_HALF if d.half else 0))
+             | (O.FLAG_HALF if d.half else 0) | (O.FLAG_ENERGY if d.block_energy else 0))
     return O.Inst(op=OPMAP[d.op], dims=d.dims3, block=d.block3, tau=d.tau, dx=d.dx, dt=d.dt,
                   p=tuple(d.params), flags=flags, refresh_period=d.refresh, full_steps=d.full_steps,
                   interval=d.control_interval, target_ratio=d.target_ratio, deadband=d.deadband,

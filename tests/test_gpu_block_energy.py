@@ -1,0 +1,128 @@
+"""Block-energy measure (SPDBA_FLAG_BLOCK_ENERGY with the state measure) on the
+GPU against the oracle.
+
+The block energy is an FP64 sum whose order differs between the kernels
+(lane, then lanes, then waves) and the oracle (ascending modes), so a_b and G
+agree to rounding (relative 1e-12 for sums of non-negative terms), masks agree
+except at a documented near-tie (|a_b - fl(tau^2 G)| <= 1e-12 of the
+threshold in the oracle), and where the masks agree the updated coefficients
+are bit-exact.  Run to run the GPU sums are bit-identical.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from _parity import assert_bits_equal, draw_apply_inputs, k0path, oracle_apply, oracle_inst, rel_l2
+from paper_2609_03922_amd import inputs
+from paper_2609_03922_amd import spdba as S
+
+pytestmark = pytest.mark.gpu
+
+PAR = {"ch": (1.0, 1.0), "gs": (0.16, 0.08, 0.035, 0.060), "nlse": (-21.7, 1.3, 0.0)}
+DXT = {"ch": (1.0, 0.01), "gs": (1.0, 1.0), "nlse": (15.625, 0.8)}
+
+
+def D(op, dtype, ndim, n, block, tau, **kw):
+    dx, dt = DXT[op]
+    return S.Desc(op=op, dtype=dtype, ndim=ndim, n=n, block=block, tau=tau, dx=dx, dt=dt, params=PAR[op],
+                  state_indicator=True, block_energy=True, **kw)
+
+
+def compare(plan, i, d, ref, tag, q_in):
+    ab, G = plan.indicator(i)
+    rab = ref["a_b"]
+    assert np.all(np.abs(ab - rab) <= 1e-12 * rab), (tag, "a_b", np.max(np.abs(ab - rab) / np.maximum(rab, 1e-300)))
+    assert abs(G - ref["G"]) <= 1e-12 * ref["G"], (tag, G, ref["G"])
+    m, rm = plan.active_mask(i), ref["mask"]
+    bad = np.flatnonzero(m != rm)
+    thr = d.tau * d.tau * ref["G"]
+    assert np.all(np.abs(rab[bad] - thr) <= 1e-12 * thr), (tag, "mask", bad[:8])
+    hat, k0g = plan.get_spectrum(i)
+    hat = hat.cpu().numpy()
+    if bad.size == 0:
+        assert_bits_equal(hat, ref["q"], tag + " coefficients")
+        if k0path(d):
+            assert_bits_equal(k0g, ref["k0"], tag + " k0")
+    return bad.size
+
+
+CASES = [
+    ([D("ch", "f32", 3, 32, 8, 0.3)], 131),
+    ([D("ch", "f64", 2, 64, 16, 0.1)], 132),
+    ([D("ch", "f32", 3, 32, 4, 0.3, pin_k0=False)], 133),
+    ([D("gs", "f32", 2, n, 32, 0.2) for n in (128, 64, 256)], 134),
+    ([D("gs", "f64", 2, 64, 16, 0.2)], 135),
+    ([D("nlse", "f32", 1, n, 1024, 0.2) for n in (4096, 16384)], 136),  # one wave per block
+    ([D("nlse", "f64", 1, 4096, 256, 0.2)], 137),
+    ([D("ch", "f32", 1, 4096, 1024, 0.3)], 138),
+]
+
+
+@pytest.mark.parametrize("descs,seed", CASES, ids=[f"case{c[1]}" for c in CASES])
+def test_block_energy_apply_matches_oracle(descs, seed):
+    import torch
+
+    print(f"block-energy apply case {seed}", flush=True)
+    plan = S.Plan(descs)
+    ins = [draw_apply_inputs(d, seed, i, floor=1e-4) for i, d in enumerate(descs)]
+    for i, (d, (q, r, k0, rk0)) in enumerate(zip(descs, ins)):
+        plan.set_spectrum(i, torch.from_numpy(q), k0=k0 if k0path(d) else None)
+    rhs = rk = None
+    if descs[0].op != "nlse":
+        rhs = torch.from_numpy(np.concatenate([x[1] for x in ins]))
+        if k0path(descs[0]):
+            rk = np.concatenate([x[3] for x in ins])
+    plan.apply(rhs, rk)
+    ties, counts = 0, []
+    for i, (d, (q, r, k0, rk0)) in enumerate(zip(descs, ins)):
+        ref = oracle_apply(d, q, r, k0, rk0)
+        ties += compare(plan, i, d, ref, f"case {seed} inst {i}", q)
+        counts.append((ref["count"], d.n_blocks))
+    assert ties <= 1
+    assert any(0 < c < nb for c, nb in counts), counts
+    plan.destroy()
+
+
+def test_block_energy_is_bit_reproducible_run_to_run():
+    import torch
+
+    d = D("gs", "f32", 2, 128, 32, 0.2)
+    q, r, k0, rk0 = draw_apply_inputs(d, 139, 0, floor=1e-4)
+    out = []
+    for _ in range(2):
+        plan = S.Plan([d])
+        plan.set_spectrum(0, torch.from_numpy(q), k0=k0)
+        plan.apply(torch.from_numpy(r), rk0)
+        out.append(plan.indicator(0)[0])
+        plan.destroy()
+    assert_bits_equal(out[0], out[1], "a_b run to run")
+
+
+def test_block_energy_f64_trajectory():
+    import torch
+
+    n, steps, tau = 64, 40, 3e-2
+    d = D("ch", "f64", 2, n, 8, tau)
+    c0 = inputs.uniform_field(1301, 0, (n, n), 0.0, 0.05)
+    ref = O.step(oracle_inst(d), O.fft(c0, -1), steps, masks=True, ab=True)
+    plan = S.Plan([d])
+    plan.set_field(0, torch.from_numpy(c0.ravel()))
+    ties, seen = 0, set()
+    for st in range(steps):
+        plan.step(1)
+        m = plan.active_mask(0)
+        seen.add(int(m.sum()))
+        r = ref["masks"][st, 0]
+        if not np.array_equal(m, r):
+            ab = ref["ab"][st, 0]
+            thr = tau * tau * ab.max()
+            bad = np.flatnonzero(m != r)
+            assert np.all(np.abs(ab[bad] - thr) <= 1e-12 * thr), f"step {st}: mask mismatch at {bad[:8]}"
+            ties += bad.size
+    assert ties <= 2
+    got = plan.get_field(0).cpu().numpy()
+    want = O.fft(ref["state"].reshape(n, n), +1).real.ravel()
+    err = rel_l2(got, want)
+    print(f"block energy f64 trajectory: rel-L2 {err:.3e}, active counts {sorted(seen)[:6]}", flush=True)
+    assert err <= 1e-10 and min(seen) < d.n_blocks
+    plan.destroy()
