@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--control", action="store_true",
                     help="time the sp-DBA steps with consistency control (transition blocks and the "
                          "threshold controller, target non-frozen ratio 0.2)")
-    ap.add_argument("--measure", choices=("increment", "state"), default=None,
+    ap.add_argument("--measure", choices=("increment", "state", "energy"), default=None,
                     help="activity measure of the timed sp-DBA runs (default: the workload's)")
     ap.add_argument("--layout", choices=("full", "half"), default=None,
                     help="stored spectrum of the real fields (default: the workload's)")
@@ -79,14 +79,14 @@ def init_fields(plan, cfg, sizes, inputs, np, torch, ic_dtype=None):
             plan.set_field(i, torch.from_numpy(sig))
 
 
-def indicator_bytes(cfg, descs):
+def indicator_bytes(cfg, descs, state_only=False):
     """Algorithmic bytes of one indicator launch: every mode's state and
-    right-hand side (NLSE: state only) in the working precision, plus one FP64
-    a_b per block."""
+    right-hand side (NLSE, and the state measures: state only) in the working
+    precision, plus one FP64 a_b per block."""
     tot = 0
     for d in descs:
         esz = 16 if d.dtype == "f64" else 8
-        arrays = {"ch": 2, "gs": 4, "nlse": 1}[d.op]
+        arrays = ({"ch": 1, "gs": 2, "nlse": 1} if state_only else {"ch": 2, "gs": 4, "nlse": 1})[d.op]
         tot += d.n_modes * esz * arrays + 8 * d.n_blocks
     return tot
 
@@ -176,7 +176,8 @@ def kernel_rooflines(cfg, descs, measure, layout, stage_ms, s_ind, act_modes, ac
                         "the timed steps, eager, stage events"),
           "update": ("k_update_h" if layout == "half" else "k_update", upd_bytes, stage_ms["update"], launches,
                      "the timed steps, eager, stage events"),
-          "indicator": (iname, indicator_bytes(cfg, descs), s_ind["indicator_kernel_ms"], launches,
+          "indicator": (iname, indicator_bytes(cfg, descs, state_only=measure == "energy"),
+                        s_ind["indicator_kernel_ms"], launches,
                         "increment measure, eager, dispatch stamps" if measure == "state"
                         else "the timed steps, eager, dispatch stamps")}
     kernels = {}
@@ -288,7 +289,8 @@ def main():
     mpb = [modes_per_block(d, np) for d in descs]
 
     def timed_run(dense_flag, graph, meas=None):
-        m = dict(state_indicator=(meas or measure) == "state")
+        mm = meas or measure
+        m = dict(state_indicator=mm in ("state", "energy"), block_energy=mm == "energy")
         dd, _ = build_descs(cfg, S, inputs, dense=dense_flag, timing=not graph, graph=graph,
                             **({} if dense_flag else {**ctl, **m}))
         p = S.Plan(dd)
@@ -543,6 +545,8 @@ def equal_error(cfg, sizes, K, W, S, inputs, autotune, arch, np, torch,
     res.update({"spdba_steps_per_s_at_config_tau": K / T6, "speedup_steps_vs_dense_at_config_tau": Td / T6})
     res["control"] = control_sweep(cfg, K, run, timed, make, err, e_d, Td, s_est, np, torch, tau_star)
     res["state_indicator"] = state_sweep(cfg, K, run, timed, make, err, e_d, Td, s_est, np, torch)
+    if cfg.get("layout", "full") != "half":  # the half layout's indicator keeps block maxima only
+        res["block_energy"] = state_sweep(cfg, K, run, timed, make, err, e_d, Td, s_est, np, torch, energy=True)
     return res
 
 
@@ -559,11 +563,11 @@ def best_at_equal_error(eq):
     if cb:
         cands.append({"measure": "increment with control: " + cb["setting"], "tau": None,
                       "steps_per_s": cb["steps_per_s"], "speedup_vs_dense": cb["speedup_steps_vs_dense"]})
-    si = eq.get("state_indicator") or {}
-    if si.get("tau_star") is not None:
-        cands.append({"measure": "state amplitude", "tau": si["tau_star"],
-                      "steps_per_s": si["steps_per_s_at_tau_star"],
-                      "speedup_vs_dense": si["speedup_steps_vs_dense_at_equal_error"]})
+    for key, name in (("state_indicator", "state amplitude"), ("block_energy", "block energy")):
+        si = eq.get(key) or {}
+        if si.get("tau_star") is not None:
+            cands.append({"measure": name, "tau": si["tau_star"], "steps_per_s": si["steps_per_s_at_tau_star"],
+                          "speedup_vs_dense": si["speedup_steps_vs_dense_at_equal_error"]})
     if not cands:
         return None
     b = max(cands, key=lambda c: c["speedup_vs_dense"])
@@ -572,14 +576,16 @@ def best_at_equal_error(eq):
 
 
 def state_sweep(cfg, K, run, timed, make, err, e_d, Td, s_est, np, torch,
-                taus=(1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7)):
+                taus=(1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7), energy=False):
     """The state-amplitude activity measure (a(k) = sum over species of |q|^2,
-    k = 0 left out) against the same FP64 truth: threshold sweep, the largest
+    k = 0 left out; its block maximum, or with energy its block sum, the block
+    energy) against the same FP64 truth: threshold sweep, the largest
     threshold within the equal-error bar, its graph-replay speed against dense
     and its eager stage times."""
+    kw = dict(state_indicator=True, block_energy=energy)
     rows = []
     for tau in taus:
-        f, acts, _ = run("f32", tau, False, state_indicator=True)
+        f, acts, _ = run("f32", tau, False, **kw)
         am = float(np.mean(acts))
         rows.append({"tau": tau, "rel_l2": err(f), "active_fraction_mean": round(am, 4),
                      "active_fraction_last_step": round(acts[-1], 4), "s_estimate": s_est(am)})
@@ -587,8 +593,8 @@ def state_sweep(cfg, K, run, timed, make, err, e_d, Td, s_est, np, torch,
     out = {"sweep": rows, "tau_star": max(r["tau"] for r in ok) if ok else None}
     if ok:
         t = out["tau_star"]
-        Ts = timed(t, False, state_indicator=True)
-        p = make("f32", t, False, timing=True, state_indicator=True)
+        Ts = timed(t, False, **kw)
+        p = make("f32", t, False, timing=True, **kw)
         p.step(K)
         torch.cuda.synchronize()
         st = p.stats(0)
@@ -837,7 +843,8 @@ def oracle_baseline(cfg, descs, sizes, inputs, np, budget=10.0, one_core=True, m
     d = descs[0]
     opmap = {"ch": O.OP_CH, "gs": O.OP_GS, "nlse": O.OP_NLSE}
     inst = O.Inst(op=opmap[d.op], dims=d.dims3, block=d.block3, tau=d.tau, dx=d.dx, dt=d.dt,
-                  p=tuple(d.params), flags=O.FLAG_PIN_K0 | (O.FLAG_STATE if measure == "state" else 0)
+                  p=tuple(d.params), flags=O.FLAG_PIN_K0 | (O.FLAG_STATE if measure in ("state", "energy") else 0)
+                  | (O.FLAG_ENERGY if measure == "energy" else 0)
                   | (O.FLAG_HALF if d.half else 0))
     n = sizes[0]
     fwd = (lambda a: O.rfft(a)) if d.half else (lambda a: O.fft(a, -1))
