@@ -301,7 +301,8 @@ void ring_advance(spdba_plan p) {
 bool kept_measure(spdba_plan p) { return !p->dense && p->ab_inc && p->ab_valid && !p->d_skip; }
 
 // update stage: indicator + compaction + active update, or the dense update
-spdba_status update_stage(spdba_plan p, int ev_base) {
+// (ind_done: the state measure's full pass already ran at the step's start)
+spdba_status update_stage(spdba_plan p, int ev_base, bool ind_done = false) {
     const bool d = p->dbl;
     if (p->dense) {
         TRY_HIP(launch_dense(p->ctx, d, p->dense_threads, p->stream));
@@ -318,9 +319,11 @@ spdba_status update_stage(spdba_plan p, int ev_base) {
     // state measure kept by the last update: only G (and the merge of the
     // stored blocks' measures) is left to do
     const bool inc = kept_measure(p);
-    if (k0) p->evk_set[p->ring][hs] = true;
-    if (inc) TRY_HIP(launch_gmax(p->ctx, p->stream, k0, k1));
-    else TRY_HIP(launch_indicator(p->ctx, d, p->ind_waves, p->stream, k0, k1));
+    if (!ind_done) {
+        if (k0) p->evk_set[p->ring][hs] = true;
+        if (inc) TRY_HIP(launch_gmax(p->ctx, p->stream, k0, k1));
+        else TRY_HIP(launch_indicator(p->ctx, d, p->ind_waves, p->stream, k0, k1));
+    }
     // the next update may continue incrementally only from a step without a
     // skip set (skipped blocks report a_b = 0, not their measure)
     p->ab_valid = p->ab_inc && !p->d_skip;
@@ -369,6 +372,20 @@ spdba_status enqueue_step(spdba_plan p) {
     const bool d = p->dbl;
     if (p->op != OP_NLSE) {
         record(p, 0);
+        // the state measure's full pass reads only the state the last update
+        // stored: it runs first, before the transforms leave their output to
+        // be written back from the caches while it streams
+        const bool early = !p->dense && p->ctx.state_ind && !kept_measure(p);
+        if (early) {
+            hipEvent_t k0 = nullptr, k1 = nullptr;
+            if (p->timing && p->have_events && !p->use_graph) {
+                k0 = p->evk[p->ring][0];
+                k1 = p->evk[p->ring][1];
+                p->evk_set[p->ring][0] = true;
+            }
+            TRY_HIP(launch_indicator(p->ctx, d, p->ind_waves, p->stream, k0, k1));
+        }
+        record(p, 7);
         for (auto &g : p->groups) {
             if (p->half) TRY(inverse_half(p, g.inv_oop, g.off, 2 * g.off, g.N * g.count * p->nspec));
             else TRY(inverse_keep(p, g.inv_oop, g.inv_ip, g.off, g.N * g.count * p->nspec));
@@ -379,7 +396,7 @@ spdba_status enqueue_step(spdba_plan p) {
         for (auto &g : p->groups) TRY(exec_fft(p, g.fwd_oop, work_ptr(p, g.off), rhs_ptr(p, g.off)));
         if (p->op == OP_GS && !d) TRY_HIP(launch_k0_rhs(p->ctx, p->stream));
         record(p, 3);
-        TRY(update_stage(p, 4));
+        TRY(update_stage(p, 4, early));
         return SPDBA_OK;
     }
     // NLSE: linear half step, Kerr step, linear half step (all in place on the state)
@@ -1139,10 +1156,10 @@ spdba_status spdba_stats(spdba_plan p, int32_t inst, spdba_stats_t *out) {
             };
             double st[6] = {0, 0, 0, 0, 0, 0};
             if (p->op != OP_NLSE) {
-                st[0] = el(0, 1) + el(2, 3);
+                st[0] = el(7, 1) + el(2, 3);
                 st[1] = el(1, 2);
                 if (!p->last_dense) {
-                    st[2] = el(3, 4);
+                    st[2] = el(0, 7) + el(3, 4);  // a state-measure full pass runs first
                     st[3] = el(4, 5);
                     st[4] = el(5, 6);
                 } else {

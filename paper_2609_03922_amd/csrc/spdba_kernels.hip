@@ -462,7 +462,9 @@ __device__ __forceinline__ void indicator_rows(const Ctx &c, const InstDev &I, i
                                                bool want_eb, double &amax, double &esum, double &ebs,
                                                bool &bad, bool z_lane = false) {
     constexpr int V = CV<T>::V;
-    constexpr int U = OP == OP_GS ? 2 : 4;  // rows in flight per wave (GS: two species, half)
+    // rows in flight per wave (GS: two species, half; the state measure reads no
+    // right-hand side, so it keeps twice the rows in flight)
+    constexpr int U = (SI ? 2 : 1) * (OP == OP_GS ? 2 : 4);
     // every instance field the row loop needs, read once (fields first read
     // inside the predicated load block would be re-fetched row by row)
     const Geo g = Geo::of(I, sbz, sby);
