@@ -263,9 +263,15 @@ def main():
 
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     tuned = None
+    # activity measure of the timed sp-DBA runs: the workload's (the
+    # increment where it prescribes it, else the paper's state amplitude)
+    measure = args.measure or cfg.get("measure", "increment")
     if args.tune:
+        # tuned with the timed runs' measure (it decides which update variants apply)
+        tm = dict(state_indicator=measure in ("state", "energy"), block_energy=measure == "energy")
+
         def make_plan(dense):
-            dd, _ = build_descs(cfg, S, inputs, dense=dense, timing=True)
+            dd, _ = build_descs(cfg, S, inputs, dense=dense, timing=True, **({} if dense else tm))
             return S.Plan(dd)
         choice, timings = autotune.tune(make_plan, lambda p: init_fields(p, cfg, sizes, inputs, np, torch),
                                         arch=arch, warm=min(cfg["steps"], 500) // 2)
@@ -281,10 +287,6 @@ def main():
         sys.exit(2)
     ctl = (dict(transition=True, target_ratio=0.2, control_interval=10, deadband=0.05,
                 full_steps=max(1, K // 10)) if args.control else {})
-
-    # activity measure of the timed sp-DBA runs: the workload's (the
-    # increment where it prescribes it, else the paper's state amplitude)
-    measure = args.measure or cfg.get("measure", "increment")
 
     mpb = [modes_per_block(d, np) for d in descs]
 

@@ -2,11 +2,13 @@
 
 Times candidate launch shapes of the indicator (waves per workgroup), the
 active update (strip walk: waves per workgroup and persistent workgroups per
-compute unit; block-list walk: workgroups per compute unit) and the dense
+compute unit; block-list walks, one workgroup or one wave per entry:
+workgroups per compute unit) and the dense
 update (threads per workgroup) with the library's per-stage HIP events, keeps the
 fastest, and caches the choice in a JSON file keyed by GPU architecture,
-operator, precision, block shape, the multiset of grid sizes and the stored
-layout.  Launch shape
+operator, precision, block shape, the multiset of grid sizes, the stored
+layout and the measure (the kept state measure changes which update variants
+apply).  Launch shape
 never changes results (the reductions it touches are order-free maxima), so
 tuning is safe between runs.  The activation block shape is not tuned: it
 changes the masks.
@@ -34,7 +36,8 @@ def cache_key(descs, arch: str) -> str:
     d = descs[0]
     sizes = ",".join(str(x) for x in sorted((x.n for x in descs), reverse=True))
     layout = "|half" if getattr(d, "half", False) else ""
-    return f"{arch}|{d.op}|{d.dtype}|nd{d.ndim}|b{d.block}|n[{sizes}]{layout}"
+    measure = ("|energy" if getattr(d, "block_energy", False) else "|state") if getattr(d, "state_indicator", False) else ""
+    return f"{arch}|{d.op}|{d.dtype}|nd{d.ndim}|b{d.block}|n[{sizes}]{layout}{measure}"
 
 
 def load_cache(path: str = CACHE_PATH) -> dict:
@@ -106,11 +109,13 @@ def tune(make_plan, init_fields, steps: int = 20, arch: str = "gfx950", path: st
             ps, t_strip = sweep(plan, 1, fixed=((3, 1), (4, w4)), tag="strip ")
             p1, t_list = sweep(plan, 1, fixed=((3, 0),), tag="list ")
             p2, t_multi = sweep(plan, 1, fixed=((3, 2),), tag="list4 ")
-            best = min((t_strip, 1), (t_list, 0), (t_multi, 2))[1]
+            p3, t_wave = sweep(plan, 1, fixed=((3, 3),), tag="wave ")
+            best = min((t_strip, 1), (t_list, 0), (t_multi, 2), (t_wave, 3))[1]
             result[3] = best
             result[4] = w4
-            result[1] = {1: ps, 0: p1, 2: p2}[best]
-        key = cache_key(plan.descs, arch)
+            result[1] = {1: ps, 0: p1, 2: p2, 3: p3}[best]
+        if not dense:  # the sparse plan carries the measure the key names
+            key = cache_key(plan.descs, arch)
         plan.destroy()
     if path:
         cache = load_cache(path)

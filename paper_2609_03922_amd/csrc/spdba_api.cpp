@@ -86,9 +86,11 @@ struct spdba_plan_s {
     bool inv_preserving = true;
     // launch geometry
     int ind_waves = 4, nl_waves = 4, upd_per_cu = 4, dense_threads = 256, cu_count = 256;
-    int upd_mode = 1;      // 0: block-list walk, 1: strip walk, 2: block-list walk, 4 entries in flight
+    int upd_mode = 1;      // 0: block-list walk, 1: strip walk, 2: block-list walk, 4 entries in flight,
+                           // 3: block-list walk, one wave per entry
     int upd_waves = 4;     // strip walk: waves per workgroup
     int max_slots = 0;     // largest block in 16-byte lane slots
+    int min_slots = 0;     // smallest block in 16-byte lane slots
     bool list_stale = false;  // the ordered active list lags the mask
     // graph of one step
     hipGraphExec_t graph = nullptr;
@@ -358,8 +360,10 @@ spdba_status update_stage(spdba_plan p, int ev_base, bool ind_done = false) {
         p->list_stale = true;
         // a multiple of 8: the update splits its list into one segment per XCD
         const int grid = ((p->cu_count * p->upd_per_cu + 7) / 8) * 8;
-        // four entries in flight need blocks of at most one slot per thread
-        const int multi = (p->upd_mode == 2 && p->max_slots <= 256 && !p->ab_inc && !p->half) ? 1 : 0;
+        // four entries in flight need blocks of at most one slot per thread;
+        // one wave per entry needs blocks of at least one slot per lane
+        int multi = (p->upd_mode == 2 && p->max_slots <= 256 && !p->ab_inc && !p->half) ? 1 : 0;
+        if (p->upd_mode == 3 && p->min_slots >= 64 && !p->half) multi = 2;
         TRY_HIP(launch_update(p->ctx, d, grid, multi, p->stream));
     }
     record(p, ev_base + 2);
@@ -568,6 +572,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
         I.lchunks = lg(I.chunks);
         I.lnbxm = lg(I.nbxm);
         p->max_slots = std::max(p->max_slots, I.b[0] * I.b[1] * (I.b[2] / V));
+        p->min_slots = i == 0 ? I.b[0] * I.b[1] * (I.b[2] / V) : std::min(p->min_slots, I.b[0] * I.b[1] * (I.b[2] / V));
         // half layout: one indicator strip per (z, y) block row; tiles of TE
         // values, enough for the reals of the nonlinear term and for the
         // stored values (padding included) of the dense update
@@ -1204,7 +1209,7 @@ spdba_status spdba_set_launch(spdba_plan p, int32_t kernel, int32_t value) {
         case 0: if (!pow2_in(value, 1, 16)) return SPDBA_EINVAL; p->ind_waves = value; break;
         case 1: if (value < 1 || value > 64) return SPDBA_EINVAL; p->upd_per_cu = value; break;
         case 2: if (!pow2_in(value, 64, 1024)) return SPDBA_EINVAL; p->dense_threads = value; break;
-        case 3: if (value < 0 || value > 2) return SPDBA_EINVAL; p->upd_mode = value; break;
+        case 3: if (value < 0 || value > 3) return SPDBA_EINVAL; p->upd_mode = value; break;
         case 4: if (!pow2_in(value, 1, 16)) return SPDBA_EINVAL; p->upd_waves = value; break;
         default: return SPDBA_EINVAL;
     }

@@ -1413,6 +1413,136 @@ __global__ void __launch_bounds__(256) k_update_multi(Ctx c) {
     }
 }
 
+// Update of one listed block by one wave (the block-list walk, wave form):
+// the lanes take the block's 16-byte slots in chunks of UB x 64 and issue all
+// loads of a chunk before any store.  With the kept state measure the block
+// maximum is a wave reduction, so no workgroup barrier separates one list
+// entry from the next.  Blocks of at least 64 slots keep every lane busy.
+template <typename T, int OP>
+__device__ __forceinline__ void update_block_wave(const Ctx &c, uint32_t gb, int lane) {
+    constexpr int V = CV<T>::V, UB = 4;
+    const int ii = c.blk_inst[gb];
+    const InstDev &I = c.inst[ii];
+    const int64_t lb = (int64_t)gb - I.blk_off;
+    const int bx = (int)(lb & (I.nbk[2] - 1));
+    const int64_t t = lb >> I.lnbk[2];
+    const int by = (int)(t & (I.nbk[1] - 1));
+    const int bz = (int)(t >> I.lnbk[1]);
+    const int llpr = I.lb[2] - (V == 2 ? 1 : 0);  // log2 lanes per block row
+    const int slots = (I.b[0] * I.b[1]) << llpr;
+    const Geo g = Geo::of(I, bz, by);
+    const Coef K = Coef::of(I);
+    const int x_blk = bx << I.lb[2];
+    const bool k0_blk = I.k0path && lb == 0;
+    T *q0p = reinterpret_cast<T *>(c.state) + 2 * I.off;
+    const T *r0p = reinterpret_cast<const T *>(c.rhs) + 2 * I.off;
+    T *q1p = q0p + 2 * I.N;
+    const T *r1p = r0p + 2 * I.N;
+    const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
+    const T *htab = (OP == OP_NLSE && I.ht_off >= 0) ? reinterpret_cast<const T *>(c.htab) + 2 * I.ht_off : nullptr;
+    const bool ab = OP != OP_NLSE && c.ab_inc;  // wave-uniform
+    double amax = 0.0;
+    for (int s0 = 0; s0 < slots; s0 += 64 * UB) {
+        T qr[UB][V], qi[UB][V], nr[UB][V], ni[UB][V], q2r[UB][V], q2i[UB][V], n2r[UB][V], n2i[UB][V];
+        int64_t ex[UB];
+        int x0s[UB];
+        double myz[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            const int s = s0 + u * 64 + lane;
+            ex[u] = -1;
+            if (s >= slots) continue;
+            const int r = s >> llpr, l = s & ((1 << llpr) - 1);
+            const int z = g.z0 + (r >> g.lb1);
+            const int y = g.y0 + (r & g.b1m);
+            const int x0 = x_blk + l * V;
+            const int64_t e = ((((int64_t)z << g.ln1) + y) << g.ln2) + x0;
+            ex[u] = e;
+            x0s[u] = x0;
+            myz[u] = sq_d(sidx(z, g.n0)) + sq_d(sidx(y, g.n1));
+            CV<T>::ld(q0p + 2 * e, qr[u], qi[u]);
+            if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr[u], ni[u]);
+            else if (htab) nlse_tab_ld<T>(htab, x0, g.n2, nr[u], ni[u]);
+            if (OP == OP_GS) {
+                CV<T>::ld(q1p + 2 * e, q2r[u], q2i[u]);
+                CV<T>::ld(r1p + 2 * e, n2r[u], n2i[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            if (ex[u] < 0) continue;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const double mx = (double)sidx(x0s[u] + v, g.n2);
+                const double m2 = __builtin_fma(mx, mx, myz[u]);
+                T cr, ci, dr = (T)0, di = (T)0;
+                if (OP == OP_CH) {
+                    T sc, f;
+                    ch_coef<T>(K, m2, sc, f);
+                    ch_cand<T>(sc, f, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
+                } else if (OP == OP_GS) {
+                    T au, av;
+                    gs_coef<T>(K, m2, au, av);
+                    gs_cand<T>(dt, au, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
+                    gs_cand<T>(dt, av, q2r[u][v], q2i[u][v], n2r[u][v], n2i[u][v], dr, di);
+                } else {
+                    T hr = nr[u][v], hi = ni[u][v];
+                    if (!htab) nlse_coef<T>(K, m2, hr, hi);
+                    nlse_cand<T>(hr, hi, qr[u][v], qi[u][v], cr, ci);
+                }
+                qr[u][v] = cr;
+                qi[u][v] = ci;
+                if (OP == OP_GS) {
+                    q2r[u][v] = dr;
+                    q2i[u][v] = di;
+                }
+            }
+            const bool first = s0 == 0 && u == 0 && lane == 0;  // slot 0 holds k = 0 in block 0
+            if (k0_blk && first) {  // the FP32 slot of k = 0 stays zero (its value lives in FP64)
+                qr[u][0] = qi[u][0] = (T)0;
+                q2r[u][0] = q2i[u][0] = (T)0;
+            }
+            if (ab) {  // the state measure of what is stored; k = 0 left out
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    double a = sq2((double)qr[u][v], (double)qi[u][v]);
+                    if (OP == OP_GS) a = a + sq2((double)q2r[u][v], (double)q2i[u][v]);
+                    if (lb == 0 && first && v == 0) a = 0.0;
+                    amax = fmax(amax, a);
+                }
+            }
+            CV<T>::st(q0p + 2 * ex[u], qr[u], qi[u]);
+            if (OP == OP_GS) CV<T>::st(q1p + 2 * ex[u], q2r[u], q2i[u]);
+        }
+    }
+    if (ab) {
+        amax = wave_max(amax);
+        if (lane == 0) c.a_next[gb] = amax;
+    }
+    if (k0_blk && lane == 0) {
+        double tmp[2];
+        k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+        c.k0[2 * ii] = tmp[0];
+        if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
+    }
+}
+
+// persistent walk of the list, one wave per entry: the list is split into one
+// segment per XCD as in k_update, and the waves of a workgroup take
+// consecutive entries of their segment
+template <typename T, int OP>
+__global__ void __launch_bounds__(256) k_update_wave(Ctx c) {
+    const uint32_t total = *c.count;
+    const int P = gridDim.x;  // multiple of 8
+    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per = P >> 3;
+    const uint32_t wpg = blockDim.x >> 6, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const uint32_t seg = (total + 7) / 8;
+    const uint32_t lo = min(total, seg * xcd), hi = min(total, seg * (xcd + 1));
+    for (uint32_t e = lo + (uint32_t)local * wpg + w; e < hi; e += (uint32_t)per * wpg)
+        update_block_wave<T, OP>(c, c.worklist[e], lane);
+}
+
 // -------------------------------------------------------------------------
 // active update, strip variant: the indicator's traversal (one workgroup per
 // strip of S x-adjacent blocks, waves split the rows, 16 B per lane, 1 KiB per
@@ -2474,6 +2604,7 @@ static void upd_launch_op(const Ctx &c, int grid, int multi, bool tr, bool ctl, 
     if (ctl && tr)
         hipLaunchKernelGGL((k_update<T, OP, true, true>), dim3(grid), dim3(256), (size_t)c.sig_bytes, s, c);
     else if (ctl) hipLaunchKernelGGL((k_update<T, OP, false, true>), dim3(grid), dim3(256), 0, s, c);
+    else if (multi == 2) hipLaunchKernelGGL((k_update_wave<T, OP>), dim3(grid), dim3(256), 0, s, c);
     else if (multi) hipLaunchKernelGGL((k_update_multi<T, OP, 4>), dim3(grid), dim3(256), 0, s, c);
     else hipLaunchKernelGGL((k_update<T, OP, false, false>), dim3(grid), dim3(256), 0, s, c);
 }

@@ -1,0 +1,58 @@
+"""Host logic of the launch autotuner, on the CPU with a stand-in plan: the
+cache key names the measure and the layout (the kept state measure changes
+which update variants apply), the key of a tuning comes from the sparse plan,
+and the fastest update variant and its grid are the ones kept."""
+from paper_2609_03922_amd import autotune as A
+from paper_2609_03922_amd import spdba as S
+
+
+def _desc(**kw):
+    return S.Desc(op="ch", dtype="f32", ndim=3, n=64, block=8, tau=1e-6, dx=1.0, dt=0.01, params=(1.0, 1.0), **kw)
+
+
+def test_cache_key_names_measure_and_layout():
+    keys = {A.cache_key([_desc(**kw)], "gfx950") for kw in
+            ({}, {"state_indicator": True}, {"state_indicator": True, "block_energy": True}, {"half": True})}
+    assert len(keys) == 4
+    assert A.cache_key([_desc(state_indicator=True)], "gfx950").endswith("|state")
+    assert A.cache_key([_desc()], "gfx950") == "gfx950|ch|f32|nd3|b8|n[64]"
+
+
+class FakePlan:
+    """Stage times from a table: update stages (3, 4) by (variant, per-CU), the
+    indicator (2) by its waves, the dense update (4) by its threads."""
+
+    def __init__(self, descs, dense):
+        self.descs, self.dense, self.launch = descs, dense, {}
+
+    def set_launch(self, k, v):
+        self.launch[k] = v
+
+    def step(self, n):
+        pass
+
+    def stats(self, i):
+        st = [0.0] * 5
+        if self.dense:
+            st[4] = 1.0 / self.launch.get(2, 256)
+        else:
+            st[2] = 1.0 + self.launch.get(0, 4)
+            v, g = self.launch.get(3, 1), self.launch.get(1, 4)
+            st[3] = 0.1
+            st[4] = {0: 5.0, 1: 6.0, 2: 5.5, 3: 4.0}[v] + abs(g - (8 if v == 3 else 4)) * 0.1
+        return {"stage_ms": st}
+
+    def destroy(self):
+        pass
+
+
+def test_tune_keys_the_sparse_plan_and_keeps_the_fastest_variant(tmp_path):
+    sparse = [_desc(state_indicator=True)]
+    path = str(tmp_path / "cache.json")
+    res, timings = A.tune(lambda dense: FakePlan([_desc()] if dense else sparse, dense), lambda p: None,
+                          steps=1, path=path)
+    assert res[3] == 3 and res[1] == 8 and res[0] == 1 and res[2] == 1024
+    assert "wave 1:8" in timings and "list4 1:4" in timings
+    cache = A.load_cache(path)
+    assert list(cache) == [A.cache_key(sparse, "gfx950")]
+    assert cache[A.cache_key(sparse, "gfx950")]["choice"]["3"] == 3

@@ -84,6 +84,13 @@ SEQ = [
 ]
 
 
+@pytest.mark.parametrize("descs,seed", SEQ[:6], ids=[f"seq{c[1]}" for c in SEQ[:6]])
+def test_state_measure_update_sequence_wave_walk(descs, seed):
+    # one wave per list entry: the kept measure is a wave reduction
+    print(f"state-measure sequence {seed}, wave walk", flush=True)
+    run_sequence(descs, seed, variant=3)
+
+
 @pytest.mark.parametrize("descs,seed", SEQ, ids=[f"seq{c[1]}" for c in SEQ])
 def test_state_measure_update_sequence_bit_exact(descs, seed):
     print(f"state-measure sequence {seed}: {[(d.op, d.dtype, d.n, d.block) for d in descs]}", flush=True)
@@ -92,11 +99,11 @@ def test_state_measure_update_sequence_bit_exact(descs, seed):
     assert any(0 < c < d.n_blocks for c, d in zip(counts, descs * len(counts)))
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_state_measure_sequence_other_variants_and_reload(variant):
     # the strip walk and the four-in-flight walk requested: the plan keeps the
-    # measure through the block-list walk; a reload in the middle forces a
-    # full evaluation
+    # measure through the block-list walk; the wave walk keeps it itself; a
+    # reload in the middle forces a full evaluation
     run_sequence([D("ch", "f32", 3, 32, 8, 1e-2)], 68, n_apply=5, variant=variant, reload_at=3)
 
 

@@ -236,15 +236,16 @@ def test_determinism_and_batched_equals_singles():
 
 def test_stage_timing_and_update_variants_agree():
     """With timing on, the indicator's dispatch-stamped time is positive and
-    fits inside its event-bracketed stage; the three update variants (and the
-    strip walk at another persistent grid size) produce the same bits step
+    fits inside its event-bracketed stage; the four update variants (and the
+    strip walk at another persistent grid size, the wave walk at two grid
+    sizes) produce the same bits step
     after step.  Grids with more strips than workgroups are covered by the
     full-size parity cases."""
     import torch
 
     f = inputs.uniform_field(1002, 9, (64, 64, 64), 0.1, 0.02, dtype=np.float32).ravel()
     plans = []
-    for variant, per_cu in ((0, 4), (1, 4), (2, 4), (1, 1)):
+    for variant, per_cu in ((0, 4), (1, 4), (2, 4), (1, 1), (3, 4), (3, 16)):
         p = S.Plan([ch_desc("f32", 3, 64, 8, 1e-5, timing=True)])
         p.set_launch(3, variant)
         p.set_launch(1, per_cu)
