@@ -118,8 +118,8 @@ enum {
                                           order over (z, y).  The x block edge must
                                           divide nx/2 and nx/(2 block[2]) + 1 <= 2048;
                                           not with consistency control; the update
-                                          walks the block list (variant 3 is ignored)
-                                          (otherwise EUNSUPPORTED)                     */
+                                          walks the block list whatever update variant
+                                          is set (otherwise EUNSUPPORTED)               */
     SPDBA_FLAG_BLOCK_ENERGY = 1u << 9, /* with SPDBA_FLAG_STATE_INDICATOR (else EINVAL):
                                           a_b = the block's FP64 sum of a(k), the
                                           block energy of the main text (XPFC) and the
@@ -127,9 +127,14 @@ enum {
                                           block maximum; summed per lane over rows in
                                           order, then over lanes and waves in a fixed
                                           order (bit-reproducible run to run, equal to
-                                          other summation orders within rounding).
-                                          Every update evaluates it in full.  Not with
-                                          SPDBA_FLAG_HALF_SPECTRUM (EUNSUPPORTED)       */
+                                          other summation orders within rounding).  For
+                                          CH and GS the update kernel keeps it, as it
+                                          keeps the maximum: the blocks it stores get
+                                          their sum (per lane over its slots, then over
+                                          lanes and waves in a fixed order), the others
+                                          keep theirs, and a step needs no full pass.
+                                          Not with SPDBA_FLAG_HALF_SPECTRUM
+                                          (EUNSUPPORTED)                               */
     SPDBA_FLAG_DYN_THRESHOLD = 1u << 6 /* tau follows target_ratio: after every
                                           control_interval steps that are not full, the
                                           mean ratio r of non-frozen blocks (over the

@@ -769,7 +769,7 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     // (the block energy is a sum: the full pass computes it every update in
     // one fixed order, so the update kernel does not keep it)
     c.ab_sum = (p->desc[0].flags & SPDBA_FLAG_BLOCK_ENERGY) ? 1 : 0;
-    p->ab_inc = c.state_ind && !c.ab_sum && p->op != OP_NLSE && !p->dense;
+    p->ab_inc = c.state_ind && p->op != OP_NLSE && !p->dense;
     c.ab_inc = p->ab_inc ? 1 : 0;
     c.a_next = reinterpret_cast<double *>(p->d_work + p->w_anext);
     p->ab_valid = false;

@@ -1183,6 +1183,7 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
     const uint32_t faces = (entry >> 25) & 63u;
     const int b0 = I.b[0], b1 = I.b[1], b2 = I.b[2];
     const bool ab = OP != OP_NLSE && c.ab_inc;  // workgroup-uniform
+    const bool esum = c.ab_sum;                  // block energy: the sum, else the maximum
     double amax = 0.0;
     for (int s = threadIdx.x; s < slots; s += blockDim.x) {
         const int r = s >> llpr, l = s & ((1 << llpr) - 1);
@@ -1245,19 +1246,19 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
                 double a = sq2((double)qr[v], (double)qi[v]);
                 if (OP == OP_GS) a = a + sq2((double)q2r[v], (double)q2i[v]);
                 if (lb == 0 && s == 0 && v == 0) a = 0.0;
-                amax = fmax(amax, a);
+                amax = esum ? amax + a : fmax(amax, a);
             }
         }
         CV<T>::st(q0p + 2 * e, qr, qi);
         if (OP == OP_GS) CV<T>::st(q1p + 2 * e, q2r, q2i);
     }
-    if (ab) {
-        amax = wave_max(amax);
+    if (ab) {  // block energy: lanes, then waves in order
+        amax = esum ? wave_sum(amax) : wave_max(amax);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
         __syncthreads();
         if (threadIdx.x == 0) {
             double m = red[0];
-            for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, red[k]);
+            for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = esum ? m + red[k] : fmax(m, red[k]);
             c.a_next[gb] = m;
         }
         __syncthreads();  // red is free for the next block
@@ -1417,7 +1418,9 @@ __global__ void __launch_bounds__(256) k_update_multi(Ctx c) {
 // the lanes take the block's 16-byte slots in chunks of UB x 64 and issue all
 // loads of a chunk before any store.  With the kept state measure the block
 // maximum is a wave reduction, so no workgroup barrier separates one list
-// entry from the next.  Blocks of at least 64 slots keep every lane busy.
+// entry from the next (the block energy: the lanes' sums over their slots in
+// order, then a fixed butterfly over the lanes).  Blocks of at least 64 slots
+// keep every lane busy.
 template <typename T, int OP>
 __device__ __forceinline__ void update_block_wave(const Ctx &c, uint32_t gb, int lane) {
     constexpr int V = CV<T>::V, UB = 4;
@@ -1441,6 +1444,7 @@ __device__ __forceinline__ void update_block_wave(const Ctx &c, uint32_t gb, int
     const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
     const T *htab = (OP == OP_NLSE && I.ht_off >= 0) ? reinterpret_cast<const T *>(c.htab) + 2 * I.ht_off : nullptr;
     const bool ab = OP != OP_NLSE && c.ab_inc;  // wave-uniform
+    const bool esum = c.ab_sum;                  // block energy: the sum, else the maximum
     double amax = 0.0;
     for (int s0 = 0; s0 < slots; s0 += 64 * UB) {
         T qr[UB][V], qi[UB][V], nr[UB][V], ni[UB][V], q2r[UB][V], q2i[UB][V], n2r[UB][V], n2i[UB][V];
@@ -1508,7 +1512,7 @@ __device__ __forceinline__ void update_block_wave(const Ctx &c, uint32_t gb, int
                     double a = sq2((double)qr[u][v], (double)qi[u][v]);
                     if (OP == OP_GS) a = a + sq2((double)q2r[u][v], (double)q2i[u][v]);
                     if (lb == 0 && first && v == 0) a = 0.0;
-                    amax = fmax(amax, a);
+                    amax = esum ? amax + a : fmax(amax, a);
                 }
             }
             CV<T>::st(q0p + 2 * ex[u], qr[u], qi[u]);
@@ -1516,7 +1520,7 @@ __device__ __forceinline__ void update_block_wave(const Ctx &c, uint32_t gb, int
         }
     }
     if (ab) {
-        amax = wave_max(amax);
+        amax = esum ? wave_sum(amax) : wave_max(amax);
         if (lane == 0) c.a_next[gb] = amax;
     }
     if (k0_blk && lane == 0) {
