@@ -111,3 +111,11 @@ def shaped_spectrum(seed: int, stream: int, dims, width: float, floor: float = 1
         dist2 = dist2 + (d.reshape(sh)) ** 2
     amp = np.exp(-dist2 / (2.0 * width * width)) + floor
     return (scale * amp * g).astype(dtype)
+
+
+def perturbed_components(seed: int, M: int, dims, base: float, amp: float, dtype=np.float64) -> np.ndarray:
+    """M real fields of shape dims: base + a uniform perturbation in [-amp, amp)
+    per point and component (a nearly homogeneous start with random
+    perturbation), shape (M, *dims)."""
+    r = rng_for(seed, 7, M)
+    return (base + r.uniform(-amp, amp, (M, *dims))).astype(dtype)
