@@ -478,8 +478,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     TRY_HIP(hipGetDevice(&dev));
     hipDeviceProp_t prop;
     TRY_HIP(hipGetDeviceProperties(&prop, dev));
-    std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
-    if (g_rocfft_setup != rocfft_status_success) return SPDBA_EFFT;
+    if (spdba::fft_setup() != SPDBA_OK) return SPDBA_EFFT;
 
     spdba_plan p = new (std::nothrow) spdba_plan_s();
     if (!p) return SPDBA_EDEVICE;
@@ -1246,3 +1245,9 @@ spdba_status spdba_destroy(spdba_plan p) {
 }
 
 }  // extern "C"
+
+// rocFFT's library set-up, once per process, shared by every plan type
+int32_t spdba::fft_setup() {
+    std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
+    return g_rocfft_setup == rocfft_status_success ? SPDBA_OK : SPDBA_EFFT;
+}

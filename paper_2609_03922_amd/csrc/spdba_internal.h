@@ -174,6 +174,9 @@ hipError_t launch_copy_half(const Ctx &c, bool dbl, int inst, const void *src, v
 hipError_t launch_fill_pattern(void *buf, int64_t n_elems, bool dbl, hipStream_t s);
 hipError_t launch_check_pattern(const void *buf, int64_t n_elems, bool dbl, uint32_t *bad, hipStream_t s);
 
+// rocFFT's library set-up, once per process (spdba_api.cpp)
+int32_t fft_setup();  // an spdba_status
+
 // plan internals for the proposer kernels (spdba_api.cpp)
 const Ctx *plan_ctx(::spdba_plan_s *p);
 const InstDev *plan_hinst(::spdba_plan_s *p, int *n_inst, int64_t *nb_total);

@@ -1,0 +1,752 @@
+// sp-DBA for multicomponent reaction--cross-diffusion (Supplementary S4):
+// kernels and the C ABI of include/spdba_rcd.h.
+//
+// Kernels (one plan, one instance, M components stored component after
+// component, N modes each):
+//   k_rcd_reaction   real space: u = Re(W)/N per component, W <- R(u) (S4.1)
+//   k_rcd_measure    per block: a_b = max over modes of sum_m |q_m|^2 (FP64,
+//                    components in order, k = 0 left out); one workgroup per block
+//   k_rcd_gmax       G = max_b a_b (one workgroup)
+//   k_rcd_compact    mask and an unordered list of the active blocks
+//                    (wave-aggregated append)
+//   k_rcd_update     persistent walk of the list (or of every block for the
+//                    Regular update): per mode b = q + dt R, then the eigen form
+//                    of S4.3, x = V diag(1/(1 + dt k^2 lambda)) V^T b, with V^T
+//                    and lambda in LDS (read as broadcasts) and b, x in
+//                    registers (MM-wide tiles, zero-padded past M)
+//
+// The per-mode contraction moves 24 M bytes (FP32) for 4 MM^2 FMAs; up to
+// MM = 16 that is well below the balance point of FP32 vector arithmetic
+// against HBM, so it runs on the vector units, not on matrix cores.  Tiles:
+// 2, 4, 8, 16 in FP32 and 2, 4, 8 in FP64, the widths whose operands stay in
+// registers without scratch.
+
+#include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "spdba_internal.h"
+#include "spdba_rcd.h"
+
+namespace {
+
+constexpr double kTwoPiR = 6.283185307179586476925286766559;
+constexpr int kMaxMF32 = 16, kMaxMF64 = 8;  // register tiles that compile without scratch
+
+struct RGeo {
+    int n[3], ln[3], b[3], lb[3], nbk[3], lnbk[3];
+    int64_t N, nb;
+    int bvol, lbvol;
+    double kf[3];  // 2 pi / (n dx) per axis
+};
+
+struct RCtx {
+    RGeo g;
+    int M;
+    void *state;         // M x N complex
+    const void *rhs;     // M x N complex
+    double *ab;          // [nb]
+    uint8_t *mask;       // [nb]
+    uint32_t *list;      // [nb]
+    uint32_t *count;     // active blocks
+    unsigned long long *G;
+    const void *vt;      // [MM][MM] V^T, zero-padded
+    const void *lam;     // [MM], zero-padded
+    double tau2, dt, invN;
+    double alpha, beta, r, a;
+    int pin, dense, mm;
+};
+
+__device__ __forceinline__ double rsq2(double x, double y) { return x * x + y * y; }
+
+// signed frequency index of position i on an axis of n points (n = 1: 0)
+__device__ __forceinline__ int rsidx(int i, int n) { return i <= ((n - 1) >> 1) ? i : i - n; }
+
+__device__ __forceinline__ double rwave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <typename T> struct C2;
+template <> struct C2<float> { using t = float2; };
+template <> struct C2<double> { using t = double2; };
+
+// mode index and |k|^2 of slot s of block b
+__device__ __forceinline__ void mode_of(const RGeo &g, int64_t b, int s, int64_t &e, double &k2) {
+    const int bx = (int)(b & (g.nbk[2] - 1));
+    const int by = (int)((b >> g.lnbk[2]) & (g.nbk[1] - 1));
+    const int bz = (int)(b >> (g.lnbk[2] + g.lnbk[1]));
+    const int lx = s & (g.b[2] - 1);
+    const int ly = (s >> g.lb[2]) & (g.b[1] - 1);
+    const int lz = s >> (g.lb[2] + g.lb[1]);
+    const int z = (bz << g.lb[0]) + lz, y = (by << g.lb[1]) + ly, x = (bx << g.lb[2]) + lx;
+    e = ((((int64_t)z << g.ln[1]) + y) << g.ln[2]) + x;
+    const double kz = rsidx(z, g.n[0]) * g.kf[0], ky = rsidx(y, g.n[1]) * g.kf[1], kx = rsidx(x, g.n[2]) * g.kf[2];
+    k2 = kz * kz + ky * ky + kx * kx;
+}
+
+__global__ void k_rcd_reset(RCtx c) {
+    if (threadIdx.x == 0) {
+        *c.G = 0ull;
+        *c.count = 0u;
+    }
+}
+
+// R(u) in place on the inverse transforms: Re(W)/N per component; the
+// interaction sum as beta (S - u_i) + alpha (u_{i-1} + u_{i+1}) for M >= 3
+// and (beta + alpha) u_{1-i} for M = 2 (S4.1)
+template <typename T, int MM>
+__global__ void __launch_bounds__(256) k_rcd_reaction(RCtx c, typename C2<T>::t *w) {
+    const int M = c.M;
+    const int64_t N = c.g.N;
+    const T invN = (T)c.invN, r = (T)c.r, a = (T)c.a, al = (T)c.alpha, be = (T)c.beta;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+        T u[MM];
+        T S = (T)0;
+#pragma unroll
+        for (int m = 0; m < MM; ++m) {
+            u[m] = m < M ? w[m * N + p].x * invN : (T)0;
+            S = S + u[m];
+        }
+        T ulast = (T)0;
+#pragma unroll
+        for (int m = 0; m < MM; ++m)
+            if (m == M - 1) ulast = u[m];
+#pragma unroll
+        for (int m = 0; m < MM; ++m) {
+            if (m >= M) continue;
+            T inter;
+            if (M == 2) {
+                inter = (al + be) * (m == 0 ? u[1] : u[0]);
+            } else {
+                const T left = m == 0 ? ulast : u[m > 0 ? m - 1 : 0];
+                const T right = m == M - 1 ? u[0] : u[m + 1 < MM ? m + 1 : 0];
+                inter = be * (S - u[m]) + al * (left + right);
+            }
+            typename C2<T>::t o;
+            o.x = u[m] * (r - a * u[m] - inter);
+            o.y = (T)0;
+            w[m * N + p] = o;
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_rcd_measure(RCtx c) {
+    __shared__ double red[4];
+    using V2 = typename C2<T>::t;
+    const V2 *q = reinterpret_cast<const V2 *>(c.state);
+    const int64_t b = blockIdx.x;
+    const int64_t N = c.g.N;
+    double amax = 0.0;
+    for (int s = threadIdx.x; s < c.g.bvol; s += blockDim.x) {
+        int64_t e;
+        double k2;
+        mode_of(c.g, b, s, e, k2);
+        double acc = 0.0;
+        for (int m = 0; m < c.M; ++m) {
+            const V2 v = q[m * N + e];
+            acc = acc + rsq2((double)v.x, (double)v.y);
+        }
+        if (e == 0) acc = 0.0;
+        amax = fmax(amax, acc);
+    }
+    amax = rwave_max(amax);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, red[k]);
+        c.ab[b] = m;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_rcd_gmax(RCtx c) {
+    __shared__ double red[16];
+    double m = 0.0;
+    for (int64_t b = threadIdx.x; b < c.g.nb; b += blockDim.x) m = fmax(m, c.ab[b]);
+    m = rwave_max(m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double g = red[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) g = fmax(g, red[k]);
+        *c.G = (unsigned long long)__double_as_longlong(g);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_rcd_compact(RCtx c) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    bool act = false;
+    if (b < c.g.nb) {
+        const double G = __longlong_as_double((long long)*c.G);
+        act = (c.pin && b == 0) || c.ab[b] > c.tau2 * G;
+        c.mask[b] = act ? 1 : 0;
+    }
+    const unsigned long long bal = __ballot(act);
+    if (bal == 0ull) return;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(c.count, (uint32_t)__popcll(bal));
+    base = __shfl(base, 0, 64);
+    if (act) c.list[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)b;
+}
+
+template <typename T, int MM>
+__global__ void __launch_bounds__(256) k_rcd_update(RCtx c) {
+    using V2 = typename C2<T>::t;
+    __shared__ T vt[MM * MM];
+    __shared__ T lam[MM];
+    for (int i = threadIdx.x; i < MM * MM; i += blockDim.x) vt[i] = reinterpret_cast<const T *>(c.vt)[i];
+    for (int i = threadIdx.x; i < MM; i += blockDim.x) lam[i] = reinterpret_cast<const T *>(c.lam)[i];
+    __syncthreads();
+    V2 *q = reinterpret_cast<V2 *>(c.state);
+    const V2 *rh = reinterpret_cast<const V2 *>(c.rhs);
+    const int M = c.M;
+    const int64_t N = c.g.N;
+    const T dt = (T)c.dt;
+    const int64_t total = c.dense ? c.g.nb : (int64_t)*c.count;
+    for (int64_t ent = blockIdx.x; ent < total; ent += gridDim.x) {
+        const int64_t b = c.dense ? ent : (int64_t)c.list[ent];
+        for (int s = threadIdx.x; s < c.g.bvol; s += blockDim.x) {
+            int64_t e;
+            double k2;
+            mode_of(c.g, b, s, e, k2);
+            const T dk = (T)(c.dt * k2);
+            T br[MM], bi[MM];
+#pragma unroll
+            for (int m = 0; m < MM; ++m) {
+                br[m] = bi[m] = (T)0;
+                if (m < M) {
+                    const V2 v = q[m * N + e], f = rh[m * N + e];
+                    br[m] = fma(dt, f.x, v.x);
+                    bi[m] = fma(dt, f.y, v.y);
+                }
+            }
+            T xr[MM], xi[MM];
+#pragma unroll
+            for (int m = 0; m < MM; ++m) xr[m] = xi[m] = (T)0;
+#pragma unroll
+            for (int j = 0; j < MM; ++j) {
+                // keeps V^T in LDS: read where used (broadcasts), not hoisted
+                // out of the mode loops into registers
+                asm volatile("" ::: "memory");
+                T wr = (T)0, wi = (T)0;
+#pragma unroll
+                for (int i = 0; i < MM; ++i) {
+                    const T v = vt[j * MM + i];
+                    wr = fma(v, br[i], wr);
+                    wi = fma(v, bi[i], wi);
+                }
+                const T sj = (T)1 / ((T)1 + dk * lam[j]);
+                wr = wr * sj;
+                wi = wi * sj;
+#pragma unroll
+                for (int m = 0; m < MM; ++m) {
+                    const T v = vt[j * MM + m];
+                    xr[m] = fma(v, wr, xr[m]);
+                    xi[m] = fma(v, wi, xi[m]);
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < MM; ++m)
+                if (m < M) {
+                    V2 o;
+                    o.x = xr[m];
+                    o.y = xi[m];
+                    q[m * N + e] = o;
+                }
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_rcd_real_in(int64_t n, const T *re, typename C2<T>::t *out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        typename C2<T>::t o;
+        o.x = re[i];
+        o.y = (T)0;
+        out[i] = o;
+    }
+}
+
+template <typename T>
+__global__ void k_rcd_real_out(int64_t n, const typename C2<T>::t *in, T *re, T invN) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        re[i] = in[i].x * invN;
+}
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int64_t v) { int l = 0; while ((int64_t(1) << l) < v) ++l; return l; }
+
+// FP64 cyclic Jacobi for the symmetric D: D = V diag(lam) V^T, V[i*M + j] = V_ij
+void jacobi(int M, std::vector<double> A, std::vector<double> &V, std::vector<double> &lam) {
+    V.assign((size_t)M * M, 0.0);
+    for (int i = 0; i < M; ++i) V[(size_t)i * M + i] = 1.0;
+    auto at = [&](int i, int j) -> double & { return A[(size_t)i * M + j]; };
+    double diag = 0.0;
+    for (int i = 0; i < M; ++i) diag += at(i, i) * at(i, i);
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < M; ++p)
+            for (int q = p + 1; q < M; ++q) off += at(p, q) * at(p, q);
+        if (off <= 1e-32 * std::max(diag, 1e-300)) break;
+        for (int p = 0; p < M; ++p)
+            for (int q = p + 1; q < M; ++q) {
+                if (at(p, q) == 0.0) continue;
+                const double th = (at(q, q) - at(p, p)) / (2.0 * at(p, q));
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < M; ++k) {
+                    const double kp = at(k, p), kq = at(k, q);
+                    at(k, p) = cs * kp - sn * kq;
+                    at(k, q) = sn * kp + cs * kq;
+                }
+                for (int k = 0; k < M; ++k) {
+                    const double pk = at(p, k), qk = at(q, k);
+                    at(p, k) = cs * pk - sn * qk;
+                    at(q, k) = sn * pk + cs * qk;
+                }
+                for (int k = 0; k < M; ++k) {
+                    const double vp = V[(size_t)k * M + p], vq = V[(size_t)k * M + q];
+                    V[(size_t)k * M + p] = cs * vp - sn * vq;
+                    V[(size_t)k * M + q] = sn * vp + cs * vq;
+                }
+            }
+    }
+    lam.resize(M);
+    for (int i = 0; i < M; ++i) lam[i] = at(i, i);
+}
+
+std::vector<double> diffusion(int M, double dd, double dc) {
+    std::vector<double> D((size_t)M * M, 0.0);
+    for (int i = 0; i < M; ++i) {
+        D[(size_t)i * M + i] = dd + 2.0 * dc;
+        D[(size_t)i * M + (i + 1) % M] = -dc;
+        D[(size_t)i * M + (i + M - 1) % M] = -dc;
+    }
+    return D;
+}
+
+int tile_of(int M) {
+    int mm = 2;
+    while (mm < M) mm <<= 1;
+    return mm;
+}
+
+}  // namespace
+
+struct spdba_rcd_s {
+    spdba_rcd_desc d{};
+    RCtx c{};
+    bool dbl = false, timing = false, bound = false;
+    int nd = 0, esize = 8;
+    hipStream_t stream = nullptr;
+    size_t state_bytes = 0, work_bytes = 0;
+    size_t o_rhs = 0, o_fft = 0, o_ab = 0, o_mask = 0, o_list = 0, o_ctl = 0, o_vt = 0, o_lam = 0;
+    size_t fft_work = 0;
+    rocfft_plan fwd = nullptr, inv = nullptr;
+    rocfft_execution_info info = nullptr;
+    std::vector<double> V, lam;
+    char *d_state = nullptr, *d_work = nullptr;
+    int cu = 256;
+    hipEvent_t ev[5] = {};
+    bool ev_valid = false;
+};
+
+namespace {
+
+#define RTRY_HIP(x)                                   \
+    do {                                              \
+        if ((x) != hipSuccess) return SPDBA_EDEVICE;  \
+    } while (0)
+#define RTRY(x)                                       \
+    do {                                              \
+        spdba_status s_ = (x);                        \
+        if (s_ != SPDBA_OK) return s_;                \
+    } while (0)
+
+spdba_status validate(const spdba_rcd_desc *d) {
+    if (!d) return SPDBA_EINVAL;
+    if (d->ndim < 1 || d->ndim > 3 || d->M < 2) return SPDBA_EINVAL;
+    if (d->dtype != SPDBA_F32 && d->dtype != SPDBA_F64) return SPDBA_EINVAL;
+    if (d->flags & ~(uint32_t)(SPDBA_RCD_DENSE | SPDBA_RCD_PIN_K0 | SPDBA_RCD_TIMING)) return SPDBA_EINVAL;
+    for (int a = 0; a < 3; ++a) {
+        const bool used = a >= 3 - d->ndim;
+        if (!used && (d->dims[a] != 1 || d->block[a] != 1)) return SPDBA_EINVAL;
+        if (!pow2(d->dims[a]) || !pow2(d->block[a]) || d->block[a] > d->dims[a]) return SPDBA_EINVAL;
+        if (d->dims[a] > (int64_t(1) << 24)) return SPDBA_EINVAL;
+    }
+    const double vals[] = {d->tau, d->dt, d->dx, d->d_diag, d->d_cross, d->alpha, d->beta, d->r, d->a};
+    for (double v : vals)
+        if (!std::isfinite(v)) return SPDBA_EINVAL;
+    if (d->tau < 0 || d->dt <= 0 || d->dx <= 0 || d->d_diag <= 0 || d->d_cross < 0) return SPDBA_EINVAL;
+    const int64_t N = d->dims[0] * d->dims[1] * d->dims[2];
+    if (N > (int64_t(1) << 31) || (int64_t)d->M * N > (int64_t(1) << 36)) return SPDBA_EINVAL;
+    if (d->M > (d->dtype == SPDBA_F64 ? kMaxMF64 : kMaxMF32)) return SPDBA_EUNSUPPORTED;
+    return SPDBA_OK;
+}
+
+template <typename T>
+void launch_update_t(const RCtx &c, int grid, hipStream_t s) {
+    switch (c.mm) {
+        case 2: hipLaunchKernelGGL((k_rcd_update<T, 2>), dim3(grid), dim3(256), 0, s, c); break;
+        case 4: hipLaunchKernelGGL((k_rcd_update<T, 4>), dim3(grid), dim3(256), 0, s, c); break;
+        case 8: hipLaunchKernelGGL((k_rcd_update<T, 8>), dim3(grid), dim3(256), 0, s, c); break;
+        default:  // tile 16: FP32 only (validated at creation)
+            if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_rcd_update<T, 16>), dim3(grid), dim3(256), 0, s, c);
+            break;
+    }
+}
+
+template <typename T>
+void launch_reaction_t(const RCtx &c, void *w, int grid, hipStream_t s) {
+    auto *p = reinterpret_cast<typename C2<T>::t *>(w);
+    switch (c.mm) {
+        case 2: hipLaunchKernelGGL((k_rcd_reaction<T, 2>), dim3(grid), dim3(256), 0, s, c, p); break;
+        case 4: hipLaunchKernelGGL((k_rcd_reaction<T, 4>), dim3(grid), dim3(256), 0, s, c, p); break;
+        case 8: hipLaunchKernelGGL((k_rcd_reaction<T, 8>), dim3(grid), dim3(256), 0, s, c, p); break;
+        default:  // tile 16: FP32 only (validated at creation)
+            if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_rcd_reaction<T, 16>), dim3(grid), dim3(256), 0, s, c, p);
+            break;
+    }
+}
+
+void rec(spdba_rcd_plan p, int i) {
+    if (p->timing) (void)hipEventRecord(p->ev[i], p->stream);
+}
+
+spdba_status exec(spdba_rcd_plan p, rocfft_plan f, void *buf) {
+    void *ib[1] = {buf};
+    return rocfft_execute(f, ib, nullptr, p->info) == rocfft_status_success ? SPDBA_OK : SPDBA_EFFT;
+}
+
+// measure, threshold and compaction, update; rhs: device spectra of R
+spdba_status update_stage(spdba_rcd_plan p, const void *rhs) {
+    RCtx c = p->c;
+    c.rhs = rhs;
+    const int nbg = (int)std::min<int64_t>(c.g.nb, (int64_t)1 << 30);
+    if (!c.dense) {
+        hipLaunchKernelGGL(k_rcd_reset, dim3(1), dim3(64), 0, p->stream, c);
+        if (p->dbl) hipLaunchKernelGGL(k_rcd_measure<double>, dim3(nbg), dim3(256), 0, p->stream, c);
+        else hipLaunchKernelGGL(k_rcd_measure<float>, dim3(nbg), dim3(256), 0, p->stream, c);
+        hipLaunchKernelGGL(k_rcd_gmax, dim3(1), dim3(1024), 0, p->stream, c);
+        RTRY_HIP(hipGetLastError());
+        rec(p, 2);
+        hipLaunchKernelGGL(k_rcd_compact, dim3((unsigned)((c.g.nb + 255) / 256)), dim3(256), 0, p->stream, c);
+        RTRY_HIP(hipGetLastError());
+    } else {
+        rec(p, 2);
+    }
+    rec(p, 3);
+    // persistent: at most a few workgroups per compute unit, never more than blocks
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(c.g.nb, (int64_t)p->cu * 8));
+    if (p->dbl) launch_update_t<double>(c, grid, p->stream);
+    else launch_update_t<float>(c, grid, p->stream);
+    RTRY_HIP(hipGetLastError());
+    rec(p, 4);
+    p->ev_valid = p->timing;
+    return SPDBA_OK;
+}
+
+spdba_status one_step(spdba_rcd_plan p) {
+    const RCtx &c = p->c;
+    char *rhs = p->d_work + p->o_rhs;
+    const size_t bytes = (size_t)c.M * c.g.N * p->esize;
+    rec(p, 0);
+    RTRY_HIP(hipMemcpyAsync(rhs, p->d_state, bytes, hipMemcpyDeviceToDevice, p->stream));
+    RTRY(exec(p, p->inv, rhs));
+    const int grid = (int)std::min<int64_t>((c.g.N + 255) / 256, (int64_t)p->cu * 16);
+    if (p->dbl) launch_reaction_t<double>(c, rhs, grid, p->stream);
+    else launch_reaction_t<float>(c, rhs, grid, p->stream);
+    RTRY_HIP(hipGetLastError());
+    RTRY(exec(p, p->fwd, rhs));
+    rec(p, 1);
+    return update_stage(p, rhs);
+}
+
+}  // namespace
+
+extern "C" {
+
+spdba_status spdba_rcd_eigen(int32_t M, double d_diag, double d_cross, double *V, double *lam) {
+    if (M < 2 || M > 1024 || !V || !lam || !std::isfinite(d_diag) || !std::isfinite(d_cross)) return SPDBA_EINVAL;
+    std::vector<double> v, l;
+    jacobi(M, diffusion(M, d_diag, d_cross), v, l);
+    std::memcpy(V, v.data(), sizeof(double) * v.size());
+    std::memcpy(lam, l.data(), sizeof(double) * l.size());
+    return SPDBA_OK;
+}
+
+spdba_status spdba_rcd_create(const spdba_rcd_desc *desc, void *stream, spdba_rcd_plan *out) {
+    if (!out) return SPDBA_EINVAL;
+    *out = nullptr;
+    RTRY(validate(desc));
+    spdba_rcd_plan p = new (std::nothrow) spdba_rcd_s();
+    if (!p) return SPDBA_EDEVICE;
+    p->d = *desc;
+    p->dbl = desc->dtype == SPDBA_F64;
+    p->esize = p->dbl ? 16 : 8;
+    p->timing = (desc->flags & SPDBA_RCD_TIMING) != 0;
+    p->nd = desc->ndim;
+    p->stream = reinterpret_cast<hipStream_t>(stream);
+    RCtx &c = p->c;
+    RGeo &g = c.g;
+    g.N = 1;
+    g.nb = 1;
+    g.bvol = 1;
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = (int)desc->dims[a];
+        g.b[a] = desc->block[a];
+        g.nbk[a] = g.n[a] / g.b[a];
+        g.ln[a] = ilog2(g.n[a]);
+        g.lb[a] = ilog2(g.b[a]);
+        g.lnbk[a] = ilog2(g.nbk[a]);
+        g.kf[a] = kTwoPiR / ((double)g.n[a] * desc->dx);
+        g.N *= g.n[a];
+        g.nb *= g.nbk[a];
+        g.bvol *= g.b[a];
+    }
+    g.lbvol = ilog2(g.bvol);
+    c.M = desc->M;
+    c.mm = tile_of(desc->M);
+    c.tau2 = desc->tau * desc->tau;
+    c.dt = desc->dt;
+    c.invN = 1.0 / (double)g.N;
+    c.alpha = desc->alpha;
+    c.beta = desc->beta;
+    c.r = desc->r;
+    c.a = desc->a;
+    c.pin = (desc->flags & SPDBA_RCD_PIN_K0) ? 1 : 0;
+    c.dense = (desc->flags & SPDBA_RCD_DENSE) ? 1 : 0;
+    jacobi(c.M, diffusion(c.M, desc->d_diag, desc->d_cross), p->V, p->lam);
+
+    auto fail = [&](spdba_status s) {
+        spdba_rcd_destroy(p);
+        return s;
+    };
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(SPDBA_EDEVICE);
+    p->cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    if (spdba::fft_setup() != SPDBA_OK) return fail(SPDBA_EFFT);
+    size_t len[3];
+    for (int a = 0; a < p->nd; ++a) len[a] = (size_t)g.n[2 - a];  // fastest first
+    const rocfft_precision prec = p->dbl ? rocfft_precision_double : rocfft_precision_single;
+    if (rocfft_plan_create(&p->fwd, rocfft_placement_inplace, rocfft_transform_type_complex_forward, prec,
+                           (size_t)p->nd, len, (size_t)c.M, nullptr) != rocfft_status_success ||
+        rocfft_plan_create(&p->inv, rocfft_placement_inplace, rocfft_transform_type_complex_inverse, prec,
+                           (size_t)p->nd, len, (size_t)c.M, nullptr) != rocfft_status_success)
+        return fail(SPDBA_EFFT);
+    size_t w1 = 0, w2 = 0;
+    if (rocfft_plan_get_work_buffer_size(p->fwd, &w1) != rocfft_status_success ||
+        rocfft_plan_get_work_buffer_size(p->inv, &w2) != rocfft_status_success)
+        return fail(SPDBA_EFFT);
+    p->fft_work = std::max(w1, w2);
+    if (rocfft_execution_info_create(&p->info) != rocfft_status_success ||
+        rocfft_execution_info_set_stream(p->info, p->stream) != rocfft_status_success)
+        return fail(SPDBA_EFFT);
+    if (p->timing)
+        for (auto &e : p->ev)
+            if (hipEventCreate(&e) != hipSuccess) return fail(SPDBA_EDEVICE);
+
+    const size_t spec = (size_t)c.M * g.N * p->esize;
+    const size_t tsz = p->dbl ? 8 : 4;
+    p->state_bytes = spec;
+    size_t o = 0;
+    p->o_rhs = o;
+    o = al256(o + spec);
+    p->o_fft = o;
+    o = al256(o + p->fft_work);
+    p->o_ab = o;
+    o = al256(o + sizeof(double) * g.nb);
+    p->o_mask = o;
+    o = al256(o + g.nb);
+    p->o_list = o;
+    o = al256(o + sizeof(uint32_t) * g.nb);
+    p->o_ctl = o;
+    o = al256(o + 16);
+    p->o_vt = o;
+    o = al256(o + tsz * c.mm * c.mm);
+    p->o_lam = o;
+    o = al256(o + tsz * c.mm);
+    p->work_bytes = o;
+    *out = p;
+    return SPDBA_OK;
+}
+
+spdba_status spdba_rcd_buffer_sizes(spdba_rcd_plan p, size_t *state_bytes, size_t *work_bytes) {
+    if (!p || !state_bytes || !work_bytes) return SPDBA_EINVAL;
+    *state_bytes = p->state_bytes;
+    *work_bytes = p->work_bytes;
+    return SPDBA_OK;
+}
+
+spdba_status spdba_rcd_bind(spdba_rcd_plan p, void *d_state, void *d_work) {
+    if (!p || !d_state || !d_work) return SPDBA_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(d_state) & 255) || (reinterpret_cast<uintptr_t>(d_work) & 255))
+        return SPDBA_EINVAL;
+    p->d_state = static_cast<char *>(d_state);
+    p->d_work = static_cast<char *>(d_work);
+    RCtx &c = p->c;
+    c.state = p->d_state;
+    c.ab = reinterpret_cast<double *>(p->d_work + p->o_ab);
+    c.mask = reinterpret_cast<uint8_t *>(p->d_work + p->o_mask);
+    c.list = reinterpret_cast<uint32_t *>(p->d_work + p->o_list);
+    c.G = reinterpret_cast<unsigned long long *>(p->d_work + p->o_ctl);
+    c.count = reinterpret_cast<uint32_t *>(p->d_work + p->o_ctl + 8);
+    c.vt = p->d_work + p->o_vt;
+    c.lam = p->d_work + p->o_lam;
+    if (p->fft_work &&
+        rocfft_execution_info_set_work_buffer(p->info, p->d_work + p->o_fft, p->fft_work) != rocfft_status_success)
+        return SPDBA_EFFT;
+    // V^T and lambda, zero-padded to the register tile, in the kernels' precision
+    const int M = c.M, mm = c.mm;
+    std::vector<double> vt((size_t)mm * mm, 0.0), lam(mm, 0.0);
+    for (int j = 0; j < M; ++j) {
+        lam[j] = p->lam[j];
+        for (int i = 0; i < M; ++i) vt[(size_t)j * mm + i] = p->V[(size_t)i * M + j];
+    }
+    if (p->dbl) {
+        RTRY_HIP(hipMemcpy(p->d_work + p->o_vt, vt.data(), 8 * vt.size(), hipMemcpyHostToDevice));
+        RTRY_HIP(hipMemcpy(p->d_work + p->o_lam, lam.data(), 8 * lam.size(), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> vf(vt.begin(), vt.end()), lf(lam.begin(), lam.end());
+        RTRY_HIP(hipMemcpy(p->d_work + p->o_vt, vf.data(), 4 * vf.size(), hipMemcpyHostToDevice));
+        RTRY_HIP(hipMemcpy(p->d_work + p->o_lam, lf.data(), 4 * lf.size(), hipMemcpyHostToDevice));
+    }
+    // the tables read back before any update: zero a_b, mask, G and the count
+    RTRY_HIP(hipMemsetAsync(p->d_work + p->o_ab, 0, p->o_vt - p->o_ab, p->stream));
+    RTRY_HIP(hipStreamSynchronize(p->stream));
+    p->bound = true;
+    return SPDBA_OK;
+}
+
+spdba_status spdba_rcd_set_spectrum(spdba_rcd_plan p, const void *src) {
+    if (!p || !src) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    RTRY_HIP(hipMemcpyAsync(p->d_state, src, p->state_bytes, hipMemcpyDeviceToDevice, p->stream));
+    return SPDBA_OK;
+}
+
+spdba_status spdba_rcd_get_spectrum(spdba_rcd_plan p, void *dst) {
+    if (!p || !dst) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    RTRY_HIP(hipMemcpyAsync(dst, p->d_state, p->state_bytes, hipMemcpyDeviceToDevice, p->stream));
+    return SPDBA_OK;
+}
+
+spdba_status spdba_rcd_set_field(spdba_rcd_plan p, const void *re) {
+    if (!p || !re) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    const int64_t n = (int64_t)p->c.M * p->c.g.N;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, (int64_t)p->cu * 16);
+    if (p->dbl)
+        hipLaunchKernelGGL(k_rcd_real_in<double>, dim3(grid), dim3(256), 0, p->stream, n,
+                           static_cast<const double *>(re), reinterpret_cast<double2 *>(p->d_state));
+    else
+        hipLaunchKernelGGL(k_rcd_real_in<float>, dim3(grid), dim3(256), 0, p->stream, n,
+                           static_cast<const float *>(re), reinterpret_cast<float2 *>(p->d_state));
+    RTRY_HIP(hipGetLastError());
+    return exec(p, p->fwd, p->d_state);
+}
+
+spdba_status spdba_rcd_get_field(spdba_rcd_plan p, void *re) {
+    if (!p || !re) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    char *w = p->d_work + p->o_rhs;
+    RTRY_HIP(hipMemcpyAsync(w, p->d_state, p->state_bytes, hipMemcpyDeviceToDevice, p->stream));
+    RTRY(exec(p, p->inv, w));
+    const int64_t n = (int64_t)p->c.M * p->c.g.N;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, (int64_t)p->cu * 16);
+    if (p->dbl)
+        hipLaunchKernelGGL(k_rcd_real_out<double>, dim3(grid), dim3(256), 0, p->stream, n,
+                           reinterpret_cast<const double2 *>(w), static_cast<double *>(re), p->c.invN);
+    else
+        hipLaunchKernelGGL(k_rcd_real_out<float>, dim3(grid), dim3(256), 0, p->stream, n,
+                           reinterpret_cast<const float2 *>(w), static_cast<float *>(re), (float)p->c.invN);
+    RTRY_HIP(hipGetLastError());
+    return SPDBA_OK;
+}
+
+spdba_status spdba_rcd_apply(spdba_rcd_plan p, const void *rhs) {
+    if (!p || !rhs) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    rec(p, 0);
+    rec(p, 1);
+    return update_stage(p, rhs);
+}
+
+spdba_status spdba_rcd_step(spdba_rcd_plan p, int32_t n) {
+    if (!p || n < 0) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    for (int32_t i = 0; i < n; ++i) RTRY(one_step(p));
+    return SPDBA_OK;
+}
+
+spdba_status spdba_rcd_indicator(spdba_rcd_plan p, double *ab, size_t n, double *G) {
+    if (!p || (ab && n < (size_t)p->c.g.nb)) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    RTRY_HIP(hipStreamSynchronize(p->stream));
+    if (ab) RTRY_HIP(hipMemcpy(ab, p->c.ab, sizeof(double) * p->c.g.nb, hipMemcpyDeviceToHost));
+    if (G) {
+        unsigned long long bits = 0;
+        RTRY_HIP(hipMemcpy(&bits, p->c.G, 8, hipMemcpyDeviceToHost));
+        std::memcpy(G, &bits, 8);
+    }
+    return SPDBA_OK;
+}
+
+spdba_status spdba_rcd_active_mask(spdba_rcd_plan p, uint8_t *mask, size_t n, int64_t *count) {
+    if (!p || (mask && n < (size_t)p->c.g.nb)) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    RTRY_HIP(hipStreamSynchronize(p->stream));
+    if (p->c.dense) {
+        if (mask) std::memset(mask, 1, p->c.g.nb);
+        if (count) *count = p->c.g.nb;
+        return SPDBA_OK;
+    }
+    if (mask) RTRY_HIP(hipMemcpy(mask, p->c.mask, p->c.g.nb, hipMemcpyDeviceToHost));
+    if (count) {
+        uint32_t c = 0;
+        RTRY_HIP(hipMemcpy(&c, p->c.count, 4, hipMemcpyDeviceToHost));
+        *count = c;
+    }
+    return SPDBA_OK;
+}
+
+spdba_status spdba_rcd_stats(spdba_rcd_plan p, spdba_rcd_stats_t *out) {
+    if (!p || !out) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    std::memset(out, 0, sizeof(*out));
+    out->n_blocks = p->c.g.nb;
+    RTRY(spdba_rcd_active_mask(p, nullptr, 0, &out->active_blocks));
+    if (!p->c.dense) RTRY(spdba_rcd_indicator(p, nullptr, 0, &out->G));
+    if (p->timing && p->ev_valid)
+        for (int i = 0; i < 4; ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p->ev[i], p->ev[i + 1]) == hipSuccess) out->stage_ms[i] = ms;
+        }
+    return SPDBA_OK;
+}
+
+spdba_status spdba_rcd_destroy(spdba_rcd_plan p) {
+    if (!p) return SPDBA_OK;
+    if (p->fwd) rocfft_plan_destroy(p->fwd);
+    if (p->inv) rocfft_plan_destroy(p->inv);
+    if (p->info) rocfft_execution_info_destroy(p->info);
+    for (auto &e : p->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete p;
+    return SPDBA_OK;
+}
+
+}  // extern "C"

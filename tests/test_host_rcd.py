@@ -1,0 +1,78 @@
+"""Host-side checks of the RCD entry points (include/spdba_rcd.h) that need no
+GPU: every declared symbol is exported, the eigen form the plan uses
+reconstructs D and matches the circulant spectrum in closed form, and invalid
+descriptors are rejected before any device call."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import rcd as OR
+from paper_2609_03922_amd import rcd, spdba
+from test_host_lib import header_functions
+
+
+def test_rcd_exports():
+    lib = rcd.load()
+    names = header_functions("spdba_rcd.h")
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(rcd.RCD_EXPORTS)
+
+
+@pytest.mark.parametrize("M", [2, 3, 8, 16, 33])
+def test_eigen_form_reconstructs_D(M):
+    V, lam = rcd.eigen(M, 0.5, 0.05)
+    D = OR.diffusion_matrix(M, 0.5, 0.05)
+    assert np.max(np.abs(V @ np.diag(lam) @ V.T - D)) <= 1e-14
+    assert np.max(np.abs(V.T @ V - np.eye(M))) <= 1e-14
+    want = np.array([0.55, 0.65]) if M == 2 else 0.6 - 0.1 * np.cos(2 * np.pi * np.arange(M) / M)
+    assert np.allclose(np.sort(lam), np.sort(want), rtol=0, atol=1e-14)
+
+
+def _bad(**kw):
+    d = rcd.make_desc(8, 3, 32, 8)
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("kw,expect", [
+    ({"M": 1}, spdba.SPDBA_EINVAL),
+    ({"ndim": 0}, spdba.SPDBA_EINVAL),
+    ({"ndim": 4}, spdba.SPDBA_EINVAL),
+    ({"tau": -1.0}, spdba.SPDBA_EINVAL),
+    ({"tau": math.nan}, spdba.SPDBA_EINVAL),
+    ({"dt": 0.0}, spdba.SPDBA_EINVAL),
+    ({"dx": -0.5}, spdba.SPDBA_EINVAL),
+    ({"d_diag": 0.0}, spdba.SPDBA_EINVAL),
+    ({"d_cross": -0.1}, spdba.SPDBA_EINVAL),
+    ({"alpha": math.inf}, spdba.SPDBA_EINVAL),
+    ({"dtype": 7}, spdba.SPDBA_EINVAL),
+    ({"flags": 64}, spdba.SPDBA_EINVAL),
+    ({"M": 17}, spdba.SPDBA_EUNSUPPORTED),
+    ({"M": 9, "dtype": spdba.SPDBA_F64}, spdba.SPDBA_EUNSUPPORTED),
+])
+def test_invalid_descriptors_rejected_without_device(kw, expect):
+    assert rcd.create_status(_bad(**kw)) == expect
+
+
+def test_invalid_shapes_rejected_without_device():
+    d = rcd.make_desc(4, 3, 32, 8)
+    d.dims[2] = 24                      # not a power of two
+    assert rcd.create_status(d) == spdba.SPDBA_EINVAL
+    d = rcd.make_desc(4, 3, 32, 8)
+    d.block[1] = 64                     # larger than the axis
+    assert rcd.create_status(d) == spdba.SPDBA_EINVAL
+    d = rcd.make_desc(4, 2, 32, 8)
+    d.dims[0] = 2                       # an unused axis must be 1
+    assert rcd.create_status(d) == spdba.SPDBA_EINVAL
+
+
+def test_null_arguments():
+    lib = rcd.load()
+    assert lib.spdba_rcd_create(None, None, None) == spdba.SPDBA_EINVAL
+    assert lib.spdba_rcd_destroy(None) == spdba.SPDBA_OK
+    assert lib.spdba_rcd_step(None, 1) == spdba.SPDBA_EINVAL
+    assert lib.spdba_rcd_stats(None, None) == spdba.SPDBA_EINVAL
+    assert lib.spdba_rcd_eigen(1, 0.5, 0.05, None, None) == spdba.SPDBA_EINVAL
