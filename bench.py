@@ -250,6 +250,8 @@ def main():
     cfg = configs.BY_NAME[args.config]
     if "proposer" in cfg:
         return proposer_bench(args, cfg)
+    if cfg["op"] == "rcd":
+        return rcd_bench(args, cfg)
     if args.layout:
         cfg = dict(cfg, layout=args.layout)
     layout = cfg.get("layout", "full")
@@ -831,6 +833,141 @@ def proposer_bench(args, cfg):
         "equal_error_best": best_at_equal_error(eq) if eq else None,
     }
     print(json.dumps(out), flush=True)
+
+
+def rcd_bench(args, cfg):
+    """Reaction--cross-diffusion (Supplementary S4) at 256^3 with M = 8 in
+    FP32: sp-DBA with the eigen-form update against the Regular update at equal
+    error.  Each threshold of the sweep runs W + K full steps from the seeded
+    start; the error is the rel-L2 of the fluctuation fields (each component
+    minus its mean) against an FP64 Regular run on the GPU; tau* is the largest
+    threshold within 1.1 e_d.  Steps/s over the K timed steps (HIP events on the
+    plan's stream); per-stage times and the update kernel's roofline from an
+    eager run with stage events at tau*."""
+    import numpy as np
+    import torch
+
+    from paper_2609_03922_amd import configs, inputs, rcd
+
+    M, n, bl = cfg["M"], cfg["n"], cfg["block"]
+    K = args.steps if args.steps is not None else cfg["steps"]
+    W = args.warmup
+    par = {k: cfg[k] for k in ("dt", "dx", "d_diag", "d_cross", "alpha", "beta", "r", "a")}
+    base = configs.lv_equilibrium(M, cfg["alpha"], cfg["beta"], cfg["r"], cfg["a"])
+    u0 = inputs.perturbed_components(cfg["seed"], M, (n, n, n), base, cfg["ic"]["amp"])
+    N = n ** 3
+
+    def make(dtype, tau, dense, timing=False):
+        return rcd.RcdPlan(rcd.make_desc(M, 3, n, bl, dtype=dtype, tau=tau, dense=dense, timing=timing, **par))
+
+    def fluct(u):
+        u = u.reshape(M, N).astype(np.float64)
+        return u - u.mean(axis=1, keepdims=True)
+
+    def run(dtype, tau, dense):
+        p = make(dtype, tau, dense)
+        p.set_field(torch.from_numpy(u0.astype(np.float64 if dtype == "f64" else np.float32).ravel()))
+        p.step(W)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p.stream.synchronize()
+        e0.record(p.stream)
+        p.step(K)
+        e1.record(p.stream)
+        p.stream.synchronize()
+        ms = e0.elapsed_time(e1)
+        _, count = p.active_mask()
+        f = fluct(p.get_field().cpu().numpy())
+        nb = p.n_blocks
+        p.destroy()
+        return {"steps_per_s": K / (ms / 1e3), "field": f, "active_fraction_last": count / nb}
+
+    truth = run("f64", 0.0, True)["field"]
+    tn = np.linalg.norm(truth)
+
+    def err(f):
+        return float(np.linalg.norm(f - truth) / tn)
+
+    dense = run("f32", 0.0, True)
+    e_d = err(dense["field"])
+    sweep = []
+    for tau in cfg["taus"]:
+        r = run("f32", tau, False)
+        sweep.append({"tau": tau, "rel_l2": err(r["field"]), "steps_per_s": round(r["steps_per_s"], 2),
+                      "active_fraction_last_step": round(r["active_fraction_last"], 4)})
+        print(f"rcd sweep tau={tau}: {sweep[-1]}", file=sys.stderr, flush=True)
+    ok = [s for s in sweep if s["rel_l2"] <= 1.1 * e_d]
+    # no threshold within the bar: the smallest one is timed, and tau* is null
+    star = max(ok, key=lambda s: s["tau"]) if ok else min(sweep, key=lambda s: s["tau"])
+
+    def stages(tau, dense_flag, steps=20):
+        steps = min(steps, K)
+        p = make("f32", tau, dense_flag, timing=True)
+        p.set_field(torch.from_numpy(u0.astype(np.float32).ravel()))
+        p.step(W + K - steps)
+        acc, act = np.zeros(4), []
+        for _ in range(steps):
+            p.step(1)
+            st = p.stats()
+            acc += np.array(st["stage_ms"])
+            act.append(st["active_blocks"])
+        p.destroy()
+        return acc / steps, float(np.mean(act))
+
+    st_sp, act_sp = stages(star["tau"], False)
+    st_d, _ = stages(0.0, True)
+    bvol = bl ** 3
+    upd_bytes = act_sp * bvol * 24 * M          # FP32: read q and R, write q; 8 B each per component
+    achieved = upd_bytes / (st_sp[3] * 1e-3) / 1e9
+    dense_bytes = (N // bvol) * bvol * 24 * M
+    sps = star["steps_per_s"]
+    line = {
+        "metric": "spectral-update Gpts/s + steps/s, sp-DBA vs dense on GPU at fixed L2 error",
+        "value": round(N * sps / 1e9, 4), "unit": "Gpts/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(1e3 / sps, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": cfg["name"], "grid": f"{n}^3", "components": M, "block": bl,
+                   "tau": star["tau"], "at_equal_error": bool(ok), "update": "eigen form (S4.3)",
+                   "parallelism": "single-gpu"},
+        "steps_per_s": sps, "dense_steps_per_s": round(dense["steps_per_s"], 2),
+        "speedup_steps_vs_dense": round(sps / dense["steps_per_s"], 4),
+        "equal_error": {"truth": "FP64 Regular run on the GPU, fluctuation fields", "e_d": e_d,
+                        "bar": 1.1 * e_d, "sweep": sweep, "tau_star": star["tau"] if ok else None},
+        "stage_ms": {"transforms_and_reaction": round(st_sp[0], 4), "measure": round(st_sp[1], 4),
+                     "compaction": round(st_sp[2], 4), "update": round(st_sp[3], 4)},
+        "dense_stage_ms": {"transforms_and_reaction": round(st_d[0], 4), "update": round(st_d[3], 4)},
+        "update_stage_speedup_vs_dense": round(st_d[3] / max(1e-9, st_sp[1] + st_sp[2] + st_sp[3]), 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(achieved / 8000.0, 4), "traffic": None, "kernel": "k_rcd_update",
+                     "bytes_per_launch": int(upd_bytes), "avg_launch_us": round(st_sp[3] * 1e3, 2),
+                     "active_blocks_mean": round(act_sp, 1),
+                     "dense_achieved": round(dense_bytes / (st_d[3] * 1e-3) / 1e9, 1),
+                     "run": f"eager, stage events, last {min(20, K)} steps"},
+        "cpu_baseline": None if args.no_cpu else rcd_cpu_baseline(cfg, u0, np),
+    }
+    print(json.dumps(line))
+
+
+def rcd_cpu_baseline(cfg, u0, np):
+    """The oracle's full steps on a bounded sample: the workload's parameters
+    and start on the leading 128^3 corner of its field (four steps, one BLAS
+    thread; numpy's transforms are single-threaded), scaled to grid points per
+    second."""
+    import time
+
+    from threadpoolctl import threadpool_limits
+
+    from oracle import rcd as OR
+
+    M, s, steps = cfg["M"], 128, 4
+    u = u0[:, :s, :s, :s]
+    q = np.stack([np.fft.fftn(u[m]).ravel() for m in range(M)])
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        OR.step(q, steps, (s, s, s), (cfg["block"],) * 3, cfg["taus"][0], cfg["dt"], cfg["dx"], cfg["d_diag"],
+                cfg["d_cross"], cfg["alpha"], cfg["beta"], cfg["r"], cfg["a"])
+        dt = time.perf_counter() - t0
+    return {"value": round(steps * s ** 3 / dt / 1e9, 6), "unit": "Gpts/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} full FP64 steps of the workload at 128^3 (M = {M}), {dt:.1f} s"}
 
 
 def oracle_baseline(cfg, descs, sizes, inputs, np, budget=10.0, one_core=True, measure="increment"):

@@ -23,7 +23,10 @@
  * block b active iff a_b > fl(tau^2 G), or it holds k = 0 and
  * SPDBA_RCD_PIN_K0 is set.  The RMS 1/M and square root cancel in this
  * relative rule.  Active blocks update all M components; frozen blocks keep
- * their coefficients bit for bit.
+ * their coefficients bit for bit.  The update kernel keeps the measure of the
+ * blocks it stores (the same FP64 sums of the stored values), so a step after
+ * an update reduces G without a pass over the frozen blocks; after a load
+ * (set_field, set_spectrum) the next update measures in full.
  *
  * Layout: a spectrum is M arrays of N = dims[0]*dims[1]*dims[2] interleaved
  * complex values (FP32 pairs or FP64 pairs per dtype), component after

@@ -55,4 +55,30 @@ CH3D_512_F32_PROPOSER = dict(
 )
 
 ALL = [CH2D_128_F64, CH3D_256_F32, NLSE1D_BATCH48_F32, GS2D_BATCH32_F32, CH3D_512_F32_PROPOSER]
-BY_NAME = {c["name"]: c for c in ALL}
+
+
+def lv_equilibrium(M: int, alpha: float, beta: float, r: float = 1.0, a: float = 1.0) -> float:
+    """Homogeneous coexistence state of the Lotka--Volterra reaction with the
+    circulant interactions of Supplementary S4.1 (neighbours beta + alpha,
+    others beta): r / (a + 2 (beta + alpha) + (M - 3) beta), or
+    r / (a + beta + alpha) for M = 2 -- the reference state the initial
+    condition perturbs."""
+    others = (beta + alpha) if M == 2 else 2.0 * (beta + alpha) + (M - 3) * beta
+    return r / (a + others)
+
+
+# Reaction--cross-diffusion (Supplementary S4.2): 256^3, M = 8 components,
+# 8^3 blocks, dx = 0.5, dt = 0.01, D_diag = 0.5, D_cross = 0.05, alpha = 1,
+# beta = 0.3, r_i = a_i = 1; a nearly homogeneous start with random
+# perturbation of amplitude 0.1.  The relative thresholds of the sweep stand in
+# for the paper's absolute threshold with its controller (target active ratio
+# 3 to 20 %).
+RCD3D_256_M8_F32 = dict(
+    name="rcd3d_256_m8_f32",
+    op="rcd", dtype="f32", ndim=3, n=256, block=8, M=8, steps=200, seed=1006,
+    dt=0.01, dx=0.5, d_diag=0.5, d_cross=0.05, alpha=1.0, beta=0.3, r=1.0, a=1.0,
+    ic=dict(kind="perturbed", amp=0.1),
+    taus=(1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7),
+)
+
+BY_NAME = {c["name"]: c for c in ALL + [RCD3D_256_M8_F32]}

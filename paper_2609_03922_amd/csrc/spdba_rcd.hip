@@ -6,14 +6,18 @@
 //   k_rcd_reaction   real space: u = Re(W)/N per component, W <- R(u) (S4.1)
 //   k_rcd_measure    per block: a_b = max over modes of sum_m |q_m|^2 (FP64,
 //                    components in order, k = 0 left out); one workgroup per block
-//   k_rcd_gmax       G = max_b a_b (one workgroup)
+//   k_rcd_gmax       G = max_b a_b (after an update: merged with the measure the
+//                    update kept for the blocks it stored)
 //   k_rcd_compact    mask and an unordered list of the active blocks
 //                    (wave-aggregated append)
 //   k_rcd_update     persistent walk of the list (or of every block for the
 //                    Regular update): per mode b = q + dt R, then the eigen form
 //                    of S4.3, x = V diag(1/(1 + dt k^2 lambda)) V^T b, with V^T
 //                    and lambda in LDS (read as broadcasts) and b, x in
-//                    registers (MM-wide tiles, zero-padded past M)
+//                    registers (MM-wide tiles, zero-padded past M); it also
+//                    keeps the measure of every block it stores (the next
+//                    update's state is what it stored, frozen blocks are
+//                    unchanged), so only a load is followed by a full pass
 //
 // The per-mode contraction moves 24 M bytes (FP32) for 4 MM^2 FMAs; up to
 // MM = 16 that is well below the balance point of FP32 vector arithmetic
@@ -51,6 +55,8 @@ struct RCtx {
     void *state;         // M x N complex
     const void *rhs;     // M x N complex
     double *ab;          // [nb]
+    double *anext;       // [nb] measure of the blocks the update stored
+    int keep;            // the update writes anext
     uint8_t *mask;       // [nb]
     uint32_t *list;      // [nb]
     uint32_t *count;     // active blocks
@@ -137,12 +143,17 @@ __global__ void __launch_bounds__(256) k_rcd_reaction(RCtx c, typename C2<T>::t 
     }
 }
 
+// XCD-aware: workgroup i runs on XCD i % 8, so the blocks are dealt out in
+// eight contiguous ranges, one per XCD.  x-adjacent blocks of 8 FP32 values
+// per row share 128-byte lines; on one XCD the second read hits its L2.
 template <typename T>
 __global__ void __launch_bounds__(256) k_rcd_measure(RCtx c) {
     __shared__ double red[4];
     using V2 = typename C2<T>::t;
     const V2 *q = reinterpret_cast<const V2 *>(c.state);
-    const int64_t b = blockIdx.x;
+    const int64_t per = (c.g.nb + 7) >> 3;
+    const int64_t b = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (b >= c.g.nb) return;  // workgroup-uniform, before any barrier
     const int64_t N = c.g.N;
     double amax = 0.0;
     for (int s = threadIdx.x; s < c.g.bvol; s += blockDim.x) {
@@ -167,17 +178,29 @@ __global__ void __launch_bounds__(256) k_rcd_measure(RCtx c) {
     }
 }
 
-__global__ void __launch_bounds__(1024) k_rcd_gmax(RCtx c) {
+// G = max_b a_b, one block per thread, one atomic max per workgroup on the
+// bit pattern (non-negative doubles order as their bits; G was cleared by
+// k_rcd_reset).  merge: the measure kept by the last update -- the blocks it
+// stored (mask set) take the value it computed, the others keep theirs
+__global__ void __launch_bounds__(1024) k_rcd_gmax(RCtx c, int merge) {
     __shared__ double red[16];
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double m = 0.0;
-    for (int64_t b = threadIdx.x; b < c.g.nb; b += blockDim.x) m = fmax(m, c.ab[b]);
+    if (b < c.g.nb) {
+        if (merge && c.mask[b]) {
+            m = c.anext[b];
+            c.ab[b] = m;
+        } else {
+            m = c.ab[b];
+        }
+    }
     m = rwave_max(m);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
         double g = red[0];
         for (int k = 1; k < (int)(blockDim.x >> 6); ++k) g = fmax(g, red[k]);
-        *c.G = (unsigned long long)__double_as_longlong(g);
+        if (g > 0.0) atomicMax(c.G, (unsigned long long)__double_as_longlong(g));
     }
 }
 
@@ -203,6 +226,7 @@ __global__ void __launch_bounds__(256) k_rcd_update(RCtx c) {
     using V2 = typename C2<T>::t;
     __shared__ T vt[MM * MM];
     __shared__ T lam[MM];
+    __shared__ double red[4];
     for (int i = threadIdx.x; i < MM * MM; i += blockDim.x) vt[i] = reinterpret_cast<const T *>(c.vt)[i];
     for (int i = threadIdx.x; i < MM; i += blockDim.x) lam[i] = reinterpret_cast<const T *>(c.lam)[i];
     __syncthreads();
@@ -212,8 +236,15 @@ __global__ void __launch_bounds__(256) k_rcd_update(RCtx c) {
     const int64_t N = c.g.N;
     const T dt = (T)c.dt;
     const int64_t total = c.dense ? c.g.nb : (int64_t)*c.count;
-    for (int64_t ent = blockIdx.x; ent < total; ent += gridDim.x) {
+    // one contiguous segment of the list per XCD (grid a multiple of 8): the
+    // list is in block order within each wave's append, so x-adjacent blocks,
+    // which share 128-byte lines, are updated on one XCD
+    const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
+    const int64_t seg = (total + 7) >> 3;
+    const int64_t lo = std::min<int64_t>(total, seg * xcd), hi = std::min<int64_t>(total, seg * (xcd + 1));
+    for (int64_t ent = lo + (blockIdx.x >> 3); ent < hi; ent += per) {
         const int64_t b = c.dense ? ent : (int64_t)c.list[ent];
+        double amax = 0.0;
         for (int s = threadIdx.x; s < c.g.bvol; s += blockDim.x) {
             int64_t e;
             double k2;
@@ -262,6 +293,25 @@ __global__ void __launch_bounds__(256) k_rcd_update(RCtx c) {
                     o.y = xi[m];
                     q[m * N + e] = o;
                 }
+            if (c.keep) {  // the measure of what is stored, as k_rcd_measure sums it
+                double acc = 0.0;
+#pragma unroll
+                for (int m = 0; m < MM; ++m)
+                    if (m < M) acc = acc + rsq2((double)xr[m], (double)xi[m]);
+                if (e == 0) acc = 0.0;
+                amax = fmax(amax, acc);
+            }
+        }
+        if (c.keep) {  // workgroup-uniform
+            amax = rwave_max(amax);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double mx = red[0];
+                for (int k = 1; k < (int)(blockDim.x >> 6); ++k) mx = fmax(mx, red[k]);
+                c.anext[b] = mx;
+            }
+            __syncthreads();  // red is free for the next entry
         }
     }
 }
@@ -350,9 +400,11 @@ struct spdba_rcd_s {
     int nd = 0, esize = 8;
     hipStream_t stream = nullptr;
     size_t state_bytes = 0, work_bytes = 0;
-    size_t o_rhs = 0, o_fft = 0, o_ab = 0, o_mask = 0, o_list = 0, o_ctl = 0, o_vt = 0, o_lam = 0;
+    size_t o_rhs = 0, o_fft = 0, o_ab = 0, o_anext = 0, o_mask = 0, o_list = 0, o_ctl = 0, o_vt = 0, o_lam = 0;
     size_t fft_work = 0;
-    rocfft_plan fwd = nullptr, inv = nullptr;
+    rocfft_plan fwd = nullptr, inv = nullptr, inv_oop = nullptr;
+    bool inv_keeps = false;  // the out-of-place inverse leaves its input intact (probed at bind)
+    bool ab_valid = false;   // a_b and anext describe the current state (no load since the last update)
     rocfft_execution_info info = nullptr;
     std::vector<double> V, lam;
     char *d_state = nullptr, *d_work = nullptr;
@@ -423,21 +475,34 @@ void rec(spdba_rcd_plan p, int i) {
     if (p->timing) (void)hipEventRecord(p->ev[i], p->stream);
 }
 
-spdba_status exec(spdba_rcd_plan p, rocfft_plan f, void *buf) {
-    void *ib[1] = {buf};
-    return rocfft_execute(f, ib, nullptr, p->info) == rocfft_status_success ? SPDBA_OK : SPDBA_EFFT;
+spdba_status exec(spdba_rcd_plan p, rocfft_plan f, void *buf, void *out = nullptr) {
+    void *ib[1] = {buf}, *ob[1] = {out};
+    return rocfft_execute(f, ib, out ? ob : nullptr, p->info) == rocfft_status_success ? SPDBA_OK : SPDBA_EFFT;
+}
+
+// inverse transforms of the state into the work spectra, the state kept
+spdba_status inverse_into(spdba_rcd_plan p, char *dst) {
+    if (p->inv_keeps) return exec(p, p->inv_oop, p->d_state, dst);
+    RTRY_HIP(hipMemcpyAsync(dst, p->d_state, p->state_bytes, hipMemcpyDeviceToDevice, p->stream));
+    return exec(p, p->inv, dst);
 }
 
 // measure, threshold and compaction, update; rhs: device spectra of R
 spdba_status update_stage(spdba_rcd_plan p, const void *rhs) {
     RCtx c = p->c;
     c.rhs = rhs;
-    const int nbg = (int)std::min<int64_t>(c.g.nb, (int64_t)1 << 30);
+    const int nbg = (int)(((c.g.nb + 7) >> 3) << 3);  // k_rcd_measure: eight XCD ranges
     if (!c.dense) {
         hipLaunchKernelGGL(k_rcd_reset, dim3(1), dim3(64), 0, p->stream, c);
-        if (p->dbl) hipLaunchKernelGGL(k_rcd_measure<double>, dim3(nbg), dim3(256), 0, p->stream, c);
-        else hipLaunchKernelGGL(k_rcd_measure<float>, dim3(nbg), dim3(256), 0, p->stream, c);
-        hipLaunchKernelGGL(k_rcd_gmax, dim3(1), dim3(1024), 0, p->stream, c);
+        // the state entering this update is what the last one stored (frozen
+        // blocks unchanged), so its measure is the kept one; after a load, a
+        // full pass
+        if (!p->ab_valid) {
+            if (p->dbl) hipLaunchKernelGGL(k_rcd_measure<double>, dim3(nbg), dim3(256), 0, p->stream, c);
+            else hipLaunchKernelGGL(k_rcd_measure<float>, dim3(nbg), dim3(256), 0, p->stream, c);
+        }
+        hipLaunchKernelGGL(k_rcd_gmax, dim3((unsigned)((c.g.nb + 1023) / 1024)), dim3(1024), 0, p->stream, c,
+                           p->ab_valid ? 1 : 0);
         RTRY_HIP(hipGetLastError());
         rec(p, 2);
         hipLaunchKernelGGL(k_rcd_compact, dim3((unsigned)((c.g.nb + 255) / 256)), dim3(256), 0, p->stream, c);
@@ -446,11 +511,14 @@ spdba_status update_stage(spdba_rcd_plan p, const void *rhs) {
         rec(p, 2);
     }
     rec(p, 3);
-    // persistent: at most a few workgroups per compute unit, never more than blocks
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(c.g.nb, (int64_t)p->cu * 8));
+    // persistent: a few workgroups per compute unit, a multiple of 8 (one list
+    // segment per XCD)
+    const int grid = (int)(std::max<int64_t>(8, std::min<int64_t>(c.g.nb, (int64_t)p->cu * 8)) + 7) / 8 * 8;
+    c.keep = c.dense ? 0 : 1;
     if (p->dbl) launch_update_t<double>(c, grid, p->stream);
     else launch_update_t<float>(c, grid, p->stream);
     RTRY_HIP(hipGetLastError());
+    p->ab_valid = !c.dense;
     rec(p, 4);
     p->ev_valid = p->timing;
     return SPDBA_OK;
@@ -459,10 +527,8 @@ spdba_status update_stage(spdba_rcd_plan p, const void *rhs) {
 spdba_status one_step(spdba_rcd_plan p) {
     const RCtx &c = p->c;
     char *rhs = p->d_work + p->o_rhs;
-    const size_t bytes = (size_t)c.M * c.g.N * p->esize;
     rec(p, 0);
-    RTRY_HIP(hipMemcpyAsync(rhs, p->d_state, bytes, hipMemcpyDeviceToDevice, p->stream));
-    RTRY(exec(p, p->inv, rhs));
+    RTRY(inverse_into(p, rhs));
     const int grid = (int)std::min<int64_t>((c.g.N + 255) / 256, (int64_t)p->cu * 16);
     if (p->dbl) launch_reaction_t<double>(c, rhs, grid, p->stream);
     else launch_reaction_t<float>(c, rhs, grid, p->stream);
@@ -544,13 +610,16 @@ spdba_status spdba_rcd_create(const spdba_rcd_desc *desc, void *stream, spdba_rc
     if (rocfft_plan_create(&p->fwd, rocfft_placement_inplace, rocfft_transform_type_complex_forward, prec,
                            (size_t)p->nd, len, (size_t)c.M, nullptr) != rocfft_status_success ||
         rocfft_plan_create(&p->inv, rocfft_placement_inplace, rocfft_transform_type_complex_inverse, prec,
+                           (size_t)p->nd, len, (size_t)c.M, nullptr) != rocfft_status_success ||
+        rocfft_plan_create(&p->inv_oop, rocfft_placement_notinplace, rocfft_transform_type_complex_inverse, prec,
                            (size_t)p->nd, len, (size_t)c.M, nullptr) != rocfft_status_success)
         return fail(SPDBA_EFFT);
-    size_t w1 = 0, w2 = 0;
+    size_t w1 = 0, w2 = 0, w3 = 0;
     if (rocfft_plan_get_work_buffer_size(p->fwd, &w1) != rocfft_status_success ||
-        rocfft_plan_get_work_buffer_size(p->inv, &w2) != rocfft_status_success)
+        rocfft_plan_get_work_buffer_size(p->inv, &w2) != rocfft_status_success ||
+        rocfft_plan_get_work_buffer_size(p->inv_oop, &w3) != rocfft_status_success)
         return fail(SPDBA_EFFT);
-    p->fft_work = std::max(w1, w2);
+    p->fft_work = std::max(w1, std::max(w2, w3));
     if (rocfft_execution_info_create(&p->info) != rocfft_status_success ||
         rocfft_execution_info_set_stream(p->info, p->stream) != rocfft_status_success)
         return fail(SPDBA_EFFT);
@@ -567,6 +636,8 @@ spdba_status spdba_rcd_create(const spdba_rcd_desc *desc, void *stream, spdba_rc
     p->o_fft = o;
     o = al256(o + p->fft_work);
     p->o_ab = o;
+    o = al256(o + sizeof(double) * g.nb);
+    p->o_anext = o;
     o = al256(o + sizeof(double) * g.nb);
     p->o_mask = o;
     o = al256(o + g.nb);
@@ -599,6 +670,7 @@ spdba_status spdba_rcd_bind(spdba_rcd_plan p, void *d_state, void *d_work) {
     RCtx &c = p->c;
     c.state = p->d_state;
     c.ab = reinterpret_cast<double *>(p->d_work + p->o_ab);
+    c.anext = reinterpret_cast<double *>(p->d_work + p->o_anext);
     c.mask = reinterpret_cast<uint8_t *>(p->d_work + p->o_mask);
     c.list = reinterpret_cast<uint32_t *>(p->d_work + p->o_list);
     c.G = reinterpret_cast<unsigned long long *>(p->d_work + p->o_ctl);
@@ -625,7 +697,17 @@ spdba_status spdba_rcd_bind(spdba_rcd_plan p, void *d_state, void *d_work) {
     }
     // the tables read back before any update: zero a_b, mask, G and the count
     RTRY_HIP(hipMemsetAsync(p->d_work + p->o_ab, 0, p->o_vt - p->o_ab, p->stream));
+    // does the out-of-place inverse keep its input?  A pattern in the state,
+    // one transform, a check (the state's contents are undefined until loaded)
+    uint32_t *bad = reinterpret_cast<uint32_t *>(p->d_work + p->o_ctl + 12);
+    const int64_t ne = (int64_t)M * c.g.N;
+    RTRY_HIP(spdba::launch_fill_pattern(p->d_state, ne, p->dbl, p->stream));
+    RTRY(exec(p, p->inv_oop, p->d_state, p->d_work + p->o_rhs));
+    RTRY_HIP(spdba::launch_check_pattern(p->d_state, ne, p->dbl, bad, p->stream));
+    uint32_t h = 1;
+    RTRY_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, p->stream));
     RTRY_HIP(hipStreamSynchronize(p->stream));
+    p->inv_keeps = (h == 0);
     p->bound = true;
     return SPDBA_OK;
 }
@@ -633,6 +715,7 @@ spdba_status spdba_rcd_bind(spdba_rcd_plan p, void *d_state, void *d_work) {
 spdba_status spdba_rcd_set_spectrum(spdba_rcd_plan p, const void *src) {
     if (!p || !src) return SPDBA_EINVAL;
     if (!p->bound) return SPDBA_ESTATE;
+    p->ab_valid = false;
     RTRY_HIP(hipMemcpyAsync(p->d_state, src, p->state_bytes, hipMemcpyDeviceToDevice, p->stream));
     return SPDBA_OK;
 }
@@ -647,6 +730,7 @@ spdba_status spdba_rcd_get_spectrum(spdba_rcd_plan p, void *dst) {
 spdba_status spdba_rcd_set_field(spdba_rcd_plan p, const void *re) {
     if (!p || !re) return SPDBA_EINVAL;
     if (!p->bound) return SPDBA_ESTATE;
+    p->ab_valid = false;
     const int64_t n = (int64_t)p->c.M * p->c.g.N;
     const int grid = (int)std::min<int64_t>((n + 255) / 256, (int64_t)p->cu * 16);
     if (p->dbl)
@@ -663,8 +747,7 @@ spdba_status spdba_rcd_get_field(spdba_rcd_plan p, void *re) {
     if (!p || !re) return SPDBA_EINVAL;
     if (!p->bound) return SPDBA_ESTATE;
     char *w = p->d_work + p->o_rhs;
-    RTRY_HIP(hipMemcpyAsync(w, p->d_state, p->state_bytes, hipMemcpyDeviceToDevice, p->stream));
-    RTRY(exec(p, p->inv, w));
+    RTRY(inverse_into(p, w));
     const int64_t n = (int64_t)p->c.M * p->c.g.N;
     const int grid = (int)std::min<int64_t>((n + 255) / 256, (int64_t)p->cu * 16);
     if (p->dbl)
@@ -742,6 +825,7 @@ spdba_status spdba_rcd_destroy(spdba_rcd_plan p) {
     if (!p) return SPDBA_OK;
     if (p->fwd) rocfft_plan_destroy(p->fwd);
     if (p->inv) rocfft_plan_destroy(p->inv);
+    if (p->inv_oop) rocfft_plan_destroy(p->inv_oop);
     if (p->info) rocfft_execution_info_destroy(p->info);
     for (auto &e : p->ev)
         if (e) (void)hipEventDestroy(e);

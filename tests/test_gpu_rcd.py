@@ -216,3 +216,39 @@ def test_rcd_full_size_sampled():
     b = q[:, ia].astype(np.complex128) + P["dt"] * r[:, ia].astype(np.complex128)
     ratio = np.max(np.abs(got[:, ia] - x), axis=0) / np.sqrt(np.sum(np.abs(b) ** 2, axis=0))
     assert np.all(ratio <= tol_of(M, "f32")), float(ratio.max())
+
+
+@pytest.mark.parametrize("M,dtype,ndim,n,bl,tau", [(8, "f32", 3, 32, 8, 0.03), (4, "f64", 2, 64, 8, 0.05),
+                                                   (16, "f32", 2, 64, 16, 0.05)])
+def test_rcd_kept_measure_over_a_sequence(M, dtype, ndim, n, bl, tau):
+    """From the second update on, the measure is the one the last update kept
+    for the blocks it stored (frozen blocks unchanged): before every update the
+    oracle gets the GPU's current state, and a_b, G, mask and count agree bit
+    for bit; a reload in the middle forces a full pass."""
+    import torch
+
+    print(f"rcd kept-measure sequence M={M} {dtype} {ndim}-D n={n}", flush=True)
+    dims, block = dims_of(ndim, n), block_of(ndim, bl)
+    q, _ = draw(400 + M, M, dims, dtype)
+    plan = rcd.RcdPlan(rcd.make_desc(M, ndim, n, bl, dtype=dtype, tau=tau, **P))
+    plan.set_spectrum(torch.from_numpy(q.ravel()))
+    counts = []
+    for step in range(6):
+        if step == 3:  # reload the same state: the next update measures in full
+            plan.set_spectrum(plan.get_spectrum())
+        cur = plan.get_spectrum().cpu().numpy().reshape(M, -1)
+        _, r = draw(500 + 10 * M + step, M, dims, dtype)
+        plan.apply(torch.from_numpy(r.ravel()))
+        ref = OR.apply(cur, r, dims, block, tau, P["dt"], P["dx"], P["d_diag"], P["d_cross"])
+        mask, count = plan.active_mask()
+        ab, G = plan.indicator()
+        tag = f"update {step}"
+        assert_bits_equal(ab, ref["a_b"], tag + " a_b")
+        assert G == ref["G"], tag
+        assert_bits_equal(mask, ref["mask"], tag + " mask")
+        assert count == ref["count"]
+        counts.append(count)
+        ref["mask_modes"] = ref["mask"][OR.block_ids(dims, block)].astype(bool)
+        check_update(plan.get_spectrum().cpu().numpy().reshape(M, -1), cur, r, ref, M, dtype, tag)
+    assert any(0 < c < plan.n_blocks for c in counts), counts
+    plan.destroy()
