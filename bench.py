@@ -857,8 +857,9 @@ def rcd_bench(args, cfg):
     u0 = inputs.perturbed_components(cfg["seed"], M, (n, n, n), base, cfg["ic"]["amp"])
     N = n ** 3
 
-    def make(dtype, tau, dense, timing=False):
-        return rcd.RcdPlan(rcd.make_desc(M, 3, n, bl, dtype=dtype, tau=tau, dense=dense, timing=timing, **par))
+    def make(dtype, tau, dense, timing=False, direct=False):
+        return rcd.RcdPlan(rcd.make_desc(M, 3, n, bl, dtype=dtype, tau=tau, dense=dense, timing=timing,
+                                         direct=direct, **par))
 
     def fluct(u):
         u = u.reshape(M, N).astype(np.float64)
@@ -899,9 +900,9 @@ def rcd_bench(args, cfg):
     # no threshold within the bar: the smallest one is timed, and tau* is null
     star = max(ok, key=lambda s: s["tau"]) if ok else min(sweep, key=lambda s: s["tau"])
 
-    def stages(tau, dense_flag, steps=20):
+    def stages(tau, dense_flag, steps=20, direct=False):
         steps = min(steps, K)
-        p = make("f32", tau, dense_flag, timing=True)
+        p = make("f32", tau, dense_flag, timing=True, direct=direct)
         p.set_field(torch.from_numpy(u0.astype(np.float32).ravel()))
         p.step(W + K - steps)
         acc, act = np.zeros(4), []
@@ -915,6 +916,14 @@ def rcd_bench(args, cfg):
 
     st_sp, act_sp = stages(star["tau"], False)
     st_d, _ = stages(0.0, True)
+    # the four configurations of the paper's comparison (Regular and sp-DBA,
+    # each with the direct coupled update of S4.2 and with the eigen form of
+    # S4.3): update-stage ms (measure + compaction + update)
+    four = {"regular_eigen": st_d, "spdba_eigen": st_sp}
+    if M <= 8:
+        four["regular_direct"], _ = stages(0.0, True, direct=True)
+        four["spdba_direct"], _ = stages(star["tau"], False, direct=True)
+    upd_ms = {k: round(float(v[1] + v[2] + v[3]), 4) for k, v in four.items()}
     bvol = bl ** 3
     upd_bytes = act_sp * bvol * 24 * M          # FP32: read q and R, write q; 8 B each per component
     achieved = upd_bytes / (st_sp[3] * 1e-3) / 1e9
@@ -936,6 +945,9 @@ def rcd_bench(args, cfg):
                      "compaction": round(st_sp[2], 4), "update": round(st_sp[3], 4)},
         "dense_stage_ms": {"transforms_and_reaction": round(st_d[0], 4), "update": round(st_d[3], 4)},
         "update_stage_speedup_vs_dense": round(st_d[3] / max(1e-9, st_sp[1] + st_sp[2] + st_sp[3]), 4),
+        "update_stage_ms_four": upd_ms,
+        "update_stage_speedup_vs_regular_direct": (round(upd_ms["regular_direct"] / upd_ms["spdba_eigen"], 4)
+                                                   if "regular_direct" in upd_ms else None),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                      "frac": round(achieved / 8000.0, 4), "traffic": None, "kernel": "k_rcd_update",
                      "bytes_per_launch": int(upd_bytes), "avg_launch_us": round(st_sp[3] * 1e3, 2),

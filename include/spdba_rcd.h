@@ -36,7 +36,8 @@
  * Ownership and errors: the caller owns every device buffer (sized by
  * spdba_rcd_buffer_sizes) and the stream; the plan owns host metadata and its
  * rocFFT plans.  Descriptor errors return SPDBA_EINVAL before any device call;
- * M beyond the kernels' register tiles (16 in FP32, 8 in FP64) returns
+ * M beyond the kernels' register tiles (16 in FP32, 8 in FP64; 8 for
+ * SPDBA_RCD_DIRECT) returns
  * SPDBA_EUNSUPPORTED; calls before bind return SPDBA_ESTATE; HIP and rocFFT
  * failures return SPDBA_EDEVICE / SPDBA_EFFT.  Calls are asynchronous on the
  * plan's stream unless stated.  A plan is not thread-safe.
@@ -56,7 +57,10 @@ extern "C" {
 enum {
     SPDBA_RCD_DENSE = 1u << 0,  /* Regular: every block updates, no measure   */
     SPDBA_RCD_PIN_K0 = 1u << 1, /* the block holding k = 0 is always active  */
-    SPDBA_RCD_TIMING = 1u << 2  /* HIP events around the stages (stats)       */
+    SPDBA_RCD_TIMING = 1u << 2, /* HIP events around the stages (stats)       */
+    SPDBA_RCD_DIRECT = 1u << 3  /* the coupled update as written in S4.2: per
+                                   mode a Cholesky solve of I + dt k^2 D (SPD),
+                                   instead of the eigen form; M <= 8           */
 };
 
 typedef struct {

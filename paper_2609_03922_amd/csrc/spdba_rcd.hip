@@ -41,6 +41,7 @@ namespace {
 
 constexpr double kTwoPiR = 6.283185307179586476925286766559;
 constexpr int kMaxMF32 = 16, kMaxMF64 = 8;  // register tiles that compile without scratch
+constexpr int kMaxMDirect = 8;              // the direct form's factor: MM (MM + 1) / 2 registers
 
 struct RGeo {
     int n[3], ln[3], b[3], lb[3], nbk[3], lnbk[3];
@@ -62,6 +63,8 @@ struct RCtx {
     uint32_t *count;     // active blocks
     unsigned long long *G;
     const void *vt;      // [MM][MM] V^T, zero-padded
+    const void *dm;      // [MM][MM] D, zero-padded (direct form)
+    int direct;
     const void *lam;     // [MM], zero-padded
     double tau2, dt, invN;
     double alpha, beta, r, a;
@@ -221,13 +224,18 @@ __global__ void __launch_bounds__(256) k_rcd_compact(RCtx c) {
     if (act) c.list[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)b;
 }
 
-template <typename T, int MM>
+// DIRECT: the coupled update of S4.2 as written, a per-mode solve of
+// (I + dt k^2 D) x = b by Cholesky (the matrix is symmetric positive definite:
+// D's eigenvalues are at least d_diag > 0), D in LDS in place of V^T, the
+// factor in registers with the reciprocals of its diagonal
+template <typename T, int MM, bool DIRECT>
 __global__ void __launch_bounds__(256) k_rcd_update(RCtx c) {
     using V2 = typename C2<T>::t;
-    __shared__ T vt[MM * MM];
+    __shared__ T vt[MM * MM];  // V^T, or D (DIRECT); zero-padded past M
     __shared__ T lam[MM];
     __shared__ double red[4];
-    for (int i = threadIdx.x; i < MM * MM; i += blockDim.x) vt[i] = reinterpret_cast<const T *>(c.vt)[i];
+    const T *msrc = reinterpret_cast<const T *>(DIRECT ? c.dm : c.vt);
+    for (int i = threadIdx.x; i < MM * MM; i += blockDim.x) vt[i] = msrc[i];
     for (int i = threadIdx.x; i < MM; i += blockDim.x) lam[i] = reinterpret_cast<const T *>(c.lam)[i];
     __syncthreads();
     V2 *q = reinterpret_cast<V2 *>(c.state);
@@ -263,6 +271,47 @@ __global__ void __launch_bounds__(256) k_rcd_update(RCtx c) {
             T xr[MM], xi[MM];
 #pragma unroll
             for (int m = 0; m < MM; ++m) xr[m] = xi[m] = (T)0;
+            if constexpr (DIRECT) {
+                T L[MM][MM];  // lower factor; L[j][j] holds 1 / l_jj
+#pragma unroll
+                for (int j = 0; j < MM; ++j) {
+                    asm volatile("" ::: "memory");  // D read from LDS where used
+                    T d = (T)1 + dk * vt[j * MM + j];
+#pragma unroll
+                    for (int k = 0; k < j; ++k) d = fma(-L[j][k], L[j][k], d);
+                    const T inv = (T)1 / sqrt(d);
+                    L[j][j] = inv;
+#pragma unroll
+                    for (int i = j + 1; i < MM; ++i) {
+                        T t = dk * vt[i * MM + j];
+#pragma unroll
+                        for (int k = 0; k < j; ++k) t = fma(-L[i][k], L[j][k], t);
+                        L[i][j] = t * inv;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < MM; ++i) {  // L y = b
+                    T yr = br[i], yi = bi[i];
+#pragma unroll
+                    for (int k = 0; k < i; ++k) {
+                        yr = fma(-L[i][k], xr[k], yr);
+                        yi = fma(-L[i][k], xi[k], yi);
+                    }
+                    xr[i] = yr * L[i][i];
+                    xi[i] = yi * L[i][i];
+                }
+#pragma unroll
+                for (int i = MM - 1; i >= 0; --i) {  // L^T x = y
+                    T yr = xr[i], yi = xi[i];
+#pragma unroll
+                    for (int k = i + 1; k < MM; ++k) {
+                        yr = fma(-L[k][i], xr[k], yr);
+                        yi = fma(-L[k][i], xi[k], yi);
+                    }
+                    xr[i] = yr * L[i][i];
+                    xi[i] = yi * L[i][i];
+                }
+            } else
 #pragma unroll
             for (int j = 0; j < MM; ++j) {
                 // keeps V^T in LDS: read where used (broadcasts), not hoisted
@@ -400,7 +449,8 @@ struct spdba_rcd_s {
     int nd = 0, esize = 8;
     hipStream_t stream = nullptr;
     size_t state_bytes = 0, work_bytes = 0;
-    size_t o_rhs = 0, o_fft = 0, o_ab = 0, o_anext = 0, o_mask = 0, o_list = 0, o_ctl = 0, o_vt = 0, o_lam = 0;
+    size_t o_rhs = 0, o_fft = 0, o_ab = 0, o_anext = 0, o_mask = 0, o_list = 0, o_ctl = 0, o_vt = 0, o_lam = 0,
+           o_dm = 0;
     size_t fft_work = 0;
     rocfft_plan fwd = nullptr, inv = nullptr, inv_oop = nullptr;
     bool inv_keeps = false;  // the out-of-place inverse leaves its input intact (probed at bind)
@@ -429,7 +479,8 @@ spdba_status validate(const spdba_rcd_desc *d) {
     if (!d) return SPDBA_EINVAL;
     if (d->ndim < 1 || d->ndim > 3 || d->M < 2) return SPDBA_EINVAL;
     if (d->dtype != SPDBA_F32 && d->dtype != SPDBA_F64) return SPDBA_EINVAL;
-    if (d->flags & ~(uint32_t)(SPDBA_RCD_DENSE | SPDBA_RCD_PIN_K0 | SPDBA_RCD_TIMING)) return SPDBA_EINVAL;
+    if (d->flags & ~(uint32_t)(SPDBA_RCD_DENSE | SPDBA_RCD_PIN_K0 | SPDBA_RCD_TIMING | SPDBA_RCD_DIRECT))
+        return SPDBA_EINVAL;
     for (int a = 0; a < 3; ++a) {
         const bool used = a >= 3 - d->ndim;
         if (!used && (d->dims[a] != 1 || d->block[a] != 1)) return SPDBA_EINVAL;
@@ -443,19 +494,26 @@ spdba_status validate(const spdba_rcd_desc *d) {
     const int64_t N = d->dims[0] * d->dims[1] * d->dims[2];
     if (N > (int64_t(1) << 31) || (int64_t)d->M * N > (int64_t(1) << 36)) return SPDBA_EINVAL;
     if (d->M > (d->dtype == SPDBA_F64 ? kMaxMF64 : kMaxMF32)) return SPDBA_EUNSUPPORTED;
+    if ((d->flags & SPDBA_RCD_DIRECT) && d->M > kMaxMDirect) return SPDBA_EUNSUPPORTED;
     return SPDBA_OK;
 }
 
-template <typename T>
-void launch_update_t(const RCtx &c, int grid, hipStream_t s) {
+template <typename T, bool DIRECT>
+void launch_update_d(const RCtx &c, int grid, hipStream_t s) {
     switch (c.mm) {
-        case 2: hipLaunchKernelGGL((k_rcd_update<T, 2>), dim3(grid), dim3(256), 0, s, c); break;
-        case 4: hipLaunchKernelGGL((k_rcd_update<T, 4>), dim3(grid), dim3(256), 0, s, c); break;
-        case 8: hipLaunchKernelGGL((k_rcd_update<T, 8>), dim3(grid), dim3(256), 0, s, c); break;
-        default:  // tile 16: FP32 only (validated at creation)
-            if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_rcd_update<T, 16>), dim3(grid), dim3(256), 0, s, c);
+        case 2: hipLaunchKernelGGL((k_rcd_update<T, 2, DIRECT>), dim3(grid), dim3(256), 0, s, c); break;
+        case 4: hipLaunchKernelGGL((k_rcd_update<T, 4, DIRECT>), dim3(grid), dim3(256), 0, s, c); break;
+        case 8: hipLaunchKernelGGL((k_rcd_update<T, 8, DIRECT>), dim3(grid), dim3(256), 0, s, c); break;
+        default:  // tile 16: FP32 eigen form only (validated at creation)
+            if constexpr (sizeof(T) == 4 && !DIRECT)
+                hipLaunchKernelGGL((k_rcd_update<T, 16, false>), dim3(grid), dim3(256), 0, s, c);
             break;
     }
+}
+template <typename T>
+void launch_update_t(const RCtx &c, int grid, hipStream_t s) {
+    if (c.direct) launch_update_d<T, true>(c, grid, s);
+    else launch_update_d<T, false>(c, grid, s);
 }
 
 template <typename T>
@@ -592,6 +650,7 @@ spdba_status spdba_rcd_create(const spdba_rcd_desc *desc, void *stream, spdba_rc
     c.a = desc->a;
     c.pin = (desc->flags & SPDBA_RCD_PIN_K0) ? 1 : 0;
     c.dense = (desc->flags & SPDBA_RCD_DENSE) ? 1 : 0;
+    c.direct = (desc->flags & SPDBA_RCD_DIRECT) ? 1 : 0;
     jacobi(c.M, diffusion(c.M, desc->d_diag, desc->d_cross), p->V, p->lam);
 
     auto fail = [&](spdba_status s) {
@@ -649,6 +708,8 @@ spdba_status spdba_rcd_create(const spdba_rcd_desc *desc, void *stream, spdba_rc
     o = al256(o + tsz * c.mm * c.mm);
     p->o_lam = o;
     o = al256(o + tsz * c.mm);
+    p->o_dm = o;
+    o = al256(o + tsz * c.mm * c.mm);
     p->work_bytes = o;
     *out = p;
     return SPDBA_OK;
@@ -677,23 +738,30 @@ spdba_status spdba_rcd_bind(spdba_rcd_plan p, void *d_state, void *d_work) {
     c.count = reinterpret_cast<uint32_t *>(p->d_work + p->o_ctl + 8);
     c.vt = p->d_work + p->o_vt;
     c.lam = p->d_work + p->o_lam;
+    c.dm = p->d_work + p->o_dm;
     if (p->fft_work &&
         rocfft_execution_info_set_work_buffer(p->info, p->d_work + p->o_fft, p->fft_work) != rocfft_status_success)
         return SPDBA_EFFT;
     // V^T and lambda, zero-padded to the register tile, in the kernels' precision
     const int M = c.M, mm = c.mm;
-    std::vector<double> vt((size_t)mm * mm, 0.0), lam(mm, 0.0);
+    std::vector<double> vt((size_t)mm * mm, 0.0), lam(mm, 0.0), dm((size_t)mm * mm, 0.0);
+    const std::vector<double> D = diffusion(M, p->d.d_diag, p->d.d_cross);
     for (int j = 0; j < M; ++j) {
         lam[j] = p->lam[j];
-        for (int i = 0; i < M; ++i) vt[(size_t)j * mm + i] = p->V[(size_t)i * M + j];
+        for (int i = 0; i < M; ++i) {
+            vt[(size_t)j * mm + i] = p->V[(size_t)i * M + j];
+            dm[(size_t)j * mm + i] = D[(size_t)j * M + i];
+        }
     }
     if (p->dbl) {
         RTRY_HIP(hipMemcpy(p->d_work + p->o_vt, vt.data(), 8 * vt.size(), hipMemcpyHostToDevice));
         RTRY_HIP(hipMemcpy(p->d_work + p->o_lam, lam.data(), 8 * lam.size(), hipMemcpyHostToDevice));
+        RTRY_HIP(hipMemcpy(p->d_work + p->o_dm, dm.data(), 8 * dm.size(), hipMemcpyHostToDevice));
     } else {
-        std::vector<float> vf(vt.begin(), vt.end()), lf(lam.begin(), lam.end());
+        std::vector<float> vf(vt.begin(), vt.end()), lf(lam.begin(), lam.end()), df(dm.begin(), dm.end());
         RTRY_HIP(hipMemcpy(p->d_work + p->o_vt, vf.data(), 4 * vf.size(), hipMemcpyHostToDevice));
         RTRY_HIP(hipMemcpy(p->d_work + p->o_lam, lf.data(), 4 * lf.size(), hipMemcpyHostToDevice));
+        RTRY_HIP(hipMemcpy(p->d_work + p->o_dm, df.data(), 4 * df.size(), hipMemcpyHostToDevice));
     }
     // the tables read back before any update: zero a_b, mask, G and the count
     RTRY_HIP(hipMemsetAsync(p->d_work + p->o_ab, 0, p->o_vt - p->o_ab, p->stream));

@@ -13,7 +13,7 @@ import numpy as np
 
 from . import spdba as S
 
-SPDBA_RCD_DENSE, SPDBA_RCD_PIN_K0, SPDBA_RCD_TIMING = 1, 2, 4
+SPDBA_RCD_DENSE, SPDBA_RCD_PIN_K0, SPDBA_RCD_TIMING, SPDBA_RCD_DIRECT = 1, 2, 4, 8
 
 # every entry point include/spdba_rcd.h declares
 RCD_EXPORTS = (
@@ -75,7 +75,8 @@ def eigen(M: int, d_diag: float, d_cross: float):
 
 
 def make_desc(M, ndim, n, block, dtype="f32", tau=1e-6, dt=0.01, dx=0.5, d_diag=0.5, d_cross=0.05,
-              alpha=1.0, beta=0.3, r=1.0, a=1.0, dense=False, pin_k0=True, timing=False) -> RcdDesc:
+              alpha=1.0, beta=0.3, r=1.0, a=1.0, dense=False, pin_k0=True, timing=False,
+              direct=False) -> RcdDesc:
     c = RcdDesc()
     c.ndim, c.M = ndim, M
     for ax in range(3):
@@ -84,7 +85,7 @@ def make_desc(M, ndim, n, block, dtype="f32", tau=1e-6, dt=0.01, dx=0.5, d_diag=
         c.block[ax] = block if used else 1
     c.dtype = S.DTYPES[dtype]
     c.flags = (SPDBA_RCD_DENSE if dense else 0) | (SPDBA_RCD_PIN_K0 if pin_k0 else 0) | \
-              (SPDBA_RCD_TIMING if timing else 0)
+              (SPDBA_RCD_TIMING if timing else 0) | (SPDBA_RCD_DIRECT if direct else 0)
     c.tau, c.dt, c.dx = tau, dt, dx
     c.d_diag, c.d_cross, c.alpha, c.beta, c.r, c.a = d_diag, d_cross, alpha, beta, r, a
     return c

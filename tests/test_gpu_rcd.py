@@ -8,7 +8,9 @@ b = q + dt R is the mode's component vector and u the unit roundoff.  The
 bound follows the eigen form: two contractions with an orthonormal V of M
 terms each (|V_j| = 1, so each is within (M + 1) u ||b||), one scaling at most
 1, and V rounded to the kernel's precision; the oracle's direct solve is
-within a few u (the system's condition number is below 2 here).
+within a few u (the system's condition number is below 2 here).  The direct
+form (Cholesky, backward stable with error of order (M + 1) u |L||L^T|, the
+matrix at least I so that ||x|| <= ||b||) meets the same bound.
 """
 import numpy as np
 import pytest
@@ -67,6 +69,13 @@ CASES = [
     (5, "f64", 3, 16, 4, 0.05, {}),
     (8, "f64", 2, 64, 16, 0.05, {}),
     (2, "f64", 1, 2048, 128, 0.05, {}),
+    # the direct form of S4.2 (per-mode Cholesky of I + dt k^2 D)
+    (2, "f32", 3, 32, 8, 0.05, {"direct": True}),
+    (3, "f32", 3, 32, 4, 0.05, {"direct": True}),
+    (8, "f32", 3, 32, 8, 0.03, {"direct": True}),
+    (8, "f32", 3, 32, 8, 0.0, {"direct": True, "dense": True}),
+    (5, "f64", 3, 16, 4, 0.05, {"direct": True}),
+    (8, "f64", 2, 64, 16, 0.05, {"direct": True}),
 ]
 
 

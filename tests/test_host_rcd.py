@@ -52,6 +52,7 @@ def _bad(**kw):
     ({"flags": 64}, spdba.SPDBA_EINVAL),
     ({"M": 17}, spdba.SPDBA_EUNSUPPORTED),
     ({"M": 9, "dtype": spdba.SPDBA_F64}, spdba.SPDBA_EUNSUPPORTED),
+    ({"M": 9, "flags": 2 | 8}, spdba.SPDBA_EUNSUPPORTED),   # the direct form: M <= 8
 ])
 def test_invalid_descriptors_rejected_without_device(kw, expect):
     assert rcd.create_status(_bad(**kw)) == expect
