@@ -882,21 +882,23 @@ def rcd_bench(args, cfg):
         p.destroy()
         return {"steps_per_s": K / (ms / 1e3), "field": f, "active_fraction_last": count / nb}
 
-    truth = run("f64", 0.0, True)["field"]
+    wide = M > 8  # no FP64 path: the FP32 Regular run is the reference
+    dense = run("f32", 0.0, True)
+    truth = dense["field"] if wide else run("f64", 0.0, True)["field"]
     tn = np.linalg.norm(truth)
 
     def err(f):
         return float(np.linalg.norm(f - truth) / tn)
 
-    dense = run("f32", 0.0, True)
     e_d = err(dense["field"])
+    bar = cfg["err_bar"] if wide else 1.1 * e_d
     sweep = []
     for tau in cfg["taus"]:
         r = run("f32", tau, False)
         sweep.append({"tau": tau, "rel_l2": err(r["field"]), "steps_per_s": round(r["steps_per_s"], 2),
                       "active_fraction_last_step": round(r["active_fraction_last"], 4)})
         print(f"rcd sweep tau={tau}: {sweep[-1]}", file=sys.stderr, flush=True)
-    ok = [s for s in sweep if s["rel_l2"] <= 1.1 * e_d]
+    ok = [s for s in sweep if s["rel_l2"] <= bar]
     # no threshold within the bar: the smallest one is timed, and tau* is null
     star = max(ok, key=lambda s: s["tau"]) if ok else min(sweep, key=lambda s: s["tau"])
 
@@ -929,6 +931,20 @@ def rcd_bench(args, cfg):
     achieved = upd_bytes / (st_sp[3] * 1e-3) / 1e9
     dense_bytes = (N // bvol) * bvol * 24 * M
     sps = star["steps_per_s"]
+    if M <= 16:  # register tiles on the vector units: bound by HBM
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                "frac": round(achieved / 8000.0, 4), "bytes_per_launch": int(upd_bytes),
+                "dense_achieved": round(dense_bytes / (st_d[3] * 1e-3) / 1e9, 1)}
+    else:  # two GEMMs per chunk on the matrix cores: 8 M^2 algorithmic flops per mode (FP32 MFMA peak)
+        fl = act_sp * bvol * 8.0 * M * M
+        fd = N * 8.0 * M * M
+        roof = {"bound": "mfma", "achieved": round(fl / (st_sp[3] * 1e-3) / 1e12, 2), "peak": 157.3,
+                "unit": "TFLOP/s", "frac": round(fl / (st_sp[3] * 1e-3) / 1e12 / 157.3, 4),
+                "flops_per_launch": int(fl), "hbm_GBps": round(achieved, 1),
+                "dense_achieved": round(fd / (st_d[3] * 1e-3) / 1e12, 2)}
+    roof.update({"traffic": None, "kernel": "k_rcd_update" if M <= 16 else "k_rcd_update_mfma",
+                 "avg_launch_us": round(st_sp[3] * 1e3, 2), "active_blocks_mean": round(act_sp, 1),
+                 "run": f"eager, stage events, last {min(20, K)} steps"})
     line = {
         "metric": "spectral-update Gpts/s + steps/s, sp-DBA vs dense on GPU at fixed L2 error",
         "value": round(N * sps / 1e9, 4), "unit": "Gpts/s", "n_gpus": 1, "steps": K, "warmup": W,
@@ -939,8 +955,9 @@ def rcd_bench(args, cfg):
                    "parallelism": "single-gpu"},
         "steps_per_s": sps, "dense_steps_per_s": round(dense["steps_per_s"], 2),
         "speedup_steps_vs_dense": round(sps / dense["steps_per_s"], 4),
-        "equal_error": {"truth": "FP64 Regular run on the GPU, fluctuation fields", "e_d": e_d,
-                        "bar": 1.1 * e_d, "sweep": sweep, "tau_star": star["tau"] if ok else None},
+        "equal_error": {"truth": ("FP32 Regular run (no FP64 path above M = 8), fluctuation fields" if wide
+                                  else "FP64 Regular run on the GPU, fluctuation fields"),
+                        "e_d": e_d, "bar": bar, "sweep": sweep, "tau_star": star["tau"] if ok else None},
         "stage_ms": {"transforms_and_reaction": round(st_sp[0], 4), "measure": round(st_sp[1], 4),
                      "compaction": round(st_sp[2], 4), "update": round(st_sp[3], 4)},
         "dense_stage_ms": {"transforms_and_reaction": round(st_d[0], 4), "update": round(st_d[3], 4)},
@@ -948,12 +965,7 @@ def rcd_bench(args, cfg):
         "update_stage_ms_four": upd_ms,
         "update_stage_speedup_vs_regular_direct": (round(upd_ms["regular_direct"] / upd_ms["spdba_eigen"], 4)
                                                    if "regular_direct" in upd_ms else None),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-                     "frac": round(achieved / 8000.0, 4), "traffic": None, "kernel": "k_rcd_update",
-                     "bytes_per_launch": int(upd_bytes), "avg_launch_us": round(st_sp[3] * 1e3, 2),
-                     "active_blocks_mean": round(act_sp, 1),
-                     "dense_achieved": round(dense_bytes / (st_d[3] * 1e-3) / 1e9, 1),
-                     "run": f"eager, stage events, last {min(20, K)} steps"},
+        "roofline": roof,
         "cpu_baseline": None if args.no_cpu else rcd_cpu_baseline(cfg, u0, np),
     }
     print(json.dumps(line))

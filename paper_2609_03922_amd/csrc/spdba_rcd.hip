@@ -21,9 +21,10 @@
 //
 // The per-mode contraction moves 24 M bytes (FP32) for 4 MM^2 FMAs; up to
 // MM = 16 that is well below the balance point of FP32 vector arithmetic
-// against HBM, so it runs on the vector units, not on matrix cores.  Tiles:
-// 2, 4, 8, 16 in FP32 and 2, 4, 8 in FP64, the widths whose operands stay in
-// registers without scratch.
+// against HBM, so it runs on the vector units (tiles 2, 4, 8, 16 in FP32 and
+// 2, 4, 8 in FP64, the widths whose operands stay in registers without
+// scratch).  Wider FP32 tiles (32, 48, 64) are dense contractions and run as two
+// GEMMs per chunk of modes on the matrix cores (k_rcd_update_mfma).
 
 #include <hip/hip_runtime.h>
 #include <rocfft/rocfft.h>
@@ -40,7 +41,7 @@
 namespace {
 
 constexpr double kTwoPiR = 6.283185307179586476925286766559;
-constexpr int kMaxMF32 = 16, kMaxMF64 = 8;  // register tiles that compile without scratch
+constexpr int kMaxMF32 = 64, kMaxMF64 = 8;  // FP32: register tiles to 16, matrix-core GEMMs to 64
 constexpr int kMaxMDirect = 8;              // the direct form's factor: MM (MM + 1) / 2 registers
 
 struct RGeo {
@@ -143,6 +144,37 @@ __global__ void __launch_bounds__(256) k_rcd_reaction(RCtx c, typename C2<T>::t 
             o.y = (T)0;
             w[m * N + p] = o;
         }
+    }
+}
+
+// R(u) for wide components (FP32, M > 16): u staged in LDS per thread
+// (component-major, thread-minor), the sum S first, then each component with
+// its periodic neighbours from LDS; the same interaction sum as above
+__global__ void __launch_bounds__(256) k_rcd_reaction_wide(RCtx c, float2 *w) {
+    __shared__ float us[64 * 256];
+    const int M = c.M, t = threadIdx.x;
+    const int64_t N = c.g.N;
+    const float invN = (float)c.invN, r = (float)c.r, a = (float)c.a, al = (float)c.alpha, be = (float)c.beta;
+    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x; p0 < N; p0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = p0 + t;  // N is a multiple of 256 or smaller than it: guard
+        const bool ok = p < N;
+        float S = 0.f;
+        for (int m = 0; m < M; ++m) {
+            const float u = ok ? w[m * N + p].x * invN : 0.f;
+            us[m * 256 + t] = u;
+            S = S + u;
+        }
+        if (ok)
+            for (int m = 0; m < M; ++m) {
+                const float u = us[m * 256 + t];
+                const float left = us[(m == 0 ? M - 1 : m - 1) * 256 + t];
+                const float right = us[(m == M - 1 ? 0 : m + 1) * 256 + t];
+                const float inter = be * (S - u) + al * (left + right);
+                float2 o;
+                o.x = u * (r - a * u - inter);
+                o.y = 0.f;
+                w[m * N + p] = o;
+            }
     }
 }
 
@@ -365,6 +397,129 @@ __global__ void __launch_bounds__(256) k_rcd_update(RCtx c) {
     }
 }
 
+// Wide components (FP32, 16 < M <= 64): the eigen form as two small GEMMs on
+// the matrix cores.  Per chunk of up to 64 modes of a block, B holds the
+// modes' b = q + dt R as 128 real columns (re, im of each mode) over MM
+// component rows; then
+//   W = V^T B        (MM x MM times MM x 128, v_mfma_f32_16x16x4f32)
+//   W_jc *= 1 / (1 + dt k^2 lambda_j)
+//   X = V W
+// and X goes back through LDS so that the stores are the loads' coalesced
+// pattern and the kept measure sums the components in order.  Four waves
+// share the 16 x 16 output tiles; LDS: V^T, V, B (reused for X), W.
+typedef float rcd_f4 __attribute__((ext_vector_type(4)));
+
+template <int MM>
+__global__ void __launch_bounds__(256) k_rcd_update_mfma(RCtx c) {
+    constexpr int NC = 128;      // real columns per chunk: 64 modes
+    constexpr int SA = MM + 4;   // row pitches padded so that the 64 lanes of an
+    constexpr int SB = NC + 16;  // operand read fall on distinct LDS banks
+    __shared__ float vtl[MM * SA];  // V^T (row j, column i)
+    __shared__ float vl[MM * SA];   // V (row m, column j)
+    __shared__ float bs[MM * SB];   // B, then X
+    __shared__ float ws[MM * SB];   // W
+    __shared__ float laml[MM];
+    __shared__ float dks[NC / 2];
+    __shared__ int64_t eofs[NC / 2];
+    __shared__ double red[4];
+    const float *vsrc = reinterpret_cast<const float *>(c.vt);  // V^T, zero-padded
+    for (int k = threadIdx.x; k < MM * MM; k += blockDim.x) {
+        const int r = k / MM, q2 = k - r * MM;
+        vtl[r * SA + q2] = vsrc[k];
+        vl[q2 * SA + r] = vsrc[k];
+    }
+    for (int k = threadIdx.x; k < MM; k += blockDim.x) laml[k] = reinterpret_cast<const float *>(c.lam)[k];
+    __syncthreads();
+    float2 *q = reinterpret_cast<float2 *>(c.state);
+    const float2 *rh = reinterpret_cast<const float2 *>(c.rhs);
+    const int M = c.M, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t N = c.g.N;
+    const float dt = (float)c.dt;
+    const int64_t total = c.dense ? c.g.nb : (int64_t)*c.count;
+    const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
+    const int64_t seg = (total + 7) >> 3;
+    const int64_t lo = std::min<int64_t>(total, seg * xcd), hi = std::min<int64_t>(total, seg * (xcd + 1));
+    const int row = lane & 15, kq = lane >> 4;  // MFMA operand position of this lane
+    for (int64_t ent = lo + (blockIdx.x >> 3); ent < hi; ent += per) {
+        const int64_t b = c.dense ? ent : (int64_t)c.list[ent];
+        double amax = 0.0;
+        for (int s0 = 0; s0 < c.g.bvol; s0 += NC / 2) {
+            const int nm = min(NC / 2, c.g.bvol - s0);  // modes in this chunk
+            if (t < NC / 2) {
+                int64_t e = 0;
+                double k2 = 0.0;
+                if (t < nm) mode_of(c.g, b, s0 + t, e, k2);
+                eofs[t] = e;
+                dks[t] = (float)(c.dt * k2);
+            }
+            __syncthreads();
+            for (int k = t; k < MM * (NC / 2); k += blockDim.x) {
+                const int i = k / (NC / 2), md = k - i * (NC / 2);
+                float2 bb = make_float2(0.f, 0.f);
+                if (i < M && md < nm) {
+                    const int64_t e = eofs[md];
+                    const float2 v = q[i * N + e], f = rh[i * N + e];
+                    bb.x = fmaf(dt, f.x, v.x);
+                    bb.y = fmaf(dt, f.y, v.y);
+                }
+                bs[i * SB + 2 * md] = bb.x;
+                bs[i * SB + 2 * md + 1] = bb.y;
+            }
+            __syncthreads();
+            // W = V^T B, scaled; tiles (jt, ct) dealt to the four waves
+            for (int tile = wave; tile < (MM / 16) * (NC / 16); tile += 4) {
+                const int jt = tile / (NC / 16), ct = tile - jt * (NC / 16);
+                rcd_f4 acc = {0.f, 0.f, 0.f, 0.f};
+                for (int k0 = 0; k0 < MM; k0 += 4) {
+                    const float av = vtl[(jt * 16 + row) * SA + k0 + kq];
+                    const float bv = bs[(k0 + kq) * SB + ct * 16 + row];
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+                }
+                const int col = ct * 16 + row;
+                const float dk = dks[col >> 1];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j = jt * 16 + kq * 4 + r;
+                    ws[j * SB + col] = acc[r] * (1.f / (1.f + dk * laml[j]));
+                }
+            }
+            __syncthreads();
+            // X = V W into bs
+            for (int tile = wave; tile < (MM / 16) * (NC / 16); tile += 4) {
+                const int mt = tile / (NC / 16), ct = tile - mt * (NC / 16);
+                rcd_f4 acc = {0.f, 0.f, 0.f, 0.f};
+                for (int k0 = 0; k0 < MM; k0 += 4) {
+                    const float av = vl[(mt * 16 + row) * SA + k0 + kq];
+                    const float bv = ws[(k0 + kq) * SB + ct * 16 + row];
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+                }
+                const int col = ct * 16 + row;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) bs[(mt * 16 + kq * 4 + r) * SB + col] = acc[r];
+            }
+            __syncthreads();
+            for (int k = t; k < M * (NC / 2); k += blockDim.x) {
+                const int i = k / (NC / 2), md = k - i * (NC / 2);
+                if (md < nm) q[i * N + eofs[md]] = make_float2(bs[i * SB + 2 * md], bs[i * SB + 2 * md + 1]);
+            }
+            if (c.keep && t < nm) {  // the measure of what is stored, components in order
+                double acc = 0.0;
+                for (int i = 0; i < M; ++i) acc = acc + rsq2((double)bs[i * SB + 2 * t], (double)bs[i * SB + 2 * t + 1]);
+                if (eofs[t] == 0) acc = 0.0;
+                amax = fmax(amax, acc);
+            }
+            __syncthreads();  // bs, eofs and dks are free for the next chunk
+        }
+        if (c.keep) {  // workgroup-uniform
+            amax = rwave_max(amax);
+            if (lane == 0) red[wave] = amax;
+            __syncthreads();
+            if (t == 0) c.anext[b] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+            __syncthreads();
+        }
+    }
+}
+
 template <typename T>
 __global__ void k_rcd_real_in(int64_t n, const T *re, typename C2<T>::t *out) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -434,7 +589,9 @@ std::vector<double> diffusion(int M, double dd, double dc) {
     return D;
 }
 
+// register tiles 2, 4, 8, 16; matrix-core tiles 32, 48, 64 (multiples of the 16-row MFMA tile)
 int tile_of(int M) {
+    if (M > 32) return M > 48 ? 64 : 48;
     int mm = 2;
     while (mm < M) mm <<= 1;
     return mm;
@@ -512,6 +669,20 @@ void launch_update_d(const RCtx &c, int grid, hipStream_t s) {
 }
 template <typename T>
 void launch_update_t(const RCtx &c, int grid, hipStream_t s) {
+    if constexpr (sizeof(T) == 4) {
+        if (c.mm == 32) {
+            hipLaunchKernelGGL((k_rcd_update_mfma<32>), dim3(grid), dim3(256), 0, s, c);
+            return;
+        }
+        if (c.mm == 48) {
+            hipLaunchKernelGGL((k_rcd_update_mfma<48>), dim3(grid), dim3(256), 0, s, c);
+            return;
+        }
+        if (c.mm == 64) {
+            hipLaunchKernelGGL((k_rcd_update_mfma<64>), dim3(grid), dim3(256), 0, s, c);
+            return;
+        }
+    }
     if (c.direct) launch_update_d<T, true>(c, grid, s);
     else launch_update_d<T, false>(c, grid, s);
 }
@@ -523,8 +694,11 @@ void launch_reaction_t(const RCtx &c, void *w, int grid, hipStream_t s) {
         case 2: hipLaunchKernelGGL((k_rcd_reaction<T, 2>), dim3(grid), dim3(256), 0, s, c, p); break;
         case 4: hipLaunchKernelGGL((k_rcd_reaction<T, 4>), dim3(grid), dim3(256), 0, s, c, p); break;
         case 8: hipLaunchKernelGGL((k_rcd_reaction<T, 8>), dim3(grid), dim3(256), 0, s, c, p); break;
-        default:  // tile 16: FP32 only (validated at creation)
+        case 16:  // FP32 only (validated at creation)
             if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_rcd_reaction<T, 16>), dim3(grid), dim3(256), 0, s, c, p);
+            break;
+        default:  // tiles 32 and 64: FP32 only, u staged in LDS
+            if constexpr (sizeof(T) == 4) hipLaunchKernelGGL(k_rcd_reaction_wide, dim3(grid), dim3(256), 0, s, c, p);
             break;
     }
 }

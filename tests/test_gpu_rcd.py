@@ -69,6 +69,12 @@ CASES = [
     (5, "f64", 3, 16, 4, 0.05, {}),
     (8, "f64", 2, 64, 16, 0.05, {}),
     (2, "f64", 1, 2048, 128, 0.05, {}),
+    # wide components (FP32, b staged in LDS): tiles 32 and 64
+    (24, "f32", 3, 16, 4, 0.05, {}),
+    (33, "f32", 2, 32, 8, 0.05, {}),
+    (48, "f32", 3, 16, 4, 0.05, {}),
+    (64, "f32", 3, 16, 4, 0.05, {}),
+    (48, "f32", 3, 16, 4, 0.0, {"dense": True}),
     # the direct form of S4.2 (per-mode Cholesky of I + dt k^2 D)
     (2, "f32", 3, 32, 8, 0.05, {"direct": True}),
     (3, "f32", 3, 32, 4, 0.05, {"direct": True}),
@@ -150,7 +156,8 @@ def test_rcd_field_round_trip():
     plan.destroy()
 
 
-@pytest.mark.parametrize("dtype,M,n,steps,tau", [("f64", 4, 16, 25, 0.02), ("f32", 8, 32, 10, 0.1)])
+@pytest.mark.parametrize("dtype,M,n,steps,tau", [("f64", 4, 16, 25, 0.02), ("f32", 8, 32, 10, 0.1),
+                                                 ("f32", 24, 16, 25, 0.1)])
 def test_rcd_trajectory_matches_oracle(dtype, M, n, steps, tau):
     """Full steps (transforms, Lotka--Volterra reaction, measure, update) from a
     perturbed homogeneous state: masks of every step agree with the oracle's
@@ -228,7 +235,7 @@ def test_rcd_full_size_sampled():
 
 
 @pytest.mark.parametrize("M,dtype,ndim,n,bl,tau", [(8, "f32", 3, 32, 8, 0.03), (4, "f64", 2, 64, 8, 0.05),
-                                                   (16, "f32", 2, 64, 16, 0.05)])
+                                                   (16, "f32", 2, 64, 16, 0.05), (48, "f32", 3, 16, 4, 0.05)])
 def test_rcd_kept_measure_over_a_sequence(M, dtype, ndim, n, bl, tau):
     """From the second update on, the measure is the one the last update kept
     for the blocks it stored (frozen blocks unchanged): before every update the

@@ -50,7 +50,7 @@ def _bad(**kw):
     ({"alpha": math.inf}, spdba.SPDBA_EINVAL),
     ({"dtype": 7}, spdba.SPDBA_EINVAL),
     ({"flags": 64}, spdba.SPDBA_EINVAL),
-    ({"M": 17}, spdba.SPDBA_EUNSUPPORTED),
+    ({"M": 65}, spdba.SPDBA_EUNSUPPORTED),
     ({"M": 9, "dtype": spdba.SPDBA_F64}, spdba.SPDBA_EUNSUPPORTED),
     ({"M": 9, "flags": 2 | 8}, spdba.SPDBA_EUNSUPPORTED),   # the direct form: M <= 8
 ])
