@@ -119,3 +119,32 @@ def perturbed_components(seed: int, M: int, dims, base: float, amp: float, dtype
     perturbation), shape (M, *dims)."""
     r = rng_for(seed, 7, M)
     return (base + r.uniform(-amp, amp, (M, *dims))).astype(dtype)
+
+
+def gaussian_packets(N: int, T: float, M: int, P0: float = 1000.0, w: float = 10.0,
+                     offsets=(-20.0, 0.0, 20.0), carriers=(-0.15, 0.0, 0.15)) -> np.ndarray:
+    """The transmitted field of the multimode tests: on the time grid of N
+    samples over the window T (t from -T/2), a sum of Gaussian packets of width
+    w at the given time offsets, each with amplitude sqrt(P0 / packets) and a
+    carrier 2 pi N/T times the given fraction; the same waveform on all M
+    modes.  Shape (M, N), complex128."""
+    t = (np.arange(N) - N // 2) * (T / N)
+    A0 = np.sqrt(P0 / len(offsets))
+    e = np.zeros(N, np.complex128)
+    for tq, cq in zip(offsets, carriers):
+        e = e + A0 * np.exp(-((t - tq) ** 2) / (2.0 * w * w)) * np.exp(1j * 2.0 * np.pi * N / T * cq * t)
+    return np.tile(e, (M, 1))
+
+
+def hermitian_coupling(seed: int, M: int) -> np.ndarray:
+    """A constant Hermitian mode-coupling matrix: real N(0,1) diagonal, real and
+    imaginary parts of the upper triangle N(0,1), the lower triangle by
+    Hermitian symmetry, scaled so that the mean of |K_ij|^2 is 1."""
+    r = rng_for(seed, 9, M)
+    K = np.zeros((M, M), np.complex128)
+    for i in range(M):
+        K[i, i] = r.standard_normal()
+        for j in range(i + 1, M):
+            K[i, j] = r.standard_normal() + 1j * r.standard_normal()
+            K[j, i] = np.conj(K[i, j])
+    return K / np.sqrt(np.mean(np.abs(K) ** 2))
