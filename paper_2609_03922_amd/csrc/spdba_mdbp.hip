@@ -1,0 +1,636 @@
+// sp-DBA for multimode digital backpropagation (Supplementary S5): kernels
+// and the C ABI of include/spdba_mdbp.h.
+//
+//   k_md_measure   per block of bins: a_b = max of sum_m |E_m|^2 (FP64, modes
+//                  in order, omega = 0 left out); blocks dealt to the XCDs in
+//                  eight contiguous ranges
+//   k_md_gmax      G = max_b a_b (one atomic max per workgroup)
+//   k_md_compact   mask and an unordered list of the active blocks
+//   k_md_update    persistent walk of the list, one list segment per XCD; per
+//                  bin the M modes in registers, then E'_m = h(omega) sum_j
+//                  W_mj E_j row by row with W in LDS (read as broadcasts)
+//   k_md_kerr      time domain: E_m <- E_m / n exp(i gamma 8/9 P dz), P the
+//                  total power of the sample (the phase in FP64)
+//
+// Per bin the update moves 16 M bytes (FP32) for 4 M^2 FMAs: up to M = 16
+// below the FP32 vector balance point against HBM, above it compute-heavy;
+// the matrix W stays in LDS, the modes in registers.
+
+#include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "spdba_internal.h"
+#include "spdba_mdbp.h"
+
+namespace {
+
+constexpr int kMaxF32 = 64, kMaxF64 = 32;
+
+struct MCtx {
+    int M, mm;
+    int64_t n, nb;
+    int B, lB;
+    void *E;             // M x n complex (the state)
+    double *ab;
+    uint8_t *mask;
+    uint32_t *list;
+    uint32_t *count;
+    unsigned long long *G;
+    const void *W;       // [mm][mm] complex, zero-padded
+    double tau2, T, dz, alpha, beta2, gamma, invn;
+    int pin, dense;
+};
+
+template <typename T> struct V2T;
+template <> struct V2T<float> { using t = float2; };
+template <> struct V2T<double> { using t = double2; };
+
+__device__ __forceinline__ double msq2(double x, double y) { return x * x + y * y; }
+
+__device__ __forceinline__ double mwave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__global__ void k_md_reset(MCtx c) {
+    if (threadIdx.x == 0) {
+        *c.G = 0ull;
+        *c.count = 0u;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_md_measure(MCtx c) {
+    __shared__ double red[4];
+    using V2 = typename V2T<T>::t;
+    const V2 *E = reinterpret_cast<const V2 *>(c.E);
+    const int64_t per = (c.nb + 7) >> 3;
+    const int64_t b = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (b >= c.nb) return;  // workgroup-uniform, before any barrier
+    double amax = 0.0;
+    for (int s = threadIdx.x; s < c.B; s += blockDim.x) {
+        const int64_t e = (b << c.lB) + s;
+        double acc = 0.0;
+        for (int m = 0; m < c.M; ++m) {
+            const V2 v = E[m * c.n + e];
+            acc = acc + msq2((double)v.x, (double)v.y);
+        }
+        if (e == 0) acc = 0.0;
+        amax = fmax(amax, acc);
+    }
+    amax = mwave_max(amax);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, red[k]);
+        c.ab[b] = m;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_md_gmax(MCtx c) {
+    __shared__ double red[16];
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double m = b < c.nb ? c.ab[b] : 0.0;
+    m = mwave_max(m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double g = red[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) g = fmax(g, red[k]);
+        if (g > 0.0) atomicMax(c.G, (unsigned long long)__double_as_longlong(g));
+    }
+}
+
+__global__ void __launch_bounds__(256) k_md_compact(MCtx c) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    bool act = false;
+    if (b < c.nb) {
+        const double G = __longlong_as_double((long long)*c.G);
+        act = (c.pin && b == 0) || c.ab[b] > c.tau2 * G;
+        c.mask[b] = act ? 1 : 0;
+    }
+    const unsigned long long bal = __ballot(act);
+    if (bal == 0ull) return;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(c.count, (uint32_t)__popcll(bal));
+    base = __shfl(base, 0, 64);
+    if (act) c.list[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)b;
+}
+
+template <typename T, int MM>
+__global__ void __launch_bounds__(256) k_md_update(MCtx c) {
+    using V2 = typename V2T<T>::t;
+    __shared__ V2 w[MM * MM];
+    for (int i = threadIdx.x; i < MM * MM; i += blockDim.x) w[i] = reinterpret_cast<const V2 *>(c.W)[i];
+    __syncthreads();
+    V2 *E = reinterpret_cast<V2 *>(c.E);
+    const int M = c.M;
+    const int64_t n = c.n;
+    const int64_t total = c.dense ? c.nb : (int64_t)*c.count;
+    const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
+    const int64_t seg = (total + 7) >> 3;
+    const int64_t lo = std::min<int64_t>(total, seg * xcd), hi = std::min<int64_t>(total, seg * (xcd + 1));
+    const double att = exp(-c.alpha * c.dz / 4.0);
+    for (int64_t ent = lo + (blockIdx.x >> 3); ent < hi; ent += per) {
+        const int64_t b = c.dense ? ent : (int64_t)c.list[ent];
+        for (int s = threadIdx.x; s < c.B; s += blockDim.x) {
+            const int64_t e = (b << c.lB) + s;
+            const int64_t si = e <= ((n - 1) >> 1) ? e : e - n;
+            const double om = 6.283185307179586476925286766559 * (double)si / c.T;
+            const double ph = c.beta2 * 0.5 * om * om * c.dz * 0.5;
+            double sp, cp;
+            sincos(ph, &sp, &cp);
+            const T hr = (T)(att * cp), hi2 = (T)(att * sp);
+            T br[MM], bi[MM];
+#pragma unroll
+            for (int j = 0; j < MM; ++j) {
+                br[j] = bi[j] = (T)0;
+                if (j < M) {
+                    const V2 v = E[j * n + e];
+                    br[j] = v.x;
+                    bi[j] = v.y;
+                }
+            }
+            for (int m = 0; m < M; ++m) {
+                T xr = (T)0, xi = (T)0;
+#pragma unroll
+                for (int j = 0; j < MM; ++j) {
+                    const V2 wv = w[m * MM + j];
+                    xr = fma(wv.x, br[j], xr);
+                    xr = fma(-wv.y, bi[j], xr);
+                    xi = fma(wv.x, bi[j], xi);
+                    xi = fma(wv.y, br[j], xi);
+                }
+                V2 o;
+                o.x = hr * xr - hi2 * xi;
+                o.y = hr * xi + hi2 * xr;
+                E[m * n + e] = o;
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_md_kerr(MCtx c) {
+    using V2 = typename V2T<T>::t;
+    V2 *E = reinterpret_cast<V2 *>(c.E);
+    const double k = c.gamma * (8.0 / 9.0) * c.dz;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < c.n; p += (int64_t)gridDim.x * blockDim.x) {
+        double P = 0.0;
+        for (int m = 0; m < c.M; ++m) {
+            const V2 v = E[m * c.n + p];
+            P = P + msq2((double)v.x * c.invn, (double)v.y * c.invn);
+        }
+        double sp, cp;
+        sincos(k * P, &sp, &cp);
+        const T cr = (T)(cp * c.invn), ci = (T)(sp * c.invn);
+        for (int m = 0; m < c.M; ++m) {
+            const V2 v = E[m * c.n + p];
+            V2 o;
+            o.x = cr * v.x - ci * v.y;
+            o.y = cr * v.y + ci * v.x;
+            E[m * c.n + p] = o;
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_md_scale(int64_t cnt, const typename V2T<T>::t *in, typename V2T<T>::t *out, T s) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+        typename V2T<T>::t o = in[i];
+        o.x *= s;
+        o.y *= s;
+        out[i] = o;
+    }
+}
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int64_t v) { int l = 0; while ((int64_t(1) << l) < v) ++l; return l; }
+
+using cd = std::complex<double>;
+
+// exp(i delta K) by scaling and squaring of the Taylor series (FP64)
+std::vector<cd> expm_i(int M, const double *K, double delta) {
+    std::vector<cd> A((size_t)M * M), R((size_t)M * M, 0.0), term, tmp((size_t)M * M);
+    double nrm = 0.0;
+    for (int i = 0; i < M; ++i) {
+        double row = 0.0;
+        for (int j = 0; j < M; ++j) {
+            A[(size_t)i * M + j] = cd(0.0, delta) * cd(K[2 * ((size_t)i * M + j)], K[2 * ((size_t)i * M + j) + 1]);
+            row += std::abs(A[(size_t)i * M + j]);
+        }
+        nrm = std::max(nrm, row);
+    }
+    int sq = 0;
+    while (nrm > 0.25) {
+        nrm *= 0.5;
+        ++sq;
+    }
+    const double sc = std::ldexp(1.0, -sq);
+    for (auto &v : A) v *= sc;
+    auto mul = [&](const std::vector<cd> &X, const std::vector<cd> &Y, std::vector<cd> &Z) {
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j) {
+                cd s = 0.0;
+                for (int k = 0; k < M; ++k) s += X[(size_t)i * M + k] * Y[(size_t)k * M + j];
+                Z[(size_t)i * M + j] = s;
+            }
+    };
+    term.assign((size_t)M * M, 0.0);
+    for (int i = 0; i < M; ++i) term[(size_t)i * M + i] = R[(size_t)i * M + i] = 1.0;
+    for (int k = 1; k <= 24; ++k) {  // |A| <= 1/4: the remainder is below 1e-30
+        mul(term, A, tmp);
+        for (auto &v : tmp) v /= (double)k;
+        term.swap(tmp);
+        for (size_t i = 0; i < R.size(); ++i) R[i] += term[i];
+    }
+    for (int s = 0; s < sq; ++s) {
+        mul(R, R, tmp);
+        R.swap(tmp);
+    }
+    return R;
+}
+
+int tile_of(int M) {
+    int mm = 2;
+    while (mm < M) mm <<= 1;
+    return mm;
+}
+
+}  // namespace
+
+struct spdba_mdbp_s {
+    spdba_mdbp_desc d{};
+    MCtx c{};
+    bool dbl = false, timing = false, bound = false;
+    int esize = 8, cu = 256;
+    hipStream_t stream = nullptr;
+    size_t state_bytes = 0, work_bytes = 0, fft_work = 0;
+    size_t o_fft = 0, o_ab = 0, o_mask = 0, o_list = 0, o_ctl = 0, o_w = 0, o_tmp = 0;
+    rocfft_plan fwd = nullptr, inv = nullptr;
+    rocfft_execution_info info = nullptr;
+    std::vector<cd> W;
+    char *d_state = nullptr, *d_work = nullptr;
+    hipEvent_t ev[6] = {};
+    bool ev_valid = false;
+    float lin_ms = 0.f;
+};
+
+namespace {
+
+#define MTRY_HIP(x)                                   \
+    do {                                              \
+        if ((x) != hipSuccess) return SPDBA_EDEVICE;  \
+    } while (0)
+#define MTRY(x)                                       \
+    do {                                              \
+        spdba_status s_ = (x);                        \
+        if (s_ != SPDBA_OK) return s_;                \
+    } while (0)
+
+spdba_status validate(const spdba_mdbp_desc *d, const double *K) {
+    if (!d || !K) return SPDBA_EINVAL;
+    if (d->M < 1 || d->dtype < SPDBA_F32 || d->dtype > SPDBA_F64) return SPDBA_EINVAL;
+    if (d->flags & ~(uint32_t)(SPDBA_MDBP_DENSE | SPDBA_MDBP_PIN_K0 | SPDBA_MDBP_TIMING)) return SPDBA_EINVAL;
+    if (!pow2(d->n) || d->n < 16 || d->n > (int64_t(1) << 28)) return SPDBA_EINVAL;
+    if (!pow2(d->block) || d->block > d->n) return SPDBA_EINVAL;
+    const double vals[] = {d->tau, d->T, d->dz, d->alpha, d->beta2, d->gamma};
+    for (double v : vals)
+        if (!std::isfinite(v)) return SPDBA_EINVAL;
+    if (d->tau < 0 || d->T <= 0 || d->dz <= 0) return SPDBA_EINVAL;
+    if ((int64_t)d->M * d->n > (int64_t(1) << 34)) return SPDBA_EINVAL;
+    if (d->M > (d->dtype == SPDBA_F64 ? kMaxF64 : kMaxF32)) return SPDBA_EUNSUPPORTED;
+    double scale = 0.0;
+    for (int i = 0; i < d->M * d->M * 2; ++i) {
+        if (!std::isfinite(K[i])) return SPDBA_EINVAL;
+        scale = std::max(scale, std::fabs(K[i]));
+    }
+    for (int i = 0; i < d->M; ++i)
+        for (int j = 0; j < d->M; ++j) {
+            const double *a = K + 2 * ((size_t)i * d->M + j), *b = K + 2 * ((size_t)j * d->M + i);
+            if (std::fabs(a[0] - b[0]) > 1e-12 * scale || std::fabs(a[1] + b[1]) > 1e-12 * scale) return SPDBA_EINVAL;
+        }
+    return SPDBA_OK;
+}
+
+template <typename T>
+void launch_upd(const MCtx &c, int grid, hipStream_t s) {
+    switch (c.mm) {
+        case 2: hipLaunchKernelGGL((k_md_update<T, 2>), dim3(grid), dim3(256), 0, s, c); break;
+        case 4: hipLaunchKernelGGL((k_md_update<T, 4>), dim3(grid), dim3(256), 0, s, c); break;
+        case 8: hipLaunchKernelGGL((k_md_update<T, 8>), dim3(grid), dim3(256), 0, s, c); break;
+        case 16: hipLaunchKernelGGL((k_md_update<T, 16>), dim3(grid), dim3(256), 0, s, c); break;
+        case 32: hipLaunchKernelGGL((k_md_update<T, 32>), dim3(grid), dim3(256), 0, s, c); break;
+        default:  // tile 64: FP32 only (validated at creation)
+            if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_md_update<T, 64>), dim3(grid), dim3(256), 0, s, c);
+            break;
+    }
+}
+
+spdba_status exec(spdba_mdbp_plan p, rocfft_plan f, void *buf) {
+    void *ib[1] = {buf};
+    return rocfft_execute(f, ib, nullptr, p->info) == rocfft_status_success ? SPDBA_OK : SPDBA_EFFT;
+}
+
+spdba_status linear_half(spdba_mdbp_plan p) {
+    const MCtx &c = p->c;
+    if (!c.dense) {
+        hipLaunchKernelGGL(k_md_reset, dim3(1), dim3(64), 0, p->stream, c);
+        const int nbg = (int)(((c.nb + 7) >> 3) << 3);
+        if (p->dbl) hipLaunchKernelGGL(k_md_measure<double>, dim3(nbg), dim3(256), 0, p->stream, c);
+        else hipLaunchKernelGGL(k_md_measure<float>, dim3(nbg), dim3(256), 0, p->stream, c);
+        hipLaunchKernelGGL(k_md_gmax, dim3((unsigned)((c.nb + 1023) / 1024)), dim3(1024), 0, p->stream, c);
+        hipLaunchKernelGGL(k_md_compact, dim3((unsigned)((c.nb + 255) / 256)), dim3(256), 0, p->stream, c);
+        MTRY_HIP(hipGetLastError());
+    }
+    const int grid = (int)(std::max<int64_t>(8, std::min<int64_t>(c.nb, (int64_t)p->cu * 8)) + 7) / 8 * 8;
+    if (p->dbl) launch_upd<double>(c, grid, p->stream);
+    else launch_upd<float>(c, grid, p->stream);
+    MTRY_HIP(hipGetLastError());
+    return SPDBA_OK;
+}
+
+void rec(spdba_mdbp_plan p, int i) {
+    if (p->timing) (void)hipEventRecord(p->ev[i], p->stream);
+}
+
+spdba_status one_step(spdba_mdbp_plan p) {
+    const MCtx &c = p->c;
+    rec(p, 0);
+    MTRY(linear_half(p));
+    rec(p, 1);
+    MTRY(exec(p, p->inv, p->d_state));
+    rec(p, 2);
+    const int grid = (int)std::min<int64_t>((c.n + 255) / 256, (int64_t)p->cu * 16);
+    if (p->dbl) hipLaunchKernelGGL(k_md_kerr<double>, dim3(grid), dim3(256), 0, p->stream, c);
+    else hipLaunchKernelGGL(k_md_kerr<float>, dim3(grid), dim3(256), 0, p->stream, c);
+    MTRY_HIP(hipGetLastError());
+    rec(p, 3);
+    MTRY(exec(p, p->fwd, p->d_state));
+    rec(p, 4);
+    MTRY(linear_half(p));
+    rec(p, 5);
+    p->ev_valid = p->timing;
+    return SPDBA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+spdba_status spdba_mdbp_coupling(int32_t M, const double *K, double delta, double *out) {
+    if (M < 1 || M > 1024 || !K || !out || !std::isfinite(delta)) return SPDBA_EINVAL;
+    const std::vector<cd> W = expm_i(M, K, delta);
+    for (size_t i = 0; i < W.size(); ++i) {
+        out[2 * i] = W[i].real();
+        out[2 * i + 1] = W[i].imag();
+    }
+    return SPDBA_OK;
+}
+
+spdba_status spdba_mdbp_create(const spdba_mdbp_desc *desc, const double *K, void *stream, spdba_mdbp_plan *out) {
+    if (!out) return SPDBA_EINVAL;
+    *out = nullptr;
+    MTRY(validate(desc, K));
+    spdba_mdbp_plan p = new (std::nothrow) spdba_mdbp_s();
+    if (!p) return SPDBA_EDEVICE;
+    p->d = *desc;
+    p->dbl = desc->dtype == SPDBA_F64;
+    p->esize = p->dbl ? 16 : 8;
+    p->timing = (desc->flags & SPDBA_MDBP_TIMING) != 0;
+    p->stream = reinterpret_cast<hipStream_t>(stream);
+    MCtx &c = p->c;
+    c.M = desc->M;
+    c.mm = tile_of(desc->M);
+    c.n = desc->n;
+    c.B = desc->block;
+    c.lB = ilog2(desc->block);
+    c.nb = desc->n / desc->block;
+    c.tau2 = desc->tau * desc->tau;
+    c.T = desc->T;
+    c.dz = desc->dz;
+    c.alpha = desc->alpha;
+    c.beta2 = desc->beta2;
+    c.gamma = desc->gamma;
+    c.invn = 1.0 / (double)desc->n;
+    c.pin = (desc->flags & SPDBA_MDBP_PIN_K0) ? 1 : 0;
+    c.dense = (desc->flags & SPDBA_MDBP_DENSE) ? 1 : 0;
+    p->W = expm_i(c.M, K, desc->dz / 2.0);
+    auto fail = [&](spdba_status s) {
+        spdba_mdbp_destroy(p);
+        return s;
+    };
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(SPDBA_EDEVICE);
+    p->cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    if (spdba::fft_setup() != SPDBA_OK) return fail(SPDBA_EFFT);
+    size_t len[1] = {(size_t)c.n};
+    const rocfft_precision prec = p->dbl ? rocfft_precision_double : rocfft_precision_single;
+    if (rocfft_plan_create(&p->fwd, rocfft_placement_inplace, rocfft_transform_type_complex_forward, prec, 1, len,
+                           (size_t)c.M, nullptr) != rocfft_status_success ||
+        rocfft_plan_create(&p->inv, rocfft_placement_inplace, rocfft_transform_type_complex_inverse, prec, 1, len,
+                           (size_t)c.M, nullptr) != rocfft_status_success)
+        return fail(SPDBA_EFFT);
+    size_t w1 = 0, w2 = 0;
+    if (rocfft_plan_get_work_buffer_size(p->fwd, &w1) != rocfft_status_success ||
+        rocfft_plan_get_work_buffer_size(p->inv, &w2) != rocfft_status_success)
+        return fail(SPDBA_EFFT);
+    p->fft_work = std::max(w1, w2);
+    if (rocfft_execution_info_create(&p->info) != rocfft_status_success ||
+        rocfft_execution_info_set_stream(p->info, p->stream) != rocfft_status_success)
+        return fail(SPDBA_EFFT);
+    if (p->timing)
+        for (auto &e : p->ev)
+            if (hipEventCreate(&e) != hipSuccess) return fail(SPDBA_EDEVICE);
+    const size_t spec = (size_t)c.M * c.n * p->esize;
+    p->state_bytes = spec;
+    size_t o = 0;
+    p->o_fft = o;
+    o = al256(o + p->fft_work);
+    p->o_ab = o;
+    o = al256(o + sizeof(double) * c.nb);
+    p->o_mask = o;
+    o = al256(o + c.nb);
+    p->o_list = o;
+    o = al256(o + sizeof(uint32_t) * c.nb);
+    p->o_ctl = o;
+    o = al256(o + 16);
+    p->o_w = o;
+    o = al256(o + (size_t)p->esize * c.mm * c.mm);
+    p->o_tmp = o;  // get_field's copy
+    o = al256(o + spec);
+    p->work_bytes = o;
+    *out = p;
+    return SPDBA_OK;
+}
+
+spdba_status spdba_mdbp_buffer_sizes(spdba_mdbp_plan p, size_t *sb, size_t *wb) {
+    if (!p || !sb || !wb) return SPDBA_EINVAL;
+    *sb = p->state_bytes;
+    *wb = p->work_bytes;
+    return SPDBA_OK;
+}
+
+spdba_status spdba_mdbp_bind(spdba_mdbp_plan p, void *d_state, void *d_work) {
+    if (!p || !d_state || !d_work) return SPDBA_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(d_state) & 255) || (reinterpret_cast<uintptr_t>(d_work) & 255))
+        return SPDBA_EINVAL;
+    p->d_state = static_cast<char *>(d_state);
+    p->d_work = static_cast<char *>(d_work);
+    MCtx &c = p->c;
+    c.E = p->d_state;
+    c.ab = reinterpret_cast<double *>(p->d_work + p->o_ab);
+    c.mask = reinterpret_cast<uint8_t *>(p->d_work + p->o_mask);
+    c.list = reinterpret_cast<uint32_t *>(p->d_work + p->o_list);
+    c.G = reinterpret_cast<unsigned long long *>(p->d_work + p->o_ctl);
+    c.count = reinterpret_cast<uint32_t *>(p->d_work + p->o_ctl + 8);
+    c.W = p->d_work + p->o_w;
+    if (p->fft_work &&
+        rocfft_execution_info_set_work_buffer(p->info, p->d_work + p->o_fft, p->fft_work) != rocfft_status_success)
+        return SPDBA_EFFT;
+    const int M = c.M, mm = c.mm;
+    std::vector<double> wd((size_t)2 * mm * mm, 0.0);
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) {
+            wd[2 * ((size_t)i * mm + j)] = p->W[(size_t)i * M + j].real();
+            wd[2 * ((size_t)i * mm + j) + 1] = p->W[(size_t)i * M + j].imag();
+        }
+    if (p->dbl) {
+        MTRY_HIP(hipMemcpy(p->d_work + p->o_w, wd.data(), 8 * wd.size(), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> wf(wd.begin(), wd.end());
+        MTRY_HIP(hipMemcpy(p->d_work + p->o_w, wf.data(), 4 * wf.size(), hipMemcpyHostToDevice));
+    }
+    MTRY_HIP(hipMemsetAsync(p->d_work + p->o_ab, 0, p->o_w - p->o_ab, p->stream));
+    MTRY_HIP(hipStreamSynchronize(p->stream));
+    p->bound = true;
+    return SPDBA_OK;
+}
+
+spdba_status spdba_mdbp_set_spectrum(spdba_mdbp_plan p, const void *src) {
+    if (!p || !src) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    MTRY_HIP(hipMemcpyAsync(p->d_state, src, p->state_bytes, hipMemcpyDeviceToDevice, p->stream));
+    return SPDBA_OK;
+}
+
+spdba_status spdba_mdbp_get_spectrum(spdba_mdbp_plan p, void *dst) {
+    if (!p || !dst) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    MTRY_HIP(hipMemcpyAsync(dst, p->d_state, p->state_bytes, hipMemcpyDeviceToDevice, p->stream));
+    return SPDBA_OK;
+}
+
+spdba_status spdba_mdbp_set_field(spdba_mdbp_plan p, const void *src) {
+    MTRY(spdba_mdbp_set_spectrum(p, src));
+    return exec(p, p->fwd, p->d_state);
+}
+
+spdba_status spdba_mdbp_get_field(spdba_mdbp_plan p, void *dst) {
+    if (!p || !dst) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    char *tmp = p->d_work + p->o_tmp;
+    MTRY_HIP(hipMemcpyAsync(tmp, p->d_state, p->state_bytes, hipMemcpyDeviceToDevice, p->stream));
+    MTRY(exec(p, p->inv, tmp));
+    const int64_t cnt = (int64_t)p->c.M * p->c.n;
+    const int grid = (int)std::min<int64_t>((cnt + 255) / 256, (int64_t)p->cu * 16);
+    if (p->dbl)
+        hipLaunchKernelGGL(k_md_scale<double>, dim3(grid), dim3(256), 0, p->stream, cnt,
+                           reinterpret_cast<const double2 *>(tmp), static_cast<double2 *>(dst), p->c.invn);
+    else
+        hipLaunchKernelGGL(k_md_scale<float>, dim3(grid), dim3(256), 0, p->stream, cnt,
+                           reinterpret_cast<const float2 *>(tmp), static_cast<float2 *>(dst), (float)p->c.invn);
+    MTRY_HIP(hipGetLastError());
+    return SPDBA_OK;
+}
+
+spdba_status spdba_mdbp_apply(spdba_mdbp_plan p) {
+    if (!p) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    return linear_half(p);
+}
+
+spdba_status spdba_mdbp_step(spdba_mdbp_plan p, int32_t n) {
+    if (!p || n < 0) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    for (int32_t i = 0; i < n; ++i) MTRY(one_step(p));
+    return SPDBA_OK;
+}
+
+spdba_status spdba_mdbp_indicator(spdba_mdbp_plan p, double *ab, size_t n, double *G) {
+    if (!p || (ab && n < (size_t)p->c.nb)) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    MTRY_HIP(hipStreamSynchronize(p->stream));
+    if (ab) MTRY_HIP(hipMemcpy(ab, p->c.ab, sizeof(double) * p->c.nb, hipMemcpyDeviceToHost));
+    if (G) {
+        unsigned long long bits = 0;
+        MTRY_HIP(hipMemcpy(&bits, p->c.G, 8, hipMemcpyDeviceToHost));
+        std::memcpy(G, &bits, 8);
+    }
+    return SPDBA_OK;
+}
+
+spdba_status spdba_mdbp_active_mask(spdba_mdbp_plan p, uint8_t *mask, size_t n, int64_t *count) {
+    if (!p || (mask && n < (size_t)p->c.nb)) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    MTRY_HIP(hipStreamSynchronize(p->stream));
+    if (p->c.dense) {
+        if (mask) std::memset(mask, 1, p->c.nb);
+        if (count) *count = p->c.nb;
+        return SPDBA_OK;
+    }
+    if (mask) MTRY_HIP(hipMemcpy(mask, p->c.mask, p->c.nb, hipMemcpyDeviceToHost));
+    if (count) {
+        uint32_t v = 0;
+        MTRY_HIP(hipMemcpy(&v, p->c.count, 4, hipMemcpyDeviceToHost));
+        *count = v;
+    }
+    return SPDBA_OK;
+}
+
+spdba_status spdba_mdbp_stats(spdba_mdbp_plan p, spdba_mdbp_stats_t *out) {
+    if (!p || !out) return SPDBA_EINVAL;
+    if (!p->bound) return SPDBA_ESTATE;
+    std::memset(out, 0, sizeof(*out));
+    out->n_blocks = p->c.nb;
+    MTRY(spdba_mdbp_active_mask(p, nullptr, 0, &out->active_blocks));
+    if (!p->c.dense) MTRY(spdba_mdbp_indicator(p, nullptr, 0, &out->G));
+    if (p->timing && p->ev_valid) {
+        float a = 0.f, b = 0.f, t1 = 0.f, t2 = 0.f, k = 0.f;
+        (void)hipEventElapsedTime(&a, p->ev[0], p->ev[1]);
+        (void)hipEventElapsedTime(&t1, p->ev[1], p->ev[2]);
+        (void)hipEventElapsedTime(&k, p->ev[2], p->ev[3]);
+        (void)hipEventElapsedTime(&t2, p->ev[3], p->ev[4]);
+        (void)hipEventElapsedTime(&b, p->ev[4], p->ev[5]);
+        out->stage_ms[0] = a + b;
+        out->stage_ms[1] = t1 + t2;
+        out->stage_ms[2] = k;
+    }
+    return SPDBA_OK;
+}
+
+spdba_status spdba_mdbp_destroy(spdba_mdbp_plan p) {
+    if (!p) return SPDBA_OK;
+    if (p->fwd) rocfft_plan_destroy(p->fwd);
+    if (p->inv) rocfft_plan_destroy(p->inv);
+    if (p->info) rocfft_execution_info_destroy(p->info);
+    for (auto &e : p->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete p;
+    return SPDBA_OK;
+}
+
+}  // extern "C"

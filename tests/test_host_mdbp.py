@@ -1,0 +1,62 @@
+"""Host-side checks of the multimode DBP entry points (include/spdba_mdbp.h)
+that need no GPU: every declared symbol is exported, the coupling propagator
+the plan computes (scaling and squaring of the Taylor series) equals the
+oracle's eigen-based one and is unitary, and invalid descriptors or a
+non-Hermitian K are rejected before any device call."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mdbp as OM
+from paper_2609_03922_amd import inputs, mdbp, spdba
+from test_host_lib import header_functions
+
+
+def test_mdbp_exports():
+    lib = mdbp.load()
+    names = header_functions("spdba_mdbp.h")
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(mdbp.MDBP_EXPORTS)
+
+
+@pytest.mark.parametrize("M,delta", [(1, 0.05), (2, 0.05), (8, 0.05), (32, 0.05), (64, 0.3), (8, -2.0)])
+def test_coupling_matches_the_eigen_form(M, delta):
+    K = inputs.hermitian_coupling(11, M)
+    W = mdbp.coupling(K, delta)
+    assert np.max(np.abs(W - OM.coupling(K, delta))) <= 1e-13
+    assert np.max(np.abs(W.conj().T @ W - np.eye(M))) <= 1e-13
+
+
+def _K(M=4):
+    return inputs.hermitian_coupling(12, M)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    ({"M": 0}, spdba.SPDBA_EINVAL),
+    ({"n": 1000}, spdba.SPDBA_EINVAL),
+    ({"n": 8}, spdba.SPDBA_EINVAL),
+    ({"block": 24}, spdba.SPDBA_EINVAL),
+    ({"tau": -1.0}, spdba.SPDBA_EINVAL),
+    ({"dz": 0.0}, spdba.SPDBA_EINVAL),
+    ({"T": -1.0}, spdba.SPDBA_EINVAL),
+    ({"gamma": math.nan}, spdba.SPDBA_EINVAL),
+    ({"flags": 16}, spdba.SPDBA_EINVAL),
+    ({"M": 65}, spdba.SPDBA_EUNSUPPORTED),
+    ({"M": 33, "dtype": spdba.SPDBA_F64}, spdba.SPDBA_EUNSUPPORTED),
+])
+def test_invalid_descriptors_rejected_without_device(kw, expect):
+    d = mdbp.make_desc(4, 4096, 32)
+    for k, v in kw.items():
+        setattr(d, k, v)
+    M = max(1, d.M)
+    assert mdbp.create_status(d, inputs.hermitian_coupling(12, M)) == expect
+
+
+def test_non_hermitian_coupling_rejected():
+    K = _K()
+    K[0, 1] += 0.5
+    assert mdbp.create_status(mdbp.make_desc(4, 4096, 32), K) == spdba.SPDBA_EINVAL
+    assert mdbp.load().spdba_mdbp_create(None, None, None, None) == spdba.SPDBA_EINVAL
+    assert mdbp.load().spdba_mdbp_destroy(None) == spdba.SPDBA_OK
