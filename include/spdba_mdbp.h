@@ -48,7 +48,12 @@ extern "C" {
 enum {
     SPDBA_MDBP_DENSE = 1u << 0,  /* Regular: every block updates, no measure   */
     SPDBA_MDBP_PIN_K0 = 1u << 1, /* the block holding omega = 0 is always active */
-    SPDBA_MDBP_TIMING = 1u << 2  /* HIP events around the stages (stats)       */
+    SPDBA_MDBP_TIMING = 1u << 2, /* HIP events around the stages (stats)       */
+    SPDBA_MDBP_GRAPH = 1u << 3   /* spdba_mdbp_step replays one captured step as
+                                    a HIP graph (captured on the first call; the
+                                    plan's stream must not be the legacy default
+                                    stream); not with SPDBA_MDBP_TIMING
+                                    (EUNSUPPORTED)                             */
 };
 
 typedef struct {

@@ -94,4 +94,28 @@ RCD3D_128_M48_F32 = dict(
 )
 
 RCD = [RCD3D_256_M8_F32, RCD3D_128_M48_F32]
-BY_NAME = {c["name"]: c for c in ALL + RCD}
+
+# Multimode digital backpropagation (Supplementary S5.3), the large end of the
+# paper's scaling tests: M = 32 coupled modes (the widest with an FP64 path
+# for the truth), 262,144 samples over T = 1000, 32-bin blocks, dz = 0.1 over
+# 500 (5000 steps),
+# beta2 = -21, alpha = 0.1, gamma = 1.3; three Gaussian packets (width 10,
+# offsets -20/0/20, carriers -0.15/0/0.15 of 2 pi N/T) on every mode; K a
+# seeded Hermitian matrix with mean |K_ij|^2 = 1.  P0 = 0.1 instead of the
+# printed 1000: at 1000 the Kerr phase is tens of radians per step and the
+# spectrum fills every block within twenty steps (the oracle shows it), which
+# contradicts the localized bands the paper reports; 0.1 keeps them localized.
+MDBP1D_262144_M32_F32 = dict(
+    name="mdbp1d_262144_m32_f32",
+    op="mdbp", dtype="f32", M=32, n=262144, block=32, steps=5000, seed=1234,
+    T=1000.0, dz=0.1, alpha=0.1, beta2=-21.0, gamma=1.3, P0=0.1,
+    taus=(1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5),
+)
+
+# M = 64, the paper's widest: no FP64 path above M = 32, so the reference is
+# the FP32 Regular back-propagation and the threshold is the largest whose
+# recovered field stays within err_bar of it
+MDBP1D_262144_M64_F32 = dict(MDBP1D_262144_M32_F32, name="mdbp1d_262144_m64_f32", M=64, err_bar=1e-3)
+
+MDBP = [MDBP1D_262144_M32_F32, MDBP1D_262144_M64_F32]
+BY_NAME = {c["name"]: c for c in ALL + RCD + MDBP}

@@ -3,7 +3,8 @@
 //
 //   k_md_measure   per block of bins: a_b = max of sum_m |E_m|^2 (FP64, modes
 //                  in order, omega = 0 left out); blocks dealt to the XCDs in
-//                  eight contiguous ranges
+//                  eight contiguous ranges (k_md_measure_small for blocks of
+//                  at most 64 bins: a thread per bin, a max over lane groups)
 //   k_md_gmax      G = max_b a_b (one atomic max per workgroup)
 //   k_md_compact   mask and an unordered list of the active blocks
 //   k_md_update    persistent walk of the list, one list segment per XCD; per
@@ -96,6 +97,32 @@ __global__ void __launch_bounds__(256) k_md_measure(MCtx c) {
     }
 }
 
+// blocks of at most 64 bins: one thread per bin, the block maximum a max over
+// groups of B lanes (n is a multiple of 64, so every wave runs whole)
+__global__ void __launch_bounds__(256) k_md_measure_small(MCtx c, int fp64) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < c.n; e += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        if (fp64) {
+            const double2 *E = reinterpret_cast<const double2 *>(c.E);
+#pragma unroll 8
+            for (int m = 0; m < c.M; ++m) {
+                const double2 v = E[m * c.n + e];
+                acc = acc + msq2(v.x, v.y);
+            }
+        } else {
+            const float2 *E = reinterpret_cast<const float2 *>(c.E);
+#pragma unroll 8
+            for (int m = 0; m < c.M; ++m) {
+                const float2 v = E[m * c.n + e];
+                acc = acc + msq2((double)v.x, (double)v.y);
+            }
+        }
+        if (e == 0) acc = 0.0;
+        for (int off = c.B >> 1; off >= 1; off >>= 1) acc = fmax(acc, __shfl_xor(acc, off, 64));
+        if ((e & (c.B - 1)) == 0) c.ab[e >> c.lB] = acc;
+    }
+}
+
 __global__ void __launch_bounds__(1024) k_md_gmax(MCtx c) {
     __shared__ double red[16];
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -141,9 +168,14 @@ __global__ void __launch_bounds__(256) k_md_update(MCtx c) {
     const int64_t seg = (total + 7) >> 3;
     const int64_t lo = std::min<int64_t>(total, seg * xcd), hi = std::min<int64_t>(total, seg * (xcd + 1));
     const double att = exp(-c.alpha * c.dz / 4.0);
-    for (int64_t ent = lo + (blockIdx.x >> 3); ent < hi; ent += per) {
+    // blocks narrower than the workgroup: several list entries per iteration
+    const int lanes = c.B < (int)blockDim.x ? c.B : (int)blockDim.x;
+    const int epi = (int)blockDim.x / lanes, sub = (int)threadIdx.x / lanes, s0 = (int)threadIdx.x - sub * lanes;
+    for (int64_t base = lo + (int64_t)(blockIdx.x >> 3) * epi; base < hi; base += (int64_t)per * epi) {
+        const int64_t ent = base + sub;
+        if (ent >= hi) continue;
         const int64_t b = c.dense ? ent : (int64_t)c.list[ent];
-        for (int s = threadIdx.x; s < c.B; s += blockDim.x) {
+        for (int s = s0; s < c.B; s += lanes) {
             const int64_t e = (b << c.lB) + s;
             const int64_t si = e <= ((n - 1) >> 1) ? e : e - n;
             const double om = 6.283185307179586476925286766559 * (double)si / c.T;
@@ -284,7 +316,9 @@ struct spdba_mdbp_s {
     char *d_state = nullptr, *d_work = nullptr;
     hipEvent_t ev[6] = {};
     bool ev_valid = false;
-    float lin_ms = 0.f;
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
@@ -302,7 +336,9 @@ namespace {
 spdba_status validate(const spdba_mdbp_desc *d, const double *K) {
     if (!d || !K) return SPDBA_EINVAL;
     if (d->M < 1 || d->dtype < SPDBA_F32 || d->dtype > SPDBA_F64) return SPDBA_EINVAL;
-    if (d->flags & ~(uint32_t)(SPDBA_MDBP_DENSE | SPDBA_MDBP_PIN_K0 | SPDBA_MDBP_TIMING)) return SPDBA_EINVAL;
+    if (d->flags & ~(uint32_t)(SPDBA_MDBP_DENSE | SPDBA_MDBP_PIN_K0 | SPDBA_MDBP_TIMING | SPDBA_MDBP_GRAPH))
+        return SPDBA_EINVAL;
+    if ((d->flags & SPDBA_MDBP_GRAPH) && (d->flags & SPDBA_MDBP_TIMING)) return SPDBA_EUNSUPPORTED;
     if (!pow2(d->n) || d->n < 16 || d->n > (int64_t(1) << 28)) return SPDBA_EINVAL;
     if (!pow2(d->block) || d->block > d->n) return SPDBA_EINVAL;
     const double vals[] = {d->tau, d->T, d->dz, d->alpha, d->beta2, d->gamma};
@@ -347,14 +383,20 @@ spdba_status linear_half(spdba_mdbp_plan p) {
     const MCtx &c = p->c;
     if (!c.dense) {
         hipLaunchKernelGGL(k_md_reset, dim3(1), dim3(64), 0, p->stream, c);
-        const int nbg = (int)(((c.nb + 7) >> 3) << 3);
-        if (p->dbl) hipLaunchKernelGGL(k_md_measure<double>, dim3(nbg), dim3(256), 0, p->stream, c);
-        else hipLaunchKernelGGL(k_md_measure<float>, dim3(nbg), dim3(256), 0, p->stream, c);
+        if (c.B <= 64 && c.n >= 64) {
+            const int g = (int)std::min<int64_t>((c.n + 255) / 256, (int64_t)p->cu * 16);
+            hipLaunchKernelGGL(k_md_measure_small, dim3(g), dim3(256), 0, p->stream, c, p->dbl ? 1 : 0);
+        } else {
+            const int nbg = (int)(((c.nb + 7) >> 3) << 3);
+            if (p->dbl) hipLaunchKernelGGL(k_md_measure<double>, dim3(nbg), dim3(256), 0, p->stream, c);
+            else hipLaunchKernelGGL(k_md_measure<float>, dim3(nbg), dim3(256), 0, p->stream, c);
+        }
         hipLaunchKernelGGL(k_md_gmax, dim3((unsigned)((c.nb + 1023) / 1024)), dim3(1024), 0, p->stream, c);
         hipLaunchKernelGGL(k_md_compact, dim3((unsigned)((c.nb + 255) / 256)), dim3(256), 0, p->stream, c);
         MTRY_HIP(hipGetLastError());
     }
-    const int grid = (int)(std::max<int64_t>(8, std::min<int64_t>(c.nb, (int64_t)p->cu * 8)) + 7) / 8 * 8;
+    const int64_t epi = c.B < 256 ? 256 / c.B : 1;  // list entries per workgroup iteration
+    const int grid = (int)(std::max<int64_t>(8, std::min<int64_t>((c.nb + epi - 1) / epi, (int64_t)p->cu * 8)) + 7) / 8 * 8;
     if (p->dbl) launch_upd<double>(c, grid, p->stream);
     else launch_upd<float>(c, grid, p->stream);
     MTRY_HIP(hipGetLastError());
@@ -409,6 +451,7 @@ spdba_status spdba_mdbp_create(const spdba_mdbp_desc *desc, const double *K, voi
     p->dbl = desc->dtype == SPDBA_F64;
     p->esize = p->dbl ? 16 : 8;
     p->timing = (desc->flags & SPDBA_MDBP_TIMING) != 0;
+    p->use_graph = (desc->flags & SPDBA_MDBP_GRAPH) != 0;
     p->stream = reinterpret_cast<hipStream_t>(stream);
     MCtx &c = p->c;
     c.M = desc->M;
@@ -566,7 +609,24 @@ spdba_status spdba_mdbp_apply(spdba_mdbp_plan p) {
 spdba_status spdba_mdbp_step(spdba_mdbp_plan p, int32_t n) {
     if (!p || n < 0) return SPDBA_EINVAL;
     if (!p->bound) return SPDBA_ESTATE;
-    for (int32_t i = 0; i < n; ++i) MTRY(one_step(p));
+    if (!p->use_graph || n == 0) {
+        for (int32_t i = 0; i < n; ++i) MTRY(one_step(p));
+        return SPDBA_OK;
+    }
+    if (!p->gexec) {  // one whole step captured once (kernels and rocFFT launches, no memset nodes)
+        MTRY_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+        const spdba_status st = one_step(p);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(p->stream, &g);
+        if (st != SPDBA_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        MTRY_HIP(ec);
+        p->graph = g;
+        MTRY_HIP(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+    }
+    for (int32_t i = 0; i < n; ++i) MTRY_HIP(hipGraphLaunch(p->gexec, p->stream));
     return SPDBA_OK;
 }
 
@@ -629,6 +689,8 @@ spdba_status spdba_mdbp_destroy(spdba_mdbp_plan p) {
     if (p->info) rocfft_execution_info_destroy(p->info);
     for (auto &e : p->ev)
         if (e) (void)hipEventDestroy(e);
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
     delete p;
     return SPDBA_OK;
 }

@@ -13,7 +13,7 @@ import numpy as np
 
 from . import spdba as S
 
-SPDBA_MDBP_DENSE, SPDBA_MDBP_PIN_K0, SPDBA_MDBP_TIMING = 1, 2, 4
+SPDBA_MDBP_DENSE, SPDBA_MDBP_PIN_K0, SPDBA_MDBP_TIMING, SPDBA_MDBP_GRAPH = 1, 2, 4, 8
 
 # every entry point include/spdba_mdbp.h declares
 MDBP_EXPORTS = (
@@ -76,11 +76,11 @@ def coupling(K, delta: float) -> np.ndarray:
 
 
 def make_desc(M, n, block, dtype="f32", tau=1e-6, T=1000.0, dz=0.1, alpha=0.1, beta2=-21.0, gamma=1.3,
-              dense=False, pin_k0=True, timing=False) -> MdbpDesc:
+              dense=False, pin_k0=True, timing=False, graph=False) -> MdbpDesc:
     d = MdbpDesc()
     d.M, d.block, d.n, d.dtype = M, block, n, S.DTYPES[dtype]
     d.flags = (SPDBA_MDBP_DENSE if dense else 0) | (SPDBA_MDBP_PIN_K0 if pin_k0 else 0) | \
-              (SPDBA_MDBP_TIMING if timing else 0)
+              (SPDBA_MDBP_TIMING if timing else 0) | (SPDBA_MDBP_GRAPH if graph else 0)
     d.tau, d.T, d.dz, d.alpha, d.beta2, d.gamma = tau, T, dz, alpha, beta2, gamma
     return d
 

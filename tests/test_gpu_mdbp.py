@@ -143,3 +143,24 @@ def test_mdbp_dense_equals_threshold_zero():
         out.append(p.get_spectrum().cpu().numpy())
         p.destroy()
     assert_bits_equal(out[0], out[1], "dense vs tau = 0")
+
+
+def test_mdbp_graph_replay_equals_eager():
+    """Whole steps replayed as a HIP graph give the eager steps' bits (the
+    graph is replayed several times, with reads between the replays)."""
+    import torch
+
+    M, n = 8, 4096
+    K = inputs.hermitian_coupling(43, M)
+    Et = inputs.gaussian_packets(n, PHYS["T"], M, P0=0.1).astype(np.complex64)
+    plans = [mdbp.MdbpPlan(mdbp.make_desc(M, n, 32, tau=1e-3, graph=g, **PHYS), K) for g in (False, True)]
+    for p in plans:
+        p.set_field(torch.from_numpy(Et.ravel()))
+    for rep in range(3):
+        for p in plans:
+            p.step(4)
+        a, b = (p.get_spectrum().cpu().numpy() for p in plans)
+        assert_bits_equal(b, a, f"graph vs eager after {4 * (rep + 1)} steps")
+        assert np.array_equal(plans[0].active_mask()[0], plans[1].active_mask()[0])
+    for p in plans:
+        p.destroy()

@@ -43,6 +43,7 @@ def _K(M=4):
     ({"T": -1.0}, spdba.SPDBA_EINVAL),
     ({"gamma": math.nan}, spdba.SPDBA_EINVAL),
     ({"flags": 16}, spdba.SPDBA_EINVAL),
+    ({"flags": 2 | 4 | 8}, spdba.SPDBA_EUNSUPPORTED),    # graph replay has no stage events
     ({"M": 65}, spdba.SPDBA_EUNSUPPORTED),
     ({"M": 33, "dtype": spdba.SPDBA_F64}, spdba.SPDBA_EUNSUPPORTED),
 ])
