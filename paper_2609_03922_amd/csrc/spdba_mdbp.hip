@@ -9,7 +9,9 @@
 //   k_md_compact   mask and an unordered list of the active blocks
 //   k_md_update    persistent walk of the list, one list segment per XCD; per
 //                  bin the M modes in registers, then E'_m = h(omega) sum_j
-//                  W_mj E_j row by row with W in LDS (read as broadcasts)
+//                  W_mj E_j row by row with W in LDS (read as broadcasts);
+//                  FP32 with M > 16: k_md_update_mfma, one real GEMM per chunk
+//                  of 64 bins on the matrix cores
 //   k_md_kerr      time domain: E_m <- E_m / n exp(i gamma 8/9 P dz), P the
 //                  total power of the sample (the phase in FP64)
 //
@@ -212,6 +214,106 @@ __global__ void __launch_bounds__(256) k_md_update(MCtx c) {
     }
 }
 
+// Wide modes (FP32, M > 16): the coupled half-step as one real GEMM per chunk
+// of 64 bins on the matrix cores.  With W = Wr + i Wi and b = br + i bi,
+// [xr; xi] = [[Wr, -Wi], [Wi, Wr]] [br; bi]; B holds the chunk's bins as 64
+// columns over 2 MM rows (re rows, then im rows), the product goes to LDS
+// and the stores apply h(omega) in the loads' coalesced pattern.  LDS pitches
+// padded so that an operand read falls on distinct banks.
+typedef float md_f4 __attribute__((ext_vector_type(4)));
+
+template <int MM>
+__global__ void __launch_bounds__(256) k_md_update_mfma(MCtx c) {
+    constexpr int R = 2 * MM, NC = 64, SA = R + 4, SB = NC + 16;
+    __shared__ float wa[R * SA];  // the real form of W
+    __shared__ float bs[R * SB];  // B, then X
+    __shared__ int64_t eofs[NC];
+    __shared__ float2 hs[NC];     // h(omega) of the chunk's bins
+    const float2 *wsrc = reinterpret_cast<const float2 *>(c.W);  // [MM][MM] complex, zero-padded
+    for (int k = threadIdx.x; k < MM * MM; k += blockDim.x) {
+        const int i = k / MM, j = k - i * MM;
+        const float2 v = wsrc[k];
+        wa[i * SA + j] = v.x;
+        wa[i * SA + MM + j] = -v.y;
+        wa[(MM + i) * SA + j] = v.y;
+        wa[(MM + i) * SA + MM + j] = v.x;
+    }
+    __syncthreads();
+    float2 *E = reinterpret_cast<float2 *>(c.E);
+    const int M = c.M, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t n = c.n;
+    const int64_t total = c.dense ? c.nb : (int64_t)*c.count;
+    const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
+    const int64_t seg = (total + 7) >> 3;
+    const int64_t lo = std::min<int64_t>(total, seg * xcd), hi = std::min<int64_t>(total, seg * (xcd + 1));
+    const int row = lane & 15, kq = lane >> 4;
+    const double att = exp(-c.alpha * c.dz / 4.0);
+    // chunks of 64 bins: NC / B blocks of the list per chunk when B < 64
+    const int bpc = c.B < NC ? NC / c.B : 1;
+    for (int64_t base = lo + (int64_t)(blockIdx.x >> 3) * bpc; base < hi; base += (int64_t)per * bpc) {
+        const int nblk = (int)std::min<int64_t>(bpc, hi - base);
+        for (int s0 = 0; s0 < (bpc > 1 ? 1 : c.B); s0 += NC) {  // blocks of at least 64 bins: in chunks
+            const int nm = bpc > 1 ? nblk * c.B : min(NC, c.B - s0);
+            if (t < NC) {
+                int64_t e = 0;
+                if (t < nm) {
+                    const int64_t b = bpc > 1 ? (c.dense ? base + t / c.B : (int64_t)c.list[base + t / c.B]) :
+                                                (c.dense ? base : (int64_t)c.list[base]);
+                    e = (b << c.lB) + (bpc > 1 ? (t & (c.B - 1)) : s0 + t);
+                }
+                eofs[t] = e;
+                const int64_t si = e <= ((n - 1) >> 1) ? e : e - n;
+                const double om = 6.283185307179586476925286766559 * (double)si / c.T;
+                double sp, cp;
+                sincos(c.beta2 * 0.5 * om * om * c.dz * 0.5, &sp, &cp);
+                hs[t] = make_float2((float)(att * cp), (float)(att * sp));
+            }
+            __syncthreads();
+            for (int k = t; k < MM * NC; k += blockDim.x) {
+                const int i = k / NC, md = k - i * NC;
+                float2 v = make_float2(0.f, 0.f);
+                if (i < M && md < nm) v = E[i * n + eofs[md]];
+                bs[i * SB + md] = v.x;
+                bs[(MM + i) * SB + md] = v.y;
+            }
+            __syncthreads();
+            // X = Wa B: (R / 16) x (NC / 16) tiles over the four waves; the
+            // results wait in registers until every wave has read B
+            md_f4 acc[(R / 16) * (NC / 16) / 4];
+#pragma unroll
+            for (int q = 0; q < (R / 16) * (NC / 16) / 4; ++q) {
+                const int tile = wave + 4 * q;
+                const int rt = tile / (NC / 16), ct = tile - rt * (NC / 16);
+                md_f4 a4 = {0.f, 0.f, 0.f, 0.f};
+                for (int k0 = 0; k0 < R; k0 += 4) {
+                    const float av = wa[(rt * 16 + row) * SA + k0 + kq];
+                    const float bv = bs[(k0 + kq) * SB + ct * 16 + row];
+                    a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, a4, 0, 0, 0);
+                }
+                acc[q] = a4;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < (R / 16) * (NC / 16) / 4; ++q) {
+                const int tile = wave + 4 * q;
+                const int rt = tile / (NC / 16), ct = tile - rt * (NC / 16);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) bs[(rt * 16 + kq * 4 + r) * SB + ct * 16 + row] = acc[q][r];
+            }
+            __syncthreads();
+            for (int k = t; k < M * NC; k += blockDim.x) {
+                const int i = k / NC, md = k - i * NC;
+                if (md < nm) {
+                    const float2 h = hs[md];
+                    const float xr = bs[i * SB + md], xi = bs[(MM + i) * SB + md];
+                    E[i * n + eofs[md]] = make_float2(h.x * xr - h.y * xi, h.x * xi + h.y * xr);
+                }
+            }
+            __syncthreads();  // bs and eofs are free for the next chunk
+        }
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_md_kerr(MCtx c) {
     using V2 = typename V2T<T>::t;
@@ -362,6 +464,22 @@ spdba_status validate(const spdba_mdbp_desc *d, const double *K) {
 
 template <typename T>
 void launch_upd(const MCtx &c, int grid, hipStream_t s) {
+    // wide modes, sparse walk: the matrix cores (two blocks of 32 bins per
+    // workgroup keep many workgroups busy at low activity); the Regular
+    // update of every block is faster on the vector units (its 109 KB of LDS
+    // at M = 64 would leave one workgroup per compute unit)
+    if constexpr (sizeof(T) == 4) {
+        if (c.dense) goto vector;
+        if (c.mm == 32) {
+            hipLaunchKernelGGL((k_md_update_mfma<32>), dim3(grid), dim3(256), 0, s, c);
+            return;
+        }
+        if (c.mm == 64) {
+            hipLaunchKernelGGL((k_md_update_mfma<64>), dim3(grid), dim3(256), 0, s, c);
+            return;
+        }
+    }
+vector:
     switch (c.mm) {
         case 2: hipLaunchKernelGGL((k_md_update<T, 2>), dim3(grid), dim3(256), 0, s, c); break;
         case 4: hipLaunchKernelGGL((k_md_update<T, 4>), dim3(grid), dim3(256), 0, s, c); break;

@@ -40,6 +40,7 @@ CASES = [
     (64, "f32", 2048, 32, 0.05, {}),
     (8, "f32", 4096, 32, 0.05, {"pin_k0": False}),
     (8, "f32", 4096, 32, 0.0, {"dense": True}),
+    (64, "f32", 2048, 32, 0.0, {"dense": True}),   # Regular at tile 64: the vector path
     (4, "f64", 4096, 32, 0.05, {}),
     (16, "f64", 4096, 32, 0.05, {}),
     (32, "f64", 2048, 32, 0.05, {}),
