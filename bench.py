@@ -217,7 +217,7 @@ def main():
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is "
-                                   "described in DESIGN.md and not built", "n_gpus": args.gpus}))
+                                   "designed (slab decomposition over RCCL) but not built", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch
