@@ -146,7 +146,26 @@ def modes_per_block(d, np):
     return np.concatenate([np.full(nbm, full, np.int64), np.full(rows, b[0] * b[1], np.int64)])
 
 
-def kernel_rooflines(cfg, descs, measure, layout, stage_ms, s_ind, act_modes, act_blocks, torch):
+def update_kernel_name(cfg, descs, measure, layout, choice):
+    """The active-update kernel the plan launches for its tuned variant (launch
+    kernel 3; default 1): the half layout has its own walk; the strip walk and
+    the x4 walk stand aside for the measure the update keeps (CH, GS); the
+    one-wave-per-entry walk needs blocks of at least 64 lane slots."""
+    if layout == "half":
+        return "k_update_h"
+    v = int((choice or {}).get("3", 1))
+    kept = measure in ("state", "energy") and cfg["op"] != "nlse"
+    slots = min(d.block3[0] * d.block3[1] * d.block3[2] // (1 if d.dtype == "f64" else 2) for d in descs)
+    if v == 3 and slots >= 64:
+        return "k_update_wave"
+    if v == 2 and not kept and slots <= 256:
+        return "k_update_multi"
+    if v == 1 and not kept:
+        return "k_update_strip"
+    return "k_update"
+
+
+def kernel_rooflines(cfg, descs, measure, layout, stage_ms, s_ind, act_modes, act_blocks, torch, upd_name="k_update"):
     """Per-kernel HBM rooflines of the timed workload.  Times: the eager run of
     the same steps, HIP events on the plan's stream recorded right before and
     after the nonlinear and update kernels (the stage events: they include one
@@ -174,7 +193,7 @@ def kernel_rooflines(cfg, descs, measure, layout, stage_ms, s_ind, act_modes, ac
              else "k_indicator")
     kn = {"nonlinear": ("k_nonlinear_h" if layout == "half" else "k_nonlinear", nl_bytes, stage_ms["nonlinear"], 1,
                         "the timed steps, eager, stage events"),
-          "update": ("k_update_h" if layout == "half" else "k_update", upd_bytes, stage_ms["update"], launches,
+          "update": (upd_name, upd_bytes, stage_ms["update"], launches,
                      "the timed steps, eager, stage events"),
           "indicator": (iname, indicator_bytes(cfg, descs, state_only=measure == "energy"),
                         s_ind["indicator_kernel_ms"], launches,
@@ -344,7 +363,8 @@ def main():
         plan, _, _ = timed_run(False, False, meas="increment")
         s_ind = plan.stats(0)
     plan.destroy()
-    roof, kernels = kernel_rooflines(cfg, descs, measure, layout, stage_ms, s_ind, last_modes, last_blocks, torch)
+    roof, kernels = kernel_rooflines(cfg, descs, measure, layout, stage_ms, s_ind, last_modes, last_blocks, torch,
+                                     update_kernel_name(cfg, descs, measure, layout, tuned))
 
     # ---- dense (Regular) run on the same input ----------------------------
     dense = None
