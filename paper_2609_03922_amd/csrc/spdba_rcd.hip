@@ -147,37 +147,6 @@ __global__ void __launch_bounds__(256) k_rcd_reaction(RCtx c, typename C2<T>::t 
     }
 }
 
-// R(u) for wide components (FP32, M > 16): u staged in LDS per thread
-// (component-major, thread-minor), the sum S first, then each component with
-// its periodic neighbours from LDS; the same interaction sum as above
-__global__ void __launch_bounds__(256) k_rcd_reaction_wide(RCtx c, float2 *w) {
-    __shared__ float us[64 * 256];
-    const int M = c.M, t = threadIdx.x;
-    const int64_t N = c.g.N;
-    const float invN = (float)c.invN, r = (float)c.r, a = (float)c.a, al = (float)c.alpha, be = (float)c.beta;
-    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x; p0 < N; p0 += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = p0 + t;  // N is a multiple of 256 or smaller than it: guard
-        const bool ok = p < N;
-        float S = 0.f;
-        for (int m = 0; m < M; ++m) {
-            const float u = ok ? w[m * N + p].x * invN : 0.f;
-            us[m * 256 + t] = u;
-            S = S + u;
-        }
-        if (ok)
-            for (int m = 0; m < M; ++m) {
-                const float u = us[m * 256 + t];
-                const float left = us[(m == 0 ? M - 1 : m - 1) * 256 + t];
-                const float right = us[(m == M - 1 ? 0 : m + 1) * 256 + t];
-                const float inter = be * (S - u) + al * (left + right);
-                float2 o;
-                o.x = u * (r - a * u - inter);
-                o.y = 0.f;
-                w[m * N + p] = o;
-            }
-    }
-}
-
 // XCD-aware: workgroup i runs on XCD i % 8, so the blocks are dealt out in
 // eight contiguous ranges, one per XCD.  x-adjacent blocks of 8 FP32 values
 // per row share 128-byte lines; on one XCD the second read hits its L2.
@@ -697,8 +666,14 @@ void launch_reaction_t(const RCtx &c, void *w, int grid, hipStream_t s) {
         case 16:  // FP32 only (validated at creation)
             if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_rcd_reaction<T, 16>), dim3(grid), dim3(256), 0, s, c, p);
             break;
-        default:  // tiles 32 and 64: FP32 only, u staged in LDS
-            if constexpr (sizeof(T) == 4) hipLaunchKernelGGL(k_rcd_reaction_wide, dim3(grid), dim3(256), 0, s, c, p);
+        case 32:  // FP32 only (validated at creation)
+            if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_rcd_reaction<T, 32>), dim3(grid), dim3(256), 0, s, c, p);
+            break;
+        case 48:
+            if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_rcd_reaction<T, 48>), dim3(grid), dim3(256), 0, s, c, p);
+            break;
+        default:  // tile 64
+            if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_rcd_reaction<T, 64>), dim3(grid), dim3(256), 0, s, c, p);
             break;
     }
 }

@@ -157,7 +157,8 @@ def test_rcd_field_round_trip():
 
 
 @pytest.mark.parametrize("dtype,M,n,steps,tau", [("f64", 4, 16, 25, 0.02), ("f32", 8, 32, 10, 0.1),
-                                                 ("f32", 24, 16, 25, 0.1)])
+                                                 ("f32", 24, 16, 25, 0.1), ("f32", 40, 16, 25, 0.1),
+                                                 ("f32", 64, 16, 25, 0.1)])
 def test_rcd_trajectory_matches_oracle(dtype, M, n, steps, tau):
     """Full steps (transforms, Lotka--Volterra reaction, measure, update) from a
     perturbed homogeneous state: masks of every step agree with the oracle's
