@@ -904,7 +904,7 @@ def rcd_bench(args, cfg):
         p.destroy()
         return {"steps_per_s": K / (ms / 1e3), "field": f, "active_fraction_last": count / nb}
 
-    wide = M > 8  # no FP64 path: the FP32 Regular run is the reference
+    wide = M > 48  # no FP64 path: the FP32 Regular run is the reference
     dense = run("f32", 0.0, True)
     truth = dense["field"] if wide else run("f64", 0.0, True)["field"]
     tn = np.linalg.norm(truth)
@@ -977,7 +977,7 @@ def rcd_bench(args, cfg):
                    "parallelism": "single-gpu"},
         "steps_per_s": sps, "dense_steps_per_s": round(dense["steps_per_s"], 2),
         "speedup_steps_vs_dense": round(sps / dense["steps_per_s"], 4),
-        "equal_error": {"truth": ("FP32 Regular run (no FP64 path above M = 8), fluctuation fields" if wide
+        "equal_error": {"truth": ("FP32 Regular run (no FP64 path above M = 48), fluctuation fields" if wide
                                   else "FP64 Regular run on the GPU, fluctuation fields"),
                         "e_d": e_d, "bar": bar, "sweep": sweep, "tau_star": star["tau"] if ok else None},
         "stage_ms": {"transforms_and_reaction": round(st_sp[0], 4), "measure": round(st_sp[1], 4),

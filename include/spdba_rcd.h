@@ -36,7 +36,7 @@
  * Ownership and errors: the caller owns every device buffer (sized by
  * spdba_rcd_buffer_sizes) and the stream; the plan owns host metadata and its
  * rocFFT plans.  Descriptor errors return SPDBA_EINVAL before any device call;
- * M beyond the kernels' tiles (64 in FP32, 8 in FP64; 8 for
+ * M beyond the kernels' tiles (64 in FP32, 48 in FP64; 8 for
  * SPDBA_RCD_DIRECT) returns
  * SPDBA_EUNSUPPORTED; calls before bind return SPDBA_ESTATE; HIP and rocFFT
  * failures return SPDBA_EDEVICE / SPDBA_EFFT.  Calls are asynchronous on the

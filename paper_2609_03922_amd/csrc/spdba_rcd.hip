@@ -41,7 +41,7 @@
 namespace {
 
 constexpr double kTwoPiR = 6.283185307179586476925286766559;
-constexpr int kMaxMF32 = 64, kMaxMF64 = 8;  // FP32: register tiles to 16, matrix-core GEMMs to 64
+constexpr int kMaxMF32 = 64, kMaxMF64 = 48;  // register tiles to 16 (FP32) / 8 (FP64), then matrix-core GEMMs
 constexpr int kMaxMDirect = 8;              // the direct form's factor: MM (MM + 1) / 2 registers
 
 struct RGeo {
@@ -376,34 +376,55 @@ __global__ void __launch_bounds__(256) k_rcd_update(RCtx c) {
 // and X goes back through LDS so that the stores are the loads' coalesced
 // pattern and the kept measure sums the components in order.  Four waves
 // share the 16 x 16 output tiles; LDS: V^T, V, B (reused for X), W.
-typedef float rcd_f4 __attribute__((ext_vector_type(4)));
+// the 16 x 16 x 4 matrix-core product in the kernel's precision
+template <typename T> struct RMf;
+// Operands: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] in both
+// precisions.  Result element r of lane l is D[drow(l / 16, r)][l % 16]: rows
+// 4 (l / 16) + r in FP32, l / 16 + 4 r in FP64 (the FP64 row order checked on
+// the device with one-hot operands).
+template <> struct RMf<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int drow(int kq, int r) { return kq * 4 + r; }
+};
+template <> struct RMf<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int drow(int kq, int r) { return kq + 4 * r; }
+};
 
-template <int MM>
+template <typename T, int MM>
 __global__ void __launch_bounds__(256) k_rcd_update_mfma(RCtx c) {
+    using V2 = typename C2<T>::t;
+    using v4 = typename RMf<T>::v4;
     constexpr int NC = 128;      // real columns per chunk: 64 modes
     constexpr int SA = MM + 4;   // row pitches padded so that the 64 lanes of an
     constexpr int SB = NC + 16;  // operand read fall on distinct LDS banks
-    __shared__ float vtl[MM * SA];  // V^T (row j, column i)
-    __shared__ float vl[MM * SA];   // V (row m, column j)
-    __shared__ float bs[MM * SB];   // B, then X
-    __shared__ float ws[MM * SB];   // W
-    __shared__ float laml[MM];
-    __shared__ float dks[NC / 2];
+    __shared__ T vtl[MM * SA];  // V^T (row j, column i)
+    __shared__ T vl[MM * SA];   // V (row m, column j)
+    __shared__ T bs[MM * SB];   // B, then X
+    __shared__ T ws[MM * SB];   // W
+    __shared__ T laml[MM];
+    __shared__ T dks[NC / 2];
     __shared__ int64_t eofs[NC / 2];
     __shared__ double red[4];
-    const float *vsrc = reinterpret_cast<const float *>(c.vt);  // V^T, zero-padded
+    const T *vsrc = reinterpret_cast<const T *>(c.vt);  // V^T, zero-padded
     for (int k = threadIdx.x; k < MM * MM; k += blockDim.x) {
         const int r = k / MM, q2 = k - r * MM;
         vtl[r * SA + q2] = vsrc[k];
         vl[q2 * SA + r] = vsrc[k];
     }
-    for (int k = threadIdx.x; k < MM; k += blockDim.x) laml[k] = reinterpret_cast<const float *>(c.lam)[k];
+    for (int k = threadIdx.x; k < MM; k += blockDim.x) laml[k] = reinterpret_cast<const T *>(c.lam)[k];
     __syncthreads();
-    float2 *q = reinterpret_cast<float2 *>(c.state);
-    const float2 *rh = reinterpret_cast<const float2 *>(c.rhs);
+    V2 *q = reinterpret_cast<V2 *>(c.state);
+    const V2 *rh = reinterpret_cast<const V2 *>(c.rhs);
     const int M = c.M, t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t N = c.g.N;
-    const float dt = (float)c.dt;
+    const T dt = (T)c.dt;
     const int64_t total = c.dense ? c.g.nb : (int64_t)*c.count;
     const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
     const int64_t seg = (total + 7) >> 3;
@@ -419,57 +440,62 @@ __global__ void __launch_bounds__(256) k_rcd_update_mfma(RCtx c) {
                 double k2 = 0.0;
                 if (t < nm) mode_of(c.g, b, s0 + t, e, k2);
                 eofs[t] = e;
-                dks[t] = (float)(c.dt * k2);
+                dks[t] = (T)(c.dt * k2);
             }
             __syncthreads();
             for (int k = t; k < MM * (NC / 2); k += blockDim.x) {
                 const int i = k / (NC / 2), md = k - i * (NC / 2);
-                float2 bb = make_float2(0.f, 0.f);
+                T bx = (T)0, by = (T)0;
                 if (i < M && md < nm) {
                     const int64_t e = eofs[md];
-                    const float2 v = q[i * N + e], f = rh[i * N + e];
-                    bb.x = fmaf(dt, f.x, v.x);
-                    bb.y = fmaf(dt, f.y, v.y);
+                    const V2 v = q[i * N + e], f = rh[i * N + e];
+                    bx = fma(dt, f.x, v.x);
+                    by = fma(dt, f.y, v.y);
                 }
-                bs[i * SB + 2 * md] = bb.x;
-                bs[i * SB + 2 * md + 1] = bb.y;
+                bs[i * SB + 2 * md] = bx;
+                bs[i * SB + 2 * md + 1] = by;
             }
             __syncthreads();
             // W = V^T B, scaled; tiles (jt, ct) dealt to the four waves
             for (int tile = wave; tile < (MM / 16) * (NC / 16); tile += 4) {
                 const int jt = tile / (NC / 16), ct = tile - jt * (NC / 16);
-                rcd_f4 acc = {0.f, 0.f, 0.f, 0.f};
+                v4 acc = {(T)0, (T)0, (T)0, (T)0};
                 for (int k0 = 0; k0 < MM; k0 += 4) {
-                    const float av = vtl[(jt * 16 + row) * SA + k0 + kq];
-                    const float bv = bs[(k0 + kq) * SB + ct * 16 + row];
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+                    const T av = vtl[(jt * 16 + row) * SA + k0 + kq];
+                    const T bv = bs[(k0 + kq) * SB + ct * 16 + row];
+                    acc = RMf<T>::mac(av, bv, acc);
                 }
                 const int col = ct * 16 + row;
-                const float dk = dks[col >> 1];
+                const T dk = dks[col >> 1];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int j = jt * 16 + kq * 4 + r;
-                    ws[j * SB + col] = acc[r] * (1.f / (1.f + dk * laml[j]));
+                    const int j = jt * 16 + RMf<T>::drow(kq, r);
+                    ws[j * SB + col] = acc[r] * ((T)1 / ((T)1 + dk * laml[j]));
                 }
             }
             __syncthreads();
             // X = V W into bs
             for (int tile = wave; tile < (MM / 16) * (NC / 16); tile += 4) {
                 const int mt = tile / (NC / 16), ct = tile - mt * (NC / 16);
-                rcd_f4 acc = {0.f, 0.f, 0.f, 0.f};
+                v4 acc = {(T)0, (T)0, (T)0, (T)0};
                 for (int k0 = 0; k0 < MM; k0 += 4) {
-                    const float av = vl[(mt * 16 + row) * SA + k0 + kq];
-                    const float bv = ws[(k0 + kq) * SB + ct * 16 + row];
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+                    const T av = vl[(mt * 16 + row) * SA + k0 + kq];
+                    const T bv = ws[(k0 + kq) * SB + ct * 16 + row];
+                    acc = RMf<T>::mac(av, bv, acc);
                 }
                 const int col = ct * 16 + row;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) bs[(mt * 16 + kq * 4 + r) * SB + col] = acc[r];
+                for (int r = 0; r < 4; ++r) bs[(mt * 16 + RMf<T>::drow(kq, r)) * SB + col] = acc[r];
             }
             __syncthreads();
             for (int k = t; k < M * (NC / 2); k += blockDim.x) {
                 const int i = k / (NC / 2), md = k - i * (NC / 2);
-                if (md < nm) q[i * N + eofs[md]] = make_float2(bs[i * SB + 2 * md], bs[i * SB + 2 * md + 1]);
+                if (md < nm) {
+                    V2 o;
+                    o.x = bs[i * SB + 2 * md];
+                    o.y = bs[i * SB + 2 * md + 1];
+                    q[i * N + eofs[md]] = o;
+                }
             }
             if (c.keep && t < nm) {  // the measure of what is stored, components in order
                 double acc = 0.0;
@@ -636,24 +662,27 @@ void launch_update_d(const RCtx &c, int grid, hipStream_t s) {
             break;
     }
 }
+// the eigen form: register tiles (FP32 2..16, FP64 2..8) on the vector units,
+// wider tiles (FP64 16; 32, 48; FP32 64) as matrix-core GEMMs
 template <typename T>
 void launch_update_t(const RCtx &c, int grid, hipStream_t s) {
-    if constexpr (sizeof(T) == 4) {
-        if (c.mm == 32) {
-            hipLaunchKernelGGL((k_rcd_update_mfma<32>), dim3(grid), dim3(256), 0, s, c);
-            return;
-        }
-        if (c.mm == 48) {
-            hipLaunchKernelGGL((k_rcd_update_mfma<48>), dim3(grid), dim3(256), 0, s, c);
-            return;
-        }
-        if (c.mm == 64) {
-            hipLaunchKernelGGL((k_rcd_update_mfma<64>), dim3(grid), dim3(256), 0, s, c);
-            return;
-        }
+    if (c.direct) {
+        launch_update_d<T, true>(c, grid, s);
+        return;
     }
-    if (c.direct) launch_update_d<T, true>(c, grid, s);
-    else launch_update_d<T, false>(c, grid, s);
+    const bool mfma = c.mm >= 32 || (sizeof(T) == 8 && c.mm == 16);
+    if (!mfma) {
+        launch_update_d<T, false>(c, grid, s);
+        return;
+    }
+    switch (c.mm) {
+        case 16: hipLaunchKernelGGL((k_rcd_update_mfma<T, 16>), dim3(grid), dim3(256), 0, s, c); break;
+        case 32: hipLaunchKernelGGL((k_rcd_update_mfma<T, 32>), dim3(grid), dim3(256), 0, s, c); break;
+        case 48: hipLaunchKernelGGL((k_rcd_update_mfma<T, 48>), dim3(grid), dim3(256), 0, s, c); break;
+        default:  // tile 64: FP32 only (its FP64 LDS would exceed 160 KB; validated at creation)
+            if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_rcd_update_mfma<T, 64>), dim3(grid), dim3(256), 0, s, c);
+            break;
+    }
 }
 
 template <typename T>
@@ -663,16 +692,10 @@ void launch_reaction_t(const RCtx &c, void *w, int grid, hipStream_t s) {
         case 2: hipLaunchKernelGGL((k_rcd_reaction<T, 2>), dim3(grid), dim3(256), 0, s, c, p); break;
         case 4: hipLaunchKernelGGL((k_rcd_reaction<T, 4>), dim3(grid), dim3(256), 0, s, c, p); break;
         case 8: hipLaunchKernelGGL((k_rcd_reaction<T, 8>), dim3(grid), dim3(256), 0, s, c, p); break;
-        case 16:  // FP32 only (validated at creation)
-            if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_rcd_reaction<T, 16>), dim3(grid), dim3(256), 0, s, c, p);
-            break;
-        case 32:  // FP32 only (validated at creation)
-            if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_rcd_reaction<T, 32>), dim3(grid), dim3(256), 0, s, c, p);
-            break;
-        case 48:
-            if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_rcd_reaction<T, 48>), dim3(grid), dim3(256), 0, s, c, p);
-            break;
-        default:  // tile 64
+        case 16: hipLaunchKernelGGL((k_rcd_reaction<T, 16>), dim3(grid), dim3(256), 0, s, c, p); break;
+        case 32: hipLaunchKernelGGL((k_rcd_reaction<T, 32>), dim3(grid), dim3(256), 0, s, c, p); break;
+        case 48: hipLaunchKernelGGL((k_rcd_reaction<T, 48>), dim3(grid), dim3(256), 0, s, c, p); break;
+        default:  // tile 64: FP32 only (validated at creation)
             if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_rcd_reaction<T, 64>), dim3(grid), dim3(256), 0, s, c, p);
             break;
     }

@@ -75,6 +75,10 @@ CASES = [
     (48, "f32", 3, 16, 4, 0.05, {}),
     (64, "f32", 3, 16, 4, 0.05, {}),
     (48, "f32", 3, 16, 4, 0.0, {"dense": True}),
+    # FP64 on the matrix cores: tiles 16, 32, 48
+    (12, "f64", 3, 16, 4, 0.05, {}),
+    (24, "f64", 3, 16, 4, 0.05, {}),
+    (48, "f64", 3, 16, 4, 0.05, {}),
     # the direct form of S4.2 (per-mode Cholesky of I + dt k^2 D)
     (2, "f32", 3, 32, 8, 0.05, {"direct": True}),
     (3, "f32", 3, 32, 4, 0.05, {"direct": True}),
@@ -158,7 +162,7 @@ def test_rcd_field_round_trip():
 
 @pytest.mark.parametrize("dtype,M,n,steps,tau", [("f64", 4, 16, 25, 0.02), ("f32", 8, 32, 10, 0.1),
                                                  ("f32", 24, 16, 25, 0.1), ("f32", 40, 16, 25, 0.1),
-                                                 ("f32", 64, 16, 25, 0.1)])
+                                                 ("f32", 64, 16, 25, 0.1), ("f64", 24, 16, 25, 0.1)])
 def test_rcd_trajectory_matches_oracle(dtype, M, n, steps, tau):
     """Full steps (transforms, Lotka--Volterra reaction, measure, update) from a
     perturbed homogeneous state: masks of every step agree with the oracle's

@@ -51,7 +51,7 @@ def _bad(**kw):
     ({"dtype": 7}, spdba.SPDBA_EINVAL),
     ({"flags": 64}, spdba.SPDBA_EINVAL),
     ({"M": 65}, spdba.SPDBA_EUNSUPPORTED),
-    ({"M": 9, "dtype": spdba.SPDBA_F64}, spdba.SPDBA_EUNSUPPORTED),
+    ({"M": 49, "dtype": spdba.SPDBA_F64}, spdba.SPDBA_EUNSUPPORTED),
     ({"M": 9, "flags": 2 | 8}, spdba.SPDBA_EUNSUPPORTED),   # the direct form: M <= 8
 ])
 def test_invalid_descriptors_rejected_without_device(kw, expect):
