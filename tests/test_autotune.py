@@ -56,3 +56,23 @@ def test_tune_keys_the_sparse_plan_and_keeps_the_fastest_variant(tmp_path):
     cache = A.load_cache(path)
     assert list(cache) == [A.cache_key(sparse, "gfx950")]
     assert cache[A.cache_key(sparse, "gfx950")]["choice"]["3"] == 3
+
+
+def test_bench_names_the_update_kernel_of_the_tuned_variant():
+    """The roofline line names the kernel the plan launches for the tuned
+    update variant: the kept state measure rules out the strip walk and the x4
+    walk; the wave walk needs blocks of at least 64 lane slots."""
+    import bench
+    from paper_2609_03922_amd import configs as C
+
+    cfg = C.CH3D_256_F32
+    d = [S.desc_from_config(cfg)]
+    name = bench.update_kernel_name
+    assert name(cfg, d, "state", "full", {"3": 3}) == "k_update_wave"
+    assert name(cfg, d, "state", "full", {"3": 1}) == "k_update"
+    assert name(cfg, d, "state", "full", {"3": 2}) == "k_update"
+    assert name(cfg, d, "increment", "full", {"3": 2}) == "k_update_multi"
+    assert name(cfg, d, "increment", "full", None) == "k_update_strip"
+    assert name(cfg, d, "state", "half", {"3": 3}) == "k_update_h"
+    small = [S.Desc(op="ch", dtype="f32", ndim=2, n=16, block=4, tau=1e-2, dx=1.0, dt=0.01, params=(1.0, 1.0))]
+    assert name(cfg, small, "increment", "full", {"3": 3}) == "k_update"   # 8 slots: below a wave
