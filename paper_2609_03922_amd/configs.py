@@ -92,7 +92,11 @@ RCD3D_128_M48_F32 = dict(
     err_bar=1e-4,  # used only where the FP64 path stops (M > 48)
 )
 
-RCD = [RCD3D_256_M8_F32, RCD3D_128_M48_F32]
+# the paper's widest point (M = 64): no FP64 path, so the FP32 Regular run is
+# the reference and err_bar the tolerance
+RCD3D_128_M64_F32 = dict(RCD3D_128_M48_F32, name="rcd3d_128_m64_f32", M=64, seed=1008)
+
+RCD = [RCD3D_256_M8_F32, RCD3D_128_M48_F32, RCD3D_128_M64_F32]
 
 # Multimode digital backpropagation (Supplementary S5.3), the large end of the
 # paper's scaling tests: M = 32 coupled modes (the widest with an FP64 path
