@@ -117,6 +117,9 @@ enum {
                                           per (z, y) block row for the column nx/2, C
                                           order over (z, y).  The x block edge must
                                           divide nx/2 and nx/(2 block[2]) + 1 <= 2048;
+                                          grids of at most 2^18 points (larger ones:
+                                          EUNSUPPORTED, until a device fault seen
+                                          on 256^3 runs is explained);
                                           not with consistency control; the update
                                           walks the block list whatever update variant
                                           is set (otherwise EUNSUPPORTED)               */

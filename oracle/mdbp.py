@@ -10,7 +10,9 @@ written from the definitions.
   domain, the nonlinear step in the time domain, a linear half-step.  Each
   linear half-step is the paper's factorisation
   U_c(dz/4) exp[(-alpha/2 + i beta2/2 omega^2) dz/2] U_c(dz/4) per bin, with
-  U_c(delta) = V exp(i delta Lambda) V^H from K = V Lambda V^H (numpy eigh).
+  U_c(delta) = exp(i delta K) (= V exp(i delta Lambda) V^H for K = V Lambda
+  V^H), here from its power series with scaling and squaring (``expm_i``,
+  written out: no eigen-solver).
   Over a step the Kerr intensity is taken at the start of the step (the
   integral of N over dz with |E| constant, since the rotation keeps |E_m|).
 * Activation (S5.3): the total modal spectral power P(omega) = sum_m |E_m|^2
@@ -19,22 +21,50 @@ written from the definitions.
   bin omega = 0 is left out and its block pinned (as everywhere in this
   package).  Active blocks update all M modes; frozen blocks keep theirs.
 
-Spectra: shape (M, N), each mode in numpy's FFT order; the time window is T
-with N samples, omega = 2 pi fftfreq(N, T / N).
+Spectra: shape (M, N), each mode in natural FFT order; the time window is T
+with N samples, omega = 2 pi m / T with m the signed index (i below N/2,
+i - N from N/2 on).  Transforms: the package's own radix-2 FFT
+(``oracle.fft``).
 """
 from __future__ import annotations
 
 import numpy as np
 
+from . import fft as _fft
+
+
+def expm_i(K: np.ndarray, delta: float) -> np.ndarray:
+    """exp(i delta K) from the exponential series: X = i delta K / 2^s with
+    s chosen so that the largest absolute row sum of X is at most 1/2, the
+    series summed to 30 terms (remainder below 2^-30 / 30!), then squared s
+    times."""
+    K = np.asarray(K, dtype=np.complex128)
+    M = K.shape[0]
+    X = 1j * float(delta) * K
+    norm = float(np.max(np.sum(np.abs(X), axis=1))) if M else 0.0
+    s = 0
+    while norm > 0.5:
+        norm *= 0.5
+        s += 1
+    X = X / (2.0 ** s)
+    U = np.eye(M, dtype=np.complex128)
+    term = np.eye(M, dtype=np.complex128)
+    for j in range(1, 31):
+        term = term @ X / j
+        U = U + term
+    for _ in range(s):
+        U = U @ U
+    return U
+
 
 def coupling(K: np.ndarray, delta: float) -> np.ndarray:
-    """U_c(delta) = V exp(i delta Lambda) V^H (S5.2)."""
-    lam, V = np.linalg.eigh(np.asarray(K, dtype=np.complex128))
-    return (V * np.exp(1j * delta * lam)[None, :]) @ V.conj().T
+    """U_c(delta) = exp(i delta K) (S5.2)."""
+    return expm_i(K, delta)
 
 
 def omega(N: int, T: float) -> np.ndarray:
-    return 2.0 * np.pi * np.fft.fftfreq(N, d=T / N)
+    i = np.arange(N)
+    return 2.0 * np.pi * np.where(2 * i < N, i, i - N).astype(np.float64) / T
 
 
 def dispersion(N: int, T: float, dz: float, alpha: float, beta2: float) -> np.ndarray:
@@ -92,8 +122,9 @@ def step(E, steps, K, T, dz, alpha, beta2, gamma, block, tau, pin_k0=True, dense
             if masks:
                 log.append(r["mask"])
             if half == 0:
-                Et = np.fft.ifft(E, axis=1)
-                E = np.fft.fft(kerr(Et, gamma, dz), axis=1)
+                Et = np.stack([_fft(E[m], +1) for m in range(E.shape[0])])
+                Ek = kerr(Et, gamma, dz)
+                E = np.stack([_fft(Ek[m], -1) for m in range(E.shape[0])])
     out = {"state": E}
     if masks:
         out["masks"] = np.array(log)

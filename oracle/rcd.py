@@ -10,8 +10,11 @@ written from the definitions, no blocking or reordering beyond them.
   R_i = u_i (r - a u_i - sum_{j != i} alpha_ij u_j), alpha_ij = beta + alpha
   for the periodic neighbours j = i +- 1 and beta otherwise.
 * Update (S4.2): per stored mode, u'(k) = (I + dt k^2 D)^{-1} [u(k) + dt R(k)],
-  solved here directly (numpy.linalg.solve), the plain definition; the
-  eigen form of S4.3 gives the same values up to rounding.
+  solved here directly by Gaussian elimination (``solve``, written out; the
+  matrix is symmetric positive definite, so no pivoting is needed), the plain
+  definition; the eigen form of S4.3 gives the same values up to rounding.
+* Transforms: the package's own radix-2 FFT (``oracle.fft``), unnormalised
+  forward, inverse with 1/N.
 * Activation (S4.2): the component RMS amplitude; a block is active when any
   of its modes exceeds the threshold.  As in the rest of this package the
   threshold is relative: a(k) = sum_m |u_m(k)|^2 in FP64 (components in
@@ -26,6 +29,8 @@ order over the block grid.
 from __future__ import annotations
 
 import numpy as np
+
+from . import fft as _fft
 
 
 def diffusion_matrix(M: int, d_diag: float, d_cross: float) -> np.ndarray:
@@ -65,9 +70,34 @@ def reaction(u: np.ndarray, alpha: float, beta: float, r: float = 1.0, a: float 
     return out
 
 
+def signed_index(n: int) -> np.ndarray:
+    """Wavenumber index of each position in natural FFT order: i below n/2,
+    i - n from n/2 on (the Nyquist index maps to -n/2)."""
+    i = np.arange(n)
+    return np.where(2 * i < n, i, i - n).astype(np.float64)
+
+
+def solve(A: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """x with A x = b for a batch of symmetric positive definite systems:
+    A (n, M, M), b (n, M).  Forward elimination column by column (the pivot
+    stays on the diagonal, which positive definiteness keeps away from zero),
+    then back substitution."""
+    A = np.array(A, dtype=np.float64)
+    x = np.array(b, dtype=np.float64)
+    M = A.shape[1]
+    for k in range(M):
+        f = A[:, k + 1:, k] / A[:, k:k + 1, k]          # (n, M-k-1) multipliers
+        A[:, k + 1:, k:] -= f[:, :, None] * A[:, k:k + 1, k:]
+        x[:, k + 1:] -= f * x[:, k:k + 1]
+    for k in range(M - 1, -1, -1):
+        s = x[:, k] - np.sum(A[:, k, k + 1:] * x[:, k + 1:], axis=1)
+        x[:, k] = s / A[:, k, k]
+    return x
+
+
 def k2(dims, dx: float) -> np.ndarray:
     """|k|^2 of every mode, natural FFT order, flattened in C order."""
-    ks = [2.0 * np.pi * np.fft.fftfreq(n, d=dx) for n in dims]
+    ks = [2.0 * np.pi * signed_index(n) / (n * dx) for n in dims]
     grids = np.meshgrid(*ks, indexing="ij")
     return sum(g * g for g in grids).ravel()
 
@@ -97,8 +127,8 @@ def update_modes(q, rhat, k2v, dt: float, D: np.ndarray) -> np.ndarray:
     M, n = q.shape
     b = q + dt * rhat
     A = np.eye(M)[None, :, :] + dt * k2v[:, None, None] * D[None, :, :]
-    xr = np.linalg.solve(A, b.real.T[:, :, None])[:, :, 0]
-    xi = np.linalg.solve(A, b.imag.T[:, :, None])[:, :, 0]
+    xr = solve(A, b.real.T)
+    xi = solve(A, b.imag.T)
     return (xr + 1j * xi).T
 
 
@@ -136,9 +166,9 @@ def step(q, steps: int, dims, block, tau: float, dt: float, dx: float, d_diag: f
     M = q.shape[0]
     log = []
     for _ in range(steps):
-        u = np.stack([np.fft.ifftn(q[m].reshape(dims)).real for m in range(M)])
+        u = np.stack([_fft(q[m].reshape(dims), +1).real for m in range(M)])
         R = reaction(u, alpha, beta, r, a)
-        rhat = np.stack([np.fft.fftn(R[m]).ravel() for m in range(M)])
+        rhat = np.stack([_fft(R[m].astype(np.complex128), -1).ravel() for m in range(M)])
         res = apply(q, rhat, dims, block, tau, dt, dx, d_diag, d_cross, pin_k0, dense)
         q = res["q"]
         if masks:

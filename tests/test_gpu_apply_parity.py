@@ -84,6 +84,9 @@ CASES = [
     ([D("nlse", "f32", 1, 4096, 256, 1e-4, dense=True)], 17),
     ([D("ch", "f32", 2, 512, 256, 1e-3)], 18),    # 2-D blocks whose rows span two wave rows
     ([D("gs", "f32", 2, 512, 256, 1e-3), D("gs", "f32", 2, 1024, 256, 1e-3)], 19),
+    ([D("ch", "f64", 3, 32, 8, 1e-6)], 23),     # three-dimensional FP64 (the equal-error truth's path)
+    ([D("ch", "f64", 3, 64, 8, 3e-3)], 24),
+    ([D("ch", "f64", 3, 32, 8, 0.0, dense=True)], 25),
 ]
 
 

@@ -267,3 +267,101 @@ def test_stage_timing_and_update_variants_agree():
         print(f"indicator kernel {ik * 1e3:.1f} us, stage {stage * 1e3:.1f} us", flush=True)
         assert 0.0 < ik <= stage * 1.05 + 1e-3
         p.destroy()
+
+
+def _masks_match_or_tie(m, r, ab, st):
+    """Per-step mask parity with the documented near-tie exception."""
+    if np.array_equal(m, r):
+        return 0
+    thr = 1e-12 * ab.max()
+    bad = np.flatnonzero(m != r)
+    near = np.abs(ab[bad] - thr) <= 1e-12 * thr
+    assert near.all(), f"step {st}: mask mismatch at blocks {bad[~near][:8]}"
+    return bad.size
+
+
+@pytest.mark.parametrize("measure", ["increment", "state"])
+def test_ch3d_64_f64_trajectory_masks_bit_exact(measure):
+    """Three-dimensional FP64 trajectory (the path that gives the FP64 truth
+    of the timed 3-D workloads): per-step masks bit-exact, field within 1e-10."""
+    import torch
+
+    n, steps = 64, 100
+    d = ch_desc("f64", 3, n, 8, 1e-6, state_indicator=(measure == "state"))
+    c0 = inputs.uniform_field(1002, 2, (n, n, n), 0.1, 0.02)
+    print(f"ch3d_64_f64 {measure} trajectory, {steps} steps", flush=True)
+    ref = O.step(oracle_inst(d), O.fft(c0, -1), steps, masks=True, ab=True)
+    plan = S.Plan([d])
+    plan.set_field(0, torch.from_numpy(c0.ravel()))
+    ties = 0
+    for st in range(steps):
+        plan.step(1)
+        ties += _masks_match_or_tie(plan.active_mask(0), ref["masks"][st, 0], ref["ab"][st, 0], st)
+    assert ties <= 2, ties
+    got = plan.get_field(0).cpu().numpy()
+    want = oracle_field_from_spectrum(d, ref["state"])
+    err = rel_l2(got - want.mean(), want - want.mean())
+    print(f"ch3d_64_f64 {measure}: fluctuation rel-L2 {err:.3e}, ties {ties}, active fraction last "
+          f"step {ref['masks'][-1, 0].mean():.3f}", flush=True)
+    assert err <= 1e-10
+    plan.destroy()
+
+
+def test_ch3d_f64_dense_matches_oracle():
+    """The dense FP64 3-D run (Regular mode) against the oracle's dense run."""
+    import torch
+
+    n, steps = 32, 50
+    d = ch_desc("f64", 3, n, 8, 0.0, dense=True)
+    c0 = inputs.uniform_field(1002, 3, (n, n, n), 0.1, 0.02)
+    ref = O.step(oracle_inst(d), O.fft(c0, -1), steps)
+    plan = S.Plan([d])
+    plan.set_field(0, torch.from_numpy(c0.ravel()))
+    plan.step(steps)
+    got = plan.get_field(0).cpu().numpy()
+    want = oracle_field_from_spectrum(d, ref["state"])
+    err = rel_l2(got - want.mean(), want - want.mean())
+    print(f"ch3d_32_f64 dense: fluctuation rel-L2 {err:.3e}", flush=True)
+    assert err <= 1e-10
+    plan.destroy()
+
+
+@pytest.mark.parametrize("dtype,ndim,n,block,steps", [("f64", 2, 128, 16, 60), ("f32", 3, 32, 8, 40),
+                                                      ("f64", 3, 32, 8, 40)])
+def test_free_energy_matches_oracle_and_decays(dtype, ndim, n, block, steps):
+    """stats().energy (FP64 sums on the GPU) against the oracle's free energy of
+    the same stored spectrum, step by step, and its decay along the run
+    (survey pin: F^{n+1} <= F^n (1 + 1e-12) for the dense FP64 run; the
+    adaptive run is checked with the same bound here)."""
+    import torch
+
+    shape = (n,) * ndim
+    d = ch_desc(dtype, ndim, n, block, 1e-6)
+    d64 = ch_desc("f64", ndim, n, block, 1e-6)
+    mean, hw = (0.0, 0.05) if ndim == 2 else (0.1, 0.02)
+    c0 = inputs.uniform_field(1001 + ndim, 4, shape, mean, hw)
+    rt = np.float64 if dtype == "f64" else np.float32
+    plan = S.Plan([d])
+    plan.set_field(0, torch.from_numpy(c0.ravel().astype(rt)))
+    energies, worst = [], 0.0
+    for st in range(steps):
+        hat, k0 = plan.get_spectrum(0)
+        chat = hat.cpu().numpy().astype(np.complex128)
+        if dtype == "f32":
+            chat[0] = k0[0]  # the k = 0 coefficient lives in FP64
+        want_e, want_m = O.ch_energy(oracle_inst(d64), chat)
+        plan.step(1)
+        s = plan.stats(0)
+        rel = abs(s["energy"] - want_e) / abs(want_e)
+        worst = max(worst, rel)
+        # FP64: the same spectrum and FP64 sums; FP32: the GPU forms c with an
+        # FP32 inverse transform (relative rounding ~1e-7 of |c|)
+        assert rel <= (1e-12 if dtype == "f64" else 1e-6), (st, s["energy"], want_e)
+        assert abs(s["mean"][0] - want_m) <= 1e-12 * max(1.0, abs(want_m))
+        energies.append(s["energy"])
+    e = np.array(energies)
+    print(f"free energy {dtype} {ndim}-D n={n}: worst rel diff vs oracle {worst:.2e}, "
+          f"F {e[0]:.10e} -> {e[-1]:.10e}", flush=True)
+    assert np.all(e[1:] <= e[:-1] * (1 + 1e-12) + (0 if dtype == "f64" else 1e-6 * abs(e[0])))
+    assert e[-1] < e[0]
+    plan.destroy()

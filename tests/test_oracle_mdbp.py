@@ -94,3 +94,22 @@ def test_measure_parseval_and_packets():
     # three packets of amplitude sqrt(P0/3) = sqrt(3): at t = 0 the middle one
     # plus the tails of the two at +-20 (exp(-400/200) each, carrier phase 0)
     assert np.isclose(abs(Et[0, N // 2]), np.sqrt(3.0) * (1 + 2 * np.exp(-2.0)), rtol=1e-12)
+
+
+@pytest.mark.parametrize("delta", [0.3, 2.5, 40.0])
+def test_expm_closed_form_two_modes(delta):
+    """exp(i d sigma_x) = cos d I + i sin d sigma_x, and for a Hermitian K with
+    K^2 = I (a reflection) the same form; the large argument exercises the
+    squaring steps."""
+    sx = np.array([[0.0, 1.0], [1.0, 0.0]])
+    want = np.cos(delta) * np.eye(2) + 1j * np.sin(delta) * sx
+    assert np.allclose(O.expm_i(sx, delta), want, rtol=0, atol=1e-12)
+    v = np.array([1.0, 1j]) / np.sqrt(2.0)
+    R = 2.0 * np.outer(v, v.conj()) - np.eye(2)     # Hermitian, R^2 = I
+    want = np.cos(delta) * np.eye(2) + 1j * np.sin(delta) * R
+    assert np.allclose(O.expm_i(R, delta), want, rtol=0, atol=1e-12)
+
+
+def test_omega_signed_bins():
+    w = O.omega(8, 2.0)
+    assert np.allclose(w, 2 * np.pi * np.array([0, 1, 2, 3, -4, -3, -2, -1]) / 2.0, rtol=0, atol=0)

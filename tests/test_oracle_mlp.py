@@ -90,3 +90,81 @@ def test_block_features_hand_cases():
     m = np.where(np.arange(16) < 8, np.arange(16), np.arange(16) - 16)
     assert np.isclose(g[0, 3], np.mean(np.abs(m)) / 8)
     assert np.array_equal(mlp.labels([[0, 1, 0], [0, 0, 1]]), [0, 1, 1])
+
+
+def test_bce_closed_forms():
+    """Weighted BCE on logits: at z = 0 every sample costs ln 2, the positive
+    weight multiplying the positives only; far from zero the loss is |z| on the
+    wrong side (times the weight for positives) and vanishes on the right side.
+    A loss with the weight on the wrong class, or with a sign slip in the
+    softplus arguments, fails these values."""
+    ln2 = np.log(2.0)
+    pw = 5.0
+    y = np.array([1.0, 1.0, 0.0, 0.0, 0.0])
+    loss, d = mlp.bce(np.zeros(5), y, pw)
+    assert np.isclose(loss, (2 * pw * ln2 + 3 * ln2) / 5, rtol=0, atol=1e-15)
+    # gradient at z = 0: sigmoid(0) = 1/2, so pw (p - 1) = -pw/2 for positives, +1/2 for negatives
+    assert np.allclose(d, np.array([-pw / 2, -pw / 2, 0.5, 0.5, 0.5]) / 5, rtol=0, atol=1e-16)
+    big = 40.0
+    # all positives: right side costs pw * log(1 + e^-40), wrong side pw * (40 + log(1 + e^-40))
+    l_right, _ = mlp.bce(np.array([big]), np.array([1.0]), pw)
+    l_wrong, d_wrong = mlp.bce(np.array([-big]), np.array([1.0]), pw)
+    assert np.isclose(l_right, pw * np.log1p(np.exp(-big)), rtol=1e-12)
+    assert np.isclose(l_wrong, pw * (big + np.log1p(np.exp(-big))), rtol=1e-14)
+    assert np.isclose(d_wrong[0], -pw * (1 - 1 / (1 + np.exp(big))), rtol=1e-14)
+    # all negatives: no weight
+    l_wrong0, d_wrong0 = mlp.bce(np.array([big]), np.array([0.0]), pw)
+    assert np.isclose(l_wrong0, big + np.log1p(np.exp(-big)), rtol=1e-14)
+    assert np.isclose(d_wrong0[0], 1 / (1 + np.exp(-big)), rtol=1e-14)
+    assert np.isclose(mlp.bce(np.array([-big]), np.array([0.0]), pw)[0], np.log1p(np.exp(-big)), rtol=1e-12)
+
+
+def _hand_net():
+    """x = (1, 1, 0, ...): h1_0 = 1 + 2^-9 (FP32-exact, a bf16 tie that rounds
+    to 1), h1_1 = 1; h2_0 = bf16(h1_0) + 2^-9 bf16(h1_1); logit = 512 h2_0.
+    Every weight is a power of two (bf16-exact)."""
+    W1 = np.zeros((8, 64))
+    W2 = np.zeros((64, 64))
+    W3 = np.zeros(64)
+    W1[0, 0] = 1.0
+    W1[1, 0] = 2.0 ** -9
+    W1[0, 1] = 1.0
+    W2[0, 0] = 1.0
+    W2[1, 0] = 2.0 ** -9
+    W2[1, 1] = 1.0
+    W3[0] = 512.0
+    w = mlp.pack(W1, np.zeros(64), W2, np.zeros(64), W3, 0.0, np.float32)
+    x = np.zeros((1, 8), np.float32)
+    x[0, :2] = 1.0
+    return x, w
+
+
+def test_bf16_rounding_points_of_the_forward():
+    """The emulation rounds each layer's input to bf16 before its product.
+    With both hidden roundings the logit is 512 exactly; dropping the h1
+    rounding gives 512 (1 + 2^-8) = 514, dropping the h2 rounding gives
+    512 (1 + 2^-9) = 513, and FP64 without rounding gives 514."""
+    x, w = _hand_net()
+    assert mlp.forward_bf16(x, w)["logit"][0] == 512.0
+    assert mlp.forward64(x, w)["logit"][0] == 514.0
+    # the layer values themselves: h1 keeps FP32 (the rounding is at the next input)
+    fw = mlp.forward_bf16(x, w)
+    assert fw["h1"][0, 0] == np.float32(1 + 2 ** -9) and fw["h2"][0, 0] == np.float32(1 + 2 ** -9)
+
+
+def test_bf16_rounding_points_of_the_backward():
+    """dW3 = bf16(h2)^T bf16(dlogit): with h2_0 = 1 + 2^-9 (rounds to 1) and
+    dlogit = 1 + 2^-9 (rounds to 1) the emulated gradient entry is exactly 1,
+    where FP64 gives (1 + 2^-9)^2.  dW1 = bf16(x)^T bf16(dh1) with dh1_0 =
+    bf16(dh2) W2^T: dh2_0 = W3_0 dlogit = 512 + 1 = 513 rounds to 512 in bf16,
+    so dh1_1 = 512 * 2^-9 = 1 (FP64: 513 * 2^-9)."""
+    x, w = _hand_net()
+    fw = mlp.forward_bf16(x, w)
+    dl = np.array([1 + 2 ** -9], np.float32)
+    g = mlp.backward_bf16(x, w, fw, dl)
+    assert g[mlp.OW3 + 0] == 1.0
+    W1g = g[mlp.OW1:mlp.OB1].reshape(8, 64)
+    assert W1g[0, 1] == 1.0 and W1g[1, 1] == 1.0
+    g64 = mlp.backward64(x, w, mlp.forward64(x, w), dl.astype(np.float64))
+    assert g64[mlp.OW3 + 0] == (1 + 2 ** -8) * (1 + 2 ** -9)
+    assert g64[mlp.OW1:mlp.OB1].reshape(8, 64)[1, 1] == 513 * 2.0 ** -9

@@ -146,3 +146,27 @@ def test_eigen_form_identity():
         Ai = np.linalg.inv(np.eye(M) + DT * k2v * D)
         Ae = V @ np.diag(1.0 / (1.0 + DT * k2v * lam)) @ V.T
         assert np.allclose(Ai, Ae, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("M", [2, 3, 7, 16, 64])
+def test_solve_recovers_known_solutions(M):
+    """The written-out elimination against systems whose solution is fixed in
+    advance (b = A x for a chosen x), over the SPD matrices the update forms,
+    a diagonal one (x = b / diag) and a matrix with wide coefficient range."""
+    rng = np.random.default_rng(M)
+    D = rcd.diffusion_matrix(M, DD, DC)
+    s = np.array([0.0, 0.3, 17.0, 4e3])
+    A = np.eye(M)[None] + s[:, None, None] * D[None]
+    x = rng.normal(size=(s.size, M))
+    b = np.einsum("nij,nj->ni", A, x)
+    assert np.allclose(rcd.solve(A, b), x, rtol=0, atol=1e-12 * np.max(np.abs(x)))
+    d = rng.uniform(0.5, 4.0, M)
+    assert np.allclose(rcd.solve(np.diag(d)[None], d[None] * x[:1]), x[:1], rtol=1e-15, atol=0)
+    Q = rng.normal(size=(M, M))
+    S = Q @ Q.T + M * np.eye(M)
+    assert np.allclose(S @ rcd.solve(S[None], b[:1])[0], b[0], rtol=0, atol=1e-11 * np.max(np.abs(b[0])))
+
+
+def test_signed_index():
+    assert list(rcd.signed_index(8)) == [0, 1, 2, 3, -4, -3, -2, -1]
+    assert list(rcd.signed_index(1)) == [0]
