@@ -1,17 +1,26 @@
 """Benchmark of the sp-DBA hot path on one MI355X.
 
-Default workload: 3-D Cahn-Hilliard on a 256^3 periodic grid, FP32 fields and
-transforms with FP64 k = 0 mode and FP64 indicator reductions, 8^3 k-space
-blocks, relative threshold 1e-6, dt = 0.01, seeded initial field
+Default workload: 3-D Cahn-Hilliard on a 512^3 periodic grid, FP32 fields and
+transforms with the FP64 k = 0 mode and FP64 indicator reductions, 8^3 k-space
+blocks, dt = 0.01, a 500-step horizon from the seeded initial field
 0.1 + U(-0.02, 0.02).  A step is one full pass of the hot path: inverse FFT,
-fused nonlinear term, forward FFT, indicator, compaction, active-block update.
+fused nonlinear term, forward FFT, activity measure, compaction, active-block
+update.  The timed steps are the last K of the horizon (``--steps K``,
+default 20), three repeats from the same device state after W untimed
+warm-up steps (``--warmup W``), HIP-graph replay.
 
-Prints ONE JSON line.  ``value`` is whole-job throughput in Gpts/s: grid points
-advanced per second over the timed steps (transforms included), inputs resident
-in HBM.  Extra keys report steps/s, the update-stage rate, the dense (Regular)
-run on the same input, the roofline of the dominant kernel of the update stage
-(the indicator, from HIP events on the plan's stream inside the timed region)
-and the CPU oracle on a bounded sample.
+Dense (Regular), plain sp-DBA with the kept state measure and with the
+increment measure (threshold sweeps) and the learned proposer all run the same
+horizon; the equal-L2-error protocol compares their fields at step 500 with
+the FP64 dense run on the GPU.
+
+Prints ONE JSON line.  ``value`` is whole-job throughput in Gpts/s of the
+fastest plain sp-DBA run that meets the equal-error bar: grid points advanced
+per second over the timed steps (transforms included), inputs resident in HBM.
+Extra keys give steps/s against dense, the spectral-update rate of the update
+stage, the stage breakdown, the roofline of the active update (HIP events on
+the plan's stream), the proposer leg and the CPU oracle on a bounded sample.
+Other workloads: ``--config NAME`` (configs.py).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME] [--no-cpu]
 """
@@ -35,12 +44,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="ch3d_256_f32")
+    ap.add_argument("--config", default="ch3d_512_f32_proposer")
+    ap.add_argument("--no-proposer", action="store_true", help="512^3 workload: skip the learned proposer leg")
+    ap.add_argument("--only", default=None, metavar="MEASURE:TAU",
+                    help="512^3 workload, profiling runs: one eager sp-DBA run of the horizon with that "
+                         "measure and threshold (and an eager dense run), printing the active blocks of each "
+                         "timed step; no equal-error protocol")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense comparison run")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager steps instead of HIP-graph replay (the stage breakdown is always eager)")
     ap.add_argument("--tune", action="store_true", help="re-run the launch autotuner first")
+    ap.add_argument("--tune-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-equal-error", action="store_true",
                     help="skip the threshold sweep at equal L2 error against the FP64 dense run")
     ap.add_argument("--control", action="store_true",
@@ -150,12 +165,16 @@ def update_kernel_name(cfg, descs, measure, layout, choice):
     """The active-update kernel the plan launches for its tuned variant (launch
     kernel 3; default 1): the half layout has its own walk; the strip walk and
     the x4 walk stand aside for the measure the update keeps (CH, GS); the
-    one-wave-per-entry walk needs blocks of at least 64 lane slots."""
+    one-wave-per-entry walk needs blocks of at least 64 lane slots; the run
+    walk equal blocks of 256 or 512 slots, CH or GS, and no block-energy sum."""
     if layout == "half":
         return "k_update_h"
     v = int((choice or {}).get("3", 1))
     kept = measure in ("state", "energy") and cfg["op"] != "nlse"
     slots = min(d.block3[0] * d.block3[1] * d.block3[2] // (1 if d.dtype == "f64" else 2) for d in descs)
+    slots_max = max(d.block3[0] * d.block3[1] * d.block3[2] // (1 if d.dtype == "f64" else 2) for d in descs)
+    if v == 4 and cfg["op"] != "nlse" and measure != "energy" and slots == slots_max and slots in (256, 512):
+        return "k_update_run"
     if v == 3 and slots >= 64:
         return "k_update_wave"
     if v == 2 and not kept and slots <= 256:
@@ -268,7 +287,7 @@ def main():
 
     cfg = configs.BY_NAME[args.config]
     if "proposer" in cfg:
-        return proposer_bench(args, cfg)
+        return c5_bench(args, cfg)
     if cfg["op"] == "rcd":
         return rcd_bench(args, cfg)
     if cfg["op"] == "mdbp":
@@ -708,13 +727,27 @@ def copy_peak(torch, nbytes=1 << 30, reps=5):
     return round(2 * nbytes / ms / 1e6, 1)
 
 
-def proposer_bench(args, cfg):
-    """512^3 CH with the learned proposer, at equal L2 error: tau* from a
-    sweep against the FP64 dense truth at 512^3; train on logged 256^3 plain
-    runs at tau*,
-    pick the threshold by simulating the window protocol on a held-out seed
-    (largest expected skipped share with at most 20 % miss windows), then time the
-    proposer, the plain rule and the dense update on the workload's seed."""
+# ---------------------------------------------------------------------------
+# headline workload: 512^3 Cahn-Hilliard FP32, timed at the end of its horizon
+# ---------------------------------------------------------------------------
+
+def c5_bench(args, cfg):
+    """512^3 CH (FP32 fields and transforms, FP64 k = 0 and reductions, 8^3
+    blocks): dense (Regular), plain sp-DBA with the kept state measure and with
+    the increment measure over threshold sweeps, and the learned proposer, all
+    at equal L2 error against the FP64 dense run of the same 500-step horizon
+    (the GPU's FP64 path, parity-tested in three dimensions against the
+    oracle).
+
+    Timing protocol (paper: warm-up, then three repeats, wall clock between
+    synchronisations): every run advances the workload's first H - K steps
+    untimed (HIP-graph replay, the graph captured and warmed on the way), keeps
+    a device copy of its state and work buffers, takes W untimed warm-up steps
+    from it, then times the last K steps of the horizon three times, restoring
+    the copy before each repeat; the median is reported.  The field after the
+    last repeat is the field at step H, whose error the equal-error protocol
+    uses.  Stage times and the active update's roofline come from an eager
+    run of the same window with the plan's per-stage HIP events."""
     import numpy as np
     import torch
 
@@ -722,59 +755,263 @@ def proposer_bench(args, cfg):
     from paper_2609_03922_amd import proposer as P
     from paper_2609_03922_amd import spdba as S
 
-    pc = cfg["proposer"]
-    Kw, audit = pc["K"], pc["audit_steps"]
-    K = args.steps if args.steps is not None else min(cfg["steps"], 500)
-    W = args.warmup
+    t_start = time.perf_counter()
+    H = cfg["steps"]
+    K = args.steps if args.steps is not None else 20
+    K = max(1, min(K, H))
+    A = H - K
+    W = max(0, args.warmup)
+    n = cfg["n"]
+    ntot = n ** 3
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
-    n_train = pc["train_n"]
-    seeds = list(pc["train_seeds"])
-    log_steps = int(os.environ.get("SPDBA_PROPOSER_LOG_STEPS", cfg["steps"]))
+    ic = cfg["ic"]
+    f64 = inputs.uniform_field(cfg["seed"], 0, (n,) * 3, ic["mean"], ic["half_width"])
+    field = {"f64": torch.from_numpy(f64.ravel()),
+             "f32": torch.from_numpy(f64.astype(np.float32).ravel())}
+    meas_flags = {"increment": {}, "state": dict(state_indicator=True),
+                  "energy": dict(state_indicator=True, block_energy=True)}
 
-    # the comparison runs at equal L2 error: tau* from the sweep against the
-    # FP64 dense truth at the workload's size and horizon (--no-equal-error:
-    # the configured tau)
-    eq = None
-    tau = cfg["tau"]
-    if not args.no_equal_error:
-        eq = equal_error(cfg, [cfg["n"]], cfg["steps"], W, S, inputs, autotune, arch, np, torch,
-                         taus=(1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6))
-        if eq.get("tau_star") is not None:
-            tau = eq["tau_star"]
+    def log(msg):
+        print(f"[{time.perf_counter() - t_start:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
-    def make(n, seed, **kw):
-        kw.setdefault("tau", tau)
-        d = S.desc_from_config(cfg, n=n, timing=True, **kw)
+    def make(dtype="f32", tau=None, dense=False, measure="increment", graph=True, timing=False, n_=n, seed=None):
+        d = S.desc_from_config(cfg, n=n_, dtype=dtype, tau=cfg["tau"] if tau is None else tau, dense=dense,
+                               graph=graph, timing=timing, **({} if dense else meas_flags[measure]))
         p = S.Plan([d])
-        autotune.apply_cached(p, arch)
-        ic = cfg["ic"]
-        f = inputs.uniform_field(seed, 0, (n,) * 3, ic["mean"], ic["half_width"], dtype=np.float32)
-        p.set_field(0, torch.from_numpy(f.ravel()))
+        entry = autotune.apply_cached(p, arch)
+        if seed is None and n_ == n:
+            p.set_field(0, field[dtype])
+        else:
+            f = inputs.uniform_field(cfg["seed"] if seed is None else seed, 0, (n_,) * 3, ic["mean"],
+                                     ic["half_width"], dtype=np.float64 if dtype == "f64" else np.float32)
+            p.set_field(0, torch.from_numpy(f.ravel()))
+        p.entry = entry
         return p
 
-    if args.tune:
+    def window(p):
+        """Advance to step H - K, keep a copy, take W untimed warm-up steps,
+        then time the last K steps three times from the copy; returns the
+        median ms per step."""
+        p.step(A)
+        torch.cuda.synchronize()
+        snap = (p.d_state.clone(), p.d_work.clone())
+        if W:  # untimed warm-up steps from the copy
+            p.step(W)
+            torch.cuda.synchronize()
+        ms = []
+        for rep in range(3):
+            p.d_state.copy_(snap[0])
+            p.d_work.copy_(snap[1])
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(p.stream)
+            p.step(K)
+            e1.record(p.stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1) / K)
+        del snap
+        return float(np.median(ms)), ms
+
+    if args.tune:  # launch geometry of the state-measure plan, tuned at the timed window's activity
         def make_tune(dense):
-            return make(cfg["n"], cfg["seed"], dense=dense)
+            d = S.desc_from_config(cfg, timing=True, dense=dense, **({} if dense else meas_flags["state"]))
+            return S.Plan([d])
 
-        def init_tune(p):
-            ic = cfg["ic"]
-            f = inputs.uniform_field(cfg["seed"], 0, (cfg["n"],) * 3, ic["mean"], ic["half_width"],
-                                     dtype=np.float32)
-            p.set_field(0, torch.from_numpy(f.ravel()))
-
-        _, timings = autotune.tune(make_tune, init_tune, steps=10, arch=arch, warm=100)
+        choice, timings = autotune.tune(make_tune, lambda p: p.set_field(0, field["f32"]), arch=arch, warm=A)
+        log(f"launch tuning: {choice}")
         print("launch tuning (stage ms):", json.dumps(timings), file=sys.stderr, flush=True)
+        if args.tune_only:
+            print(json.dumps({"tuned": {str(k): v for k, v in choice.items()}}), flush=True)
+            return
 
+    if args.only:  # profiling: eager runs of the horizon, no truth, no sweeps
+        measure, tau = args.only.split(":")
+        res = {}
+        for key, kw in (("dense", dict(dense=True)), (args.only, dict(measure=measure, tau=float(tau)))):
+            p = make(graph=False, timing=True, **kw)
+            for s0 in range(0, A, 100):
+                p.step(min(100, A - s0))
+                torch.cuda.synchronize()
+                log(f"{key}: {s0 + min(100, A - s0)} steps")
+            act = []
+            for _ in range(K):
+                p.step(1)
+                act.append(p.stats(0)["active_blocks"])
+            st = p.stats(0)
+            res[key] = {"active_blocks_per_timed_step": act, "launch": (p.entry or {}).get("choice"),
+                        "stage_ms_last64": [round(v, 4) for v in st["stage_ms"]]}
+            p.destroy()
+            log(f"{key}: {A} + {K} eager steps")
+        print(json.dumps({"only": args.only, "horizon": H, "timed_steps": K, "runs": res}), flush=True)
+        return
+
+    # ---- truth: FP64 dense run over the horizon -----------------------------
+    p = make("f64", tau=0.0, dense=True)
+    p.step(H)
+    truth = p.get_field(0).double()
+    p.destroy()
+    tmean = float(truth.mean())
+    tnorm = float(torch.linalg.norm(truth - tmean))
+    log(f"FP64 dense truth, {H} steps")
+
+    def err_of(p):
+        g = p.get_field(0).double()
+        return float(torch.linalg.norm(g - truth)) / tnorm
+
+    runs = {}
+
+    def timed(key, **kw):
+        p = make(**kw)
+        ms, reps = window(p)
+        st = p.stats(0)
+        r = {"ms_per_step": round(ms, 4), "repeats_ms": [round(x, 4) for x in reps], "rel_l2": err_of(p),
+             "active_fraction_last_step": round(st["active_blocks"] / st["total_blocks"], 4),
+             "launch": (p.entry or {}).get("choice")}
+        p.destroy()
+        runs[key] = r
+        log(f"{key}: {ms:.4f} ms/step, rel-L2 {r['rel_l2']:.3e}, active {r['active_fraction_last_step']}")
+        return r
+
+    dense = timed("dense", dense=True)
+    e_d = dense["rel_l2"]
+    bar = 1.1 * e_d
+    sweeps = {}
+    for measure, taus in (("state", (1e-5, 3e-6, 1e-6, 3e-7)),
+                          ("increment", (1e-4, 3e-5, 1e-5, 3e-6, 1e-6))):
+        rows = []
+        for tau in taus:
+            r = timed(f"{measure} tau={tau:g}", tau=tau, measure=measure)
+            rows.append(dict(tau=tau, **r, meets_equal_error=r["rel_l2"] <= bar,
+                             speedup_steps_vs_dense=round(dense["ms_per_step"] / r["ms_per_step"], 4)))
+        ok = [r for r in rows if r["meets_equal_error"]]
+        star = max(ok, key=lambda r: r["tau"]) if ok else None
+        sweeps[measure] = {"sweep": rows, "tau_star": star["tau"] if star else None,
+                           "speedup_steps_vs_dense_at_equal_error": star["speedup_steps_vs_dense"] if star else None}
+
+    # ---- stage breakdown and the active update's roofline (eager window) ----
+    def stages(measure, tau, dense_flag=False):
+        p = make(tau=tau, measure=measure, dense=dense_flag, graph=False, timing=True)
+        p.step(A)
+        torch.cuda.synchronize()
+        choice = (p.entry or {}).get("choice") or {}
+        p.set_launch(3, int(choice.get("3", 1)))  # resets the stage-time ring
+        act = []
+        for _ in range(K):
+            p.step(1)
+            act.append(p.stats(0)["active_blocks"])
+        st = p.stats(0)
+        p.destroy()
+        names = ("fft", "nonlinear", "indicator", "compaction", "update", "step")
+        return {k: round(float(v), 4) for k, v in zip(names, st["stage_ms"])}, act, choice
+
+    best_measure = max((m for m in sweeps if sweeps[m]["tau_star"] is not None),
+                       key=lambda m: sweeps[m]["speedup_steps_vs_dense_at_equal_error"], default=None)
+    dense_stage, _, dense_choice = stages("increment", 0.0, dense_flag=True)
+    log("stage breakdown: dense")
+    best = None
+    if best_measure is not None:
+        tau_b = sweeps[best_measure]["tau_star"]
+        best = runs[f"{best_measure} tau={tau_b:g}"]
+        sp_stage, act, choice = stages(best_measure, tau_b)
+        log(f"stage breakdown: {best_measure} tau={tau_b:g}")
+    else:  # nothing meets the bar: report the configured threshold's run
+        tau_b = 1e-6
+        best_measure = "state"
+        best = runs["state tau=1e-06"]
+        sp_stage, act, choice = stages("state", tau_b)
+
+    # active update: 24 B per active mode (state, right-hand side, state) and
+    # 12 B per active block (list entry, kept measure); mean over the window
+    bpb = cfg["block"] ** 3
+    mean_act = float(np.mean(act))
+    upd_bytes = mean_act * (bpb * 24 + 12)
+    upd_us = sp_stage["update"] * 1e3
+    upd_name = update_kernel_name(cfg, [S.desc_from_config(cfg)], best_measure, "full", choice)
+    ach = upd_bytes / (upd_us * 1e-6) / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": upd_name,
+            "role": "active update (the sp-DBA step's own kernel)", "bytes_per_launch": int(upd_bytes),
+            "avg_launch_us": round(upd_us, 2), "active_blocks_mean": round(mean_act, 1),
+            "run": f"eager window, {best_measure} tau={tau_b:g}, update-stage HIP events on the plan stream",
+            "copy_achievable_gbs": copy_peak(torch)}
+    ratio = profiled_traffic_ratio(upd_name, cfg["name"])
+    if ratio is not None:
+        roof["traffic"] = int(ratio * upd_bytes)
+        roof["traffic_over_algorithmic"] = ratio
+    dense_bytes = ntot * 24
+    kernels = {
+        "update": {"kernel": upd_name, "avg_launch_us": round(upd_us, 2), "bytes_per_launch": int(upd_bytes),
+                   "frac": roof["frac"]},
+        "dense_update": {"kernel": "k_dense", "avg_launch_us": round(dense_stage["update"] * 1e3, 2),
+                         "bytes_per_launch": dense_bytes,
+                         "frac": round(dense_bytes / (dense_stage["update"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "nonlinear": {"kernel": "k_nonlinear", "avg_launch_us": round(sp_stage["nonlinear"] * 1e3, 2),
+                      "bytes_per_launch": ntot * 16,
+                      "frac": round(ntot * 16 / (sp_stage["nonlinear"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+    }
+
+    # ---- learned proposer (increment measure at its tau*) -------------------
+    prop_out = None
+    tau_i = sweeps["increment"]["tau_star"] or cfg["tau"]
+    if not args.no_proposer:
+        prop_out = c5_proposer(cfg, make, truth, tnorm, tau_i, A, K, H, P, np, torch, log)
+
+    # ---- CPU oracle ----------------------------------------------------------
+    cpu = None
+    if not args.no_cpu:
+        cpu = oracle_baseline(cfg, [S.desc_from_config(cfg)], [n], inputs, np, budget=12.0, one_core=False,
+                              measure=best_measure)
+        log("CPU oracle sample")
+
+    ms_b = best["ms_per_step"]
+    upd_stage = sp_stage["indicator"] + sp_stage["compaction"] + sp_stage["update"]
+    r8 = runs.get("increment tau=1e-06")
+    out = {
+        "metric": METRIC, "value": round(ntot / (ms_b * 1e-3) / 1e9, 4), "unit": "Gpts/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": ms_b, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": cfg["name"], "grid": f"{n}^3", "block": cfg["block"], "measure": best_measure,
+                   "tau": tau_b, "horizon_steps": H, "timed_steps": f"{A}..{H - 1} (the last {K} of the horizon)",
+                   "timing": "HIP graph replay, median of 3 repeats from the same state", "parallelism": "single-gpu"},
+        "steps_per_s": round(1e3 / ms_b, 3),
+        "dense_steps_per_s": round(1e3 / dense["ms_per_step"], 3),
+        "speedup_steps_vs_dense_at_equal_error": round(dense["ms_per_step"] / ms_b, 4),
+        "equal_error": {"truth": "GPU FP64 dense run, same horizon", "dense_f32_rel_l2": e_d, "bar": bar,
+                        "measures": sweeps},
+        "increment_rule_tau_1e-6": ({"ms_per_step": r8["ms_per_step"], "rel_l2": r8["rel_l2"],
+                                     "speedup_steps_vs_dense": round(dense["ms_per_step"] / r8["ms_per_step"], 4)}
+                                    if r8 else None),
+        "stage_ms": sp_stage, "dense_stage_ms": dense_stage,
+        "update_stage_ms": round(upd_stage, 4),
+        "spectral_update_gpts_s": round(ntot / (upd_stage * 1e-3) / 1e9, 2),
+        "dense_spectral_update_gpts_s": round(ntot / (dense_stage["update"] * 1e-3) / 1e9, 2),
+        "update_stage_speedup_vs_dense": round(dense_stage["update"] / upd_stage, 3),
+        "active_fraction_window_mean": round(mean_act / (n // cfg["block"]) ** 3, 4),
+        "roofline": roof, "kernels": kernels,
+        "proposer": prop_out,
+        "cpu_baseline": cpu,
+        "wall_s": round(time.perf_counter() - t_start, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def c5_proposer(cfg, make, truth, tnorm, tau, A, K, H, P, np, torch, log):
+    """Train the proposer on masks logged from plain 256^3 runs (increment
+    measure at tau), pick its threshold by simulating the window protocol on a
+    held-out seed, then run it and the plain rule on the workload with the
+    window protocol (eager steps), timing the last K steps of the horizon."""
+    pc = cfg["proposer"]
+    Kw, audit = pc["K"], pc["audit_steps"]
+    n_train = pc["train_n"]
+    seeds = list(pc["train_seeds"])
     t0 = time.perf_counter()
     data = []
     for sd in seeds:
-        p = make(n_train, sd)
-        run = P.WindowRunner(p, None, K=Kw, audit=audit, total_steps=log_steps, log_masks=True)
-        run.step(log_steps)
+        p = make(tau=tau, graph=False, timing=False, n_=n_train, seed=sd)
+        run = P.WindowRunner(p, None, K=Kw, audit=audit, total_steps=H, log_masks=True)
+        run.step(H)
         data.append(run.dataset())
         p.destroy()
-        print(f"proposer training data: seed {sd}, {log_steps} logged steps at {n_train}^3",
-              file=sys.stderr, flush=True)
     X = torch.cat([d[0] for d in data[:-1]])
     Y = torch.cat([d[1] for d in data[:-1]])
     prop = P.Proposer(seed=1)
@@ -784,77 +1021,68 @@ def proposer_bench(args, cfg):
     held = [r for r in prop.threshold_table if r[0] == thr][0]
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-
-    results = {}
-    fields = {}
-    for mode in ("proposer", "plain", "dense"):
-        p = make(cfg["n"], cfg["seed"], dense=(mode == "dense"))
-        # the step-fraction feature is measured against the workload's nominal
-        # horizon, as in the logged training runs
-        horizon = cfg["steps"]
-        run = P.WindowRunner(p, prop if mode == "proposer" else None, K=Kw, audit=audit, total_steps=horizon)
-        run.step(W)
-        ic = cfg["ic"]
-        f = inputs.uniform_field(cfg["seed"], 0, (cfg["n"],) * 3, ic["mean"], ic["half_width"], dtype=np.float32)
-        p.set_field(0, torch.from_numpy(f.ravel()))
-        run = P.WindowRunner(p, prop if mode == "proposer" else None, K=Kw, audit=audit, total_steps=horizon)
+    log(f"proposer trained: {X.shape[0]} samples, threshold {thr:.4f}, {t_train:.1f} s")
+    out = {"tau": tau, "K": Kw, "audit_steps": audit, "threshold": thr,
+           "training": {"samples": int(X.shape[0]), "losses": [round(l, 5) for l in losses],
+                        "runs": f"{len(seeds) - 1} seeds x {H} steps at {n_train}^3 (one more held out)",
+                        "held_out_skip_share": round(held[1], 4), "held_out_miss_windows": round(held[2], 4),
+                        "seconds": round(t_train, 2)}}
+    for mode in ("plain", "proposer"):
+        p = make(tau=tau, graph=False, timing=True)
+        run = P.WindowRunner(p, prop if mode == "proposer" else None, K=Kw, audit=audit, total_steps=H)
+        run.step(A)
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
+        h0 = dict(run.history) if mode == "proposer" else None
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(p.stream)
         run.step(K)
+        e1.record(p.stream)
         torch.cuda.synchronize()
-        T = time.perf_counter() - t1
-        print(f"{mode}: {K} steps in {T:.2f} s", file=sys.stderr, flush=True)
+        ms = e0.elapsed_time(e1) / K
+        g = p.get_field(0).double()
+        err = float(torch.linalg.norm(g - truth)) / tnorm
         st = p.stats(0)
-        fields[mode] = p.get_field(0).double()
         nb = p.total_blocks()
-        results[mode] = {"steps_per_s": K / T, "wall_s": T,
-                         "stage_ms_last64": {k: round(v, 4) for k, v in zip(
-                             ("fft", "nonlinear", "indicator", "compaction", "update", "step"), st["stage_ms"])},
-                         "indicator_kernel_ms": round(st["indicator_kernel_ms"], 4),
-                         "active_fraction_last_step": st["active_blocks"] / nb}
+        r = {"ms_per_step": round(ms, 4), "rel_l2": err,
+             "stage_ms_last64": {k: round(v, 4) for k, v in zip(
+                 ("fft", "nonlinear", "indicator", "compaction", "update", "step"), st["stage_ms"])},
+             "active_fraction_last_step": round(st["active_blocks"] / nb, 4)}
         if mode == "proposer":
             h = run.history
-            results[mode]["windows"] = h["windows"]
-            results[mode]["misses"] = h["misses"]
-            results[mode]["skipped_block_step_share"] = h["skipped_block_steps"] / max(1, h["steps"] * nb)
+            r["windows"], r["misses"] = h["windows"], h["misses"]
+            r["skipped_block_step_share"] = round(h["skipped_block_steps"] / max(1, h["steps"] * nb), 4)
+            r["skipped_block_step_share_window"] = round(
+                (h["skipped_block_steps"] - h0["skipped_block_steps"]) / max(1, (h["steps"] - h0["steps"]) * nb), 4)
+            r["misses_window"] = h["misses"] - h0["misses"]
         p.destroy()
-    mean = float(fields["dense"].mean())
-    def rel(a, b):
-        return float(torch.linalg.norm(a - b) / torch.linalg.norm(b - mean))
-    errs = {"proposer_vs_dense": rel(fields["proposer"], fields["dense"]),
-            "plain_vs_dense": rel(fields["plain"], fields["dense"]),
-            "proposer_vs_plain": rel(fields["proposer"], fields["plain"])}
-    modes = cfg["n"] ** 3
-    pr = results["proposer"]
-    pl = results["plain"]
-    upd = lambda r: r["stage_ms_last64"]["indicator"] + r["stage_ms_last64"]["compaction"] + r["stage_ms_last64"]["update"]
-    ib = modes * 16 + 8 * (cfg["n"] // cfg["block"]) ** 3
-    ind_s = pl["indicator_kernel_ms"] * 1e-3
-    out = {
-        "metric": METRIC, "value": round(modes * pr["steps_per_s"] / 1e9, 4), "unit": "Gpts/s", "n_gpus": 1,
-        "steps": K, "warmup": W, "ms_per_step": round(1e3 / pr["steps_per_s"], 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": cfg["name"], "grid": f"{cfg['n']}^3", "block": cfg["block"], "tau": tau,
-                   "K": Kw, "audit_steps": audit, "train": f"{len(seeds) - 1} seeds x {log_steps} steps at {n_train}^3",
-                   "parallelism": "single-gpu"},
-        "proposer": pr, "plain": pl, "dense": results["dense"], "field_rel_l2": errs,
-        "training": {"samples": int(X.shape[0]), "losses": [round(l, 5) for l in losses], "threshold": thr,
-                     "held_out_skip_share": round(held[1], 4), "held_out_miss_windows": round(held[2], 4),
-                     "seconds": round(t_train, 2)},
-        "speedup_steps_vs_plain": round(pr["steps_per_s"] / pl["steps_per_s"], 4),
-        "speedup_steps_vs_dense": round(pr["steps_per_s"] / results["dense"]["steps_per_s"], 4),
-        "update_stage_ms": {"proposer": round(upd(pr), 4), "plain": round(upd(pl), 4),
-                            "dense": results["dense"]["stage_ms_last64"]["update"]},
-        "launch": (autotune.load_cache().get(autotune.cache_key([S.desc_from_config(cfg)], arch)) or {}).get("choice"),
-        "roofline": {"bound": "hbm", "achieved": round(ib / ind_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ib / ind_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": profiled_traffic("k_indicator", cfg["name"]),
-                     "kernel": "k_indicator (plain run, all blocks)", "bytes_per_launch": ib,
-                     "avg_launch_us": round(ind_s * 1e6, 2)},
-        "cpu_baseline": None,
-        "equal_error": eq,
-        "equal_error_best": best_at_equal_error(eq) if eq else None,
-    }
-    print(json.dumps(out), flush=True)
+        out[mode] = r
+        log(f"proposer bench {mode}: {ms:.4f} ms/step, rel-L2 {err:.3e}")
+    out["speedup_steps_vs_plain_eager"] = round(out["plain"]["ms_per_step"] / out["proposer"]["ms_per_step"], 4)
+    return out
+
+
+def profiled_traffic_ratio(kernel: str, workload: str):
+    """HBM traffic over algorithmic bytes of a kernel from its committed
+    rocprofv3 PMC summary (the same workload and window), or None when the
+    kernel's source changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            k, _, v = line.partition(":")
+            vals[k.strip()] = v.strip()
+    src = open(os.path.join(ROOT, "paper_2609_03922_amd", "csrc", "spdba_kernels.hip")).read()
+    try:
+        sha = kernel_source_sha(src, [f.strip() for f in vals["kernel_source_functions"].split(",")])
+    except (KeyError, ValueError):
+        return None
+    if vals.get("kernel_source_sha256_16") != sha or "traffic_over_algorithmic" not in vals:
+        return None
+    return float(vals["traffic_over_algorithmic"])
 
 
 def rcd_bench(args, cfg):

@@ -290,10 +290,14 @@ spdba_status spdba_stats(spdba_plan plan, int32_t inst, spdba_stats_t *out);
  * skips strips whose largest block value is at or below it, 2 = block-list
  * walk with four entries in flight per workgroup, 3 = block-list walk with
  * one wave per entry, each lane issuing up to four 16-byte slots' loads before
- * its stores, for blocks of at least 64 slots on the full layout; default 1).
+ * its stores, for blocks of at least 64 slots on the full layout; 4 = run walk:
+ * x-adjacent active blocks of a block row are cut into aligned pieces of up to
+ * 16 blocks and each piece into bands of rows as wide as the piece, one wave
+ * per band, for CH and GS on the full layout with equal blocks of 256 or 512
+ * slots, no transition blocks and no block-energy sum; default 1).
  * Where a variant does not apply (1 and 2 with the kept state measure, 2 on
- * blocks of more than 256 slots, 3 on blocks of fewer than 64) the update runs
- * as variant 0; on the half layout every variant runs that layout's own
+ * blocks of more than 256 slots, 3 on blocks of fewer than 64, 4 where its
+ * conditions fail) the update runs as variant 0; on the half layout every variant runs that layout's own
  * block-list walk.  4 = strip-walk update (waves per workgroup, power of two
  * 1..16).
  * Resets the stage-time ring. */

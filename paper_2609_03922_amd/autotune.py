@@ -110,10 +110,11 @@ def tune(make_plan, init_fields, steps: int = 20, arch: str = "gfx950", path: st
             p1, t_list = sweep(plan, 1, fixed=((3, 0),), tag="list ")
             p2, t_multi = sweep(plan, 1, fixed=((3, 2),), tag="list4 ")
             p3, t_wave = sweep(plan, 1, fixed=((3, 3),), tag="wave ")
-            best = min((t_strip, 1), (t_list, 0), (t_multi, 2), (t_wave, 3))[1]
+            p4, t_run = sweep(plan, 1, fixed=((3, 4),), tag="run ")
+            best = min((t_strip, 1), (t_list, 0), (t_multi, 2), (t_wave, 3), (t_run, 4))[1]
             result[3] = best
             result[4] = w4
-            result[1] = {1: ps, 0: p1, 2: p2, 3: p3}[best]
+            result[1] = {1: ps, 0: p1, 2: p2, 3: p3, 4: p4}[best]
         if not dense:  # the sparse plan carries the measure the key names
             key = cache_key(plan.descs, arch)
         plan.destroy()

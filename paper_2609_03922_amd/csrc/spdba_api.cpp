@@ -88,7 +88,9 @@ struct spdba_plan_s {
     // launch geometry
     int ind_waves = 4, nl_waves = 4, upd_per_cu = 4, dense_threads = 256, cu_count = 256;
     int upd_mode = 1;      // 0: block-list walk, 1: strip walk, 2: block-list walk, 4 entries in flight,
-                           // 3: block-list walk, one wave per entry
+                           // 3: block-list walk, one wave per entry, 4: run walk (band list)
+    int run_lmax = 0;      // run walk: longest piece in blocks, 0 where the walk does not apply
+    int run_ub = 0;        // run walk: slots per block / 64
     int upd_waves = 4;     // strip walk: waves per workgroup
     int max_slots = 0;     // largest block in 16-byte lane slots
     int min_slots = 0;     // smallest block in 16-byte lane slots
@@ -358,6 +360,13 @@ spdba_status update_stage(spdba_plan p, int ev_base, bool ind_done = false) {
         const int64_t grid = std::min<int64_t>(p->n_strips, (int64_t)p->cu_count * p->upd_per_cu);
         TRY_HIP(launch_update_strip(p->ctx, d, p->upd_waves, (int)grid, p->stream));
         p->list_stale = true;
+    } else if (p->upd_mode == 4 && p->run_lmax > 0) {
+        // threshold, mask and the band list of aligned runs, then the run walk
+        TRY_HIP(launch_compact_runs(p->ctx, p->stream));
+        record(p, ev_base + 1);
+        p->list_stale = true;
+        const int grid = ((p->cu_count * p->upd_per_cu + 7) / 8) * 8;
+        TRY_HIP(launch_update(p->ctx, d, grid, 3, p->stream));
     } else {
         // one-pass threshold, mask and unordered append of the active blocks
         TRY_HIP(launch_compact_append(p->ctx, p->stream));
@@ -627,6 +636,23 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
         p->hinst[i] = I;
     }
     p->nb_total = blk;
+    // the run walk: full layout, CH / GS without transition blocks or the
+    // block-energy sum (its bands give partial sums), equal blocks of 256 or
+    // 512 slots whose rows are at most one wave row, list entries of 24 bits
+    if (!p->half && p->op != OP_NLSE && !p->trans && !(inst[0].flags & SPDBA_FLAG_BLOCK_ENERGY) &&
+        p->min_slots == p->max_slots && (p->max_slots == 256 || p->max_slots == 512) && blk <= (int64_t)1 << 24) {
+        int lmax = 16;
+        for (int i = 0; i < n_inst; ++i) {
+            const InstDev &I = p->hinst[i];
+            const int lpr = I.b[2] / V;
+            if (lpr > 64) lmax = 0;
+            else lmax = std::min({lmax, 64 / lpr, I.nbk[2], I.b[0] * I.b[1]});
+        }
+        if (lmax > 0) {
+            p->run_lmax = lmax;
+            p->run_ub = p->max_slots / 64;
+        }
+    }
     p->n_taper = taper;
     p->n_htab = htab;
     p->n_strips = strip;
@@ -773,6 +799,8 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     // (the block energy is a sum: the full pass computes it every update in
     // one fixed order, so the update kernel does not keep it)
     c.ab_sum = (p->desc[0].flags & SPDBA_FLAG_BLOCK_ENERGY) ? 1 : 0;
+    c.run_lmax = p->run_lmax;
+    c.run_ub = p->run_ub;
     p->ab_inc = c.state_ind && p->op != OP_NLSE && !p->dense;
     c.ab_inc = p->ab_inc ? 1 : 0;
     c.a_next = reinterpret_cast<double *>(p->d_work + p->w_anext);
@@ -1213,7 +1241,7 @@ spdba_status spdba_set_launch(spdba_plan p, int32_t kernel, int32_t value) {
         case 0: if (!pow2_in(value, 1, 16)) return SPDBA_EINVAL; p->ind_waves = value; break;
         case 1: if (value < 1 || value > 64) return SPDBA_EINVAL; p->upd_per_cu = value; break;
         case 2: if (!pow2_in(value, 64, 1024)) return SPDBA_EINVAL; p->dense_threads = value; break;
-        case 3: if (value < 0 || value > 3) return SPDBA_EINVAL; p->upd_mode = value; break;
+        case 3: if (value < 0 || value > 4) return SPDBA_EINVAL; p->upd_mode = value; break;
         case 4: if (!pow2_in(value, 1, 16)) return SPDBA_EINVAL; p->upd_waves = value; break;
         default: return SPDBA_EINVAL;
     }

@@ -123,6 +123,8 @@ struct Ctx {
     int32_t half;              // half-spectrum layout
     int32_t half_nb;           // half: largest number of blocks of one (z, y) block row
     int32_t ab_sum;            // state measure: a_b is the block's sum (block energy), not its maximum
+    int32_t run_lmax;          // run walk: longest piece in blocks (power of two), 0 = not available
+    int32_t run_ub;            // run walk: 16-byte loads per lane and array (slots per block / 64)
     int64_t nb_total;
     int64_t n_strips;
     int64_t n_tiles;
@@ -143,12 +145,15 @@ hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s, hi
                             hipEvent_t e1 = nullptr);
 hipError_t launch_compact(const Ctx &c, hipStream_t s, int from_mask = 0);
 hipError_t launch_compact_append(const Ctx &c, hipStream_t s);
+// run walk: threshold, mask and the band list of aligned runs of active blocks
+hipError_t launch_compact_runs(const Ctx &c, hipStream_t s);
 // consistency control: block states and list; reset; roll-off tables
 hipError_t launch_compact_states(const Ctx &c, hipStream_t s);
 hipError_t launch_gmax(const Ctx &c, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_ctl_reset(const Ctx &c, int only_inst, hipStream_t s);
 hipError_t launch_tapers(const Ctx &c, hipStream_t s);
 hipError_t launch_htable(const Ctx &c, bool dbl, hipStream_t s);
+// multi: 0 block-list walk, 1 four entries in flight, 2 one wave per entry, 3 run walk (band list);
 // tr: transition weights; ctl: end-of-update control in the last workgroup
 hipError_t launch_update(const Ctx &c, bool dbl, int grid, int multi, hipStream_t s, bool tr = false,
                          bool ctl = false);

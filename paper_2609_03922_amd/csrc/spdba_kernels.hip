@@ -745,30 +745,70 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
 
 // Incremental state measure: the blocks the previous update stored (mask
 // nonzero) take the measure the update kernel wrote for them, the others keep
-// theirs; G of every instance is the maximum.  One block per thread; a wave
-// inside one instance sends one atomic.  Clears the append counter, as the
-// indicator does.
+// theirs; G of every instance is the maximum.  A workgroup takes 256 x
+// GMAX_PER consecutive blocks, GMAX_PER per thread at a stride of 256.  A
+// wave whose blocks lie in one instance reduces them, and the workgroup sends
+// one atomic per instance of its waves (device-scope atomics on one address
+// serialise, so one per wave would dominate the kernel); lanes whose blocks
+// span instances send their own.  Clears the append counter, as the indicator does.
+constexpr int GMAX_PER = 8;
 __global__ void __launch_bounds__(256) k_gmax(Ctx c) {
-    const int lane = threadIdx.x & 63;
-    const int64_t gb = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (gb == 0) *c.count = 0u;
+    __shared__ double wmax[4];
+    __shared__ int winst[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the workgroup's 256 * GMAX_PER blocks, thread t takes t, t + 256, ...
+    const int64_t b0 = (int64_t)blockIdx.x * 256 * GMAX_PER + threadIdx.x;
+    if (b0 == 0) *c.count = 0u;
     double v = 0.0;
-    int ii = -1;
-    if (gb < c.nb_total) {
-        ii = c.blk_inst[gb];
+    int ii = -1;     // instance of every block of this thread, or -2 if they differ
+    for (int k = 0; k < GMAX_PER; ++k) {
+        const int64_t gb = b0 + 256 * k;
+        if (gb >= c.nb_total) break;
+        const int ib = c.blk_inst[gb];
+        double a;
         if (c.mask[gb]) {
-            v = c.a_next[gb];
-            c.a_b[gb] = v;
+            a = c.a_next[gb];
+            c.a_b[gb] = a;
         } else {
-            v = c.a_b[gb];
+            a = c.a_b[gb];
+        }
+        if (ii == -1) ii = ib;
+        else if (ii != ib) ii = -2;
+        v = fmax(v, a);
+    }
+    if (ii == -2) {  // this thread's blocks span instances: one atomic per block
+        for (int k = 0; k < GMAX_PER; ++k) {
+            const int64_t gb = b0 + 256 * k;
+            if (gb >= c.nb_total) break;
+            const double a = c.a_b[gb];
+            if (a > 0.0) atomicMax(c.G + c.blk_inst[gb], (unsigned long long)__double_as_longlong(a));
         }
     }
+    // lanes with no block (ii == -1) or spanning ones (-2) join with value 0
     const int i0 = __shfl(ii, 0, 64);
-    if (__all(ii == i0 || ii < 0)) {
-        const double m = wave_max(v);
-        if (lane == 0 && i0 >= 0 && m > 0.0) atomicMax(c.G + i0, (unsigned long long)__double_as_longlong(m));
+    const bool uni = __all(ii == i0 || ii < 0) && i0 >= 0;
+    double m = 0.0;
+    if (uni) {
+        m = wave_max(ii >= 0 ? v : 0.0);
     } else if (ii >= 0 && v > 0.0) {
         atomicMax(c.G + ii, (unsigned long long)__double_as_longlong(v));
+    }
+    if (lane == 0) {
+        wmax[w] = m;
+        winst[w] = uni ? i0 : -1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 4; ++k) {
+            if (winst[k] < 0) continue;
+            double mm = wmax[k];
+            for (int q = k + 1; q < 4; ++q)
+                if (winst[q] == winst[k]) {
+                    mm = fmax(mm, wmax[q]);
+                    winst[q] = -1;
+                }
+            if (mm > 0.0) atomicMax(c.G + winst[k], (unsigned long long)__double_as_longlong(mm));
+        }
     }
 }
 
@@ -1545,6 +1585,230 @@ __global__ void __launch_bounds__(256) k_update_wave(Ctx c) {
     const uint32_t lo = min(total, seg * xcd), hi = min(total, seg * (xcd + 1));
     for (uint32_t e = lo + (uint32_t)local * wpg + w; e < hi; e += (uint32_t)per * wpg)
         update_block_wave<T, OP>(c, c.worklist[e], lane);
+}
+
+// -------------------------------------------------------------------------
+// active update, run walk (launch variant 4): the active blocks of one block
+// row that are x-neighbours form runs; each run is cut into aligned pieces of
+// L = 2^k blocks (L <= the plan's run_lmax) and each piece into L bands of
+// rows, one list entry per band.  A band is one block's worth of slots (the
+// list keeps one entry per active block), but its rows are L blocks wide, so
+// a wave row reads L x 64 contiguous bytes (FP32 8^3 blocks) instead of one
+// 64-byte block row.  List entry: first block of the piece (bits 0..23),
+// log2 L (bits 24..26), band (bits 27..30).  The kept measure of a block is
+// the maximum over its L bands: the compaction zeroes a_next of every active
+// block, and each band sends one atomic maximum per block (non-negative
+// doubles order as their bit patterns).
+// -------------------------------------------------------------------------
+
+constexpr uint32_t kRunId = (1u << 24) - 1;
+constexpr int RUN_GROUP = 16;  // blocks per compaction thread (aligned group)
+
+// blocks a and b (a <= b) lie in one block row of one instance
+__device__ __forceinline__ bool same_row(const Ctx &c, int64_t a, int64_t b) {
+    const int ia = c.blk_inst[a];
+    if (c.blk_inst[b] != ia) return false;
+    const InstDev &I = c.inst[ia];
+    return ((a - I.blk_off) >> I.lnbk[2]) == ((b - I.blk_off) >> I.lnbk[2]);
+}
+
+// Positions for `mine` entries per thread: exclusive prefix within the wave,
+// then across the four waves, then one atomic per workgroup.
+__device__ __forceinline__ uint32_t list_slots(const Ctx &c, uint32_t mine, uint32_t *wsum, uint32_t &base) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t incl = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t v = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += v;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        base = tot ? atomicAdd(c.count, tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t pos = base + incl - mine;
+    for (int i = 0; i < w; ++i) pos += wsum[i];
+    return pos;
+}
+
+// Threshold, mask and the band list.  Thread t owns the aligned group of
+// RUN_GROUP blocks starting at 16 t of its workgroup's range; pieces never
+// cross a group, a block row or an instance.  The last workgroup to arrive
+// hands G over (as k_compact_append).
+__global__ void __launch_bounds__(256) k_compact_runs(Ctx c) {
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t base;
+    const int64_t b0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * RUN_GROUP;
+    uint32_t bits = 0;
+    for (int k = 0; k < RUN_GROUP; ++k) {
+        const int64_t gb = b0 + k;
+        if (gb < c.nb_total) {
+            const bool on = block_active(c, gb);
+            c.mask[gb] = on ? 1 : 0;
+            if (on && c.ab_inc) c.a_next[gb] = 0.0;
+            bits |= (on ? 1u : 0u) << k;
+        }
+    }
+    uint32_t pos = list_slots(c, (uint32_t)__popc(bits), wsum, base);
+    int k = 0;
+    while (k < RUN_GROUP) {
+        if (!((bits >> k) & 1u)) {
+            ++k;
+            continue;
+        }
+        int L = c.run_lmax;
+        for (; L > 1; L >>= 1) {
+            if ((k & (L - 1)) != 0 || k + L > RUN_GROUP) continue;
+            const uint32_t m = ((1u << L) - 1u) << k;
+            if ((bits & m) == m && same_row(c, b0 + k, b0 + k + L - 1)) break;
+        }
+        const uint32_t lg = (uint32_t)__builtin_ctz((unsigned)L);
+        for (int q = 0; q < L; ++q) c.worklist[pos++] = (uint32_t)(b0 + k) | (lg << 24) | ((uint32_t)q << 27);
+        k += L;
+    }
+    // every G read of this workgroup happened before the barriers above
+    if (threadIdx.x == 0) {
+        const unsigned int done = atomicAdd(c.done, 1u);
+        if (done == gridDim.x - 1) {
+            for (int i = 0; i < c.n_inst; ++i) {
+                c.G_last[i] = c.G[i];
+                c.G[i] = 0ull;
+            }
+            *c.done = 0u;
+        }
+    }
+}
+
+// One band of a piece by one wave.  UB = slots per block / 64: every lane
+// issues UB loads of 16 bytes per array before its stores; the lanes of one
+// piece row are contiguous, so lane l sits in block j = (l mod (lpr L)) / lpr
+// for every load (lpr = lanes per block row).
+template <typename T, int OP, int UB>
+__device__ __forceinline__ void update_band(const Ctx &c, uint32_t entry, int lane) {
+    constexpr int V = CV<T>::V;
+    const int64_t gb0 = (int64_t)(entry & kRunId);
+    const int lgL = (int)((entry >> 24) & 7u);
+    const int band = (int)(entry >> 27);
+    const int ii = c.blk_inst[gb0];
+    const InstDev &I = c.inst[ii];
+    const int64_t lb0 = gb0 - I.blk_off;
+    const int bx0 = (int)(lb0 & (I.nbk[2] - 1));
+    const int64_t t = lb0 >> I.lnbk[2];
+    const int by = (int)(t & (I.nbk[1] - 1));
+    const int bz = (int)(t >> I.lnbk[1]);
+    const int llpr = I.lb[2] - (V == 2 ? 1 : 0);  // log2 lanes per block row
+    const int lrow = llpr + lgL;                  // log2 lanes per piece row (<= 6)
+    const int lstep = 6 - lrow;                   // log2 piece rows per wave load
+    const int r0 = band << (I.lb[0] + I.lb[1] - lgL);
+    const int col = lane & ((1 << lrow) - 1);
+    const int j = col >> llpr;
+    const int x0 = ((bx0 + j) << I.lb[2]) + (col & ((1 << llpr) - 1)) * V;
+    const int64_t lb = lb0 + j;
+    const Geo g = Geo::of(I, bz, by);
+    const Coef K = Coef::of(I);
+    T *q0p = reinterpret_cast<T *>(c.state) + 2 * I.off;
+    const T *r0p = reinterpret_cast<const T *>(c.rhs) + 2 * I.off;
+    T *q1p = q0p + 2 * I.N;
+    const T *r1p = r0p + 2 * I.N;
+    const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
+    const bool ab = c.ab_inc;  // wave-uniform
+    double mx2[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const double m = (double)sidx(x0 + v, g.n2);
+        mx2[v] = m * m;
+    }
+    T qr[UB][V], qi[UB][V], nr[UB][V], ni[UB][V], q2r[UB][V], q2i[UB][V], n2r[UB][V], n2i[UB][V];
+    int64_t ex[UB];
+    double myz[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+        const int r = r0 + (u << lstep) + (lane >> lrow);
+        const int z = g.z0 + (r >> g.lb1);
+        const int y = g.y0 + (r & g.b1m);
+        const int64_t e = ((((int64_t)z << g.ln1) + y) << g.ln2) + x0;
+        ex[u] = e;
+        myz[u] = sq_d(sidx(z, g.n0)) + sq_d(sidx(y, g.n1));
+        CV<T>::ld(q0p + 2 * e, qr[u], qi[u]);
+        CV<T>::ld(r0p + 2 * e, nr[u], ni[u]);
+        if (OP == OP_GS) {
+            CV<T>::ld(q1p + 2 * e, q2r[u], q2i[u]);
+            CV<T>::ld(r1p + 2 * e, n2r[u], n2i[u]);
+        }
+    }
+    // the lane holding k = 0 (block 0 of the instance, row 0, column 0)
+    const bool z_lane = lb == 0 && x0 == 0 && r0 == 0 && (lane >> lrow) == 0;
+    double amax = 0.0;
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const double m2 = myz[u] + mx2[v];
+            T cr, ci, dr = (T)0, di = (T)0;
+            if (OP == OP_CH) {
+                T sc, f;
+                ch_coef<T>(K, m2, sc, f);
+                ch_cand<T>(sc, f, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
+            } else {
+                T au, av;
+                gs_coef<T>(K, m2, au, av);
+                gs_cand<T>(dt, au, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
+                gs_cand<T>(dt, av, q2r[u][v], q2i[u][v], n2r[u][v], n2i[u][v], dr, di);
+            }
+            qr[u][v] = cr;
+            qi[u][v] = ci;
+            if (OP == OP_GS) {
+                q2r[u][v] = dr;
+                q2i[u][v] = di;
+            }
+        }
+        if (I.k0path && z_lane && u == 0) {  // the FP32 slot of k = 0 stays zero (its value lives in FP64)
+            qr[0][0] = qi[0][0] = (T)0;
+            q2r[0][0] = q2i[0][0] = (T)0;
+        }
+        if (ab) {  // the state measure of what is stored; k = 0 left out
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                double a = sq2((double)qr[u][v], (double)qi[u][v]);
+                if (OP == OP_GS) a = a + sq2((double)q2r[u][v], (double)q2i[u][v]);
+                if (z_lane && u == 0 && v == 0) a = 0.0;
+                amax = fmax(amax, a);
+            }
+        }
+        CV<T>::st(q0p + 2 * ex[u], qr[u], qi[u]);
+        if (OP == OP_GS) CV<T>::st(q1p + 2 * ex[u], q2r[u], q2i[u]);
+    }
+    if (ab) {  // maximum over the lanes of block j: sub-row lanes, then rows
+        for (int off = 1; off < (1 << llpr); off <<= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+        for (int off = 1 << lrow; off < 64; off <<= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+        if (lane < (1 << lrow) && (lane & ((1 << llpr) - 1)) == 0 && amax > 0.0)
+            atomicMax(reinterpret_cast<unsigned long long *>(c.a_next) + (I.blk_off + lb),
+                      (unsigned long long)__double_as_longlong(amax));
+    }
+    if (I.k0path && z_lane) {
+        double tmp[2];
+        k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+        c.k0[2 * ii] = tmp[0];
+        if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
+    }
+}
+
+// persistent walk of the band list, one wave per entry, one segment of the
+// list per XCD as in k_update
+template <typename T, int OP, int UB>
+__global__ void __launch_bounds__(256) k_update_run(Ctx c) {
+    const uint32_t total = *c.count;
+    const int P = gridDim.x;  // multiple of 8
+    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per = P >> 3;
+    const uint32_t wpg = blockDim.x >> 6, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const uint32_t seg = (total + 7) / 8;
+    const uint32_t lo = min(total, seg * xcd), hi = min(total, seg * (xcd + 1));
+    for (uint32_t e = lo + (uint32_t)local * wpg + w; e < hi; e += (uint32_t)per * wpg)
+        update_band<T, OP, UB>(c, c.worklist[e], lane);
 }
 
 // -------------------------------------------------------------------------
@@ -2568,8 +2832,15 @@ hipError_t launch_compact_append(const Ctx &c, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_compact_runs(const Ctx &c, hipStream_t s) {
+    const int64_t per = 256 * RUN_GROUP;
+    hipLaunchKernelGGL(k_compact_runs, dim3((unsigned)((c.nb_total + per - 1) / per)), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+
 hipError_t launch_gmax(const Ctx &c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL(k_gmax, dim3((unsigned)((c.nb_total + 255) / 256)), dim3(256), 0, s, e0, e1, 0, c);
+    hipExtLaunchKernelGGL(k_gmax, dim3((unsigned)((c.nb_total + 256 * GMAX_PER - 1) / (256 * GMAX_PER))), dim3(256), 0,
+                          s, e0, e1, 0, c);
     return hipGetLastError();
 }
 
@@ -2608,7 +2879,12 @@ static void upd_launch_op(const Ctx &c, int grid, int multi, bool tr, bool ctl, 
     if (ctl && tr)
         hipLaunchKernelGGL((k_update<T, OP, true, true>), dim3(grid), dim3(256), (size_t)c.sig_bytes, s, c);
     else if (ctl) hipLaunchKernelGGL((k_update<T, OP, false, true>), dim3(grid), dim3(256), 0, s, c);
-    else if (multi == 2) hipLaunchKernelGGL((k_update_wave<T, OP>), dim3(grid), dim3(256), 0, s, c);
+    else if (multi == 3) {  // the run walk (no NLSE: its blocks are one row wider than a wave row)
+        if constexpr (OP != OP_NLSE) {
+            if (c.run_ub == 8) hipLaunchKernelGGL((k_update_run<T, OP, 8>), dim3(grid), dim3(256), 0, s, c);
+            else hipLaunchKernelGGL((k_update_run<T, OP, 4>), dim3(grid), dim3(256), 0, s, c);
+        }
+    } else if (multi == 2) hipLaunchKernelGGL((k_update_wave<T, OP>), dim3(grid), dim3(256), 0, s, c);
     else if (multi) hipLaunchKernelGGL((k_update_multi<T, OP, 4>), dim3(grid), dim3(256), 0, s, c);
     else hipLaunchKernelGGL((k_update<T, OP, false, false>), dim3(grid), dim3(256), 0, s, c);
 }

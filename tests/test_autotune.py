@@ -39,7 +39,7 @@ class FakePlan:
             st[2] = 1.0 + self.launch.get(0, 4)
             v, g = self.launch.get(3, 1), self.launch.get(1, 4)
             st[3] = 0.1
-            st[4] = {0: 5.0, 1: 6.0, 2: 5.5, 3: 4.0}[v] + abs(g - (8 if v == 3 else 4)) * 0.1
+            st[4] = {0: 5.0, 1: 6.0, 2: 5.5, 3: 4.0, 4: 4.5}[v] + abs(g - (8 if v == 3 else 4)) * 0.1
         return {"stage_ms": st}
 
     def destroy(self):
@@ -52,7 +52,7 @@ def test_tune_keys_the_sparse_plan_and_keeps_the_fastest_variant(tmp_path):
     res, timings = A.tune(lambda dense: FakePlan([_desc()] if dense else sparse, dense), lambda p: None,
                           steps=1, path=path)
     assert res[3] == 3 and res[1] == 8 and res[0] == 1 and res[2] == 1024
-    assert "wave 1:8" in timings and "list4 1:4" in timings
+    assert "wave 1:8" in timings and "list4 1:4" in timings and "run 1:4" in timings
     cache = A.load_cache(path)
     assert list(cache) == [A.cache_key(sparse, "gfx950")]
     assert cache[A.cache_key(sparse, "gfx950")]["choice"]["3"] == 3
@@ -74,5 +74,9 @@ def test_bench_names_the_update_kernel_of_the_tuned_variant():
     assert name(cfg, d, "increment", "full", {"3": 2}) == "k_update_multi"
     assert name(cfg, d, "increment", "full", None) == "k_update_strip"
     assert name(cfg, d, "state", "half", {"3": 3}) == "k_update_h"
+    assert name(cfg, d, "state", "full", {"3": 4}) == "k_update_run"
+    assert name(cfg, d, "increment", "full", {"3": 4}) == "k_update_run"
+    assert name(cfg, d, "energy", "full", {"3": 4}) == "k_update"      # block energy: no band sums
     small = [S.Desc(op="ch", dtype="f32", ndim=2, n=16, block=4, tau=1e-2, dx=1.0, dt=0.01, params=(1.0, 1.0))]
     assert name(cfg, small, "increment", "full", {"3": 3}) == "k_update"   # 8 slots: below a wave
+    assert name(cfg, small, "increment", "full", {"3": 4}) == "k_update"   # run walk: 256 or 512 slots

@@ -90,7 +90,8 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("variant", [1, 0, 2, 3], ids=["strip_walk", "block_list", "block_list_x4", "wave_walk"])
+@pytest.mark.parametrize("variant", [1, 0, 2, 3, 4],
+                         ids=["strip_walk", "block_list", "block_list_x4", "wave_walk", "run_walk"])
 @pytest.mark.parametrize("descs,seed", CASES, ids=[f"case{c[1]}" for c in CASES])
 def test_apply_bit_exact(descs, seed, variant):
     print(f"apply parity case {seed} update variant {variant}: "
@@ -151,7 +152,7 @@ STATE_CASES = [
 ]
 
 
-@pytest.mark.parametrize("variant", [1, 0, 3], ids=["strip_walk", "block_list", "wave_walk"])
+@pytest.mark.parametrize("variant", [1, 0, 3, 4], ids=["strip_walk", "block_list", "wave_walk", "run_walk"])
 @pytest.mark.parametrize("descs,seed", STATE_CASES, ids=[f"case{c[1]}" for c in STATE_CASES])
 def test_apply_state_indicator_bit_exact(descs, seed, variant):
     print(f"state-indicator apply case {seed} variant {variant}", flush=True)

@@ -91,6 +91,14 @@ def test_state_measure_update_sequence_wave_walk(descs, seed):
     run_sequence(descs, seed, variant=3)
 
 
+@pytest.mark.parametrize("descs,seed", SEQ[:6], ids=[f"seq{c[1]}" for c in SEQ[:6]])
+def test_state_measure_update_sequence_run_walk(descs, seed):
+    # aligned runs of x-adjacent active blocks in bands of rows: the kept
+    # measure is an atomic maximum over the bands of each block
+    print(f"state-measure sequence {seed}, run walk", flush=True)
+    run_sequence(descs, seed, variant=4)
+
+
 @pytest.mark.parametrize("descs,seed", SEQ, ids=[f"seq{c[1]}" for c in SEQ])
 def test_state_measure_update_sequence_bit_exact(descs, seed):
     print(f"state-measure sequence {seed}: {[(d.op, d.dtype, d.n, d.block) for d in descs]}", flush=True)
@@ -99,7 +107,7 @@ def test_state_measure_update_sequence_bit_exact(descs, seed):
     assert any(0 < c < d.n_blocks for c, d in zip(counts, descs * len(counts)))
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
 def test_state_measure_sequence_other_variants_and_reload(variant):
     # the strip walk and the four-in-flight walk requested: the plan keeps the
     # measure through the block-list walk; the wave walk keeps it itself; a
