@@ -745,48 +745,69 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
 
 // Incremental state measure: the blocks the previous update stored (mask
 // nonzero) take the measure the update kernel wrote for them, the others keep
-// theirs; G of every instance is the maximum.  A workgroup takes 256 x
-// GMAX_PER consecutive blocks, GMAX_PER per thread at a stride of 256.  A
-// wave whose blocks lie in one instance reduces them, and the workgroup sends
-// one atomic per instance of its waves (device-scope atomics on one address
-// serialise, so one per wave would dominate the kernel); lanes whose blocks
-// span instances send their own.  Clears the append counter, as the indicator does.
+// theirs; G of every instance is the maximum.  Each thread takes GMAX_PER = 8
+// consecutive blocks and issues their loads at once (one 8-byte mask word,
+// 64 bytes of a_b and of a_next); a wave whose blocks lie in one instance
+// reduces them, and the workgroup sends one atomic per instance of its waves
+// (device-scope atomics on one address serialise, so one per wave would
+// dominate the kernel); threads whose blocks span instances send their own.
+// Clears the append counter, as the indicator does.
 constexpr int GMAX_PER = 8;
 __global__ void __launch_bounds__(256) k_gmax(Ctx c) {
     __shared__ double wmax[4];
     __shared__ int winst[4];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    // the workgroup's 256 * GMAX_PER blocks, thread t takes t, t + 256, ...
-    const int64_t b0 = (int64_t)blockIdx.x * 256 * GMAX_PER + threadIdx.x;
+    const int64_t b0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * GMAX_PER;
     if (b0 == 0) *c.count = 0u;
     double v = 0.0;
-    int ii = -1;     // instance of every block of this thread, or -2 if they differ
-    for (int k = 0; k < GMAX_PER; ++k) {
-        const int64_t gb = b0 + 256 * k;
-        if (gb >= c.nb_total) break;
-        const int ib = c.blk_inst[gb];
-        double a;
-        if (c.mask[gb]) {
-            a = c.a_next[gb];
-            c.a_b[gb] = a;
-        } else {
-            a = c.a_b[gb];
+    int ii = -1;  // instance of every block of this thread, -2 if they differ
+    if (b0 + GMAX_PER <= c.nb_total) {  // whole group: vector loads (nb_total is not always a multiple of 8)
+        const uint64_t mw = *reinterpret_cast<const uint64_t *>(c.mask + b0);
+        double a[GMAX_PER], an[GMAX_PER];
+#pragma unroll
+        for (int k = 0; k < GMAX_PER; k += 2) {
+            const double2 x = *reinterpret_cast<const double2 *>(c.a_b + b0 + k);
+            const double2 y = *reinterpret_cast<const double2 *>(c.a_next + b0 + k);
+            a[k] = x.x;
+            a[k + 1] = x.y;
+            an[k] = y.x;
+            an[k + 1] = y.y;
         }
-        if (ii == -1) ii = ib;
-        else if (ii != ib) ii = -2;
-        v = fmax(v, a);
+#pragma unroll
+        for (int k = 0; k < GMAX_PER; ++k) {
+            if ((mw >> (8 * k)) & 0xFFull) {
+                a[k] = an[k];
+                c.a_b[b0 + k] = a[k];
+            }
+            v = fmax(v, a[k]);
+        }
+        ii = c.blk_inst[b0];
+        if (c.blk_inst[b0 + GMAX_PER - 1] != ii) ii = -2;
+    } else {
+        for (int64_t gb = b0; gb < c.nb_total; ++gb) {
+            double a = c.a_b[gb];
+            if (c.mask[gb]) {
+                a = c.a_next[gb];
+                c.a_b[gb] = a;
+            }
+            const int ib = c.blk_inst[gb];
+            ii = (ii == -1 || ii == ib) ? ib : -2;
+            v = fmax(v, a);
+        }
     }
     if (ii == -2) {  // this thread's blocks span instances: one atomic per block
-        for (int k = 0; k < GMAX_PER; ++k) {
-            const int64_t gb = b0 + 256 * k;
-            if (gb >= c.nb_total) break;
+        for (int64_t gb = b0; gb < b0 + GMAX_PER && gb < c.nb_total; ++gb) {
             const double a = c.a_b[gb];
             if (a > 0.0) atomicMax(c.G + c.blk_inst[gb], (unsigned long long)__double_as_longlong(a));
         }
     }
     // lanes with no block (ii == -1) or spanning ones (-2) join with value 0
-    const int i0 = __shfl(ii, 0, 64);
-    const bool uni = __all(ii == i0 || ii < 0) && i0 >= 0;
+    int i0 = __shfl(ii, 0, 64);
+    if (i0 < 0) {  // the first lane with a single-instance group names the wave's instance
+        const uint64_t ok = __ballot(ii >= 0);
+        i0 = ok ? __shfl(ii, __builtin_ctzll(ok), 64) : -1;
+    }
+    const bool uni = i0 >= 0 && __all(ii == i0 || ii < 0);
     double m = 0.0;
     if (uni) {
         m = wave_max(ii >= 0 ? v : 0.0);
