@@ -20,7 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-OP_CH, OP_GS, OP_NLSE = 1, 2, 3
+OP_CH, OP_GS, OP_NLSE, OP_XPFC = 1, 2, 3, 4
 FLAG_DENSE, FLAG_PIN_K0 = 1, 2
 FLAG_TRANSITION, FLAG_REFRESH, FLAG_DYN_TAU = 4, 8, 16  # consistency control (S1.1, S1.3)
 FLAG_STATE = 32  # state-amplitude activity measure (main text; S4.2; S5.3)
@@ -50,6 +50,8 @@ class _Inst(ctypes.Structure):
         ("full_now", ctypes.c_int32),
         ("target_ratio", ctypes.c_double),
         ("deadband", ctypes.c_double),
+        ("hist_valid", ctypes.c_int32),
+        ("pad2", ctypes.c_int32),
     ]
 
 
@@ -77,6 +79,7 @@ class Inst:
     target_ratio: float = 0.0
     deadband: float = 0.0
     full_now: int = 0  # apply(): this update activates every block
+    hist_valid: int = 0  # XPFC step(): the state carries the three older nonlinear transforms
 
     @property
     def half(self) -> bool:
@@ -117,6 +120,7 @@ class Inst:
         s.refresh_period, s.full_steps = int(self.refresh_period), int(self.full_steps)
         s.interval, s.full_now = int(self.interval), int(self.full_now)
         s.target_ratio, s.deadband = float(self.target_ratio), float(self.deadband)
+        s.hist_valid = int(self.hist_valid)
         return s
 
 
@@ -141,6 +145,11 @@ def _load():
         lib.or_taper.argtypes = [ctypes.c_int64, P]
         lib.or_ch_energy.argtypes = [P, P, P, P]
         lib.or_r2c.argtypes = [ctypes.POINTER(ctypes.c_int64), P, P]
+        lib.or_etd4_phi.argtypes = [ctypes.c_double, P]
+        lib.or_etd4_coef.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
+        lib.or_xpfc_linear.argtypes = [P, ctypes.c_double]
+        lib.or_xpfc_linear.restype = ctypes.c_double
+        lib.or_xpfc_energy.argtypes = [P, P, P, P]
         lib.or_c2r.argtypes = [ctypes.POINTER(ctypes.c_int64), P, P]
         _lib = lib
     return _lib
@@ -265,4 +274,36 @@ def ch_energy(inst: Inst, chat):
     ch = np.ascontiguousarray(chat, dtype=np.complex128).reshape(-1)
     e, m = ctypes.c_double(), ctypes.c_double()
     _check(lib.or_ch_energy(ctypes.byref(c), _ptr(ch), ctypes.byref(e), ctypes.byref(m)))
+    return e.value, m.value
+
+
+# ---------------------------------------------------------------------------
+# XPFC (Supplementary S3.1-S3.2): ETD4 coefficients, linear operator, energy
+# ---------------------------------------------------------------------------
+
+def etd4_phi(z: float) -> np.ndarray:
+    """(e^z, phi_1, phi_2, phi_3, phi_4) at z."""
+    out = np.zeros(5, np.float64)
+    _load().or_etd4_phi(float(z), _ptr(out))
+    return out
+
+
+def etd4_coef(z: float, dt: float, mk2: float) -> np.ndarray:
+    """(e^z, B_1, .., B_4), B_l = mk2 Phi_l."""
+    out = np.zeros(5, np.float64)
+    _load().or_etd4_coef(float(z), float(dt), float(mk2), _ptr(out))
+    return out
+
+
+def xpfc_linear(inst: Inst, k2: float) -> float:
+    c = inst._c()
+    return float(_load().or_xpfc_linear(ctypes.byref(c), float(k2)))
+
+
+def xpfc_energy(inst: Inst, psihat):
+    """(free energy, mean density) of a spectrum."""
+    c = inst._c()
+    ph = np.ascontiguousarray(psihat, dtype=np.complex128).reshape(-1)
+    e, m = ctypes.c_double(), ctypes.c_double()
+    _check(_load().or_xpfc_energy(ctypes.byref(c), _ptr(ph), ctypes.byref(e), ctypes.byref(m)))
     return e.value, m.value

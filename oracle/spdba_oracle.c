@@ -71,7 +71,7 @@ typedef struct {
 
 static int make_geom(const or_inst *d, geom_t *g) {
     int64_t ext = 0;
-    if (d->op != OR_OP_CH && d->op != OR_OP_GS && d->op != OR_OP_NLSE) return OR_EINVAL;
+    if (d->op != OR_OP_CH && d->op != OR_OP_GS && d->op != OR_OP_NLSE && d->op != OR_OP_XPFC) return OR_EINVAL;
     g->N = 1;
     g->nb = 1;
     for (int a = 0; a < 3; ++a) {
@@ -100,7 +100,7 @@ static int make_geom(const or_inst *d, geom_t *g) {
     g->nbm = g->nb;
     if (g->half) {
         /* real fields only; the transition states are not defined on this layout here */
-        if (d->op == OR_OP_NLSE || (d->flags & OR_FLAG_TRANSITION)) return OR_EINVAL;
+        if (d->op == OR_OP_NLSE || d->op == OR_OP_XPFC || (d->flags & OR_FLAG_TRANSITION)) return OR_EINVAL;
         if (g->n[2] < 2 || (g->n[2] / 2) % g->b[2] != 0) return OR_EINVAL;
         g->xs = g->n[2] / 2 + 1;
         g->nbxm = g->n[2] / (2 * g->b[2]);
@@ -327,6 +327,112 @@ static inline void nlse_coef(const consts_t *c, int64_t m2, double *hr, double *
     *hi = c->A * sn;
 }
 
+
+/* ------------------------------------------------------------------------ */
+/* XPFC: linear operator and ETD4 coefficients (Supplementary S3.1-S3.2)   */
+/* ------------------------------------------------------------------------ */
+
+/* 1/n! rounded once (n! is exact in double for n <= 18) */
+static double inv_fact(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= (double)i;
+    return 1.0 / f;
+}
+
+/* phi_4(w) by its series to the term w^14/18!, then phi_3, phi_2, phi_1 and
+ * e^w by phi_l = 1/l! + w phi_{l+1}, e^w = 1 + w phi_1 (|w| <= 1) */
+static void phi_series(double w, double out[5]) {
+    double p4 = inv_fact(18);
+    for (int j = 13; j >= 0; --j) p4 = fma(p4, w, inv_fact(4 + j));
+    const double p3 = fma(w, p4, inv_fact(3));
+    const double p2 = fma(w, p3, inv_fact(2));
+    const double p1 = fma(w, p2, 1.0);
+    out[0] = fma(w, p1, 1.0);
+    out[1] = p1;
+    out[2] = p2;
+    out[3] = p3;
+    out[4] = p4;
+}
+
+void or_etd4_phi(double z, double out[5]) {
+    if (fabs(z) <= 1.0) {
+        phi_series(z, out);
+        return;
+    }
+    int s = 0;
+    double w = z;
+    while (fabs(w) > 1.0) {
+        w *= 0.5;
+        ++s;
+    }
+    double t[5];
+    phi_series(w, t);
+    double e = t[0];
+    for (int i = 0; i < s; ++i) e = e * e;
+    out[0] = e;
+    out[1] = (e - 1.0) / z;
+    out[2] = (out[1] - 1.0) / z;
+    out[3] = (out[2] - inv_fact(2)) / z;
+    out[4] = (out[3] - inv_fact(3)) / z;
+}
+
+void or_etd4_coef(double z, double dt, double mk2, double out[5]) {
+    double ph[5];
+    or_etd4_phi(z, ph);
+    const double P1 = dt * ph[1];
+    const double P2 = dt * ph[2];
+    const double P3 = dt * (0.5 * ph[2] + ph[3]);
+    const double P4 = dt * ((ph[2] / 3.0 + ph[3]) + ph[4]);
+    out[0] = ph[0];
+    out[1] = mk2 * P1;
+    out[2] = mk2 * P2;
+    out[3] = mk2 * P3;
+    out[4] = mk2 * P4;
+}
+
+double or_xpfc_linear(const or_inst *d, double k2) {
+    const double q0 = d->p[0], sg = d->p[1], al = d->p[2], rho = d->p[5], be = d->p[6];
+    const double k = sqrt(k2);
+    const double dk = k - q0;
+    const double peak = exp(-(dk * dk) / (2.0 * (al * al)));
+    const double dw = exp(-((sg * sg) * (q0 * q0)) / (2.0 * (rho * be)));
+    const double c2 = peak * dw;
+    return -k2 * (1.0 - c2);
+}
+
+/* XPFC candidate of one mode in FP64: psi' from psi and the four transforms
+ * h[0..3] (newest first), in the order of the ETD4 formula */
+static inline void xpfc_cand64(const double co[5], double q, const double h[4], double *out) {
+    const double d1 = h[0] - h[1];
+    const double d2 = fma(-2.0, h[1], h[0]) + h[2];
+    const double d3 = fma(3.0, h[2], fma(-3.0, h[1], h[0])) - h[3];
+    double acc = co[0] * q;
+    acc = fma(co[1], h[0], acc);
+    acc = fma(co[2], d1, acc);
+    acc = fma(co[3], d2, acc);
+    acc = fma(co[4], d3, acc);
+    *out = acc;
+}
+
+static inline void xpfc_cand32(const float co[5], float q, const float h[4], float *out) {
+    const float d1 = h[0] - h[1];
+    const float d2 = fmaf(-2.0f, h[1], h[0]) + h[2];
+    const float d3 = fmaf(3.0f, h[2], fmaf(-3.0f, h[1], h[0])) - h[3];
+    float acc = co[0] * q;
+    acc = fmaf(co[1], h[0], acc);
+    acc = fmaf(co[2], d1, acc);
+    acc = fmaf(co[3], d2, acc);
+    acc = fmaf(co[4], d3, acc);
+    *out = acc;
+}
+
+/* coefficients {e^z, B1..B4} of the mode with integer |m|^2 */
+static inline void xpfc_coef(const or_inst *d, const consts_t *c, int64_t m2, double co[5]) {
+    const double k2 = c->K2 * (double)m2;
+    const double z = or_xpfc_linear(d, k2) * d->dt;
+    or_etd4_coef(z, d->dt, -k2, co);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Kernel-level apply: candidate for all modes, indicator, mask, update     */
 /* ------------------------------------------------------------------------ */
@@ -475,6 +581,18 @@ int or_apply_f64(const or_inst *d, double *q, const double *rhs, const uint8_t *
             cand[2 * N + 2 * i] = vr;
             cand[2 * N + 2 * i + 1] = vi;
             a = sq2(ur - u[2 * i], ui - u[2 * i + 1]) + sq2(vr - v[2 * i], vi - v[2 * i + 1]);
+        } else if (d->op == OR_OP_XPFC) {
+            double co[5];
+            xpfc_coef(d, &c, m2, co);
+            const double hr[4] = {rhs[2 * i], rhs[2 * (N + i)], rhs[2 * (2 * N + i)], rhs[2 * (3 * N + i)]};
+            const double hi[4] = {rhs[2 * i + 1], rhs[2 * (N + i) + 1], rhs[2 * (2 * N + i) + 1],
+                                  rhs[2 * (3 * N + i) + 1]};
+            double cr, ci;
+            xpfc_cand64(co, q[2 * i], hr, &cr);
+            xpfc_cand64(co, q[2 * i + 1], hi, &ci);
+            cand[2 * i] = cr;
+            cand[2 * i + 1] = ci;
+            a = sq2(cr - q[2 * i], ci - q[2 * i + 1]);
         } else {
             double hr, hi;
             nlse_coef(&c, m2, &hr, &hi);
@@ -576,6 +694,11 @@ int or_apply_f32(const or_inst *d, float *q, const float *rhs, double *k0,
                 k0c[0] = fma(-s, rhs_k0[0], k0[0]) * f;
                 double dr = k0c[0] - k0[0];
                 a = sq2(dr, 0.0);
+            } else if (d->op == OR_OP_XPFC) {
+                /* L(0) = 0 and the factor -k^2 of the nonlinear terms is 0:
+                 * the mean density is kept */
+                k0c[0] = k0[0];
+                a = 0.0;
             } else {
                 double au, av;
                 gs_coef(&c, 0, &au, &av);
@@ -612,6 +735,19 @@ int or_apply_f32(const or_inst *d, float *q, const float *rhs, double *k0,
             cand[2 * N + 2 * i + 1] = vi;
             a = sq2((double)ur - (double)u[2 * i], (double)ui - (double)u[2 * i + 1]) +
                 sq2((double)vr - (double)v[2 * i], (double)vi - (double)v[2 * i + 1]);
+        } else if (d->op == OR_OP_XPFC) {
+            double co[5];
+            xpfc_coef(d, &c, m2, co);
+            const float cf[5] = {(float)co[0], (float)co[1], (float)co[2], (float)co[3], (float)co[4]};
+            const float hr[4] = {rhs[2 * i], rhs[2 * (N + i)], rhs[2 * (2 * N + i)], rhs[2 * (3 * N + i)]};
+            const float hi[4] = {rhs[2 * i + 1], rhs[2 * (N + i) + 1], rhs[2 * (2 * N + i) + 1],
+                                 rhs[2 * (3 * N + i) + 1]};
+            float cr, ci;
+            xpfc_cand32(cf, q[2 * i], hr, &cr);
+            xpfc_cand32(cf, q[2 * i + 1], hi, &ci);
+            cand[2 * i] = cr;
+            cand[2 * i + 1] = ci;
+            a = sq2((double)cr - (double)q[2 * i], (double)ci - (double)q[2 * i + 1]);
         } else {
             double hr, hi;
             nlse_coef(&c, m2, &hr, &hi);
@@ -817,6 +953,8 @@ int or_step_ctl_f64(const or_inst *d0, int64_t nsteps, double *state, uint8_t *m
     double *a_b = (double *)malloc(sizeof(double) * (size_t)nb);
     uint8_t *mk = (uint8_t *)malloc((size_t)nb);
     uint32_t *wl = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)nb);
+    /* XPFC: the four nonlinear transforms of a step, newest first */
+    double *h4 = d->op == OR_OP_XPFC ? (double *)malloc(sizeof(double) * 8 * (size_t)N) : NULL;
     if (active_steps)
         for (int64_t b = 0; b < nb; ++b) active_steps[b] = 0;
     rc = OR_OK;
@@ -902,6 +1040,35 @@ int or_step_ctl_f64(const or_inst *d0, int64_t nsteps, double *state, uint8_t *m
                 or_fft(w + 2 * N, g.n, -1);
             }
             rc = or_apply_f64(d, state, w, NULL, a_b, &G, mk, wl, &cnt);
+        } else if (d->op == OR_OP_XPFC) {
+            if (diag) {
+                double F, m;
+                or_xpfc_energy(d, state, &F, &m);
+                diag[4 * st] = m;
+                diag[4 * st + 1] = F;
+                diag[4 * st + 2] = 0.0;
+                diag[4 * st + 3] = 0.0;
+            }
+            /* psi = Re F^-1[psi-hat]; H_n = F[-(omega/2) psi^2 + (u/3) psi^3] */
+            const double om = d->p[3], uu = d->p[4];
+            memcpy(h4, state, sizeof(double) * 2 * (size_t)N);
+            or_fft(h4, g.n, +1);
+            for (int64_t i = 0; i < N; ++i) {
+                const double ps = h4[2 * i];
+                const double t = ps * ps;
+                h4[2 * i] = -(om / 2.0) * t + (uu / 3.0) * (t * ps);
+                h4[2 * i + 1] = 0.0;
+            }
+            or_fft(h4, g.n, -1);
+            /* the older transforms: carried by the state, or (first step of an
+             * unset history) the initial nonlinear term itself */
+            for (int k = 1; k < 4; ++k) {
+                const double *src = (st == 0 && !d0->hist_valid) ? h4 : state + 2 * (size_t)k * N;
+                memcpy(h4 + 2 * (size_t)k * N, src, sizeof(double) * 2 * (size_t)N);
+            }
+            rc = or_apply_f64(d, state, h4, NULL, a_b, &G, mk, wl, &cnt);
+            /* shift: the state keeps H_n, H_{n-1}, H_{n-2} */
+            memcpy(state + 2 * (size_t)N, h4, sizeof(double) * 6 * (size_t)N);
         } else {
             /* symmetric split step: linear half, Kerr rotation, linear half */
             if (diag) {
@@ -958,5 +1125,45 @@ int or_step_ctl_f64(const or_inst *d0, int64_t nsteps, double *state, uint8_t *m
     free(a_b);
     free(mk);
     free(wl);
+    free(h4);
     return rc;
+}
+
+int or_xpfc_energy(const or_inst *d, const double *psihat, double *energy, double *mean) {
+    geom_t g;
+    int rc = make_geom(d, &g);
+    if (rc) return rc;
+    if (d->op != OR_OP_XPFC) return OR_EINVAL;
+    const int64_t N = g.N;
+    int ndim = (g.n[0] > 1) + (g.n[1] > 1) + (g.n[2] > 1);
+    if (ndim == 0) ndim = 1;
+    double dvol = 1.0;
+    for (int k = 0; k < ndim; ++k) dvol *= d->dx;
+    const double om = d->p[3], uu = d->p[4];
+    double *w = (double *)malloc(sizeof(double) * 2 * (size_t)N);
+    memcpy(w, psihat, sizeof(double) * 2 * (size_t)N);
+    or_fft(w, g.n, +1);
+    double bulk = 0.0, sum = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        const double ps = w[2 * i];
+        const double p2 = ps * ps;
+        bulk += 0.5 * p2 - (om / 6.0) * (p2 * ps) + (uu / 12.0) * (p2 * p2);
+        sum += ps;
+    }
+    free(w);
+    const double K2 = kk_base(&g, d->dx);
+    const double q0 = d->p[0], sg = d->p[1], al = d->p[2], rho = d->p[5], be = d->p[6];
+    const double dw = exp(-((sg * sg) * (q0 * q0)) / (2.0 * (rho * be)));
+    double corr = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t iz, iy, ix;
+        mode_idx(&g, i, &iz, &iy, &ix);
+        const double k = sqrt(K2 * (double)m2_of(&g, iz, iy, ix));
+        const double dk = k - q0;
+        const double c2 = exp(-(dk * dk) / (2.0 * (al * al))) * dw;
+        corr += c2 * sq2(psihat[2 * i], psihat[2 * i + 1]);
+    }
+    *energy = dvol * (bulk - corr / (2.0 * (double)N));
+    *mean = sum / (double)N;
+    return OR_OK;
 }

@@ -21,6 +21,7 @@
 #define OR_OP_CH 1   /* conserved (Cahn-Hilliard form) semi-implicit update    */
 #define OR_OP_GS 2   /* two-species semi-implicit reaction-diffusion update     */
 #define OR_OP_NLSE 3 /* split-step linear half-step (dispersion, attenuation)  */
+#define OR_OP_XPFC 4 /* conserved XPFC density, ETD4 multistep update (S3.1-S3.2) */
 
 #define OR_FLAG_DENSE 1u  /* Regular mode: every block updated, no indicator */
 #define OR_FLAG_PIN_K0 2u /* the block holding k = 0 is always active        */
@@ -71,7 +72,49 @@ typedef struct {
     int32_t full_now;       /* apply only: 1 = this update activates every block              */
     double target_ratio;    /* DYN_TAU: target mean ratio of non-frozen blocks, (0, 1]        */
     double deadband;        /* DYN_TAU: relative deadband eta, [0, 1)                          */
+    int32_t hist_valid;     /* XPFC steps: 1 = the state carries the three older nonlinear
+                               transforms; 0 = they are set to the first step's own      */
+    int32_t pad2;
 } or_inst;
+
+/* XPFC (Supplementary S3.1-S3.2).  p = {q0, sigma, alpha, omega, u, rho, beta}.
+ * Dynamics d psi/dt = lap[psi - C2 * psi - (omega/2) psi^2 + (u/3) psi^3] on a
+ * periodic grid; in Fourier space d psi/dt = L psi + (-k^2) H with
+ *   L(k)  = -k^2 (1 - C2(k)),
+ *   C2(k) = exp(-(k - q0)^2 / (2 alpha^2)) exp(-sigma^2 q0^2 / (2 rho beta)),
+ *   H     = F[-(omega/2) psi^2 + (u/3) psi^3].
+ * ETD4 (Cox-Matthews multistep, backward differences of H):
+ *   psi' = e^z psi + B1 H_n + B2 (H_n - H_{n-1}) + B3 (H_n - 2 H_{n-1} + H_{n-2})
+ *          + B4 (H_n - 3 H_{n-1} + 3 H_{n-2} - H_{n-3}),
+ *   z = L dt,  B_l = -k^2 Phi_l,  Phi_1 = dt phi_1, Phi_2 = dt phi_2,
+ *   Phi_3 = dt (phi_2 / 2 + phi_3),  Phi_4 = dt (phi_2 / 3 + phi_3 + phi_4),
+ *   phi_l(z) = sum_{j >= 0} z^j / (l + j)!.
+ * Apply: rhs holds the four transforms H_n, H_{n-1}, H_{n-2}, H_{n-3} (4 N
+ * complex, newest first).  Steps: the state holds psi-hat followed by the
+ * three older transforms H_{n-1}, H_{n-2}, H_{n-3} (4 N complex); with
+ * hist_valid = 0 the first step fills them with its own H_0. */
+
+/* e^z and phi_1 .. phi_4 at z (FP64): out = {e^z, phi_1, phi_2, phi_3, phi_4}.
+ * |z| <= 1: phi_4 from its series to the term z^14 / 18! (Horner, explicit
+ * fma), then phi_l = 1/l! + z phi_{l+1} for l = 3, 2, 1 and e^z = 1 + z phi_1;
+ * |z| > 1: e^z from e^w, w = z / 2^s (|w| <= 1, the same series), squared s
+ * times, then phi_1 = (e^z - 1)/z, phi_{l+1} = (phi_l - 1/l!)/z. */
+void or_etd4_phi(double z, double out[5]);
+
+/* ETD4 coefficients of one mode: out = {e^z, B1, B2, B3, B4} with
+ * B_l = mk2 Phi_l (mk2 = -k^2 for XPFC; 1 for a plain ODE dy/dt = L y + N). */
+void or_etd4_coef(double z, double dt, double mk2, double out[5]);
+
+/* L(k) of the XPFC operator at k^2 (FP64; the order of operations of the
+ * definition above: k = sqrt(k^2), d = k - q0, peak = exp(-(d d) / (2 (alpha
+ * alpha))), dw = exp(-((sigma sigma) (q0 q0)) / (2 (rho beta))), C2 = peak dw,
+ * L = -k^2 (1 - C2)). */
+double or_xpfc_linear(const or_inst *d, double k2);
+
+/* XPFC free energy and mean density of a spectrum psi-hat (FP64):
+ * F = dx^d [sum_x (psi^2/2 - omega psi^3/6 + u psi^4/12)
+ *           - (1/(2N)) sum_k C2(k) |psi-hat_k|^2]. */
+int or_xpfc_energy(const or_inst *d, const double *psihat, double *energy, double *mean);
 
 /* n-D complex FFT in place. sign = -1 forward (unnormalised), +1 inverse (1/N). */
 int or_fft(double *a, const int64_t dims[3], int sign);

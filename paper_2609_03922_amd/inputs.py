@@ -148,3 +148,37 @@ def hermitian_coupling(seed: int, M: int) -> np.ndarray:
             K[i, j] = r.standard_normal() + 1j * r.standard_normal()
             K[j, i] = np.conj(K[i, j])
     return K / np.sqrt(np.mean(np.abs(K) ** 2))
+
+
+def xpfc_seed_field(seed: int, inst: int, n: int, dx: float, q0: float = 1.0, mean: float = 0.12,
+                    amp: float = 0.25, seeds: int = 12, radius_frac: float = 0.12, width: float = 2.0,
+                    noise: float = 0.01, dtype=np.float64) -> np.ndarray:
+    """Two-dimensional polycrystalline start of the density: a uniform mean
+    with small noise, and `seeds` crystalline seeds of random centre and
+    orientation, each a triangular (hexagonal-density) wave of three plane
+    waves of wavenumber q0 at 120 degrees, `amp` each, faded out over
+    `width` grid spacings at its radius (radius_frac of the domain edge).
+    Where seeds overlap the nearest centre wins."""
+    r = rng_for(seed, inst, 17)
+    L = n * dx
+    x = (np.arange(n) * dx)[None, :]
+    y = (np.arange(n) * dx)[:, None]
+    cen = r.uniform(0.0, L, size=(seeds, 2))
+    ang = r.uniform(0.0, np.pi / 3.0, size=seeds)
+    rad = radius_frac * L
+    f = mean + noise * r.uniform(-1.0, 1.0, size=(n, n))
+    best = np.full((n, n), np.inf)
+    for s in range(seeds):
+        # periodic distance to the centre
+        dxs = (x - cen[s, 0] + 0.5 * L) % L - 0.5 * L
+        dys = (y - cen[s, 1] + 0.5 * L) % L - 0.5 * L
+        d = np.sqrt(dxs * dxs + dys * dys)
+        wave = np.zeros((n, n))
+        for j in range(3):
+            a = ang[s] + 2.0 * np.pi * j / 3.0
+            wave = wave + np.cos(q0 * (np.cos(a) * dxs + np.sin(a) * dys))
+        w = 0.5 * (1.0 - np.tanh((d - rad) / (width * dx)))
+        take = d < best
+        best = np.where(take, d, best)
+        f = np.where(take & (w > 1e-3), mean + amp * w * wave + (1.0 - w) * (f - mean), f)
+    return f.astype(dtype)
