@@ -76,8 +76,28 @@ enum {
  *   NLSE {beta2, gamma, alpha}: symmetric split step (S5.2); each linear half
  *       step E' = exp[(-alpha/2 + i beta2 w^2/2) h/2] E is one sp-DBA update,
  *       the Kerr step E <- E exp(i gamma |E|^2 h) runs in the time domain.
- *       dx is the sample spacing, dt the step h; w = 2 pi m / (n dx).       */
-enum { SPDBA_OP_CAHN_HILLIARD = 1, SPDBA_OP_GRAY_SCOTT = 2, SPDBA_OP_NLSE = 3 };
+ *       dx is the sample spacing, dt the step h; w = 2 pi m / (n dx).
+ *   XPFC {q0, sigma, alpha, omega, u, rho, beta} (alpha > 0, rho beta > 0):
+ *       conserved phase-field-crystal density of Supplementary S3.1,
+ *       d psi/dt = lap[psi - C2 * psi - (omega/2) psi^2 + (u/3) psi^3], with
+ *       C2(k) = exp(-(k - q0)^2/(2 alpha^2)) exp(-sigma^2 q0^2/(2 rho beta)),
+ *       advanced by the ETD4 multistep update of S3.2 in backward differences
+ *       of the nonlinear transforms H_n .. H_{n-3}, H = F[-(omega/2) psi^2 +
+ *       (u/3) psi^3]: psi' = e^z psi + B1 H_n + B2 dH + B3 d2H + B4 d3H, z = L dt,
+ *       L = -k^2 (1 - C2), B_l = -k^2 Phi_l (Phi_1 = dt phi_1, Phi_2 = dt phi_2,
+ *       Phi_3 = dt (phi_2/2 + phi_3), Phi_4 = dt (phi_2/3 + phi_3 + phi_4)).
+ *       The coefficients are formed per mode in FP64 from L (a per-instance
+ *       table by integer |m|^2, filled on the host) -- phi_4 by its series for
+ *       |z| <= 1 and phi_l = 1/l! + z phi_{l+1}, else e^z by scaling and
+ *       squaring and the closed forms -- and rounded once.  The four
+ *       transforms rotate through slots of the state buffer; the first step
+ *       after a field load sets the three older ones to its own.  Requires
+ *       SPDBA_FLAG_STATE_INDICATOR (the paper's block energy with
+ *       SPDBA_FLAG_BLOCK_ENERGY, or its maximum form) or SPDBA_FLAG_DENSE
+ *       (else EUNSUPPORTED); not with SPDBA_FLAG_HALF_SPECTRUM; spdba_apply
+ *       takes H_n as its right-hand side and keeps the older ones itself;
+ *       spdba_stats reports no energy (NaN).                                 */
+enum { SPDBA_OP_CAHN_HILLIARD = 1, SPDBA_OP_GRAY_SCOTT = 2, SPDBA_OP_NLSE = 3, SPDBA_OP_XPFC = 4 };
 enum { SPDBA_F32 = 0, SPDBA_F64 = 1 };
 
 enum {

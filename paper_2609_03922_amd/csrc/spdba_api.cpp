@@ -96,8 +96,15 @@ struct spdba_plan_s {
     int min_slots = 0;     // smallest block in 16-byte lane slots
     bool list_stale = false;  // the ordered active list lags the mask
     // graph of one step
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph[4] = {};  // one captured step; XPFC: one per history phase
     bool graph_failed = false;
+    // XPFC: the four nonlinear transforms rotate through slots of the state
+    // buffer; the slot of the coming step's transform is xphase
+    int xphase = 0;
+    bool hist_valid = false;  // the three older slots hold the previous steps' transforms
+    size_t st_hist = 0;       // first history slot in the state buffer
+    size_t w_ltab = 0;        // L(|m|^2) tables in the work buffer
+    std::vector<double> ltab; // host copy of the tables
     // stage events: a ring of per-step sets, read only after the stream drained
     static constexpr int kRing = 64;
     hipEvent_t ev[kRing][12] = {};
@@ -160,7 +167,19 @@ spdba_status validate(const spdba_instance_desc *d, int32_t n, void *) {
             return SPDBA_EINVAL;
         if (x.op == SPDBA_OP_GRAY_SCOTT && !(x.op_params[0] >= 0.0 && x.op_params[1] >= 0.0))
             return SPDBA_EINVAL;
-        if (x.op < SPDBA_OP_CAHN_HILLIARD || x.op > SPDBA_OP_NLSE) return SPDBA_EUNSUPPORTED;
+        if (x.op < SPDBA_OP_CAHN_HILLIARD || x.op > SPDBA_OP_XPFC) return SPDBA_EUNSUPPORTED;
+        if (x.op == SPDBA_OP_XPFC) {
+            // peak width alpha > 0 and rho beta > 0 (the Gaussian and the
+            // Debye-Waller factor); the state-amplitude measure (the paper's
+            // block energy or its maximum form) or Regular mode; full layout
+            if (!(x.op_params[2] > 0.0) || !(x.op_params[5] * x.op_params[6] > 0.0)) return SPDBA_EINVAL;
+            if (!(x.flags & (SPDBA_FLAG_STATE_INDICATOR | SPDBA_FLAG_DENSE))) return SPDBA_EUNSUPPORTED;
+            if (x.flags & SPDBA_FLAG_HALF_SPECTRUM) return SPDBA_EUNSUPPORTED;
+            // the L table holds one entry per integer |m|^2 <= ndim (n/2)^2
+            int64_t m2max = 0;
+            for (int a = 0; a < 3; ++a) m2max += (x.dims[a] / 2) * (x.dims[a] / 2);
+            if (m2max > (int64_t(1) << 28)) return SPDBA_EUNSUPPORTED;
+        }
         if (x.dtype != SPDBA_F32 && x.dtype != SPDBA_F64) return SPDBA_EUNSUPPORTED;
         if (x.flags & ~uint32_t(SPDBA_FLAG_DENSE | SPDBA_FLAG_PIN_K0 | SPDBA_FLAG_GRAPH |
                                 SPDBA_FLAG_TIMING | SPDBA_FLAG_TRANSITION | SPDBA_FLAG_REFRESH |
@@ -275,6 +294,42 @@ spdba_status exec_fft(spdba_plan p, const Fft &f, void *in, void *out) {
 char *state_ptr(spdba_plan p, int64_t elem_off) { return p->d_state + p->st_spec + elem_off * p->esize; }
 char *work_ptr(spdba_plan p, int64_t elem_off) { return p->d_work + p->w_W + elem_off * p->esize; }
 char *rhs_ptr(spdba_plan p, int64_t elem_off) { return p->d_work + p->w_R + elem_off * p->esize; }
+// XPFC: history slot `slot` (0..3) of the nonlinear transforms
+char *hist_ptr(spdba_plan p, int slot, int64_t elem_off) {
+    return p->d_state + p->st_hist + ((size_t)slot * (size_t)p->total_elems + (size_t)elem_off) * p->esize;
+}
+// XPFC: the coming step's transform goes to slot xphase, the three previous
+// steps' are in the slots behind it
+void set_phase(spdba_plan p) {
+    if (p->op != OP_XPFC) return;
+    Ctx &c = p->ctx;
+    c.rhs = hist_ptr(p, p->xphase, 0);
+    c.hist1 = hist_ptr(p, (p->xphase + 3) & 3, 0);
+    c.hist2 = hist_ptr(p, (p->xphase + 2) & 3, 0);
+    c.hist3 = hist_ptr(p, (p->xphase + 1) & 3, 0);
+}
+// XPFC: a step is done: its transform becomes the previous one
+void advance_phase(spdba_plan p) {
+    if (p->op != OP_XPFC) return;
+    p->xphase = (p->xphase + 1) & 3;
+    p->hist_valid = true;
+}
+// XPFC, first step of a new field: the older slots take this step's transform
+spdba_status fill_history(spdba_plan p) {
+    if (p->op != OP_XPFC || p->hist_valid) return SPDBA_OK;
+    const size_t bytes = (size_t)p->total_elems * p->esize;
+    for (int k = 1; k < 4; ++k)
+        TRY_HIP(hipMemcpyAsync(hist_ptr(p, (p->xphase + k) & 3, 0), hist_ptr(p, p->xphase, 0), bytes,
+                               hipMemcpyDeviceToDevice, p->stream));
+    return SPDBA_OK;
+}
+void drop_graphs(spdba_plan p) {
+    for (auto &g : p->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
 // half layout: a real field in W (offset in real values)
 char *wreal_ptr(spdba_plan p, int64_t real_off) { return p->d_work + p->w_W + real_off * (p->esize / 2); }
 
@@ -411,7 +466,10 @@ spdba_status enqueue_step(spdba_plan p) {
         record(p, 1);
         TRY_HIP(launch_nonlinear(p->ctx, d, p->nl_waves, p->stream));
         record(p, 2);
-        for (auto &g : p->groups) TRY(exec_fft(p, g.fwd_oop, work_ptr(p, g.off), rhs_ptr(p, g.off)));
+        for (auto &g : p->groups)
+            TRY(exec_fft(p, g.fwd_oop, work_ptr(p, g.off),
+                         p->op == OP_XPFC ? hist_ptr(p, p->xphase, g.off) : rhs_ptr(p, g.off)));
+        TRY(fill_history(p));  // XPFC, first step of a new field (eager)
         if (p->op == OP_GS && !d) TRY_HIP(launch_k0_rhs(p->ctx, p->stream));
         record(p, 3);
         TRY(update_stage(p, 4, early));
@@ -615,10 +673,33 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
             I.c2 = x.dt * x.op_params[1];
             I.q0 = x.op_params[2];
             I.q1 = x.op_params[3];
+        } else if (p->op == OP_XPFC) {
+            I.c0 = x.dt;
+            I.q0 = x.op_params[3];  // omega
+            I.q1 = x.op_params[4];  // u
         } else {
             I.c0 = ((x.op_params[0] * x.dt) * 0.25) * I.K2;
             I.c1 = std::exp(-(x.op_params[2] * x.dt) * 0.25);
             I.q0 = x.op_params[1] * x.dt;
+        }
+        I.ltab_off = 0;
+        if (p->op == OP_XPFC) {
+            // L(k) = -k^2 (1 - C2(k)) at every integer |m|^2 of the grid, in
+            // FP64, by the steps of the definition (Supplementary S3.1)
+            int64_t m2max = 0;
+            for (int a = 0; a < 3; ++a) m2max += (x.dims[a] / 2) * (x.dims[a] / 2);
+            I.ltab_off = (int64_t)p->ltab.size();
+            const double q0 = x.op_params[0], sg = x.op_params[1], al = x.op_params[2];
+            const double rho = x.op_params[5], be = x.op_params[6];
+            const double dw = std::exp(-((sg * sg) * (q0 * q0)) / (2.0 * (rho * be)));
+            for (int64_t m2 = 0; m2 <= m2max; ++m2) {
+                const double k2 = I.K2 * (double)m2;
+                const double k = std::sqrt(k2);
+                const double dk = k - q0;
+                const double peak = std::exp(-(dk * dk) / (2.0 * (al * al)));
+                const double c2 = peak * dw;
+                p->ltab.push_back(-k2 * (1.0 - c2));
+            }
         }
         for (int a = 0; a < 3; ++a) taper = std::max<int64_t>(taper, 2 * (int64_t)I.b[a]);
         I.full_steps = x.full_steps;
@@ -639,7 +720,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     // the run walk: full layout, CH / GS without transition blocks or the
     // block-energy sum (its bands give partial sums), equal blocks of 256 or
     // 512 slots whose rows are at most one wave row, list entries of 24 bits
-    if (!p->half && p->op != OP_NLSE && !p->trans && !(inst[0].flags & SPDBA_FLAG_BLOCK_ENERGY) &&
+    if (!p->half && p->op != OP_NLSE && p->op != OP_XPFC && !p->trans && !(inst[0].flags & SPDBA_FLAG_BLOCK_ENERGY) &&
         p->min_slots == p->max_slots && (p->max_slots == 256 || p->max_slots == 512) && blk <= (int64_t)1 << 24) {
         int lmax = 16;
         for (int i = 0; i < n_inst; ++i) {
@@ -707,6 +788,8 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     size_t o = 0;
     p->st_spec = o;
     o = align256(o + (size_t)p->total_elems * p->esize);
+    p->st_hist = o;
+    if (p->op == OP_XPFC) o = align256(o + 4 * (size_t)p->total_elems * p->esize);
     p->st_k0 = o;
     o = align256(o + (size_t)n_inst * 2 * sizeof(double));
     p->st_ctl = o;
@@ -738,6 +821,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     p->w_taper = take((size_t)p->n_taper * sizeof(double));
     p->w_htab = take((size_t)p->n_htab * p->esize);
     p->w_anext = take((size_t)blk * sizeof(double));
+    p->w_ltab = take(std::max<size_t>(p->ltab.size() * sizeof(double), 8));
     p->w_probe = take(8);
     p->work_bytes = o;
     *out = p;
@@ -791,6 +875,8 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     c.ctl = reinterpret_cast<CtlDev *>(p->d_state + p->st_ctl);
     c.taper = reinterpret_cast<const double *>(p->d_work + p->w_taper);
     c.htab = p->d_work + p->w_htab;
+    c.ltab = reinterpret_cast<const double *>(p->d_work + p->w_ltab);
+    c.hist1 = c.hist2 = c.hist3 = c.rhs;  // XPFC: set per step (set_phase)
     c.trans = p->trans ? 1 : 0;
     c.state_ind = (p->desc[0].flags & SPDBA_FLAG_STATE_INDICATOR) ? 1 : 0;
     // the state entering a CH or GS update is the state the last one stored:
@@ -827,6 +913,10 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
                            hipMemcpyHostToDevice, p->stream));
     TRY_HIP(hipMemcpyAsync(p->d_work + p->w_binst, p->blk_inst.data(),
                            p->blk_inst.size() * sizeof(uint16_t), hipMemcpyHostToDevice, p->stream));
+    if (!p->ltab.empty())
+        TRY_HIP(hipMemcpyAsync(p->d_work + p->w_ltab, p->ltab.data(), p->ltab.size() * sizeof(double),
+                               hipMemcpyHostToDevice, p->stream));
+    p->hist_valid = false;
     TRY_HIP(hipMemsetAsync(p->d_state + p->st_k0, 0, (size_t)p->n_inst * 2 * sizeof(double), p->stream));
     TRY_HIP(hipMemsetAsync(c.rhs_k0, 0, (size_t)p->n_inst * 2 * sizeof(double), p->stream));
     TRY_HIP(hipMemsetAsync(c.count, 0, 16, p->stream));
@@ -875,6 +965,7 @@ spdba_status spdba_set_field(spdba_plan p, int32_t inst, const void *d_real) {
     const int64_t n = I.N * p->nspec;
     TRY_HIP(launch_ctl_reset(p->ctx, inst, p->stream));
     p->ab_valid = false;
+    p->hist_valid = false;
     if (p->op == OP_NLSE) {
         TRY_HIP(launch_scale_copy(p->dbl, d_real, state_ptr(p, I.off), n, (double)I.N, p->stream));
         return SPDBA_OK;
@@ -924,6 +1015,7 @@ spdba_status spdba_set_spectrum(spdba_plan p, int32_t inst, const void *d_hat, c
     double *k0 = p->ctx.k0 + 2 * inst;
     TRY_HIP(launch_ctl_reset(p->ctx, inst, p->stream));
     p->ab_valid = false;
+    p->hist_valid = false;
     if (p->half)  // compact rows of nx/2 + 1 into the pitched rows
         TRY_HIP(launch_copy_half(p->ctx, p->dbl, inst, d_hat, state_ptr(p, I.off), true, I.k0path,
                                  (I.k0path && !h_k0) ? k0 : nullptr, p->stream));
@@ -962,36 +1054,47 @@ spdba_status spdba_step(spdba_plan p, int32_t n_steps) {
     if (!p || n_steps < 0) return SPDBA_EINVAL;
     if (!p->bound) return SPDBA_ESTATE;
     if (n_steps == 0) return SPDBA_OK;
-    // a graph holds the kept-measure update stage: after a field load the
-    // measure is first evaluated in full by one eager step
-    if (p->use_graph && p->ab_inc && !p->ab_valid) {
+    // a graph holds the kept-measure update stage and (XPFC) a filled
+    // history: after a field load the measure is first evaluated in full,
+    // and the history filled, by one eager step
+    while (n_steps > 0 && p->use_graph && ((p->ab_inc && !p->ab_valid) || (p->op == OP_XPFC && !p->hist_valid))) {
+        set_phase(p);
         TRY(enqueue_step(p));
+        advance_phase(p);
         p->steps++;
-        if (--n_steps == 0) return SPDBA_OK;
+        --n_steps;
     }
+    if (n_steps == 0) return SPDBA_OK;
     if (p->use_graph && !p->graph_failed) {
-        if (!p->graph) {
-            hipGraph_t gr = nullptr;
-            hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeRelaxed);
-            spdba_status st = SPDBA_OK;
-            if (e == hipSuccess) st = enqueue_step(p);
-            hipError_t e2 = hipStreamEndCapture(p->stream, &gr);
-            if (e != hipSuccess || st != SPDBA_OK || e2 != hipSuccess || !gr ||
-                hipGraphInstantiate(&p->graph, gr, nullptr, nullptr, 0) != hipSuccess) {
-                p->graph = nullptr;
-                p->graph_failed = true;
-                (void)hipGetLastError();
+        while (n_steps > 0) {
+            const int gi = p->op == OP_XPFC ? p->xphase : 0;
+            if (!p->graph[gi]) {
+                set_phase(p);
+                hipGraph_t gr = nullptr;
+                hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeRelaxed);
+                spdba_status st = SPDBA_OK;
+                if (e == hipSuccess) st = enqueue_step(p);
+                hipError_t e2 = hipStreamEndCapture(p->stream, &gr);
+                if (e != hipSuccess || st != SPDBA_OK || e2 != hipSuccess || !gr ||
+                    hipGraphInstantiate(&p->graph[gi], gr, nullptr, nullptr, 0) != hipSuccess) {
+                    p->graph[gi] = nullptr;
+                    p->graph_failed = true;
+                    (void)hipGetLastError();
+                }
+                if (gr) (void)hipGraphDestroy(gr);
+                if (!p->graph[gi]) break;  // eager from here on
             }
-            if (gr) (void)hipGraphDestroy(gr);
+            TRY_HIP(hipGraphLaunch(p->graph[gi], p->stream));
+            advance_phase(p);
+            p->steps++;
+            --n_steps;
         }
-        if (p->graph) {
-            for (int i = 0; i < n_steps; ++i) TRY_HIP(hipGraphLaunch(p->graph, p->stream));
-            p->steps += n_steps;
-            return SPDBA_OK;
-        }
+        if (n_steps == 0) return SPDBA_OK;
     }
     for (int i = 0; i < n_steps; ++i) {
+        set_phase(p);
         TRY(enqueue_step(p));
+        advance_phase(p);
         ring_advance(p);
         p->steps++;
     }
@@ -1013,7 +1116,8 @@ spdba_status spdba_apply(spdba_plan p, const void *d_rhs_hat, const double *h_rh
                 src += (int64_t)I.n[0] * I.n[1] * (I.n[2] / 2 + 1) * p->nspec;
             } else {
                 const int64_t n = I.N * p->nspec;
-                TRY_HIP(launch_copy_spectrum(p->ctx, p->dbl, i, sp, rhs_ptr(p, I.off), n, 0, rk0, p->stream));
+                char *dst = p->op == OP_XPFC ? hist_ptr(p, p->xphase, I.off) : rhs_ptr(p, I.off);
+                TRY_HIP(launch_copy_spectrum(p->ctx, p->dbl, i, sp, dst, n, 0, rk0, p->stream));
                 src += n;
             }
         }
@@ -1027,8 +1131,11 @@ spdba_status spdba_apply(spdba_plan p, const void *d_rhs_hat, const double *h_rh
         }
     }
     // the update stage alone: events 3..6 of a CH/GS step
+    TRY(fill_history(p));  // XPFC: a new field's history starts from this transform
+    set_phase(p);
     record(p, 3);
     TRY(update_stage(p, p->op == OP_NLSE ? 2 : 4));
+    advance_phase(p);
     return SPDBA_OK;
 }
 
@@ -1037,10 +1144,7 @@ spdba_status spdba_set_skip(spdba_plan p, const uint8_t *d_skip) {
     p->d_skip = d_skip;
     p->ctx.skip = d_skip;
     p->ab_valid = false;
-    if (p->graph) {  // the captured graph holds the old pointer
-        (void)hipGraphExecDestroy(p->graph);
-        p->graph = nullptr;
-    }
+    drop_graphs(p);  // a captured graph holds the old pointers
     return SPDBA_OK;
 }
 
@@ -1049,10 +1153,7 @@ spdba_status spdba_set_block_energy(spdba_plan p, double *d_eb) {
     if (p->half && d_eb) return SPDBA_EUNSUPPORTED;
     p->d_eb = d_eb;
     p->ctx.e_b = d_eb;
-    if (p->graph) {
-        (void)hipGraphExecDestroy(p->graph);
-        p->graph = nullptr;
-    }
+    drop_graphs(p);  // a captured graph holds the old pointers
     return SPDBA_OK;
 }
 
@@ -1173,7 +1274,7 @@ spdba_status spdba_stats(spdba_plan p, int32_t inst, spdba_stats_t *out) {
     for (int s = 0; s < p->nspec; ++s)
         out->mean[s] = p->op == OP_NLSE ? 0.0 : (I.k0path ? k0[s] : slot0[s][0]) * I.invN;
     out->energy = NAN;
-    if (!nlp.empty()) {
+    if (!nlp.empty() && p->op == OP_CH) {
         double bulk = 0.0, grad = 0.0;
         for (int64_t t = 0; t < I.ntiles; ++t) bulk += nlp[2 * t];
         for (double v : egp) grad += v;
@@ -1230,7 +1331,7 @@ spdba_status spdba_stats(spdba_plan p, int32_t inst, spdba_stats_t *out) {
         (void)hipGetLastError();
     }
     out->input_preserving_fft = p->inv_preserving ? 1 : 0;
-    out->graph_replay = p->graph != nullptr ? 1 : 0;
+    out->graph_replay = (p->graph[0] || p->graph[1] || p->graph[2] || p->graph[3]) ? 1 : 0;
     return check_nonfinite(p);
 }
 
@@ -1246,16 +1347,13 @@ spdba_status spdba_set_launch(spdba_plan p, int32_t kernel, int32_t value) {
         default: return SPDBA_EINVAL;
     }
     p->ring_filled = 0;  // timings of the previous geometry are stale
-    if (p->graph) {
-        (void)hipGraphExecDestroy(p->graph);
-        p->graph = nullptr;
-    }
+    drop_graphs(p);  // a captured graph holds the old pointers
     return SPDBA_OK;
 }
 
 spdba_status spdba_destroy(spdba_plan p) {
     if (!p) return SPDBA_OK;
-    if (p->graph) (void)hipGraphExecDestroy(p->graph);
+    drop_graphs(p);
     for (auto &g : p->groups) {
         destroy_fft(g.inv_oop);
         destroy_fft(g.fwd_ip);

@@ -9,7 +9,7 @@ struct spdba_plan_s;
 
 namespace spdba {
 
-enum Op : int { OP_CH = 1, OP_GS = 2, OP_NLSE = 3 };
+enum Op : int { OP_CH = 1, OP_GS = 2, OP_NLSE = 3, OP_XPFC = 4 };
 
 // Per-instance constants, uploaded once at bind.  Offsets are in complex
 // elements (state and transform buffers share one layout) or block / strip /
@@ -49,6 +49,7 @@ struct InstDev {
     double tau0;        // threshold after a reset
     double target, deadband;
     int64_t ht_off;     // NLSE in one dimension: first entry of the H(|m|) table (complex); else -1
+    int64_t ltab_off;   // XPFC: first entry of the L(|m|^2) table (FP64, one per integer |m|^2)
     // half-spectrum layout (real fields): rows of xs = nx/2 + 1 stored columns;
     // the blocks of the columns below nx/2 first (nbm of them, nbxm along x),
     // then one block per (z, y) block row for the column nx/2
@@ -112,6 +113,8 @@ struct Ctx {
     double *e_b;               // [nb_total] per-block energies or nullptr
     CtlDev *ctl;               // [n_inst] control state
     const void *htab;          // NLSE H(|m|) tables (complex, working precision)
+    const double *ltab;        // XPFC L(|m|^2) tables (FP64)
+    const void *hist1, *hist2, *hist3;  // XPFC: transforms of the three previous steps (rhs: this step's)
     const double *taper;       // roll-off tables: edge B at [B, 2B)
     uint32_t taper_bs;         // bit k: block edge 2^k in use
     int32_t wave_ind;          // every block row spans several wave rows: one wave per strip

@@ -208,6 +208,10 @@ __device__ __forceinline__ double nlse_cand(T hr, T hi, T er, T ei, T &cr, T &ci
 // FP64 k = 0 candidate of the real-field operators (coefficients at k = 0).
 __device__ __forceinline__ double k0_cand(const InstDev &I, int op, const double *k0,
                                           const double *rk0, double *out) {
+    if (op == OP_XPFC) {  // L(0) = 0 and the nonlinear terms carry -k^2 = 0: the mean is kept
+        out[0] = k0[0];
+        return 0.0;
+    }
     if (op == OP_CH) {
         const double s = I.c0 * 0.0;
         const double a = 1.0 / (1.0 + I.c1 * (0.0 * 0.0));
@@ -219,6 +223,107 @@ __device__ __forceinline__ double k0_cand(const InstDev &I, int op, const double
     out[0] = __builtin_fma(I.c0, rk0[0], k0[0]) * au;
     out[1] = __builtin_fma(I.c0, rk0[1], k0[1]) * av;
     return sq2(out[0] - k0[0], 0.0) + sq2(out[1] - k0[1], 0.0);
+}
+
+// -------------------------------------------------------------------------
+// XPFC update core (Supplementary S3.2): the ETD4 multistep update in
+// backward differences of the nonlinear transforms H_n .. H_{n-3},
+//   psi' = e^z psi + B1 H_n + B2 dH + B3 d2H + B4 d3H,  B_l = -k^2 Phi_l,
+// z = L dt with L(k) = -k^2 (1 - C2(k)) read from a per-instance FP64 table
+// by integer |m|^2 (filled on the host at plan creation).  The coefficients
+// are formed in FP64 -- phi_4 from its series for |z| <= 1 and the
+// recurrence phi_l = 1/l! + z phi_{l+1} (e^z = 1 + z phi_1), else e^z by
+// scaling and squaring and phi_1 .. phi_4 in closed form -- and rounded
+// once to the working precision; every operation explicit (fma where
+// fused), so any implementation of the same steps gives the same bits.
+// -------------------------------------------------------------------------
+
+struct InvFact {
+    double v[19];
+};
+// 1/n!, n = 0 .. 18, each rounded once (n! is exact in double up to 18!)
+constexpr InvFact make_inv_fact() {
+    InvFact t{};
+    double f = 1.0;
+    for (int n = 0; n < 19; ++n) {
+        if (n >= 2) f *= (double)n;
+        t.v[n] = 1.0 / f;
+    }
+    return t;
+}
+
+__device__ __forceinline__ void phi_series(double w, double (&o)[5]) {
+    constexpr InvFact F = make_inv_fact();
+    double p4 = F.v[18];
+#pragma unroll
+    for (int j = 13; j >= 0; --j) p4 = __builtin_fma(p4, w, F.v[4 + j]);
+    const double p3 = __builtin_fma(w, p4, F.v[3]);
+    const double p2 = __builtin_fma(w, p3, F.v[2]);
+    const double p1 = __builtin_fma(w, p2, 1.0);
+    o[0] = __builtin_fma(w, p1, 1.0);
+    o[1] = p1;
+    o[2] = p2;
+    o[3] = p3;
+    o[4] = p4;
+}
+
+// {e^z, phi_1 .. phi_4}
+__device__ __forceinline__ void etd4_phi(double z, double (&o)[5]) {
+    if (__builtin_fabs(z) <= 1.0) {
+        phi_series(z, o);
+        return;
+    }
+    constexpr InvFact F = make_inv_fact();
+    int s = 0;
+    double w = z;
+    while (__builtin_fabs(w) > 1.0) {
+        w *= 0.5;
+        ++s;
+    }
+    double t[5];
+    phi_series(w, t);
+    double e = t[0];
+    for (int i = 0; i < s; ++i) e = e * e;
+    o[0] = e;
+    o[1] = (e - 1.0) / z;
+    o[2] = (o[1] - 1.0) / z;
+    o[3] = (o[2] - F.v[2]) / z;
+    o[4] = (o[3] - F.v[3]) / z;
+}
+
+// {e^z, B1 .. B4} of the mode with integer |m|^2 (dt = K.c0)
+template <typename T>
+__device__ __forceinline__ void xpfc_coef(const Coef &K, const double *ltab, double m2, T (&co)[5]) {
+    const double k2 = K.K2 * m2;
+    const double dt = K.c0;
+    const double z = ltab[(int64_t)m2] * dt;
+    double ph[5];
+    etd4_phi(z, ph);
+    const double P1 = dt * ph[1];
+    const double P2 = dt * ph[2];
+    const double P3 = dt * (0.5 * ph[2] + ph[3]);
+    const double P4 = dt * ((ph[2] / 3.0 + ph[3]) + ph[4]);
+    const double mk2 = -k2;
+    co[0] = (T)ph[0];
+    co[1] = (T)(mk2 * P1);
+    co[2] = (T)(mk2 * P2);
+    co[3] = (T)(mk2 * P3);
+    co[4] = (T)(mk2 * P4);
+}
+
+// one real component: psi' from psi and H_n .. H_{n-3}, terms in the order of
+// the update formula
+template <typename T>
+__device__ __forceinline__ T xpfc_cand1(const T (&co)[5], T q, T h0, T h1, T h2, T h3) {
+    const T d1 = h0 - h1;
+    const T d2 = fmat((T)-2, h1, h0) + h2;
+    const T d3 = fmat((T)3, h2, fmat((T)-3, h1, h0)) - h3;
+    T acc = co[0] * q;
+    acc = fmat(co[1], h0, acc);
+    acc = fmat(co[2], d1, acc);
+    acc = fmat(co[3], d2, acc);
+    acc = fmat(co[4], d3, acc);
+    return acc;
 }
 
 // -------------------------------------------------------------------------
@@ -373,6 +478,45 @@ __global__ void __launch_bounds__(1024) k_nonlinear(Ctx c) {
                 }
                 CV<T>::st(bu + 2 * e, ur, ui);
                 CV<T>::st(bv + 2 * e, vr, vi);
+            }
+        }
+    } else if (OP == OP_XPFC) {
+        // H = F[-(omega/2) psi^2 + (u/3) psi^3] (Supplementary S3.1); q0 = omega, q1 = u
+        const T invN = (T)I.invN;
+        if (I.k0path) {
+            // W holds N (psi - psibar); expanded about the FP64 mean, the
+            // term is d (a1 + d (a2 + d a3)) plus a constant that only
+            // reaches k = 0, where the update's nonlinear coefficients are 0
+            const double pb = c.k0[2 * ii] * I.invN;
+            const T a1 = (T)(I.q1 * (pb * pb) - I.q0 * pb), a2 = (T)(I.q1 * pb - 0.5 * I.q0), a3 = (T)(I.q1 / 3.0);
+            for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
+                const int64_t e = t0 + j;
+                if (e >= I.N) break;
+                T re[V], im[V];
+                CV<T>::ld(base + 2 * e, re, im);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const T d = re[v] * invN;
+                    re[v] = d * fmat(d, fmat(d, a3, a2), a1);
+                    im[v] = (T)0;
+                }
+                CV<T>::st(base + 2 * e, re, im);
+            }
+        } else {
+            const T hw = (T)(-(I.q0 / 2.0)), u3 = (T)(I.q1 / 3.0);
+            for (int j = threadIdx.x * V; j < TE; j += blockDim.x * V) {
+                const int64_t e = t0 + j;
+                if (e >= I.N) break;
+                T re[V], im[V];
+                CV<T>::ld(base + 2 * e, re, im);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const T ps = re[v] * invN;
+                    const T t = ps * ps;
+                    re[v] = hw * t + u3 * (t * ps);
+                    im[v] = (T)0;
+                }
+                CV<T>::st(base + 2 * e, re, im);
             }
         }
     } else {
@@ -1240,6 +1384,10 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
     const T *r1p = r0p + 2 * I.N;
     const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
     const T *htab = (OP == OP_NLSE && I.ht_off >= 0) ? reinterpret_cast<const T *>(c.htab) + 2 * I.ht_off : nullptr;
+    const T *h1p = reinterpret_cast<const T *>(c.hist1) + 2 * I.off;  // XPFC history
+    const T *h2p = reinterpret_cast<const T *>(c.hist2) + 2 * I.off;
+    const T *h3p = reinterpret_cast<const T *>(c.hist3) + 2 * I.off;
+    const double *ltab = c.ltab + I.ltab_off;
     const bool trn = TR && (entry >> 31);  // workgroup-uniform
     const uint32_t faces = (entry >> 25) & 63u;
     const int b0 = I.b[0], b1 = I.b[1], b2 = I.b[2];
@@ -1254,12 +1402,18 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
         const int64_t e = ((((int64_t)z << g.ln1) + y) << g.ln2) + x0;
         const double myz = sq_d(sidx(z, g.n0)) + sq_d(sidx(y, g.n1));
         T qr[V], qi[V], nr[V], ni[V], q2r[V], q2i[V], n2r[V], n2i[V];
+        T h1r[V], h1i[V], h2r[V], h2i[V], h3r[V], h3i[V];
         CV<T>::ld(q0p + 2 * e, qr, qi);
         if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr, ni);
         else if (htab) nlse_tab_ld<T>(htab, x0, g.n2, nr, ni);
         if (OP == OP_GS) {
             CV<T>::ld(q1p + 2 * e, q2r, q2i);
             CV<T>::ld(r1p + 2 * e, n2r, n2i);
+        }
+        if (OP == OP_XPFC) {
+            CV<T>::ld(h1p + 2 * e, h1r, h1i);
+            CV<T>::ld(h2p + 2 * e, h2r, h2i);
+            CV<T>::ld(h3p + 2 * e, h3r, h3i);
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -1275,6 +1429,11 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
                 gs_coef<T>(K, m2, au, av);
                 gs_cand<T>(dt, au, qr[v], qi[v], nr[v], ni[v], cr, ci);
                 gs_cand<T>(dt, av, q2r[v], q2i[v], n2r[v], n2i[v], dr, di);
+            } else if (OP == OP_XPFC) {
+                T co[5];
+                xpfc_coef<T>(K, ltab, m2, co);
+                cr = xpfc_cand1<T>(co, qr[v], nr[v], h1r[v], h2r[v], h3r[v]);
+                ci = xpfc_cand1<T>(co, qi[v], ni[v], h1i[v], h2i[v], h3i[v]);
             } else {
                 T hr = nr[v], hi = ni[v];
                 if (!htab) nlse_coef<T>(K, m2, hr, hi);
@@ -1504,11 +1663,16 @@ __device__ __forceinline__ void update_block_wave(const Ctx &c, uint32_t gb, int
     const T *r1p = r0p + 2 * I.N;
     const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
     const T *htab = (OP == OP_NLSE && I.ht_off >= 0) ? reinterpret_cast<const T *>(c.htab) + 2 * I.ht_off : nullptr;
+    const T *h1p = reinterpret_cast<const T *>(c.hist1) + 2 * I.off;  // XPFC history
+    const T *h2p = reinterpret_cast<const T *>(c.hist2) + 2 * I.off;
+    const T *h3p = reinterpret_cast<const T *>(c.hist3) + 2 * I.off;
+    const double *ltab = c.ltab + I.ltab_off;
     const bool ab = OP != OP_NLSE && c.ab_inc;  // wave-uniform
     const bool esum = c.ab_sum;                  // block energy: the sum, else the maximum
     double amax = 0.0;
     for (int s0 = 0; s0 < slots; s0 += 64 * UB) {
         T qr[UB][V], qi[UB][V], nr[UB][V], ni[UB][V], q2r[UB][V], q2i[UB][V], n2r[UB][V], n2i[UB][V];
+        T h1r[UB][V], h1i[UB][V], h2r[UB][V], h2i[UB][V], h3r[UB][V], h3i[UB][V];
         int64_t ex[UB];
         int x0s[UB];
         double myz[UB];
@@ -1532,6 +1696,11 @@ __device__ __forceinline__ void update_block_wave(const Ctx &c, uint32_t gb, int
                 CV<T>::ld(q1p + 2 * e, q2r[u], q2i[u]);
                 CV<T>::ld(r1p + 2 * e, n2r[u], n2i[u]);
             }
+            if (OP == OP_XPFC) {
+                CV<T>::ld(h1p + 2 * e, h1r[u], h1i[u]);
+                CV<T>::ld(h2p + 2 * e, h2r[u], h2i[u]);
+                CV<T>::ld(h3p + 2 * e, h3r[u], h3i[u]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
@@ -1550,6 +1719,11 @@ __device__ __forceinline__ void update_block_wave(const Ctx &c, uint32_t gb, int
                     gs_coef<T>(K, m2, au, av);
                     gs_cand<T>(dt, au, qr[u][v], qi[u][v], nr[u][v], ni[u][v], cr, ci);
                     gs_cand<T>(dt, av, q2r[u][v], q2i[u][v], n2r[u][v], n2i[u][v], dr, di);
+                } else if (OP == OP_XPFC) {
+                    T co[5];
+                    xpfc_coef<T>(K, ltab, m2, co);
+                    cr = xpfc_cand1<T>(co, qr[u][v], nr[u][v], h1r[u][v], h2r[u][v], h3r[u][v]);
+                    ci = xpfc_cand1<T>(co, qi[u][v], ni[u][v], h1i[u][v], h2i[u][v], h3i[u][v]);
                 } else {
                     T hr = nr[u][v], hi = ni[u][v];
                     if (!htab) nlse_coef<T>(K, m2, hr, hi);
@@ -2022,6 +2196,10 @@ __global__ void __launch_bounds__(1024) k_dense(Ctx c) {
     const T *r1p = r0p + 2 * N;
     const T dt = (OP == OP_GS) ? (T)K.c0 : (T)0;
     const T *htab = (OP == OP_NLSE && I.ht_off >= 0) ? reinterpret_cast<const T *>(c.htab) + 2 * I.ht_off : nullptr;
+    const T *h1p = reinterpret_cast<const T *>(c.hist1) + 2 * I.off;  // XPFC history
+    const T *h2p = reinterpret_cast<const T *>(c.hist2) + 2 * I.off;
+    const T *h3p = reinterpret_cast<const T *>(c.hist3) + 2 * I.off;
+    const double *ltab = c.ltab + I.ltab_off;
     double acc[1] = {0.0};
     const int jstep = blockDim.x * V;
     for (int j = threadIdx.x * V; j < TE; j += jstep) {
@@ -2033,12 +2211,18 @@ __global__ void __launch_bounds__(1024) k_dense(Ctx c) {
         const int z = (int)(zy >> ln1);
         const double myz = sq_d(sidx(z, n0)) + sq_d(sidx(y, n1));
         T qr[V], qi[V], nr[V], ni[V], q2r[V], q2i[V], n2r[V], n2i[V];
+        T h1r[V], h1i[V], h2r[V], h2i[V], h3r[V], h3i[V];
         CV<T>::ld(q0p + 2 * e, qr, qi);
         if (OP != OP_NLSE) CV<T>::ld(r0p + 2 * e, nr, ni);
         else if (htab) nlse_tab_ld<T>(htab, x0, n2, nr, ni);
         if (OP == OP_GS) {
             CV<T>::ld(q1p + 2 * e, q2r, q2i);
             CV<T>::ld(r1p + 2 * e, n2r, n2i);
+        }
+        if (OP == OP_XPFC) {
+            CV<T>::ld(h1p + 2 * e, h1r, h1i);
+            CV<T>::ld(h2p + 2 * e, h2r, h2i);
+            CV<T>::ld(h3p + 2 * e, h3r, h3i);
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -2058,6 +2242,11 @@ __global__ void __launch_bounds__(1024) k_dense(Ctx c) {
                 gs_cand<T>(dt, av, q2r[v], q2i[v], n2r[v], n2i[v], dr, di);
                 q2r[v] = dr;
                 q2i[v] = di;
+            } else if (OP == OP_XPFC) {
+                T co[5];
+                xpfc_coef<T>(K, ltab, m2, co);
+                cr = xpfc_cand1<T>(co, qr[v], nr[v], h1r[v], h2r[v], h3r[v]);
+                ci = xpfc_cand1<T>(co, qi[v], ni[v], h1i[v], h2i[v], h3i[v]);
             } else {
                 T hr = nr[v], hi = ni[v];
                 if (!htab) nlse_coef<T>(K, m2, hr, hi);
@@ -2788,6 +2977,7 @@ static hipError_t nl_launch(const Ctx &c, int waves, hipStream_t s) {
     }
     if (c.op == OP_CH) hipLaunchKernelGGL((k_nonlinear<T, OP_CH>), grid, block, 0, s, c);
     else if (c.op == OP_GS) hipLaunchKernelGGL((k_nonlinear<T, OP_GS>), grid, block, 0, s, c);
+    else if (c.op == OP_XPFC) hipLaunchKernelGGL((k_nonlinear<T, OP_XPFC>), grid, block, 0, s, c);
     else hipLaunchKernelGGL((k_nonlinear<T, OP_NLSE>), grid, block, 0, s, c);
     return hipGetLastError();
 }
@@ -2841,7 +3031,10 @@ static hipError_t ind_launch(const Ctx &c, int waves, hipStream_t s, hipEvent_t 
     }
     if (c.op == OP_CH) ind_launch_op<T, OP_CH>(c, waves, s, e0, e1);
     else if (c.op == OP_GS) ind_launch_op<T, OP_GS>(c, waves, s, e0, e1);
-    else ind_launch_op<T, OP_NLSE>(c, waves, s, e0, e1);
+    else if (c.op == OP_XPFC) {  // the state-amplitude measures only
+        if (c.e_b) ind_launch_v<T, OP_XPFC, true, true>(c, waves, s, e0, e1);
+        else ind_launch_v<T, OP_XPFC, false, true>(c, waves, s, e0, e1);
+    } else ind_launch_op<T, OP_NLSE>(c, waves, s, e0, e1);
     return hipGetLastError();
 }
 hipError_t launch_indicator(const Ctx &c, bool dbl, int waves, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
@@ -2900,13 +3093,15 @@ static void upd_launch_op(const Ctx &c, int grid, int multi, bool tr, bool ctl, 
     if (ctl && tr)
         hipLaunchKernelGGL((k_update<T, OP, true, true>), dim3(grid), dim3(256), (size_t)c.sig_bytes, s, c);
     else if (ctl) hipLaunchKernelGGL((k_update<T, OP, false, true>), dim3(grid), dim3(256), 0, s, c);
-    else if (multi == 3) {  // the run walk (no NLSE: its blocks are one row wider than a wave row)
-        if constexpr (OP != OP_NLSE) {
+    else if (multi == 3) {  // the run walk: CH and GS
+        if constexpr (OP == OP_CH || OP == OP_GS) {
             if (c.run_ub == 8) hipLaunchKernelGGL((k_update_run<T, OP, 8>), dim3(grid), dim3(256), 0, s, c);
             else hipLaunchKernelGGL((k_update_run<T, OP, 4>), dim3(grid), dim3(256), 0, s, c);
         }
     } else if (multi == 2) hipLaunchKernelGGL((k_update_wave<T, OP>), dim3(grid), dim3(256), 0, s, c);
-    else if (multi) hipLaunchKernelGGL((k_update_multi<T, OP, 4>), dim3(grid), dim3(256), 0, s, c);
+    else if (multi && OP != OP_XPFC) {  // four entries in flight: not with a kept measure, so never XPFC
+        if constexpr (OP != OP_XPFC) hipLaunchKernelGGL((k_update_multi<T, OP, 4>), dim3(grid), dim3(256), 0, s, c);
+    }
     else hipLaunchKernelGGL((k_update<T, OP, false, false>), dim3(grid), dim3(256), 0, s, c);
 }
 template <typename T>
@@ -2918,6 +3113,7 @@ static hipError_t upd_launch(const Ctx &c, int grid, int multi, bool tr, bool ct
     }
     if (c.op == OP_CH) upd_launch_op<T, OP_CH>(c, grid, multi, tr, ctl, s);
     else if (c.op == OP_GS) upd_launch_op<T, OP_GS>(c, grid, multi, tr, ctl, s);
+    else if (c.op == OP_XPFC) upd_launch_op<T, OP_XPFC>(c, grid, multi == 1 ? 0 : multi, tr, ctl, s);
     else upd_launch_op<T, OP_NLSE>(c, grid, multi, tr, ctl, s);
     return hipGetLastError();
 }
@@ -2930,6 +3126,7 @@ static hipError_t upd_strip_launch(const Ctx &c, int waves, int grid, hipStream_
     dim3 g((unsigned)grid), block(64 * waves);
     if (c.op == OP_CH) hipLaunchKernelGGL((k_update_strip<T, OP_CH>), g, block, 0, s, c);
     else if (c.op == OP_GS) hipLaunchKernelGGL((k_update_strip<T, OP_GS>), g, block, 0, s, c);
+    else if (c.op == OP_XPFC) return hipErrorInvalidValue;  // the strip walk is the increment measure's
     else hipLaunchKernelGGL((k_update_strip<T, OP_NLSE>), g, block, 0, s, c);
     return hipGetLastError();
 }
@@ -2947,6 +3144,7 @@ static hipError_t dense_launch(const Ctx &c, int threads, hipStream_t s) {
     }
     if (c.op == OP_CH) hipLaunchKernelGGL((k_dense<T, OP_CH>), grid, block, 0, s, c);
     else if (c.op == OP_GS) hipLaunchKernelGGL((k_dense<T, OP_GS>), grid, block, 0, s, c);
+    else if (c.op == OP_XPFC) hipLaunchKernelGGL((k_dense<T, OP_XPFC>), grid, block, 0, s, c);
     else hipLaunchKernelGGL((k_dense<T, OP_NLSE>), grid, block, 0, s, c);
     return hipGetLastError();
 }

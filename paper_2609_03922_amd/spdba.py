@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libspdba.so")
 
 SPDBA_OK, SPDBA_EINVAL, SPDBA_EUNSUPPORTED, SPDBA_ESTATE = 0, 1, 2, 3
 SPDBA_EDEVICE, SPDBA_EFFT, SPDBA_ENONFINITE = 4, 5, 6
-SPDBA_OP_CAHN_HILLIARD, SPDBA_OP_GRAY_SCOTT, SPDBA_OP_NLSE = 1, 2, 3
+SPDBA_OP_CAHN_HILLIARD, SPDBA_OP_GRAY_SCOTT, SPDBA_OP_NLSE, SPDBA_OP_XPFC = 1, 2, 3, 4
 SPDBA_F32, SPDBA_F64 = 0, 1
 SPDBA_FLAG_DENSE, SPDBA_FLAG_PIN_K0, SPDBA_FLAG_GRAPH, SPDBA_FLAG_TIMING = 1, 2, 4, 8
 SPDBA_FLAG_TRANSITION, SPDBA_FLAG_REFRESH, SPDBA_FLAG_DYN_THRESHOLD = 16, 32, 64
@@ -27,7 +27,7 @@ SPDBA_FLAG_STATE_INDICATOR = 128
 SPDBA_FLAG_HALF_SPECTRUM = 256
 SPDBA_FLAG_BLOCK_ENERGY = 512
 
-OPS = {"ch": SPDBA_OP_CAHN_HILLIARD, "gs": SPDBA_OP_GRAY_SCOTT, "nlse": SPDBA_OP_NLSE}
+OPS = {"ch": SPDBA_OP_CAHN_HILLIARD, "gs": SPDBA_OP_GRAY_SCOTT, "nlse": SPDBA_OP_NLSE, "xpfc": SPDBA_OP_XPFC}
 DTYPES = {"f32": SPDBA_F32, "f64": SPDBA_F64}
 
 # every entry point the header declares

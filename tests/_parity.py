@@ -8,7 +8,7 @@ import oracle as O
 from paper_2609_03922_amd import inputs
 from paper_2609_03922_amd import spdba as S
 
-OPMAP = {"ch": O.OP_CH, "gs": O.OP_GS, "nlse": O.OP_NLSE}
+OPMAP = {"ch": O.OP_CH, "gs": O.OP_GS, "nlse": O.OP_NLSE, "xpfc": O.OP_XPFC}
 
 
 def oracle_inst(d: S.Desc, full_now: int = 0) -> O.Inst:

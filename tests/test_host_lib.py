@@ -122,3 +122,34 @@ def test_null_arguments():
     assert lib.spdba_destroy(None) == spdba.SPDBA_OK
     assert lib.spdba_step(None, 1) == spdba.SPDBA_EINVAL
     assert lib.spdba_stats(None, 0, None) == spdba.SPDBA_EINVAL
+
+
+def _xpfc(**kw):
+    d = spdba.Desc(op="xpfc", dtype="f32", ndim=2, n=64, block=16, tau=1e-4, dx=0.7854, dt=0.01,
+                   params=(1.0, 0.02, 0.1, 1.0, 1.0, 1.0, 1.0), state_indicator=True)
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d.to_c()
+
+
+@pytest.mark.parametrize("mutate,expect", [
+    (lambda c: c.op_params.__setitem__(2, 0.0), spdba.SPDBA_EINVAL),      # peak width alpha
+    (lambda c: c.op_params.__setitem__(5, 0.0), spdba.SPDBA_EINVAL),      # rho beta
+    (lambda c: c.op_params.__setitem__(6, -1.0), spdba.SPDBA_EINVAL),
+    (lambda c: setattr(c, "flags", c.flags & ~spdba.SPDBA_FLAG_STATE_INDICATOR), spdba.SPDBA_EUNSUPPORTED),
+    (lambda c: setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_HALF_SPECTRUM), spdba.SPDBA_EUNSUPPORTED),
+])
+def test_xpfc_descriptors_rejected(mutate, expect):
+    """XPFC needs a positive peak width and rho beta, the state-amplitude
+    measure (or Regular mode), and the full layout."""
+    c = _xpfc()
+    mutate(c)
+    assert spdba.spdba_plan_create_status([c]) == expect
+
+
+def test_half_layout_refused_above_tested_sizes():
+    """The half layout stays on grids of at most 2^18 points: timed 256^3
+    runs of it ended in device faults whose cause is still open."""
+    d = _good(half=True, state_indicator=True).to_c()
+    d.dims[0] = d.dims[1] = d.dims[2] = 128
+    assert spdba.spdba_plan_create_status([d]) == spdba.SPDBA_EUNSUPPORTED
