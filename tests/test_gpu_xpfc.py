@@ -85,7 +85,7 @@ APPLY = [
     (X("f64", 2, 64, 16, 3e-2), 1),
     (X("f32", 2, 64, 16, 3e-2), 2),
     (X("f32", 3, 32, 8, 3e-2), 3),
-    (X("f64", 3, 16, 8, 1e-1), 4),
+    (X("f64", 3, 32, 8, 3e-2), 4),
     (X("f32", 2, 64, 16, 0.0, dense=True), 5),
     (X("f32", 2, 64, 16, 3e-2, dt=0.6), 6),    # |z| up to ~20: the closed-form branch
     (X("f64", 2, 32, 8, 3e-2, dt=0.6), 7),
