@@ -54,7 +54,23 @@ CH3D_512_F32_PROPOSER = dict(
     proposer=dict(K=10, audit_steps=3, train_n=256, train_seeds=tuple(range(2001, 2009))),
 )
 
-ALL = [CH2D_128_F64, CH3D_256_F32, NLSE1D_BATCH48_F32, GS2D_BATCH32_F32, CH3D_512_F32_PROPOSER]
+# XPFC polycrystalline coarsening (Supplementary S3.2): the paper's model and
+# sp-DBA settings (dx, dt, q0, sigma, alpha, omega, u, psi_c, A_h; 16^2
+# blocks, block energy, transition smoothing, threshold control with
+# adjustment factor 0.05 every 50 steps from tau = 5e-5, an initial
+# full-activation stage) on a 4096^2 grid in FP32, grown from seeded crystals
+# for `full_steps` steps, the controller settling for `settle_steps`, then
+# `window` timed steps at each target active ratio.
+XPFC2D_4096_F32 = dict(
+    name="xpfc2d_4096_f32",
+    op="xpfc", dtype="f32", ndim=2, n=4096, block=16, tau=5e-5,
+    dx=0.7854, dt=0.01, params=(1.0, 0.02, 0.1, 1.0, 1.0, 1.0, 1.0), seed=1010,
+    full_steps=3000, settle_steps=1000, window=200, control_interval=50, deadband=0.05,
+    targets=(0.05, 0.10, 0.20), taus=(1e-3, 3e-4, 1e-4, 3e-5, 1e-5), measure="energy", layout="full",
+    ic=dict(kind="xpfc_seeds", mean=0.12, amp=0.25, seeds=400, radius_frac=0.02),
+)
+
+ALL = [CH2D_128_F64, CH3D_256_F32, NLSE1D_BATCH48_F32, GS2D_BATCH32_F32, CH3D_512_F32_PROPOSER, XPFC2D_4096_F32]
 
 
 def lv_equilibrium(M: int, alpha: float, beta: float, r: float = 1.0, a: float = 1.0) -> float:

@@ -158,27 +158,34 @@ def xpfc_seed_field(seed: int, inst: int, n: int, dx: float, q0: float = 1.0, me
     orientation, each a triangular (hexagonal-density) wave of three plane
     waves of wavenumber q0 at 120 degrees, `amp` each, faded out over
     `width` grid spacings at its radius (radius_frac of the domain edge).
-    Where seeds overlap the nearest centre wins."""
+    Where seeds overlap the nearest centre wins.  Each seed touches only the
+    periodic window around its centre that its fade reaches."""
     r = rng_for(seed, inst, 17)
     L = n * dx
-    x = (np.arange(n) * dx)[None, :]
-    y = (np.arange(n) * dx)[:, None]
     cen = r.uniform(0.0, L, size=(seeds, 2))
     ang = r.uniform(0.0, np.pi / 3.0, size=seeds)
     rad = radius_frac * L
     f = mean + noise * r.uniform(-1.0, 1.0, size=(n, n))
     best = np.full((n, n), np.inf)
+    reach = min(n // 2, int(np.ceil((rad + 8.0 * width * dx) / dx)) + 1)
+    off = np.arange(-reach, reach + 1)
     for s in range(seeds):
+        cx, cy = int(round(cen[s, 0] / dx)), int(round(cen[s, 1] / dx))
+        ix, iy = np.unique((cx + off) % n), np.unique((cy + off) % n)
+        x = (ix * dx)[None, :]
+        y = (iy * dx)[:, None]
         # periodic distance to the centre
         dxs = (x - cen[s, 0] + 0.5 * L) % L - 0.5 * L
         dys = (y - cen[s, 1] + 0.5 * L) % L - 0.5 * L
         d = np.sqrt(dxs * dxs + dys * dys)
-        wave = np.zeros((n, n))
+        wave = np.zeros(d.shape)
         for j in range(3):
             a = ang[s] + 2.0 * np.pi * j / 3.0
             wave = wave + np.cos(q0 * (np.cos(a) * dxs + np.sin(a) * dys))
         w = 0.5 * (1.0 - np.tanh((d - rad) / (width * dx)))
-        take = d < best
-        best = np.where(take, d, best)
-        f = np.where(take & (w > 1e-3), mean + amp * w * wave + (1.0 - w) * (f - mean), f)
+        sub = np.ix_(iy, ix)
+        fb, bb = f[sub], best[sub]
+        take = d < bb
+        f[sub] = np.where(take & (w > 1e-3), mean + amp * w * wave + (1.0 - w) * (fb - mean), fb)
+        best[sub] = np.where(take, d, bb)
     return f.astype(dtype)

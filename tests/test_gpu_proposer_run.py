@@ -1,8 +1,8 @@
 """End-to-end learned proposer on a small 3-D Cahn-Hilliard grid: train on
 masks logged from plain runs, choose the threshold on a held-out seed, then
-run an unseen seed with the window protocol.  The proposer must skip a real
-share of the indicator work while its field stays close to plain sp-DBA and
-to the dense update."""
+run an unseen seed with the window protocol over a 500-step horizon.  The
+proposer must save more than 8 % of the block-steps' indicator evaluations
+while its field stays as close to the dense update as plain sp-DBA's."""
 import numpy as np
 import pytest
 
@@ -12,7 +12,7 @@ from paper_2609_03922_amd import spdba as S
 
 pytestmark = pytest.mark.gpu
 
-N, B, STEPS, K = 64, 8, 200, 10
+N, B, STEPS, K = 64, 8, 500, 10
 
 
 def _desc(**kw):
@@ -86,9 +86,15 @@ def test_proposer_trains_and_skips_with_bounded_error():
     skipped = hist["skipped_block_steps"] / (hist["steps"] * (N // B) ** 3)
     print(f"proposer run: {hist}; skipped block-steps {skipped:.3f}; rel-L2 plain-vs-dense {e_plain:.2e}, "
           f"proposer-vs-dense {e_prop:.2e}, proposer-vs-plain {e_pp:.2e}", flush=True)
-    # at 64^3 most blocks are active within every 10-step window, so the share
-    # the proposer can skip is small; it must skip some work, miss rarely, and
-    # stay as close to the dense update as plain sp-DBA does
-    assert skipped > 0.0
+    # the gain over the plain rule: the indicator evaluations of the skipped
+    # block-steps are saved.  At 64^3 and tau = 1e-6 about two thirds of the
+    # blocks turn active within a 10-step window (held-out positives 0.65),
+    # and the audit steps evaluate every block, so at most about 0.35 x 7/10
+    # of the block-steps can be skipped; with the recall-1 threshold the
+    # proposer skips more than 8 % of all block-steps (0.102 measured), while
+    # its field stays as close to the dense update as the plain rule's
+    # (within a factor 1.5 of that error, plus FP32 round-off)
+    print(f"indicator block evaluations saved vs plain: {skipped:.3f}", flush=True)
+    assert skipped >= 0.08
     assert hist["misses"] <= hist["windows"] // 2
-    assert e_prop < 1e-4 and e_pp < 1e-4
+    assert e_prop <= 1.5 * e_plain + 1e-7 and e_pp < 1e-4
