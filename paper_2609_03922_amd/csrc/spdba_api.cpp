@@ -516,6 +516,86 @@ spdba_status check_nonfinite(spdba_plan p) {
 }  // namespace
 
 namespace spdba {
+
+// Per-instance constants of the device table: geometry (full layout, or the
+// half layout with row pitch `xs`), strips and tiles, the operator's
+// coefficients and the control parameters.  Offsets into the concatenated
+// spaces (off, roff, blk_off, strip_off, tile_off, ht_off, ltab_off) are
+// left 0 for the caller.
+void fill_inst(const spdba_instance_desc &x, int op, bool dbl, bool pin, bool half, int64_t xs, InstDev &I) {
+    std::memset(&I, 0, sizeof(I));
+    const int V = dbl ? 1 : 2;
+    const int64_t TE = dbl ? 512 : 1024;
+    for (int a = 0; a < 3; ++a) {
+        I.n[a] = (int32_t)x.dims[a];
+        I.b[a] = x.block[a];
+        I.nbk[a] = (int32_t)(x.dims[a] / x.block[a]);
+    }
+    I.N = x.dims[0] * x.dims[1] * xs;
+    I.nb = (int64_t)I.nbk[0] * I.nbk[1] * I.nbk[2];
+    I.half = half ? 1 : 0;
+    I.Nreal = x.dims[0] * x.dims[1] * x.dims[2];
+    I.xs = (int32_t)xs;
+    I.nbxm = half ? (int32_t)(x.dims[2] / (2 * x.block[2])) : I.nbk[2];
+    I.nbm = (int64_t)I.nbk[0] * I.nbk[1] * I.nbxm;
+    if (half) I.nb = I.nbm + (int64_t)I.nbk[0] * I.nbk[1];
+    I.S = std::min<int>(I.nbk[2], std::max(1, 64 * V / I.b[2]));
+    I.chunks = std::max(1, I.b[2] / (64 * V));
+    auto lg = [](int64_t v) { int l = 0; while ((int64_t(1) << l) < v) ++l; return l; };
+    for (int a = 0; a < 3; ++a) {
+        I.ln[a] = lg(I.n[a]);
+        I.lb[a] = lg(I.b[a]);
+        I.lnbk[a] = lg(I.nbk[a]);
+    }
+    I.lS = lg(I.S);
+    I.lchunks = lg(I.chunks);
+    I.lnbxm = lg(I.nbxm);
+    // half layout: one indicator strip per (z, y) block row; tiles of TE
+    // values, enough for the reals of the nonlinear term and for the
+    // stored values (padding included) of the dense update
+    I.nstrips = half ? (int64_t)I.nbk[0] * I.nbk[1] : (int64_t)I.nbk[0] * I.nbk[1] * (I.nbk[2] / I.S);
+    I.ntiles = ((half ? std::max(I.Nreal, I.N) : I.N) + TE - 1) / TE;
+    I.nspec = op == OP_GS ? 2 : 1;
+    I.k0path = (!dbl && op != OP_NLSE) ? 1 : 0;
+    I.pin = pin ? 1 : 0;
+    const int64_t ext = x.dims[2];
+    const double K = kTwoPi / ((double)ext * x.dx);
+    I.K2 = K * K;
+    I.tau2 = x.threshold * x.threshold;
+    I.invN = 1.0 / (double)I.Nreal;
+    double dvol = 1.0;
+    for (int a = 0; a < x.ndim; ++a) dvol *= x.dx;
+    I.dvol = dvol;
+    if (op == OP_CH) {
+        I.c0 = x.dt * x.op_params[0];
+        I.c1 = I.c0 * x.op_params[1];
+    } else if (op == OP_GS) {
+        I.c0 = x.dt;
+        I.c1 = x.dt * x.op_params[0];
+        I.c2 = x.dt * x.op_params[1];
+        I.q0 = x.op_params[2];
+        I.q1 = x.op_params[3];
+    } else if (op == OP_XPFC) {
+        I.c0 = x.dt;
+        I.q0 = x.op_params[3];  // omega
+        I.q1 = x.op_params[4];  // u
+    } else {
+        I.c0 = ((x.op_params[0] * x.dt) * 0.25) * I.K2;
+        I.c1 = std::exp(-(x.op_params[2] * x.dt) * 0.25);
+        I.q0 = x.op_params[1] * x.dt;
+    }
+    I.full_steps = x.full_steps;
+    I.refresh = (x.flags & SPDBA_FLAG_REFRESH) ? x.refresh_period : 0;
+    I.interval = (x.flags & SPDBA_FLAG_DYN_THRESHOLD) ? x.control_interval : 0;
+    I.per = op == OP_NLSE ? 2 : 1;
+    I.tau0 = x.threshold;
+    I.ht_off = -1;
+    I.target = x.target_ratio;
+    I.deadband = x.deadband;
+}
+
+spdba_status validate_desc(const spdba_instance_desc *d, int32_t n) { return validate(d, n, nullptr); }
+
 const Ctx *plan_ctx(spdba_plan p) { return p && p->bound ? &p->ctx : nullptr; }
 const InstDev *plan_hinst(spdba_plan p, int *n_inst, int64_t *nb_total) {
     if (!p) return nullptr;
@@ -609,79 +689,21 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     for (int i = 0; i < n_inst; ++i) {
         const spdba_instance_desc &x = inst[i];
         InstDev I;
-        std::memset(&I, 0, sizeof(I));
+        spdba::fill_inst(x, p->op, p->dbl, p->pin, p->half, pitch(i), I);
         I.off = mem_off[i];
-        I.N = Nof(i);
         {  // half layout: reals of the batch packed from twice the group's offset
             const Group &gg = p->groups[p->group_of[i]];
             const int64_t pos = (mem_off[i] - gg.off) / (I.N * p->nspec);
             I.roff = 2 * gg.off + pos * p->nspec * x.dims[0] * x.dims[1] * x.dims[2];
         }
-        for (int a = 0; a < 3; ++a) {
-            I.n[a] = (int32_t)x.dims[a];
-            I.b[a] = x.block[a];
-            I.nbk[a] = (int32_t)(x.dims[a] / x.block[a]);
-        }
-        I.nb = (int64_t)I.nbk[0] * I.nbk[1] * I.nbk[2];
-        I.half = p->half ? 1 : 0;
-        I.Nreal = x.dims[0] * x.dims[1] * x.dims[2];
-        I.xs = (int32_t)pitch(i);
-        I.nbxm = p->half ? (int32_t)(x.dims[2] / (2 * x.block[2])) : I.nbk[2];
-        I.nbm = (int64_t)I.nbk[0] * I.nbk[1] * I.nbxm;
-        if (p->half) I.nb = I.nbm + (int64_t)I.nbk[0] * I.nbk[1];
         I.blk_off = blk;
         blk += I.nb;
-        I.S = std::min<int>(I.nbk[2], std::max(1, 64 * V / I.b[2]));
-        I.chunks = std::max(1, I.b[2] / (64 * V));
-        auto lg = [](int64_t v) { int l = 0; while ((int64_t(1) << l) < v) ++l; return l; };
-        for (int a = 0; a < 3; ++a) {
-            I.ln[a] = lg(I.n[a]);
-            I.lb[a] = lg(I.b[a]);
-            I.lnbk[a] = lg(I.nbk[a]);
-        }
-        I.lS = lg(I.S);
-        I.lchunks = lg(I.chunks);
-        I.lnbxm = lg(I.nbxm);
         p->max_slots = std::max(p->max_slots, I.b[0] * I.b[1] * (I.b[2] / V));
         p->min_slots = i == 0 ? I.b[0] * I.b[1] * (I.b[2] / V) : std::min(p->min_slots, I.b[0] * I.b[1] * (I.b[2] / V));
-        // half layout: one indicator strip per (z, y) block row; tiles of TE
-        // values, enough for the reals of the nonlinear term and for the
-        // stored values (padding included) of the dense update
-        I.nstrips = p->half ? (int64_t)I.nbk[0] * I.nbk[1] : (int64_t)I.nbk[0] * I.nbk[1] * (I.nbk[2] / I.S);
         I.strip_off = strip;
         strip += I.nstrips;
-        I.ntiles = ((p->half ? std::max(I.Nreal, I.N) : I.N) + TE - 1) / TE;
         I.tile_off = tile;
         tile += I.ntiles;
-        I.nspec = p->nspec;
-        I.k0path = (!p->dbl && p->op != OP_NLSE) ? 1 : 0;
-        I.pin = p->pin ? 1 : 0;
-        const int64_t ext = x.dims[2];
-        const double K = kTwoPi / ((double)ext * x.dx);
-        I.K2 = K * K;
-        I.tau2 = x.threshold * x.threshold;
-        I.invN = 1.0 / (double)I.Nreal;
-        double dvol = 1.0;
-        for (int a = 0; a < x.ndim; ++a) dvol *= x.dx;
-        I.dvol = dvol;
-        if (p->op == OP_CH) {
-            I.c0 = x.dt * x.op_params[0];
-            I.c1 = I.c0 * x.op_params[1];
-        } else if (p->op == OP_GS) {
-            I.c0 = x.dt;
-            I.c1 = x.dt * x.op_params[0];
-            I.c2 = x.dt * x.op_params[1];
-            I.q0 = x.op_params[2];
-            I.q1 = x.op_params[3];
-        } else if (p->op == OP_XPFC) {
-            I.c0 = x.dt;
-            I.q0 = x.op_params[3];  // omega
-            I.q1 = x.op_params[4];  // u
-        } else {
-            I.c0 = ((x.op_params[0] * x.dt) * 0.25) * I.K2;
-            I.c1 = std::exp(-(x.op_params[2] * x.dt) * 0.25);
-            I.q0 = x.op_params[1] * x.dt;
-        }
         I.ltab_off = 0;
         if (p->op == OP_XPFC) {
             // L(k) = -k^2 (1 - C2(k)) at every integer |m|^2 of the grid, in
@@ -702,11 +724,6 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
             }
         }
         for (int a = 0; a < 3; ++a) taper = std::max<int64_t>(taper, 2 * (int64_t)I.b[a]);
-        I.full_steps = x.full_steps;
-        I.refresh = (x.flags & SPDBA_FLAG_REFRESH) ? x.refresh_period : 0;
-        I.interval = (x.flags & SPDBA_FLAG_DYN_THRESHOLD) ? x.control_interval : 0;
-        I.per = p->op == OP_NLSE ? 2 : 1;
-        I.tau0 = x.threshold;
         I.ht_off = -1;
         if (p->op == OP_NLSE && x.ndim == 1) {  // H depends on |m| only: one table entry per |m|
             I.ht_off = htab;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "spdba.h"
+
 struct spdba_plan_s;
 
 namespace spdba {
@@ -184,6 +186,12 @@ hipError_t launch_check_pattern(const void *buf, int64_t n_elems, bool dbl, uint
 
 // rocFFT's library set-up, once per process (spdba_api.cpp)
 int32_t fft_setup();  // an spdba_status
+
+// per-instance constants of the device table (spdba_api.cpp): everything but
+// the offsets into the concatenated spaces, which are left 0
+void fill_inst(const spdba_instance_desc &x, int op, bool dbl, bool pin, bool half, int64_t xs, InstDev &I);
+// descriptor validation of spdba_plan_create (an spdba_status)
+int32_t validate_desc(const spdba_instance_desc *d, int32_t n);
 
 // plan internals for the proposer kernels (spdba_api.cpp)
 const Ctx *plan_ctx(::spdba_plan_s *p);
