@@ -323,6 +323,36 @@ spdba_status spdba_stats(spdba_plan plan, int32_t inst, spdba_stats_t *out);
  * Resets the stage-time ring. */
 spdba_status spdba_set_launch(spdba_plan plan, int32_t kernel, int32_t value);
 
+/* The update stage of one instance without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): what spdba_apply does for a plan
+ * of this one instance -- indicator pass, threshold, compaction, active
+ * update, or the dense update -- with the same kernels and results, but with
+ * no plan: the scratch memory (instance table, a_b, list, counters, G,
+ * partial sums) is a file-scope device array of about 8.9 MB that each GPU
+ * the library runs on holds until the process ends.  Its address is taken
+ * once per device at the first call.  Every call on a GPU shares that array,
+ * so calls that overlap on one GPU race; each call resets what it reads.
+ *   desc     : one descriptor; CH or GS on the full layout, no consistency
+ *              control, no SPDBA_FLAG_GRAPH (else EUNSUPPORTED); at most 2^18
+ *              blocks and 2^17 x 1024 (FP32) / 2^17 x 512 (FP64) complex
+ *              values per species (else EUNSUPPORTED); other checks as
+ *              spdba_plan_create (EINVAL / EUNSUPPORTED)
+ *   d_state  : device, nspec x N complex, the stored spectrum, updated in
+ *              place on the active blocks (FP32 CH/GS: slot 0 of each species
+ *              is written 0, its value lives in d_k0)
+ *   d_rhs_hat: device, nspec x N complex, the right-hand side (slot 0 of an
+ *              FP32 CH/GS species is not read)
+ *   d_k0, d_rhs_k0: device, FP32 CH/GS only (may be NULL otherwise): the
+ *              FP64 k = 0 values per species, d_k0 updated in place
+ *   d_mask   : device, one byte per block (C order over the block grid),
+ *              written with the mask of this update
+ *   stream   : hipStream_t (NULL = default stream); the call is asynchronous
+ * A non-finite indicator value is not reported by this entry point (it has
+ * no synchronising read-back).  Requires a GPU. */
+spdba_status spdba_apply_noalloc(const spdba_instance_desc *desc, void *d_state, const void *d_rhs_hat, double *d_k0,
+                                 const double *d_rhs_k0, uint8_t *d_mask, void *stream);
+
 /* Release the plan (host metadata, rocFFT plans, graphs).  NULL-safe. */
 spdba_status spdba_destroy(spdba_plan plan);
 

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspdba.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["spdba_kernels.hip", "spdba_api.cpp", "spdba_proposer.hip", "spdba_rcd.hip", "spdba_mdbp.hip"]
+SOURCES = ["spdba_kernels.hip", "spdba_api.cpp", "spdba_proposer.hip", "spdba_rcd.hip", "spdba_mdbp.hip",
+           "spdba_static.hip"]
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -36,7 +36,7 @@ EXPORTS = (
     "spdba_get_field", "spdba_set_spectrum", "spdba_get_spectrum", "spdba_step", "spdba_apply",
     "spdba_set_skip", "spdba_active_mask", "spdba_indicator", "spdba_worklist",
     "spdba_device_views", "spdba_stats", "spdba_set_launch", "spdba_destroy",
-    "spdba_status_string",
+    "spdba_status_string", "spdba_apply_noalloc",
 )
 # entry points of include/spdba_proposer.h
 PROPOSER_EXPORTS = (
@@ -139,6 +139,7 @@ def load():
         "spdba_proposer_skip": [P, I64, ctypes.c_float, P, P, P, P],
         "spdba_proposer_miss": [P, P, I64, P, P],
         "spdba_set_block_energy": [P, P],
+        "spdba_apply_noalloc": [ctypes.POINTER(InstanceDesc), P, P, P, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -147,6 +148,16 @@ def load():
                       ctypes.c_size_t if name == "spdba_mlp_backward_scratch" else ctypes.c_int32)
     _lib = lib
     return lib
+
+
+def spdba_apply_noalloc(desc, state, rhs, k0=None, rhs_k0=None, mask=None, stream=None) -> int:
+    """The allocation-free update stage of one instance (include/spdba.h):
+    torch device tensors in and out (state updated in place, mask written);
+    returns the status."""
+    arr = descs_array([desc])
+    ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+    sp = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+    return load().spdba_apply_noalloc(arr, ptr(state), ptr(rhs), ptr(k0), ptr(rhs_k0), ptr(mask), sp)
 
 
 def status_string(s: int) -> str:
