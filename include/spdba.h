@@ -87,7 +87,8 @@ enum {
  *       L = -k^2 (1 - C2), B_l = -k^2 Phi_l (Phi_1 = dt phi_1, Phi_2 = dt phi_2,
  *       Phi_3 = dt (phi_2/2 + phi_3), Phi_4 = dt (phi_2/3 + phi_3 + phi_4)).
  *       The coefficients are formed per mode in FP64 from L (a per-instance
- *       table by integer |m|^2, filled on the host) -- phi_4 by its series for
+ *       table over (|m_z|, |m_y|, |m_x|) of (n/2 + 1)^ndim FP64 values, filled
+ *       on the host; more than 2^28: EUNSUPPORTED) -- phi_4 by its series for
  *       |z| <= 1 and phi_l = 1/l! + z phi_{l+1}, else e^z by scaling and
  *       squaring and the closed forms -- and rounded once.  The four
  *       transforms rotate through slots of the state buffer; the first step

@@ -175,10 +175,10 @@ spdba_status validate(const spdba_instance_desc *d, int32_t n, void *) {
             if (!(x.op_params[2] > 0.0) || !(x.op_params[5] * x.op_params[6] > 0.0)) return SPDBA_EINVAL;
             if (!(x.flags & (SPDBA_FLAG_STATE_INDICATOR | SPDBA_FLAG_DENSE))) return SPDBA_EUNSUPPORTED;
             if (x.flags & SPDBA_FLAG_HALF_SPECTRUM) return SPDBA_EUNSUPPORTED;
-            // the L table holds one entry per integer |m|^2 <= ndim (n/2)^2
-            int64_t m2max = 0;
-            for (int a = 0; a < 3; ++a) m2max += (x.dims[a] / 2) * (x.dims[a] / 2);
-            if (m2max > (int64_t(1) << 28)) return SPDBA_EUNSUPPORTED;
+            // the L table holds (n/2 + 1)^ndim FP64 entries
+            int64_t tab = 1;
+            for (int a = 0; a < 3; ++a) tab *= x.dims[a] / 2 + 1;
+            if (tab > (int64_t(1) << 28)) return SPDBA_EUNSUPPORTED;
         }
         if (x.dtype != SPDBA_F32 && x.dtype != SPDBA_F64) return SPDBA_EUNSUPPORTED;
         if (x.flags & ~uint32_t(SPDBA_FLAG_DENSE | SPDBA_FLAG_PIN_K0 | SPDBA_FLAG_GRAPH |
@@ -706,22 +706,26 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
         tile += I.ntiles;
         I.ltab_off = 0;
         if (p->op == OP_XPFC) {
-            // L(k) = -k^2 (1 - C2(k)) at every integer |m|^2 of the grid, in
-            // FP64, by the steps of the definition (Supplementary S3.1)
-            int64_t m2max = 0;
-            for (int a = 0; a < 3; ++a) m2max += (x.dims[a] / 2) * (x.dims[a] / 2);
+            // L(k) = -k^2 (1 - C2(k)) in FP64 by the steps of the definition
+            // (Supplementary S3.1), one entry per (|m_z|, |m_y|, |m_x|), C
+            // order over extents n/2 + 1: a row of the table serves a row of
+            // the grid with consecutive reads
+            const int64_t h0 = x.dims[0] / 2 + 1, h1 = x.dims[1] / 2 + 1, h2 = x.dims[2] / 2 + 1;
             I.ltab_off = (int64_t)p->ltab.size();
             const double q0 = x.op_params[0], sg = x.op_params[1], al = x.op_params[2];
             const double rho = x.op_params[5], be = x.op_params[6];
             const double dw = std::exp(-((sg * sg) * (q0 * q0)) / (2.0 * (rho * be)));
-            for (int64_t m2 = 0; m2 <= m2max; ++m2) {
-                const double k2 = I.K2 * (double)m2;
-                const double k = std::sqrt(k2);
-                const double dk = k - q0;
-                const double peak = std::exp(-(dk * dk) / (2.0 * (al * al)));
-                const double c2 = peak * dw;
-                p->ltab.push_back(-k2 * (1.0 - c2));
-            }
+            for (int64_t az = 0; az < h0; ++az)
+                for (int64_t ay = 0; ay < h1; ++ay)
+                    for (int64_t ax = 0; ax < h2; ++ax) {
+                        const int64_t m2 = az * az + ay * ay + ax * ax;
+                        const double k2 = I.K2 * (double)m2;
+                        const double k = std::sqrt(k2);
+                        const double dk = k - q0;
+                        const double peak = std::exp(-(dk * dk) / (2.0 * (al * al)));
+                        const double c2 = peak * dw;
+                        p->ltab.push_back(-k2 * (1.0 - c2));
+                    }
         }
         for (int a = 0; a < 3; ++a) taper = std::max<int64_t>(taper, 2 * (int64_t)I.b[a]);
         I.ht_off = -1;

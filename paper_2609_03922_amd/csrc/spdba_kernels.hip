@@ -230,7 +230,7 @@ __device__ __forceinline__ double k0_cand(const InstDev &I, int op, const double
 // backward differences of the nonlinear transforms H_n .. H_{n-3},
 //   psi' = e^z psi + B1 H_n + B2 dH + B3 d2H + B4 d3H,  B_l = -k^2 Phi_l,
 // z = L dt with L(k) = -k^2 (1 - C2(k)) read from a per-instance FP64 table
-// by integer |m|^2 (filled on the host at plan creation).  The coefficients
+// by (|m_z|, |m_y|, |m_x|) (filled on the host at plan creation).  The coefficients
 // are formed in FP64 -- phi_4 from its series for |z| <= 1 and the
 // recurrence phi_l = 1/l! + z phi_{l+1} (e^z = 1 + z phi_1), else e^z by
 // scaling and squaring and phi_1 .. phi_4 in closed form -- and rounded
@@ -291,12 +291,21 @@ __device__ __forceinline__ void etd4_phi(double z, double (&o)[5]) {
     o[4] = (o[3] - F.v[3]) / z;
 }
 
-// {e^z, B1 .. B4} of the mode with integer |m|^2 (dt = K.c0)
+// The L table of an instance is indexed by (|m_z|, |m_y|, |m_x|), C order
+// over extents n/2 + 1 (1 on unused axes): a row of it serves a grid row.
+__device__ __forceinline__ const double *xpfc_row(const Ctx &c, const InstDev &I, int z, int y) {
+    const int h1 = (I.n[1] >> 1) + 1, h2 = (I.n[2] >> 1) + 1;
+    const int az = abs(sidx(z, I.n[0])), ay = abs(sidx(y, I.n[1]));
+    return c.ltab + I.ltab_off + ((int64_t)az * h1 + ay) * h2;
+}
+
+// {e^z, B1 .. B4} of the mode with integer |m|^2 = m2 and |m_x| = ax on the
+// table row lrow (dt = K.c0)
 template <typename T>
-__device__ __forceinline__ void xpfc_coef(const Coef &K, const double *ltab, double m2, T (&co)[5]) {
+__device__ __forceinline__ void xpfc_coef(const Coef &K, const double *lrow, int ax, double m2, T (&co)[5]) {
     const double k2 = K.K2 * m2;
     const double dt = K.c0;
-    const double z = ltab[(int64_t)m2] * dt;
+    const double z = lrow[ax] * dt;
     double ph[5];
     etd4_phi(z, ph);
     const double P1 = dt * ph[1];
@@ -1387,7 +1396,6 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
     const T *h1p = reinterpret_cast<const T *>(c.hist1) + 2 * I.off;  // XPFC history
     const T *h2p = reinterpret_cast<const T *>(c.hist2) + 2 * I.off;
     const T *h3p = reinterpret_cast<const T *>(c.hist3) + 2 * I.off;
-    const double *ltab = c.ltab + I.ltab_off;
     const bool trn = TR && (entry >> 31);  // workgroup-uniform
     const uint32_t faces = (entry >> 25) & 63u;
     const int b0 = I.b[0], b1 = I.b[1], b2 = I.b[2];
@@ -1410,10 +1418,12 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
             CV<T>::ld(q1p + 2 * e, q2r, q2i);
             CV<T>::ld(r1p + 2 * e, n2r, n2i);
         }
+        const double *lrow = nullptr;
         if (OP == OP_XPFC) {
             CV<T>::ld(h1p + 2 * e, h1r, h1i);
             CV<T>::ld(h2p + 2 * e, h2r, h2i);
             CV<T>::ld(h3p + 2 * e, h3r, h3i);
+            lrow = xpfc_row(c, I, z, y);
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -1431,7 +1441,7 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
                 gs_cand<T>(dt, av, q2r[v], q2i[v], n2r[v], n2i[v], dr, di);
             } else if (OP == OP_XPFC) {
                 T co[5];
-                xpfc_coef<T>(K, ltab, m2, co);
+                xpfc_coef<T>(K, lrow, abs(sidx(x0 + v, g.n2)), m2, co);
                 cr = xpfc_cand1<T>(co, qr[v], nr[v], h1r[v], h2r[v], h3r[v]);
                 ci = xpfc_cand1<T>(co, qi[v], ni[v], h1i[v], h2i[v], h3i[v]);
             } else {
@@ -1666,7 +1676,6 @@ __device__ __forceinline__ void update_block_wave(const Ctx &c, uint32_t gb, int
     const T *h1p = reinterpret_cast<const T *>(c.hist1) + 2 * I.off;  // XPFC history
     const T *h2p = reinterpret_cast<const T *>(c.hist2) + 2 * I.off;
     const T *h3p = reinterpret_cast<const T *>(c.hist3) + 2 * I.off;
-    const double *ltab = c.ltab + I.ltab_off;
     const bool ab = OP != OP_NLSE && c.ab_inc;  // wave-uniform
     const bool esum = c.ab_sum;                  // block energy: the sum, else the maximum
     double amax = 0.0;
@@ -1676,6 +1685,7 @@ __device__ __forceinline__ void update_block_wave(const Ctx &c, uint32_t gb, int
         int64_t ex[UB];
         int x0s[UB];
         double myz[UB];
+        const double *lrows[UB];
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
             const int s = s0 + u * 64 + lane;
@@ -1700,6 +1710,7 @@ __device__ __forceinline__ void update_block_wave(const Ctx &c, uint32_t gb, int
                 CV<T>::ld(h1p + 2 * e, h1r[u], h1i[u]);
                 CV<T>::ld(h2p + 2 * e, h2r[u], h2i[u]);
                 CV<T>::ld(h3p + 2 * e, h3r[u], h3i[u]);
+                lrows[u] = xpfc_row(c, I, z, y);
             }
         }
 #pragma unroll
@@ -1721,7 +1732,7 @@ __device__ __forceinline__ void update_block_wave(const Ctx &c, uint32_t gb, int
                     gs_cand<T>(dt, av, q2r[u][v], q2i[u][v], n2r[u][v], n2i[u][v], dr, di);
                 } else if (OP == OP_XPFC) {
                     T co[5];
-                    xpfc_coef<T>(K, ltab, m2, co);
+                    xpfc_coef<T>(K, lrows[u], abs(sidx(x0s[u] + v, g.n2)), m2, co);
                     cr = xpfc_cand1<T>(co, qr[u][v], nr[u][v], h1r[u][v], h2r[u][v], h3r[u][v]);
                     ci = xpfc_cand1<T>(co, qi[u][v], ni[u][v], h1i[u][v], h2i[u][v], h3i[u][v]);
                 } else {
@@ -2199,7 +2210,6 @@ __global__ void __launch_bounds__(1024) k_dense(Ctx c) {
     const T *h1p = reinterpret_cast<const T *>(c.hist1) + 2 * I.off;  // XPFC history
     const T *h2p = reinterpret_cast<const T *>(c.hist2) + 2 * I.off;
     const T *h3p = reinterpret_cast<const T *>(c.hist3) + 2 * I.off;
-    const double *ltab = c.ltab + I.ltab_off;
     double acc[1] = {0.0};
     const int jstep = blockDim.x * V;
     for (int j = threadIdx.x * V; j < TE; j += jstep) {
@@ -2219,10 +2229,12 @@ __global__ void __launch_bounds__(1024) k_dense(Ctx c) {
             CV<T>::ld(q1p + 2 * e, q2r, q2i);
             CV<T>::ld(r1p + 2 * e, n2r, n2i);
         }
+        const double *lrow = nullptr;
         if (OP == OP_XPFC) {
             CV<T>::ld(h1p + 2 * e, h1r, h1i);
             CV<T>::ld(h2p + 2 * e, h2r, h2i);
             CV<T>::ld(h3p + 2 * e, h3r, h3i);
+            lrow = xpfc_row(c, I, z, y);
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -2244,7 +2256,7 @@ __global__ void __launch_bounds__(1024) k_dense(Ctx c) {
                 q2i[v] = di;
             } else if (OP == OP_XPFC) {
                 T co[5];
-                xpfc_coef<T>(K, ltab, m2, co);
+                xpfc_coef<T>(K, lrow, abs(sidx(x0 + v, n2)), m2, co);
                 cr = xpfc_cand1<T>(co, qr[v], nr[v], h1r[v], h2r[v], h3r[v]);
                 ci = xpfc_cand1<T>(co, qi[v], ni[v], h1i[v], h2i[v], h3i[v]);
             } else {
