@@ -36,9 +36,8 @@
  * Ownership and errors: the caller owns every device buffer (sized by
  * spdba_rcd_buffer_sizes) and the stream; the plan owns host metadata and its
  * rocFFT plans.  Descriptor errors return SPDBA_EINVAL before any device call;
- * M beyond the kernels' tiles (64 in FP32, 48 in FP64; 8 for
- * SPDBA_RCD_DIRECT) returns
- * SPDBA_EUNSUPPORTED; calls before bind return SPDBA_ESTATE; HIP and rocFFT
+ * M beyond the kernels' tiles (64 in FP32, 48 in FP64, for both forms of the
+ * update) returns SPDBA_EUNSUPPORTED; calls before bind return SPDBA_ESTATE; HIP and rocFFT
  * failures return SPDBA_EDEVICE / SPDBA_EFFT.  Calls are asynchronous on the
  * plan's stream unless stated.  A plan is not thread-safe.
  */
@@ -59,8 +58,10 @@ enum {
     SPDBA_RCD_PIN_K0 = 1u << 1, /* the block holding k = 0 is always active  */
     SPDBA_RCD_TIMING = 1u << 2, /* HIP events around the stages (stats)       */
     SPDBA_RCD_DIRECT = 1u << 3  /* the coupled update as written in S4.2: per
-                                   mode a Cholesky solve of I + dt k^2 D (SPD),
-                                   instead of the eigen form; M <= 8           */
+                                   mode a solve of I + dt k^2 D (SPD) -- a
+                                   Cholesky factor in registers to M = 8, one
+                                   wave's elimination per mode beyond --
+                                   instead of the eigen form of S4.3          */
 };
 
 typedef struct {

@@ -17,7 +17,12 @@
 //                    registers (MM-wide tiles, zero-padded past M); it also
 //                    keeps the measure of every block it stores (the next
 //                    update's state is what it stored, frozen blocks are
-//                    unchanged), so only a load is followed by a full pass
+//                    unchanged), so only a load is followed by a full pass;
+//                    with the direct form of S4.2 a per-mode Cholesky solve
+//                    of I + dt k^2 D in one thread's registers (M <= 8)
+//   k_rcd_update_direct  the direct form for M > 8: one wave per mode, a row
+//                    of [A | b] per lane, elimination and back substitution
+//                    with the pivot row's entries broadcast from its lane
 //
 // The per-mode contraction moves 24 M bytes (FP32) for 4 MM^2 FMAs; up to
 // MM = 16 that is well below the balance point of FP32 vector arithmetic
@@ -42,7 +47,7 @@ namespace {
 
 constexpr double kTwoPiR = 6.283185307179586476925286766559;
 constexpr int kMaxMF32 = 64, kMaxMF64 = 48;  // register tiles to 16 (FP32) / 8 (FP64), then matrix-core GEMMs
-constexpr int kMaxMDirect = 8;              // the direct form's factor: MM (MM + 1) / 2 registers
+constexpr int kMaxMReg = 8;  // the direct form's factor in one thread's registers: MM (MM + 1) / 2 values
 
 struct RGeo {
     int n[3], ln[3], b[3], lb[3], nbk[3], lnbk[3];
@@ -366,6 +371,114 @@ __global__ void __launch_bounds__(256) k_rcd_update(RCtx c) {
     }
 }
 
+// one lane's value as a wave-uniform one (v_readlane; l a constant)
+__device__ __forceinline__ float rlane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double rlane(double v, int l) {
+    const long long x = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(x & 0xffffffffll), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(x >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The direct form for wide systems (M > 8): one wave per mode, lane i holding
+// row i of A = I + dt k^2 D and component i of b = q + dt R.  Gaussian
+// elimination without pivoting (A is symmetric positive definite: every pivot
+// is positive) on [A | b]: at column j the pivot row's entries are taken from
+// lane j as wave-uniform values and each lane below subtracts its multiple;
+// back substitution then runs column by column, x_j formed from lane j's
+// values and removed from the rows above.  A row's entries sit in registers
+// at fixed indices, so every access names a constant register and a constant
+// lane.  Lanes from M on hold identity rows (D zero-padded), which no other
+// row reads; lanes from MM on hold zeros.  The kept measure sums the
+// components of x in order.  (Broadcasting the pivot row through LDS instead
+// measured slower: each column then waits on a store and a load.)
+template <typename T, int MM>
+__global__ void __launch_bounds__(256) k_rcd_update_direct(RCtx c) {
+    using V2 = typename C2<T>::t;
+    __shared__ T dl[MM * MM];  // D, zero-padded; symmetric, so lane i reads column i (consecutive words)
+    __shared__ double red[4];
+    for (int i = threadIdx.x; i < MM * MM; i += blockDim.x) dl[i] = reinterpret_cast<const T *>(c.dm)[i];
+    __syncthreads();
+    V2 *q = reinterpret_cast<V2 *>(c.state);
+    const V2 *rh = reinterpret_cast<const V2 *>(c.rhs);
+    const int M = c.M, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t N = c.g.N;
+    const T dt = (T)c.dt;
+    const int64_t total = c.dense ? c.g.nb : (int64_t)*c.count;
+    const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
+    const int64_t seg = (total + 7) >> 3;
+    const int64_t lo = std::min<int64_t>(total, seg * xcd), hi = std::min<int64_t>(total, seg * (xcd + 1));
+    for (int64_t ent = lo + (blockIdx.x >> 3); ent < hi; ent += per) {
+        const int64_t b = c.dense ? ent : (int64_t)c.list[ent];
+        double amax = 0.0;
+        for (int s = wave; s < c.g.bvol; s += 4) {  // wave-uniform
+            const int ln = lane;
+            int64_t e;
+            double k2;
+            mode_of(c.g, b, s, e, k2);
+            const T dk = (T)(c.dt * k2);
+            T a[MM];
+#pragma unroll
+            for (int k = 0; k < MM; ++k) {
+                asm volatile("" ::: "memory");  // D read from LDS where used
+                a[k] = ln < MM ? dk * dl[k * MM + ln] : (T)0;
+                if (k == ln) a[k] = a[k] + (T)1;
+            }
+            T br = (T)0, bi = (T)0;
+            if (ln < M) {
+                const V2 v = q[ln * N + e], f = rh[ln * N + e];
+                br = fma(dt, f.x, v.x);
+                bi = fma(dt, f.y, v.y);
+            }
+#pragma unroll
+            for (int j = 0; j < MM; ++j) {  // eliminate column j below the pivot
+                const T piv = rlane(a[j], j);  // every readlane in wave-uniform flow
+                const T g = a[j] / piv;
+                const T f = ln > j ? g : (T)0;
+#pragma unroll
+                for (int k = j + 1; k < MM; ++k) a[k] = fma(-f, rlane(a[k], j), a[k]);
+                br = fma(-f, rlane(br, j), br);
+                bi = fma(-f, rlane(bi, j), bi);
+            }
+            T xr = (T)0, xi = (T)0;
+#pragma unroll
+            for (int j = MM - 1; j >= 0; --j) {  // x_j, then its terms out of the rows above
+                const T d = rlane(a[j], j);
+                const T yr = rlane(br, j) / d, yi = rlane(bi, j) / d;
+                if (ln == j) {
+                    xr = yr;
+                    xi = yi;
+                }
+                const T u = ln < j ? a[j] : (T)0;
+                br = fma(-u, yr, br);
+                bi = fma(-u, yi, bi);
+            }
+            if (ln < M) {
+                V2 o;
+                o.x = xr;
+                o.y = xi;
+                q[ln * N + e] = o;
+            }
+            if (c.keep) {  // the measure of what is stored, as k_rcd_measure sums it
+                double acc = 0.0;
+#pragma unroll
+                for (int m = 0; m < MM; ++m)
+                    if (m < M) acc = acc + rsq2((double)rlane(xr, m), (double)rlane(xi, m));
+                if (e == 0) acc = 0.0;
+                amax = fmax(amax, acc);
+            }
+        }
+        if (c.keep) {  // workgroup-uniform; amax is uniform within each wave
+            if (lane == 0) red[wave] = amax;
+            __syncthreads();
+            if (threadIdx.x == 0) c.anext[b] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+            __syncthreads();  // red is free for the next entry
+        }
+    }
+}
+
 // Wide components (FP32, 16 < M <= 64): the eigen form as two small GEMMs on
 // the matrix cores.  Per chunk of up to 64 modes of a block, B holds the
 // modes' b = q + dt R as 128 real columns (re, im of each mode) over MM
@@ -646,7 +759,6 @@ spdba_status validate(const spdba_rcd_desc *d) {
     const int64_t N = d->dims[0] * d->dims[1] * d->dims[2];
     if (N > (int64_t(1) << 31) || (int64_t)d->M * N > (int64_t(1) << 36)) return SPDBA_EINVAL;
     if (d->M > (d->dtype == SPDBA_F64 ? kMaxMF64 : kMaxMF32)) return SPDBA_EUNSUPPORTED;
-    if ((d->flags & SPDBA_RCD_DIRECT) && d->M > kMaxMDirect) return SPDBA_EUNSUPPORTED;
     return SPDBA_OK;
 }
 
@@ -663,11 +775,24 @@ void launch_update_d(const RCtx &c, int grid, hipStream_t s) {
     }
 }
 // the eigen form: register tiles (FP32 2..16, FP64 2..8) on the vector units,
-// wider tiles (FP64 16; 32, 48; FP32 64) as matrix-core GEMMs
+// wider tiles (FP64 16; 32, 48; FP32 64) as matrix-core GEMMs; the direct
+// form: the factor in registers to tile 8, one wave per mode beyond
 template <typename T>
 void launch_update_t(const RCtx &c, int grid, hipStream_t s) {
-    if (c.direct) {
+    if (c.direct && c.mm <= kMaxMReg) {
         launch_update_d<T, true>(c, grid, s);
+        return;
+    }
+    if (c.direct) {  // wide systems: one wave per mode
+        switch (c.mm) {
+            case 16: hipLaunchKernelGGL((k_rcd_update_direct<T, 16>), dim3(grid), dim3(256), 0, s, c); break;
+            case 32: hipLaunchKernelGGL((k_rcd_update_direct<T, 32>), dim3(grid), dim3(256), 0, s, c); break;
+            case 48: hipLaunchKernelGGL((k_rcd_update_direct<T, 48>), dim3(grid), dim3(256), 0, s, c); break;
+            default:  // tile 64: FP32 only (validated at creation)
+                if constexpr (sizeof(T) == 4)
+                    hipLaunchKernelGGL((k_rcd_update_direct<T, 64>), dim3(grid), dim3(256), 0, s, c);
+                break;
+        }
         return;
     }
     const bool mfma = c.mm >= 32 || (sizeof(T) == 8 && c.mm == 16);

@@ -9,8 +9,10 @@ bound follows the eigen form: two contractions with an orthonormal V of M
 terms each (|V_j| = 1, so each is within (M + 1) u ||b||), one scaling at most
 1, and V rounded to the kernel's precision; the oracle's direct solve is
 within a few u (the system's condition number is below 2 here).  The direct
-form (Cholesky, backward stable with error of order (M + 1) u |L||L^T|, the
-matrix at least I so that ||x|| <= ||b||) meets the same bound.
+form (Cholesky to M = 8, elimination without pivoting beyond; both backward
+stable for a symmetric positive definite matrix, with error of order
+(M + 1) u |L||L^T| against a matrix at least I, so that ||x|| <= ||b||)
+meets the same bound.
 """
 import numpy as np
 import pytest
@@ -86,6 +88,16 @@ CASES = [
     (8, "f32", 3, 32, 8, 0.0, {"direct": True, "dense": True}),
     (5, "f64", 3, 16, 4, 0.05, {"direct": True}),
     (8, "f64", 2, 64, 16, 0.05, {"direct": True}),
+    # wide systems: one wave's elimination per mode (tiles 16, 32, 48, 64)
+    (12, "f32", 3, 16, 4, 0.05, {"direct": True}),
+    (24, "f32", 3, 16, 4, 0.05, {"direct": True}),
+    (33, "f32", 2, 32, 8, 0.05, {"direct": True}),
+    (48, "f32", 3, 16, 4, 0.05, {"direct": True}),
+    (64, "f32", 3, 16, 4, 0.05, {"direct": True}),
+    (48, "f32", 3, 16, 4, 0.0, {"direct": True, "dense": True}),
+    (16, "f64", 2, 64, 8, 0.05, {"direct": True}),
+    (24, "f64", 3, 16, 4, 0.05, {"direct": True}),
+    (48, "f64", 3, 16, 4, 0.05, {"direct": True}),
 ]
 
 
@@ -160,21 +172,22 @@ def test_rcd_field_round_trip():
     plan.destroy()
 
 
-@pytest.mark.parametrize("dtype,M,n,steps,tau", [("f64", 4, 16, 25, 0.02), ("f32", 8, 32, 10, 0.1),
-                                                 ("f32", 24, 16, 25, 0.1), ("f32", 40, 16, 25, 0.1),
-                                                 ("f32", 64, 16, 25, 0.1), ("f64", 24, 16, 25, 0.1)])
-def test_rcd_trajectory_matches_oracle(dtype, M, n, steps, tau):
+@pytest.mark.parametrize("dtype,M,n,steps,tau,direct", [
+    ("f64", 4, 16, 25, 0.02, False), ("f32", 8, 32, 10, 0.1, False), ("f32", 24, 16, 25, 0.1, False),
+    ("f32", 40, 16, 25, 0.1, False), ("f32", 64, 16, 25, 0.1, False), ("f64", 24, 16, 25, 0.1, False),
+    ("f32", 48, 16, 25, 0.1, True), ("f64", 24, 16, 25, 0.1, True)])
+def test_rcd_trajectory_matches_oracle(dtype, M, n, steps, tau, direct):
     """Full steps (transforms, Lotka--Volterra reaction, measure, update) from a
     perturbed homogeneous state: masks of every step agree with the oracle's
     except at near-ties; the final field within the precision's bar."""
     import torch
 
-    print(f"rcd trajectory {dtype} M={M} n={n} steps={steps} tau={tau}", flush=True)
+    print(f"rcd trajectory {dtype} M={M} n={n} steps={steps} tau={tau} direct={direct}", flush=True)
     dims = (n, n, n)
     u0 = inputs.perturbed_components(304, M, dims, OR.equilibrium(M, 1.0, 0.3), 0.1)
     if dtype == "f32":
         u0 = u0.astype(np.float32)
-    plan = rcd.RcdPlan(rcd.make_desc(M, 3, n, 4, dtype=dtype, tau=tau, **P))
+    plan = rcd.RcdPlan(rcd.make_desc(M, 3, n, 4, dtype=dtype, tau=tau, direct=direct, **P))
     plan.set_field(torch.from_numpy(u0.ravel()))
     q0 = np.stack([np.fft.fftn(u0[m].astype(np.float64)).ravel() for m in range(M)])
     ref = OR.step(q0, steps, dims, (4, 4, 4), tau, P["dt"], P["dx"], P["d_diag"], P["d_cross"], 1.0, 0.3,

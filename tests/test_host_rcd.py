@@ -52,7 +52,8 @@ def _bad(**kw):
     ({"flags": 64}, spdba.SPDBA_EINVAL),
     ({"M": 65}, spdba.SPDBA_EUNSUPPORTED),
     ({"M": 49, "dtype": spdba.SPDBA_F64}, spdba.SPDBA_EUNSUPPORTED),
-    ({"M": 9, "flags": 2 | 8}, spdba.SPDBA_EUNSUPPORTED),   # the direct form: M <= 8
+    ({"M": 65, "flags": 2 | 8}, spdba.SPDBA_EUNSUPPORTED),  # the direct form: the same tiles
+    ({"M": 49, "flags": 2 | 8, "dtype": spdba.SPDBA_F64}, spdba.SPDBA_EUNSUPPORTED),
 ])
 def test_invalid_descriptors_rejected_without_device(kw, expect):
     assert rcd.create_status(_bad(**kw)) == expect
