@@ -236,6 +236,22 @@ typedef struct spdba_plan_s *spdba_plan;
 spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, void *stream,
                                spdba_plan *out);
 
+/* Host-only audit of the memory layout a plan for these descriptors would
+ * use; needs no device and allocates no device memory.  It builds the
+ * instance table, the grid groups and the region offsets of the state and
+ * work buffers exactly as spdba_plan_create does, then checks every transform
+ * the plan executes (its input and output span, from the lengths, strides,
+ * distances and batch it is created with) and every device-to-device copy
+ * against the buffer region it is run on: the stored spectra, the work
+ * spectra W and R, the XPFC history slots, the half layout's real slots.  The
+ * half layout's grid-size limit does not apply here.  Not covered: the
+ * transforms' own work area (sized by rocFFT at plan creation) and the
+ * kernels' indexing.  Returns SPDBA_OK when every span fits, SPDBA_EINVAL
+ * with the first violation described in msg (msg_len bytes, NUL-terminated;
+ * msg may be NULL), or the status plan creation would return for invalid or
+ * unsupported descriptors. */
+spdba_status spdba_plan_audit(const spdba_instance_desc *inst, int32_t n_inst, char *msg, size_t msg_len);
+
 /* Device bytes the caller must provide: state (persistent: spectra, FP64 k = 0
  * scalars) and work (scratch: transform buffer, rocFFT work area, indicator,
  * mask, worklist, partial sums).  Both 256-byte aligned sizes. */

@@ -14,9 +14,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <numeric>
+#include <string>
 #include <vector>
 
 using namespace spdba;
@@ -137,7 +140,7 @@ bool has_control(const spdba_instance_desc &x) {
            x.full_steps > 0;
 }
 
-spdba_status validate(const spdba_instance_desc *d, int32_t n, void *) {
+spdba_status validate(const spdba_instance_desc *d, int32_t n, bool half_cap = true) {
     if (!d || n < 1 || n > 65535) return SPDBA_EINVAL;
     for (int i = 0; i < n; ++i) {
         const spdba_instance_desc &x = d[i];
@@ -198,7 +201,7 @@ spdba_status validate(const spdba_instance_desc *d, int32_t n, void *) {
             // Grids above 2^18 points are refused: timed 256^3 runs of this
             // layout ended in device faults whose cause is not yet found, while
             // every grid up to 64^3 / 512^2 passed its parity tests.
-            if (x.dims[0] * x.dims[1] * x.dims[2] > kMaxHalfPoints) return SPDBA_EUNSUPPORTED;
+            if (half_cap && x.dims[0] * x.dims[1] * x.dims[2] > kMaxHalfPoints) return SPDBA_EUNSUPPORTED;
             if (4 * 8 * (x.dims[2] / (2 * x.block[2]) + 1) > kMaxSigBytes) return SPDBA_EUNSUPPORTED;
         }
         // consistency control: schedule and controller parameters
@@ -243,34 +246,84 @@ spdba_status create_fft(spdba_plan p, const InstDev &I, Fft &f, bool forward, bo
     return SPDBA_OK;
 }
 
-// Real-to-complex (forward) or complex-to-real (inverse) plan of the half
-// layout, out of place: the real fields follow each other at nz*ny*nx values
-// (rocFFT's default; its two-dimensional batched complex-to-real plans accept
-// no other distance), the half spectra at N complex values.
-spdba_status create_fft_half(spdba_plan p, const InstDev &I, Fft &f, bool forward, int64_t batch) {
-    const int nd = p->ndim;
-    size_t len[3], rs[3], cs[3];
-    for (int a = 0; a < nd; ++a) len[a] = (size_t)I.n[2 - a];  // fastest first
+// The data layout of a rocFFT transform as the plan is created with it:
+// lengths and strides fastest dimension first, element counts of the input
+// and output sides (a real or a complex element)
+struct FftLayout {
+    int nd = 0;
+    size_t len[3] = {1, 1, 1};
+    size_t is[3] = {1, 1, 1}, os[3] = {1, 1, 1};
+    size_t idist = 0, odist = 0, batch = 0;
+    bool in_real = false, out_real = false;  // real side (half layout) or complex
+    bool in_herm = false, out_herm = false;  // Hermitian side: len[0] / 2 + 1 fastest elements
+};
+
+// elements spanned from the base: the largest offset plus one
+size_t fft_span(const FftLayout &L, bool input) {
+    const size_t *st = input ? L.is : L.os;
+    const bool herm = input ? L.in_herm : L.out_herm;
+    size_t m = (L.batch - 1) * (input ? L.idist : L.odist);
+    for (int a = 0; a < L.nd; ++a) m += ((a == 0 && herm ? L.len[0] / 2 + 1 : L.len[a]) - 1) * st[a];
+    return m + 1;
+}
+
+// Real-to-complex (forward) or complex-to-real (inverse) transforms of the
+// half layout, out of place: the real fields follow each other at nz*ny*nx
+// values (rocFFT's default; its two-dimensional batched complex-to-real plans
+// accept no other distance), the half spectra at N complex values with rows
+// of pitch xs.
+FftLayout half_fft_layout(const spdba_plan p, const InstDev &I, bool forward, int64_t batch) {
+    FftLayout L;
+    L.nd = p->ndim;
+    size_t rs[3], cs[3];
+    for (int a = 0; a < L.nd; ++a) L.len[a] = (size_t)I.n[2 - a];  // fastest first
     rs[0] = cs[0] = 1;
-    for (int a = 1; a < nd; ++a) {
-        rs[a] = rs[a - 1] * len[a - 1];
-        cs[a] = cs[a - 1] * (a == 1 ? (size_t)I.xs : len[a - 1]);
+    for (int a = 1; a < L.nd; ++a) {
+        rs[a] = rs[a - 1] * L.len[a - 1];
+        cs[a] = cs[a - 1] * (a == 1 ? (size_t)I.xs : L.len[a - 1]);
     }
     const size_t rdist = (size_t)I.Nreal, cdist = (size_t)I.N;
+    for (int a = 0; a < 3; ++a) {
+        L.is[a] = forward ? rs[a] : cs[a];
+        L.os[a] = forward ? cs[a] : rs[a];
+    }
+    L.idist = forward ? rdist : cdist;
+    L.odist = forward ? cdist : rdist;
+    L.batch = (size_t)batch;
+    L.in_real = forward;
+    L.out_real = !forward;
+    L.in_herm = !forward;
+    L.out_herm = forward;
+    return L;
+}
+
+// The full layout's complex transforms: rocFFT's default packed layout
+FftLayout full_fft_layout(const spdba_plan p, const InstDev &I, int64_t batch) {
+    FftLayout L;
+    L.nd = p->ndim;
+    for (int a = 0; a < L.nd; ++a) L.len[a] = (size_t)I.n[2 - a];
+    for (int a = 1; a < L.nd; ++a) L.is[a] = L.os[a] = L.is[a - 1] * L.len[a - 1];
+    L.idist = L.odist = (size_t)I.N;
+    L.batch = (size_t)batch;
+    return L;
+}
+
+spdba_status create_fft_half(spdba_plan p, const InstDev &I, Fft &f, bool forward, int64_t batch) {
+    const FftLayout L = half_fft_layout(p, I, forward, batch);
+    size_t is[3], os[3];
+    std::copy(L.is, L.is + 3, is);
+    std::copy(L.os, L.os + 3, os);
     rocfft_plan_description desc = nullptr;
     if (rocfft_plan_description_create(&desc) != rocfft_status_success) return SPDBA_EFFT;
-    rocfft_status st =
-        forward ? rocfft_plan_description_set_data_layout(desc, rocfft_array_type_real,
-                                                          rocfft_array_type_hermitian_interleaved, nullptr,
-                                                          nullptr, (size_t)nd, rs, rdist, (size_t)nd, cs, cdist)
-                : rocfft_plan_description_set_data_layout(desc, rocfft_array_type_hermitian_interleaved,
-                                                          rocfft_array_type_real, nullptr, nullptr, (size_t)nd,
-                                                          cs, cdist, (size_t)nd, rs, rdist);
+    const rocfft_array_type ti = forward ? rocfft_array_type_real : rocfft_array_type_hermitian_interleaved;
+    const rocfft_array_type to = forward ? rocfft_array_type_hermitian_interleaved : rocfft_array_type_real;
+    rocfft_status st = rocfft_plan_description_set_data_layout(desc, ti, to, nullptr, nullptr, (size_t)L.nd, is,
+                                                               L.idist, (size_t)L.nd, os, L.odist);
     if (st == rocfft_status_success)
         st = rocfft_plan_create(&f.plan, rocfft_placement_notinplace,
                                 forward ? rocfft_transform_type_real_forward : rocfft_transform_type_real_inverse,
-                                p->dbl ? rocfft_precision_double : rocfft_precision_single, (size_t)nd, len,
-                                (size_t)batch, desc);
+                                p->dbl ? rocfft_precision_double : rocfft_precision_single, (size_t)L.nd, L.len,
+                                L.batch, desc);
     rocfft_plan_description_destroy(desc);
     if (st != rocfft_status_success) return SPDBA_EFFT;
     size_t wb = 0;
@@ -594,7 +647,7 @@ void fill_inst(const spdba_instance_desc &x, int op, bool dbl, bool pin, bool ha
     I.deadband = x.deadband;
 }
 
-spdba_status validate_desc(const spdba_instance_desc *d, int32_t n) { return validate(d, n, nullptr); }
+spdba_status validate_desc(const spdba_instance_desc *d, int32_t n) { return validate(d, n); }
 
 const Ctx *plan_ctx(spdba_plan p) { return p && p->bound ? &p->ctx : nullptr; }
 const InstDev *plan_hinst(spdba_plan p, int *n_inst, int64_t *nb_total) {
@@ -605,35 +658,11 @@ const InstDev *plan_hinst(spdba_plan p, int *n_inst, int64_t *nb_total) {
 }
 }  // namespace spdba
 
-extern "C" {
+namespace {
 
-const char *spdba_status_string(spdba_status s) {
-    switch (s) {
-        case SPDBA_OK: return "success";
-        case SPDBA_EINVAL: return "invalid argument";
-        case SPDBA_EUNSUPPORTED: return "unsupported combination";
-        case SPDBA_ESTATE: return "call out of order";
-        case SPDBA_EDEVICE: return "HIP runtime error";
-        case SPDBA_EFFT: return "rocFFT error";
-        case SPDBA_ENONFINITE: return "non-finite indicator value";
-        default: return "unknown status";
-    }
-}
-
-spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, void *stream,
-                               spdba_plan *out) {
-    if (!out) return SPDBA_EINVAL;
-    *out = nullptr;
-    TRY(validate(inst, n_inst, stream));
-    // everything below needs a device
-    int dev = 0;
-    TRY_HIP(hipGetDevice(&dev));
-    hipDeviceProp_t prop;
-    TRY_HIP(hipGetDeviceProperties(&prop, dev));
-    if (spdba::fft_setup() != SPDBA_OK) return SPDBA_EFFT;
-
-    spdba_plan p = new (std::nothrow) spdba_plan_s();
-    if (!p) return SPDBA_EDEVICE;
+// Everything of a plan that needs no device: the instance table, the grid
+// groups and block counts, the per-instance tables (XPFC L, NLSE H)
+spdba_status build_layout(spdba_plan p, const spdba_instance_desc *inst, int32_t n_inst) {
     p->desc.assign(inst, inst + n_inst);
     p->n_inst = n_inst;
     p->op = inst[0].op;
@@ -647,9 +676,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     p->half = (inst[0].flags & SPDBA_FLAG_HALF_SPECTRUM) != 0;
     for (int i = 0; i < n_inst; ++i) p->ctl = p->ctl || has_control(inst[i]);
     p->nspec = p->op == OP_GS ? 2 : 1;
-    p->stream = reinterpret_cast<hipStream_t>(stream);
     p->esize = p->dbl ? 16 : 8;
-    p->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     const int V = p->dbl ? 1 : 2;
     const int64_t TE = p->dbl ? 512 : 1024;
 
@@ -762,49 +789,19 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     p->n_chunks = (blk + CHUNK_BLOCKS - 1) / CHUNK_BLOCKS;
     // list entries hold a block id (transition plans: 25 bits beside the
     // face bits)
-    if (blk > 0xFFFFFFFFll || (p->trans && blk > (int64_t)kEntryId)) {
-        delete p;
-        return SPDBA_EUNSUPPORTED;
-    }
+    if (blk > 0xFFFFFFFFll || (p->trans && blk > (int64_t)kEntryId)) return SPDBA_EUNSUPPORTED;
     p->blk_inst.resize(blk);
     for (int i = 0; i < n_inst; ++i)
         for (int64_t b = 0; b < p->hinst[i].nb; ++b) p->blk_inst[p->hinst[i].blk_off + b] = (uint16_t)i;
 
-    // rocFFT plans, one set per grid size
-    spdba_status st = SPDBA_OK;
-    for (auto &g : p->groups) {
-        int rep = -1;
-        for (int i = 0; i < n_inst; ++i)
-            if (p->group_of[i] == (int)(&g - &p->groups[0])) { rep = i; break; }
-        const InstDev &I = p->hinst[rep];
-        const int64_t batch = (int64_t)g.count * p->nspec;
-        if (p->op == OP_NLSE) {
-            if ((st = create_fft(p, I, g.fwd_ip, true, true, batch))) break;
-            if ((st = create_fft(p, I, g.inv_ip, false, true, batch))) break;
-        } else if (p->half) {
-            if ((st = create_fft_half(p, I, g.inv_oop, false, batch))) break;
-            if ((st = create_fft_half(p, I, g.fwd_oop, true, batch))) break;
-            if ((st = create_fft_half(p, I, g.inv1_oop, false, p->nspec))) break;
-            if ((st = create_fft_half(p, I, g.fwd1_oop, true, p->nspec))) break;
-        } else {
-            if ((st = create_fft(p, I, g.inv_oop, false, false, batch))) break;
-            if ((st = create_fft(p, I, g.fwd_oop, true, false, batch))) break;
-            if ((st = create_fft(p, I, g.inv_ip, false, true, batch))) break;
-            if ((st = create_fft(p, I, g.inv1_oop, false, false, p->nspec))) break;
-            if ((st = create_fft(p, I, g.fwd1_ip, true, true, p->nspec))) break;
-            if ((st = create_fft(p, I, g.inv1_ip, false, true, p->nspec))) break;
-        }
-    }
-    if (st == SPDBA_OK && rocfft_execution_info_create(&p->info) != rocfft_status_success)
-        st = SPDBA_EFFT;
-    if (st == SPDBA_OK && p->stream &&
-        rocfft_execution_info_set_stream(p->info, p->stream) != rocfft_status_success)
-        st = SPDBA_EFFT;
-    if (st != SPDBA_OK) {
-        spdba_destroy(p);
-        return st;
-    }
+    return SPDBA_OK;
+}
 
+// Region offsets of the state and work buffers (after the transforms' work
+// size is known)
+void build_buffers(spdba_plan p) {
+    const int64_t blk = p->nb_total, tile = p->n_tiles, strip = p->n_strips;
+    const int n_inst = p->n_inst;
     // buffer layout
     size_t o = 0;
     p->st_spec = o;
@@ -845,8 +842,192 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
     p->w_ltab = take(std::max<size_t>(p->ltab.size() * sizeof(double), 8));
     p->w_probe = take(8);
     p->work_bytes = o;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *spdba_status_string(spdba_status s) {
+    switch (s) {
+        case SPDBA_OK: return "success";
+        case SPDBA_EINVAL: return "invalid argument";
+        case SPDBA_EUNSUPPORTED: return "unsupported combination";
+        case SPDBA_ESTATE: return "call out of order";
+        case SPDBA_EDEVICE: return "HIP runtime error";
+        case SPDBA_EFFT: return "rocFFT error";
+        case SPDBA_ENONFINITE: return "non-finite indicator value";
+        default: return "unknown status";
+    }
+}
+
+spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, void *stream,
+                               spdba_plan *out) {
+    if (!out) return SPDBA_EINVAL;
+    *out = nullptr;
+    TRY(validate(inst, n_inst));
+    // everything below needs a device
+    int dev = 0;
+    TRY_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    TRY_HIP(hipGetDeviceProperties(&prop, dev));
+    if (spdba::fft_setup() != SPDBA_OK) return SPDBA_EFFT;
+
+    spdba_plan p = new (std::nothrow) spdba_plan_s();
+    if (!p) return SPDBA_EDEVICE;
+    p->stream = reinterpret_cast<hipStream_t>(stream);
+    p->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    if (spdba_status ls = build_layout(p, inst, n_inst)) {
+        delete p;
+        return ls;
+    }
+
+    // rocFFT plans, one set per grid size
+    spdba_status st = SPDBA_OK;
+    for (auto &g : p->groups) {
+        int rep = -1;
+        for (int i = 0; i < n_inst; ++i)
+            if (p->group_of[i] == (int)(&g - &p->groups[0])) { rep = i; break; }
+        const InstDev &I = p->hinst[rep];
+        const int64_t batch = (int64_t)g.count * p->nspec;
+        if (p->op == OP_NLSE) {
+            if ((st = create_fft(p, I, g.fwd_ip, true, true, batch))) break;
+            if ((st = create_fft(p, I, g.inv_ip, false, true, batch))) break;
+        } else if (p->half) {
+            if ((st = create_fft_half(p, I, g.inv_oop, false, batch))) break;
+            if ((st = create_fft_half(p, I, g.fwd_oop, true, batch))) break;
+            if ((st = create_fft_half(p, I, g.inv1_oop, false, p->nspec))) break;
+            if ((st = create_fft_half(p, I, g.fwd1_oop, true, p->nspec))) break;
+        } else {
+            if ((st = create_fft(p, I, g.inv_oop, false, false, batch))) break;
+            if ((st = create_fft(p, I, g.fwd_oop, true, false, batch))) break;
+            if ((st = create_fft(p, I, g.inv_ip, false, true, batch))) break;
+            if ((st = create_fft(p, I, g.inv1_oop, false, false, p->nspec))) break;
+            if ((st = create_fft(p, I, g.fwd1_ip, true, true, p->nspec))) break;
+            if ((st = create_fft(p, I, g.inv1_ip, false, true, p->nspec))) break;
+        }
+    }
+    if (st == SPDBA_OK && rocfft_execution_info_create(&p->info) != rocfft_status_success)
+        st = SPDBA_EFFT;
+    if (st == SPDBA_OK && p->stream &&
+        rocfft_execution_info_set_stream(p->info, p->stream) != rocfft_status_success)
+        st = SPDBA_EFFT;
+    if (st != SPDBA_OK) {
+        spdba_destroy(p);
+        return st;
+    }
+
+    build_buffers(p);
     *out = p;
     return SPDBA_OK;
+}
+
+spdba_status spdba_plan_audit(const spdba_instance_desc *inst, int32_t n_inst, char *msg, size_t msg_len) {
+    if (msg && msg_len) msg[0] = 0;
+    // the half layout's grid cap does not apply: the audit is how larger
+    // grids are examined without a device
+    TRY(validate(inst, n_inst, false));
+    std::unique_ptr<spdba_plan_s> hold(new (std::nothrow) spdba_plan_s());
+    spdba_plan p = hold.get();
+    if (!p) return SPDBA_EDEVICE;
+    TRY(build_layout(p, inst, n_inst));
+    build_buffers(p);  // the transforms' own work area (sized by rocFFT) is not part of the audit
+    // buffer bases: the pointers below are compared, never dereferenced
+    char *const S = reinterpret_cast<char *>(uintptr_t(1) << 44);
+    char *const Wk = reinterpret_cast<char *>(uintptr_t(1) << 45);
+    p->d_state = S;
+    p->d_work = Wk;
+    const size_t esz = (size_t)p->esize, rsz = esz / 2, spec = (size_t)p->total_elems * esz;
+    struct Region {
+        const char *name;
+        const char *lo;
+        size_t bytes;
+    };
+    const Region st{"state spectra", S + p->st_spec, spec}, W{"work W", Wk + p->w_W, spec},
+        R{"work R", Wk + p->w_R, spec};
+    std::vector<Region> hist;
+    if (p->op == OP_XPFC)
+        for (int k = 0; k < 4; ++k) hist.push_back(Region{"history slot", S + p->st_hist + k * spec, spec});
+    bool ok = true;
+    auto fail = [&](const std::string &what) {
+        if (ok && msg && msg_len) std::snprintf(msg, msg_len, "%s", what.c_str());
+        ok = false;
+    };
+    auto inside = [&](const std::string &what, const char *ptr, size_t bytes, const Region &r) {
+        if (ptr < r.lo || ptr + bytes > r.lo + r.bytes)
+            fail(what + ": " + std::to_string(bytes) + " bytes at offset " + std::to_string(ptr - r.lo) + " of " +
+                 r.name + " (" + std::to_string(r.bytes) + " bytes)");
+    };
+    // a transform: input and output spans against their regions
+    auto fft = [&](const std::string &what, const FftLayout &L, const char *in, const Region &ri, const char *out,
+                   const Region &ro) {
+        inside(what + " input", in, fft_span(L, true) * (L.in_real ? rsz : esz), ri);
+        inside(what + " output", out ? out : in, fft_span(L, false) * (L.out_real ? rsz : esz), out ? ro : ri);
+    };
+    if (p->state_bytes < (size_t)p->st_spec + spec || p->work_bytes < (size_t)p->w_R + spec)
+        fail("buffer sizes below their regions");
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        const Group &g = p->groups[gi];
+        int rep = -1;
+        for (int i = 0; i < n_inst; ++i)
+            if (p->group_of[i] == (int)gi) { rep = i; break; }
+        const InstDev &I = p->hinst[rep];
+        const int64_t batch = (int64_t)g.count * p->nspec, ng = g.N * batch;
+        const std::string gs = "group " + std::to_string(gi);
+        if (p->op == OP_NLSE) {  // in place on the state
+            const FftLayout L = full_fft_layout(p, I, batch);
+            fft(gs + " forward", L, state_ptr(p, g.off), st, nullptr, st);
+            continue;
+        }
+        if (p->half) {
+            const FftLayout inv = half_fft_layout(p, I, false, batch), fwd = half_fft_layout(p, I, true, batch);
+            // step: inverse from the state or from its copy in R, into W's real slots
+            inside(gs + " inverse copy source", state_ptr(p, g.off), (size_t)ng * esz, st);
+            inside(gs + " inverse copy target", rhs_ptr(p, g.off), (size_t)ng * esz, R);
+            fft(gs + " inverse", inv, state_ptr(p, g.off), st, wreal_ptr(p, 2 * g.off), W);
+            fft(gs + " inverse (from the copy)", inv, rhs_ptr(p, g.off), R, wreal_ptr(p, 2 * g.off), W);
+            fft(gs + " forward", fwd, work_ptr(p, g.off), W, rhs_ptr(p, g.off), R);
+            fft(gs + " preservation probe", inv, state_ptr(p, g.off), st, work_ptr(p, g.off), W);
+            const FftLayout inv1 = half_fft_layout(p, I, false, p->nspec), fwd1 = half_fft_layout(p, I, true, p->nspec);
+            for (int i = 0; i < n_inst; ++i) {
+                if (p->group_of[i] != (int)gi) continue;
+                const InstDev &J = p->hinst[i];
+                const std::string is = "instance " + std::to_string(i);
+                const size_t nr = (size_t)J.Nreal * p->nspec;
+                inside(is + " real slots", wreal_ptr(p, J.roff), nr * rsz, W);
+                // the real slots of the batch lie in order inside the group's transform span
+                if (J.roff < 2 * g.off || J.roff + (int64_t)nr > 2 * g.off + (int64_t)(batch * J.Nreal))
+                    fail(is + " real slots outside the batch transform's span");
+                fft(is + " field in", fwd1, wreal_ptr(p, J.roff), W, rhs_ptr(p, J.off), R);
+                inside(is + " field out copy", rhs_ptr(p, J.off), (size_t)J.N * p->nspec * esz, R);
+                fft(is + " field out", inv1, rhs_ptr(p, J.off), R, wreal_ptr(p, J.roff), W);
+            }
+            fft(gs + " preservation probe (one instance)", inv1, state_ptr(p, g.off), st, work_ptr(p, g.off), W);
+            continue;
+        }
+        const FftLayout L = full_fft_layout(p, I, batch), L1 = full_fft_layout(p, I, p->nspec);
+        fft(gs + " inverse", L, state_ptr(p, g.off), st, work_ptr(p, g.off), W);
+        inside(gs + " inverse copy", work_ptr(p, g.off), (size_t)ng * esz, W);
+        fft(gs + " inverse in place", L, work_ptr(p, g.off), W, nullptr, W);
+        if (p->op == OP_XPFC) {
+            for (int k = 0; k < 4; ++k) fft(gs + " forward", L, work_ptr(p, g.off), W, hist_ptr(p, k, g.off), hist[k]);
+        } else {
+            fft(gs + " forward", L, work_ptr(p, g.off), W, rhs_ptr(p, g.off), R);
+        }
+        for (int i = 0; i < n_inst; ++i) {
+            if (p->group_of[i] != (int)gi) continue;
+            const InstDev &J = p->hinst[i];
+            const std::string is = "instance " + std::to_string(i);
+            fft(is + " field in", L1, work_ptr(p, J.off), W, nullptr, W);
+            fft(is + " field out", L1, state_ptr(p, J.off), st, work_ptr(p, J.off), W);
+        }
+    }
+    // instances: stored spectra disjoint and in order
+    for (int i = 0; i < n_inst; ++i) {
+        const InstDev &J = p->hinst[i];
+        inside("instance " + std::to_string(i) + " spectrum", state_ptr(p, J.off), (size_t)J.N * p->nspec * esz, st);
+    }
+    return ok ? SPDBA_OK : SPDBA_EINVAL;
 }
 
 spdba_status spdba_plan_buffer_sizes(spdba_plan p, size_t *state_bytes, size_t *work_bytes) {

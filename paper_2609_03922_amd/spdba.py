@@ -36,7 +36,7 @@ EXPORTS = (
     "spdba_get_field", "spdba_set_spectrum", "spdba_get_spectrum", "spdba_step", "spdba_apply",
     "spdba_set_skip", "spdba_active_mask", "spdba_indicator", "spdba_worklist",
     "spdba_device_views", "spdba_stats", "spdba_set_launch", "spdba_destroy",
-    "spdba_status_string", "spdba_apply_noalloc",
+    "spdba_status_string", "spdba_apply_noalloc", "spdba_plan_audit",
 )
 # entry points of include/spdba_proposer.h
 PROPOSER_EXPORTS = (
@@ -140,6 +140,7 @@ def load():
         "spdba_proposer_miss": [P, P, I64, P, P],
         "spdba_set_block_energy": [P, P],
         "spdba_apply_noalloc": [ctypes.POINTER(InstanceDesc), P, P, P, P, P, P],
+        "spdba_plan_audit": [ctypes.POINTER(InstanceDesc), I32, ctypes.c_char_p, SZ],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -158,6 +159,15 @@ def spdba_apply_noalloc(desc, state, rhs, k0=None, rhs_k0=None, mask=None, strea
     ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
     sp = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
     return load().spdba_apply_noalloc(arr, ptr(state), ptr(rhs), ptr(k0), ptr(rhs_k0), ptr(mask), sp)
+
+
+def plan_audit(descs) -> tuple:
+    """The host-only layout audit (include/spdba.h): (status, message); no
+    device is needed."""
+    arr = descs_array(list(descs))
+    buf = ctypes.create_string_buffer(512)
+    st = load().spdba_plan_audit(arr, len(descs), buf, len(buf))
+    return st, buf.value.decode()
 
 
 def status_string(s: int) -> str:
