@@ -136,5 +136,9 @@ MDBP1D_262144_M32_F32 = dict(
 # recovered field stays within err_bar of it
 MDBP1D_262144_M64_F32 = dict(MDBP1D_262144_M32_F32, name="mdbp1d_262144_m64_f32", M=64, err_bar=1e-3)
 
-MDBP = [MDBP1D_262144_M32_F32, MDBP1D_262144_M64_F32]
+# the printed peak-power parameter P0 = 1000, run to measure what it does to
+# the activity (every other parameter as above)
+MDBP1D_262144_M32_F32_P1000 = dict(MDBP1D_262144_M32_F32, name="mdbp1d_262144_m32_f32_p1000", P0=1000.0)
+
+MDBP = [MDBP1D_262144_M32_F32, MDBP1D_262144_M64_F32, MDBP1D_262144_M32_F32_P1000]
 BY_NAME = {c["name"]: c for c in ALL + RCD + MDBP}

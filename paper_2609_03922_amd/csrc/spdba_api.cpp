@@ -372,8 +372,7 @@ spdba_status fill_history(spdba_plan p) {
     if (p->op != OP_XPFC || p->hist_valid) return SPDBA_OK;
     const size_t bytes = (size_t)p->total_elems * p->esize;
     for (int k = 1; k < 4; ++k)
-        TRY_HIP(hipMemcpyAsync(hist_ptr(p, (p->xphase + k) & 3, 0), hist_ptr(p, p->xphase, 0), bytes,
-                               hipMemcpyDeviceToDevice, p->stream));
+        TRY_HIP(launch_copy8(hist_ptr(p, p->xphase, 0), hist_ptr(p, (p->xphase + k) & 3, 0), bytes, p->stream));
     return SPDBA_OK;
 }
 void drop_graphs(spdba_plan p) {
@@ -389,8 +388,7 @@ char *wreal_ptr(spdba_plan p, int64_t real_off) { return p->d_work + p->w_W + re
 // inverse transform of a state region into the work buffer, keeping the state
 spdba_status inverse_keep(spdba_plan p, const Fft &oop, const Fft &ip, int64_t off, int64_t n_elems) {
     if (oop.preserves) return exec_fft(p, oop, state_ptr(p, off), work_ptr(p, off));
-    TRY_HIP(hipMemcpyAsync(work_ptr(p, off), state_ptr(p, off), (size_t)n_elems * p->esize,
-                           hipMemcpyDeviceToDevice, p->stream));
+    TRY_HIP(launch_copy8(state_ptr(p, off), work_ptr(p, off), (size_t)n_elems * p->esize, p->stream));
     return exec_fft(p, ip, work_ptr(p, off), nullptr);
 }
 
@@ -398,8 +396,7 @@ spdba_status inverse_keep(spdba_plan p, const Fft &oop, const Fft &ip, int64_t o
 // the state (through a copy in R when the plan overwrites its input)
 spdba_status inverse_half(spdba_plan p, const Fft &oop, int64_t off, int64_t roff, int64_t n_elems) {
     if (oop.preserves) return exec_fft(p, oop, state_ptr(p, off), wreal_ptr(p, roff));
-    TRY_HIP(hipMemcpyAsync(rhs_ptr(p, off), state_ptr(p, off), (size_t)n_elems * p->esize,
-                           hipMemcpyDeviceToDevice, p->stream));
+    TRY_HIP(launch_copy8(state_ptr(p, off), rhs_ptr(p, off), (size_t)n_elems * p->esize, p->stream));
     return exec_fft(p, oop, rhs_ptr(p, off), wreal_ptr(p, roff));
 }
 

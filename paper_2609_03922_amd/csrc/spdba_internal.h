@@ -182,6 +182,8 @@ hipError_t launch_copy_half(const Ctx &c, bool dbl, int inst, const void *src, v
                             int zero_slot0, double *k0_dst, hipStream_t s);
 // probe helpers
 hipError_t launch_fill_pattern(void *buf, int64_t n_elems, bool dbl, hipStream_t s);
+// bytes a multiple of 8, both pointers 8-byte aligned
+hipError_t launch_copy8(const void *src, void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_check_pattern(const void *buf, int64_t n_elems, bool dbl, uint32_t *bad, hipStream_t s);
 
 // rocFFT's library set-up, once per process (spdba_api.cpp)

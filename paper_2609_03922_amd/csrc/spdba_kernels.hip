@@ -2372,6 +2372,13 @@ __global__ void k_scale_copy(int64_t n, const T *src, T *dst, T scale) {
         dst[i] = src[i] * scale;
 }
 
+// device-to-device copy in 8-byte words (a kernel node, not a copy node, when
+// a step is captured into a graph)
+__global__ void k_copy8(const unsigned long long *src, unsigned long long *dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 template <typename T>
 __global__ void k_fill_pattern(T *buf, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * n;
@@ -3227,6 +3234,13 @@ hipError_t launch_copy_half(const Ctx &c, bool dbl, int inst, const void *src, v
     const unsigned g = 4096;
     if (dbl) hipLaunchKernelGGL(k_copy_half<double>, dim3(g), dim3(256), 0, s, c, inst, (const double *)src, (double *)dst, to_pitched ? 1 : 0, zero_slot0, k0_dst);
     else hipLaunchKernelGGL(k_copy_half<float>, dim3(g), dim3(256), 0, s, c, inst, (const float *)src, (float *)dst, to_pitched ? 1 : 0, zero_slot0, k0_dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy8(const void *src, void *dst, size_t bytes, hipStream_t s) {
+    const int64_t n = (int64_t)(bytes / 8);
+    hipLaunchKernelGGL(k_copy8, dim3(grid_for(n)), dim3(256), 0, s, (const unsigned long long *)src,
+                       (unsigned long long *)dst, n);
     return hipGetLastError();
 }
 
