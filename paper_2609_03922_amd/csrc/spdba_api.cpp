@@ -1100,6 +1100,9 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     c.half_nb = 0;
     for (const InstDev &I : p->hinst) c.half_nb = std::max(c.half_nb, I.nbxm + 1);
     for (const InstDev &I : p->hinst) c.wave_ind = c.wave_ind && I.chunks > 1;
+    // the workgroup walk serves blocks of at most 128 (64) slots two (four)
+    // at a time, so that its 256 threads are busy
+    c.upd_group = p->max_slots <= 64 ? 4 : p->max_slots <= 128 ? 2 : 1;
     c.sig_bytes = (int32_t)(p->n_taper * sizeof(double));
     c.taper_bs = 0;
     for (const InstDev &I : p->hinst)

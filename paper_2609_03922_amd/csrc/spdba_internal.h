@@ -130,6 +130,8 @@ struct Ctx {
     int32_t ab_sum;            // state measure: a_b is the block's sum (block energy), not its maximum
     int32_t run_lmax;          // run walk: longest piece in blocks (power of two), 0 = not available
     int32_t run_ub;            // run walk: 16-byte loads per lane and array (slots per block / 64)
+    int32_t upd_group;         // workgroup walk: list entries per iteration (1, 2, 4; blocks of at
+                               // most 256 / upd_group slots); 0 = 1
     int64_t nb_total;
     int64_t n_strips;
     int64_t n_tiles;

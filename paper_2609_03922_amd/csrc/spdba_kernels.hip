@@ -1369,9 +1369,15 @@ __global__ void __launch_bounds__(256) k_tapers(Ctx c, double *w) {
 // block's next measure (a_next) from the state it stores, so the next step
 // needs no pass over the frozen blocks (their state, and so their a_b, is
 // unchanged); a_b itself keeps the values that decided this update.
+// The block is served by `nthr` threads of the workgroup (tid = 0 .. nthr - 1,
+// whole waves): a workgroup takes several small blocks at once.  `valid` is
+// false for a group without an entry in this iteration; it still takes part
+// in the workgroup's barriers.
 template <typename T, int OP, bool TR>
-__device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, double *sig, double *red) {
+__device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, bool valid, double *sig, double *red,
+                                             int tid, int nthr) {
     // TR: entries carry the transition flag and the frozen-face bits
+    if (!valid) entry = 0u;  // geometry of block 0, no slot is touched
     const int64_t gb = TR ? (int64_t)(entry & kEntryId) : (int64_t)entry;
     constexpr int V = CV<T>::V;
     const int ii = c.blk_inst[gb];
@@ -1402,7 +1408,7 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
     const bool ab = OP != OP_NLSE && c.ab_inc;  // workgroup-uniform
     const bool esum = c.ab_sum;                  // block energy: the sum, else the maximum
     double amax = 0.0;
-    for (int s = threadIdx.x; s < slots; s += blockDim.x) {
+    for (int s = tid; valid && s < slots; s += nthr) {
         const int r = s >> llpr, l = s & ((1 << llpr) - 1);
         const int z = g.z0 + (r >> g.lb1);
         const int y = g.y0 + (r & g.b1m);
@@ -1482,18 +1488,19 @@ __device__ __forceinline__ void update_block(const Ctx &c, uint32_t entry, doubl
         CV<T>::st(q0p + 2 * e, qr, qi);
         if (OP == OP_GS) CV<T>::st(q1p + 2 * e, q2r, q2i);
     }
-    if (ab) {  // block energy: lanes, then waves in order
+    if (ab) {  // block energy: lanes, then the group's waves in order
         amax = esum ? wave_sum(amax) : wave_max(amax);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double m = red[0];
-            for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = esum ? m + red[k] : fmax(m, red[k]);
+        if (valid && tid == 0) {
+            const int w0 = threadIdx.x >> 6, nw = nthr >> 6;
+            double m = red[w0];
+            for (int k = 1; k < nw; ++k) m = esum ? m + red[w0 + k] : fmax(m, red[w0 + k]);
             c.a_next[gb] = m;
         }
         __syncthreads();  // red is free for the next block
     }
-    if (k0_blk && threadIdx.x == 0) {
+    if (valid && k0_blk && tid == 0) {
         double tmp[2];
         k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
         if (TR && trn) {  // block 0 in transition: the weighted increment in FP64
@@ -1535,7 +1542,16 @@ __global__ void __launch_bounds__(256) k_update(Ctx c) {
     const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per = P >> 3;
     const uint32_t seg = (total + 7) / 8;
     const uint32_t lo = min(total, seg * xcd), hi = min(total, seg * (xcd + 1));
-    for (uint32_t e = lo + local; e < hi; e += per) update_block<T, OP, TR>(c, c.worklist[e], sig, red);
+    // G consecutive entries per iteration (x-adjacent blocks of one block
+    // row), one group of blockDim / G threads each; entry lo + G m + sub goes
+    // to workgroup m mod per, so every entry of the segment is taken once
+    const int G = c.upd_group > 1 ? c.upd_group : 1;
+    const int nthr = (int)blockDim.x / G, sub = (int)threadIdx.x / nthr, tid = (int)threadIdx.x - sub * nthr;
+    for (uint32_t e = lo + (uint32_t)(local * G); e < hi; e += (uint32_t)(per * G)) {  // workgroup-uniform
+        const uint32_t my = e + (uint32_t)sub;
+        const bool valid = my < hi;
+        update_block<T, OP, TR>(c, valid ? c.worklist[my] : 0u, valid, sig, red, tid, nthr);
+    }
 }
 
 // several list entries per workgroup iteration: all their loads are issued

@@ -98,6 +98,12 @@ CASES = [
     (16, "f64", 2, 64, 8, 0.05, {"direct": True}),
     (24, "f64", 3, 16, 4, 0.05, {"direct": True}),
     (48, "f64", 3, 16, 4, 0.05, {"direct": True}),
+    # tile edges of the wave form: identity rows from lane M on (17 in tile
+    # 32, 49 in tile 64), a full tile (32), one row short of it (31, FP64)
+    (17, "f32", 3, 16, 4, 0.05, {"direct": True}),
+    (32, "f32", 2, 32, 8, 0.05, {"direct": True}),
+    (49, "f32", 3, 16, 4, 0.05, {"direct": True}),
+    (31, "f64", 3, 16, 4, 0.05, {"direct": True, "pin_k0": False}),
 ]
 
 
@@ -128,12 +134,13 @@ def test_rcd_apply_matches_oracle(case):
     plan.destroy()
 
 
-def test_rcd_no_active_block_leaves_state_unchanged():
+@pytest.mark.parametrize("M,direct", [(4, False), (4, True), (24, True)])
+def test_rcd_no_active_block_leaves_state_unchanged(M, direct):
     import torch
 
-    M, dims = 4, (32, 32, 32)
+    dims = (32, 32, 32)
     q, r = draw(301, M, dims, "f32")
-    plan = rcd.RcdPlan(rcd.make_desc(M, 3, 32, 8, tau=2.0, pin_k0=False, **P))  # tau^2 G > every a_b
+    plan = rcd.RcdPlan(rcd.make_desc(M, 3, 32, 8, tau=2.0, pin_k0=False, direct=direct, **P))  # tau^2 G > every a_b
     plan.set_spectrum(torch.from_numpy(q.ravel()))
     plan.apply(torch.from_numpy(r.ravel()))
     mask, count = plan.active_mask()
@@ -252,19 +259,21 @@ def test_rcd_full_size_sampled():
     assert np.all(ratio <= tol_of(M, "f32")), float(ratio.max())
 
 
-@pytest.mark.parametrize("M,dtype,ndim,n,bl,tau", [(8, "f32", 3, 32, 8, 0.03), (4, "f64", 2, 64, 8, 0.05),
-                                                   (16, "f32", 2, 64, 16, 0.05), (48, "f32", 3, 16, 4, 0.05)])
-def test_rcd_kept_measure_over_a_sequence(M, dtype, ndim, n, bl, tau):
+@pytest.mark.parametrize("M,dtype,ndim,n,bl,tau,direct", [
+    (8, "f32", 3, 32, 8, 0.03, False), (4, "f64", 2, 64, 8, 0.05, False), (16, "f32", 2, 64, 16, 0.05, False),
+    (48, "f32", 3, 16, 4, 0.05, False), (8, "f32", 3, 32, 8, 0.03, True), (48, "f32", 3, 16, 4, 0.05, True),
+    (24, "f64", 3, 16, 4, 0.05, True)])
+def test_rcd_kept_measure_over_a_sequence(M, dtype, ndim, n, bl, tau, direct):
     """From the second update on, the measure is the one the last update kept
     for the blocks it stored (frozen blocks unchanged): before every update the
     oracle gets the GPU's current state, and a_b, G, mask and count agree bit
     for bit; a reload in the middle forces a full pass."""
     import torch
 
-    print(f"rcd kept-measure sequence M={M} {dtype} {ndim}-D n={n}", flush=True)
+    print(f"rcd kept-measure sequence M={M} {dtype} {ndim}-D n={n} direct={direct}", flush=True)
     dims, block = dims_of(ndim, n), block_of(ndim, bl)
     q, _ = draw(400 + M, M, dims, dtype)
-    plan = rcd.RcdPlan(rcd.make_desc(M, ndim, n, bl, dtype=dtype, tau=tau, **P))
+    plan = rcd.RcdPlan(rcd.make_desc(M, ndim, n, bl, dtype=dtype, tau=tau, direct=direct, **P))
     plan.set_spectrum(torch.from_numpy(q.ravel()))
     counts = []
     for step in range(6):
