@@ -1229,6 +1229,25 @@ def xpfc_bench(args, cfg):
     ok = [r for r in sweep if r["meets_equal_error"]]
     star = max(ok, key=lambda r: r["tau"]) if ok else None
     best = max((k for k in res if k != "dense"), key=lambda k: res[k]["speedup_steps_vs_dense"])
+    # HBM rooflines from the stage events: the update reads the state and the
+    # four nonlinear transforms and writes the state, 6 x 8 B per FP32 mode,
+    # plus a list entry and the kept block energy per non-frozen block
+    bvol = cfg["block"] ** 2
+    nf = res[best]["nonfrozen_fraction_window_mean"] * nb
+    upd_bytes = nf * (bvol * 48 + 12)
+    upd_ms = res[best]["stage_ms"]["update"]
+    dense_bytes = N * 48
+    roof = {"bound": "hbm", "achieved": round(upd_bytes / (upd_ms * 1e-3) / 1e9, 1), "peak": 8000.0,
+            "unit": "GB/s", "frac": round(upd_bytes / (upd_ms * 1e-3) / 8e12, 4), "traffic": None,
+            "kernel": "k_update (transition walk)", "bytes_per_launch": int(upd_bytes),
+            "avg_launch_us": round(upd_ms * 1e3, 1), "nonfrozen_blocks_mean": round(nf, 1),
+            "run": f"{best}, eager stage events over {min(K, 64)} steps after the settle phase"}
+    kernels = {"dense_update": {"kernel": "k_dense", "avg_launch_us": round(st_d["update"] * 1e3, 1),
+                                "bytes_per_launch": dense_bytes,
+                                "frac": round(dense_bytes / (st_d["update"] * 1e-3) / 8e12, 4)},
+               "nonlinear": {"kernel": "k_nonlinear", "avg_launch_us": round(st_d["nonlinear"] * 1e3, 1),
+                             "bytes_per_launch": N * 16,
+                             "frac": round(N * 16 / (st_d["nonlinear"] * 1e-3) / 8e12, 4)}}
     out = {
         "metric": METRIC, "value": round(N / (res[best]["ms_per_step"] * 1e-3) / 1e9, 4), "unit": "Gpts/s",
         "n_gpus": 1, "steps": K, "warmup": 0, "ms_per_step": res[best]["ms_per_step"], "higher_is_better": True,
@@ -1242,9 +1261,30 @@ def xpfc_bench(args, cfg):
         "fixed_threshold_sweep": sweep, "equal_error_bar": 1.1 * e_d,
         "tau_star": star["tau"] if star else None,
         "speedup_steps_vs_dense_at_equal_error": star["speedup_steps_vs_dense"] if star else None,
+        "roofline": roof, "kernels": kernels,
+        "cpu_baseline": None if args.no_cpu else xpfc_cpu_baseline(cfg, f64, np),
         "wall_s": round(time.perf_counter() - t_start, 1),
     }
     print(json.dumps(out), flush=True)
+
+
+def xpfc_cpu_baseline(cfg, f64, np, s=1024, steps=4):
+    """The oracle's full FP64 XPFC steps (block energy, the workload's
+    threshold, no control) on a bounded sample: the leading s x s corner of
+    the seeded start, as its own periodic grid, scaled to grid points per
+    second."""
+    import oracle as O
+
+    inst = O.Inst(op=O.OP_XPFC, dims=(1, s, s), block=(1, cfg["block"], cfg["block"]), tau=cfg["tau"],
+                  dx=cfg["dx"], dt=cfg["dt"], p=tuple(cfg["params"]), flags=O.FLAG_PIN_K0 | O.FLAG_STATE | O.FLAG_ENERGY)
+    psi = O.fft(np.ascontiguousarray(f64[:s, :s]), -1).ravel()
+    st = np.concatenate([psi, np.zeros(3 * psi.size, np.complex128)])  # history filled by the first step
+    t0 = time.perf_counter()
+    O.step(inst, st, steps)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(s * s * steps / dt / 1e9, 6), "unit": "Gpts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} full FP64 steps of the leading {s}^2 corner of the {cfg['name']} start, {dt:.1f} s"}
 
 
 def rcd_bench(args, cfg):

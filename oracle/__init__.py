@@ -144,6 +144,7 @@ def _load():
         lib.or_step_ctl_f64.argtypes = [P, ctypes.c_int64, P, P, P, P, P, P]
         lib.or_taper.argtypes = [ctypes.c_int64, P]
         lib.or_ch_energy.argtypes = [P, P, P, P]
+        lib.or_sizes.argtypes = [P, P, P]
         lib.or_r2c.argtypes = [ctypes.POINTER(ctypes.c_int64), P, P]
         lib.or_etd4_phi.argtypes = [ctypes.c_double, P]
         lib.or_etd4_coef.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
@@ -202,6 +203,20 @@ def sincos(x: float):
     return s.value, c.value
 
 
+def _sizes(c) -> tuple:
+    """(stored modes per species, blocks) of a descriptor, after the C check."""
+    nm, nb = ctypes.c_int64(), ctypes.c_int64()
+    _check(_load().or_sizes(ctypes.byref(c), ctypes.byref(nm), ctypes.byref(nb)))
+    return nm.value, nb.value
+
+
+def _need(a, n: int, what: str):
+    """The C routines take array extents from the instance: refuse a wrong size
+    here rather than let them read or write past it."""
+    if a is not None and a.size != n:
+        raise ValueError(f"{what}: {a.size} values, the instance needs {n}")
+
+
 def apply(inst: Inst, q, rhs=None, *, dtype="f64", k0=None, rhs_k0=None, skip=None):
     """One kernel-level update of one instance (candidate, indicator, mask, update).
 
@@ -221,6 +236,7 @@ def apply(inst: Inst, q, rhs=None, *, dtype="f64", k0=None, rhs_k0=None, skip=No
     if dtype == "f64":
         qq = np.ascontiguousarray(q, dtype=np.complex128).reshape(-1).copy()
         rr = None if rhs is None else np.ascontiguousarray(rhs, dtype=np.complex128).reshape(-1)
+        _apply_sizes(inst, qq, rr, sk, None, None)
         rc = lib.or_apply_f64(ctypes.byref(c), _ptr(qq), _ptr(rr), _ptr(sk), _ptr(a_b),
                               ctypes.byref(G), _ptr(mask), _ptr(wl), ctypes.byref(cnt))
         k0o = None
@@ -229,6 +245,7 @@ def apply(inst: Inst, q, rhs=None, *, dtype="f64", k0=None, rhs_k0=None, skip=No
         rr = None if rhs is None else np.ascontiguousarray(rhs, dtype=np.complex64).reshape(-1)
         k0o = None if k0 is None else np.ascontiguousarray(k0, dtype=np.float64).copy()
         rk = None if rhs_k0 is None else np.ascontiguousarray(rhs_k0, dtype=np.float64)
+        _apply_sizes(inst, qq, rr, sk, k0o, rk)
         rc = lib.or_apply_f32(ctypes.byref(c), _ptr(qq), _ptr(rr), _ptr(k0o), _ptr(rk), _ptr(sk),
                               _ptr(a_b), ctypes.byref(G), _ptr(mask), _ptr(wl), ctypes.byref(cnt))
     else:
@@ -238,8 +255,20 @@ def apply(inst: Inst, q, rhs=None, *, dtype="f64", k0=None, rhs_k0=None, skip=No
     return dict(q=qq, a_b=a_b, G=G.value, mask=mask, worklist=wl[:n].copy(), count=n, k0=k0o)
 
 
+def _apply_sizes(inst: Inst, q, r, sk, k0, rk):
+    nm, nb = _sizes(inst._c())
+    ns = inst.n_species
+    _need(q, ns * nm, "q")
+    _need(r, (4 if inst.op == OP_XPFC else ns) * nm, "rhs")
+    _need(sk, nb, "skip")
+    _need(k0, ns, "k0")
+    _need(rk, ns, "rhs_k0")
+
+
 def step(inst: Inst, state, nsteps: int, *, masks=False, diag=False, ab=False):
-    """nsteps full FP64 steps.  state: CH c-hat; GS u-hat|v-hat; NLSE E(t).
+    """nsteps full FP64 steps.  state: CH c-hat; GS u-hat|v-hat; NLSE E(t);
+    XPFC psi-hat then the three older nonlinear transforms (4 n_modes values;
+    with hist_valid = 0 the first step fills them).
     The consistency-control schedule of the instance (refresh, full steps,
     threshold control) applies.
 
@@ -251,6 +280,7 @@ def step(inst: Inst, state, nsteps: int, *, masks=False, diag=False, ab=False):
     nb = inst.n_blocks
     per = 2 if inst.op == OP_NLSE else 1
     st = np.ascontiguousarray(state, dtype=np.complex128).reshape(-1).copy()
+    _need(st, (4 if inst.op == OP_XPFC else inst.n_species) * _sizes(c)[0], "state")
     mk = np.zeros((nsteps, per, nb), np.uint8) if masks else None
     dg = np.zeros((nsteps, 4), np.float64) if diag else None
     abv = np.zeros((nsteps, per, nb), np.float64) if ab else None
@@ -272,6 +302,7 @@ def ch_energy(inst: Inst, chat):
     lib = _load()
     c = inst._c()
     ch = np.ascontiguousarray(chat, dtype=np.complex128).reshape(-1)
+    _need(ch, _sizes(c)[0], "c-hat")
     e, m = ctypes.c_double(), ctypes.c_double()
     _check(lib.or_ch_energy(ctypes.byref(c), _ptr(ch), ctypes.byref(e), ctypes.byref(m)))
     return e.value, m.value
@@ -304,6 +335,7 @@ def xpfc_energy(inst: Inst, psihat):
     """(free energy, mean density) of a spectrum."""
     c = inst._c()
     ph = np.ascontiguousarray(psihat, dtype=np.complex128).reshape(-1)
+    _need(ph, _sizes(c)[0], "psi-hat")
     e, m = ctypes.c_double(), ctypes.c_double()
     _check(_load().or_xpfc_energy(ctypes.byref(c), _ptr(ph), ctypes.byref(e), ctypes.byref(m)))
     return e.value, m.value

@@ -883,6 +883,15 @@ int or_r2c(const int64_t dims[3], const double *real, double *half) {
     return rc;
 }
 
+int or_sizes(const or_inst *d, int64_t *n_modes, int64_t *n_blocks) {
+    geom_t g;
+    const int rc = make_geom(d, &g);
+    if (rc != OR_OK) return rc;
+    if (n_modes) *n_modes = g.N;
+    if (n_blocks) *n_blocks = g.nb;
+    return OR_OK;
+}
+
 int or_ch_energy(const or_inst *d, const double *chat, double *energy, double *mass) {
     /* F = dx^d sum_x f(c) + (kappa/2) (dx^d / N) sum_k k^2 |c_k|^2,
      * f(c) = (c^2 - 1)^2 / 4 (so f'(c) = c^3 - c); mass = mean of c.

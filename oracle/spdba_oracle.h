@@ -188,6 +188,11 @@ void or_taper(int64_t B, double *w);
 
 /* Free energy and mass of a CH spectrum (FP64).  Half layout: the gradient
  * sum counts the stored columns 1 .. nx/2 - 1 twice (their partners). */
+/* The descriptor's check and extents: stored modes per species and blocks
+ * (OR_EINVAL for a descriptor the other routines refuse).  The array sizes
+ * the routines above assume follow from these. */
+int or_sizes(const or_inst *d, int64_t *n_modes, int64_t *n_blocks);
+
 int or_ch_energy(const or_inst *d, const double *chat, double *energy, double *mass);
 
 #endif

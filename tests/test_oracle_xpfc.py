@@ -192,3 +192,17 @@ def test_history_starts_from_the_first_transform():
     # and that transform is F[-(omega/2) psi^2 + (u/3) psi^3] of the start
     want = O.fft(-(P[3] / 2) * f ** 2 + (P[4] / 3) * f ** 3, -1).ravel()
     assert np.allclose(st[1], want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+def test_wrong_array_sizes_are_refused_before_the_c_routines():
+    """The C routines take extents from the descriptor; the wrappers refuse
+    arrays of another size (an XPFC step needs psi-hat and three transforms)."""
+    d = inst(n=16, block=4)
+    psi = np.zeros(16 * 16, np.complex128)
+    with pytest.raises(ValueError):
+        O.step(d, psi, 1)
+    with pytest.raises(ValueError):
+        O.apply(d, psi, psi)  # the XPFC update takes four transforms
+    with pytest.raises(ValueError):
+        O.xpfc_energy(d, psi[:-1])
+    O.step(d, np.concatenate([psi, np.zeros(3 * psi.size)]), 1)
