@@ -1268,23 +1268,29 @@ def xpfc_bench(args, cfg):
     print(json.dumps(out), flush=True)
 
 
-def xpfc_cpu_baseline(cfg, f64, np, s=1024, steps=4):
+def xpfc_cpu_baseline(cfg, f64, np, budget=10.0):
     """The oracle's full FP64 XPFC steps (block energy, the workload's
-    threshold, no control) on a bounded sample: the leading s x s corner of
-    the seeded start, as its own periodic grid, scaled to grid points per
+    threshold, no control) on the workload's seeded start, the step count
+    grown until about `budget` seconds of CPU work, scaled to grid points per
     second."""
     import oracle as O
 
-    inst = O.Inst(op=O.OP_XPFC, dims=(1, s, s), block=(1, cfg["block"], cfg["block"]), tau=cfg["tau"],
+    n = cfg["n"]
+    inst = O.Inst(op=O.OP_XPFC, dims=(1, n, n), block=(1, cfg["block"], cfg["block"]), tau=cfg["tau"],
                   dx=cfg["dx"], dt=cfg["dt"], p=tuple(cfg["params"]), flags=O.FLAG_PIN_K0 | O.FLAG_STATE | O.FLAG_ENERGY)
-    psi = O.fft(np.ascontiguousarray(f64[:s, :s]), -1).ravel()
+    psi = O.fft(np.ascontiguousarray(f64), -1).ravel()
     st = np.concatenate([psi, np.zeros(3 * psi.size, np.complex128)])  # history filled by the first step
-    t0 = time.perf_counter()
-    O.step(inst, st, steps)
-    dt = time.perf_counter() - t0
+    steps = 1
+    while True:
+        t0 = time.perf_counter()
+        O.step(inst, st, steps)
+        dt = time.perf_counter() - t0
+        if dt >= budget or steps >= 64:
+            break
+        steps *= 4 if dt < budget / 4 else 2
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(s * s * steps / dt / 1e9, 6), "unit": "Gpts/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} full FP64 steps of the leading {s}^2 corner of the {cfg['name']} start, {dt:.1f} s"}
+    return {"value": round(n * n * steps / dt / 1e9, 6), "unit": "Gpts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} full FP64 steps of the {n}^2 start of {cfg['name']}, {dt:.1f} s"}
 
 
 def rcd_bench(args, cfg):
