@@ -998,6 +998,12 @@ def c5_bench(args, cfg):
         "dense_spectral_update_gpts_s": round(ntot / (dense_stage["update"] * 1e-3) / 1e9, 2),
         "update_stage_speedup_vs_dense": round(dense_stage["update"] / upd_stage, 3),
         "active_fraction_window_mean": round(mean_act / (n // cfg["block"]) ** 3, 4),
+        # the paper's block-activation estimate from the dense stage times and the
+        # window's mean active fraction alpha: (T_FFT + T_NL + T_upd) /
+        # (T_FFT + T_NL + alpha T_upd), beside the measured ratio above
+        "s_estimate": round((dense_stage["fft"] + dense_stage["nonlinear"] + dense_stage["update"])
+                            / (dense_stage["fft"] + dense_stage["nonlinear"]
+                               + mean_act / (n // cfg["block"]) ** 3 * dense_stage["update"]), 4),
         "roofline": roof, "kernels": kernels,
         "proposer": prop_out,
         "cpu_baseline": cpu,
