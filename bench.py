@@ -1118,10 +1118,11 @@ def xpfc_bench(args, cfg):
     import numpy as np
     import torch
 
-    from paper_2609_03922_amd import inputs
+    from paper_2609_03922_amd import autotune, inputs
     from paper_2609_03922_amd import spdba as S
 
     t_start = time.perf_counter()
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     n = cfg["n"]
     A, C = cfg["full_steps"], cfg["settle_steps"]
     K = args.steps if args.steps is not None else cfg["window"]
@@ -1142,8 +1143,19 @@ def xpfc_bench(args, cfg):
             kw["tau"] = tau
         d = S.desc_from_config(cfg, dtype=dtype, graph=graph, timing=timing, **kw)
         p = S.Plan([d])
+        if dtype == "f32":
+            autotune.apply_cached(p, arch)
         p.set_field(0, torch.from_numpy(f64.astype(np.float64 if dtype == "f64" else np.float32).ravel()))
         return p
+
+    if args.tune:  # launch geometry of the controlled plan, tuned in its full-activation phase
+        choice, timings = autotune.tune(lambda dense: make(dense=dense, graph=False, timing=True, target=0.05),
+                                        lambda p: None, arch=arch, warm=200)
+        log(f"launch tuning: {choice}")
+        print("launch tuning (stage ms):", json.dumps(timings), file=sys.stderr, flush=True)
+        if args.tune_only:
+            print(json.dumps({"tuned": {str(k): v for k, v in choice.items()}}), flush=True)
+            return
 
     p = make("f64", dense=True)
     for s0 in range(0, A + C + K, 500):
