@@ -168,3 +168,37 @@ def test_apply_bit_exact_full_size(name, make, seed):
     print(f"full-size apply parity {name}: {len(descs)} instances, "
           f"{sum(d.n_modes for d in descs)} modes", flush=True)
     run_case(descs, seed)
+
+
+def test_full_size_512_state_measure_in_the_timed_launch_configuration():
+    """The 512^3 workload as the bench times it: the state measure, the launch
+    shapes of the tuned cache (the wave walk), and two updates in a row, the
+    second on the measure the first one kept; everything bit-exact against
+    the oracle."""
+    import torch
+
+    from paper_2609_03922_amd import autotune
+    from paper_2609_03922_amd import configs as C
+
+    d = S.desc_from_config(C.CH3D_512_F32_PROPOSER, state_indicator=True)
+    plan = S.Plan([d])
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    entry = autotune.apply_cached(plan, arch)
+    print(f"512^3 state measure, cached launch {entry and entry['choice']}", flush=True)
+    q, r, k0, rk0 = draw_apply_inputs(d, 36, 0)
+    plan.set_spectrum(0, torch.from_numpy(q), k0=k0)
+    for step in range(2):
+        _, r, _, rk0 = draw_apply_inputs(d, 37 + step, 0)
+        plan.apply(torch.from_numpy(r), rk0)
+        ref = oracle_apply(d, q, r, k0, rk0)
+        tag = f"512^3 update {step}"
+        ab, G = plan.indicator(0)
+        assert_bits_equal(plan.active_mask(0), ref["mask"], tag + " mask")
+        assert_bits_equal(ab, ref["a_b"], tag + " a_b")
+        assert G == ref["G"], tag
+        hat, k0g = plan.get_spectrum(0)
+        assert_bits_equal(hat.cpu().numpy(), ref["q"], tag + " coefficients")
+        assert_bits_equal(k0g, ref["k0"], tag + " k0")
+        assert 0 < ref["count"] < d.n_blocks, ref["count"]
+        q, k0 = ref["q"].astype(q.dtype), ref["k0"]
+    plan.destroy()
