@@ -99,9 +99,11 @@ static int make_geom(const or_inst *d, geom_t *g) {
     g->nbxm = g->nb3[2];
     g->nbm = g->nb;
     if (g->half) {
-        /* real fields only; the transition states are not defined on this layout here */
-        if (d->op == OR_OP_NLSE || d->op == OR_OP_XPFC || (d->flags & OR_FLAG_TRANSITION)) return OR_EINVAL;
+        /* real fields only */
+        if (d->op == OR_OP_NLSE || d->op == OR_OP_XPFC) return OR_EINVAL;
         if (g->n[2] < 2 || (g->n[2] / 2) % g->b[2] != 0) return OR_EINVAL;
+        /* transition states: X_0 must hold the columns 0 and 1 (see half_face) */
+        if ((d->flags & OR_FLAG_TRANSITION) && g->b[2] < 2) return OR_EINVAL;
         g->xs = g->n[2] / 2 + 1;
         g->nbxm = g->n[2] / (2 * g->b[2]);
         g->nbm = g->nb3[0] * g->nb3[1] * g->nbxm;
@@ -476,10 +478,111 @@ static inline int64_t block_id3(const geom_t *g, const int64_t bc[3]) {
     return (bc[0] * g->nb3[1] + bc[1]) * g->nb3[2] + bc[2];
 }
 
+/* Neighbours on the half-spectrum layout (Supplementary S1.2).  A stored
+ * block is (bz, by, bx) with bx = 0 .. nbxm - 1 for the columns below nx/2
+ * (X_0 .. X_{nbxm-1}) and bx = nbxm for the column nx/2 (X_N).  Along z and
+ * y the block grid is periodic as in the full layout; along x the stored
+ * columns are a chain X_0 - ... - X_{nbxm-1} - X_N.  A neighbour in the
+ * omitted half is replaced by its conjugate counterpart, q(-k) = q*(k),
+ * taken mode by mode: the column -1 left of kx = 0 is the conjugate of
+ * column 1 (in X_0, the x block edge being at least 2), the column right of
+ * nx/2 the conjugate of column nx/2 - 1 (in X_{nbxm-1}), each at the
+ * mirrored rows -y, -z.  Since the self-conjugate column nx/2 holds each of
+ * its modes twice (at rows y and -y), the column left of it, X_{nbxm-1},
+ * meets both X_N at its own rows and X_N at the mirrored rows.  So:
+ *   x low of X_0:          X_0 at the mirrored rows (kx = 0 is a symmetry
+ *                          boundary: a block there neighbours its partners)
+ *   x high of X_N:         X_{nbxm-1} at the mirrored rows
+ *   x high of X_{nbxm-1}:  X_N at its rows and at the mirrored rows
+ * and the chain otherwise.  Rows [i b, i b + b) mirror to row (n - i b) mod n,
+ * the first row of block (nb - i) mod nb, and rows below it, in block
+ * (nb - i - 1) mod nb: up to two blocks per axis.  The relation is symmetric
+ * (an active block's neighbours are the blocks that count it as theirs). */
+static inline void half_coords(const geom_t *g, int64_t b, int64_t *bz, int64_t *by, int64_t *bx) {
+    int64_t row;
+    if (b >= g->nbm) {
+        row = b - g->nbm;
+        *bx = g->nbxm;
+    } else {
+        row = b / g->nbxm;
+        *bx = b % g->nbxm;
+    }
+    *bz = row / g->nb3[1];
+    *by = row % g->nb3[1];
+}
+static inline int64_t half_id(const geom_t *g, int64_t bz, int64_t by, int64_t bx) {
+    const int64_t row = bz * g->nb3[1] + by;
+    return bx == g->nbxm ? g->nbm + row : row * g->nbxm + bx;
+}
+/* the blocks that hold the mirrored rows of block i of an axis: 1 or 2 */
+static int mirror_blocks(int64_t i, int64_t nb, int64_t b, int64_t out[2]) {
+    out[0] = (nb - i) % nb;
+    if (b < 2) return 1;
+    out[1] = (nb - i - 1 + nb) % nb;
+    return out[1] == out[0] ? 1 : 2;
+}
+/* append the blocks of column bx at the mirrored rows of (bz, by) */
+static int add_mirrored(const geom_t *g, int64_t bz, int64_t by, int64_t bx, int64_t *out, int n) {
+    int64_t mz[2], my[2];
+    const int nz = mirror_blocks(bz, g->nb3[0], g->b[0], mz);
+    const int ny = mirror_blocks(by, g->nb3[1], g->b[1], my);
+    for (int i = 0; i < nz; ++i)
+        for (int k = 0; k < ny; ++k) {
+            const int64_t id = half_id(g, mz[i], my[k], bx);
+            int dup = 0;
+            for (int j = 0; j < n; ++j) dup |= out[j] == id;
+            if (!dup) out[n++] = id;
+        }
+    return n;
+}
+/* stored blocks standing for the neighbour across face f (0 z low, 1 z high,
+ * 2 y low, 3 y high, 4 x low, 5 x high) of stored block b; returns how many
+ * (0: an axis with one block), at most 5 */
+static int half_face(const geom_t *g, int64_t b, int f, int64_t out[8]) {
+    int64_t bz, by, bx;
+    half_coords(g, b, &bz, &by, &bx);
+    const int a = f / 2, side = f % 2 ? 1 : -1;
+    if (a < 2) {
+        const int64_t nb = g->nb3[a];
+        if (nb < 2) return 0;
+        const int64_t j = ((a == 0 ? bz : by) + side + nb) % nb;
+        out[0] = a == 0 ? half_id(g, j, by, bx) : half_id(g, bz, j, bx);
+        return 1;
+    }
+    if (side < 0) {
+        if (bx > 0) {
+            out[0] = half_id(g, bz, by, bx - 1);
+            return 1;
+        }
+        return add_mirrored(g, bz, by, 0, out, 0); /* kx = 0 */
+    }
+    if (bx == g->nbxm) return add_mirrored(g, bz, by, g->nbxm - 1, out, 0); /* beyond nx/2 */
+    out[0] = half_id(g, bz, by, bx + 1);
+    if (bx + 1 < g->nbxm) return 1;
+    return add_mirrored(g, bz, by, g->nbxm, out, 1); /* X_{nbxm-1}: X_N at both row sets */
+}
+
 /* states from the active decisions: a block that is not active and has an
  * active face neighbour becomes 2 (transition).  Axes with one block have
- * no neighbours; the block grid is periodic. */
+ * no neighbours; the block grid is periodic.  Half layout: the neighbours
+ * of half_face. */
 static void add_transition(const geom_t *g, uint8_t *mask) {
+    if (g->half) {
+        uint8_t *act = (uint8_t *)malloc((size_t)g->nb);
+        for (int64_t b = 0; b < g->nb; ++b) act[b] = mask[b] == 1;
+        for (int64_t b = 0; b < g->nb; ++b) {
+            if (act[b]) continue;
+            int near = 0;
+            for (int f = 0; f < 6 && !near; ++f) {
+                int64_t nbr[8];
+                const int n = half_face(g, b, f, nbr);
+                for (int i = 0; i < n; ++i) near |= act[nbr[i]];
+            }
+            if (near) mask[b] = 2;
+        }
+        free(act);
+        return;
+    }
     for (int64_t b = 0; b < g->nb; ++b) {
         if (mask[b] != 0) continue;
         const int64_t bc[3] = {b / (g->nb3[1] * g->nb3[2]), (b / g->nb3[2]) % g->nb3[1], b % g->nb3[2]};
@@ -501,6 +604,23 @@ static void add_transition(const geom_t *g, uint8_t *mask) {
  * x low, x high */
 static double sigma_of(const geom_t *g, const tapers_t *t, const uint8_t *mask, int64_t b, int64_t iz,
                        int64_t iy, int64_t ix) {
+    if (g->half) { /* a face borders frozen blocks when every block standing for its neighbour is frozen */
+        const int64_t li[3] = {iz % g->b[0], iy % g->b[1], 2 * ix == g->n[2] ? 0 : ix % g->b[2]};
+        const int64_t bw[3] = {g->b[0], g->b[1], 2 * ix == g->n[2] ? 1 : g->b[2]};
+        double s = 1.0;
+        for (int f = 0; f < 6; ++f) {
+            int64_t nbr[8];
+            const int n = half_face(g, b, f, nbr);
+            int frozen = n > 0;
+            for (int i = 0; i < n; ++i) frozen &= mask[nbr[i]] == 0;
+            if (!frozen) continue;
+            const int a = f / 2;
+            const double *w = bw[a] == 1 ? NULL : t->w[a];
+            const double v = w ? w[f % 2 ? bw[a] - 1 - li[a] : li[a]] : 1.0;
+            s = s * v;
+        }
+        return s;
+    }
     const int64_t bc[3] = {b / (g->nb3[1] * g->nb3[2]), (b / g->nb3[2]) % g->nb3[1], b % g->nb3[2]};
     const int64_t li[3] = {iz % g->b[0], iy % g->b[1], ix % g->b[2]};
     double s = 1.0;

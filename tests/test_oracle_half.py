@@ -206,13 +206,118 @@ def test_half_sp_dba_conserves_mass_and_freezes_blocks(oracle_mod):
     assert per_step.min() < inst.n_blocks and res["masks"][:, 0, 0].all()
 
 
-def test_half_layout_rejects_transition_and_complex_fields(oracle_mod):
+def test_half_layout_rejects_complex_fields_and_bad_blocks(oracle_mod):
     o = oracle_mod
     q = np.zeros(16 * 9, np.complex128)
-    bad = [_inst(o, o.OP_CH, (1, 16, 16), (1, 4, 4), 0.1, o.FLAG_HALF | o.FLAG_TRANSITION),
-           o.Inst(op=o.OP_NLSE, dims=(1, 1, 16), block=(1, 1, 4), tau=0.1, dx=1.0, dt=0.1,
+    bad = [o.Inst(op=o.OP_NLSE, dims=(1, 1, 16), block=(1, 1, 4), tau=0.1, dx=1.0, dt=0.1,
                   p=(-21.7, 1.3, 0.0), flags=o.FLAG_HALF),
-           _inst(o, o.OP_CH, (1, 16, 16), (1, 4, 16), 0.1, o.FLAG_HALF)]  # x block does not divide nx/2
+           _inst(o, o.OP_CH, (1, 16, 16), (1, 4, 16), 0.1, o.FLAG_HALF),  # x block does not divide nx/2
+           _inst(o, o.OP_CH, (1, 16, 16), (1, 4, 1), 0.1, o.FLAG_HALF | o.FLAG_TRANSITION)]  # X_0 needs columns 0, 1
     for inst in bad:
         with pytest.raises(o.OracleError):
             o.apply(inst, q, q)
+
+
+# ---------------------------------------------------------------------------
+# transition states on the half layout (Supplementary S1.1 with the
+# conjugate neighbour remap of S1.2)
+# ---------------------------------------------------------------------------
+N2, B2 = 32, 4
+NBY, NBXM = N2 // B2, (N2 // 2) // B2
+
+
+def _tr_inst(o, tau=1e-3, extra=0):
+    return _inst(o, o.OP_CH, (1, N2, N2), (1, B2, B2), tau,
+                 o.FLAG_HALF | o.FLAG_STATE | o.FLAG_TRANSITION | extra)
+
+
+def _blk(by, bx):
+    """Stored block id: columns below nx/2 first, then the column nx/2 (bx = NBXM)."""
+    return NBY * NBXM + by if bx == NBXM else by * NBXM + bx
+
+
+def _one_mode_in(cells):
+    q = np.zeros((N2, N2 // 2 + 1), np.complex128)
+    for by, bx in cells:
+        q[by * B2 + 1, N2 // 2 if bx == NBXM else bx * B2 + 1] = 1.0
+    return q.ravel()
+
+
+def _states(o, cells, tau=1e-3):
+    q = _one_mode_in(cells)
+    m = o.apply(_tr_inst(o, tau), q, np.zeros_like(q))["mask"]
+    return {int(b): int(v) for b, v in enumerate(m) if v}
+
+
+@pytest.mark.parametrize("active,transition", [
+    # a block of X_0 away from kx = 0's partners: its y and x neighbours, and
+    # across kx = 0 the blocks of X_0 holding the mirrored rows -y (rows 8..11
+    # mirror to 21..24: blocks 5 and 6)
+    ((2, 0), [(1, 0), (3, 0), (2, 1), (5, 0), (6, 0)]),
+    # row block 0 mirrors to rows 0 and 29..31: itself and block 7
+    ((0, 0), [(1, 0), (7, 0), (0, 1)]),
+    # the last block below nx/2: X_N at its own rows and at the mirrored ones
+    # (rows 12..15 mirror to 17..20: blocks 4 and 5)
+    ((3, NBXM - 1), [(2, NBXM - 1), (4, NBXM - 1), (3, NBXM - 2), (3, NBXM), (4, NBXM), (5, NBXM)]),
+    # the column nx/2: beyond it the mirrored rows of X_{nbxm-1}
+    ((2, NBXM), [(1, NBXM), (3, NBXM), (2, NBXM - 1), (5, NBXM - 1), (6, NBXM - 1)]),
+])
+def test_half_transition_states_hand_cases(oracle_mod, active, transition):
+    o = oracle_mod
+    got = _states(o, [active])
+    want = {_blk(*active): 1}
+    want.update({_blk(*c): 2 for c in transition})
+    assert got == want
+
+
+def test_half_transition_relation_is_symmetric(oracle_mod):
+    """Conjugation is an involution, so if one active block turns a block
+    into a transition block, that block, active alone, turns the first one
+    into a transition block as well."""
+    o = oracle_mod
+    cells = [(by, bx) for by in range(NBY) for bx in range(NBXM + 1)]
+    near = {_blk(*c): {b for b, v in _states(o, [c]).items() if v == 2} for c in cells}
+    pairs = 0
+    for a, nb in near.items():
+        for b in nb:
+            assert a in near[b], (a, b)
+            pairs += 1
+    assert pairs > 4 * len(cells)
+
+
+def test_half_transition_weights_are_the_roll_off_of_the_frozen_faces(oracle_mod):
+    """Active block (2, X_0): the transition block (1, X_0) borders the frozen
+    block (0, X_0) on its low y face and the frozen block (1, X_1) on its high
+    x face; across kx = 0 it meets the transition block (6, X_0) and on its
+    high y face the active block.  Its weight is w(ly) w(B - 1 - lx) with
+    w(i) = (1 - cos(pi i / (B - 1))) / 2."""
+    o = oracle_mod
+    rng = inputs.rng_for(83, 1)
+    q = _one_mode_in([(2, 0)]) * 1e3
+    shape = (N2, N2 // 2 + 1)
+    q = q + 1e-6 * (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).ravel()
+    rhs = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).ravel()
+    inst = _tr_inst(o, tau=1e-2)
+    res = o.apply(inst, q, rhs)
+    assert res["mask"][_blk(1, 0)] == 2 and res["mask"][_blk(1, 1)] == 0 and res["mask"][_blk(0, 0)] == 0
+    cand = o.apply(_inst(o, o.OP_CH, (1, N2, N2), (1, B2, B2), 0.0, o.FLAG_HALF | o.FLAG_DENSE), q, rhs)["q"]
+    w = 0.5 * (1.0 - np.cos(np.pi * np.arange(B2) / (B2 - 1)))
+    got = res["q"].reshape(shape)
+    c, q0 = cand.reshape(shape), q.reshape(shape)
+    for ly in range(B2):
+        for lx in range(B2):
+            y, x = 1 * B2 + ly, lx
+            sig = w[ly] * w[B2 - 1 - lx]
+            assert abs(got[y, x] - (q0[y, x] + sig * (c[y, x] - q0[y, x]))) <= 1e-12 * abs(c[y, x] - q0[y, x]) + 1e-300
+
+
+def test_half_transition_keeps_mass_and_threshold_zero_is_dense(oracle_mod):
+    o = oracle_mod
+    c0 = inputs.uniform_field(1001, 11, (N2, N2), 0.0, 0.05)
+    h0 = o.rfft(c0).ravel()
+    res = o.step(_tr_inst(o, tau=3e-2, extra=o.FLAG_PIN_K0), h0, 20, masks=True)
+    assert res["state"][0] == h0[0]
+    assert (res["masks"] == 2).any() and (res["masks"] == 0).any()
+    dense = o.step(_inst(o, o.OP_CH, (1, N2, N2), (1, B2, B2), 0.0, o.FLAG_HALF | o.FLAG_DENSE), h0, 20)["state"]
+    zero = o.step(_tr_inst(o, tau=0.0), h0, 20)["state"]
+    assert np.array_equal(zero, dense)
