@@ -194,10 +194,13 @@ spdba_status validate(const spdba_instance_desc *d, int32_t n, bool half_cap = t
         if ((x.flags & SPDBA_FLAG_BLOCK_ENERGY) && (x.flags & SPDBA_FLAG_HALF_SPECTRUM)) return SPDBA_EUNSUPPORTED;
         if (x.flags & SPDBA_FLAG_HALF_SPECTRUM) {
             // real fields of two or three dimensions; the x block edge divides
-            // nx/2 (the column nx/2 forms blocks of its own); no consistency
-            // control; the indicator keeps 4 x (blocks per block row) doubles in LDS
-            if (x.op == SPDBA_OP_NLSE || x.ndim < 2 || has_control(x)) return SPDBA_EUNSUPPORTED;
+            // nx/2 (the column nx/2 forms blocks of its own); transition
+            // states need the columns 0 and 1 in the first x block (the
+            // conjugate neighbour across kx = 0); the indicator keeps
+            // 4 x (blocks per block row) doubles in LDS
+            if (x.op == SPDBA_OP_NLSE || x.op == SPDBA_OP_XPFC || x.ndim < 2) return SPDBA_EUNSUPPORTED;
             if ((x.dims[2] / 2) % x.block[2] != 0) return SPDBA_EUNSUPPORTED;
+            if ((x.flags & SPDBA_FLAG_TRANSITION) && x.block[2] < 2) return SPDBA_EUNSUPPORTED;
             // Grids above 2^18 points are refused: timed 256^3 runs of this
             // layout ended in device faults whose cause is not yet found, while
             // every grid up to 64^3 / 512^2 passed its parity tests.
@@ -1107,6 +1110,7 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     c.taper_bs = 0;
     for (const InstDev &I : p->hinst)
         for (int a = 0; a < 3; ++a) c.taper_bs |= 1u << I.lb[a];
+    if (p->half) c.taper_bs |= 1u;  // the one-column blocks of nx/2: edge 1
     c.nb_total = p->nb_total;
     c.n_strips = p->n_strips;
     c.n_tiles = p->n_tiles;

@@ -1179,6 +1179,81 @@ __device__ __forceinline__ bool near_active(const Ctx &c, const InstDev &I, int6
     return nr;
 }
 
+// Half-spectrum layout: the stored blocks standing for the neighbour across
+// face f (0 z low, 1 z high, 2 y low, 3 y high, 4 x low, 5 x high) of the
+// stored block (bz, by, bx), bx = nbxm for the column nx/2.  z and y are
+// periodic; along x the stored columns are a chain X_0 .. X_{nbxm-1}, X_N,
+// and a neighbour in the omitted half is its conjugate counterpart, mode by
+// mode: across kx = 0 the blocks of X_0 at the mirrored rows -y, -z, beyond
+// nx/2 the blocks of X_{nbxm-1} at the mirrored rows, and X_{nbxm-1} meets
+// X_N at its own and at the mirrored rows (the column nx/2 holds each of its
+// modes at y and -y).  Rows of block i mirror into blocks (nb - i) mod nb and
+// (nb - i - 1) mod nb.  Returns the count (at most 5; 0 for an axis with one
+// block).
+__device__ __forceinline__ int64_t half_blk(const InstDev &I, int bz, int by, int bx) {
+    const int64_t row = ((int64_t)bz << I.lnbk[1]) + by;
+    return bx == I.nbxm ? I.nbm + row : (row << I.lnbxm) + bx;
+}
+__device__ __forceinline__ int half_mirrored(const InstDev &I, int bz, int by, int bx, int64_t *out, int n) {
+    const int nz0 = (I.nbk[0] - bz) & (I.nbk[0] - 1), ny0 = (I.nbk[1] - by) & (I.nbk[1] - 1);
+    const int mz[2] = {nz0, (nz0 - 1) & (I.nbk[0] - 1)}, my[2] = {ny0, (ny0 - 1) & (I.nbk[1] - 1)};
+    const int cz = (I.b[0] > 1 && mz[1] != mz[0]) ? 2 : 1, cy = (I.b[1] > 1 && my[1] != my[0]) ? 2 : 1;
+    for (int i = 0; i < cz; ++i)
+        for (int k = 0; k < cy; ++k) {
+            const int64_t id = half_blk(I, mz[i], my[k], bx);
+            bool dup = false;
+            for (int j = 0; j < n; ++j) dup |= out[j] == id;
+            if (!dup) out[n++] = id;
+        }
+    return n;
+}
+__device__ __forceinline__ int half_face(const InstDev &I, int bz, int by, int bx, int f, int64_t *out) {
+    const int a = f >> 1;
+    const int d = (f & 1) ? 1 : -1;
+    if (a < 2) {
+        const int nb = I.nbk[a];
+        if (nb < 2) return 0;
+        if (a == 0) out[0] = half_blk(I, (bz + d) & (nb - 1), by, bx);
+        else out[0] = half_blk(I, bz, (by + d) & (nb - 1), bx);
+        return 1;
+    }
+    if (d < 0) {
+        if (bx > 0) {
+            out[0] = half_blk(I, bz, by, bx - 1);
+            return 1;
+        }
+        return half_mirrored(I, bz, by, 0, out, 0);  // across kx = 0
+    }
+    if (bx == I.nbxm) return half_mirrored(I, bz, by, I.nbxm - 1, out, 0);  // beyond nx/2
+    out[0] = half_blk(I, bz, by, bx + 1);
+    if (bx + 1 < I.nbxm) return 1;
+    return half_mirrored(I, bz, by, I.nbxm, out, 1);
+}
+__device__ __forceinline__ void half_coords(const InstDev &I, int64_t lb, int &bz, int &by, int &bx) {
+    int64_t row;
+    if (lb >= I.nbm) {
+        row = lb - I.nbm;
+        bx = I.nbxm;
+    } else {
+        row = lb >> I.lnbxm;
+        bx = (int)(lb & (I.nbxm - 1));
+    }
+    by = (int)(row & (I.nbk[1] - 1));
+    bz = (int)(row >> I.lnbk[1]);
+}
+// a block of the half layout with an active neighbour
+__device__ __forceinline__ bool half_near_active(const Ctx &c, const InstDev &I, int64_t lb, double thr) {
+    int bz, by, bx;
+    half_coords(I, lb, bz, by, bx);
+    bool nr = false;
+    for (int f = 0; f < 6; ++f) {
+        int64_t nb[8];
+        const int n = half_face(I, bz, by, bx, f, nb);
+        for (int i = 0; i < n; ++i) nr = nr | nb_on(c, I, nb[i], thr);
+    }
+    return nr;
+}
+
 // Transition weight of the mode at block-local (lz, ly, lx): the product of
 // the roll-off values over the faces that border frozen blocks, in the fixed
 // order z low, z high, y low, y high, x low, x high; a face without a frozen
@@ -1228,7 +1303,22 @@ __global__ void __launch_bounds__(256) k_compact_states(Ctx c) {
         const int64_t lb = gb - I.blk_off;
         uint8_t st = active_ctl(c, I, lb, thr, C.full != 0) ? 1 : 0;
         entry = (uint32_t)gb;
-        if (!st && c.trans && near_active(c, I, lb, thr)) {
+        if (c.half) {  // the neighbours of the stored half (conjugate counterparts at its ends)
+            if (!st && c.trans && half_near_active(c, I, lb, thr)) {
+                st = 2;
+                int bz, by, bx;
+                half_coords(I, lb, bz, by, bx);
+                uint32_t f = 0;
+                for (int fc = 0; fc < 6; ++fc) {
+                    int64_t nb[8];
+                    const int n = half_face(I, bz, by, bx, fc, nb);
+                    bool fr = n > 0;  // every block standing for the neighbour is frozen
+                    for (int i = 0; i < n; ++i) fr = fr && !(nb_on(c, I, nb[i], thr) | half_near_active(c, I, nb[i], thr));
+                    f |= fr ? 1u << fc : 0u;
+                }
+                entry |= (f << 25) | (1u << 31);
+            }
+        } else if (!st && c.trans && near_active(c, I, lb, thr)) {
             st = 2;
             // a neighbour is frozen when neither it nor any of its own
             // neighbours passes the threshold rule
@@ -2744,10 +2834,16 @@ __global__ void __launch_bounds__(256) k_indicator_h(Ctx c) {
 // thread issues the loads of two slots before it computes either, so a block
 // of 512 values is one round trip for 256 threads.  red: two sets of per-wave
 // maxima used alternately (par), so one barrier per block suffices.
-template <typename T, int OP>
-__device__ __forceinline__ void update_block_h(const Ctx &c, uint32_t entry, double (*red)[4], int par) {
+// TR: the entry carries the transition flag and the frozen-face bits; a
+// transition block takes q + sigma (q' - q) with sigma from the roll-off
+// tables in sig (the column nx/2 has edge 1 along x).
+template <typename T, int OP, bool TR>
+__device__ __forceinline__ void update_block_h(const Ctx &c, uint32_t entry, double (*red)[4], int par,
+                                               const double *sig) {
     constexpr int UB = 2;
-    const int64_t gb = (int64_t)entry;
+    const int64_t gb = TR ? (int64_t)(entry & kEntryId) : (int64_t)entry;
+    const bool trn = TR && (entry >> 31);  // workgroup-uniform
+    const uint32_t faces = (entry >> 25) & 63u;
     const int ii = c.blk_inst[gb];
     const InstDev &I = c.inst[ii];
     const int64_t lb = gb - I.blk_off;
@@ -2769,6 +2865,7 @@ __device__ __forceinline__ void update_block_h(const Ctx &c, uint32_t entry, dou
     const int slots = (I.b[0] * I.b[1]) << lbx;
     const Coef K = Coef::of(I);
     const int lb1 = I.lb[1], b1m = I.b[1] - 1, ln1 = I.ln[1];
+    const int bxe = 1 << lbx;  // block edge along x: 1 for the column nx/2
     const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2], xs = I.xs;
     const int z0 = bz << I.lb[0], y0 = by << lb1;
     const bool k0_blk = I.k0path && lb == 0;
@@ -2816,6 +2913,16 @@ __device__ __forceinline__ void update_block_h(const Ctx &c, uint32_t entry, dou
                 gs_cand<T>(dt, au, qr[u], qi[u], nr[u], ni[u], cr, ci);
                 gs_cand<T>(dt, av, q2r[u], q2i[u], n2r[u], n2i[u], dr, di);
             }
+            if (TR && trn) {
+                const int s = s0 + u * step, r = s >> lbx;
+                const T sg = (T)sigma_at(sig, faces, I.b[0], I.b[1], bxe, r >> lb1, r & b1m, s & (bxe - 1));
+                cr = fmat(sg, cr - qr[u], qr[u]);
+                ci = fmat(sg, ci - qi[u], qi[u]);
+                if (OP == OP_GS) {
+                    dr = fmat(sg, dr - q2r[u], q2r[u]);
+                    di = fmat(sg, di - q2i[u], q2i[u]);
+                }
+            }
             if (k0_blk && e[u] == 0) cr = ci = dr = di = (T)0;  // the FP32 slot of k = 0 stays zero
             if (ab) {  // the state measure of what is stored; k = 0 left out
                 double a = sq2((double)cr, (double)ci);
@@ -2840,22 +2947,44 @@ __device__ __forceinline__ void update_block_h(const Ctx &c, uint32_t entry, dou
     if (k0_blk && threadIdx.x == 0) {
         double tmp[2];
         k0_cand(I, OP, c.k0 + 2 * ii, c.rhs_k0 + 2 * ii, tmp);
+        if (TR && trn) {  // block 0 in transition: the weighted increment in FP64
+            const double s0 = sigma_at(sig, faces, I.b[0], I.b[1], bxe, 0, 0, 0);
+            tmp[0] = __builtin_fma(s0, tmp[0] - c.k0[2 * ii], c.k0[2 * ii]);
+            if (OP == OP_GS) tmp[1] = __builtin_fma(s0, tmp[1] - c.k0[2 * ii + 1], c.k0[2 * ii + 1]);
+        }
         c.k0[2 * ii] = tmp[0];
         if (OP == OP_GS) c.k0[2 * ii + 1] = tmp[1];
     }
 }
 
-// persistent walk of the appended list, one segment per XCD (as k_update)
-template <typename T, int OP>
+// persistent walk of the appended list, one segment per XCD (as k_update);
+// CTL: workgroup 0 first closes the update's control step and hands G over;
+// TR: the roll-off tables are copied into dynamic LDS once per workgroup
+template <typename T, int OP, bool TR, bool CTL>
 __global__ void __launch_bounds__(256) k_update_h(Ctx c) {
+    extern __shared__ double sig[];
     __shared__ double red[2][4];
+    if (CTL && blockIdx.x == 0 && threadIdx.x < 64)
+        for (int i = threadIdx.x; i < c.n_inst; i += 64) {
+            control_inst(c, i);
+            c.G_last[i] = c.G[i];
+            c.G[i] = 0ull;
+        }
+    if (TR) {
+        for (uint32_t bs = c.taper_bs; bs; bs &= bs - 1) {
+            const int B = 1 << __builtin_ctz(bs);
+            for (int i = threadIdx.x; i < B; i += blockDim.x) sig[B + i] = c.taper[B + i];
+        }
+        __syncthreads();
+    }
     const uint32_t total = *c.count;
     const int P = gridDim.x;  // multiple of 8
     const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per = P >> 3;
     const uint32_t seg = (total + 7) / 8;
     const uint32_t lo = min(total, seg * xcd), hi = min(total, seg * (xcd + 1));
     int par = 0;
-    for (uint32_t e = lo + local; e < hi; e += per, par ^= 1) update_block_h<T, OP>(c, c.worklist[e], red, par);
+    for (uint32_t e = lo + local; e < hi; e += per, par ^= 1)
+        update_block_h<T, OP, TR>(c, c.worklist[e], red, par, sig);
 }
 
 // Regular mode on the half layout: every stored mode, tiles of tile_elems
@@ -3142,8 +3271,16 @@ static void upd_launch_op(const Ctx &c, int grid, int multi, bool tr, bool ctl, 
 template <typename T>
 static hipError_t upd_launch(const Ctx &c, int grid, int multi, bool tr, bool ctl, hipStream_t s) {
     if (c.half) {  // the block-list walk only
-        if (c.op == OP_CH) hipLaunchKernelGGL((k_update_h<T, OP_CH>), dim3(grid), dim3(256), 0, s, c);
-        else hipLaunchKernelGGL((k_update_h<T, OP_GS>), dim3(grid), dim3(256), 0, s, c);
+        const size_t lds = tr ? (size_t)c.sig_bytes : 0;
+        if (c.op == OP_CH) {
+            if (ctl && tr) hipLaunchKernelGGL((k_update_h<T, OP_CH, true, true>), dim3(grid), dim3(256), lds, s, c);
+            else if (ctl) hipLaunchKernelGGL((k_update_h<T, OP_CH, false, true>), dim3(grid), dim3(256), 0, s, c);
+            else hipLaunchKernelGGL((k_update_h<T, OP_CH, false, false>), dim3(grid), dim3(256), 0, s, c);
+        } else {
+            if (ctl && tr) hipLaunchKernelGGL((k_update_h<T, OP_GS, true, true>), dim3(grid), dim3(256), lds, s, c);
+            else if (ctl) hipLaunchKernelGGL((k_update_h<T, OP_GS, false, true>), dim3(grid), dim3(256), 0, s, c);
+            else hipLaunchKernelGGL((k_update_h<T, OP_GS, false, false>), dim3(grid), dim3(256), 0, s, c);
+        }
         return hipGetLastError();
     }
     if (c.op == OP_CH) upd_launch_op<T, OP_CH>(c, grid, multi, tr, ctl, s);

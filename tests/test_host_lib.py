@@ -86,7 +86,7 @@ def _good(**kw):
                 c.block.__setitem__(2, 8192), setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_TRANSITION)),
      spdba.SPDBA_EUNSUPPORTED),
     # half-spectrum layout: real fields of two or three dimensions, x block edge
-    # dividing nx/2, no consistency control, LDS of the indicator
+    # dividing nx/2 (at least 2 with transition states), LDS of the indicator
     (lambda c: (setattr(c, "op", spdba.OPS["nlse"]), setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_HALF_SPECTRUM)),
      spdba.SPDBA_EUNSUPPORTED),
     (lambda c: (setattr(c, "ndim", 1), [c.dims.__setitem__(a, 1) for a in (0, 1)],
@@ -94,10 +94,9 @@ def _good(**kw):
      spdba.SPDBA_EUNSUPPORTED),
     (lambda c: (c.block.__setitem__(2, 32), setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_HALF_SPECTRUM)),
      spdba.SPDBA_EUNSUPPORTED),  # 32 does not divide 16
-    (lambda c: setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_HALF_SPECTRUM | spdba.SPDBA_FLAG_TRANSITION),
-     spdba.SPDBA_EUNSUPPORTED),
-    (lambda c: (setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_HALF_SPECTRUM | spdba.SPDBA_FLAG_REFRESH),
-                setattr(c, "refresh_period", 5)), spdba.SPDBA_EUNSUPPORTED),
+    (lambda c: (setattr(c, "dtype", spdba.SPDBA_F64), c.block.__setitem__(2, 1),
+                setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_HALF_SPECTRUM | spdba.SPDBA_FLAG_TRANSITION)),
+     spdba.SPDBA_EUNSUPPORTED),  # X_0 must hold the columns 0 and 1
     (lambda c: (setattr(c, "ndim", 2), c.dims.__setitem__(0, 1), c.block.__setitem__(0, 1),
                 c.dims.__setitem__(1, 8192), c.dims.__setitem__(2, 8192), c.block.__setitem__(1, 2),
                 c.block.__setitem__(2, 2), setattr(c, "flags", c.flags | spdba.SPDBA_FLAG_HALF_SPECTRUM)),
@@ -153,3 +152,14 @@ def test_half_layout_refused_above_tested_sizes():
     d = _good(half=True, state_indicator=True).to_c()
     d.dims[0] = d.dims[1] = d.dims[2] = 128
     assert spdba.spdba_plan_create_status([d]) == spdba.SPDBA_EUNSUPPORTED
+
+
+def test_half_layout_accepts_consistency_control():
+    """Transition states (with the conjugate neighbour remap) and the
+    threshold controller on the half layout: the descriptor passes the
+    library's checks (the host-only audit runs them without a device)."""
+    d = spdba.Desc(op="ch", dtype="f32", ndim=3, n=32, block=8, tau=1e-3, dx=1.0, dt=0.01, params=(1.0, 1.0),
+                   half=True, transition=True, refresh=10, full_steps=2, target_ratio=0.2, control_interval=4,
+                   deadband=0.05)
+    st, msg = spdba.plan_audit([d])
+    assert st == spdba.SPDBA_OK, msg
