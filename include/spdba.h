@@ -140,10 +140,21 @@ enum {
                                           divide nx/2 and nx/(2 block[2]) + 1 <= 2048;
                                           grids of at most 2^18 points (larger ones:
                                           EUNSUPPORTED, until a device fault seen
-                                          on 256^3 runs is explained);
-                                          not with consistency control; the update
-                                          walks the block list whatever update variant
-                                          is set (otherwise EUNSUPPORTED)               */
+                                          on 256^3 runs is explained).  With
+                                          SPDBA_FLAG_TRANSITION (x block edge >= 2,
+                                          else EUNSUPPORTED) a neighbour in the
+                                          omitted half is its conjugate counterpart:
+                                          the x-low neighbour of the first x block is
+                                          that block at the mirrored rows (-ky, -kz);
+                                          the x-high neighbour of the column nx/2 is
+                                          the last block below it at the mirrored
+                                          rows, which in turn has both the column
+                                          nx/2 of its own rows and of the mirrored
+                                          rows as x-high neighbours (a face borders
+                                          frozen blocks when every block it touches
+                                          is frozen; the column nx/2 rolls off with
+                                          w = 1).  The update walks the block list
+                                          whatever update variant is set             */
     SPDBA_FLAG_BLOCK_ENERGY = 1u << 9, /* with SPDBA_FLAG_STATE_INDICATOR (else EINVAL):
                                           a_b = the block's FP64 sum of a(k), the
                                           block energy of the main text (XPFC) and the
