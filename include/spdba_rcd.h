@@ -82,7 +82,8 @@ typedef struct {
     int64_t active_blocks; /* of the last update                                  */
     double G;              /* of the last update (0 for Regular)                  */
     float stage_ms[4];     /* SPDBA_RCD_TIMING, last step: transforms + reaction, */
-                           /* measure, compaction, update (else zeros)            */
+                           /* measure pass, G + threshold + compaction, update    */
+                           /* (else zeros)                                        */
 } spdba_rcd_stats_t;
 
 typedef struct spdba_rcd_s *spdba_rcd_plan;

@@ -3252,6 +3252,56 @@ hipError_t launch_compact(const Ctx &c, hipStream_t s, int from_mask) {
     return hipGetLastError();
 }
 
+// aux of a BlockStage: the instance record, the owner table (all instance 0),
+// the chunk counts of the ordered compaction, each 256-byte aligned
+static size_t stage_al(size_t o) { return (o + 255) & ~(size_t)255; }
+static int64_t stage_chunks(int64_t nb) { return (nb + CHUNK_BLOCKS - 1) / CHUNK_BLOCKS; }
+
+size_t block_stage_bytes(int64_t nb) {
+    size_t o = stage_al(sizeof(InstDev));
+    o = stage_al(o + sizeof(uint16_t) * (size_t)nb);
+    return stage_al(o + sizeof(uint32_t) * (size_t)stage_chunks(nb));
+}
+
+static Ctx stage_ctx(const BlockStage &b) {
+    char *aux = static_cast<char *>(b.aux);
+    Ctx c{};
+    c.inst = reinterpret_cast<const InstDev *>(aux);
+    c.n_inst = 1;
+    c.blk_inst = reinterpret_cast<const uint16_t *>(aux + stage_al(sizeof(InstDev)));
+    c.chunk_cnt =
+        reinterpret_cast<uint32_t *>(aux + stage_al(stage_al(sizeof(InstDev)) + sizeof(uint16_t) * (size_t)b.nb));
+    c.a_b = b.a_b;
+    c.a_next = const_cast<double *>(b.a_next);
+    c.mask = b.mask;
+    c.worklist = b.list;
+    c.count = b.count;
+    c.G = b.G;
+    c.nb_total = b.nb;
+    c.n_chunks = stage_chunks(b.nb);
+    return c;
+}
+
+hipError_t block_stage_init(const BlockStage &b, double tau2, int pin, hipStream_t s) {
+    InstDev I{};
+    I.nb = b.nb;
+    I.tau2 = tau2;
+    I.pin = pin;
+    const Ctx c = stage_ctx(b);
+    hipError_t e = hipMemcpyAsync(const_cast<InstDev *>(c.inst), &I, sizeof(I), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(const_cast<uint16_t *>(c.blk_inst), 0, sizeof(uint16_t) * (size_t)b.nb, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // I lives on this stack frame
+    return e;
+}
+
+hipError_t launch_block_stage(const BlockStage &b, hipStream_t s) {
+    const Ctx c = stage_ctx(b);
+    hipError_t e = launch_gmax(c, s);
+    if (e != hipSuccess) return e;
+    return launch_compact(c, s, 0);
+}
+
 template <typename T, int OP>
 static void upd_launch_op(const Ctx &c, int grid, int multi, bool tr, bool ctl, hipStream_t s) {
     if (ctl && tr)

@@ -4,9 +4,10 @@
 //   k_md_measure   per block of bins: a_b = max of sum_m |E_m|^2 (FP64, modes
 //                  in order, omega = 0 left out); blocks dealt to the XCDs in
 //                  eight contiguous ranges (k_md_measure_small for blocks of
-//                  at most 64 bins: a thread per bin, a max over lane groups)
-//   k_md_gmax      G = max_b a_b (one atomic max per workgroup)
-//   k_md_compact   mask and an unordered list of the active blocks
+//                  at most 64 bins: a thread per bin, a max over lane groups);
+//                  both clear the mask of the blocks they measure
+//   G, the threshold, the mask and the ascending list of active blocks: the
+//                  block-activity stage of the main plan (spdba::launch_block_stage)
 //   k_md_update    persistent walk of the list, one list segment per XCD; per
 //                  bin the M modes in registers, then E'_m = h(omega) sum_j
 //                  W_mj E_j row by row with W in LDS (read as broadcasts);
@@ -96,6 +97,7 @@ __global__ void __launch_bounds__(256) k_md_measure(MCtx c) {
         double m = red[0];
         for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, red[k]);
         c.ab[b] = m;
+        c.mask[b] = 0;  // a fresh measure: nothing for the stage's G pass to merge
     }
 }
 
@@ -121,39 +123,11 @@ __global__ void __launch_bounds__(256) k_md_measure_small(MCtx c, int fp64) {
         }
         if (e == 0) acc = 0.0;
         for (int off = c.B >> 1; off >= 1; off >>= 1) acc = fmax(acc, __shfl_xor(acc, off, 64));
-        if ((e & (c.B - 1)) == 0) c.ab[e >> c.lB] = acc;
+        if ((e & (c.B - 1)) == 0) {
+            c.ab[e >> c.lB] = acc;
+            c.mask[e >> c.lB] = 0;
+        }
     }
-}
-
-__global__ void __launch_bounds__(1024) k_md_gmax(MCtx c) {
-    __shared__ double red[16];
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double m = b < c.nb ? c.ab[b] : 0.0;
-    m = mwave_max(m);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double g = red[0];
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) g = fmax(g, red[k]);
-        if (g > 0.0) atomicMax(c.G, (unsigned long long)__double_as_longlong(g));
-    }
-}
-
-__global__ void __launch_bounds__(256) k_md_compact(MCtx c) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    bool act = false;
-    if (b < c.nb) {
-        const double G = __longlong_as_double((long long)*c.G);
-        act = (c.pin && b == 0) || c.ab[b] > c.tau2 * G;
-        c.mask[b] = act ? 1 : 0;
-    }
-    const unsigned long long bal = __ballot(act);
-    if (bal == 0ull) return;
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(c.count, (uint32_t)__popcll(bal));
-    base = __shfl(base, 0, 64);
-    if (act) c.list[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)b;
 }
 
 template <typename T, int MM>
@@ -411,7 +385,8 @@ struct spdba_mdbp_s {
     int esize = 8, cu = 256;
     hipStream_t stream = nullptr;
     size_t state_bytes = 0, work_bytes = 0, fft_work = 0;
-    size_t o_fft = 0, o_ab = 0, o_mask = 0, o_list = 0, o_ctl = 0, o_w = 0, o_tmp = 0;
+    size_t o_fft = 0, o_ab = 0, o_mask = 0, o_list = 0, o_ctl = 0, o_w = 0, o_tmp = 0, o_stage = 0;
+    spdba::BlockStage stage{};  // G, threshold and ordered compaction (the main plan's kernels)
     rocfft_plan fwd = nullptr, inv = nullptr;
     rocfft_execution_info info = nullptr;
     std::vector<cd> W;
@@ -509,9 +484,8 @@ spdba_status linear_half(spdba_mdbp_plan p) {
             if (p->dbl) hipLaunchKernelGGL(k_md_measure<double>, dim3(nbg), dim3(256), 0, p->stream, c);
             else hipLaunchKernelGGL(k_md_measure<float>, dim3(nbg), dim3(256), 0, p->stream, c);
         }
-        hipLaunchKernelGGL(k_md_gmax, dim3((unsigned)((c.nb + 1023) / 1024)), dim3(1024), 0, p->stream, c);
-        hipLaunchKernelGGL(k_md_compact, dim3((unsigned)((c.nb + 255) / 256)), dim3(256), 0, p->stream, c);
         MTRY_HIP(hipGetLastError());
+        MTRY_HIP(spdba::launch_block_stage(p->stage, p->stream));
     }
     const int64_t epi = c.B < 256 ? 256 / c.B : 1;  // list entries per workgroup iteration
     const int grid = (int)(std::max<int64_t>(8, std::min<int64_t>((c.nb + epi - 1) / epi, (int64_t)p->cu * 8)) + 7) / 8 * 8;
@@ -633,6 +607,8 @@ spdba_status spdba_mdbp_create(const spdba_mdbp_desc *desc, const double *K, voi
     o = al256(o + (size_t)p->esize * c.mm * c.mm);
     p->o_tmp = o;  // get_field's copy
     o = al256(o + spec);
+    p->o_stage = o;
+    o = al256(o + spdba::block_stage_bytes(c.nb));
     p->work_bytes = o;
     *out = p;
     return SPDBA_OK;
@@ -676,6 +652,15 @@ spdba_status spdba_mdbp_bind(spdba_mdbp_plan p, void *d_state, void *d_work) {
         MTRY_HIP(hipMemcpy(p->d_work + p->o_w, wf.data(), 4 * wf.size(), hipMemcpyHostToDevice));
     }
     MTRY_HIP(hipMemsetAsync(p->d_work + p->o_ab, 0, p->o_w - p->o_ab, p->stream));
+    p->stage.nb = c.nb;
+    p->stage.a_b = c.ab;
+    p->stage.a_next = c.ab;  // no kept measure: the measure pass clears the mask every update
+    p->stage.mask = c.mask;
+    p->stage.list = c.list;
+    p->stage.count = c.count;
+    p->stage.G = c.G;
+    p->stage.aux = p->d_work + p->o_stage;
+    MTRY_HIP(spdba::block_stage_init(p->stage, c.tau2, c.pin, p->stream));
     MTRY_HIP(hipStreamSynchronize(p->stream));
     p->bound = true;
     return SPDBA_OK;

@@ -5,11 +5,12 @@
 // component, N modes each):
 //   k_rcd_reaction   real space: u = Re(W)/N per component, W <- R(u) (S4.1)
 //   k_rcd_measure    per block: a_b = max over modes of sum_m |q_m|^2 (FP64,
-//                    components in order, k = 0 left out); one workgroup per block
-//   k_rcd_gmax       G = max_b a_b (after an update: merged with the measure the
-//                    update kept for the blocks it stored)
-//   k_rcd_compact    mask and an unordered list of the active blocks
-//                    (wave-aggregated append)
+//                    components in order, k = 0 left out); one workgroup per
+//                    block; clears the block's mask (no kept measure to merge)
+//   G, the threshold, the mask and the ascending list of active blocks: the
+//                    block-activity stage of the main plan (spdba::launch_block_stage;
+//                    after an update G merges the measure the update kept for
+//                    the blocks it stored)
 //   k_rcd_update     persistent walk of the list (or of every block for the
 //                    Regular update): per mode b = q + dt R, then the eigen form
 //                    of S4.3, x = V diag(1/(1 + dt k^2 lambda)) V^T b, with V^T
@@ -184,50 +185,8 @@ __global__ void __launch_bounds__(256) k_rcd_measure(RCtx c) {
         double m = red[0];
         for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, red[k]);
         c.ab[b] = m;
+        c.mask[b] = 0;  // a fresh measure: nothing for the stage's G pass to merge
     }
-}
-
-// G = max_b a_b, one block per thread, one atomic max per workgroup on the
-// bit pattern (non-negative doubles order as their bits; G was cleared by
-// k_rcd_reset).  merge: the measure kept by the last update -- the blocks it
-// stored (mask set) take the value it computed, the others keep theirs
-__global__ void __launch_bounds__(1024) k_rcd_gmax(RCtx c, int merge) {
-    __shared__ double red[16];
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double m = 0.0;
-    if (b < c.g.nb) {
-        if (merge && c.mask[b]) {
-            m = c.anext[b];
-            c.ab[b] = m;
-        } else {
-            m = c.ab[b];
-        }
-    }
-    m = rwave_max(m);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double g = red[0];
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) g = fmax(g, red[k]);
-        if (g > 0.0) atomicMax(c.G, (unsigned long long)__double_as_longlong(g));
-    }
-}
-
-__global__ void __launch_bounds__(256) k_rcd_compact(RCtx c) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    bool act = false;
-    if (b < c.g.nb) {
-        const double G = __longlong_as_double((long long)*c.G);
-        act = (c.pin && b == 0) || c.ab[b] > c.tau2 * G;
-        c.mask[b] = act ? 1 : 0;
-    }
-    const unsigned long long bal = __ballot(act);
-    if (bal == 0ull) return;
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(c.count, (uint32_t)__popcll(bal));
-    base = __shfl(base, 0, 64);
-    if (act) c.list[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)b;
 }
 
 // DIRECT: the coupled update of S4.2 as written, a per-mode solve of
@@ -715,7 +674,8 @@ struct spdba_rcd_s {
     hipStream_t stream = nullptr;
     size_t state_bytes = 0, work_bytes = 0;
     size_t o_rhs = 0, o_fft = 0, o_ab = 0, o_anext = 0, o_mask = 0, o_list = 0, o_ctl = 0, o_vt = 0, o_lam = 0,
-           o_dm = 0;
+           o_dm = 0, o_stage = 0;
+    spdba::BlockStage stage{};  // G, threshold and ordered compaction (the main plan's kernels)
     size_t fft_work = 0;
     rocfft_plan fwd = nullptr, inv = nullptr, inv_oop = nullptr;
     bool inv_keeps = false;  // the out-of-place inverse leaves its input intact (probed at bind)
@@ -856,11 +816,9 @@ spdba_status update_stage(spdba_rcd_plan p, const void *rhs) {
             if (p->dbl) hipLaunchKernelGGL(k_rcd_measure<double>, dim3(nbg), dim3(256), 0, p->stream, c);
             else hipLaunchKernelGGL(k_rcd_measure<float>, dim3(nbg), dim3(256), 0, p->stream, c);
         }
-        hipLaunchKernelGGL(k_rcd_gmax, dim3((unsigned)((c.g.nb + 1023) / 1024)), dim3(1024), 0, p->stream, c,
-                           p->ab_valid ? 1 : 0);
         RTRY_HIP(hipGetLastError());
         rec(p, 2);
-        hipLaunchKernelGGL(k_rcd_compact, dim3((unsigned)((c.g.nb + 255) / 256)), dim3(256), 0, p->stream, c);
+        RTRY_HIP(spdba::launch_block_stage(p->stage, p->stream));
         RTRY_HIP(hipGetLastError());
     } else {
         rec(p, 2);
@@ -1007,6 +965,8 @@ spdba_status spdba_rcd_create(const spdba_rcd_desc *desc, void *stream, spdba_rc
     o = al256(o + tsz * c.mm);
     p->o_dm = o;
     o = al256(o + tsz * c.mm * c.mm);
+    p->o_stage = o;
+    o = al256(o + spdba::block_stage_bytes(g.nb));
     p->work_bytes = o;
     *out = p;
     return SPDBA_OK;
@@ -1062,6 +1022,15 @@ spdba_status spdba_rcd_bind(spdba_rcd_plan p, void *d_state, void *d_work) {
     }
     // the tables read back before any update: zero a_b, mask, G and the count
     RTRY_HIP(hipMemsetAsync(p->d_work + p->o_ab, 0, p->o_vt - p->o_ab, p->stream));
+    p->stage.nb = c.g.nb;
+    p->stage.a_b = c.ab;
+    p->stage.a_next = c.anext;
+    p->stage.mask = c.mask;
+    p->stage.list = c.list;
+    p->stage.count = c.count;
+    p->stage.G = c.G;
+    p->stage.aux = p->d_work + p->o_stage;
+    RTRY_HIP(spdba::block_stage_init(p->stage, c.tau2, c.pin, p->stream));
     // does the out-of-place inverse keep its input?  A pattern in the state,
     // one transform, a check (the state's contents are undefined until loaded)
     uint32_t *bad = reinterpret_cast<uint32_t *>(p->d_work + p->o_ctl + 12);
