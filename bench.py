@@ -330,6 +330,9 @@ def main():
                                         arch=arch, warm=min(cfg["steps"], 500) // 2)
         print("launch tuning (stage ms):", json.dumps(timings), file=sys.stderr, flush=True)
         tuned = {str(k): v for k, v in choice.items()}
+        if args.tune_only:
+            print(json.dumps({"tuned": tuned, "workload": cfg["name"]}), flush=True)
+            return
 
     # ---- sp-DBA: timed run (HIP-graph replay of whole steps), then the same
     # steps eager with per-stage HIP events for the breakdown and the roofline

@@ -328,7 +328,7 @@ spdba_status spdba_device_views(spdba_plan plan, const double **d_ab, const uint
 /* Synchronising statistics of instance `inst`. */
 spdba_status spdba_stats(spdba_plan plan, int32_t inst, spdba_stats_t *out);
 
-/* Launch geometry (autotuner hook); never changes results: kernel 0 =
+/* Launch geometry (autotuner hook); kernels 0..4 never change results: kernel 0 =
  * indicator (value = waves per workgroup, power of two 1..16), 1 = persistent
  * active update (workgroups per compute unit, 1..64; both the block-list walk
  * and the strip walk), 2 = dense update (threads per workgroup, power of two
@@ -347,7 +347,12 @@ spdba_status spdba_stats(spdba_plan plan, int32_t inst, spdba_stats_t *out);
  * blocks of more than 256 slots, 3 on blocks of fewer than 64, 4 where its
  * conditions fail) the update runs as variant 0; on the half layout every variant runs that layout's own
  * block-list walk.  4 = strip-walk update (waves per workgroup, power of two
- * 1..16).
+ * 1..16).  5 = placement of the step's forward transform of the nonlinear
+ * term (CH and GS on the full layout, else EUNSUPPORTED for 1): 0 out of
+ * place into the right-hand-side buffer (default), 1 in place in the
+ * transform buffer, which the update then reads as its right-hand side (and
+ * spdba_apply fills).  rocFFT runs different kernels for the two, so this
+ * knob, unlike the others, changes the transform's FP32/FP64 rounding.
  * Resets the stage-time ring. */
 spdba_status spdba_set_launch(spdba_plan plan, int32_t kernel, int32_t value);
 

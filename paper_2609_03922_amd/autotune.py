@@ -12,6 +12,14 @@ apply).  Launch shape
 never changes results (the reductions it touches are order-free maxima), so
 tuning is safe between runs.  The activation block shape is not tuned: it
 changes the masks.
+
+The placement of the step's forward transform (out of place, or in place in
+the transform buffer; CH and GS on the full layout) is timed on the dense plan
+and cached under a key of its own without block shape or measure, so the dense
+and the sparse plans of one grid take the same transforms.  rocFFT runs
+different kernels for the two placements, which round differently, and which
+one is faster depends on the size (in place wins for 512^3 FP32 and large 2-D
+FP32 grids, loses for 256^3 and for FP64 3-D).
 """
 from __future__ import annotations
 
@@ -25,11 +33,12 @@ CANDIDATES = {
     1: (2, 4, 8, 16),          # list walk / persistent strip walk: workgroups per CU
     2: (128, 256, 512, 1024),  # dense update: threads per workgroup
     4: (2, 4, 8),              # strip-walk update: waves per workgroup
+    5: (0, 1),                 # forward transform: out of place / in place
 }
-DEFAULTS = {0: 4, 1: 4, 2: 256, 3: 1, 4: 4}
+DEFAULTS = {0: 4, 1: 4, 2: 256, 3: 1, 4: 4, 5: 0}
 # stage_ms entries a candidate is timed by: the update variants by compaction
 # plus update, since the strip walk folds the threshold pass into the update
-STAGE_OF = {0: (2,), 1: (3, 4), 2: (4,), 4: (3, 4)}
+STAGE_OF = {0: (2,), 1: (3, 4), 2: (4,), 4: (3, 4), 5: (0,)}
 
 
 def cache_key(descs, arch: str) -> str:
@@ -38,6 +47,14 @@ def cache_key(descs, arch: str) -> str:
     layout = "|half" if getattr(d, "half", False) else ""
     measure = ("|energy" if getattr(d, "block_energy", False) else "|state") if getattr(d, "state_indicator", False) else ""
     return f"{arch}|{d.op}|{d.dtype}|nd{d.ndim}|b{d.block}|n[{sizes}]{layout}{measure}"
+
+
+def fft_key(descs, arch: str) -> str:
+    """Cache key of the transform placement: no block shape, no measure."""
+    d = descs[0]
+    sizes = ",".join(str(x) for x in sorted((x.n for x in descs), reverse=True))
+    layout = "|half" if getattr(d, "half", False) else ""
+    return f"{arch}|{d.op}|{d.dtype}|nd{d.ndim}|n[{sizes}]{layout}|fft"
 
 
 def load_cache(path: str = CACHE_PATH) -> dict:
@@ -55,11 +72,25 @@ def save_cache(cache: dict, path: str = CACHE_PATH) -> None:
 
 
 def apply_cached(plan, arch: str, path: str = CACHE_PATH) -> dict | None:
-    entry = load_cache(path).get(cache_key(plan.descs, arch))
+    cache = load_cache(path)
+    entry = cache.get(cache_key(plan.descs, arch))
     if entry:
         for k, v in sorted(entry["choice"].items()):
             plan.set_launch(int(k), int(v))
+    fft = cache.get(fft_key(plan.descs, arch))
+    if fft:
+        for k, v in sorted(fft["choice"].items()):
+            plan.set_launch(int(k), int(v))
     return entry
+
+
+def _accepts(plan, k, v) -> bool:
+    try:
+        plan.set_launch(k, v)
+    except Exception:
+        return False
+    plan.set_launch(k, DEFAULTS[k])
+    return True
 
 
 def tune(make_plan, init_fields, steps: int = 20, arch: str = "gfx950", path: str | None = CACHE_PATH,
@@ -72,6 +103,7 @@ def tune(make_plan, init_fields, steps: int = 20, arch: str = "gfx950", path: st
     active fraction.  Returns {kernel: best value} and the timings; stores them
     in the cache when `path` is given."""
     result, timings = {}, {}
+    fft_choice, fkey = None, None
 
     def measure(plan, k, v, fixed):
         for fk, fv in fixed:
@@ -101,6 +133,10 @@ def tune(make_plan, init_fields, steps: int = 20, arch: str = "gfx950", path: st
             plan.step(warm)
         if dense:
             result[2], _ = sweep(plan, 2)
+            if _accepts(plan, 5, 1):
+                fft_choice, _ = sweep(plan, 5)
+                plan.set_launch(5, DEFAULTS[5])
+                fkey = fft_key(plan.descs, arch)
         else:
             result[0], _ = sweep(plan, 0)
             plan.set_launch(0, result[0])
@@ -120,6 +156,12 @@ def tune(make_plan, init_fields, steps: int = 20, arch: str = "gfx950", path: st
         plan.destroy()
     if path:
         cache = load_cache(path)
-        cache[key] = {"choice": {str(k): v for k, v in result.items()}, "stage_ms": timings}
+        cache[key] = {"choice": {str(k): v for k, v in result.items()},
+                      "stage_ms": {t: v for t, v in timings.items() if not t.startswith("5:")}}
+        if fkey is not None:
+            cache[fkey] = {"choice": {"5": fft_choice},
+                           "stage_ms": {t: v for t, v in timings.items() if t.startswith("5:")}}
         save_cache(cache, path)
+    if fft_choice is not None:
+        result[5] = fft_choice
     return result, timings

@@ -95,6 +95,8 @@ struct spdba_plan_s {
     int run_lmax = 0;      // run walk: longest piece in blocks, 0 where the walk does not apply
     int run_ub = 0;        // run walk: slots per block / 64
     int upd_waves = 4;     // strip walk: waves per workgroup
+    bool fwd_in_place = false;  // CH/GS full layout: the step's forward transform runs in place in W,
+                                // which then holds the right-hand side the update reads
     int max_slots = 0;     // largest block in 16-byte lane slots
     int min_slots = 0;     // smallest block in 16-byte lane slots
     bool list_stale = false;  // the ordered active list lags the mask
@@ -349,7 +351,12 @@ spdba_status exec_fft(spdba_plan p, const Fft &f, void *in, void *out) {
 
 char *state_ptr(spdba_plan p, int64_t elem_off) { return p->d_state + p->st_spec + elem_off * p->esize; }
 char *work_ptr(spdba_plan p, int64_t elem_off) { return p->d_work + p->w_W + elem_off * p->esize; }
-char *rhs_ptr(spdba_plan p, int64_t elem_off) { return p->d_work + p->w_R + elem_off * p->esize; }
+// the right-hand side: R, or W when the forward transform runs in place
+char *rhs_ptr(spdba_plan p, int64_t elem_off) {
+    return p->d_work + (p->fwd_in_place ? p->w_W : p->w_R) + elem_off * p->esize;
+}
+// the full layout's CH/GS step can take its forward transform in place
+bool fwd_in_place_ok(spdba_plan p) { return !p->half && (p->op == OP_CH || p->op == OP_GS); }
 // XPFC: history slot `slot` (0..3) of the nonlinear transforms
 char *hist_ptr(spdba_plan p, int slot, int64_t elem_off) {
     return p->d_state + p->st_hist + ((size_t)slot * (size_t)p->total_elems + (size_t)elem_off) * p->esize;
@@ -519,9 +526,11 @@ spdba_status enqueue_step(spdba_plan p) {
         record(p, 1);
         TRY_HIP(launch_nonlinear(p->ctx, d, p->nl_waves, p->stream));
         record(p, 2);
-        for (auto &g : p->groups)
-            TRY(exec_fft(p, g.fwd_oop, work_ptr(p, g.off),
-                         p->op == OP_XPFC ? hist_ptr(p, p->xphase, g.off) : rhs_ptr(p, g.off)));
+        for (auto &g : p->groups) {
+            if (p->fwd_in_place) TRY(exec_fft(p, g.fwd_ip, work_ptr(p, g.off), nullptr));
+            else TRY(exec_fft(p, g.fwd_oop, work_ptr(p, g.off),
+                              p->op == OP_XPFC ? hist_ptr(p, p->xphase, g.off) : rhs_ptr(p, g.off)));
+        }
         TRY(fill_history(p));  // XPFC, first step of a new field (eager)
         if (p->op == OP_GS && !d) TRY_HIP(launch_k0_rhs(p->ctx, p->stream));
         record(p, 3);
@@ -902,6 +911,7 @@ spdba_status spdba_plan_create(const spdba_instance_desc *inst, int32_t n_inst, 
             if ((st = create_fft(p, I, g.inv_oop, false, false, batch))) break;
             if ((st = create_fft(p, I, g.fwd_oop, true, false, batch))) break;
             if ((st = create_fft(p, I, g.inv_ip, false, true, batch))) break;
+            if (fwd_in_place_ok(p) && (st = create_fft(p, I, g.fwd_ip, true, true, batch))) break;
             if ((st = create_fft(p, I, g.inv1_oop, false, false, p->nspec))) break;
             if ((st = create_fft(p, I, g.fwd1_ip, true, true, p->nspec))) break;
             if ((st = create_fft(p, I, g.inv1_ip, false, true, p->nspec))) break;
@@ -1013,6 +1023,7 @@ spdba_status spdba_plan_audit(const spdba_instance_desc *inst, int32_t n_inst, c
             for (int k = 0; k < 4; ++k) fft(gs + " forward", L, work_ptr(p, g.off), W, hist_ptr(p, k, g.off), hist[k]);
         } else {
             fft(gs + " forward", L, work_ptr(p, g.off), W, rhs_ptr(p, g.off), R);
+            fft(gs + " forward in place", L, work_ptr(p, g.off), W, nullptr, W);
         }
         for (int i = 0; i < n_inst; ++i) {
             if (p->group_of[i] != (int)gi) continue;
@@ -1055,7 +1066,7 @@ spdba_status spdba_plan_bind(spdba_plan p, void *d_state, void *d_work) {
     c.dense = p->dense ? 1 : 0;
     c.state = p->d_state + p->st_spec;
     c.work = p->d_work + p->w_W;
-    c.rhs = p->d_work + p->w_R;
+    c.rhs = rhs_ptr(p, 0);
     c.k0 = reinterpret_cast<double *>(p->d_state + p->st_k0);
     c.rhs_k0 = reinterpret_cast<double *>(p->d_work + p->w_rk0);
     c.a_b = reinterpret_cast<double *>(p->d_work + p->w_ab);
@@ -1550,6 +1561,12 @@ spdba_status spdba_set_launch(spdba_plan p, int32_t kernel, int32_t value) {
         case 2: if (!pow2_in(value, 64, 1024)) return SPDBA_EINVAL; p->dense_threads = value; break;
         case 3: if (value < 0 || value > 4) return SPDBA_EINVAL; p->upd_mode = value; break;
         case 4: if (!pow2_in(value, 1, 16)) return SPDBA_EINVAL; p->upd_waves = value; break;
+        case 5:
+            if (value != 0 && value != 1) return SPDBA_EINVAL;
+            if (value && !fwd_in_place_ok(p)) return SPDBA_EUNSUPPORTED;
+            p->fwd_in_place = value != 0;
+            if (p->bound) p->ctx.rhs = rhs_ptr(p, 0);
+            break;
         default: return SPDBA_EINVAL;
     }
     p->ring_filled = 0;  // timings of the previous geometry are stale

@@ -33,6 +33,7 @@ class FakePlan:
 
     def stats(self, i):
         st = [0.0] * 5
+        st[0] = 2.0 - 0.5 * self.launch.get(5, 0)  # transforms: in place faster here
         if self.dense:
             st[4] = 1.0 / self.launch.get(2, 256)
         else:
@@ -54,8 +55,32 @@ def test_tune_keys_the_sparse_plan_and_keeps_the_fastest_variant(tmp_path):
     assert res[3] == 3 and res[1] == 8 and res[0] == 1 and res[2] == 1024
     assert "wave 1:8" in timings and "list4 1:4" in timings and "run 1:4" in timings
     cache = A.load_cache(path)
-    assert list(cache) == [A.cache_key(sparse, "gfx950")]
+    assert sorted(cache) == sorted([A.cache_key(sparse, "gfx950"), A.fft_key(sparse, "gfx950")])
     assert cache[A.cache_key(sparse, "gfx950")]["choice"]["3"] == 3
+    # the transform placement: timed on the dense plan, cached without block shape or measure
+    assert res[5] == 1 and cache[A.fft_key(sparse, "gfx950")]["choice"] == {"5": 1}
+    assert "5" not in cache[A.cache_key(sparse, "gfx950")]["choice"]
+    assert A.fft_key([_desc()], "gfx950") == A.fft_key(sparse, "gfx950") == "gfx950|ch|f32|nd3|n[64]|fft"
+    # both plans of the grid take it
+    for descs in (sparse, [_desc()]):
+        p = FakePlan(descs, False)
+        A.apply_cached(p, "gfx950", path=path)
+        assert p.launch[5] == 1
+
+
+def test_tune_skips_the_placement_a_plan_refuses(tmp_path):
+    class NoInPlace(FakePlan):
+        def set_launch(self, k, v):
+            if k == 5 and v:
+                raise RuntimeError("EUNSUPPORTED")
+            super().set_launch(k, v)
+
+    sparse = [_desc(state_indicator=True)]
+    path = str(tmp_path / "cache.json")
+    res, _ = A.tune(lambda dense: NoInPlace([_desc()] if dense else sparse, dense), lambda p: None, steps=1,
+                    path=path)
+    assert 5 not in res
+    assert list(A.load_cache(path)) == [A.cache_key(sparse, "gfx950")]
 
 
 def test_bench_names_the_update_kernel_of_the_tuned_variant():
