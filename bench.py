@@ -1576,7 +1576,7 @@ def mdbp_bench(args, cfg):
         "update_stage_speedup_vs_dense": round(st_d[0] / max(1e-9, st_sp[0]), 4),
         "roofline": {"bound": "hbm", "achieved": round(lin_bytes / (st_sp[0] * 1e-3) / 1e9, 1), "peak": 8000.0,
                      "unit": "GB/s", "frac": round(lin_bytes / (st_sp[0] * 1e-3) / 1e9 / 8000.0, 4), "traffic": None,
-                     "kernel": "linear half-steps (k_md_measure + k_md_compact + k_md_update), per step",
+                     "kernel": "linear half-steps (k_md_measure, the shared G and compaction stage, k_md_update), per step",
                      "bytes_per_step": int(lin_bytes), "active_blocks_mean": round(act_sp, 1),
                      "dense_achieved": round(dense_bytes / (st_d[0] * 1e-3) / 1e9, 1),
                      "run": f"eager, stage events, last {min(50, K)} steps"},

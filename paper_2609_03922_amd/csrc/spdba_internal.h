@@ -189,13 +189,13 @@ hipError_t launch_copy8(const void *src, void *dst, size_t bytes, hipStream_t s)
 hipError_t launch_check_pattern(const void *buf, int64_t n_elems, bool dbl, uint32_t *bad, hipStream_t s);
 
 // The block-activity stage that every plan type runs with the same kernels
-// (k_gmax, k_compact_count, k_compact_write): G = max_b a_b, where the blocks
-// the last update stored (mask nonzero) first take the measure it kept
-// (a_next); then the threshold rule a_b > fl(tau^2) G (block 0 always active
-// when pinned), the mask and the ascending list of active blocks with its
-// count.  One instance, no skip set.  A caller whose measure pass rewrites
-// every a_b clears the mask in that pass, so nothing is merged; without a kept
-// measure a_next may alias a_b.
+// (k_gmax, k_compact_append): G = max_b a_b, where the blocks the last update
+// stored (mask nonzero) first take the measure it kept (a_next); then the
+// threshold rule a_b > fl(tau^2) G (block 0 always active when pinned), the
+// mask and the list of active blocks (ascending within chunks of 1024 blocks,
+// chunks in arrival order) with its count.  One instance, no skip set.  A
+// caller whose measure pass rewrites every a_b clears the mask in that pass,
+// so nothing is merged; without a kept measure a_next may alias a_b.
 struct BlockStage {
     int64_t nb;
     double *a_b;
@@ -204,7 +204,7 @@ struct BlockStage {
     uint32_t *list, *count;
     unsigned long long *G;     // zero before the stage (the caller clears it)
     void *aux;                 // block_stage_bytes(nb) bytes of device memory, 256-byte aligned:
-                               // the instance record, the block owner table, chunk counts
+                               // the instance record and the block owner table
 };
 size_t block_stage_bytes(int64_t nb);
 // fills aux (instance record with tau^2 and the pin flag, owner table) on s

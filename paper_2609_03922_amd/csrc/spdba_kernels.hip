@@ -1093,8 +1093,9 @@ __device__ __forceinline__ void append_bits(const Ctx &c, uint32_t bits, int64_t
 // blocks, then one atomic append of the chunk's active blocks (ascending
 // within the chunk).  The update needs no global order; the ordered list the
 // API returns is rebuilt from the mask when it is read.  The last workgroup to
-// arrive hands G over, as the strip walk does.  The indicator clears the
-// counter.
+// arrive hands G over, as the strip walk does (not when G_last is null: the
+// block-activity stage of the other plan types keeps G).  The indicator clears
+// the counter.
 __global__ void __launch_bounds__(256) k_compact_append(Ctx c) {
     __shared__ uint32_t wsum[4];
     __shared__ uint32_t base;
@@ -1111,7 +1112,7 @@ __global__ void __launch_bounds__(256) k_compact_append(Ctx c) {
     }
     append_bits(c, bits, b0, wsum, base);
     // every G read of this workgroup happened before the barriers above
-    if (threadIdx.x == 0) {
+    if (c.G_last && threadIdx.x == 0) {
         const unsigned int done = atomicAdd(c.done, 1u);
         if (done == gridDim.x - 1) {
             for (int i = 0; i < c.n_inst; ++i) {
@@ -3252,15 +3253,13 @@ hipError_t launch_compact(const Ctx &c, hipStream_t s, int from_mask) {
     return hipGetLastError();
 }
 
-// aux of a BlockStage: the instance record, the owner table (all instance 0),
-// the chunk counts of the ordered compaction, each 256-byte aligned
+// aux of a BlockStage: the instance record and the owner table (all
+// instance 0), each 256-byte aligned
 static size_t stage_al(size_t o) { return (o + 255) & ~(size_t)255; }
 static int64_t stage_chunks(int64_t nb) { return (nb + CHUNK_BLOCKS - 1) / CHUNK_BLOCKS; }
 
 size_t block_stage_bytes(int64_t nb) {
-    size_t o = stage_al(sizeof(InstDev));
-    o = stage_al(o + sizeof(uint16_t) * (size_t)nb);
-    return stage_al(o + sizeof(uint32_t) * (size_t)stage_chunks(nb));
+    return stage_al(stage_al(sizeof(InstDev)) + sizeof(uint16_t) * (size_t)nb);
 }
 
 static Ctx stage_ctx(const BlockStage &b) {
@@ -3269,14 +3268,12 @@ static Ctx stage_ctx(const BlockStage &b) {
     c.inst = reinterpret_cast<const InstDev *>(aux);
     c.n_inst = 1;
     c.blk_inst = reinterpret_cast<const uint16_t *>(aux + stage_al(sizeof(InstDev)));
-    c.chunk_cnt =
-        reinterpret_cast<uint32_t *>(aux + stage_al(stage_al(sizeof(InstDev)) + sizeof(uint16_t) * (size_t)b.nb));
     c.a_b = b.a_b;
     c.a_next = const_cast<double *>(b.a_next);
     c.mask = b.mask;
     c.worklist = b.list;
     c.count = b.count;
-    c.G = b.G;
+    c.G = b.G;  // G_last stays null: the append keeps G
     c.nb_total = b.nb;
     c.n_chunks = stage_chunks(b.nb);
     return c;
@@ -3297,9 +3294,9 @@ hipError_t block_stage_init(const BlockStage &b, double tau2, int pin, hipStream
 
 hipError_t launch_block_stage(const BlockStage &b, hipStream_t s) {
     const Ctx c = stage_ctx(b);
-    hipError_t e = launch_gmax(c, s);
+    hipError_t e = launch_gmax(c, s);  // also clears the list counter
     if (e != hipSuccess) return e;
-    return launch_compact(c, s, 0);
+    return launch_compact_append(c, s);
 }
 
 template <typename T, int OP>

@@ -6,7 +6,7 @@
 //                  eight contiguous ranges (k_md_measure_small for blocks of
 //                  at most 64 bins: a thread per bin, a max over lane groups);
 //                  both clear the mask of the blocks they measure
-//   G, the threshold, the mask and the ascending list of active blocks: the
+//   G, the threshold, the mask and the list of active blocks: the
 //                  block-activity stage of the main plan (spdba::launch_block_stage)
 //   k_md_update    persistent walk of the list, one list segment per XCD; per
 //                  bin the M modes in registers, then E'_m = h(omega) sum_j

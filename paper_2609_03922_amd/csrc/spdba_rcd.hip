@@ -7,7 +7,7 @@
 //   k_rcd_measure    per block: a_b = max over modes of sum_m |q_m|^2 (FP64,
 //                    components in order, k = 0 left out); one workgroup per
 //                    block; clears the block's mask (no kept measure to merge)
-//   G, the threshold, the mask and the ascending list of active blocks: the
+//   G, the threshold, the mask and the list of active blocks: the
 //                    block-activity stage of the main plan (spdba::launch_block_stage;
 //                    after an update G merges the measure the update kept for
 //                    the blocks it stored)
