@@ -89,6 +89,10 @@ CASES = [
     (D("gs", "f64", 2, 32, 4, 1e-3), 0.3, 5),
     (D("ch", "f32", 3, 32, 8, 1e-3, state_indicator=True), 0.02, 6),
     (D("ch", "f64", 2, 64, 2, 1e-3), 0.2, 7),   # blocks of two columns: X_0 is columns 0 and 1
+    # the largest grids the half layout takes (2^18 points)
+    (D("ch", "f32", 2, 512, 16, 1e-3), 0.08, 8),
+    (D("gs", "f32", 3, 64, 8, 1e-3), 0.05, 9),
+    (D("ch", "f64", 3, 64, 4, 1e-3, state_indicator=True), 0.01, 10),
 ]
 
 
@@ -146,16 +150,19 @@ def test_half_state_measure_sequence_with_transitions():
     plan.destroy()
 
 
-def test_half_f64_control_trajectory():
+@pytest.mark.parametrize("ndim,steps", [(2, 48), (3, 30)])
+def test_half_f64_control_trajectory(ndim, steps):
     """FP64 steps with transitions, refresh, an initial full window and the
     threshold controller: every step's states and the threshold trace equal
-    the oracle's, the field within 1e-10."""
+    the oracle's, the field within 1e-10 (64^2, and 64^3 at the layout's
+    largest size)."""
     import torch
 
-    n, steps = 64, 48
-    d = D("ch", "f64", 2, n, 8, 1e-4, refresh=7, full_steps=2, target_ratio=0.35, control_interval=3,
+    n = 64
+    d = D("ch", "f64", ndim, n, 8, 1e-4, refresh=7, full_steps=2, target_ratio=0.35, control_interval=3,
           deadband=0.1)
-    c0 = inputs.uniform_field(1111, 0, (n, n), 0.0, 0.05)
+    shape = (n,) * ndim
+    c0 = inputs.uniform_field(1111, 0, shape, 0.0, 0.05)
     ref = O.step(oracle_inst(d), O.rfft(c0), steps, masks=True, ab=True)
     plan = S.Plan([d])
     plan.set_field(0, torch.from_numpy(c0.ravel()))
@@ -169,9 +176,9 @@ def test_half_f64_control_trajectory():
         if st + 1 < steps:
             assert s["tau"] == ref["tau"][st + 1], (st, s["tau"], ref["tau"][st + 1])
     got = plan.get_field(0).cpu().numpy()
-    want = O.irfft(ref["state"].reshape(n, n // 2 + 1), (n, n)).ravel()
+    want = O.irfft(ref["state"].reshape(*shape[:-1], n // 2 + 1), shape).ravel()
     err = np.linalg.norm(got - want) / np.linalg.norm(want - want.mean())
-    print(f"half control trajectory: states {sorted(seen)}, tau {ref['tau'][0]:.3g} -> {ref['tau'][-1]:.3g}, "
+    print(f"half control trajectory {ndim}-D: states {sorted(seen)}, tau {ref['tau'][0]:.3g} -> {ref['tau'][-1]:.3g}, "
           f"rel-L2 {err:.3e}", flush=True)
     assert seen == {0, 1, 2}
     assert len(np.unique(ref["tau"])) >= 3
