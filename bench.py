@@ -1585,27 +1585,43 @@ def mdbp_bench(args, cfg):
     print(json.dumps(line))
 
 
-def rcd_cpu_baseline(cfg, u0, np):
+def rcd_cpu_baseline(cfg, u0, np, budget=20.0):
     """The oracle's full steps on a bounded sample: the workload's parameters
-    and start on the leading 128^3 corner of its field (four steps, one BLAS
-    thread; the oracle's own transforms run on one core), scaled to grid points
-    per second."""
+    and start on a leading cubic corner of its field (one BLAS thread; the
+    oracle's own transforms run on one core), scaled to grid points per
+    second.  One step on the smallest corner calibrates the cost (its work
+    grows with the corner's volume); the reported sample is the largest
+    corner (to 128^3) and step count (to 4) estimated to fit the budget."""
     import time
 
     from threadpoolctl import threadpool_limits
 
     from oracle import rcd as OR
 
-    M, s, steps = cfg["M"], 128, 4
-    u = u0[:, :s, :s, :s]
-    q = np.stack([np.fft.fftn(u[m]).ravel() for m in range(M)])
-    with threadpool_limits(1):
-        t0 = time.perf_counter()
-        OR.step(q, steps, (s, s, s), (cfg["block"],) * 3, cfg["taus"][0], cfg["dt"], cfg["dx"], cfg["d_diag"],
-                cfg["d_cross"], cfg["alpha"], cfg["beta"], cfg["r"], cfg["a"])
-        dt = time.perf_counter() - t0
-    return {"value": round(steps * s ** 3 / dt / 1e9, 6), "unit": "Gpts/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} full FP64 steps of the workload at 128^3 (M = {M}), {dt:.1f} s"}
+    M, n, bl = cfg["M"], cfg["n"], cfg["block"]
+
+    def run(s, steps):
+        print(f"rcd CPU oracle: {steps} step(s) at {s}^3 x {M}", file=sys.stderr, flush=True)
+        u = u0[:, :s, :s, :s]
+        q = np.stack([np.fft.fftn(u[m]).ravel() for m in range(M)])
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            OR.step(q, steps, (s, s, s), (bl,) * 3, cfg["taus"][0], cfg["dt"], cfg["dx"], cfg["d_diag"],
+                    cfg["d_cross"], cfg["alpha"], cfg["beta"], cfg["r"], cfg["a"])
+            return time.perf_counter() - t0
+
+    s0 = max(16, bl)
+    t1 = run(s0, 1)
+    s, steps = s0, 1
+    for cs in (16, 32, 64, 128):
+        if cs < s0 or cs > n:
+            continue
+        for st in (1, 2, 3, 4):
+            if t1 * (cs / s0) ** 3 * st <= budget and cs ** 3 * st > s ** 3 * steps:
+                s, steps = cs, st
+    dt = t1 if (s, steps) == (s0, 1) else run(s, steps)
+    return {"value": float(f"{steps * s ** 3 / dt / 1e9:.4g}"), "unit": "Gpts/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} full FP64 step(s) of the workload on its leading {s}^3 corner (M = {M}), {dt:.1f} s"}
 
 
 def oracle_baseline(cfg, descs, sizes, inputs, np, budget=10.0, one_core=True, measure="increment"):

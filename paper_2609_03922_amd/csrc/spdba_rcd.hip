@@ -482,7 +482,6 @@ __global__ void __launch_bounds__(256) k_rcd_update_mfma(RCtx c) {
     __shared__ T ws[MM * SB];   // W
     __shared__ T laml[MM];
     __shared__ T dks[NC / 2];
-    __shared__ int64_t eofs[NC / 2];
     __shared__ double red[4];
     const T *vsrc = reinterpret_cast<const T *>(c.vt);  // V^T, zero-padded
     for (int k = threadIdx.x; k < MM * MM; k += blockDim.x) {
@@ -502,88 +501,123 @@ __global__ void __launch_bounds__(256) k_rcd_update_mfma(RCtx c) {
     const int64_t seg = (total + 7) >> 3;
     const int64_t lo = std::min<int64_t>(total, seg * xcd), hi = std::min<int64_t>(total, seg * (xcd + 1));
     const int row = lane & 15, kq = lane >> 4;  // MFMA operand position of this lane
-    for (int64_t ent = lo + (blockIdx.x >> 3); ent < hi; ent += per) {
-        const int64_t b = c.dense ? ent : (int64_t)c.list[ent];
-        double amax = 0.0;
-        for (int s0 = 0; s0 < c.g.bvol; s0 += NC / 2) {
-            const int nm = min(NC / 2, c.g.bvol - s0);  // modes in this chunk
-            if (t < NC / 2) {
-                int64_t e = 0;
-                double k2 = 0.0;
-                if (t < nm) mode_of(c.g, b, s0 + t, e, k2);
-                eofs[t] = e;
-                dks[t] = (T)(c.dt * k2);
-            }
-            __syncthreads();
-            for (int k = t; k < MM * (NC / 2); k += blockDim.x) {
-                const int i = k / (NC / 2), md = k - i * (NC / 2);
-                T bx = (T)0, by = (T)0;
-                if (i < M && md < nm) {
-                    const int64_t e = eofs[md];
-                    const V2 v = q[i * N + e], f = rh[i * N + e];
-                    bx = fma(dt, f.x, v.x);
-                    by = fma(dt, f.y, v.y);
-                }
-                bs[i * SB + 2 * md] = bx;
-                bs[i * SB + 2 * md + 1] = by;
-            }
-            __syncthreads();
-            // W = V^T B, scaled; tiles (jt, ct) dealt to the four waves
-            for (int tile = wave; tile < (MM / 16) * (NC / 16); tile += 4) {
-                const int jt = tile / (NC / 16), ct = tile - jt * (NC / 16);
-                v4 acc = {(T)0, (T)0, (T)0, (T)0};
-                for (int k0 = 0; k0 < MM; k0 += 4) {
-                    const T av = vtl[(jt * 16 + row) * SA + k0 + kq];
-                    const T bv = bs[(k0 + kq) * SB + ct * 16 + row];
-                    acc = RMf<T>::mac(av, bv, acc);
-                }
-                const int col = ct * 16 + row;
-                const T dk = dks[col >> 1];
+    // The chunks of the workgroup's blocks run as one sequence, and the
+    // global loads of the next chunk are issued before the current chunk's
+    // two products, so the memory traffic overlaps the matrix-core work.
+    // Thread t holds mode t % 64 of the chunk (its offset and dt k^2 in
+    // registers) for components t / 64 + 4 j.
+    constexpr int PT = MM / 4;
+    V2 pv[PT], pf[PT];
+    int64_t pb = 0, pe = 0;
+    int pnm = 0;
+    T pdk = (T)0;
+    auto fetch = [&](int64_t en, int s) {  // workgroup-uniform arguments
+        pb = c.dense ? en : (int64_t)c.list[en];
+        pnm = min(NC / 2, c.g.bvol - s);
+        double k2 = 0.0;
+        pe = 0;
+        if (lane < pnm) mode_of(c.g, pb, s + lane, pe, k2);
+        pdk = (T)(c.dt * k2);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int j = jt * 16 + RMf<T>::drow(kq, r);
-                    ws[j * SB + col] = acc[r] * ((T)1 / ((T)1 + dk * laml[j]));
-                }
+        for (int j = 0; j < PT; ++j) {
+            const int i = wave + 4 * j;
+            V2 v, f;
+            v.x = v.y = f.x = f.y = (T)0;
+            if (i < M && lane < pnm) {
+                v = q[i * N + pe];
+                f = rh[i * N + pe];
             }
-            __syncthreads();
-            // X = V W into bs
-            for (int tile = wave; tile < (MM / 16) * (NC / 16); tile += 4) {
-                const int mt = tile / (NC / 16), ct = tile - mt * (NC / 16);
-                v4 acc = {(T)0, (T)0, (T)0, (T)0};
-                for (int k0 = 0; k0 < MM; k0 += 4) {
-                    const T av = vl[(mt * 16 + row) * SA + k0 + kq];
-                    const T bv = ws[(k0 + kq) * SB + ct * 16 + row];
-                    acc = RMf<T>::mac(av, bv, acc);
-                }
-                const int col = ct * 16 + row;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) bs[(mt * 16 + RMf<T>::drow(kq, r)) * SB + col] = acc[r];
-            }
-            __syncthreads();
-            for (int k = t; k < M * (NC / 2); k += blockDim.x) {
-                const int i = k / (NC / 2), md = k - i * (NC / 2);
-                if (md < nm) {
-                    V2 o;
-                    o.x = bs[i * SB + 2 * md];
-                    o.y = bs[i * SB + 2 * md + 1];
-                    q[i * N + eofs[md]] = o;
-                }
-            }
-            if (c.keep && t < nm) {  // the measure of what is stored, components in order
-                double acc = 0.0;
-                for (int i = 0; i < M; ++i) acc = acc + rsq2((double)bs[i * SB + 2 * t], (double)bs[i * SB + 2 * t + 1]);
-                if (eofs[t] == 0) acc = 0.0;
-                amax = fmax(amax, acc);
-            }
-            __syncthreads();  // bs, eofs and dks are free for the next chunk
+            pv[j] = v;
+            pf[j] = f;
         }
-        if (c.keep) {  // workgroup-uniform
+    };
+    int64_t ent = lo + (blockIdx.x >> 3);
+    int s0 = 0;
+    if (ent < hi) fetch(ent, 0);
+    double amax = 0.0;
+    while (ent < hi) {  // workgroup-uniform
+        const int64_t b = pb, e = pe;
+        const int nm = pnm;
+#pragma unroll
+        for (int j = 0; j < PT; ++j) {
+            const int i = wave + 4 * j;
+            T bx = (T)0, by = (T)0;
+            if (i < M && lane < nm) {
+                bx = fma(dt, pf[j].x, pv[j].x);
+                by = fma(dt, pf[j].y, pv[j].y);
+            }
+            bs[i * SB + 2 * lane] = bx;
+            bs[i * SB + 2 * lane + 1] = by;
+        }
+        if (wave == 0) dks[lane] = pdk;
+        __syncthreads();
+        // the next chunk: its loads fly while this one is multiplied
+        int s1 = s0 + NC / 2;
+        int64_t ent1 = ent;
+        const bool last = s1 >= c.g.bvol;  // the block's last chunk
+        if (last) {
+            s1 = 0;
+            ent1 += per;
+        }
+        if (ent1 < hi) fetch(ent1, s1);
+        // W = V^T B, scaled; tiles (jt, ct) dealt to the four waves
+        for (int tile = wave; tile < (MM / 16) * (NC / 16); tile += 4) {
+            const int jt = tile / (NC / 16), ct = tile - jt * (NC / 16);
+            v4 acc = {(T)0, (T)0, (T)0, (T)0};
+            for (int k0 = 0; k0 < MM; k0 += 4) {
+                const T av = vtl[(jt * 16 + row) * SA + k0 + kq];
+                const T bv = bs[(k0 + kq) * SB + ct * 16 + row];
+                acc = RMf<T>::mac(av, bv, acc);
+            }
+            const int col = ct * 16 + row;
+            const T dk = dks[col >> 1];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = jt * 16 + RMf<T>::drow(kq, r);
+                ws[j * SB + col] = acc[r] * ((T)1 / ((T)1 + dk * laml[j]));
+            }
+        }
+        __syncthreads();
+        // X = V W into bs
+        for (int tile = wave; tile < (MM / 16) * (NC / 16); tile += 4) {
+            const int mt = tile / (NC / 16), ct = tile - mt * (NC / 16);
+            v4 acc = {(T)0, (T)0, (T)0, (T)0};
+            for (int k0 = 0; k0 < MM; k0 += 4) {
+                const T av = vl[(mt * 16 + row) * SA + k0 + kq];
+                const T bv = ws[(k0 + kq) * SB + ct * 16 + row];
+                acc = RMf<T>::mac(av, bv, acc);
+            }
+            const int col = ct * 16 + row;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bs[(mt * 16 + RMf<T>::drow(kq, r)) * SB + col] = acc[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PT; ++j) {
+            const int i = wave + 4 * j;
+            if (i < M && lane < nm) {
+                V2 o;
+                o.x = bs[i * SB + 2 * lane];
+                o.y = bs[i * SB + 2 * lane + 1];
+                q[i * N + e] = o;
+            }
+        }
+        if (c.keep && t < nm) {  // the measure of what is stored, components in order
+            double acc = 0.0;
+            for (int i = 0; i < M; ++i) acc = acc + rsq2((double)bs[i * SB + 2 * t], (double)bs[i * SB + 2 * t + 1]);
+            if (e == 0) acc = 0.0;
+            amax = fmax(amax, acc);
+        }
+        if (c.keep && last) {  // workgroup-uniform
             amax = rwave_max(amax);
             if (lane == 0) red[wave] = amax;
             __syncthreads();
             if (t == 0) c.anext[b] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-            __syncthreads();
+            amax = 0.0;
         }
+        __syncthreads();  // bs, dks and red are free for the next chunk
+        ent = ent1;
+        s0 = s1;
     }
 }
 
