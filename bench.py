@@ -1097,12 +1097,10 @@ def c5_proposer(cfg, make, truth, tnorm, tau, A, K, H, P, np, torch, log):
     return out
 
 
-def profiled_traffic_ratio(kernel: str, workload: str):
+def profiled_traffic_ratio(kernel: str, workload: str, source: str = "spdba_kernels.hip"):
     """HBM traffic over algorithmic bytes of a kernel from its committed
-    rocprofv3 PMC summary (the same workload and window), or None when the
-    kernel's source changed since the counters were taken."""
-    import hashlib
-
+    rocprofv3 PMC summary (the same workload), or None when the kernel's
+    source (in csrc/<source>) changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -1111,7 +1109,7 @@ def profiled_traffic_ratio(kernel: str, workload: str):
         if ":" in line and not line.startswith(("|", "#", "`")):
             k, _, v = line.partition(":")
             vals[k.strip()] = v.strip()
-    src = open(os.path.join(ROOT, "paper_2609_03922_amd", "csrc", "spdba_kernels.hip")).read()
+    src = open(os.path.join(ROOT, "paper_2609_03922_amd", "csrc", source)).read()
     try:
         sha = kernel_source_sha(src, [f.strip() for f in vals["kernel_source_functions"].split(",")])
     except (KeyError, ValueError):
@@ -1437,9 +1435,16 @@ def rcd_bench(args, cfg):
                 "unit": "TFLOP/s", "frac": round(fl / (st_sp[3] * 1e-3) / 1e12 / 157.3, 4),
                 "flops_per_launch": int(fl), "hbm_GBps": round(achieved, 1),
                 "dense_achieved": round(fd / (st_d[3] * 1e-3) / 1e12, 2)}
-    roof.update({"traffic": None, "kernel": "k_rcd_update" if M <= 16 else "k_rcd_update_mfma",
+    kname = "k_rcd_update" if M <= 16 else "k_rcd_update_mfma"
+    roof.update({"traffic": None, "kernel": kname,
                  "avg_launch_us": round(st_sp[3] * 1e3, 2), "active_blocks_mean": round(act_sp, 1),
                  "run": f"eager, stage events, last {min(20, K)} steps"})
+    # HBM traffic per byte from the PMC summary of an every-block dispatch of
+    # the same workload, applied to this launch's algorithmic bytes
+    ratio = profiled_traffic_ratio(kname, cfg["name"], source="spdba_rcd.hip")
+    if ratio is not None:
+        roof["traffic"] = int(ratio * upd_bytes)
+        roof["traffic_over_algorithmic"] = ratio
     line = {
         "metric": "spectral-update Gpts/s + steps/s, sp-DBA vs dense on GPU at fixed L2 error",
         "value": round(N * sps / 1e9, 4), "unit": "Gpts/s", "n_gpus": 1, "steps": K, "warmup": W,
