@@ -201,8 +201,6 @@ __global__ void __launch_bounds__(256) k_md_update_mfma(MCtx c) {
     constexpr int R = 2 * MM, NC = 64, SA = R + 4, SB = NC + 16;
     __shared__ float wa[R * SA];  // the real form of W
     __shared__ float bs[R * SB];  // B, then X
-    __shared__ int64_t eofs[NC];
-    __shared__ float2 hs[NC];     // h(omega) of the chunk's bins
     const float2 *wsrc = reinterpret_cast<const float2 *>(c.W);  // [MM][MM] complex, zero-padded
     for (int k = threadIdx.x; k < MM * MM; k += blockDim.x) {
         const int i = k / MM, j = k - i * MM;
@@ -222,69 +220,95 @@ __global__ void __launch_bounds__(256) k_md_update_mfma(MCtx c) {
     const int64_t lo = std::min<int64_t>(total, seg * xcd), hi = std::min<int64_t>(total, seg * (xcd + 1));
     const int row = lane & 15, kq = lane >> 4;
     const double att = exp(-c.alpha * c.dz / 4.0);
-    // chunks of 64 bins: NC / B blocks of the list per chunk when B < 64
+    // chunks of 64 bins: NC / B blocks of the list per chunk when B < 64.
+    // The chunks of the workgroup run as one sequence, and the global loads
+    // of the next chunk are issued before the current chunk's product.
+    // Thread t holds bin t % 64 of the chunk (its offset and h(omega) in
+    // registers) for the modes t / 64 + 4 j.
     const int bpc = c.B < NC ? NC / c.B : 1;
-    for (int64_t base = lo + (int64_t)(blockIdx.x >> 3) * bpc; base < hi; base += (int64_t)per * bpc) {
-        const int nblk = (int)std::min<int64_t>(bpc, hi - base);
-        for (int s0 = 0; s0 < (bpc > 1 ? 1 : c.B); s0 += NC) {  // blocks of at least 64 bins: in chunks
-            const int nm = bpc > 1 ? nblk * c.B : min(NC, c.B - s0);
-            if (t < NC) {
-                int64_t e = 0;
-                if (t < nm) {
-                    const int64_t b = bpc > 1 ? (c.dense ? base + t / c.B : (int64_t)c.list[base + t / c.B]) :
-                                                (c.dense ? base : (int64_t)c.list[base]);
-                    e = (b << c.lB) + (bpc > 1 ? (t & (c.B - 1)) : s0 + t);
-                }
-                eofs[t] = e;
-                const int64_t si = e <= ((n - 1) >> 1) ? e : e - n;
-                const double om = 6.283185307179586476925286766559 * (double)si / c.T;
-                double sp, cp;
-                sincos(c.beta2 * 0.5 * om * om * c.dz * 0.5, &sp, &cp);
-                hs[t] = make_float2((float)(att * cp), (float)(att * sp));
-            }
-            __syncthreads();
-            for (int k = t; k < MM * NC; k += blockDim.x) {
-                const int i = k / NC, md = k - i * NC;
-                float2 v = make_float2(0.f, 0.f);
-                if (i < M && md < nm) v = E[i * n + eofs[md]];
-                bs[i * SB + md] = v.x;
-                bs[(MM + i) * SB + md] = v.y;
-            }
-            __syncthreads();
-            // X = Wa B: (R / 16) x (NC / 16) tiles over the four waves; the
-            // results wait in registers until every wave has read B
-            md_f4 acc[(R / 16) * (NC / 16) / 4];
-#pragma unroll
-            for (int q = 0; q < (R / 16) * (NC / 16) / 4; ++q) {
-                const int tile = wave + 4 * q;
-                const int rt = tile / (NC / 16), ct = tile - rt * (NC / 16);
-                md_f4 a4 = {0.f, 0.f, 0.f, 0.f};
-                for (int k0 = 0; k0 < R; k0 += 4) {
-                    const float av = wa[(rt * 16 + row) * SA + k0 + kq];
-                    const float bv = bs[(k0 + kq) * SB + ct * 16 + row];
-                    a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, a4, 0, 0, 0);
-                }
-                acc[q] = a4;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < (R / 16) * (NC / 16) / 4; ++q) {
-                const int tile = wave + 4 * q;
-                const int rt = tile / (NC / 16), ct = tile - rt * (NC / 16);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) bs[(rt * 16 + kq * 4 + r) * SB + ct * 16 + row] = acc[q][r];
-            }
-            __syncthreads();
-            for (int k = t; k < M * NC; k += blockDim.x) {
-                const int i = k / NC, md = k - i * NC;
-                if (md < nm) {
-                    const float2 h = hs[md];
-                    const float xr = bs[i * SB + md], xi = bs[(MM + i) * SB + md];
-                    E[i * n + eofs[md]] = make_float2(h.x * xr - h.y * xi, h.x * xi + h.y * xr);
-                }
-            }
-            __syncthreads();  // bs and eofs are free for the next chunk
+    constexpr int PT = MM / 4;
+    float2 pv[PT];
+    int64_t pe = 0;
+    int pnm = 0;
+    float2 ph = make_float2(0.f, 0.f);
+    auto fetch = [&](int64_t bs0, int s) {  // workgroup-uniform arguments
+        const int nblk = (int)std::min<int64_t>(bpc, hi - bs0);
+        pnm = bpc > 1 ? nblk * c.B : min(NC, c.B - s);
+        pe = 0;
+        if (lane < pnm) {
+            const int64_t b = bpc > 1 ? (c.dense ? bs0 + lane / c.B : (int64_t)c.list[bs0 + lane / c.B]) :
+                                        (c.dense ? bs0 : (int64_t)c.list[bs0]);
+            pe = (b << c.lB) + (bpc > 1 ? (lane & (c.B - 1)) : s + lane);
         }
+        const int64_t si = pe <= ((n - 1) >> 1) ? pe : pe - n;
+        const double om = 6.283185307179586476925286766559 * (double)si / c.T;
+        double sp, cp;
+        sincos(c.beta2 * 0.5 * om * om * c.dz * 0.5, &sp, &cp);
+        ph = make_float2((float)(att * cp), (float)(att * sp));
+#pragma unroll
+        for (int j = 0; j < PT; ++j) {
+            const int i = wave + 4 * j;
+            pv[j] = (i < M && lane < pnm) ? E[i * n + pe] : make_float2(0.f, 0.f);
+        }
+    };
+    int64_t base = lo + (int64_t)(blockIdx.x >> 3) * bpc;
+    int s0 = 0;
+    if (base < hi) fetch(base, 0);
+    while (base < hi) {  // workgroup-uniform
+        const int nm = pnm;
+        const int64_t e = pe;
+        const float2 h = ph;
+#pragma unroll
+        for (int j = 0; j < PT; ++j) {
+            const int i = wave + 4 * j;
+            bs[i * SB + lane] = pv[j].x;
+            bs[(MM + i) * SB + lane] = pv[j].y;
+        }
+        __syncthreads();
+        // the next chunk (blocks of at least 64 bins go in chunks): its loads
+        // fly while this one is multiplied
+        int s1 = s0 + NC;
+        int64_t base1 = base;
+        if (bpc > 1 || s1 >= c.B) {
+            s1 = 0;
+            base1 += (int64_t)per * bpc;
+        }
+        if (base1 < hi) fetch(base1, s1);
+        // X = Wa B: (R / 16) x (NC / 16) tiles over the four waves; the
+        // results wait in registers until every wave has read B
+        md_f4 acc[(R / 16) * (NC / 16) / 4];
+#pragma unroll
+        for (int q = 0; q < (R / 16) * (NC / 16) / 4; ++q) {
+            const int tile = wave + 4 * q;
+            const int rt = tile / (NC / 16), ct = tile - rt * (NC / 16);
+            md_f4 a4 = {0.f, 0.f, 0.f, 0.f};
+            for (int k0 = 0; k0 < R; k0 += 4) {
+                const float av = wa[(rt * 16 + row) * SA + k0 + kq];
+                const float bv = bs[(k0 + kq) * SB + ct * 16 + row];
+                a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, a4, 0, 0, 0);
+            }
+            acc[q] = a4;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < (R / 16) * (NC / 16) / 4; ++q) {
+            const int tile = wave + 4 * q;
+            const int rt = tile / (NC / 16), ct = tile - rt * (NC / 16);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bs[(rt * 16 + kq * 4 + r) * SB + ct * 16 + row] = acc[q][r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PT; ++j) {
+            const int i = wave + 4 * j;
+            if (i < M && lane < nm) {
+                const float xr = bs[i * SB + lane], xi = bs[(MM + i) * SB + lane];
+                E[i * n + e] = make_float2(h.x * xr - h.y * xi, h.x * xi + h.y * xr);
+            }
+        }
+        __syncthreads();  // bs is free for the next chunk
+        base = base1;
+        s0 = s1;
     }
 }
 
